@@ -1,0 +1,304 @@
+"""CPU oracle for the hybrid PIC/MCC discharge step (arXiv 1508.02892).
+
+TEST INFRASTRUCTURE ONLY: this package may be imported by ``tests/``, by the
+smoke check and by the CPU-baseline leg of the benchmark, never by the product
+path.  It wraps ``oracle.cpp`` (plain C++17, FP64 field and fluid, particle
+scalar float or double) through ctypes and shares no code with the GPU
+library.
+
+Parameters are passed as a plain dict (see ``paper_1508_02892_amd.workloads``
+for the seeded workload definitions); cross sections are given per channel on
+the uniform energy grid E_i = i / inv_de_per_eV.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+KIND = {"elastic": 0, "excitation": 1, "ionization": 2}
+N_COUNTERS = 24
+MAX_CHANNELS = 16
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.cpp into liboracle.so (g++, -O2, no FP contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Channel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("threshold_eV", C.c_double),
+                ("sigma_m2", C.POINTER(C.c_double))]
+
+
+class _Params(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("ion_model", C.c_int32), ("n_cells", C.c_int32),
+        ("n_energy", C.c_int32), ("n_channels", C.c_int32), ("sort_every", C.c_int32),
+        ("eedf_every", C.c_int32), ("n_eedf_bins", C.c_int32), ("n_macro", C.c_int64),
+        ("seed", C.c_uint64),
+        ("n_gas_m3", C.c_double), ("t_gas_K", C.c_double), ("m_gas_amu", C.c_double),
+        ("gap_m", C.c_double),
+        ("v_amp_V", C.c_double), ("f_rf_Hz", C.c_double), ("phase_rad", C.c_double),
+        ("n_e0_m3", C.c_double), ("t_e0_eV", C.c_double), ("load_lo", C.c_double),
+        ("load_hi", C.c_double),
+        ("gamma_see", C.c_double), ("e_sec_eV", C.c_double),
+        ("m_ion_amu", C.c_double), ("mu_const", C.c_double), ("nu_const", C.c_double),
+        ("dt_s", C.c_double), ("inv_de_per_eV", C.c_double), ("eedf_emax_eV", C.c_double),
+        ("channels", C.POINTER(_Channel)),
+    ]
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = C.CDLL(_LIB)
+            vp = C.c_void_p
+            L.orc_create.restype = vp
+            L.orc_create.argtypes = [C.POINTER(_Params)]
+            L.orc_free.argtypes = [vp]
+            L.orc_step.argtypes = [vp, C.c_int64]
+            L.orc_step_index.restype = C.c_int64
+            L.orc_step_index.argtypes = [vp]
+            L.orc_num_particles.restype = C.c_int64
+            L.orc_num_particles.argtypes = [vp]
+            L.orc_next_id.restype = C.c_uint32
+            L.orc_next_id.argtypes = [vp]
+            L.orc_get_particles.argtypes = [vp] * 7
+            L.orc_set_particles.argtypes = [vp, C.c_int64] + [vp] * 6
+            L.orc_set_ions.argtypes = [vp, vp, vp]
+            L.orc_get_grid.argtypes = [vp] * 8
+            L.orc_get_counters.argtypes = [vp, vp]
+            L.orc_get_accum.argtypes = [vp, vp, vp, vp]
+            L.orc_get_derived.argtypes = [vp, vp]
+            L.orc_get_table.argtypes = [vp, vp]
+            L.orc_last_error.restype = C.c_char_p
+            L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+            L.orc_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
+                                       C.c_int64, vp]
+            L.orc_thomas.argtypes = [C.c_int] + [vp] * 5
+            L.orc_field.argtypes = [vp, vp, vp, C.c_double, vp, vp]
+            L.orc_fluid.argtypes = [vp] * 5
+            L.orc_push.argtypes = [C.c_int, C.c_int64, vp, vp, vp, vp, C.c_int, C.c_double,
+                                   C.c_int64, vp]
+            L.orc_collide.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_uint32, vp, vp]
+            L.orc_sphere.argtypes = [C.c_int, C.c_uint64, C.c_int64, vp, C.c_uint32, vp]
+            L.orc_deposit.argtypes = [C.c_int, C.c_int64, vp, vp, vp]
+            L.orc_emit.restype = C.c_int64
+            L.orc_emit.argtypes = [vp, C.c_int, C.c_double, C.c_uint32] + [vp] * 5 + [C.c_int64]
+            _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def pdtype(precision: int):
+    return np.float32 if precision == 0 else np.float64
+
+
+class Oracle:
+    """One discharge advanced by the CPU oracle."""
+
+    def __init__(self, params: dict):
+        L = lib()
+        self.params = dict(params)
+        chans = params.get("channels", [])
+        self._sig = [np.ascontiguousarray(ch["sigma_m2"], dtype=np.float64) for ch in chans]
+        for s in self._sig:
+            if s.shape[0] != params["n_energy"]:
+                raise ValueError("sigma table length must equal n_energy")
+        arr = (_Channel * max(1, len(chans)))()
+        for k, ch in enumerate(chans):
+            arr[k].kind = KIND[ch["kind"]] if isinstance(ch["kind"], str) else int(ch["kind"])
+            arr[k].threshold_eV = float(ch.get("threshold_eV", 0.0))
+            arr[k].sigma_m2 = self._sig[k].ctypes.data_as(C.POINTER(C.c_double))
+        self._chans = arr
+        P = _Params()
+        for name, ctype in _Params._fields_:
+            if name == "channels":
+                continue
+            setattr(P, name, params[name] if name != "n_channels" else len(chans))
+        P.channels = C.cast(arr, C.POINTER(_Channel))
+        self._P = P
+        self.h = L.orc_create(C.byref(P))
+        if not self.h:
+            raise ValueError("oracle: " + L.orc_last_error().decode())
+        self.nn = params["n_cells"] + 1
+        self.K = len(chans)
+        self.dt = pdtype(params["precision"])
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_free(h)
+            self.h = None
+
+    def step(self, n: int = 1):
+        if lib().orc_step(self.h, int(n)) != 0:
+            raise RuntimeError("oracle step failed")
+
+    @property
+    def step_index(self) -> int:
+        return lib().orc_step_index(self.h)
+
+    @property
+    def next_id(self) -> int:
+        return lib().orc_next_id(self.h)
+
+    def particles(self) -> dict:
+        n = lib().orc_num_particles(self.h)
+        out = {"cell": np.empty(n, np.int32), "id": np.empty(n, np.uint32)}
+        for k in ("off", "vx", "vy", "vz"):
+            out[k] = np.empty(n, self.dt)
+        lib().orc_get_particles(self.h, _p(out["cell"]), _p(out["off"]), _p(out["vx"]),
+                                _p(out["vy"]), _p(out["vz"]), _p(out["id"]))
+        return out
+
+    def set_particles(self, cell, off, vx, vy, vz, ids):
+        cell = np.ascontiguousarray(cell, np.int32)
+        arrs = [np.ascontiguousarray(a, self.dt) for a in (off, vx, vy, vz)]
+        ids = np.ascontiguousarray(ids, np.uint32)
+        lib().orc_set_particles(self.h, len(cell), _p(cell), *[_p(a) for a in arrs], _p(ids))
+
+    def set_ions(self, ni=None, gam=None):
+        ni = None if ni is None else np.ascontiguousarray(ni, np.float64)
+        gam = None if gam is None else np.ascontiguousarray(gam, np.float64)
+        lib().orc_set_ions(self.h, _p(ni), _p(gam))
+
+    def grid(self) -> dict:
+        nn = self.nn
+        g = {"cnt": np.empty(nn, np.int64), "n_i": np.empty(nn), "gamma": np.empty(nn),
+             "n_e": np.empty(nn), "phi": np.empty(nn), "E": np.empty(nn),
+             "Ep": np.empty(nn, self.dt)}
+        lib().orc_get_grid(self.h, _p(g["cnt"]), _p(g["n_i"]), _p(g["gamma"]), _p(g["n_e"]),
+                           _p(g["phi"]), _p(g["E"]), _p(g["Ep"]))
+        return g
+
+    def counters(self) -> dict:
+        c = np.empty(N_COUNTERS, np.uint64)
+        lib().orc_get_counters(self.h, _p(c))
+        return {"coll": c[:self.K].copy(), "absorbed": c[16:18].copy(),
+                "emitted": c[18:20].copy(), "created": int(c[20]), "overflow": int(c[21]),
+                "see_clamped": int(c[22]), "n_acc": int(c[23])}
+
+    def accum(self) -> dict:
+        nb = self.params["n_eedf_bins"] + 1
+        a = {"acc_cnt": np.empty(self.nn, np.uint64), "acc_ni": np.empty(self.nn),
+             "eedf": np.empty(nb, np.uint64)}
+        lib().orc_get_accum(self.h, _p(a["acc_cnt"]), _p(a["acc_ni"]), _p(a["eedf"]))
+        return a
+
+    def derived(self) -> dict:
+        v = np.empty(14)
+        lib().orc_get_derived(self.h, _p(v))
+        keys = ["dz", "w", "nu_max", "Pmax", "KE", "invKE", "kdz", "delta", "keedf", "qm_dt",
+                "kappa", "TN", "M", "nfloor"]
+        return dict(zip(keys, v.tolist()))
+
+    def table(self) -> np.ndarray:
+        t = np.empty(self.params["n_energy"] * self.K)
+        lib().orc_get_table(self.h, _p(t))
+        return t.reshape(self.params["n_energy"], self.K)
+
+    def field(self, cnt, ni, V):
+        cnt = np.ascontiguousarray(cnt, np.int64)
+        ni = np.ascontiguousarray(ni, np.float64)
+        phi = np.empty(self.nn)
+        E = np.empty(self.nn)
+        lib().orc_field(self.h, _p(cnt), _p(ni), float(V), _p(phi), _p(E))
+        return phi, E
+
+    def fluid(self, ni, gam, E):
+        ni = np.array(ni, np.float64)
+        gam = np.array(gam, np.float64)
+        E = np.ascontiguousarray(E, np.float64)
+        gw = np.empty(2)
+        lib().orc_fluid(self.h, _p(ni), _p(gam), _p(E), _p(gw))
+        return ni, gam, gw
+
+    def collide(self, cell, off, vx, vy, vz, ids, step):
+        n = len(cell)
+        cell = np.ascontiguousarray(cell, np.int32)
+        off = np.ascontiguousarray(off, self.dt)
+        vx, vy, vz = (np.array(a, self.dt) for a in (vx, vy, vz))
+        ids = np.ascontiguousarray(ids, np.uint32)
+        ch = np.empty(n, np.int32)
+        kid = np.empty((n, 3), self.dt)
+        lib().orc_collide(self.h, n, _p(cell), _p(off), _p(vx), _p(vy), _p(vz), _p(ids),
+                          int(step), _p(ch), _p(kid))
+        return ch, vx, vy, vz, kid
+
+    def emit(self, side, F, step, cap=1 << 16):
+        c = np.empty(cap, np.int32)
+        arrs = [np.empty(cap, self.dt) for _ in range(4)]
+        m = lib().orc_emit(self.h, int(side), float(F), int(step), _p(c), *[_p(a) for a in arrs],
+                           int(cap))
+        return {"cell": c[:m], "off": arrs[0][:m], "vx": arrs[1][:m], "vy": arrs[2][:m],
+                "vz": arrs[3][:m]}
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    o = np.empty(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(o))
+    return o
+
+
+def uniforms(seed, tag, id_, step, precision, n):
+    o = np.empty(n)
+    lib().orc_uniforms(seed, tag, id_, step, precision, n, _p(o))
+    return o
+
+
+def thomas(a, b, c, d):
+    a, b, c, d = (np.ascontiguousarray(v, np.float64) for v in (a, b, c, d))
+    x = np.empty(len(b))
+    lib().orc_thomas(len(b), _p(a), _p(b), _p(c), _p(d), _p(x))
+    return x
+
+
+def push(precision, cell, off, vz, Ep, nc, kdz, steps):
+    dt = pdtype(precision)
+    cell = np.array(cell, np.int32)
+    off = np.array(off, dt)
+    vz = np.array(vz, dt)
+    Ep = np.ascontiguousarray(Ep, dt)
+    st = np.empty(len(cell), np.int32)
+    lib().orc_push(precision, len(cell), _p(cell), _p(off), _p(vz), _p(Ep), int(nc), float(kdz),
+                   int(steps), _p(st))
+    return cell, off, vz, st
+
+
+def sphere(precision, seed, ids, step):
+    ids = np.ascontiguousarray(ids, np.uint32)
+    o = np.empty((len(ids), 3))
+    lib().orc_sphere(precision, seed, len(ids), _p(ids), int(step), _p(o))
+    return o
+
+
+def deposit(precision, cell, off, nn):
+    cell = np.ascontiguousarray(cell, np.int32)
+    off = np.ascontiguousarray(off, pdtype(precision))
+    g = np.zeros(nn, np.int64)
+    lib().orc_deposit(precision, len(cell), _p(cell), _p(off), _p(g))
+    return g

@@ -1,0 +1,1188 @@
+// Plain CPU oracle for the 1D hybrid PIC/MCC discharge step of Eremin, Hemke &
+// Mussenbrock, "A New Hybrid Scheme for Simulations of Highly Collisional
+// RF-Driven Plasmas" (arXiv 1508.02892).
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+// this file: it exists so that tests, the smoke check and the CPU-baseline leg
+// of the benchmark can check the GPU library against an independent, slow,
+// obviously-correct implementation.  It shares no code, header, table or
+// constant generator with the GPU library.
+//
+// Field/fluid arithmetic is FP64.  The electron particle state and the Monte
+// Carlo arithmetic use the scalar type P (float or double), selected at run
+// time by the `precision` parameter.  Expressions are written in a fixed
+// evaluation order and compiled with -ffp-contract=off; where a fused
+// multiply-add is part of the definition it is written as std::fma.
+//
+// Parity status per function (pins live in tests/test_oracle_*.py):
+//   philox4x32_10 ............ pinned (published known-answer vectors, rocRAND)
+//   uniform maps .............. pinned (exact bit patterns)
+//   initial load .............. pinned (exact charge, statistical moments)
+//   field solve (Poisson) ..... pinned (dense solve, linear/parabolic closed forms,
+//                               discrete Gauss law)
+//   push ...................... pinned (free streaming, uniform-field leapfrog)
+//   null-collision MCC ........ pinned (binomial collision counts, channel
+//                               fractions, energy bookkeeping, isotropy)
+//   CIC deposit ............... pinned (exact total, single-node case)
+//   DD ion fluid .............. pinned (conservation, centroid drift, Boltzmann
+//                               steady state)
+//   full ion fluid ............ pinned (closed-form relaxation, dense Thomas)
+//   secondary emission ........ pinned (mean count, cosine law)
+//   compaction + sort ......... pinned (equals a stable sort by cell)
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Physical constants (CODATA 2018).
+// ---------------------------------------------------------------------------
+constexpr double kE = 1.602176634e-19;      // elementary charge [C]
+constexpr double kMe = 9.1093837015e-31;    // electron mass [kg]
+constexpr double kEps0 = 8.8541878128e-12;  // vacuum permittivity [F/m]
+constexpr double kKb = 1.380649e-23;        // Boltzmann constant [J/K]
+constexpr double kAmu = 1.66053906660e-27;  // atomic mass unit [kg]
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr int kMaxChannels = 16;
+constexpr int kSphereTries = 64;     // rejection-loop bound (probability of
+                                     // exhausting it is (1-pi/4)^64 ~ 1e-43)
+constexpr int64_t kSeeMaxPerSide = 4096;
+
+thread_local std::string g_err;
+
+}  // namespace
+
+extern "C" {
+
+// Mirrors the parameters of the discharge problem (see the header comment of
+// oracle/__init__.py for the field meanings).  This struct is the oracle's own.
+typedef struct orc_channel {
+  int32_t kind;  // 0 elastic, 1 excitation, 2 ionization
+  int32_t pad;
+  double threshold_eV;
+  const double* sigma_m2;  // n_energy values at E_i = i / inv_de_per_eV
+} orc_channel;
+
+typedef struct orc_params {
+  int32_t precision;  // 0: float particles, 1: double particles
+  int32_t ion_model;  // 0: drift-diffusion, constant mobility; 1: full fluid, constant nu
+  int32_t n_cells;
+  int32_t n_energy;
+  int32_t n_channels;
+  int32_t sort_every;
+  int32_t eedf_every;
+  int32_t n_eedf_bins;
+  int64_t n_macro;
+  uint64_t seed;
+  double n_gas_m3, t_gas_K, m_gas_amu;
+  double gap_m;
+  double v_amp_V, f_rf_Hz, phase_rad;
+  double n_e0_m3, t_e0_eV, load_lo, load_hi;
+  double gamma_see, e_sec_eV;
+  double m_ion_amu, mu_const, nu_const;
+  double dt_s;
+  double inv_de_per_eV;
+  double eedf_emax_eV;
+  const orc_channel* channels;
+} orc_params;
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications with the round constants of that paper, the key
+// bumped by the Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t y0 = hi1 ^ x1 ^ k0;
+    const uint32_t y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+// A random stream S(tag, id, step): Philox blocks b = 0, 1, 2, ... with
+// counter {id, step, b, tag} and key {seed_lo, seed_hi}; the words of each
+// block are consumed strictly in order.
+struct Stream {
+  uint32_t key[2];
+  uint32_t ctr[4];
+  uint32_t w[4];
+  int pos;
+  Stream(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step) {
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    ctr[0] = id;
+    ctr[1] = step;
+    ctr[2] = 0;
+    ctr[3] = tag;
+    pos = 4;
+  }
+  uint32_t word() {
+    if (pos == 4) {
+      philox4x32_10(ctr, key, w);
+      ctr[2] += 1;
+      pos = 0;
+    }
+    return w[pos++];
+  }
+};
+
+// Uniform in [0,1): float from the top 24 bits of one word; double from the
+// top 53 bits of two consecutive words (first word high).
+inline float uniform_f32(Stream& s) { return (float)(s.word() >> 8) * 0x1p-24f; }
+inline double uniform_f64(Stream& s) {
+  const uint64_t hi = s.word();
+  const uint64_t lo = s.word();
+  return (double)(((hi << 32) | lo) >> 11) * 0x1p-53;
+}
+template <class P> P uniform(Stream& s);
+template <> float uniform<float>(Stream& s) { return uniform_f32(s); }
+template <> double uniform<double>(Stream& s) { return uniform_f64(s); }
+
+enum Tag : uint32_t { kTagElectron = 0, kTagLoad = 1, kTagEmission = 2 };
+
+// ---------------------------------------------------------------------------
+// Derived constants, computed once in FP64 from the parameters.
+// ---------------------------------------------------------------------------
+struct Derived {
+  int nc, nn;     // cells, nodes
+  double L, dz;
+  double w;       // superparticle weight per unit electrode area [m^-2], Eq (1.2)
+  std::vector<double> dV;     // control length of node j: dz inside, dz/2 at walls
+  std::vector<double> scale;  // density per fixed-point count unit at node j
+  // Poisson: inverse pivots of the constant (-1, 2, -1) matrix
+  std::vector<double> ip;
+  double kp;        // dz^2 / eps0
+  double inv_dz, inv_2dz, hdz_eps;  // 1/dz, 1/(2 dz), dz/(2 eps0)
+  double qm_dt;     // (-e/m_e) dt
+  // ion fluid
+  double M;         // ion mass
+  double TN;        // background gas temperature [J]
+  double kappa;     // Wannier factor of Eq (2.8): (m_i+m_N)/(5 m_i+3 m_N) m_N
+  double dt_2dz, dt_dz;
+  double e_M_dt;    // e dt / M
+  double dt_2dzM;   // dt / (2 dz M)
+  double hdt;       // dt / 2
+  double nfloor;    // density below which u = Gamma/n is taken as zero
+  // collisions
+  double nu_max, Pmax;
+  std::vector<double> cum;  // (n_energy x K) cumulative probabilities, FP64
+  // electron constants
+  double KE;        // m_e/(2e): energy [eV] per (m/s)^2
+  double invKE;     // 2e/m_e
+  double kdz;       // dt/dz
+  double delta;     // 2 m_e / M_gas
+  double keedf;     // n_bins / E_max
+};
+
+bool derive(const orc_params& p, Derived& d) {
+  if (p.n_cells < 2 || p.n_energy < 2 || p.n_channels < 0 || p.n_channels > kMaxChannels ||
+      p.sort_every < 1 || p.eedf_every < 1 || p.n_eedf_bins < 1 || p.n_macro < 0 ||
+      !(p.gap_m > 0) || !(p.dt_s > 0) || !(p.inv_de_per_eV > 0) || !(p.load_hi > p.load_lo) ||
+      p.load_lo < 0 || p.load_hi > 1 || (p.ion_model != 0 && p.ion_model != 1) ||
+      (p.precision != 0 && p.precision != 1) || (p.n_channels > 0 && !p.channels)) {
+    g_err = "invalid parameters";
+    return false;
+  }
+  d.nc = p.n_cells;
+  d.nn = p.n_cells + 1;
+  d.L = p.gap_m;
+  d.dz = p.gap_m / p.n_cells;
+  // Eq (1.2): N_p/sp = n_e0 dV / N_s0 with N_s0 the initial superparticles per
+  // cell; per unit electrode area this is n_e0 (hi-lo) L / N_0.
+  d.w = p.n_macro > 0 ? p.n_e0_m3 * (p.load_hi - p.load_lo) * p.gap_m / (double)p.n_macro : 0.0;
+  d.dV.assign(d.nn, d.dz);
+  d.dV[0] = 0.5 * d.dz;
+  d.dV[d.nc] = 0.5 * d.dz;
+  d.scale.resize(d.nn);
+  for (int j = 0; j < d.nn; ++j) d.scale[j] = std::ldexp(d.w, -32) / d.dV[j];
+  // Thomas factors of the interior Poisson matrix (unknowns j = 1..nc-1).
+  const int m = d.nc - 1;
+  d.ip.assign(d.nn, 0.0);
+  if (m >= 1) {
+    double den = 2.0;
+    d.ip[1] = 1.0 / den;
+    for (int j = 2; j <= m; ++j) {
+      den = 2.0 - d.ip[j - 1];
+      d.ip[j] = 1.0 / den;
+    }
+  }
+  d.kp = d.dz * d.dz / kEps0;
+  d.inv_dz = 1.0 / d.dz;
+  d.inv_2dz = 0.5 / d.dz;
+  d.hdz_eps = d.dz / (2.0 * kEps0);
+  d.qm_dt = (-kE / kMe) * p.dt_s;
+  d.M = p.m_ion_amu * kAmu;
+  const double mN = p.m_gas_amu * kAmu;
+  d.TN = kKb * p.t_gas_K;
+  d.kappa = (d.M + mN) / (5.0 * d.M + 3.0 * mN) * mN;
+  d.dt_2dz = p.dt_s / (2.0 * d.dz);
+  d.dt_dz = p.dt_s / d.dz;
+  d.e_M_dt = kE * p.dt_s / d.M;
+  d.dt_2dzM = p.dt_s / (2.0 * d.dz * d.M);
+  d.hdt = 0.5 * p.dt_s;
+  d.nfloor = 1e-10 * p.n_e0_m3;
+  // Null-collision tables: nu_k(E_i) = N_g sigma_k(E_i) sqrt(2 e E_i / m_e),
+  // nu_max = max_i sum_k nu_k(E_i), P_max = 1 - exp(-nu_max dt); the cumulative
+  // probabilities P_max sum_{m<=k} nu_m / nu_max select the channel.
+  const int ne = p.n_energy, K = p.n_channels;
+  std::vector<double> nu((size_t)ne * K, 0.0);
+  d.nu_max = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const double Ei = (double)i / p.inv_de_per_eV;
+    const double v = std::sqrt(2.0 * kE * Ei / kMe);
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double s = p.channels[k].sigma_m2[i];
+      if (!(s >= 0) || !std::isfinite(s)) {
+        g_err = "cross section must be finite and non-negative";
+        return false;
+      }
+      nu[(size_t)i * K + k] = p.n_gas_m3 * s * v;
+      tot += nu[(size_t)i * K + k];
+    }
+    if (tot > d.nu_max) d.nu_max = tot;
+  }
+  d.Pmax = d.nu_max > 0 ? 1.0 - std::exp(-d.nu_max * p.dt_s) : 0.0;
+  d.cum.assign((size_t)ne * K, 0.0);
+  for (int i = 0; i < ne; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) {
+      acc += nu[(size_t)i * K + k];
+      d.cum[(size_t)i * K + k] = d.nu_max > 0 ? d.Pmax * acc / d.nu_max : 0.0;
+    }
+  }
+  d.KE = 0.5 * kMe / kE;
+  d.invKE = 2.0 * kE / kMe;
+  d.kdz = p.dt_s / d.dz;
+  d.delta = 2.0 * kMe / (p.m_gas_amu * kAmu);
+  d.keedf = (double)p.n_eedf_bins / p.eedf_emax_eV;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Field solve (coupling through Poisson's equation, Sec. II.D).
+// rho_j = e (n_i,j - n_e,j);  -phi_{j-1} + 2 phi_j - phi_{j+1} = dz^2 rho_j / eps0
+// for the interior nodes, phi_0 = V(t_n) (powered electrode at z = 0) and
+// phi_N = 0 (grounded electrode at z = L).  Thomas elimination with the
+// constant pivots: y_j = (d_j + y_{j-1}) / b'_j and phi_j = y_j + phi_{j+1}/b'_j,
+// each written as one fused multiply-add.  E from centred differences inside
+// and from Gauss's law over the half cells at the walls.
+// ---------------------------------------------------------------------------
+void field_solve(const Derived& d, const int64_t* cnt, const double* ni, double V, double* ne_out,
+                 double* rho, double* phi, double* E) {
+  const int nc = d.nc, nn = d.nn;
+  for (int j = 0; j < nn; ++j) {
+    ne_out[j] = (double)cnt[j] * d.scale[j];
+    rho[j] = kE * (ni[j] - ne_out[j]);
+  }
+  phi[0] = V;
+  phi[nc] = 0.0;
+  const int m = nc - 1;
+  if (m >= 1) {
+    std::vector<double> y(nn, 0.0);
+    for (int j = 1; j <= m; ++j) {
+      double dj = d.kp * rho[j];
+      if (j == 1) dj = dj + phi[0];
+      if (j == m) dj = dj + phi[nc];
+      const double g = dj * d.ip[j];
+      y[j] = (j == 1) ? g : std::fma(y[j - 1], d.ip[j], g);
+    }
+    phi[m] = y[m];
+    for (int j = m - 1; j >= 1; --j) phi[j] = std::fma(d.ip[j], phi[j + 1], y[j]);
+  }
+  for (int j = 1; j < nc; ++j) E[j] = (phi[j - 1] - phi[j + 1]) * d.inv_2dz;
+  E[0] = (phi[0] - phi[1]) * d.inv_dz - rho[0] * d.hdz_eps;
+  E[nc] = (phi[nc - 1] - phi[nc]) * d.inv_dz + rho[nc] * d.hdz_eps;
+}
+
+// ---------------------------------------------------------------------------
+// Ion fluid.  Temperature from Eq (2.8), diffusion coefficient from Eq (2.7).
+// ---------------------------------------------------------------------------
+inline double ion_temperature(const Derived& d, double mu, double E) {
+  const double x = mu * std::fabs(E);
+  return d.TN + d.kappa * (x * x);
+}
+
+// Drift-diffusion (Sec. II.C), explicit: Gamma_j^n from Eq (2.5) with central
+// differences, wall fluxes by the field-direction switch (drift only), and the
+// continuity update of Eq (2.4) with half cells at the walls.  Returns the wall
+// fluxes Gamma_0 and Gamma_N in gw[0], gw[1]; gam receives Gamma^n.
+void fluid_dd(const Derived& d, double mu, double* ni, const double* E, double* gam, double gw[2]) {
+  const int nc = d.nc, nn = d.nn;
+  std::vector<double> n0(ni, ni + nn);
+  for (int j = 1; j < nc; ++j) {
+    const double T = ion_temperature(d, mu, E[j]);
+    const double D = mu * T / kE;
+    gam[j] = mu * n0[j] * E[j] - D * (n0[j + 1] - n0[j - 1]) * d.inv_2dz;
+  }
+  gam[0] = mu * n0[0] * std::min(E[0], 0.0);
+  gam[nc] = mu * n0[nc] * std::max(E[nc], 0.0);
+  for (int j = 1; j < nc; ++j) ni[j] = n0[j] - d.dt_2dz * (gam[j + 1] - gam[j - 1]);
+  ni[0] = n0[0] - d.dt_dz * (gam[1] - gam[0]);
+  ni[nc] = n0[nc] - d.dt_dz * (gam[nc] - gam[nc - 1]);
+  gw[0] = gam[0];
+  gw[1] = gam[nc];
+}
+
+// Thomas algorithm for a general tridiagonal system a_j x_{j-1} + b_j x_j +
+// c_j x_{j+1} = d_j, j = 0..n-1 (a_0 and c_{n-1} unused).  One reciprocal of
+// the pivot per row.
+void thomas(int n, const double* a, const double* b, const double* c, const double* dd,
+            double* x) {
+  std::vector<double> cp(n), dp(n);
+  for (int j = 0; j < n; ++j) {
+    double den = b[j];
+    if (j > 0) den = b[j] - a[j] * cp[j - 1];
+    const double r = 1.0 / den;
+    cp[j] = c[j] * r;
+    double num = dd[j];
+    if (j > 0) num = dd[j] - a[j] * dp[j - 1];
+    dp[j] = num * r;
+  }
+  x[n - 1] = dp[n - 1];
+  for (int j = n - 2; j >= 0; --j) x[j] = dp[j] - cp[j] * x[j + 1];
+}
+
+// Full fluid (Sec. II.B): Eq (2.3) for Gamma^{n+1/2} with the lagged friction
+// frequency nu^n and semi-implicit advection, solved by the Thomas method;
+// Gamma at the wall nodes from the field-direction switch with mu = e/(M nu)
+// (Eq (2.6)); then Eq (2.4) with G^n applied by the caller.  gam holds
+// Gamma^{n-1/2} on entry and Gamma^{n+1/2} on exit.
+void fluid_full(const Derived& d, double nu_const, double* ni, const double* E, double* gam,
+                double gw[2]) {
+  const int nc = d.nc, nn = d.nn;
+  std::vector<double> n0(ni, ni + nn), g0(gam, gam + nn), u(nn), T(nn), nu(nn), mu(nn);
+  for (int j = 0; j < nn; ++j) {
+    nu[j] = nu_const;
+    mu[j] = kE / (d.M * nu[j]);
+    u[j] = (n0[j] > d.nfloor) ? g0[j] / n0[j] : 0.0;
+    T[j] = ion_temperature(d, mu[j], E[j]);
+  }
+  const double gl = mu[0] * n0[0] * std::min(E[0], 0.0);
+  const double gr = mu[nc] * n0[nc] * std::max(E[nc], 0.0);
+  const int m = nc - 1;
+  std::vector<double> a(m), b(m), c(m), rhs(m), x(m);
+  for (int j = 1; j <= m; ++j) {
+    const int r = j - 1;
+    a[r] = -d.dt_2dz * u[j - 1];
+    b[r] = 1.0 + nu[j] * d.hdt;
+    c[r] = d.dt_2dz * u[j + 1];
+    rhs[r] = g0[j] * (1.0 - nu[j] * d.hdt) + d.e_M_dt * n0[j] * E[j] -
+             d.dt_2dzM * (n0[j + 1] * T[j + 1] - n0[j - 1] * T[j - 1]);
+  }
+  rhs[0] = rhs[0] - a[0] * gl;
+  rhs[m - 1] = rhs[m - 1] - c[m - 1] * gr;
+  thomas(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+  gam[0] = gl;
+  gam[nc] = gr;
+  for (int j = 1; j <= m; ++j) gam[j] = x[j - 1];
+  for (int j = 1; j < nc; ++j) ni[j] = n0[j] - d.dt_2dz * (gam[j + 1] - gam[j - 1]);
+  ni[0] = n0[0] - d.dt_dz * (gam[1] - gam[0]);
+  ni[nc] = n0[nc] - d.dt_dz * (gam[nc] - gam[nc - 1]);
+  gw[0] = gl;
+  gw[1] = gr;
+}
+
+// ---------------------------------------------------------------------------
+// Electrons (Sec. II.A).
+// ---------------------------------------------------------------------------
+template <class P>
+struct Particle {
+  int32_t c;  // cell index; -1 marks a removed particle (a hole until compaction)
+  P off;      // position inside the cell, in [0, 1)
+  P vx, vy, vz;
+  uint32_t id;
+};
+
+// Electron-side constants rounded to the particle precision.
+template <class P>
+struct PConst {
+  P Pmax, KE, invKE, inv_dE, kdz, delta, keedf;
+  P thr[kMaxChannels];
+  int kind[kMaxChannels];
+  int K, ne, nbins, nc;
+  std::vector<P> tab;  // (ne x K) cumulative probabilities rounded to P
+};
+
+template <class P>
+void make_pconst(const orc_params& p, const Derived& d, PConst<P>& q) {
+  q.Pmax = (P)d.Pmax;
+  q.KE = (P)d.KE;
+  q.invKE = (P)d.invKE;
+  q.inv_dE = (P)p.inv_de_per_eV;
+  q.kdz = (P)d.kdz;
+  q.delta = (P)d.delta;
+  q.keedf = (P)d.keedf;
+  q.K = p.n_channels;
+  q.ne = p.n_energy;
+  q.nbins = p.n_eedf_bins;
+  q.nc = d.nc;
+  for (int k = 0; k < q.K; ++k) {
+    q.thr[k] = (P)p.channels[k].threshold_eV;
+    q.kind[k] = p.channels[k].kind;
+  }
+  q.tab.resize(d.cum.size());
+  for (size_t i = 0; i < d.cum.size(); ++i) q.tab[i] = (P)d.cum[i];
+}
+
+// Leapfrog push with linear (cloud-in-cell) gather, 1D3V: only v_z is
+// accelerated.  Ep holds (-e/m_e) dt E_j at the nodes.  Returns 0 when the
+// particle stays inside, 1 when it leaves through z = 0, 2 through z = L.
+template <class P>
+int push(int32_t& c, P& off, P& vz, const P* Ep, int nc, P kdz) {
+  const P e0 = Ep[c];
+  const P e1 = Ep[c + 1];
+  const P t1 = e1 - e0;
+  const P g = e0 + off * t1;
+  vz = vz + g;
+  const P s = off + vz * kdz;
+  const P f = std::floor(s);
+  if (!(f >= (P)(-c))) return 1;
+  if (f >= (P)(nc - c)) return 2;
+  int32_t cn = c + (int32_t)f;
+  P on = s - f;
+  if (on == (P)1) {
+    cn = cn + 1;
+    on = (P)0;
+  }
+  c = cn;
+  off = on;
+  return 0;
+}
+
+// Marsaglia (1972): a point on the unit sphere from a uniform point in the
+// unit disk, (2a sqrt(1-q), 2b sqrt(1-q), 1-2q) with q = a^2 + b^2.
+template <class P>
+void sphere(Stream& s, P n[3]) {
+  for (int t = 0; t < kSphereTries; ++t) {
+    const P a = (P)2 * uniform<P>(s) - (P)1;
+    const P b = (P)2 * uniform<P>(s) - (P)1;
+    const P q = a * a + b * b;
+    if (q < (P)1) {
+      const P r = (P)2 * std::sqrt((P)1 - q);
+      n[0] = a * r;
+      n[1] = b * r;
+      n[2] = (P)1 - (P)2 * q;
+      return;
+    }
+  }
+  n[0] = (P)0;
+  n[1] = (P)0;
+  n[2] = (P)1;
+}
+
+// Outcome of the collision step for one particle.
+template <class P>
+struct Mcc {
+  int channel = -1;     // -1: no collision (null or not a candidate)
+  bool overflow = false;
+  bool child = false;
+  Particle<P> kid;
+};
+
+// Null-collision Monte Carlo (Sec. II.A): one uniform R per particle; R <
+// P_max makes it a candidate; the channel is the first k whose interpolated
+// cumulative probability exceeds R.  Isotropic scattering for every channel
+// ("scattering on a sphere"), elastic recoil loss 2 m_e/M (1 - cos chi),
+// excitation loses the threshold, ionization shares the remaining energy
+// uniformly between the primary and a new electron created at the same place
+// (Sec. II.D).
+template <class P>
+Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step) {
+  Mcc<P> r;
+  Stream st(seed, kTagElectron, pt.id, step);
+  const P u0 = uniform<P>(st);
+  if (!(u0 < q.Pmax)) return r;
+  const P v2 = (pt.vx * pt.vx + pt.vy * pt.vy) + pt.vz * pt.vz;
+  const P en = q.KE * v2;
+  const P s = en * q.inv_dE;
+  int i;
+  P t;
+  if (s >= (P)(q.ne - 1)) {
+    i = q.ne - 2;
+    t = (P)1;
+    r.overflow = true;
+  } else {
+    i = (int)s;
+    t = s - (P)i;
+  }
+  int ch = -1;
+  for (int k = 0; k < q.K; ++k) {
+    const P pa = q.tab[(size_t)i * q.K + k];
+    const P pb = q.tab[(size_t)(i + 1) * q.K + k];
+    const P pk = pa + t * (pb - pa);
+    if (u0 < pk) {
+      ch = k;
+      break;
+    }
+  }
+  r.channel = ch;
+  if (ch < 0) return r;
+  const int kind = q.kind[ch];
+  P n[3];
+  if (kind == 0) {
+    sphere(st, n);
+    const P vm = std::sqrt(v2);
+    const P cosx = ((pt.vx * n[0] + pt.vy * n[1]) + pt.vz * n[2]) / vm;
+    const P fac = (P)1 - q.delta * ((P)1 - cosx);
+    const P vn = std::sqrt(v2 * fac);
+    pt.vx = vn * n[0];
+    pt.vy = vn * n[1];
+    pt.vz = vn * n[2];
+  } else if (kind == 1) {
+    sphere(st, n);
+    P er = en - q.thr[ch];
+    if (er < (P)0) er = (P)0;
+    const P vn = std::sqrt(er * q.invKE);
+    pt.vx = vn * n[0];
+    pt.vy = vn * n[1];
+    pt.vz = vn * n[2];
+  } else {
+    sphere(st, n);
+    const P us = uniform<P>(st);
+    P er = en - q.thr[ch];
+    if (er < (P)0) er = (P)0;
+    const P es = us * er;
+    const P ep = er - es;
+    const P vn = std::sqrt(ep * q.invKE);
+    pt.vx = vn * n[0];
+    pt.vy = vn * n[1];
+    pt.vz = vn * n[2];
+    P m2[3];
+    sphere(st, m2);
+    const P vc = std::sqrt(es * q.invKE);
+    r.child = true;
+    r.kid.c = pt.c;
+    r.kid.off = pt.off;
+    r.kid.vx = vc * m2[0];
+    r.kid.vy = vc * m2[1];
+    r.kid.vz = vc * m2[2];
+    r.kid.id = 0;
+  }
+  return r;
+}
+
+// Cloud-in-cell charge assignment in 64-bit fixed point: weight
+// W1 = rint(off 2^32) on node c+1 and 2^32 - W1 on node c.
+template <class P>
+inline void deposit(int32_t c, P off, int64_t* g) {
+  const int64_t W1 = (int64_t)std::rint(off * (P)4294967296.0);
+  const int64_t W0 = ((int64_t)1 << 32) - W1;
+  g[c] += W0;
+  g[c + 1] += W1;
+}
+
+template <class P>
+inline int eedf_bin(const Particle<P>& p, const PConst<P>& q) {
+  const P en = q.KE * ((p.vx * p.vx + p.vy * p.vy) + p.vz * p.vz);
+  const P x = en * q.keedf;
+  return (x < (P)q.nbins) ? (int)x : q.nbins;
+}
+
+struct Counters {
+  uint64_t coll[kMaxChannels] = {};
+  uint64_t absorbed[2] = {};
+  uint64_t emitted[2] = {};
+  uint64_t created = 0;
+  uint64_t overflow = 0;
+  uint64_t see_clamped = 0;
+};
+
+// ---------------------------------------------------------------------------
+// One discharge.
+// ---------------------------------------------------------------------------
+struct Base {
+  orc_params p;
+  std::vector<orc_channel> ch;
+  std::vector<std::vector<double>> sig;
+  Derived d;
+  int64_t step = 0;
+  uint32_t next_id = 0;
+  std::vector<int64_t> cnt, ion_src;
+  std::vector<double> ni, gam, ne, rho, phi, E;
+  std::vector<uint64_t> acc_cnt, eedf;
+  std::vector<double> acc_ni;
+  uint64_t n_acc = 0;
+  Counters ctr;
+  virtual ~Base() {}
+  virtual int do_step() = 0;
+  virtual int64_t count() const = 0;
+  virtual void get(int32_t*, void*, void*, void*, void*, uint32_t*) const = 0;
+  virtual void get_ep(void*) const = 0;
+  virtual void set_particles(int64_t, const int32_t*, const void*, const void*, const void*,
+                             const void*, const uint32_t*) = 0;
+
+  double volt(int64_t n) const {
+    const double two_pi_f = 2.0 * kPi * p.f_rf_Hz;
+    const double t = (double)n * p.dt_s;
+    return p.v_amp_V * std::sin(two_pi_f * t + p.phase_rad);
+  }
+  void field() {
+    field_solve(d, cnt.data(), ni.data(), volt(step), ne.data(), rho.data(), phi.data(), E.data());
+  }
+};
+
+template <class P>
+struct Discharge : Base {
+  PConst<P> q;
+  std::vector<Particle<P>> parts;
+  std::vector<P> Ep;
+
+  bool init() {
+    make_pconst(p, d, q);
+    const int nn = d.nn;
+    cnt.assign(nn, 0);
+    ion_src.assign(nn, 0);
+    ni.assign(nn, 0.0);
+    gam.assign(nn, 0.0);
+    ne.assign(nn, 0.0);
+    rho.assign(nn, 0.0);
+    phi.assign(nn, 0.0);
+    E.assign(nn, 0.0);
+    Ep.assign(nn, (P)0);
+    acc_cnt.assign(nn, 0);
+    acc_ni.assign(nn, 0.0);
+    eedf.assign((size_t)p.n_eedf_bins + 1, 0);
+    load();
+    // Ions start equal to the deposited electron density, so the net charge
+    // is exactly zero at t = 0; Gamma^{-1/2} = 0.
+    for (int j = 0; j < nn; ++j) ni[j] = (double)cnt[j] * d.scale[j];
+    return true;
+  }
+
+  // Initial load (Sec. II.A, Eq (1.1)-(1.2)): uniform positions in
+  // [lo L, hi L), isotropic Maxwellian velocities with kT = t_e0 (three normal
+  // deviates from two Marsaglia polar pairs), stream (tag 1, id = k, step 0).
+  void load() {
+    const int64_t N = p.n_macro;
+    parts.resize((size_t)N);
+    const double vth = std::sqrt(p.t_e0_eV * kE / kMe);
+    for (int64_t k = 0; k < N; ++k) {
+      Stream st(p.seed, kTagLoad, (uint32_t)k, 0);
+      const double u0 = uniform_f64(st);
+      const double z = p.gap_m * (p.load_lo + (p.load_hi - p.load_lo) * u0);
+      const double s = z / d.dz;
+      const double fl = std::floor(s);
+      int32_t c = (int32_t)fl;
+      P off = (P)(s - fl);
+      if (off == (P)1) {
+        c = c + 1;
+        off = (P)0;
+      }
+      double g[4];
+      for (int pair = 0; pair < 2; ++pair) {
+        double a = 0, b = 0, qq = 0;
+        for (;;) {
+          a = 2.0 * uniform_f64(st) - 1.0;
+          b = 2.0 * uniform_f64(st) - 1.0;
+          qq = a * a + b * b;
+          if (qq < 1.0 && qq > 0.0) break;
+        }
+        const double f = std::sqrt(-2.0 * std::log(qq) / qq);
+        g[2 * pair] = a * f;
+        g[2 * pair + 1] = b * f;
+      }
+      Particle<P>& pt = parts[(size_t)k];
+      pt.c = c;
+      pt.off = off;
+      pt.vx = (P)(vth * g[0]);
+      pt.vy = (P)(vth * g[1]);
+      pt.vz = (P)(vth * g[2]);
+      pt.id = (uint32_t)k;
+      deposit<P>(c, off, cnt.data());
+    }
+    next_id = (uint32_t)N;
+  }
+
+  // Secondary electrons from the ion wall flux (Sec. II.D): X = gamma F dt / w
+  // superparticles per step, int(X) plus one more with probability X - int(X).
+  // Emission energy e_sec, cosine law in polar angle, uniform azimuth (disk
+  // rejection), placed at a uniformly random fraction of one step's flight.
+  void emit(int side, double F, uint32_t n, std::vector<Particle<P>>& out) {
+    Stream st(p.seed, kTagEmission, (uint32_t)side, n);
+    const double X = ((p.gamma_see * F) * p.dt_s) / d.w;
+    const double fl = std::floor(X);
+    const double ub = uniform_f64(st);
+    int64_t ns = (int64_t)fl + ((ub < X - fl) ? 1 : 0);
+    if (ns > kSeeMaxPerSide) {
+      ctr.see_clamped += (uint64_t)(ns - kSeeMaxPerSide);
+      ns = kSeeMaxPerSide;
+    }
+    const double v = std::sqrt(p.e_sec_eV * d.invKE);
+    for (int64_t s = 0; s < ns; ++s) {
+      const double uc = uniform_f64(st);
+      const double cth = std::sqrt(uc);
+      const double sth = std::sqrt(1.0 - uc);
+      double a = 1.0, b = 0.0, qq = 1.0;
+      for (int t = 0; t < kSphereTries; ++t) {
+        const double ta = 2.0 * uniform_f64(st) - 1.0;
+        const double tb = 2.0 * uniform_f64(st) - 1.0;
+        const double tq = ta * ta + tb * tb;
+        if (tq < 1.0 && tq > 0.0) {
+          a = ta;
+          b = tb;
+          qq = tq;
+          break;
+        }
+      }
+      const double cph = (a * a - b * b) / qq;
+      const double sph = (2.0 * a * b) / qq;
+      const double vz = v * cth;
+      const double vp = v * sth;
+      const double upp = uniform_f64(st);
+      const double flight = (vz * p.dt_s) * upp;
+      const double z = side == 0 ? flight : d.L - flight;
+      const double sc = z / d.dz;
+      const double fc = std::floor(sc);
+      int32_t c = (int32_t)fc;
+      P off = (P)(sc - fc);
+      if (off == (P)1) {
+        c = c + 1;
+        off = (P)0;
+      }
+      ctr.emitted[side] += 1;
+      if (c < 0 || c >= d.nc) {
+        ctr.absorbed[side] += 1;
+        continue;
+      }
+      Particle<P> e;
+      e.c = c;
+      e.off = off;
+      e.vx = (P)(vp * cph);
+      e.vy = (P)(vp * sph);
+      e.vz = (P)(side == 0 ? vz : -vz);
+      e.id = 0;
+      out.push_back(e);
+    }
+  }
+
+  // The canonical step n (see DESIGN notes in the repository):
+  //  1. field from cnt^n, n_i^n and V(t_n);  2. ion fluid with E^n;
+  //  3. every particle in array order: push, removal, collision, deposit
+  //     (children deposited and their ions recorded at the parent position);
+  //  4. secondary emission from the step-2 wall fluxes;  5. append children,
+  //  then left then right secondaries, with consecutive ids;  6. ion sources,
+  //  run accumulators;  7. every sort_every steps drop holes and sort stably
+  //  by cell.
+  int do_step() override {
+    const uint32_t n = (uint32_t)step;
+    field();
+    for (int j = 0; j < d.nn; ++j) Ep[j] = (P)(d.qm_dt * E[j]);
+    double gw[2];
+    if (p.ion_model == 0)
+      fluid_dd(d, p.mu_const, ni.data(), E.data(), gam.data(), gw);
+    else
+      fluid_full(d, p.nu_const, ni.data(), E.data(), gam.data(), gw);
+    std::vector<int64_t> nxt(d.nn, 0);
+    std::vector<Particle<P>> kids;
+    const bool sample = ((step + 1) % p.eedf_every) == 0;
+    for (size_t k = 0; k < parts.size(); ++k) {
+      Particle<P>& pt = parts[k];
+      if (pt.c < 0) continue;
+      const int out = push<P>(pt.c, pt.off, pt.vz, Ep.data(), d.nc, q.kdz);
+      if (out != 0) {
+        ctr.absorbed[out - 1] += 1;
+        pt.c = -1;
+        continue;
+      }
+      Mcc<P> r = collide<P>(pt, q, p.seed, n);
+      if (r.overflow) ctr.overflow += 1;
+      if (r.channel >= 0) ctr.coll[r.channel] += 1;
+      deposit<P>(pt.c, pt.off, nxt.data());
+      if (sample) eedf[eedf_bin(pt, q)] += 1;
+      if (r.child) {
+        deposit<P>(r.kid.c, r.kid.off, nxt.data());
+        deposit<P>(r.kid.c, r.kid.off, ion_src.data());
+        if (sample) eedf[eedf_bin(r.kid, q)] += 1;
+        ctr.created += 1;
+        kids.push_back(r.kid);
+      }
+    }
+    std::vector<Particle<P>> see[2];
+    emit(0, std::max(-gw[0], 0.0), n, see[0]);
+    emit(1, std::max(gw[1], 0.0), n, see[1]);
+    for (int s = 0; s < 2; ++s)
+      for (auto& e : see[s]) deposit<P>(e.c, e.off, nxt.data());
+    for (auto& e : kids) {
+      e.id = next_id++;
+      parts.push_back(e);
+    }
+    for (int s = 0; s < 2; ++s)
+      for (auto& e : see[s]) {
+        e.id = next_id++;
+        parts.push_back(e);
+      }
+    cnt.swap(nxt);
+    for (int j = 0; j < d.nn; ++j) {
+      ni[j] = ni[j] + (double)ion_src[j] * d.scale[j];
+      ion_src[j] = 0;
+      acc_cnt[j] += (uint64_t)cnt[j];
+      acc_ni[j] += ni[j];
+    }
+    n_acc += 1;
+    step += 1;
+    if (step % p.sort_every == 0) {
+      std::vector<Particle<P>> live;
+      live.reserve(parts.size());
+      for (auto& e : parts)
+        if (e.c >= 0) live.push_back(e);
+      std::stable_sort(live.begin(), live.end(),
+                       [](const Particle<P>& x, const Particle<P>& y) { return x.c < y.c; });
+      parts.swap(live);
+    }
+    return 0;
+  }
+
+  int64_t count() const override { return (int64_t)parts.size(); }
+  void get(int32_t* c, void* off, void* vx, void* vy, void* vz, uint32_t* id) const override {
+    for (size_t k = 0; k < parts.size(); ++k) {
+      const Particle<P>& e = parts[k];
+      if (c) c[k] = e.c;
+      if (off) ((P*)off)[k] = e.off;
+      if (vx) ((P*)vx)[k] = e.vx;
+      if (vy) ((P*)vy)[k] = e.vy;
+      if (vz) ((P*)vz)[k] = e.vz;
+      if (id) id[k] = e.id;
+    }
+  }
+  void get_ep(void* out) const override {
+    std::vector<double> ne2(d.nn), rho2(d.nn), phi2(d.nn), E2(d.nn);
+    field_solve(d, cnt.data(), ni.data(), volt(step), ne2.data(), rho2.data(), phi2.data(),
+                E2.data());
+    for (int j = 0; j < d.nn; ++j) ((P*)out)[j] = (P)(d.qm_dt * E2[j]);
+  }
+  void set_particles(int64_t n, const int32_t* c, const void* off, const void* vx, const void* vy,
+                     const void* vz, const uint32_t* id) override {
+    parts.resize((size_t)n);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t k = 0; k < n; ++k) {
+      Particle<P>& e = parts[(size_t)k];
+      e.c = c[k];
+      e.off = ((const P*)off)[k];
+      e.vx = ((const P*)vx)[k];
+      e.vy = ((const P*)vy)[k];
+      e.vz = ((const P*)vz)[k];
+      e.id = id[k];
+      if (e.c >= 0) deposit<P>(e.c, e.off, cnt.data());
+    }
+  }
+};
+
+Base* make(const orc_params* pp) {
+  if (!pp) {
+    g_err = "null params";
+    return nullptr;
+  }
+  Base* b = nullptr;
+  if (pp->precision == 0)
+    b = new Discharge<float>();
+  else
+    b = new Discharge<double>();
+  b->p = *pp;
+  // keep private copies of the cross sections
+  b->sig.resize(pp->n_channels > 0 ? pp->n_channels : 0);
+  b->ch.resize(b->sig.size());
+  for (size_t k = 0; k < b->sig.size(); ++k) {
+    if (!pp->channels || !pp->channels[k].sigma_m2 || pp->n_energy < 2) {
+      g_err = "missing cross section";
+      delete b;
+      return nullptr;
+    }
+    b->sig[k].assign(pp->channels[k].sigma_m2, pp->channels[k].sigma_m2 + pp->n_energy);
+    b->ch[k] = pp->channels[k];
+    b->ch[k].sigma_m2 = b->sig[k].data();
+  }
+  b->p.channels = b->ch.empty() ? nullptr : b->ch.data();
+  if (!derive(b->p, b->d)) {
+    delete b;
+    return nullptr;
+  }
+  bool ok = (pp->precision == 0) ? static_cast<Discharge<float>*>(b)->init()
+                                 : static_cast<Discharge<double>*>(b)->init();
+  if (!ok) {
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C interface for the Python test harness.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* orc_last_error(void) { return g_err.c_str(); }
+
+void* orc_create(const orc_params* p) { return make(p); }
+void orc_free(void* h) { delete static_cast<Base*>(h); }
+
+int orc_step(void* h, int64_t n) {
+  Base* b = static_cast<Base*>(h);
+  for (int64_t i = 0; i < n; ++i)
+    if (b->do_step() != 0) return -1;
+  return 0;
+}
+
+int64_t orc_step_index(void* h) { return static_cast<Base*>(h)->step; }
+int64_t orc_num_particles(void* h) { return static_cast<Base*>(h)->count(); }
+uint32_t orc_next_id(void* h) { return static_cast<Base*>(h)->next_id; }
+
+void orc_get_particles(void* h, int32_t* c, void* off, void* vx, void* vy, void* vz, uint32_t* id) {
+  static_cast<Base*>(h)->get(c, off, vx, vy, vz, id);
+}
+
+// Replace the particle population (testing hook): cnt is re-deposited from
+// the given particles; ion fields are left untouched.
+void orc_set_particles(void* h, int64_t n, const int32_t* c, const void* off, const void* vx,
+                       const void* vy, const void* vz, const uint32_t* id) {
+  static_cast<Base*>(h)->set_particles(n, c, off, vx, vy, vz, id);
+}
+
+void orc_set_ions(void* h, const double* ni, const double* gam) {
+  Base* b = static_cast<Base*>(h);
+  if (ni) std::copy(ni, ni + b->d.nn, b->ni.begin());
+  if (gam) std::copy(gam, gam + b->d.nn, b->gam.begin());
+}
+
+// Grid state at the current step: cnt^n, n_i^n, Gamma, and the field of step n
+// (phi, E, E' rounded to the particle precision) computed from them.
+void orc_get_grid(void* h, int64_t* cnt, double* ni, double* gam, double* ne, double* phi,
+                  double* E, void* Ep) {
+  Base* b = static_cast<Base*>(h);
+  const int nn = b->d.nn;
+  std::vector<double> ne2(nn), rho2(nn), phi2(nn), E2(nn);
+  field_solve(b->d, b->cnt.data(), b->ni.data(), b->volt(b->step), ne2.data(), rho2.data(),
+              phi2.data(), E2.data());
+  for (int j = 0; j < nn; ++j) {
+    if (cnt) cnt[j] = b->cnt[j];
+    if (ni) ni[j] = b->ni[j];
+    if (gam) gam[j] = b->gam[j];
+    if (ne) ne[j] = ne2[j];
+    if (phi) phi[j] = phi2[j];
+    if (E) E[j] = E2[j];
+  }
+  if (Ep) b->get_ep(Ep);
+}
+
+// counters: [coll[0..15], absorbed L, absorbed R, emitted L, emitted R,
+//            created, overflow, see_clamped, n_acc]  (24 values)
+void orc_get_counters(void* h, uint64_t* out) {
+  Base* b = static_cast<Base*>(h);
+  for (int k = 0; k < kMaxChannels; ++k) out[k] = b->ctr.coll[k];
+  out[16] = b->ctr.absorbed[0];
+  out[17] = b->ctr.absorbed[1];
+  out[18] = b->ctr.emitted[0];
+  out[19] = b->ctr.emitted[1];
+  out[20] = b->ctr.created;
+  out[21] = b->ctr.overflow;
+  out[22] = b->ctr.see_clamped;
+  out[23] = b->n_acc;
+}
+
+void orc_get_accum(void* h, uint64_t* acc_cnt, double* acc_ni, uint64_t* eedf) {
+  Base* b = static_cast<Base*>(h);
+  if (acc_cnt) std::copy(b->acc_cnt.begin(), b->acc_cnt.end(), acc_cnt);
+  if (acc_ni) std::copy(b->acc_ni.begin(), b->acc_ni.end(), acc_ni);
+  if (eedf) std::copy(b->eedf.begin(), b->eedf.end(), eedf);
+}
+
+// Derived scalars: [dz, w, nu_max, Pmax, KE, invKE, kdz, delta, keedf, qm_dt,
+//                   kappa, TN, M, nfloor]
+void orc_get_derived(void* h, double* out) {
+  const Derived& d = static_cast<Base*>(h)->d;
+  const double v[] = {d.dz, d.w, d.nu_max, d.Pmax, d.KE, d.invKE, d.kdz,
+                      d.delta, d.keedf, d.qm_dt, d.kappa, d.TN, d.M, d.nfloor};
+  std::copy(v, v + 14, out);
+}
+
+// The cumulative collision-probability table (FP64, n_energy x K).
+void orc_get_table(void* h, double* out) {
+  const Derived& d = static_cast<Base*>(h)->d;
+  std::copy(d.cum.begin(), d.cum.end(), out);
+}
+
+// ---- unit-level entry points used by the pins --------------------------
+
+void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+  philox4x32_10(ctr, key, out);
+}
+
+// n uniforms of stream S(tag, id, step) in the given precision.
+void orc_uniforms(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step, int precision, int64_t n,
+                  double* out) {
+  Stream s(seed, tag, id, step);
+  for (int64_t i = 0; i < n; ++i) out[i] = precision == 0 ? (double)uniform_f32(s) : uniform_f64(s);
+}
+
+void orc_thomas(int n, const double* a, const double* b, const double* c, const double* d,
+                double* x) {
+  thomas(n, a, b, c, d, x);
+}
+
+// Field solve for a discharge's geometry with externally given cnt, n_i, V.
+void orc_field(void* h, const int64_t* cnt, const double* ni, double V, double* phi, double* E) {
+  Base* b = static_cast<Base*>(h);
+  const int nn = b->d.nn;
+  std::vector<double> ne2(nn), rho2(nn);
+  field_solve(b->d, cnt, ni, V, ne2.data(), rho2.data(), phi, E);
+}
+
+// One ion-fluid update in place (n_i, Gamma) with a given E; returns wall fluxes.
+void orc_fluid(void* h, double* ni, double* gam, const double* E, double* gw) {
+  Base* b = static_cast<Base*>(h);
+  if (b->p.ion_model == 0)
+    fluid_dd(b->d, b->p.mu_const, ni, E, gam, gw);
+  else
+    fluid_full(b->d, b->p.nu_const, ni, E, gam, gw);
+}
+
+// Push n particles (precision 0: float arrays, 1: double arrays) through
+// `steps` leapfrog steps in a fixed E' (node array of length nc+1).  status[k]
+// is 0 inside, 1/2 when removed through the left/right wall (then frozen).
+void orc_push(int precision, int64_t n, int32_t* c, void* off, void* vz, const void* Ep, int nc,
+              double kdz, int64_t steps, int32_t* status) {
+  for (int64_t k = 0; k < n; ++k) status[k] = 0;
+  for (int64_t s = 0; s < steps; ++s)
+    for (int64_t k = 0; k < n; ++k) {
+      if (status[k] != 0) continue;
+      if (precision == 0)
+        status[k] = push<float>(c[k], ((float*)off)[k], ((float*)vz)[k], (const float*)Ep, nc,
+                                (float)kdz);
+      else
+        status[k] = push<double>(c[k], ((double*)off)[k], ((double*)vz)[k], (const double*)Ep, nc,
+                                 kdz);
+    }
+}
+
+// Collision step of a discharge's tables for n particles at step `step`
+// (positions untouched).  channel[k] = -1 for no collision; child velocities
+// written for ionizations (kid_v: n x 3, zero otherwise).
+void orc_collide(void* h, int64_t n, const int32_t* c, const void* off, void* vx, void* vy,
+                 void* vz, const uint32_t* id, uint32_t step, int32_t* channel, void* kid_v) {
+  Base* b = static_cast<Base*>(h);
+  if (b->p.precision == 0) {
+    auto* D = static_cast<Discharge<float>*>(b);
+    for (int64_t k = 0; k < n; ++k) {
+      Particle<float> pt{c[k], ((const float*)off)[k], ((float*)vx)[k], ((float*)vy)[k],
+                         ((float*)vz)[k], id[k]};
+      Mcc<float> r = collide<float>(pt, D->q, b->p.seed, step);
+      ((float*)vx)[k] = pt.vx;
+      ((float*)vy)[k] = pt.vy;
+      ((float*)vz)[k] = pt.vz;
+      channel[k] = r.channel;
+      float* kv = (float*)kid_v + 3 * k;
+      kv[0] = r.child ? r.kid.vx : 0.f;
+      kv[1] = r.child ? r.kid.vy : 0.f;
+      kv[2] = r.child ? r.kid.vz : 0.f;
+    }
+  } else {
+    auto* D = static_cast<Discharge<double>*>(b);
+    for (int64_t k = 0; k < n; ++k) {
+      Particle<double> pt{c[k], ((const double*)off)[k], ((double*)vx)[k], ((double*)vy)[k],
+                          ((double*)vz)[k], id[k]};
+      Mcc<double> r = collide<double>(pt, D->q, b->p.seed, step);
+      ((double*)vx)[k] = pt.vx;
+      ((double*)vy)[k] = pt.vy;
+      ((double*)vz)[k] = pt.vz;
+      channel[k] = r.channel;
+      double* kv = (double*)kid_v + 3 * k;
+      kv[0] = r.child ? r.kid.vx : 0.0;
+      kv[1] = r.child ? r.kid.vy : 0.0;
+      kv[2] = r.child ? r.kid.vz : 0.0;
+    }
+  }
+}
+
+// Unit sphere samples from stream S(tag 0, id, step), one per id.
+void orc_sphere(int precision, uint64_t seed, int64_t n, const uint32_t* id, uint32_t step,
+                double* out) {
+  for (int64_t k = 0; k < n; ++k) {
+    Stream s(seed, kTagElectron, id[k], step);
+    if (precision == 0) {
+      float v[3];
+      sphere<float>(s, v);
+      for (int i = 0; i < 3; ++i) out[3 * k + i] = v[i];
+    } else {
+      double v[3];
+      sphere<double>(s, v);
+      for (int i = 0; i < 3; ++i) out[3 * k + i] = v[i];
+    }
+  }
+}
+
+// CIC deposit of n particles into g (length nc+1).
+void orc_deposit(int precision, int64_t n, const int32_t* c, const void* off, int64_t* g) {
+  for (int64_t k = 0; k < n; ++k) {
+    if (c[k] < 0) continue;
+    if (precision == 0)
+      deposit<float>(c[k], ((const float*)off)[k], g);
+    else
+      deposit<double>(c[k], ((const double*)off)[k], g);
+  }
+}
+
+// Secondary emission of one side for wall flux F at step n: returns the number
+// of emitted particles (<= cap) and writes their state.
+int64_t orc_emit(void* h, int side, double F, uint32_t n, int32_t* c, void* off, void* vx, void* vy,
+                 void* vz, int64_t cap) {
+  Base* b = static_cast<Base*>(h);
+  int64_t m = 0;
+  if (b->p.precision == 0) {
+    std::vector<Particle<float>> out;
+    static_cast<Discharge<float>*>(b)->emit(side, F, n, out);
+    for (auto& e : out) {
+      if (m >= cap) break;
+      c[m] = e.c;
+      ((float*)off)[m] = e.off;
+      ((float*)vx)[m] = e.vx;
+      ((float*)vy)[m] = e.vy;
+      ((float*)vz)[m] = e.vz;
+      ++m;
+    }
+  } else {
+    std::vector<Particle<double>> out;
+    static_cast<Discharge<double>*>(b)->emit(side, F, n, out);
+    for (auto& e : out) {
+      if (m >= cap) break;
+      c[m] = e.c;
+      ((double*)off)[m] = e.off;
+      ((double*)vx)[m] = e.vx;
+      ((double*)vy)[m] = e.vy;
+      ((double*)vz)[m] = e.vz;
+      ++m;
+    }
+  }
+  return m;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+"""Whole-step invariants of the oracle discharge: initial load, exact charge
+bookkeeping, ion-source accounting, compaction + stable sort, and the EEDF of
+an undriven Maxwellian."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_02892_amd import workloads as W
+
+E_CH = 1.602176634e-19
+ME = 9.1093837015e-31
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_initial_load_statistics(precision):
+    p = W.small(precision=precision, n_cells=128, n_macro=50_000, gap_m=1e-3)
+    o = oracle.Oracle(p)
+    g = o.grid()
+    assert int(g["cnt"].sum()) == 50_000 * 2 ** 32
+    np.testing.assert_array_equal(g["n_i"], g["n_e"])
+    pt = o.particles()
+    z = (pt["cell"] + pt["off"].astype(np.float64)) / 128
+    assert z.min() >= 0.2 - 1e-9 and z.max() < 0.8 + 1e-9
+    assert abs(z.mean() - 0.5) < 5 * 0.6 / np.sqrt(12 * len(z))
+    vth2 = 2.0 * E_CH / ME
+    for k in ("vx", "vy", "vz"):
+        v = pt[k].astype(np.float64)
+        assert abs(v.mean()) < 5 * np.sqrt(vth2 / len(v))
+        assert abs(v.var() / vth2 - 1) < 5 * np.sqrt(2 / len(v))
+    np.testing.assert_array_equal(pt["id"], np.arange(50_000))
+
+
+def _hot(precision, **kw):
+    # a hot plasma (50 eV) ionizes at a good rate; a strong drive at its peak
+    # (phase pi/2) pushes ions into the powered electrode and feeds emission
+    return W.small(precision=precision, n_cells=64, n_macro=20_000, t_e0_eV=50.0,
+                   v_amp_V=2000.0, phase_rad=np.pi / 2, gamma_see=1.0, load_lo=0.0,
+                   load_hi=1.0, **kw)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_particle_and_charge_bookkeeping(precision):
+    o = oracle.Oracle(_hot(precision, ion_model=1))
+    for _ in range(40):
+        o.step(1)
+        g = o.grid()
+        pt = o.particles()
+        live = int((pt["cell"] >= 0).sum())
+        assert int(g["cnt"].sum()) == live * 2 ** 32
+    c = o.counters()
+    assert c["created"] > 0 and c["absorbed"].sum() > 0 and c["emitted"].sum() > 0
+    assert live == 20_000 + c["created"] + c["emitted"].sum() - c["absorbed"].sum()
+    assert c["coll"][2] == c["created"]
+    assert o.next_id == 20_000 + c["created"] + c["emitted"].sum()
+    ids = pt["id"][pt["cell"] >= 0]
+    assert len(np.unique(ids)) == len(ids)
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_ion_sources_match_created_electrons(model):
+    o = oracle.Oracle(_hot(1, ion_model=model))
+    d = o.derived()
+    dV = np.full(65, d["dz"])
+    dV[0] = dV[-1] = d["dz"] / 2
+    for _ in range(12):
+        g0 = o.grid()
+        c0 = o.counters()["created"]
+        # replay the fluid update alone on the same state to isolate the sources
+        ni_f, _, gw = o.fluid(g0["n_i"], g0["gamma"], g0["E"])
+        o.step(1)
+        g1 = o.grid()
+        made = o.counters()["created"] - c0
+        src = ((g1["n_i"] - ni_f) * dV).sum()
+        assert src == pytest.approx(made * d["w"], rel=1e-9, abs=1e-6 * d["w"])
+
+
+def test_compaction_and_sort_equal_stable_sort_by_cell():
+    p = _hot(0)
+    a = oracle.Oracle(dict(p, sort_every=100000))
+    b = oracle.Oracle(dict(p, sort_every=16))
+    a.step(16)
+    b.step(16)
+    pa, pb = a.particles(), b.particles()
+    live = pa["cell"] >= 0
+    order = np.argsort(pa["cell"][live], kind="stable")
+    for k in ("cell", "off", "vx", "vy", "vz", "id"):
+        np.testing.assert_array_equal(pb[k], pa[k][live][order])
+    np.testing.assert_array_equal(a.grid()["cnt"], b.grid()["cnt"])
+
+
+def test_eedf_of_undriven_maxwellian():
+    # No drive, elastic-only, 16 steps: the population stays a 2 eV Maxwellian,
+    # f(E) dE ~ sqrt(E) exp(-E/T) dE.
+    chans = [W.he_channels()[0]]
+    p = W.small(precision=1, n_cells=64, n_macro=200_000, v_amp_V=0.0, channels=chans,
+                eedf_every=16, gamma_see=0.0)
+    o = oracle.Oracle(p)
+    o.step(16)
+    h = o.accum()["eedf"].astype(np.float64)
+    assert h.sum() == (o.particles()["cell"] >= 0).sum()
+    edges = np.linspace(0, 50, 129)
+    from scipy.special import gammainc
+    T = 2.0
+    cdf = gammainc(1.5, edges / T)
+    expect = np.diff(cdf) * h.sum()
+    expect = np.append(expect, (1 - cdf[-1]) * h.sum())
+    m = expect > 20
+    chi2 = ((h[m] - expect[m]) ** 2 / expect[m]).sum()
+    assert chi2 < m.sum() + 6 * np.sqrt(2 * m.sum())

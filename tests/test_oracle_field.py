@@ -1,0 +1,100 @@
+"""Pins of the oracle's field solve and tridiagonal solver against dense
+linear algebra, closed forms and the discrete Gauss law."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_02892_amd import workloads as W
+
+E_CH = 1.602176634e-19
+EPS0 = 8.8541878128e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 200])
+def test_thomas_matches_dense_solve(n):
+    rng = np.random.default_rng(n)
+    a = rng.normal(size=n)
+    c = rng.normal(size=n)
+    b = np.abs(a) + np.abs(c) + 1.0 + rng.random(n)
+    d = rng.normal(size=n)
+    x = oracle.thomas(a, b, c, d)
+    A = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+    np.testing.assert_allclose(x, np.linalg.solve(A, d), rtol=1e-12, atol=1e-14)
+
+
+def _disch(nc, gap=1e-3):
+    return oracle.Oracle(W.small(n_cells=nc, n_macro=0, gap_m=gap))
+
+
+def _dense_phi(nc, dz, rho, V):
+    m = nc - 1
+    A = 2 * np.eye(m) - np.eye(m, k=1) - np.eye(m, k=-1)
+    rhs = dz * dz / EPS0 * rho[1:nc].copy()
+    rhs[0] += V
+    phi = np.zeros(nc + 1)
+    phi[0] = V
+    phi[1:nc] = np.linalg.solve(A, rhs)
+    return phi
+
+
+@pytest.mark.parametrize("nc", [2, 3, 8, 16, 64])
+def test_poisson_matches_dense_solve(nc):
+    o = _disch(nc)
+    dz = o.derived()["dz"]
+    rng = np.random.default_rng(nc)
+    ni = rng.uniform(0, 1e17, nc + 1)
+    phi, E = o.field(np.zeros(nc + 1, np.int64), ni, 37.5)
+    rho = E_CH * ni
+    np.testing.assert_allclose(phi, _dense_phi(nc, dz, rho, 37.5), rtol=1e-11, atol=1e-12)
+
+
+def test_vacuum_field_is_linear():
+    nc = 64
+    o = _disch(nc)
+    L = 1e-3
+    phi, E = o.field(np.zeros(nc + 1, np.int64), np.zeros(nc + 1), 150.0)
+    z = np.arange(nc + 1) * L / nc
+    np.testing.assert_allclose(phi, 150.0 * (1 - z / L), rtol=1e-13, atol=1e-11)
+    np.testing.assert_allclose(E, 150.0 / L, rtol=1e-12)
+
+
+def test_uniform_charge_gives_exact_parabola():
+    # -phi'' = rho/eps0 with phi(0) = V, phi(L) = 0: the 3-point scheme is
+    # exact for quadratics.
+    nc, L, V, n0 = 128, 1e-3, 80.0, 3e17
+    o = _disch(nc, L)
+    phi, E = o.field(np.zeros(nc + 1, np.int64), np.full(nc + 1, n0), V)
+    rho = E_CH * n0
+    z = np.arange(nc + 1) * L / nc
+    exact = V * (1 - z / L) + rho * z * (L - z) / (2 * EPS0)
+    np.testing.assert_allclose(phi, exact, rtol=1e-11, atol=1e-10 * abs(exact).max())
+    Ez = V / L - rho * (L - 2 * z) / (2 * EPS0)  # E = -phi'
+    np.testing.assert_allclose(E, Ez, rtol=1e-9, atol=1e-9 * abs(Ez).max())
+
+
+def test_discrete_gauss_law():
+    nc = 96
+    o = _disch(nc)
+    d = o.derived()
+    rng = np.random.default_rng(7)
+    cnt = rng.integers(0, 2 ** 40, nc + 1).astype(np.int64)
+    ni = rng.uniform(0, 2e17, nc + 1)
+    phi, E = o.field(cnt, ni, -20.0)
+    dV = np.full(nc + 1, d["dz"])
+    dV[0] = dV[-1] = d["dz"] / 2
+    ne = cnt.astype(np.float64) * (d["w"] * 2.0 ** -32) / dV
+    rho = E_CH * (ni - ne)
+    lhs = E[-1] - E[0]
+    rhs = (rho * dV).sum() / EPS0
+    assert abs(lhs - rhs) <= 1e-9 * (abs(E).max())
+
+
+def test_electron_density_from_counts():
+    o = oracle.Oracle(W.small(n_cells=32, n_macro=512))
+    g = o.grid()
+    d = o.derived()
+    dV = np.full(33, d["dz"])
+    dV[0] = dV[-1] = d["dz"] / 2
+    np.testing.assert_allclose(g["n_e"], g["cnt"] * (d["w"] * 2.0 ** -32) / dV, rtol=1e-15)
+    # ions start as the deposited electron density: zero net charge
+    np.testing.assert_array_equal(g["n_i"], g["n_e"])

@@ -1,0 +1,154 @@
+"""Pins of the oracle's null-collision Monte Carlo: collision counts against
+the binomial law of the null-collision method, channel fractions, energy
+bookkeeping of each channel and isotropy of the scattering directions."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_02892_amd import workloads as W
+
+E_CH = 1.602176634e-19
+ME = 9.1093837015e-31
+NG = 2.45e25
+DT = 2e-14
+
+
+def _speed(eV):
+    return np.sqrt(2 * E_CH * eV / ME)
+
+
+def _disch(channels, precision=1, m_gas=W.HE_AMU):
+    return oracle.Oracle(W.small(precision=precision, n_macro=0, n_cells=16, channels=channels,
+                                 m_gas_amu=m_gas))
+
+
+def _beam(n, eV, precision, rng=None):
+    v = _speed(eV)
+    if rng is None:
+        vx, vy, vz = np.zeros(n), np.zeros(n), np.full(n, v)
+    else:
+        u = rng.normal(size=(n, 3))
+        u /= np.linalg.norm(u, axis=1)[:, None]
+        vx, vy, vz = (v * u[:, 0], v * u[:, 1], v * u[:, 2])
+    return (np.full(n, 3, np.int32), np.full(n, 0.5), vx, vy, vz,
+            np.arange(n, dtype=np.uint32))
+
+
+def _binom_ok(k, n, p, nsig=5.0):
+    return abs(k - n * p) <= nsig * np.sqrt(n * p * (1 - p)) + 1
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_constant_frequency_collision_count(precision):
+    # sigma ~ 1/sqrt(E) makes nu = N_g sigma v constant = nu_max, so every
+    # particle collides with probability 1 - exp(-nu dt) per step.
+    Eg = W.energy_grid()
+    sig = np.zeros_like(Eg)
+    sig[1:] = 2e-20 / np.sqrt(Eg[1:] / 10.0)
+    o = _disch([{"kind": "elastic", "threshold_eV": 0.0, "sigma_m2": sig}], precision,
+               m_gas=1e12)
+    nu = NG * 2e-20 * _speed(10.0)
+    p = 1 - np.exp(-nu * DT)
+    assert o.derived()["nu_max"] == pytest.approx(nu, rel=1e-12)
+    n = 200_000
+    ch, *_ = o.collide(*_beam(n, 10.0, precision), step=0)
+    assert _binom_ok((ch == 0).sum(), n, p)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_constant_cross_section_count_is_nullcollision_binomial(precision):
+    Eg = W.energy_grid()
+    o = _disch([{"kind": "elastic", "threshold_eV": 0.0, "sigma_m2": np.full_like(Eg, 5e-20)}],
+               precision, m_gas=1e12)
+    nu_max = NG * 5e-20 * _speed(Eg[-1])
+    Pmax = 1 - np.exp(-nu_max * DT)
+    p = Pmax * (NG * 5e-20 * _speed(4.0)) / nu_max
+    n = 200_000
+    ch, *_ = o.collide(*_beam(n, 4.0, precision), step=3)
+    assert _binom_ok((ch == 0).sum(), n, p)
+    # N_g sigma v dt agrees with the per-step probability to first order
+    assert p == pytest.approx(NG * 5e-20 * _speed(4.0) * DT, rel=0.2)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_channel_fractions_at_100eV(precision):
+    chans = W.he_channels()
+    o = _disch(chans, precision)
+    Eg = W.energy_grid()
+    v = np.sqrt(2 * E_CH * Eg / ME)
+    nus = np.array([NG * c["sigma_m2"] * v for c in chans])
+    nu_max = nus.sum(axis=0).max()
+    Pmax = 1 - np.exp(-nu_max * DT)
+    i100 = 1000
+    n = 400_000
+    ch, *_ = o.collide(*_beam(n, 100.0, precision), step=7)
+    for k in range(3):
+        pk = Pmax * nus[k, i100] / nu_max
+        assert _binom_ok((ch == k).sum(), n, pk), k
+    assert ((ch >= -1) & (ch <= 2)).all()
+
+
+def _energy(vx, vy, vz):
+    return 0.5 * ME * (vx.astype(np.float64) ** 2 + vy.astype(np.float64) ** 2 +
+                       vz.astype(np.float64) ** 2) / E_CH
+
+
+@pytest.mark.parametrize("precision,rtol", [(0, 2e-6), (1, 1e-13)])
+def test_excitation_loses_exactly_the_threshold(precision, rtol):
+    Eg = W.energy_grid()
+    sig = np.where(Eg >= 5.0, 1e-19, 0.0)
+    o = _disch([{"kind": "excitation", "threshold_eV": 5.0, "sigma_m2": sig}], precision)
+    n = 20000
+    b = _beam(n, 30.0, precision, np.random.default_rng(1))
+    E0 = _energy(*(np.asarray(x, pdt := oracle.pdtype(precision)) for x in b[2:5]))
+    ch, vx, vy, vz, _ = o.collide(*b, step=1)
+    hit = ch == 0
+    assert hit.sum() > 100
+    np.testing.assert_allclose(_energy(vx, vy, vz)[hit], E0[hit] - 5.0, rtol=rtol)
+    np.testing.assert_allclose(_energy(vx, vy, vz)[~hit], E0[~hit], rtol=rtol)
+
+
+@pytest.mark.parametrize("precision,rtol", [(0, 2e-6), (1, 1e-13)])
+def test_ionization_shares_the_remaining_energy(precision, rtol):
+    Eg = W.energy_grid()
+    sig = np.where(Eg >= 10.0, 1e-19, 0.0)
+    o = _disch([{"kind": "ionization", "threshold_eV": 10.0, "sigma_m2": sig}], precision)
+    n = 20000
+    b = _beam(n, 60.0, precision, np.random.default_rng(2))
+    E0 = _energy(*(np.asarray(x, oracle.pdtype(precision)) for x in b[2:5]))
+    ch, vx, vy, vz, kid = o.collide(*b, step=2)
+    hit = ch == 0
+    assert hit.sum() > 100
+    Ep = _energy(vx, vy, vz)[hit]
+    Es = _energy(kid[hit, 0], kid[hit, 1], kid[hit, 2])
+    np.testing.assert_allclose(Ep + Es, E0[hit] - 10.0, rtol=rtol)
+    # uniform split: the secondary's share is U(0,1)
+    share = Es / (E0[hit] - 10.0)
+    assert abs(share.mean() - 0.5) < 5 * np.sqrt(1 / 12 / hit.sum())
+    assert (kid[~hit] == 0).all()
+
+
+def test_elastic_mean_energy_loss_is_delta():
+    Eg = W.energy_grid()
+    o = _disch([{"kind": "elastic", "threshold_eV": 0.0,
+                 "sigma_m2": np.full_like(Eg, 2e-18)}], 1)
+    delta = o.derived()["delta"]
+    n = 200_000
+    b = _beam(n, 10.0, 1, np.random.default_rng(3))
+    ch, vx, vy, vz, _ = o.collide(*b, step=4)
+    hit = ch == 0
+    loss = 1 - _energy(vx, vy, vz)[hit] / 10.0
+    m = hit.sum()
+    assert abs(loss.mean() - delta) < 5 * delta * np.sqrt(1 / 3 / m)
+    assert loss.min() >= -1e-12 and loss.max() <= 2 * delta + 1e-12
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sphere_is_isotropic(precision):
+    n = 100_000
+    s = oracle.sphere(precision, 11, np.arange(n), 5)
+    tol = 1e-6 if precision == 0 else 1e-14
+    np.testing.assert_allclose((s ** 2).sum(axis=1), 1.0, atol=tol)
+    assert np.all(np.abs(s.mean(axis=0)) < 5 * np.sqrt(1 / 3 / n))
+    assert abs((s[:, 2] ** 2).mean() - 1 / 3) < 5 * np.sqrt(4 / 45 / n)
+    assert abs((s[:, 0] * s[:, 2]).mean()) < 5 * np.sqrt(1 / 15 / n)
