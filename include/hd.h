@@ -1,0 +1,213 @@
+/*
+ * hd.h -- C ABI of the MI355X (gfx950) hybrid PIC/MCC discharge stepper.
+ *
+ * Method: Eremin, Hemke & Mussenbrock, "A New Hybrid Scheme for Simulations
+ * of Highly Collisional RF-Driven Plasmas" (arXiv 1508.02892).  A 1D
+ * parallel-plate discharge (powered electrode at z = 0, grounded at z = L,
+ * Sec. II) with kinetic 1D3V PIC/MCC electrons (Sec. II.A) and a fluid ion
+ * species (Sec. II.B full model, Eqs 2.3-2.4; Sec. II.C drift-diffusion,
+ * Eqs 2.4-2.8), coupled through Poisson's equation, impact ionization and
+ * ion-induced secondary emission (Sec. II.D).
+ *
+ * Every step of the time loop runs in HIP kernels on the device; the host
+ * only validates parameters, computes derived constants and collision
+ * tables, performs the initial particle load and enqueues work.
+ *
+ * Conventions
+ *  - All functions return HD_OK (0) or a negative HD_E* code and never throw.
+ *    hd_last_error() returns a thread-local description of the last failure.
+ *  - Handles are not thread-safe: one handle is driven by one host thread,
+ *    and its work is enqueued on the stream given at creation.
+ *  - "Caller-owned" buffers are host memory unless stated otherwise; the
+ *    library copies what it needs and never keeps caller pointers.
+ *  - Units are SI except energies, which are in eV.
+ */
+#ifndef HD_H
+#define HD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HD_ABI_VERSION 1
+
+enum hd_status {
+  HD_OK = 0,
+  HD_EINVAL = -1,     /* invalid or inconsistent parameters / arguments      */
+  HD_ENOMEM = -2,     /* device allocation failed or arena too small          */
+  HD_EDEVICE = -3,    /* HIP runtime error (sticky for the handle)            */
+  HD_ECAPACITY = -4,  /* particle capacity exceeded; the step that overflowed
+                         was not appended, the handle refuses further steps   */
+  HD_ENUMERIC = -5,   /* non-finite field detected                            */
+  HD_ESTATE = -6      /* operation not valid in the handle's current state    */
+};
+
+enum hd_precision { HD_FP32 = 0, HD_FP64 = 1 };
+
+/* Ion model: drift-diffusion with constant mobility (Sec. II.C, explicit
+ * option) or the full fluid with inertia and constant momentum-exchange
+ * frequency (Sec. II.B, Eq 2.3 solved by the Thomas method). */
+enum hd_ion_model { HD_ION_DD_CONST_MU = 0, HD_ION_FULL_CONST_NU = 1 };
+
+/* Electron-neutral reaction kinds (Table 1: R1 elastic, R2 ionization,
+ * R3 excitation). */
+enum hd_xs_kind { HD_XS_ELASTIC = 0, HD_XS_EXCITATION = 1, HD_XS_IONIZATION = 2 };
+
+#define HD_MAX_CHANNELS 16
+
+/* One electron-neutral channel.  sigma_m2 holds n_energy cross sections [m^2]
+ * on the uniform grid E_i = i / inv_de_per_eV (caller-owned, copied). */
+typedef struct hd_xs_channel {
+  int32_t kind;          /* enum hd_xs_kind                                  */
+  int32_t reserved;
+  double threshold_eV;   /* energy lost in excitation / ionization           */
+  const double* sigma_m2;
+} hd_xs_channel;
+
+/* Problem statement of one discharge (caller-owned, copied at creation). */
+typedef struct hd_params {
+  int32_t abi_version;   /* must be HD_ABI_VERSION                           */
+  int32_t precision;     /* enum hd_precision: particle state and MCC math   */
+  int32_t ion_model;     /* enum hd_ion_model                                */
+  int32_t n_cells;       /* N_c >= 2 uniform cells; nodes j = 0 .. N_c       */
+  int32_t n_energy;      /* collision-table points (>= 2)                    */
+  int32_t n_channels;    /* 0 .. HD_MAX_CHANNELS                             */
+  int32_t sort_every;    /* compaction + stable cell sort every this many steps */
+  int32_t eedf_every;    /* EEDF sample every this many steps                */
+  int32_t n_eedf_bins;   /* EEDF bins over [0, eedf_emax_eV)                 */
+  int32_t reserved;
+  int64_t n_macro;       /* N_0 initial electron superparticles              */
+  int64_t capacity;      /* particle slots reserved (>= n_macro)             */
+  uint64_t seed;         /* Philox key                                       */
+  /* background gas: uniform, constant (Sec. II.A) */
+  double n_gas_m3, t_gas_K, m_gas_amu;
+  /* geometry */
+  double gap_m;
+  /* drive: V(t) = v_amp_V sin(2 pi f_rf_Hz t + phase_rad) at z = 0 */
+  double v_amp_V, f_rf_Hz, phase_rad;
+  /* electron load: uniform in [load_lo L, load_hi L), Maxwellian t_e0_eV;
+     superparticle weight from Eq 1.2 */
+  double n_e0_m3, t_e0_eV, load_lo, load_hi;
+  /* ion-induced secondary emission (Sec. II.D) */
+  double gamma_see, e_sec_eV;
+  /* ions: mass, constant mobility (DD) or momentum-exchange frequency (full) */
+  double m_ion_amu, mu_const, nu_const;
+  /* numerics */
+  double dt_s;
+  double inv_de_per_eV;  /* collision-table points per eV                    */
+  double eedf_emax_eV;
+  const hd_xs_channel* channels; /* n_channels entries, caller-owned, copied */
+} hd_params;
+
+/* Device context.  stream: a hipStream_t (NULL = the default stream).
+ * device: HIP device ordinal. */
+typedef struct hd_device_ctx {
+  void* stream;
+  int32_t device;
+  int32_t reserved;
+} hd_device_ctx;
+
+/* Moments of one discharge (Sec. III reports density profiles and the EEDF).
+ * Array pointers are caller-owned host buffers sized as noted; any may be
+ * NULL to skip it.  hd_moments fills the scalar fields and the non-NULL
+ * arrays. */
+typedef struct hd_moment_set {
+  int64_t step;            /* completed steps                                */
+  int64_t n_live;          /* live electron superparticles                   */
+  int64_t n_slots;         /* particle slots in use, including holes         */
+  int32_t n_nodes;         /* N_c + 1                                        */
+  int32_t n_channels;
+  int32_t n_eedf_bins;
+  int32_t error;           /* device-side sticky error (0 = none)            */
+  double* n_e;             /* [n_nodes] electron density of the current step */
+  double* n_i;             /* [n_nodes] ion density                          */
+  double* phi;             /* [n_nodes] potential of the current step [V]    */
+  double* E;               /* [n_nodes] field of the current step [V/m]      */
+  double* gamma_i;         /* [n_nodes] last ion flux [m^-2 s^-1]            */
+  double* n_e_avg;         /* [n_nodes] average of n_e over completed steps  */
+  double* n_i_avg;         /* [n_nodes] average of n_i over completed steps  */
+  int64_t* cnt;            /* [n_nodes] fixed-point deposit (2^32 per particle) */
+  uint64_t* eedf_counts;   /* [n_eedf_bins + 1], last entry = overflow       */
+  double* eedf;            /* [n_eedf_bins] normalised: sum f dE = 1         */
+  uint64_t coll[HD_MAX_CHANNELS];  /* collisions per channel                 */
+  uint64_t absorbed[2];    /* electrons absorbed at z = 0 / z = L            */
+  uint64_t emitted[2];     /* secondaries emitted at z = 0 / z = L           */
+  uint64_t created;        /* electrons created by ionization                */
+  uint64_t e_overflow;     /* collision candidates above the table's top     */
+  uint64_t see_clamped;    /* secondaries dropped by the per-step cap        */
+  uint64_t n_acc;          /* steps in the averages                          */
+} hd_moment_set;
+
+typedef struct hd_batch hd_batch;
+typedef struct hd_discharge hd_discharge;
+
+/* ---- library ------------------------------------------------------------ */
+
+int32_t hd_abi_version(void);
+const char* hd_last_error(void);
+
+/* Device bytes one discharge with these parameters occupies (0 if invalid). */
+size_t hd_required_bytes(const hd_params* params);
+
+/* ---- one discharge (Sec. II) -------------------------------------------- */
+
+/* Validates params, builds the null-collision tables (Sec. II.A), loads the
+ * electrons (Eqs 1.1-1.2) and ions, allocates device state and computes the
+ * field of step 0.  Synchronous.  *out is set only on HD_OK. */
+int hd_init_discharge(const hd_params* params, const hd_device_ctx* ctx, hd_discharge** out);
+
+/* Enqueues n_steps >= 0 time steps on the handle's stream and returns
+ * without waiting.  Each step: ion fluid and electron push / removal /
+ * null-collision MCC / CIC deposit, then emission, ion sources, averages,
+ * appending, the field of the next step, and every sort_every steps a
+ * compaction and stable cell sort. */
+int hd_step(hd_discharge* h, int64_t n_steps);
+
+/* Waits for the handle's stream and fills *out (see hd_moment_set). */
+int hd_moments(hd_discharge* h, hd_moment_set* out);
+
+/* Waits and copies the particle slots [0, n_slots) into caller-owned host
+ * arrays of length cap: cell (int32; -1 marks a hole), off/vx/vy/vz (float
+ * for HD_FP32, double for HD_FP64), id (uint32).  *n_out = n_slots.  Any
+ * array may be NULL.  HD_EINVAL if cap < n_slots. */
+int hd_get_particles(hd_discharge* h, int32_t* cell, void* off, void* vx, void* vy, void* vz,
+                     uint32_t* id, int64_t cap, int64_t* n_out);
+
+/* Waits and copies E' = (-e/m_e) dt E at the nodes, rounded to the particle
+ * precision (float or double array of n_nodes), as used by the next push. */
+int hd_get_push_field(hd_discharge* h, void* ep);
+
+/* Releases device state.  NULL-safe. */
+int hd_free(hd_discharge* h);
+
+/* ---- many independent discharges in one launch per phase ---------------- */
+
+/* All discharges of a batch share precision, sort_every and eedf_every;
+ * gap, grid, particle count, drive and seed may differ.  Each discharge's
+ * result is bitwise identical to a one-discharge run of the same params. */
+int hd_batch_create(const hd_params* const* params, int32_t n, const hd_device_ctx* ctx,
+                    hd_batch** out);
+int hd_batch_step(hd_batch* b, int64_t n_steps);
+int hd_batch_moments(hd_batch* b, int32_t index, hd_moment_set* out);
+int hd_batch_get_particles(hd_batch* b, int32_t index, int32_t* cell, void* off, void* vx,
+                           void* vy, void* vz, uint32_t* id, int64_t cap, int64_t* n_out);
+int hd_batch_free(hd_batch* b);
+
+/* ---- diagnostics -------------------------------------------------------- */
+
+/* Evaluates, on the device, the correctly-rounded primitives the particle
+ * arithmetic relies on, for n inputs: out[4k+0] = sqrt(a[k]),
+ * out[4k+1] = a[k] / b[k], out[4k+2] = rint(a[k] * 2^32),
+ * out[4k+3] = floor(a[k]).  precision selects float or double arrays
+ * (a, b, out of the given type, host memory).  Synchronous. */
+int hd_diag_arith(int32_t precision, int64_t n, const void* a, const void* b, void* out,
+                  const hd_device_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HD_H */

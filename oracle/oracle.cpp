@@ -720,6 +720,9 @@ struct Discharge : Base {
       deposit<P>(c, off, cnt.data());
     }
     next_id = (uint32_t)N;
+    // The load ends with the same stable sort by cell as the periodic one.
+    std::stable_sort(parts.begin(), parts.end(),
+                     [](const Particle<P>& x, const Particle<P>& y) { return x.c < y.c; });
   }
 
   // Secondary electrons from the ion wall flux (Sec. II.D): X = gamma F dt / w
@@ -762,13 +765,17 @@ struct Discharge : Base {
       const double z = side == 0 ? flight : d.L - flight;
       const double sc = z / d.dz;
       const double fc = std::floor(sc);
+      ctr.emitted[side] += 1;
+      if (!(fc > -2147483648.0 && fc < 2147483647.0)) {  // outside any cell index
+        ctr.absorbed[side] += 1;
+        continue;
+      }
       int32_t c = (int32_t)fc;
       P off = (P)(sc - fc);
       if (off == (P)1) {
         c = c + 1;
         off = (P)0;
       }
-      ctr.emitted[side] += 1;
       if (c < 0 || c >= d.nc) {
         ctr.absorbed[side] += 1;
         continue;

@@ -1,0 +1,120 @@
+// Internal layout of the discharge state in device memory, shared by the
+// kernels and the host runtime of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hd {
+
+constexpr int kMaxK = 16;          // collision channels
+constexpr int kThreads = 256;      // electron-kernel workgroup
+constexpr int kPerThread = 4;      // particles per thread per chunk (vector loads)
+constexpr int kTile = kThreads * kPerThread;  // particles per chunk
+constexpr int kQueue = 256;        // collision-queue entries per round
+constexpr int kSeeMax = 4096;      // secondaries per wall per step
+constexpr int kSphereTries = 64;   // bound of the rejection loops
+constexpr int kSortTile = 4096;    // items per sort tile (one wave)
+constexpr int kFinThreads = 256;   // field/finalize workgroup
+
+// Mutable per-discharge scalars.  They live in device memory so that a
+// captured sequence of launches can advance without host involvement.
+struct State {
+  int64_t step;          // completed steps
+  int64_t steps_left;    // steps still to run in the current request (<= 0: idle)
+  uint32_t n_main;       // particle slots in use (holes included)
+  uint32_t next_id;      // id of the next appended particle
+  uint32_t append_base;  // first slot of this step's appended particles
+  uint32_t id_base;      // id of this step's first appended particle
+  uint32_t n_kids;       // children created this step
+  uint32_t n_see[2];     // secondaries emitted this step (left, right)
+  uint32_t n_chunks;     // chunks processed by the last electron launch
+  int32_t buf;           // current particle buffer (0/1)
+  int32_t cbuf;          // cnt buffer holding the deposit of the current step
+  int32_t error;         // sticky error (HD_E* code)
+  int32_t sort_due;      // set by the finalize kernel when a sort follows
+  int32_t append_pending;  // set by the finalize kernel when particles are to be appended
+  uint32_t n_live_sorted;  // live particles counted by the sort
+  double wall[2];        // ion wall fluxes Gamma_0, Gamma_N of the last fluid update
+  uint64_t coll[kMaxK];
+  uint64_t absorbed[2];
+  uint64_t emitted[2];
+  uint64_t created;
+  uint64_t overflow;
+  uint64_t see_clamped;
+  uint64_t n_acc;
+};
+
+// Immutable constants and device pointers of one discharge.
+template <class P>
+struct Disch {
+  int32_t nc, nn, ne, K;
+  int32_t nbins, sort_every, eedf_every, ion_model;
+  uint32_t capacity;        // slots per particle buffer (multiple of kTile)
+  uint32_t cap_chunks;      // capacity / kTile
+  uint32_t sort_tiles_max;  // capacity / kSortTile (rounded up)
+  uint32_t pad0;
+  uint64_t seed;
+  // electron constants rounded to P
+  P Pmax, KE, invKE, inv_dE, kdz, delta, keedf;
+  P thr[kMaxK];
+  int32_t kind[kMaxK];
+  // FP64 constants of the field, fluid and emission
+  double dz, L, w, kp, inv_dz, inv_2dz, hdz_eps, qm_dt, scale_in, scale_wall;
+  double mu, nu, mu_full, TN, kappa, M, dt, dt_2dz, dt_dz, e_M_dt, dt_2dzM, hdt, nfloor;
+  double gamma_see, see_v;  // emission coefficient and speed sqrt(E_sec 2e/m_e)
+  int64_t volt_len;
+  // tables
+  const double* ip;    // [nn] inverse Thomas pivots of the Poisson matrix
+  const P* tab;        // [ne*K] cumulative collision probabilities
+  const double* volt;  // [volt_len] electrode voltage per step
+  // particles: two buffers for out-of-place sorting
+  int32_t* cell[2];
+  P* off[2];
+  P* vx[2];
+  P* vy[2];
+  P* vz[2];
+  uint32_t* id[2];
+  // children staging: chunk k writes its children at [k*kTile, ...)
+  int32_t* kc;
+  P* koff;
+  P* kvx;
+  P* kvy;
+  P* kvz;
+  uint32_t* chunk_kids;  // [cap_chunks]
+  uint32_t* chunk_base;  // [cap_chunks]
+  // secondaries of this step: side s at [s*kSeeMax, ...)
+  int32_t* sc;
+  P* soff;
+  P* svx;
+  P* svy;
+  P* svz;
+  // grids
+  int64_t* cnt[2];
+  int64_t* ion_src;
+  double* ni;
+  double* gam;
+  double* phi;
+  double* E;
+  P* Ep;
+  double* scratch;  // [12*nn] solver work space
+  uint64_t* acc_cnt;
+  double* acc_ni;
+  uint64_t* eedf;  // [nbins+1]
+  // sort
+  uint32_t* hist;  // [nc * sort_tiles_max]
+  uint32_t* bin_start;  // [nc + 1]
+  State* st;
+};
+
+}  // namespace hd
+
+// Launch wrappers implemented in the kernel translation units.
+namespace hd {
+template <class P>
+hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, hipStream_t s);
+template <class P>
+hipError_t launch_append(const Disch<P>* d_dev, int D, int grid, hipStream_t s);
+template <class P>
+hipError_t launch_diag(int64_t n, const P* a, const P* b, P* out, hipStream_t s);
+}  // namespace hd

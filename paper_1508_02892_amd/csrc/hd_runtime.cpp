@@ -1,0 +1,972 @@
+// Host runtime of the MI355X hybrid PIC/MCC stepper: parameter validation,
+// derived constants and null-collision tables (FP64), the initial electron
+// load, the device layout of each discharge, launch sequencing (with a
+// captured hipGraph per sort interval) and the C ABI of include/hd.h.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/hd.h"
+#include "hd_internal.h"
+
+namespace hd {
+
+// kernel-side entry points (k_electron.hip, k_field.hip, k_sort.hip)
+template <class P>
+size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max);
+template <class P>
+hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
+                                int nb1_max, hipStream_t s);
+template <class P>
+int electron_occupancy(int tab_max, int nn_max, int nb1_max, int D);
+template <class P>
+hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s);
+template <class P>
+hipError_t sort_set_lds(int nc_max);
+size_t sort_parts(size_t nc, size_t tiles);
+template <class P>
+hipError_t launch_set_steps(const Disch<P>* d_dev, int D, int64_t n, hipStream_t s);
+
+namespace {
+
+// CODATA 2018
+constexpr double kE = 1.602176634e-19;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kKb = 1.380649e-23;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& m) {
+  g_err = m;
+  return code;
+}
+
+#define HD_TRY(expr)                                                                  \
+  do {                                                                                \
+    hipError_t _e = (expr);                                                           \
+    if (_e != hipSuccess)                                                             \
+      return fail(HD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Counter-based stream for the initial load (same Philox4x32-10 definition
+// as on the device).
+void philox_host(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t k0, uint32_t k1,
+                 uint32_t o[4]) {
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+  }
+  o[0] = x0;
+  o[1] = x1;
+  o[2] = x2;
+  o[3] = x3;
+}
+
+struct HostStream {
+  uint32_t k0, k1, id, step, tag, blk = 0;
+  uint32_t w[4];
+  int pos = 4;
+  HostStream(uint64_t seed, uint32_t tag_, uint32_t id_, uint32_t step_)
+      : k0((uint32_t)seed), k1((uint32_t)(seed >> 32)), id(id_), step(step_), tag(tag_) {}
+  uint32_t word() {
+    if (pos == 4) {
+      philox_host(id, step, blk, tag, k0, k1, w);
+      blk += 1;
+      pos = 0;
+    }
+    return w[pos++];
+  }
+  double u64() {
+    const uint64_t hi = word();
+    const uint64_t lo = word();
+    return (double)(((hi << 32) | lo) >> 11) * 0x1p-53;
+  }
+};
+
+bool validate(const hd_params* p, std::string& why) {
+  if (!p) return (why = "null params"), false;
+  if (p->abi_version != HD_ABI_VERSION) return (why = "abi_version mismatch"), false;
+  if (p->precision != HD_FP32 && p->precision != HD_FP64) return (why = "precision"), false;
+  if (p->ion_model != HD_ION_DD_CONST_MU && p->ion_model != HD_ION_FULL_CONST_NU)
+    return (why = "ion_model"), false;
+  if (p->n_cells < 2 || p->n_cells > 65536) return (why = "n_cells out of [2, 65536]"), false;
+  if (p->n_energy < 2 || p->n_energy > (1 << 20)) return (why = "n_energy"), false;
+  if (p->n_channels < 0 || p->n_channels > HD_MAX_CHANNELS) return (why = "n_channels"), false;
+  if (p->n_channels > 0 && !p->channels) return (why = "channels missing"), false;
+  for (int k = 0; k < p->n_channels; ++k) {
+    const hd_xs_channel& c = p->channels[k];
+    if (c.kind < HD_XS_ELASTIC || c.kind > HD_XS_IONIZATION || !c.sigma_m2)
+      return (why = "channel " + std::to_string(k)), false;
+    for (int i = 0; i < p->n_energy; ++i)
+      if (!(c.sigma_m2[i] >= 0) || !std::isfinite(c.sigma_m2[i]))
+        return (why = "cross section must be finite and non-negative"), false;
+  }
+  if (p->sort_every < 1 || p->eedf_every < 1 || p->n_eedf_bins < 1 || p->n_eedf_bins > 65536)
+    return (why = "sort_every / eedf_every / n_eedf_bins"), false;
+  if (p->n_macro < 0 || p->capacity < p->n_macro || p->capacity > (int64_t)2000000000)
+    return (why = "n_macro / capacity"), false;
+  if (!(p->gap_m > 0) || !(p->dt_s > 0) || !(p->inv_de_per_eV > 0) || !(p->eedf_emax_eV > 0))
+    return (why = "gap / dt / energy grid"), false;
+  if (!(p->load_lo >= 0) || !(p->load_hi <= 1) || !(p->load_hi > p->load_lo))
+    return (why = "load interval"), false;
+  if (p->n_macro > 0 && !(p->n_e0_m3 > 0)) return (why = "n_e0"), false;
+  if (!(p->m_gas_amu > 0) || !(p->m_ion_amu > 0) || !(p->n_gas_m3 >= 0) || !(p->t_gas_K >= 0))
+    return (why = "gas / ion parameters"), false;
+  if (p->ion_model == HD_ION_FULL_CONST_NU && !(p->nu_const > 0)) return (why = "nu_const"), false;
+  if (!(p->gamma_see >= 0) || !(p->e_sec_eV >= 0)) return (why = "emission parameters"), false;
+  return true;
+}
+
+size_t round_capacity(int64_t cap) {
+  const size_t c = (size_t)std::max<int64_t>(cap, 1);
+  return align_up(c, (size_t)kSortTile);  // also a multiple of kTile
+}
+
+// Byte layout of one discharge's device block.
+struct Layout {
+  size_t total = 0;
+  size_t take(size_t bytes) {
+    const size_t o = total;
+    total = align_up(total + bytes, 256);
+    return o;
+  }
+};
+
+template <class P>
+struct Offsets {
+  size_t cell[2], off[2], vx[2], vy[2], vz[2], id[2];
+  size_t kc, koff, kvx, kvy, kvz, chunk_kids, chunk_base;
+  size_t sc, soff, svx, svy, svz;
+  size_t cnt[2], ion_src, ni, gam, phi, E, Ep, scratch, acc_cnt, acc_ni, eedf;
+  size_t ip, tab, hist, parts, st, volt;
+  size_t total;
+};
+
+template <class P>
+Offsets<P> layout(const hd_params& p, int64_t volt_len) {
+  Offsets<P> o;
+  Layout L;
+  const size_t C = round_capacity(p.capacity);
+  const size_t nn = (size_t)p.n_cells + 1;
+  for (int b = 0; b < 2; ++b) {
+    o.cell[b] = L.take(C * 4);
+    o.off[b] = L.take(C * sizeof(P));
+    o.vx[b] = L.take(C * sizeof(P));
+    o.vy[b] = L.take(C * sizeof(P));
+    o.vz[b] = L.take(C * sizeof(P));
+    o.id[b] = L.take(C * 4);
+  }
+  o.kc = L.take(C * 4);
+  o.koff = L.take(C * sizeof(P));
+  o.kvx = L.take(C * sizeof(P));
+  o.kvy = L.take(C * sizeof(P));
+  o.kvz = L.take(C * sizeof(P));
+  o.chunk_kids = L.take(C / kTile * 4);
+  o.chunk_base = L.take(C / kTile * 4);
+  o.sc = L.take(2 * kSeeMax * 4);
+  o.soff = L.take(2 * kSeeMax * sizeof(P));
+  o.svx = L.take(2 * kSeeMax * sizeof(P));
+  o.svy = L.take(2 * kSeeMax * sizeof(P));
+  o.svz = L.take(2 * kSeeMax * sizeof(P));
+  o.cnt[0] = L.take(nn * 8);
+  o.cnt[1] = L.take(nn * 8);
+  o.ion_src = L.take(nn * 8);
+  o.ni = L.take(nn * 8);
+  o.gam = L.take(nn * 8);
+  o.phi = L.take(nn * 8);
+  o.E = L.take(nn * 8);
+  o.Ep = L.take(nn * sizeof(P));
+  o.scratch = L.take(12 * nn * 8);
+  o.acc_cnt = L.take(nn * 8);
+  o.acc_ni = L.take(nn * 8);
+  o.eedf = L.take(((size_t)p.n_eedf_bins + 1) * 8);
+  o.ip = L.take(nn * 8);
+  o.tab = L.take((size_t)p.n_energy * (size_t)std::max(p.n_channels, 1) * sizeof(P));
+  o.hist = L.take((size_t)p.n_cells * (C / kSortTile) * 4);
+  o.parts = L.take(sort_parts((size_t)p.n_cells, C / kSortTile) * 4);
+  o.st = L.take(sizeof(State));
+  o.volt = L.take((size_t)volt_len * 8);
+  o.total = L.total;
+  return o;
+}
+
+constexpr int64_t kVoltInitial = 1 << 15;
+
+// Everything the host keeps for one discharge.
+template <class P>
+struct Host {
+  hd_params p{};
+  std::vector<hd_xs_channel> ch;
+  std::vector<std::vector<double>> sig;
+  Disch<P> dd{};             // host copy of the device descriptor
+  unsigned char* base = nullptr;
+  size_t bytes = 0;
+  int64_t volt_len = 0;
+  double* volt_dev = nullptr;
+  int64_t host_step = 0;     // steps enqueued so far
+  // derived FP64 values kept for moments
+  double scale_in = 0, scale_wall = 0, keedf = 0;
+};
+
+template <class P>
+void derive(Host<P>& h, std::vector<double>& ip, std::vector<P>& tab) {
+  const hd_params& p = h.p;
+  Disch<P>& d = h.dd;
+  d.nc = p.n_cells;
+  d.nn = p.n_cells + 1;
+  d.ne = p.n_energy;
+  d.K = p.n_channels;
+  d.nbins = p.n_eedf_bins;
+  d.sort_every = p.sort_every;
+  d.eedf_every = p.eedf_every;
+  d.ion_model = p.ion_model;
+  d.seed = p.seed;
+  const double dz = p.gap_m / p.n_cells;
+  const double w =
+      p.n_macro > 0 ? p.n_e0_m3 * (p.load_hi - p.load_lo) * p.gap_m / (double)p.n_macro : 0.0;
+  d.dz = dz;
+  d.L = p.gap_m;
+  d.w = w;
+  d.kp = dz * dz / kEps0;
+  d.inv_dz = 1.0 / dz;
+  d.inv_2dz = 0.5 / dz;
+  d.hdz_eps = dz / (2.0 * kEps0);
+  d.qm_dt = (-kE / kMe) * p.dt_s;
+  d.scale_in = std::ldexp(w, -32) / dz;
+  d.scale_wall = std::ldexp(w, -32) / (0.5 * dz);
+  h.scale_in = d.scale_in;
+  h.scale_wall = d.scale_wall;
+  // Poisson pivots
+  ip.assign(d.nn, 0.0);
+  if (d.nc - 1 >= 1) {
+    double den = 2.0;
+    ip[1] = 1.0 / den;
+    for (int j = 2; j <= d.nc - 1; ++j) {
+      den = 2.0 - ip[j - 1];
+      ip[j] = 1.0 / den;
+    }
+  }
+  // ion fluid
+  d.mu = p.mu_const;
+  d.nu = p.nu_const;
+  d.M = p.m_ion_amu * kAmu;
+  const double mN = p.m_gas_amu * kAmu;
+  d.TN = kKb * p.t_gas_K;
+  d.kappa = (d.M + mN) / (5.0 * d.M + 3.0 * mN) * mN;
+  d.mu_full = p.nu_const > 0 ? kE / (d.M * p.nu_const) : 0.0;
+  d.dt = p.dt_s;
+  d.dt_2dz = p.dt_s / (2.0 * dz);
+  d.dt_dz = p.dt_s / dz;
+  d.e_M_dt = kE * p.dt_s / d.M;
+  d.dt_2dzM = p.dt_s / (2.0 * dz * d.M);
+  d.hdt = 0.5 * p.dt_s;
+  d.nfloor = 1e-10 * p.n_e0_m3;
+  // emission
+  d.gamma_see = p.gamma_see;
+  const double invKE = 2.0 * kE / kMe;
+  d.see_v = std::sqrt(p.e_sec_eV * invKE);
+  // null-collision tables: nu_k(E_i) = N_g sigma_k(E_i) sqrt(2 e E_i / m_e)
+  const int ne = p.n_energy, K = p.n_channels;
+  std::vector<double> nu((size_t)ne * K);
+  double nu_max = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const double Ei = (double)i / p.inv_de_per_eV;
+    const double v = std::sqrt(2.0 * kE * Ei / kMe);
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) {
+      nu[(size_t)i * K + k] = p.n_gas_m3 * p.channels[k].sigma_m2[i] * v;
+      tot += nu[(size_t)i * K + k];
+    }
+    if (tot > nu_max) nu_max = tot;
+  }
+  const double Pmax = nu_max > 0 ? 1.0 - std::exp(-nu_max * p.dt_s) : 0.0;
+  tab.assign((size_t)ne * std::max(K, 1), (P)0);
+  for (int i = 0; i < ne; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) {
+      acc += nu[(size_t)i * K + k];
+      tab[(size_t)i * K + k] = (P)(nu_max > 0 ? Pmax * acc / nu_max : 0.0);
+    }
+  }
+  d.Pmax = (P)Pmax;
+  d.KE = (P)(0.5 * kMe / kE);
+  d.invKE = (P)invKE;
+  d.inv_dE = (P)p.inv_de_per_eV;
+  d.kdz = (P)(p.dt_s / dz);
+  d.delta = (P)(2.0 * kMe / (p.m_gas_amu * kAmu));
+  h.keedf = (double)p.n_eedf_bins / p.eedf_emax_eV;
+  d.keedf = (P)h.keedf;
+  for (int k = 0; k < kMaxK; ++k) {
+    d.thr[k] = k < K ? (P)p.channels[k].threshold_eV : (P)0;
+    d.kind[k] = k < K ? p.channels[k].kind : 0;
+  }
+}
+
+// Initial load: stream (tag 1, id k, step 0); uniform position in
+// [lo L, hi L), isotropic Maxwellian velocity (two polar-method pairs, the
+// fourth deviate unused); then a stable sort by cell and the fixed-point
+// deposit.
+template <class P>
+struct Loaded {
+  std::vector<int32_t> cell;
+  std::vector<P> off, vx, vy, vz;
+  std::vector<uint32_t> id;
+  std::vector<int64_t> cnt;
+};
+
+template <class P>
+void load_one(const hd_params& p, double dz, double vth, int64_t k, int32_t& c, P& off, P& vx,
+              P& vy, P& vz) {
+  HostStream st(p.seed, 1u, (uint32_t)k, 0u);
+  const double u0 = st.u64();
+  const double z = p.gap_m * (p.load_lo + (p.load_hi - p.load_lo) * u0);
+  const double s = z / dz;
+  const double fl = std::floor(s);
+  c = (int32_t)fl;
+  off = (P)(s - fl);
+  if (off == (P)1) {
+    c = c + 1;
+    off = (P)0;
+  }
+  double g[4];
+  for (int pair = 0; pair < 2; ++pair) {
+    double a, b, q;
+    for (;;) {
+      a = 2.0 * st.u64() - 1.0;
+      b = 2.0 * st.u64() - 1.0;
+      q = a * a + b * b;
+      if (q < 1.0 && q > 0.0) break;
+    }
+    const double f = std::sqrt(-2.0 * std::log(q) / q);
+    g[2 * pair] = a * f;
+    g[2 * pair + 1] = b * f;
+  }
+  vx = (P)(vth * g[0]);
+  vy = (P)(vth * g[1]);
+  vz = (P)(vth * g[2]);
+}
+
+template <class P>
+void load(const hd_params& p, double dz, Loaded<P>& out) {
+  const int64_t N = p.n_macro;
+  const int nc = p.n_cells;
+  std::vector<int32_t> c0(N);
+  std::vector<P> o0(N), x0(N), y0(N), z0(N);
+  const double vth = std::sqrt(p.t_e0_eV * kE / kMe);
+  unsigned nt = std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  if (N < 65536) nt = 1;
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) {
+    th.emplace_back([&, t]() {
+      const int64_t a = N * t / nt, b = N * (t + 1) / nt;
+      for (int64_t k = a; k < b; ++k) load_one<P>(p, dz, vth, k, c0[k], o0[k], x0[k], y0[k], z0[k]);
+    });
+  }
+  for (auto& x : th) x.join();
+  // stable counting sort by cell
+  std::vector<int64_t> start(nc + 1, 0);
+  for (int64_t k = 0; k < N; ++k) start[c0[k] + 1] += 1;
+  for (int c = 0; c < nc; ++c) start[c + 1] += start[c];
+  out.cell.resize(N);
+  out.off.resize(N);
+  out.vx.resize(N);
+  out.vy.resize(N);
+  out.vz.resize(N);
+  out.id.resize(N);
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t o = start[c0[k]]++;
+    out.cell[o] = c0[k];
+    out.off[o] = o0[k];
+    out.vx[o] = x0[k];
+    out.vy[o] = y0[k];
+    out.vz[o] = z0[k];
+    out.id[o] = (uint32_t)k;
+  }
+  out.cnt.assign(nc + 1, 0);
+  for (int64_t k = 0; k < N; ++k) {
+    const int64_t W1 = (int64_t)std::rint(out.off[k] * (P)4294967296.0);
+    out.cnt[out.cell[k]] += ((int64_t)1 << 32) - W1;
+    out.cnt[out.cell[k] + 1] += W1;
+  }
+}
+
+double volt_at(const hd_params& p, int64_t n) {
+  const double two_pi_f = 2.0 * kPi * p.f_rf_Hz;
+  const double t = (double)n * p.dt_s;
+  return p.v_amp_V * std::sin(two_pi_f * t + p.phase_rad);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batch of discharges advanced together.
+// ---------------------------------------------------------------------------
+struct BatchBase {
+  int precision = 0;
+  int D = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int sort_every = 16;
+  int grid_e = 0, grid_a = 0, grid_s = 0;
+  int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0;
+  int64_t host_step = 0;  // steps enqueued (all discharges advance together)
+  hipGraphExec_t graph = nullptr;
+  bool graph_ok = true;   // capture supported
+  int error = 0;
+  hipStream_t own_stream = nullptr;  // created when the caller passes the null stream
+  virtual ~BatchBase() {
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+  }
+};
+
+template <class P>
+struct Batch : BatchBase {
+  std::vector<Host<P>> hs;
+  Disch<P>* d_desc = nullptr;
+
+  ~Batch() override {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (double* p : extra) (void)hipFree(p);
+    for (auto& h : hs)
+      if (h.base) (void)hipFree(h.base);
+    if (d_desc) (void)hipFree(d_desc);
+  }
+
+  void fill_pointers(Host<P>& h, const Offsets<P>& o) {
+    unsigned char* b = h.base;
+    Disch<P>& d = h.dd;
+    const size_t C = round_capacity(h.p.capacity);
+    d.capacity = (uint32_t)h.p.capacity;  // limit; buffers are rounded up to C
+    d.cap_chunks = (uint32_t)(C / kTile);
+    d.sort_tiles_max = (uint32_t)(C / kSortTile);
+    for (int i = 0; i < 2; ++i) {
+      d.cell[i] = (int32_t*)(b + o.cell[i]);
+      d.off[i] = (P*)(b + o.off[i]);
+      d.vx[i] = (P*)(b + o.vx[i]);
+      d.vy[i] = (P*)(b + o.vy[i]);
+      d.vz[i] = (P*)(b + o.vz[i]);
+      d.id[i] = (uint32_t*)(b + o.id[i]);
+      d.cnt[i] = (int64_t*)(b + o.cnt[i]);
+    }
+    d.kc = (int32_t*)(b + o.kc);
+    d.koff = (P*)(b + o.koff);
+    d.kvx = (P*)(b + o.kvx);
+    d.kvy = (P*)(b + o.kvy);
+    d.kvz = (P*)(b + o.kvz);
+    d.chunk_kids = (uint32_t*)(b + o.chunk_kids);
+    d.chunk_base = (uint32_t*)(b + o.chunk_base);
+    d.sc = (int32_t*)(b + o.sc);
+    d.soff = (P*)(b + o.soff);
+    d.svx = (P*)(b + o.svx);
+    d.svy = (P*)(b + o.svy);
+    d.svz = (P*)(b + o.svz);
+    d.ion_src = (int64_t*)(b + o.ion_src);
+    d.ni = (double*)(b + o.ni);
+    d.gam = (double*)(b + o.gam);
+    d.phi = (double*)(b + o.phi);
+    d.E = (double*)(b + o.E);
+    d.Ep = (P*)(b + o.Ep);
+    d.scratch = (double*)(b + o.scratch);
+    d.acc_cnt = (uint64_t*)(b + o.acc_cnt);
+    d.acc_ni = (double*)(b + o.acc_ni);
+    d.eedf = (uint64_t*)(b + o.eedf);
+    d.ip = (const double*)(b + o.ip);
+    d.tab = (const P*)(b + o.tab);
+    d.hist = (uint32_t*)(b + o.hist);
+    d.bin_start = (uint32_t*)(b + o.parts);
+    d.st = (State*)(b + o.st);
+    h.volt_dev = (double*)(b + o.volt);
+    d.volt = h.volt_dev;
+    d.volt_len = h.volt_len;
+  }
+
+  int create(const hd_params* const* params, int n, const hd_device_ctx* ctx) {
+    D = n;
+    stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    device = ctx ? ctx->device : 0;
+    HD_TRY(hipSetDevice(device));
+    if (!stream) {  // the legacy default stream cannot be captured into a graph
+      HD_TRY(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+      stream = own_stream;
+    }
+    hs.resize(n);
+    for (int i = 0; i < n; ++i) {
+      Host<P>& h = hs[i];
+      h.p = *params[i];
+      h.sig.resize(h.p.n_channels);
+      h.ch.resize(h.p.n_channels);
+      for (int k = 0; k < h.p.n_channels; ++k) {
+        h.sig[k].assign(h.p.channels[k].sigma_m2, h.p.channels[k].sigma_m2 + h.p.n_energy);
+        h.ch[k] = h.p.channels[k];
+        h.ch[k].sigma_m2 = h.sig[k].data();
+      }
+      h.p.channels = h.ch.empty() ? nullptr : h.ch.data();
+      tab_max = std::max(tab_max, h.p.n_energy * std::max(1, h.p.n_channels));
+      nn_max = std::max(nn_max, h.p.n_cells + 1);
+      nc_max = std::max(nc_max, h.p.n_cells);
+      nb1_max = std::max(nb1_max, h.p.n_eedf_bins + 1);
+    }
+    sort_every = hs[0].p.sort_every;
+    // launch geometry
+    hipDeviceProp_t prop;
+    HD_TRY(hipGetDeviceProperties(&prop, device));
+    const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max);
+    if (lds > (size_t)prop.sharedMemPerBlock)
+      return fail(HD_EINVAL, "electron kernel needs " + std::to_string(lds) +
+                                 " B of LDS, device allows " +
+                                 std::to_string(prop.sharedMemPerBlock));
+    const size_t slds = (size_t)4 * (nc_max + 1) * 4;
+    if (slds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "sort LDS too large");
+    HD_TRY(sort_set_lds<P>(nc_max));
+    int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, D);
+    if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
+    const int cus = prop.multiProcessorCount;
+    grid_e = D + cus * occ;
+    grid_a = cus;
+    grid_s = cus * 2;
+    // per-discharge state
+    for (int i = 0; i < n; ++i) {
+      Host<P>& h = hs[i];
+      std::vector<double> ip;
+      std::vector<P> tab;
+      derive<P>(h, ip, tab);
+      h.volt_len = kVoltInitial;
+      const Offsets<P> o = layout<P>(h.p, h.volt_len);
+      h.bytes = o.total;
+      if (hipMalloc((void**)&h.base, h.bytes) != hipSuccess) {
+        h.base = nullptr;
+        return fail(HD_ENOMEM, "hipMalloc of " + std::to_string(h.bytes) + " bytes failed");
+      }
+      fill_pointers(h, o);
+      HD_TRY(hipMemsetAsync(h.base, 0, h.bytes, stream));
+      Loaded<P> ld;
+      load<P>(h.p, h.dd.dz, ld);
+      const size_t N = (size_t)h.p.n_macro;
+      Disch<P>& d = h.dd;
+      if (N) {
+        HD_TRY(hipMemcpyAsync(d.cell[0], ld.cell.data(), N * 4, hipMemcpyHostToDevice, stream));
+        HD_TRY(hipMemcpyAsync(d.off[0], ld.off.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+        HD_TRY(hipMemcpyAsync(d.vx[0], ld.vx.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+        HD_TRY(hipMemcpyAsync(d.vy[0], ld.vy.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+        HD_TRY(hipMemcpyAsync(d.vz[0], ld.vz.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+        HD_TRY(hipMemcpyAsync(d.id[0], ld.id.data(), N * 4, hipMemcpyHostToDevice, stream));
+      }
+      std::vector<double> ni(d.nn);
+      for (int j = 0; j < d.nn; ++j)
+        ni[j] = (double)ld.cnt[j] * ((j == 0 || j == d.nc) ? h.scale_wall : h.scale_in);
+      HD_TRY(hipMemcpyAsync(d.cnt[0], ld.cnt.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync(d.ni, ni.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync((void*)d.ip, ip.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync((void*)d.tab, tab.data(), tab.size() * sizeof(P),
+                            hipMemcpyHostToDevice, stream));
+      std::vector<double> vt(h.volt_len);
+      for (int64_t s = 0; s < h.volt_len; ++s) vt[s] = volt_at(h.p, s);
+      HD_TRY(hipMemcpyAsync(h.volt_dev, vt.data(), vt.size() * 8, hipMemcpyHostToDevice, stream));
+      State st{};
+      st.n_main = (uint32_t)N;
+      st.next_id = (uint32_t)N;
+      HD_TRY(hipMemcpyAsync(d.st, &st, sizeof(State), hipMemcpyHostToDevice, stream));
+      HD_TRY(hipStreamSynchronize(stream));
+    }
+    HD_TRY(hipMalloc((void**)&d_desc, sizeof(Disch<P>) * D));
+    HD_TRY(upload_desc());
+    HD_TRY(launch_finalize<P>(d_desc, D, 1, stream));
+    HD_TRY(hipStreamSynchronize(stream));
+    return HD_OK;
+  }
+
+  hipError_t upload_desc() {
+    std::vector<Disch<P>> v(D);
+    for (int i = 0; i < D; ++i) v[i] = hs[i].dd;
+    hipError_t e = hipMemcpyAsync(d_desc, v.data(), sizeof(Disch<P>) * D, hipMemcpyHostToDevice,
+                                  stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(stream);
+  }
+
+  // Make every discharge's voltage table cover steps [0, upto].
+  int ensure_volt(int64_t upto) {
+    bool changed = false;
+    for (auto& h : hs) {
+      if (upto < h.volt_len) continue;
+      int64_t len = h.volt_len;
+      while (len <= upto) len *= 2;
+      double* nv = nullptr;
+      if (hipMalloc((void**)&nv, (size_t)len * 8) != hipSuccess)
+        return fail(HD_ENOMEM, "voltage table allocation failed");
+      std::vector<double> vt(len);
+      for (int64_t s = 0; s < len; ++s) vt[s] = volt_at(h.p, s);
+      HD_TRY(hipMemcpy(nv, vt.data(), (size_t)len * 8, hipMemcpyHostToDevice));
+      // the original table lives inside the discharge block; extra tables are kept here
+      extra.push_back(nv);
+      h.volt_dev = nv;
+      h.volt_len = len;
+      h.dd.volt = nv;
+      h.dd.volt_len = len;
+      changed = true;
+    }
+    if (changed) {
+      HD_TRY(hipStreamSynchronize(stream));
+      HD_TRY(upload_desc());
+      if (graph) {
+        (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+      }
+    }
+    return HD_OK;
+  }
+  std::vector<double*> extra;
+
+  hipError_t enqueue_step(bool with_sort) {
+    hipError_t e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, stream);
+    if (e != hipSuccess) return e;
+    e = launch_finalize<P>(d_desc, D, 0, stream);
+    if (e != hipSuccess) return e;
+    e = launch_append<P>(d_desc, D, grid_a, stream);
+    if (e != hipSuccess) return e;
+    if (with_sort) e = launch_sort_impl<P>(d_desc, D, grid_s, nc_max, stream);
+    return e;
+  }
+
+  int capture() {
+    hipGraph_t g = nullptr;
+    HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < sort_every && e == hipSuccess; ++s) e = enqueue_step(s == sort_every - 1);
+    hipError_t e2 = hipStreamEndCapture(stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      graph_ok = false;
+      return HD_OK;  // fall back to direct launches of the same kernels
+    }
+    e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      graph = nullptr;
+      graph_ok = false;
+    }
+    return HD_OK;
+  }
+
+  int step(int64_t n) {
+    if (n < 0) return fail(HD_EINVAL, "n_steps < 0");
+    if (error) return fail(error, "handle is in an error state");
+    if (n == 0) return HD_OK;
+    const int64_t target = host_step + n;
+    int rc = ensure_volt(target + 1);
+    if (rc) return rc;
+    HD_TRY(launch_set_steps<P>(d_desc, D, n, stream));
+    while (host_step < target) {
+      const int64_t left = target - host_step;
+      if (host_step % sort_every == 0 && left >= sort_every && graph_ok && use_graph) {
+        if (!graph) {
+          rc = capture();
+          if (rc) return rc;
+          if (!graph) continue;
+        }
+        HD_TRY(hipGraphLaunch(graph, stream));
+        host_step += sort_every;
+      } else {
+        const bool srt = ((host_step + 1) % sort_every) == 0;
+        HD_TRY(enqueue_step(srt));
+        host_step += 1;
+      }
+    }
+    return HD_OK;
+  }
+  bool use_graph = true;
+
+  int sync_state(int i, State& st) {
+    HD_TRY(hipStreamSynchronize(stream));
+    HD_TRY(hipMemcpy(&st, hs[i].dd.st, sizeof(State), hipMemcpyDeviceToHost));
+    if (st.error) {
+      error = st.error;
+      return fail(st.error, "device reported error " + std::to_string(st.error) +
+                                " (particle capacity exceeded)");
+    }
+    return HD_OK;
+  }
+
+  int moments(int i, hd_moment_set* m) {
+    if (i < 0 || i >= D || !m) return fail(HD_EINVAL, "bad index or output");
+    State st;
+    int rc = sync_state(i, st);
+    const Host<P>& h = hs[i];
+    const Disch<P>& d = h.dd;
+    const int nn = d.nn;
+    m->step = st.step;
+    m->n_slots = st.n_main;
+    m->n_nodes = nn;
+    m->n_channels = d.K;
+    m->n_eedf_bins = d.nbins;
+    m->error = st.error;
+    for (int k = 0; k < HD_MAX_CHANNELS; ++k) m->coll[k] = k < kMaxK ? st.coll[k] : 0;
+    m->absorbed[0] = st.absorbed[0];
+    m->absorbed[1] = st.absorbed[1];
+    m->emitted[0] = st.emitted[0];
+    m->emitted[1] = st.emitted[1];
+    m->created = st.created;
+    m->e_overflow = st.overflow;
+    m->see_clamped = st.see_clamped;
+    m->n_acc = st.n_acc;
+    std::vector<int64_t> cnt(nn);
+    HD_TRY(hipMemcpy(cnt.data(), d.cnt[st.cbuf], nn * 8, hipMemcpyDeviceToHost));
+    int64_t tot = 0;
+    for (int j = 0; j < nn; ++j) tot += cnt[j];
+    m->n_live = tot >> 32;
+    auto sc = [&](int j) { return (j == 0 || j == d.nc) ? h.scale_wall : h.scale_in; };
+    if (m->cnt) std::copy(cnt.begin(), cnt.end(), m->cnt);
+    if (m->n_e)
+      for (int j = 0; j < nn; ++j) m->n_e[j] = (double)cnt[j] * sc(j);
+    if (m->n_i) HD_TRY(hipMemcpy(m->n_i, d.ni, nn * 8, hipMemcpyDeviceToHost));
+    if (m->phi) HD_TRY(hipMemcpy(m->phi, d.phi, nn * 8, hipMemcpyDeviceToHost));
+    if (m->E) HD_TRY(hipMemcpy(m->E, d.E, nn * 8, hipMemcpyDeviceToHost));
+    if (m->gamma_i) HD_TRY(hipMemcpy(m->gamma_i, d.gam, nn * 8, hipMemcpyDeviceToHost));
+    if (m->n_e_avg) {
+      std::vector<uint64_t> a(nn);
+      HD_TRY(hipMemcpy(a.data(), d.acc_cnt, nn * 8, hipMemcpyDeviceToHost));
+      for (int j = 0; j < nn; ++j)
+        m->n_e_avg[j] = st.n_acc ? (double)a[j] * sc(j) / (double)st.n_acc : 0.0;
+    }
+    if (m->n_i_avg) {
+      std::vector<double> a(nn);
+      HD_TRY(hipMemcpy(a.data(), d.acc_ni, nn * 8, hipMemcpyDeviceToHost));
+      for (int j = 0; j < nn; ++j) m->n_i_avg[j] = st.n_acc ? a[j] / (double)st.n_acc : 0.0;
+    }
+    if (m->eedf_counts || m->eedf) {
+      std::vector<uint64_t> e(d.nbins + 1);
+      HD_TRY(hipMemcpy(e.data(), d.eedf, e.size() * 8, hipMemcpyDeviceToHost));
+      if (m->eedf_counts) std::copy(e.begin(), e.end(), m->eedf_counts);
+      if (m->eedf) {
+        uint64_t in = 0;
+        for (int b = 0; b < d.nbins; ++b) in += e[b];
+        const double de = 1.0 / h.keedf;
+        for (int b = 0; b < d.nbins; ++b) m->eedf[b] = in ? (double)e[b] / ((double)in * de) : 0.0;
+      }
+    }
+    return rc;
+  }
+
+  int particles(int i, int32_t* cell, void* off, void* vx, void* vy, void* vz, uint32_t* id,
+                int64_t cap, int64_t* n_out) {
+    if (i < 0 || i >= D) return fail(HD_EINVAL, "bad index");
+    State st;
+    int rc = sync_state(i, st);
+    const Disch<P>& d = hs[i].dd;
+    const size_t n = st.n_main;
+    if (n_out) *n_out = (int64_t)n;
+    if (cap < (int64_t)n) return fail(HD_EINVAL, "cap < n_slots");
+    const int b = st.buf;
+    if (cell) HD_TRY(hipMemcpy(cell, d.cell[b], n * 4, hipMemcpyDeviceToHost));
+    if (off) HD_TRY(hipMemcpy(off, d.off[b], n * sizeof(P), hipMemcpyDeviceToHost));
+    if (vx) HD_TRY(hipMemcpy(vx, d.vx[b], n * sizeof(P), hipMemcpyDeviceToHost));
+    if (vy) HD_TRY(hipMemcpy(vy, d.vy[b], n * sizeof(P), hipMemcpyDeviceToHost));
+    if (vz) HD_TRY(hipMemcpy(vz, d.vz[b], n * sizeof(P), hipMemcpyDeviceToHost));
+    if (id) HD_TRY(hipMemcpy(id, d.id[b], n * 4, hipMemcpyDeviceToHost));
+    return rc;
+  }
+
+  int push_field(int i, void* out) {
+    State st;
+    int rc = sync_state(i, st);
+    HD_TRY(hipMemcpy(out, hs[i].dd.Ep, hs[i].dd.nn * sizeof(P), hipMemcpyDeviceToHost));
+    return rc;
+  }
+};
+
+template <class P>
+size_t required_bytes(const hd_params& p) {
+  return layout<P>(p, kVoltInitial).total + sizeof(Disch<P>);
+}
+
+}  // namespace hd
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct hd_batch {
+  hd::BatchBase* impl;
+};
+struct hd_discharge {
+  hd_batch b;
+};
+
+namespace {
+
+int make_batch(const hd_params* const* params, int32_t n, const hd_device_ctx* ctx,
+               hd::BatchBase** out) {
+  using namespace hd;
+  if (!params || n < 1) return fail(HD_EINVAL, "no discharges");
+  std::string why;
+  for (int i = 0; i < n; ++i)
+    if (!validate(params[i], why)) return fail(HD_EINVAL, "discharge " + std::to_string(i) + ": " + why);
+  for (int i = 1; i < n; ++i)
+    if (params[i]->precision != params[0]->precision ||
+        params[i]->sort_every != params[0]->sort_every ||
+        params[i]->eedf_every != params[0]->eedf_every)
+      return fail(HD_EINVAL, "batch members must share precision, sort_every and eedf_every");
+  BatchBase* b = nullptr;
+  int rc;
+  if (params[0]->precision == HD_FP32) {
+    auto* x = new Batch<float>();
+    x->precision = HD_FP32;
+    rc = x->create(params, n, ctx);
+    b = x;
+  } else {
+    auto* x = new Batch<double>();
+    x->precision = HD_FP64;
+    rc = x->create(params, n, ctx);
+    b = x;
+  }
+  if (rc != HD_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return HD_OK;
+}
+
+template <class F>
+int dispatch(hd::BatchBase* b, F&& f) {
+  if (b->precision == HD_FP32) return f(static_cast<hd::Batch<float>*>(b));
+  return f(static_cast<hd::Batch<double>*>(b));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t hd_abi_version(void) { return HD_ABI_VERSION; }
+const char* hd_last_error(void) { return hd::g_err.c_str(); }
+
+size_t hd_required_bytes(const hd_params* p) {
+  std::string why;
+  if (!hd::validate(p, why)) return 0;
+  return p->precision == HD_FP32 ? hd::required_bytes<float>(*p) : hd::required_bytes<double>(*p);
+}
+
+int hd_init_discharge(const hd_params* params, const hd_device_ctx* ctx, hd_discharge** out) {
+  if (!out) return hd::fail(HD_EINVAL, "null out");
+  hd::BatchBase* b = nullptr;
+  const hd_params* arr[1] = {params};
+  int rc = make_batch(arr, 1, ctx, &b);
+  if (rc) return rc;
+  *out = new hd_discharge{hd_batch{b}};
+  return HD_OK;
+}
+
+int hd_step(hd_discharge* h, int64_t n) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl, [&](auto* x) { return x->step(n); });
+}
+
+int hd_moments(hd_discharge* h, hd_moment_set* out) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl, [&](auto* x) { return x->moments(0, out); });
+}
+
+int hd_get_particles(hd_discharge* h, int32_t* cell, void* off, void* vx, void* vy, void* vz,
+                     uint32_t* id, int64_t cap, int64_t* n_out) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl,
+                  [&](auto* x) { return x->particles(0, cell, off, vx, vy, vz, id, cap, n_out); });
+}
+
+int hd_get_push_field(hd_discharge* h, void* ep) {
+  if (!h || !ep) return hd::fail(HD_EINVAL, "null argument");
+  return dispatch(h->b.impl, [&](auto* x) { return x->push_field(0, ep); });
+}
+
+int hd_free(hd_discharge* h) {
+  if (!h) return HD_OK;
+  delete h->b.impl;
+  delete h;
+  return HD_OK;
+}
+
+int hd_batch_create(const hd_params* const* params, int32_t n, const hd_device_ctx* ctx,
+                    hd_batch** out) {
+  if (!out) return hd::fail(HD_EINVAL, "null out");
+  hd::BatchBase* b = nullptr;
+  int rc = make_batch(params, n, ctx, &b);
+  if (rc) return rc;
+  *out = new hd_batch{b};
+  return HD_OK;
+}
+
+int hd_batch_step(hd_batch* b, int64_t n) {
+  if (!b) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(b->impl, [&](auto* x) { return x->step(n); });
+}
+
+int hd_batch_moments(hd_batch* b, int32_t i, hd_moment_set* out) {
+  if (!b) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(b->impl, [&](auto* x) { return x->moments(i, out); });
+}
+
+int hd_batch_get_particles(hd_batch* b, int32_t i, int32_t* cell, void* off, void* vx, void* vy,
+                           void* vz, uint32_t* id, int64_t cap, int64_t* n_out) {
+  if (!b) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(b->impl,
+                  [&](auto* x) { return x->particles(i, cell, off, vx, vy, vz, id, cap, n_out); });
+}
+
+int hd_batch_free(hd_batch* b) {
+  if (!b) return HD_OK;
+  delete b->impl;
+  delete b;
+  return HD_OK;
+}
+
+int hd_diag_arith(int32_t precision, int64_t n, const void* a, const void* b, void* out,
+                  const hd_device_ctx* ctx) {
+  if (n < 0 || (n > 0 && (!a || !b || !out))) return hd::fail(HD_EINVAL, "bad arguments");
+  if (precision != HD_FP32 && precision != HD_FP64) return hd::fail(HD_EINVAL, "precision");
+  if (n == 0) return HD_OK;
+  hipStream_t s = ctx ? (hipStream_t)ctx->stream : nullptr;
+  const size_t es = precision == HD_FP32 ? 4 : 8;
+  void *da = nullptr, *db = nullptr, *dout = nullptr;
+  auto cleanup = [&]() {
+    if (da) (void)hipFree(da);
+    if (db) (void)hipFree(db);
+    if (dout) (void)hipFree(dout);
+  };
+  if (hipMalloc(&da, n * es) != hipSuccess || hipMalloc(&db, n * es) != hipSuccess ||
+      hipMalloc(&dout, 4 * n * es) != hipSuccess) {
+    cleanup();
+    return hd::fail(HD_ENOMEM, "diag allocation failed");
+  }
+  hipError_t e = hipMemcpy(da, a, n * es, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db, b, n * es, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = precision == HD_FP32
+            ? hd::launch_diag<float>(n, (const float*)da, (const float*)db, (float*)dout, s)
+            : hd::launch_diag<double>(n, (const double*)da, (const double*)db, (double*)dout, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(out, dout, 4 * n * es, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) return hd::fail(HD_EDEVICE, hipGetErrorString(e));
+  return HD_OK;
+}
+
+}  // extern "C"

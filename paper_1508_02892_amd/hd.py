@@ -1,0 +1,299 @@
+"""Thin ctypes binding of the C ABI in include/hd.h (argument marshalling only).
+
+Every step of the discharge runs in the HIP kernels of libhd.so; this module
+only converts Python parameter dicts to ``hd_params``, calls the entry points
+and wraps the caller-owned output buffers as numpy arrays.  If the library is
+not built, or cannot be loaded, the calls raise: there is no fallback.
+PyTorch, when present, only supplies the stream the work is enqueued on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhd.so")
+
+HD_ABI_VERSION = 1
+HD_MAX_CHANNELS = 16
+STATUS = {0: "HD_OK", -1: "HD_EINVAL", -2: "HD_ENOMEM", -3: "HD_EDEVICE", -4: "HD_ECAPACITY",
+          -5: "HD_ENUMERIC", -6: "HD_ESTATE"}
+KIND = {"elastic": 0, "excitation": 1, "ionization": 2}
+
+# Every entry point declared in include/hd.h.
+SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_discharge",
+           "hd_step", "hd_moments", "hd_get_particles", "hd_get_push_field", "hd_free",
+           "hd_batch_create", "hd_batch_step", "hd_batch_moments", "hd_batch_get_particles",
+           "hd_batch_free", "hd_diag_arith"]
+
+
+class HdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class XsChannel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("threshold_eV", C.c_double),
+                ("sigma_m2", C.POINTER(C.c_double))]
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("precision", C.c_int32), ("ion_model", C.c_int32),
+        ("n_cells", C.c_int32), ("n_energy", C.c_int32), ("n_channels", C.c_int32),
+        ("sort_every", C.c_int32), ("eedf_every", C.c_int32), ("n_eedf_bins", C.c_int32),
+        ("reserved", C.c_int32), ("n_macro", C.c_int64), ("capacity", C.c_int64),
+        ("seed", C.c_uint64),
+        ("n_gas_m3", C.c_double), ("t_gas_K", C.c_double), ("m_gas_amu", C.c_double),
+        ("gap_m", C.c_double),
+        ("v_amp_V", C.c_double), ("f_rf_Hz", C.c_double), ("phase_rad", C.c_double),
+        ("n_e0_m3", C.c_double), ("t_e0_eV", C.c_double), ("load_lo", C.c_double),
+        ("load_hi", C.c_double), ("gamma_see", C.c_double), ("e_sec_eV", C.c_double),
+        ("m_ion_amu", C.c_double), ("mu_const", C.c_double), ("nu_const", C.c_double),
+        ("dt_s", C.c_double), ("inv_de_per_eV", C.c_double), ("eedf_emax_eV", C.c_double),
+        ("channels", C.POINTER(XsChannel)),
+    ]
+
+
+class DeviceCtx(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("device", C.c_int32), ("reserved", C.c_int32)]
+
+
+_D = C.POINTER(C.c_double)
+
+
+class MomentSet(C.Structure):
+    _fields_ = [
+        ("step", C.c_int64), ("n_live", C.c_int64), ("n_slots", C.c_int64),
+        ("n_nodes", C.c_int32), ("n_channels", C.c_int32), ("n_eedf_bins", C.c_int32),
+        ("error", C.c_int32),
+        ("n_e", _D), ("n_i", _D), ("phi", _D), ("E", _D), ("gamma_i", _D), ("n_e_avg", _D),
+        ("n_i_avg", _D), ("cnt", C.POINTER(C.c_int64)), ("eedf_counts", C.POINTER(C.c_uint64)),
+        ("eedf", _D),
+        ("coll", C.c_uint64 * HD_MAX_CHANNELS), ("absorbed", C.c_uint64 * 2),
+        ("emitted", C.c_uint64 * 2), ("created", C.c_uint64), ("e_overflow", C.c_uint64),
+        ("see_clamped", C.c_uint64), ("n_acc", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhd.so; raise if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError("libhd.so is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.hd_abi_version.restype = C.c_int32
+        L.hd_last_error.restype = C.c_char_p
+        L.hd_required_bytes.restype = C.c_size_t
+        L.hd_required_bytes.argtypes = [C.POINTER(Params)]
+        L.hd_init_discharge.argtypes = [C.POINTER(Params), C.POINTER(DeviceCtx), C.POINTER(vp)]
+        L.hd_step.argtypes = [vp, C.c_int64]
+        L.hd_moments.argtypes = [vp, C.POINTER(MomentSet)]
+        L.hd_get_particles.argtypes = [vp] * 7 + [C.c_int64, C.POINTER(C.c_int64)]
+        L.hd_get_push_field.argtypes = [vp, vp]
+        L.hd_free.argtypes = [vp]
+        L.hd_batch_create.argtypes = [C.POINTER(C.POINTER(Params)), C.c_int32,
+                                      C.POINTER(DeviceCtx), C.POINTER(vp)]
+        L.hd_batch_step.argtypes = [vp, C.c_int64]
+        L.hd_batch_moments.argtypes = [vp, C.c_int32, C.POINTER(MomentSet)]
+        L.hd_batch_get_particles.argtypes = [vp, C.c_int32] + [vp] * 6 + \
+            [C.c_int64, C.POINTER(C.c_int64)]
+        L.hd_batch_free.argtypes = [vp]
+        L.hd_diag_arith.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, C.POINTER(DeviceCtx)]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise HdError(rc, lib().hd_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def pdtype(precision: int):
+    return np.float32 if precision == 0 else np.float64
+
+
+def make_params(p: dict):
+    """hd_params from a parameter dict; returns (struct, keep-alive objects)."""
+    chans = p.get("channels", [])
+    keep = []
+    arr = (XsChannel * max(1, len(chans)))()
+    for k, ch in enumerate(chans):
+        s = np.ascontiguousarray(ch["sigma_m2"], dtype=np.float64)
+        keep.append(s)
+        arr[k].kind = KIND[ch["kind"]] if isinstance(ch["kind"], str) else int(ch["kind"])
+        arr[k].threshold_eV = float(ch.get("threshold_eV", 0.0))
+        arr[k].sigma_m2 = s.ctypes.data_as(_D)
+    keep.append(arr)
+    P = Params()
+    P.abi_version = HD_ABI_VERSION
+    for name, _ in Params._fields_:
+        if name in ("abi_version", "reserved", "channels", "n_channels"):
+            continue
+        setattr(P, name, p[name])
+    P.n_channels = len(chans)
+    P.channels = C.cast(arr, C.POINTER(XsChannel))
+    return P, keep
+
+
+def _ctx(stream=None, device=0):
+    c = DeviceCtx()
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                stream = torch.cuda.current_stream(device).cuda_stream
+        except Exception:  # torch absent: the default stream
+            stream = None
+    c.stream = stream
+    c.device = device
+    return c
+
+
+def required_bytes(p: dict) -> int:
+    P, keep = make_params(p)
+    return int(lib().hd_required_bytes(C.byref(P)))
+
+
+class _Moments:
+    def __init__(self, nn, nb, K):
+        self.arrs = {k: np.zeros(nn) for k in ("n_e", "n_i", "phi", "E", "gamma_i", "n_e_avg",
+                                                 "n_i_avg")}
+        self.arrs["cnt"] = np.zeros(nn, np.int64)
+        self.arrs["eedf_counts"] = np.zeros(nb + 1, np.uint64)
+        self.arrs["eedf"] = np.zeros(nb)
+        self.m = MomentSet()
+        for k, a in self.arrs.items():
+            setattr(self.m, k, a.ctypes.data_as(dict(MomentSet._fields_)[k]))
+        self.K = K
+
+    def result(self):
+        m = self.m
+        out = dict(self.arrs)
+        out.update(step=m.step, n_live=m.n_live, n_slots=m.n_slots, error=m.error,
+                   coll=np.array(m.coll[:self.K], np.uint64),
+                   absorbed=np.array(m.absorbed[:], np.uint64),
+                   emitted=np.array(m.emitted[:], np.uint64), created=int(m.created),
+                   overflow=int(m.e_overflow), see_clamped=int(m.see_clamped),
+                   n_acc=int(m.n_acc))
+        return out
+
+
+class Discharge:
+    """One discharge: hd_init_discharge / hd_step / hd_moments / hd_free."""
+
+    def __init__(self, params: dict, stream=None, device: int = 0):
+        self.params = dict(params)
+        self._P, self._keep = make_params(params)
+        self._ctx = _ctx(stream, device)
+        h = C.c_void_p()
+        _check(lib().hd_init_discharge(C.byref(self._P), C.byref(self._ctx), C.byref(h)))
+        self.h = h
+        self.nn = params["n_cells"] + 1
+        self.dt = pdtype(params["precision"])
+
+    def step(self, n: int = 1):
+        _check(lib().hd_step(self.h, int(n)))
+
+    def moments(self) -> dict:
+        M = _Moments(self.nn, self.params["n_eedf_bins"], len(self.params["channels"]))
+        _check(lib().hd_moments(self.h, C.byref(M.m)))
+        return M.result()
+
+    def particles(self) -> dict:
+        n = C.c_int64()
+        cap = int(self.params["capacity"]) + 8192
+        out = {"cell": np.empty(cap, np.int32), "id": np.empty(cap, np.uint32)}
+        for k in ("off", "vx", "vy", "vz"):
+            out[k] = np.empty(cap, self.dt)
+        _check(lib().hd_get_particles(self.h, _ptr(out["cell"]), _ptr(out["off"]),
+                                      _ptr(out["vx"]), _ptr(out["vy"]), _ptr(out["vz"]),
+                                      _ptr(out["id"]), cap, C.byref(n)))
+        return {k: v[:n.value].copy() for k, v in out.items()}
+
+    def push_field(self) -> np.ndarray:
+        ep = np.empty(self.nn, self.dt)
+        _check(lib().hd_get_push_field(self.h, _ptr(ep)))
+        return ep
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hd_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent discharges advanced together: hd_batch_*."""
+
+    def __init__(self, params_list, stream=None, device: int = 0):
+        self.params = [dict(p) for p in params_list]
+        made = [make_params(p) for p in params_list]
+        self._keep = made
+        arr = (C.POINTER(Params) * len(made))(*[C.pointer(m[0]) for m in made])
+        self._arr = arr
+        self._ctx = _ctx(stream, device)
+        h = C.c_void_p()
+        _check(lib().hd_batch_create(arr, len(made), C.byref(self._ctx), C.byref(h)))
+        self.h = h
+
+    def step(self, n: int = 1):
+        _check(lib().hd_batch_step(self.h, int(n)))
+
+    def moments(self, i: int) -> dict:
+        p = self.params[i]
+        M = _Moments(p["n_cells"] + 1, p["n_eedf_bins"], len(p["channels"]))
+        _check(lib().hd_batch_moments(self.h, int(i), C.byref(M.m)))
+        return M.result()
+
+    def particles(self, i: int) -> dict:
+        p = self.params[i]
+        dt = pdtype(p["precision"])
+        cap = int(p["capacity"]) + 8192
+        n = C.c_int64()
+        out = {"cell": np.empty(cap, np.int32), "id": np.empty(cap, np.uint32)}
+        for k in ("off", "vx", "vy", "vz"):
+            out[k] = np.empty(cap, dt)
+        _check(lib().hd_batch_get_particles(self.h, int(i), _ptr(out["cell"]), _ptr(out["off"]),
+                                            _ptr(out["vx"]), _ptr(out["vy"]), _ptr(out["vz"]),
+                                            _ptr(out["id"]), cap, C.byref(n)))
+        return {k: v[:n.value].copy() for k, v in out.items()}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hd_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def diag_arith(precision: int, a, b) -> np.ndarray:
+    """Device sqrt, divide, rint(x 2^32) and floor of the inputs (n x 4)."""
+    dt = pdtype(precision)
+    a = np.ascontiguousarray(a, dt)
+    b = np.ascontiguousarray(b, dt)
+    out = np.empty((len(a), 4), dt)
+    ctx = _ctx()
+    _check(lib().hd_diag_arith(precision, len(a), _ptr(a), _ptr(b), _ptr(out), C.byref(ctx)))
+    return out

@@ -27,7 +27,10 @@ def test_initial_load_statistics(precision):
         v = pt[k].astype(np.float64)
         assert abs(v.mean()) < 5 * np.sqrt(vth2 / len(v))
         assert abs(v.var() / vth2 - 1) < 5 * np.sqrt(2 / len(v))
-    np.testing.assert_array_equal(pt["id"], np.arange(50_000))
+    # the load ends with a stable sort by cell: ids are the load order within a cell
+    order = np.lexsort((pt["id"], pt["cell"]))
+    np.testing.assert_array_equal(order, np.arange(50_000))
+    np.testing.assert_array_equal(np.sort(pt["id"]), np.arange(50_000))
 
 
 def _hot(precision, **kw):
