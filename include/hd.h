@@ -139,6 +139,8 @@ typedef struct hd_moment_set {
   uint64_t e_overflow;     /* collision candidates above the table's top     */
   uint64_t see_clamped;    /* secondaries dropped by the per-step cap        */
   uint64_t n_acc;          /* steps in the averages                          */
+  uint64_t pushed;         /* particle-steps: live electrons pushed, summed
+                              over all steps so far                          */
 } hd_moment_set;
 
 typedef struct hd_batch hd_batch;
@@ -196,7 +198,74 @@ int hd_batch_get_particles(hd_batch* b, int32_t index, int32_t* cell, void* off,
                            void* vy, void* vz, uint32_t* id, int64_t cap, int64_t* n_out);
 int hd_batch_free(hd_batch* b);
 
+/* ---- served job stream (continuous batching) ----------------------------- */
+
+/* A server owns max_slots discharge slots on one device.  A host thread admits
+ * submitted jobs first-come first-served into free slots while the device
+ * bytes of the admitted jobs stay within hbm_budget_bytes, advances all
+ * occupied slots together one sort interval (sort_every steps) per launch
+ * sequence, and retires a job once it has run its steps, keeping its final
+ * moments.  Jobs start at interval boundaries, so each job's result is
+ * bitwise identical to the same discharge run alone.  Every job must match
+ * the server's precision, sort_every and eedf_every and fit its caps. */
+typedef struct hd_server hd_server;
+
+typedef struct hd_server_config {
+  int32_t precision;        /* enum hd_precision of every job              */
+  int32_t max_slots;        /* discharges resident at once (>= 1)          */
+  int32_t sort_every;       /* steps per interval                          */
+  int32_t eedf_every;
+  int32_t max_cells;        /* caps that size the kernels' LDS             */
+  int32_t max_energy;
+  int32_t max_channels;
+  int32_t max_eedf_bins;
+  int32_t allow_full_fluid; /* admit HD_ION_FULL_CONST_NU jobs             */
+  int32_t reserved;
+  uint64_t hbm_budget_bytes;/* bound on the summed device bytes of the jobs */
+} hd_server_config;
+
+typedef struct hd_server_counters {
+  uint64_t submitted, completed, failed, queued, running;
+  uint64_t intervals;       /* launch sequences replayed                   */
+  uint64_t particle_steps;  /* of completed jobs                           */
+  uint64_t bytes_in_use;
+  double busy_s;            /* host time spent waiting on intervals        */
+  double wall_s;            /* since creation                              */
+  int32_t error;
+  int32_t reserved;
+} hd_server_counters;
+
+int hd_server_create(const hd_server_config* cfg, const hd_device_ctx* ctx, hd_server** out);
+
+/* Queues a job of n_steps > 0 steps; *job_id identifies it.  HD_ENOMEM if the
+ * job alone exceeds the budget, HD_EINVAL if it does not fit the slots. */
+int hd_server_submit(hd_server* s, const hd_params* params, int64_t n_steps, uint64_t* job_id);
+
+/* *state: 0 queued, 1 running, 2 done, 3 failed.  times (may be NULL) gets
+ * [submit->admit, submit->done, admit->done] in seconds (-1 if not yet).
+ * When done and out != NULL, out is filled like hd_moments. */
+int hd_server_poll(hd_server* s, uint64_t job_id, int32_t* state, hd_moment_set* out,
+                   double* times);
+
+int hd_server_stats(hd_server* s, hd_server_counters* out);
+
+/* Waits until every submitted job has finished (HD_ESTATE on timeout). */
+int hd_server_drain(hd_server* s, double timeout_s);
+
+/* Stops after the queued and running jobs finish, then releases everything.
+ * NULL-safe. */
+int hd_server_free(hd_server* s);
+
 /* ---- diagnostics -------------------------------------------------------- */
+
+/* Advances the discharge by n_steps > 0 real steps launched one kernel at a
+ * time, with a HIP event pair on the handle's stream around each kernel
+ * group, waits, and writes mean device durations in milliseconds to
+ * out_ms[0..4]: [0] fused electron step (push, removal, MCC, deposit, and
+ * the ion fluid in concurrent workgroups), [1] finalize + field solve,
+ * [2] append, [3] compaction + sort (mean over the sorts that ran, 0 if
+ * none), [4] whole step.  Used to price the kernels against the roofline. */
+int hd_profile_steps(hd_discharge* h, int64_t n_steps, double* out_ms);
 
 /* Evaluates, on the device, the correctly-rounded primitives the particle
  * arithmetic relies on, for n inputs: out[4k+0] = sqrt(a[k]),

@@ -26,7 +26,7 @@ _lock = threading.Lock()
 _lib = None
 
 KIND = {"elastic": 0, "excitation": 1, "ionization": 2}
-N_COUNTERS = 24
+N_COUNTERS = 25
 MAX_CHANNELS = 16
 
 
@@ -198,7 +198,7 @@ class Oracle:
         lib().orc_get_counters(self.h, _p(c))
         return {"coll": c[:self.K].copy(), "absorbed": c[16:18].copy(),
                 "emitted": c[18:20].copy(), "created": int(c[20]), "overflow": int(c[21]),
-                "see_clamped": int(c[22]), "n_acc": int(c[23])}
+                "see_clamped": int(c[22]), "n_acc": int(c[23]), "pushed": int(c[24])}
 
     def accum(self) -> dict:
         nb = self.params["n_eedf_bins"] + 1

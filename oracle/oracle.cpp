@@ -614,6 +614,7 @@ struct Counters {
   uint64_t created = 0;
   uint64_t overflow = 0;
   uint64_t see_clamped = 0;
+  uint64_t pushed = 0;  // particle-steps: live particles pushed
 };
 
 // ---------------------------------------------------------------------------
@@ -814,6 +815,7 @@ struct Discharge : Base {
     for (size_t k = 0; k < parts.size(); ++k) {
       Particle<P>& pt = parts[k];
       if (pt.c < 0) continue;
+      ctr.pushed += 1;
       const int out = push<P>(pt.c, pt.off, pt.vz, Ep.data(), d.nc, q.kdz);
       if (out != 0) {
         ctr.absorbed[out - 1] += 1;
@@ -1002,7 +1004,7 @@ void orc_get_grid(void* h, int64_t* cnt, double* ni, double* gam, double* ne, do
 }
 
 // counters: [coll[0..15], absorbed L, absorbed R, emitted L, emitted R,
-//            created, overflow, see_clamped, n_acc]  (24 values)
+//            created, overflow, see_clamped, n_acc, pushed]  (25 values)
 void orc_get_counters(void* h, uint64_t* out) {
   Base* b = static_cast<Base*>(h);
   for (int k = 0; k < kMaxChannels; ++k) out[k] = b->ctr.coll[k];
@@ -1014,6 +1016,7 @@ void orc_get_counters(void* h, uint64_t* out) {
   out[21] = b->ctr.overflow;
   out[22] = b->ctr.see_clamped;
   out[23] = b->n_acc;
+  out[24] = b->ctr.pushed;
 }
 
 void orc_get_accum(void* h, uint64_t* acc_cnt, double* acc_ni, uint64_t* eedf) {

@@ -43,6 +43,7 @@ struct State {
   uint64_t overflow;
   uint64_t see_clamped;
   uint64_t n_acc;
+  uint64_t pushed;  // live particles pushed (particle-steps) since creation
 };
 
 // Immutable constants and device pointers of one discharge.
@@ -103,7 +104,8 @@ struct Disch {
   uint64_t* eedf;  // [nbins+1]
   // sort
   uint32_t* hist;  // [nc * sort_tiles_max]
-  uint32_t* bin_start;  // [nc + 1]
+  uint32_t* bin_start;  // scan partials
+  int32_t* tile_rng;    // [2 * sort_tiles_max] lowest / highest live cell of each tile
   State* st;
 };
 
@@ -112,7 +114,8 @@ struct Disch {
 // Launch wrappers implemented in the kernel translation units.
 namespace hd {
 template <class P>
-hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, hipStream_t s);
+hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_max,
+                           hipStream_t s);
 template <class P>
 hipError_t launch_append(const Disch<P>* d_dev, int D, int grid, hipStream_t s);
 template <class P>

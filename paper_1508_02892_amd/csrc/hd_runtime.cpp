@@ -4,7 +4,13 @@
 // captured hipGraph per sort interval) and the C ABI of include/hd.h.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -18,12 +24,14 @@ namespace hd {
 
 // kernel-side entry points (k_electron.hip, k_field.hip, k_sort.hip)
 template <class P>
-size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max);
+size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn);
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
-                                int nb1_max, hipStream_t s);
+                                int nb1_max, int fluid_nn, hipStream_t s);
 template <class P>
-int electron_occupancy(int tab_max, int nn_max, int nb1_max, int D);
+int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int D);
+template <class P>
+hipError_t finalize_set_lds(int nn_max);
 template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s);
 template <class P>
@@ -109,7 +117,7 @@ bool validate(const hd_params* p, std::string& why) {
   if (p->precision != HD_FP32 && p->precision != HD_FP64) return (why = "precision"), false;
   if (p->ion_model != HD_ION_DD_CONST_MU && p->ion_model != HD_ION_FULL_CONST_NU)
     return (why = "ion_model"), false;
-  if (p->n_cells < 2 || p->n_cells > 65536) return (why = "n_cells out of [2, 65536]"), false;
+  if (p->n_cells < 2 || p->n_cells > 4096) return (why = "n_cells out of [2, 4096]"), false;
   if (p->n_energy < 2 || p->n_energy > (1 << 20)) return (why = "n_energy"), false;
   if (p->n_channels < 0 || p->n_channels > HD_MAX_CHANNELS) return (why = "n_channels"), false;
   if (p->n_channels > 0 && !p->channels) return (why = "channels missing"), false;
@@ -158,7 +166,7 @@ struct Offsets {
   size_t kc, koff, kvx, kvy, kvz, chunk_kids, chunk_base;
   size_t sc, soff, svx, svy, svz;
   size_t cnt[2], ion_src, ni, gam, phi, E, Ep, scratch, acc_cnt, acc_ni, eedf;
-  size_t ip, tab, hist, parts, st, volt;
+  size_t ip, tab, hist, parts, tile_rng, st, volt;
   size_t total;
 };
 
@@ -204,6 +212,7 @@ Offsets<P> layout(const hd_params& p, int64_t volt_len) {
   o.tab = L.take((size_t)p.n_energy * (size_t)std::max(p.n_channels, 1) * sizeof(P));
   o.hist = L.take((size_t)p.n_cells * (C / kSortTile) * 4);
   o.parts = L.take(sort_parts((size_t)p.n_cells, C / kSortTile) * 4);
+  o.tile_rng = L.take(2 * (C / kSortTile) * 4);
   o.st = L.take(sizeof(State));
   o.volt = L.take((size_t)volt_len * 8);
   o.total = L.total;
@@ -428,7 +437,7 @@ struct BatchBase {
   int device = 0;
   int sort_every = 16;
   int grid_e = 0, grid_a = 0, grid_s = 0;
-  int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0;
+  int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0, fluid_nn = 0;
   int64_t host_step = 0;  // steps enqueued (all discharges advance together)
   hipGraphExec_t graph = nullptr;
   bool graph_ok = true;   // capture supported
@@ -452,7 +461,62 @@ struct Batch : BatchBase {
     if (d_desc) (void)hipFree(d_desc);
   }
 
-  void fill_pointers(Host<P>& h, const Offsets<P>& o) {
+  // Host-side preparation of one discharge (no device calls): derived
+  // constants, tables, the initial load and the voltage table.
+  struct Prepared {
+    std::vector<double> ip, ni, vt;
+    std::vector<P> tab;
+    Loaded<P> ld;
+  };
+  static void prepare_host(Host<P>& h, int64_t volt_len, Prepared& pr) {
+    derive<P>(h, pr.ip, pr.tab);
+    h.volt_len = volt_len;
+    load<P>(h.p, h.dd.dz, pr.ld);
+    const int nn = h.dd.nn;
+    pr.ni.resize(nn);
+    for (int j = 0; j < nn; ++j)
+      pr.ni[j] = (double)pr.ld.cnt[j] * ((j == 0 || j == h.dd.nc) ? h.scale_wall : h.scale_in);
+    pr.vt.resize(volt_len);
+    for (int64_t s = 0; s < volt_len; ++s) pr.vt[s] = volt_at(h.p, s);
+  }
+
+  // Allocates the discharge's device block and uploads the prepared state
+  // (enqueued on the stream; the caller synchronises).
+  static int upload_state(Host<P>& h, const Prepared& pr, hipStream_t stream) {
+    const Offsets<P> o = layout<P>(h.p, h.volt_len);
+    h.bytes = o.total;
+    if (hipMalloc((void**)&h.base, h.bytes) != hipSuccess) {
+      h.base = nullptr;
+      return fail(HD_ENOMEM, "hipMalloc of " + std::to_string(h.bytes) + " bytes failed");
+    }
+    fill_pointers(h, o);
+    HD_TRY(hipMemsetAsync(h.base, 0, h.bytes, stream));
+    const Loaded<P>& ld = pr.ld;
+    const size_t N = (size_t)h.p.n_macro;
+    Disch<P>& d = h.dd;
+    if (N) {
+      HD_TRY(hipMemcpyAsync(d.cell[0], ld.cell.data(), N * 4, hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync(d.off[0], ld.off.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync(d.vx[0], ld.vx.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync(d.vy[0], ld.vy.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync(d.vz[0], ld.vz.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
+      HD_TRY(hipMemcpyAsync(d.id[0], ld.id.data(), N * 4, hipMemcpyHostToDevice, stream));
+    }
+    HD_TRY(hipMemcpyAsync(d.cnt[0], ld.cnt.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
+    HD_TRY(hipMemcpyAsync(d.ni, pr.ni.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
+    HD_TRY(hipMemcpyAsync((void*)d.ip, pr.ip.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
+    HD_TRY(hipMemcpyAsync((void*)d.tab, pr.tab.data(), pr.tab.size() * sizeof(P),
+                          hipMemcpyHostToDevice, stream));
+    HD_TRY(hipMemcpyAsync(h.volt_dev, pr.vt.data(), pr.vt.size() * 8, hipMemcpyHostToDevice,
+                          stream));
+    State st{};
+    st.n_main = (uint32_t)N;
+    st.next_id = (uint32_t)N;
+    HD_TRY(hipMemcpyAsync(d.st, &st, sizeof(State), hipMemcpyHostToDevice, stream));
+    return HD_OK;
+  }
+
+  static void fill_pointers(Host<P>& h, const Offsets<P>& o) {
     unsigned char* b = h.base;
     Disch<P>& d = h.dd;
     const size_t C = round_capacity(h.p.capacity);
@@ -494,6 +558,7 @@ struct Batch : BatchBase {
     d.tab = (const P*)(b + o.tab);
     d.hist = (uint32_t*)(b + o.hist);
     d.bin_start = (uint32_t*)(b + o.parts);
+    d.tile_rng = (int32_t*)(b + o.tile_rng);
     d.st = (State*)(b + o.st);
     h.volt_dev = (double*)(b + o.volt);
     d.volt = h.volt_dev;
@@ -525,12 +590,13 @@ struct Batch : BatchBase {
       nn_max = std::max(nn_max, h.p.n_cells + 1);
       nc_max = std::max(nc_max, h.p.n_cells);
       nb1_max = std::max(nb1_max, h.p.n_eedf_bins + 1);
+      if (h.p.ion_model == HD_ION_FULL_CONST_NU) fluid_nn = std::max(fluid_nn, h.p.n_cells + 1);
     }
     sort_every = hs[0].p.sort_every;
     // launch geometry
     hipDeviceProp_t prop;
     HD_TRY(hipGetDeviceProperties(&prop, device));
-    const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max);
+    const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn);
     if (lds > (size_t)prop.sharedMemPerBlock)
       return fail(HD_EINVAL, "electron kernel needs " + std::to_string(lds) +
                                  " B of LDS, device allows " +
@@ -538,7 +604,8 @@ struct Batch : BatchBase {
     const size_t slds = (size_t)4 * (nc_max + 1) * 4;
     if (slds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "sort LDS too large");
     HD_TRY(sort_set_lds<P>(nc_max));
-    int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, D);
+    HD_TRY(finalize_set_lds<P>(nn_max));
+    int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, D);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     const int cus = prop.multiProcessorCount;
     grid_e = D + cus * occ;
@@ -546,51 +613,15 @@ struct Batch : BatchBase {
     grid_s = cus * 2;
     // per-discharge state
     for (int i = 0; i < n; ++i) {
-      Host<P>& h = hs[i];
-      std::vector<double> ip;
-      std::vector<P> tab;
-      derive<P>(h, ip, tab);
-      h.volt_len = kVoltInitial;
-      const Offsets<P> o = layout<P>(h.p, h.volt_len);
-      h.bytes = o.total;
-      if (hipMalloc((void**)&h.base, h.bytes) != hipSuccess) {
-        h.base = nullptr;
-        return fail(HD_ENOMEM, "hipMalloc of " + std::to_string(h.bytes) + " bytes failed");
-      }
-      fill_pointers(h, o);
-      HD_TRY(hipMemsetAsync(h.base, 0, h.bytes, stream));
-      Loaded<P> ld;
-      load<P>(h.p, h.dd.dz, ld);
-      const size_t N = (size_t)h.p.n_macro;
-      Disch<P>& d = h.dd;
-      if (N) {
-        HD_TRY(hipMemcpyAsync(d.cell[0], ld.cell.data(), N * 4, hipMemcpyHostToDevice, stream));
-        HD_TRY(hipMemcpyAsync(d.off[0], ld.off.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
-        HD_TRY(hipMemcpyAsync(d.vx[0], ld.vx.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
-        HD_TRY(hipMemcpyAsync(d.vy[0], ld.vy.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
-        HD_TRY(hipMemcpyAsync(d.vz[0], ld.vz.data(), N * sizeof(P), hipMemcpyHostToDevice, stream));
-        HD_TRY(hipMemcpyAsync(d.id[0], ld.id.data(), N * 4, hipMemcpyHostToDevice, stream));
-      }
-      std::vector<double> ni(d.nn);
-      for (int j = 0; j < d.nn; ++j)
-        ni[j] = (double)ld.cnt[j] * ((j == 0 || j == d.nc) ? h.scale_wall : h.scale_in);
-      HD_TRY(hipMemcpyAsync(d.cnt[0], ld.cnt.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
-      HD_TRY(hipMemcpyAsync(d.ni, ni.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
-      HD_TRY(hipMemcpyAsync((void*)d.ip, ip.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
-      HD_TRY(hipMemcpyAsync((void*)d.tab, tab.data(), tab.size() * sizeof(P),
-                            hipMemcpyHostToDevice, stream));
-      std::vector<double> vt(h.volt_len);
-      for (int64_t s = 0; s < h.volt_len; ++s) vt[s] = volt_at(h.p, s);
-      HD_TRY(hipMemcpyAsync(h.volt_dev, vt.data(), vt.size() * 8, hipMemcpyHostToDevice, stream));
-      State st{};
-      st.n_main = (uint32_t)N;
-      st.next_id = (uint32_t)N;
-      HD_TRY(hipMemcpyAsync(d.st, &st, sizeof(State), hipMemcpyHostToDevice, stream));
+      Prepared pr;
+      prepare_host(hs[i], kVoltInitial, pr);
+      const int rc = upload_state(hs[i], pr, stream);
+      if (rc) return rc;
       HD_TRY(hipStreamSynchronize(stream));
     }
     HD_TRY(hipMalloc((void**)&d_desc, sizeof(Disch<P>) * D));
     HD_TRY(upload_desc());
-    HD_TRY(launch_finalize<P>(d_desc, D, 1, stream));
+    HD_TRY(launch_finalize<P>(d_desc, D, 1, nn_max, stream));
     HD_TRY(hipStreamSynchronize(stream));
     return HD_OK;
   }
@@ -638,9 +669,9 @@ struct Batch : BatchBase {
   std::vector<double*> extra;
 
   hipError_t enqueue_step(bool with_sort) {
-    hipError_t e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, stream);
+    hipError_t e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, stream);
     if (e != hipSuccess) return e;
-    e = launch_finalize<P>(d_desc, D, 0, stream);
+    e = launch_finalize<P>(d_desc, D, 0, nn_max, stream);
     if (e != hipSuccess) return e;
     e = launch_append<P>(d_desc, D, grid_a, stream);
     if (e != hipSuccess) return e;
@@ -710,9 +741,15 @@ struct Batch : BatchBase {
   int moments(int i, hd_moment_set* m) {
     if (i < 0 || i >= D || !m) return fail(HD_EINVAL, "bad index or output");
     State st;
-    int rc = sync_state(i, st);
-    const Host<P>& h = hs[i];
+    const int rc = sync_state(i, st);
+    const int rc2 = fill_moments(hs[i], st, m);
+    return rc ? rc : rc2;
+  }
+
+  // Moments of a discharge whose stream is idle, given its State.
+  static int fill_moments(const Host<P>& h, const State& st, hd_moment_set* m) {
     const Disch<P>& d = h.dd;
+    const int rc = HD_OK;
     const int nn = d.nn;
     m->step = st.step;
     m->n_slots = st.n_main;
@@ -729,6 +766,7 @@ struct Batch : BatchBase {
     m->e_overflow = st.overflow;
     m->see_clamped = st.see_clamped;
     m->n_acc = st.n_acc;
+    m->pushed = st.pushed;
     std::vector<int64_t> cnt(nn);
     HD_TRY(hipMemcpy(cnt.data(), d.cnt[st.cbuf], nn * 8, hipMemcpyDeviceToHost));
     int64_t tot = 0;
@@ -786,6 +824,60 @@ struct Batch : BatchBase {
     return rc;
   }
 
+  // Real steps, one kernel group at a time, with event pairs around each.
+  int profile(int64_t n, double* out_ms) {
+    if (n <= 0 || !out_ms) return fail(HD_EINVAL, "n_steps must be positive");
+    if (error) return fail(error, "handle is in an error state");
+    int rc = ensure_volt(host_step + n + 1);
+    if (rc) return rc;
+    HD_TRY(launch_set_steps<P>(d_desc, D, n, stream));
+    std::vector<hipEvent_t> ev((size_t)n * 8);
+    for (auto& e : ev) HD_TRY(hipEventCreate(&e));
+    std::vector<int> sorted((size_t)n, 0);
+    hipError_t err = hipSuccess;
+    for (int64_t s = 0; s < n && err == hipSuccess; ++s) {
+      hipEvent_t* e = &ev[(size_t)s * 8];
+      const bool srt = ((host_step + 1) % sort_every) == 0;
+      sorted[(size_t)s] = srt;
+      err = hipEventRecord(e[0], stream);
+      if (err == hipSuccess)
+        err = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, stream);
+      if (err == hipSuccess) err = hipEventRecord(e[1], stream);
+      if (err == hipSuccess) err = hipEventRecord(e[2], stream);
+      if (err == hipSuccess) err = launch_finalize<P>(d_desc, D, 0, nn_max, stream);
+      if (err == hipSuccess) err = hipEventRecord(e[3], stream);
+      if (err == hipSuccess) err = hipEventRecord(e[4], stream);
+      if (err == hipSuccess) err = launch_append<P>(d_desc, D, grid_a, stream);
+      if (err == hipSuccess) err = hipEventRecord(e[5], stream);
+      if (err == hipSuccess) err = hipEventRecord(e[6], stream);
+      if (err == hipSuccess && srt) err = launch_sort_impl<P>(d_desc, D, grid_s, nc_max, stream);
+      if (err == hipSuccess) err = hipEventRecord(e[7], stream);
+      host_step += 1;
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    double acc[5] = {0, 0, 0, 0, 0};
+    int nsort = 0;
+    for (int64_t s = 0; s < n && err == hipSuccess; ++s) {
+      hipEvent_t* e = &ev[(size_t)s * 8];
+      float t[5];
+      err = hipEventElapsedTime(&t[0], e[0], e[1]);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t[1], e[2], e[3]);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t[2], e[4], e[5]);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t[3], e[6], e[7]);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t[4], e[0], e[7]);
+      for (int k = 0; k < 5; ++k)
+        if (k != 3) acc[k] += t[k];
+      if (sorted[(size_t)s]) {
+        acc[3] += t[3];
+        nsort += 1;
+      }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess) return fail(HD_EDEVICE, hipGetErrorString(err));
+    for (int k = 0; k < 5; ++k) out_ms[k] = k == 3 ? (nsort ? acc[3] / nsort : 0.0) : acc[k] / n;
+    return HD_OK;
+  }
+
   int push_field(int i, void* out) {
     State st;
     int rc = sync_state(i, st);
@@ -798,6 +890,379 @@ template <class P>
 size_t required_bytes(const hd_params& p) {
   return layout<P>(p, kVoltInitial).total + sizeof(Disch<P>);
 }
+
+// ---------------------------------------------------------------------------
+// Served job stream: continuous batching over a fixed set of slots.  A host
+// thread admits queued jobs into free slots while the device-memory budget
+// allows, replays one captured interval of sort_every steps over all slots
+// (idle slots point at an idle State and cost nothing), and retires jobs that
+// reached their step count.  Jobs start at interval boundaries, so each
+// job's steps -- and its result -- are exactly those of a run alone.
+// ---------------------------------------------------------------------------
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct JobResult {
+  std::vector<double> n_e, n_i, phi, E, gam, n_e_avg, n_i_avg, eedf;
+  std::vector<int64_t> cnt;
+  std::vector<uint64_t> eedf_counts;
+  hd_moment_set m{};
+};
+
+struct Job {
+  uint64_t id = 0;
+  hd_params p{};
+  std::vector<hd_xs_channel> ch;
+  std::vector<std::vector<double>> sig;
+  int64_t n_steps = 0;
+  size_t bytes = 0;
+  int state = 0;  // 0 queued, 1 running, 2 done, 3 failed
+  int err = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  JobResult res;
+};
+
+struct ServerBase {
+  virtual ~ServerBase() {}
+  virtual int submit(const hd_params* p, int64_t n, uint64_t* id) = 0;
+  virtual int poll(uint64_t id, int32_t* state, hd_moment_set* out, double* times) = 0;
+  virtual int stats(hd_server_counters* out) = 0;
+  virtual int drain(double timeout_s) = 0;
+};
+
+template <class P>
+struct Server : ServerBase {
+  using B = Batch<P>;
+  hd_server_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr, own_stream = nullptr;
+  int S = 0;
+  Disch<P>* d_desc = nullptr;
+  State* d_idle = nullptr;
+  std::vector<Host<P>> hs;
+  std::vector<Job*> slot_job;
+  std::vector<int64_t> slot_done;  // steps completed by the job in the slot
+  int grid_e = 0, grid_a = 0, grid_s = 0, tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0,
+      fluid_nn = 0;
+  hipGraphExec_t graph = nullptr;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread worker;
+  bool stop = false;
+  int worker_err = 0;
+  std::string worker_msg;
+  std::map<uint64_t, std::unique_ptr<Job>> jobs;
+  std::deque<Job*> queue;
+  uint64_t next_job = 1;
+  size_t used = 0;
+  uint64_t chunks = 0, pushed_done = 0, completed = 0, failed = 0;
+  double busy_s = 0, t_start = 0;
+
+  ~Server() override {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    if (worker.joinable()) worker.join();
+    if (graph) (void)hipGraphExecDestroy(graph);
+    for (auto& h : hs)
+      if (h.base) (void)hipFree(h.base);
+    if (d_desc) (void)hipFree(d_desc);
+    if (d_idle) (void)hipFree(d_idle);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+  }
+
+  Disch<P> idle_entry() const {
+    Disch<P> e{};
+    e.st = d_idle;
+    return e;
+  }
+
+  int create(const hd_server_config* c, const hd_device_ctx* ctx) {
+    cfg = *c;
+    S = cfg.max_slots;
+    device = ctx ? ctx->device : 0;
+    stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    HD_TRY(hipSetDevice(device));
+    if (!stream) {
+      HD_TRY(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+      stream = own_stream;
+    }
+    tab_max = cfg.max_energy * std::max(1, cfg.max_channels);
+    nn_max = cfg.max_cells + 1;
+    nc_max = cfg.max_cells;
+    nb1_max = cfg.max_eedf_bins + 1;
+    fluid_nn = cfg.allow_full_fluid ? nn_max : 0;
+    hipDeviceProp_t prop;
+    HD_TRY(hipGetDeviceProperties(&prop, device));
+    const size_t lds = electron_lds_bytes<P>(S, tab_max, nn_max, nb1_max, fluid_nn);
+    if (lds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "slot caps exceed LDS");
+    HD_TRY(sort_set_lds<P>(nc_max));
+    HD_TRY(finalize_set_lds<P>(nn_max));
+    const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, S);
+    if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
+    grid_e = S + prop.multiProcessorCount * occ;
+    grid_a = prop.multiProcessorCount;
+    grid_s = prop.multiProcessorCount * 2;
+    HD_TRY(hipMalloc((void**)&d_idle, sizeof(State)));
+    HD_TRY(hipMemset(d_idle, 0, sizeof(State)));
+    HD_TRY(hipMalloc((void**)&d_desc, sizeof(Disch<P>) * S));
+    hs.resize(S);
+    slot_job.assign(S, nullptr);
+    slot_done.assign(S, 0);
+    std::vector<Disch<P>> v(S, idle_entry());
+    HD_TRY(hipMemcpy(d_desc, v.data(), sizeof(Disch<P>) * S, hipMemcpyHostToDevice));
+    // capture one interval of sort_every steps over all slots
+    hipGraph_t g = nullptr;
+    HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < cfg.sort_every && e == hipSuccess; ++s) {
+      e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, stream);
+      if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, stream);
+      if (e == hipSuccess) e = launch_append<P>(d_desc, S, grid_a, stream);
+      if (e == hipSuccess && s == cfg.sort_every - 1)
+        e = launch_sort_impl<P>(d_desc, S, grid_s, nc_max, stream);
+    }
+    const hipError_t e2 = hipStreamEndCapture(stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess)
+      return fail(HD_EDEVICE, std::string("capture failed: ") + hipGetErrorString(e ? e : e2));
+    e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(HD_EDEVICE, hipGetErrorString(e));
+    t_start = now_s();
+    worker = std::thread([this]() { loop(); });
+    return HD_OK;
+  }
+
+  int submit(const hd_params* p, int64_t n, uint64_t* id) override {
+    std::string why;
+    if (!validate(p, why)) return fail(HD_EINVAL, why);
+    if (n < 1) return fail(HD_EINVAL, "n_steps must be positive");
+    if (p->precision != cfg.precision || p->sort_every != cfg.sort_every ||
+        p->eedf_every != cfg.eedf_every || p->n_cells > cfg.max_cells ||
+        p->n_energy * std::max(1, p->n_channels) > tab_max ||
+        p->n_eedf_bins > cfg.max_eedf_bins ||
+        (p->ion_model == HD_ION_FULL_CONST_NU && !cfg.allow_full_fluid))
+      return fail(HD_EINVAL, "job does not fit the server's slot configuration");
+    auto job = std::make_unique<Job>();
+    job->p = *p;
+    job->sig.resize(p->n_channels);
+    job->ch.resize(p->n_channels);
+    for (int k = 0; k < p->n_channels; ++k) {
+      job->sig[k].assign(p->channels[k].sigma_m2, p->channels[k].sigma_m2 + p->n_energy);
+      job->ch[k] = p->channels[k];
+      job->ch[k].sigma_m2 = job->sig[k].data();
+    }
+    job->p.channels = job->ch.empty() ? nullptr : job->ch.data();
+    job->n_steps = n;
+    job->bytes = layout<P>(job->p, std::max<int64_t>(kVoltInitial, n + 2)).total;
+    if (job->bytes > cfg.hbm_budget_bytes) return fail(HD_ENOMEM, "job exceeds the HBM budget");
+    job->t_submit = now_s();
+    std::lock_guard<std::mutex> g(mu);
+    if (worker_err) return fail(worker_err, worker_msg);
+    job->id = next_job++;
+    *id = job->id;
+    queue.push_back(job.get());
+    jobs[job->id] = std::move(job);
+    cv.notify_all();
+    return HD_OK;
+  }
+
+  void set_error(int code, const std::string& m) {
+    std::lock_guard<std::mutex> g(mu);
+    worker_err = code;
+    worker_msg = m;
+    stop = true;
+    cv.notify_all();
+  }
+
+  // Admit one job into a slot (worker thread; device calls on the stream).
+  int admit(int slot, Job* job) {
+    Host<P>& h = hs[slot];
+    h = Host<P>();
+    h.p = job->p;
+    h.p.channels = job->ch.empty() ? nullptr : job->ch.data();
+    typename B::Prepared pr;
+    B::prepare_host(h, std::max<int64_t>(kVoltInitial, job->n_steps + 2), pr);
+    int rc = B::upload_state(h, pr, stream);
+    if (rc) return rc;
+    HD_TRY(hipMemcpyAsync(d_desc + slot, &h.dd, sizeof(Disch<P>), hipMemcpyHostToDevice, stream));
+    HD_TRY(launch_finalize<P>(d_desc + slot, 1, 1, nn_max, stream));
+    const int64_t n = job->n_steps;
+    HD_TRY(hipMemcpyAsync(&h.dd.st->steps_left, &n, sizeof(int64_t), hipMemcpyHostToDevice,
+                          stream));
+    HD_TRY(hipStreamSynchronize(stream));
+    slot_job[slot] = job;
+    slot_done[slot] = 0;
+    return HD_OK;
+  }
+
+  int retire(int slot) {
+    Host<P>& h = hs[slot];
+    Job* job = slot_job[slot];
+    State st;
+    HD_TRY(hipMemcpy(&st, h.dd.st, sizeof(State), hipMemcpyDeviceToHost));
+    const int nn = h.dd.nn;
+    JobResult& r = job->res;
+    r.n_e.resize(nn);
+    r.n_i.resize(nn);
+    r.phi.resize(nn);
+    r.E.resize(nn);
+    r.gam.resize(nn);
+    r.n_e_avg.resize(nn);
+    r.n_i_avg.resize(nn);
+    r.cnt.resize(nn);
+    r.eedf_counts.resize(h.dd.nbins + 1);
+    r.eedf.resize(h.dd.nbins);
+    hd_moment_set& m = r.m;
+    m.n_e = r.n_e.data();
+    m.n_i = r.n_i.data();
+    m.phi = r.phi.data();
+    m.E = r.E.data();
+    m.gamma_i = r.gam.data();
+    m.n_e_avg = r.n_e_avg.data();
+    m.n_i_avg = r.n_i_avg.data();
+    m.cnt = r.cnt.data();
+    m.eedf_counts = r.eedf_counts.data();
+    m.eedf = r.eedf.data();
+    const int rc = B::fill_moments(h, st, &m);
+    const Disch<P> ie = idle_entry();
+    HD_TRY(hipMemcpy(d_desc + slot, &ie, sizeof(Disch<P>), hipMemcpyHostToDevice));
+    (void)hipFree(h.base);
+    h.base = nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    job->t_done = now_s();
+    job->err = st.error ? st.error : rc;
+    job->state = job->err ? 3 : 2;
+    (job->err ? failed : completed) += 1;
+    pushed_done += st.pushed;
+    used -= job->bytes;
+    slot_job[slot] = nullptr;
+    cv.notify_all();
+    return HD_OK;
+  }
+
+  void loop() {
+    if (hipSetDevice(device) != hipSuccess) return set_error(HD_EDEVICE, "hipSetDevice failed");
+    for (;;) {
+      std::vector<std::pair<int, Job*>> admits;
+      {
+        std::unique_lock<std::mutex> g(mu);
+        for (int s = 0; s < S && !queue.empty(); ++s) {
+          if (slot_job[s]) continue;
+          Job* j = queue.front();
+          if (used + j->bytes > cfg.hbm_budget_bytes) break;
+          queue.pop_front();
+          used += j->bytes;
+          j->state = 1;
+          j->t_admit = now_s();
+          slot_job[s] = j;  // reserved
+          admits.push_back({s, j});
+        }
+        bool active = !admits.empty();
+        for (int s = 0; s < S; ++s) active = active || slot_job[s] != nullptr;
+        if (!active) {
+          if (stop) return;
+          cv.wait_for(g, std::chrono::milliseconds(2));
+          continue;
+        }
+      }
+      for (auto& a : admits) {
+        const int rc = admit(a.first, a.second);
+        if (rc) return set_error(rc, g_err);
+      }
+      const double t0 = now_s();
+      if (hipGraphLaunch(graph, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+        return set_error(HD_EDEVICE, "interval launch failed");
+      busy_s += now_s() - t0;
+      chunks += 1;
+      for (int s = 0; s < S; ++s) {
+        Job* j = slot_job[s];
+        if (!j) continue;
+        slot_done[s] += cfg.sort_every;
+        if (slot_done[s] >= j->n_steps) {
+          const int rc = retire(s);
+          if (rc) return set_error(rc, g_err);
+        }
+      }
+      std::lock_guard<std::mutex> g(mu);
+      if (stop && queue.empty()) {
+        bool active = false;
+        for (int s = 0; s < S; ++s) active = active || slot_job[s] != nullptr;
+        if (!active) return;
+      }
+    }
+  }
+
+  int poll(uint64_t id, int32_t* state, hd_moment_set* out, double* times) override {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = jobs.find(id);
+    if (it == jobs.end()) return fail(HD_EINVAL, "unknown job");
+    Job* j = it->second.get();
+    if (state) *state = j->state;
+    if (times) {
+      times[0] = j->state >= 1 ? j->t_admit - j->t_submit : -1.0;
+      times[1] = j->state >= 2 ? j->t_done - j->t_submit : -1.0;
+      times[2] = j->state >= 2 ? j->t_done - j->t_admit : -1.0;
+    }
+    if (j->state < 2 || !out) return HD_OK;
+    const hd_moment_set& m = j->res.m;
+    double* arr_out[] = {out->n_e, out->n_i, out->phi, out->E, out->gamma_i, out->n_e_avg,
+                         out->n_i_avg};
+    const double* arr_in[] = {m.n_e, m.n_i, m.phi, m.E, m.gamma_i, m.n_e_avg, m.n_i_avg};
+    for (int k = 0; k < 7; ++k)
+      if (arr_out[k]) std::copy(arr_in[k], arr_in[k] + m.n_nodes, arr_out[k]);
+    if (out->cnt) std::copy(m.cnt, m.cnt + m.n_nodes, out->cnt);
+    if (out->eedf_counts) std::copy(m.eedf_counts, m.eedf_counts + m.n_eedf_bins + 1, out->eedf_counts);
+    if (out->eedf) std::copy(m.eedf, m.eedf + m.n_eedf_bins, out->eedf);
+    hd_moment_set keep = *out;
+    *out = m;
+    out->n_e = keep.n_e;
+    out->n_i = keep.n_i;
+    out->phi = keep.phi;
+    out->E = keep.E;
+    out->gamma_i = keep.gamma_i;
+    out->n_e_avg = keep.n_e_avg;
+    out->n_i_avg = keep.n_i_avg;
+    out->cnt = keep.cnt;
+    out->eedf_counts = keep.eedf_counts;
+    out->eedf = keep.eedf;
+    return j->err ? fail(j->err, "job failed on the device") : HD_OK;
+  }
+
+  int stats(hd_server_counters* out) override {
+    std::lock_guard<std::mutex> g(mu);
+    out->submitted = next_job - 1;
+    out->completed = completed;
+    out->failed = failed;
+    out->queued = queue.size();
+    uint64_t running = 0;
+    for (int s = 0; s < S; ++s) running += slot_job[s] ? 1 : 0;
+    out->running = running;
+    out->intervals = chunks;
+    out->particle_steps = pushed_done;
+    out->bytes_in_use = used;
+    out->busy_s = busy_s;
+    out->wall_s = now_s() - t_start;
+    out->error = worker_err;
+    return worker_err ? fail(worker_err, worker_msg) : HD_OK;
+  }
+
+  int drain(double timeout_s) override {
+    const double t_end = now_s() + timeout_s;
+    std::unique_lock<std::mutex> g(mu);
+    for (;;) {
+      if (worker_err) return fail(worker_err, worker_msg);
+      bool busy = !queue.empty();
+      for (int s = 0; s < S; ++s) busy = busy || slot_job[s] != nullptr;
+      if (!busy) return HD_OK;
+      if (now_s() > t_end) return fail(HD_ESTATE, "drain timed out");
+      cv.wait_for(g, std::chrono::milliseconds(5));
+    }
+  }
+};
 
 }  // namespace hd
 
@@ -895,6 +1360,70 @@ int hd_get_particles(hd_discharge* h, int32_t* cell, void* off, void* vx, void* 
 int hd_get_push_field(hd_discharge* h, void* ep) {
   if (!h || !ep) return hd::fail(HD_EINVAL, "null argument");
   return dispatch(h->b.impl, [&](auto* x) { return x->push_field(0, ep); });
+}
+
+struct hd_server {
+  hd::ServerBase* impl;
+};
+
+int hd_server_create(const hd_server_config* cfg, const hd_device_ctx* ctx, hd_server** out) {
+  if (!cfg || !out) return hd::fail(HD_EINVAL, "null argument");
+  if ((cfg->precision != HD_FP32 && cfg->precision != HD_FP64) || cfg->max_slots < 1 ||
+      cfg->max_slots > 1024 || cfg->sort_every < 1 || cfg->eedf_every < 1 ||
+      cfg->max_cells < 2 || cfg->max_cells > 4096 || cfg->max_energy < 2 ||
+      cfg->max_channels < 0 || cfg->max_channels > HD_MAX_CHANNELS || cfg->max_eedf_bins < 1 ||
+      cfg->hbm_budget_bytes == 0)
+    return hd::fail(HD_EINVAL, "invalid server configuration");
+  hd::ServerBase* s = nullptr;
+  int rc;
+  if (cfg->precision == HD_FP32) {
+    auto* x = new hd::Server<float>();
+    rc = x->create(cfg, ctx);
+    s = x;
+  } else {
+    auto* x = new hd::Server<double>();
+    rc = x->create(cfg, ctx);
+    s = x;
+  }
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  *out = new hd_server{s};
+  return HD_OK;
+}
+
+int hd_server_submit(hd_server* s, const hd_params* p, int64_t n, uint64_t* job_id) {
+  if (!s || !job_id) return hd::fail(HD_EINVAL, "null argument");
+  return s->impl->submit(p, n, job_id);
+}
+
+int hd_server_poll(hd_server* s, uint64_t job_id, int32_t* state, hd_moment_set* out,
+                   double* times) {
+  if (!s) return hd::fail(HD_EINVAL, "null handle");
+  return s->impl->poll(job_id, state, out, times);
+}
+
+int hd_server_stats(hd_server* s, hd_server_counters* out) {
+  if (!s || !out) return hd::fail(HD_EINVAL, "null argument");
+  return s->impl->stats(out);
+}
+
+int hd_server_drain(hd_server* s, double timeout_s) {
+  if (!s) return hd::fail(HD_EINVAL, "null handle");
+  return s->impl->drain(timeout_s);
+}
+
+int hd_server_free(hd_server* s) {
+  if (!s) return HD_OK;
+  delete s->impl;
+  delete s;
+  return HD_OK;
+}
+
+int hd_profile_steps(hd_discharge* h, int64_t n, double* out_ms) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl, [&](auto* x) { return x->profile(n, out_ms); });
 }
 
 int hd_free(hd_discharge* h) {

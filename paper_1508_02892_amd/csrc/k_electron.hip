@@ -33,6 +33,7 @@ struct ElecArgs {
   int tab_max;    // max ne*K over the batch
   int nn_max;     // max nodes
   int nb1_max;    // max eedf bins + 1
+  int fluid_nn;   // max nodes of a full-fluid discharge (its solver lives in LDS), 0 if none
 };
 
 struct Lds {
@@ -40,7 +41,7 @@ struct Lds {
 };
 
 // LDS counters: [0, kMaxK) collisions per channel, then these.
-enum { kCtrAbsL = kMaxK, kCtrAbsR, kCtrCreated, kCtrOverflow, kCtrN };
+enum { kCtrAbsL = kMaxK, kCtrAbsR, kCtrCreated, kCtrOverflow, kCtrPushed, kCtrN };
 
 template <class P>
 __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
@@ -54,6 +55,8 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
   L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
   L.wsum = al(L.pre + (uint32_t)(a.D + 1) * 4u);
   L.total = al(L.wsum + 16u * 4u);
+  const uint32_t fluid = 4u * (uint32_t)a.fluid_nn * 8u;  // a, b, c/c', r/d' of Eq (2.3)
+  if (fluid > L.total) L.total = al(fluid);
   return L;
 }
 
@@ -144,32 +147,49 @@ __device__ void handle(const Disch<P>& d, QEntry<P>& e, uint32_t lc, uint32_t st
   atomicAdd(&ctr[e.ch], 1u);
 }
 
+// The four consecutive slots a thread owns in a chunk.
+template <class P>
+struct Slots {
+  int32_t c[4];
+  P off[4], vx[4], vy[4], vz[4];
+  uint32_t id[4];
+};
+
+template <class P>
+__device__ __forceinline__ void load_slots(const Disch<P>& d, int buf, uint32_t lc, Slots<P>& s) {
+  const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)threadIdx.x * (uint32_t)kPerThread;
+  ld4(d.cell[buf] + i0, s.c);
+  ld4(d.off[buf] + i0, s.off);
+  ld4(d.vx[buf] + i0, s.vx);
+  ld4(d.vy[buf] + i0, s.vy);
+  ld4(d.vz[buf] + i0, s.vz);
+  ld4(d.id[buf] + i0, s.id);
+}
+
 // One chunk of kTile consecutive particle slots.
 template <class P>
 __device__ void chunk(const Disch<P>& d, uint32_t lc, uint32_t step, uint32_t n_main, int buf,
                       bool sample, const P* tab, int64_t* bins, QEntry<P>* q, uint32_t* eedf,
-                      uint32_t* ctr, uint32_t* wsum) {
+                      uint32_t* ctr, uint32_t* wsum, Slots<P>& in) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
-  int32_t c[4];
-  P off[4], vx[4], vy[4], vz[4];
-  uint32_t id[4];
-  ld4(d.cell[buf] + i0, c);
-  ld4(d.off[buf] + i0, off);
-  ld4(d.vx[buf] + i0, vx);
-  ld4(d.vy[buf] + i0, vy);
-  ld4(d.vz[buf] + i0, vz);
-  ld4(d.id[buf] + i0, id);
+  int32_t (&c)[4] = in.c;
+  P (&off)[4] = in.off;
+  P (&vx)[4] = in.vx;
+  P (&vy)[4] = in.vy;
+  P (&vz)[4] = in.vz;
+  uint32_t (&id)[4] = in.id;
   const P* Ep = d.Ep;
   const int K = d.K;
   int ch[4];
   bool alive[4];
-  uint32_t n_absl = 0, n_absr = 0, n_ovf = 0;
+  uint32_t n_absl = 0, n_absr = 0, n_ovf = 0, n_push = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     ch[j] = -1;
     alive[j] = (i0 + (uint32_t)j < n_main) && (c[j] >= 0);
+    n_push += (uint32_t)__popcll(__ballot(alive[j]));
     if (alive[j]) {
       // leapfrog push, linear gather of E' = (-e/m_e) dt E
       const P e0 = Ep[c[j]];
@@ -239,6 +259,7 @@ __device__ void chunk(const Disch<P>& d, uint32_t lc, uint32_t step, uint32_t n_
   if (n_absl) atomicAdd(&ctr[kCtrAbsL], n_absl);
   if (n_absr) atomicAdd(&ctr[kCtrAbsR], n_absr);
   if (n_ovf) atomicAdd(&ctr[kCtrOverflow], n_ovf);
+  if (lane == 0 && n_push) atomicAdd(&ctr[kCtrPushed], n_push);
 
   // collision queue positions and child slots, in particle order
   bool col[4], ion[4];
@@ -369,8 +390,14 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   const int buf = st->buf;
   int64_t* cnt = d.cnt[st->cbuf ^ 1];
   __syncthreads();
-  for (uint32_t lc = lc0; lc < lc1; ++lc)
-    chunk<P>(d, lc, step, n_main, buf, sample, tab, bins, q, eedf, ctr, wsum);
+  // the next chunk's slots are loaded before the current one is processed
+  Slots<P> cur, nxt;
+  load_slots<P>(d, buf, lc0, cur);
+  for (uint32_t lc = lc0; lc < lc1; ++lc) {
+    if (lc + 1 < lc1) load_slots<P>(d, buf, lc + 1, nxt);
+    chunk<P>(d, lc, step, n_main, buf, sample, tab, bins, q, eedf, ctr, wsum, cur);
+    cur = nxt;
+  }
   __syncthreads();
   for (int i = tid; i < d.nn; i += kThreads) {
     const int64_t v = bins[i];
@@ -390,6 +417,8 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->created), (unsigned long long)ctr[tid]);
   if (tid == kCtrOverflow && ctr[tid])
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->overflow), (unsigned long long)ctr[tid]);
+  if (tid == kCtrPushed && ctr[tid])
+    atomicAdd(reinterpret_cast<unsigned long long*>(&st->pushed), (unsigned long long)ctr[tid]);
   __syncthreads();
 }
 
@@ -451,7 +480,7 @@ __device__ void fluid_dd(const Disch<P>& d) {
 // advection (tridiagonal; Thomas method, one reciprocal per row), drift wall
 // fluxes with mu = e/(M nu) (Eq 2.6), then Eq (2.4).
 template <class P>
-__device__ void fluid_full(const Disch<P>& d) {
+__device__ void fluid_full(const Disch<P>& d, double* lds) {
   const int tid = threadIdx.x, nc = d.nc, nn = d.nn, m = nc - 1;
   double* ni = d.ni;
   double* gam = d.gam;
@@ -460,12 +489,6 @@ __device__ void fluid_full(const Disch<P>& d) {
   double* g0 = n0 + nn;
   double* u = g0 + nn;
   double* T = u + nn;
-  double* a = T + nn;
-  double* b = a + nn;
-  double* c = b + nn;
-  double* r = c + nn;
-  double* cp = r + nn;
-  double* dp = cp + nn;
   const double nu = d.nu, mu = d.mu_full;
   for (int j = tid; j < nn; j += kThreads) {
     const double nj = ni[j], gj = gam[j];
@@ -475,45 +498,52 @@ __device__ void fluid_full(const Disch<P>& d) {
     T[j] = ion_temperature(d, mu, E[j]);
   }
   __syncthreads();
+  // tridiagonal coefficients in LDS so that the serial elimination reads
+  // its operands at LDS latency; c and r are overwritten by c' and d'
+  double* La = lds;
+  double* Lb = La + nn;
+  double* Lc = Lb + nn;
+  double* Lr = Lc + nn;
   for (int j = 1 + tid; j <= m; j += kThreads) {
     const int k = j - 1;
-    a[k] = -d.dt_2dz * u[j - 1];
-    b[k] = 1.0 + nu * d.hdt;
-    c[k] = d.dt_2dz * u[j + 1];
-    r[k] = (g0[j] * (1.0 - nu * d.hdt) + (d.e_M_dt * n0[j]) * E[j]) -
-           d.dt_2dzM * (n0[j + 1] * T[j + 1] - n0[j - 1] * T[j - 1]);
+    La[k] = -d.dt_2dz * u[j - 1];
+    Lb[k] = 1.0 + nu * d.hdt;
+    Lc[k] = d.dt_2dz * u[j + 1];
+    Lr[k] = (g0[j] * (1.0 - nu * d.hdt) + (d.e_M_dt * n0[j]) * E[j]) -
+            d.dt_2dzM * (n0[j + 1] * T[j + 1] - n0[j - 1] * T[j - 1]);
   }
   __syncthreads();
+  const double gl = (mu * n0[0]) * dmin0(E[0]);
+  const double gr = (mu * n0[nc]) * dmax0(E[nc]);
   if (tid == 0) {
-    const double gl = (mu * n0[0]) * dmin0(E[0]);
-    const double gr = (mu * n0[nc]) * dmax0(E[nc]);
-    r[0] = r[0] - a[0] * gl;
-    r[m - 1] = r[m - 1] - c[m - 1] * gr;
-    double cpp = 0.0, dpp = 0.0;
-    for (int k = 0; k < m; ++k) {
-      double den = b[k];
-      double num = r[k];
-      if (k > 0) {
-        den = b[k] - a[k] * cpp;
-        num = r[k] - a[k] * dpp;
-      }
-      const double rr = 1.0 / den;
-      cpp = c[k] * rr;
+    Lr[0] = Lr[0] - La[0] * gl;
+    Lr[m - 1] = Lr[m - 1] - Lc[m - 1] * gr;
+    double rr = 1.0 / Lb[0];
+    double cpp = Lc[0] * rr;
+    double dpp = Lr[0] * rr;
+    Lc[0] = cpp;
+    Lr[0] = dpp;
+    for (int k = 1; k < m; ++k) {
+      const double ak = La[k];
+      const double den = Lb[k] - ak * cpp;
+      const double num = Lr[k] - ak * dpp;
+      rr = 1.0 / den;
+      cpp = Lc[k] * rr;
       dpp = num * rr;
-      cp[k] = cpp;
-      dp[k] = dpp;
+      Lc[k] = cpp;
+      Lr[k] = dpp;
     }
-    double x = dp[m - 1];
-    gam[m] = x;
+    double x = dpp;
+    La[m - 1] = x;
     for (int k = m - 2; k >= 0; --k) {
-      x = dp[k] - cp[k] * x;
-      gam[k + 1] = x;
+      x = Lr[k] - Lc[k] * x;
+      La[k] = x;
     }
-    gam[0] = gl;
-    gam[nc] = gr;
     d.st->wall[0] = gl;
     d.st->wall[1] = gr;
   }
+  __syncthreads();
+  for (int j = tid; j < nn; j += kThreads) gam[j] = (j == 0) ? gl : (j == nc) ? gr : La[j - 1];
   __syncthreads();
   for (int j = tid; j < nn; j += kThreads) {
     double v;
@@ -538,7 +568,7 @@ __global__ __launch_bounds__(kThreads) void k_electron(const Disch<P>* __restric
       if (d.ion_model == 0)
         fluid_dd<P>(d);
       else
-        fluid_full<P>(d);
+        fluid_full<P>(d, reinterpret_cast<double*>(smem));
     }
     return;
   }
@@ -572,24 +602,24 @@ __global__ __launch_bounds__(kThreads) void k_electron(const Disch<P>* __restric
 }  // namespace
 
 template <class P>
-size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max) {
-  ElecArgs a{D, tab_max, nn_max, nb1_max};
+size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn) {
+  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn};
   return lds_layout<P>(a).total;
 }
 
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
-                                int nb1_max, hipStream_t s) {
-  ElecArgs a{D, tab_max, nn_max, nb1_max};
+                                int nb1_max, int fluid_nn, hipStream_t s) {
+  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn};
   const size_t lds = lds_layout<P>(a).total;
   hipLaunchKernelGGL(k_electron<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, a);
   return hipGetLastError();
 }
 
 template <class P>
-int electron_occupancy(int tab_max, int nn_max, int nb1_max, int D) {
+int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int D) {
   int nb = 0;
-  const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max);
+  const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn);
   if (hipFuncSetAttribute((const void*)k_electron<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds) != hipSuccess)
     return 0;
@@ -598,13 +628,13 @@ int electron_occupancy(int tab_max, int nn_max, int nb1_max, int D) {
   return nb;
 }
 
-template size_t electron_lds_bytes<float>(int, int, int, int);
-template size_t electron_lds_bytes<double>(int, int, int, int);
-template hipError_t launch_electron_impl<float>(const Disch<float>*, int, int, int, int, int,
+template size_t electron_lds_bytes<float>(int, int, int, int, int);
+template size_t electron_lds_bytes<double>(int, int, int, int, int);
+template hipError_t launch_electron_impl<float>(const Disch<float>*, int, int, int, int, int, int,
                                                 hipStream_t);
 template hipError_t launch_electron_impl<double>(const Disch<double>*, int, int, int, int, int,
-                                                 hipStream_t);
-template int electron_occupancy<float>(int, int, int, int);
-template int electron_occupancy<double>(int, int, int, int);
+                                                 int, hipStream_t);
+template int electron_occupancy<float>(int, int, int, int, int);
+template int electron_occupancy<double>(int, int, int, int, int);
 
 }  // namespace hd

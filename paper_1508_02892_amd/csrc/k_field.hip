@@ -119,70 +119,49 @@ __device__ __forceinline__ double scale_of(const Disch<P>& d, int j) {
 // the constant inverse pivots, one fused multiply-add per sweep step), E from
 // centred differences inside and Gauss's law over the wall half cells, and
 // E' = (-e/m_e) dt E rounded to the particle precision.
+// The serial sweeps read their operands (g_j = d_j/b'_j, 1/b'_j, y_j) from
+// LDS; lds holds 3 * nn doubles.
 template <class P>
-__device__ void field(const Disch<P>& d, const int64_t* cn, double V) {
+__device__ void field(const Disch<P>& d, const int64_t* cn, double V, double* lds) {
   const int tid = threadIdx.x, nc = d.nc, nn = d.nn, m = nc - 1;
   double* rho = d.scratch;
-  double* g = rho + nn;
-  double* y = g + nn;
-  double* phi = d.phi;
+  double* g = lds;         // g_j, then phi_j
+  double* ip = lds + nn;   // 1 / b'_j
+  double* y = ip + nn;     // forward-sweep values
   for (int j = tid; j < nn; j += kFinThreads) {
     const double ne = (double)load_dev(&cn[j]) * scale_of(d, j);
     const double r = kECharge * (d.ni[j] - ne);
     rho[j] = r;
+    const double ipj = d.ip[j];
+    ip[j] = ipj;
     if (j >= 1 && j <= m) {
       double dj = d.kp * r;
       if (j == 1) dj = dj + V;
       if (j == m) dj = dj + 0.0;
-      g[j] = dj * d.ip[j];
+      g[j] = dj * ipj;
     }
   }
   __syncthreads();
+  if (tid == 0 && m >= 1) {
+    double acc = g[1];
+    y[1] = acc;
+    for (int j = 2; j <= m; ++j) {
+      acc = fma(acc, ip[j], g[j]);
+      y[j] = acc;
+    }
+    double x = acc;
+    g[m] = x;
+    for (int j = m - 1; j >= 1; --j) {
+      x = fma(ip[j], x, y[j]);
+      g[j] = x;
+    }
+  }
   if (tid == 0) {
-    phi[0] = V;
-    phi[nc] = 0.0;
-    if (m >= 1) {
-      double acc = g[1];
-      y[1] = acc;
-      int j = 2;
-      for (; j + 3 <= m; j += 4) {
-        const double g0 = g[j], g1 = g[j + 1], g2 = g[j + 2], g3 = g[j + 3];
-        const double i0 = d.ip[j], i1 = d.ip[j + 1], i2 = d.ip[j + 2], i3 = d.ip[j + 3];
-        acc = fma(acc, i0, g0);
-        y[j] = acc;
-        acc = fma(acc, i1, g1);
-        y[j + 1] = acc;
-        acc = fma(acc, i2, g2);
-        y[j + 2] = acc;
-        acc = fma(acc, i3, g3);
-        y[j + 3] = acc;
-      }
-      for (; j <= m; ++j) {
-        acc = fma(acc, d.ip[j], g[j]);
-        y[j] = acc;
-      }
-      double x = y[m];
-      phi[m] = x;
-      j = m - 1;
-      for (; j - 3 >= 1; j -= 4) {
-        const double y0 = y[j], y1 = y[j - 1], y2 = y[j - 2], y3 = y[j - 3];
-        const double i0 = d.ip[j], i1 = d.ip[j - 1], i2 = d.ip[j - 2], i3 = d.ip[j - 3];
-        x = fma(i0, x, y0);
-        phi[j] = x;
-        x = fma(i1, x, y1);
-        phi[j - 1] = x;
-        x = fma(i2, x, y2);
-        phi[j - 2] = x;
-        x = fma(i3, x, y3);
-        phi[j - 3] = x;
-      }
-      for (; j >= 1; --j) {
-        x = fma(d.ip[j], x, y[j]);
-        phi[j] = x;
-      }
-    }
+    g[0] = V;
+    g[nc] = 0.0;
   }
   __syncthreads();
+  const double* phi = g;
   for (int j = tid; j < nn; j += kFinThreads) {
     double e;
     if (j == 0)
@@ -191,6 +170,7 @@ __device__ void field(const Disch<P>& d, const int64_t* cn, double V) {
       e = (phi[nc - 1] - phi[nc]) * d.inv_dz + rho[nc] * d.hdz_eps;
     else
       e = (phi[j - 1] - phi[j + 1]) * d.inv_2dz;
+    d.phi[j] = phi[j];
     d.E[j] = e;
     d.Ep[j] = (P)(d.qm_dt * e);
   }
@@ -199,6 +179,7 @@ __device__ void field(const Disch<P>& d, const int64_t* cn, double V) {
 template <class P>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __restrict__ ds,
                                                           int field_only) {
+  extern __shared__ __align__(16) unsigned char smem[];
   const Disch<P>& d = ds[blockIdx.x];
   State* st = d.st;
   const int tid = threadIdx.x;
@@ -272,7 +253,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   const int cur = st->cbuf;
   const int64_t step = st->step;
   const double V = (step < d.volt_len) ? d.volt[step] : 0.0;
-  field<P>(d, d.cnt[cur], V);
+  field<P>(d, d.cnt[cur], V, reinterpret_cast<double*>(smem));
   // clear the deposit target of the next step
   int64_t* nxt = d.cnt[cur ^ 1];
   for (int j = tid; j < d.nn; j += kFinThreads) nxt[j] = 0;
@@ -344,10 +325,21 @@ __global__ void k_diag(int64_t n, const P* a, const P* b, P* out) {
 }  // namespace
 
 template <class P>
-hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize<P>, dim3(D), dim3(kFinThreads), 0, s, d_dev, field_only);
+hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_max,
+                           hipStream_t s) {
+  const size_t lds = (size_t)3 * (size_t)nn_max * 8u;
+  hipLaunchKernelGGL(k_finalize<P>, dim3(D), dim3(kFinThreads), lds, s, d_dev, field_only);
   return hipGetLastError();
 }
+
+template <class P>
+hipError_t finalize_set_lds(int nn_max) {
+  return hipFuncSetAttribute((const void*)k_finalize<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             3 * nn_max * 8);
+}
+
+template hipError_t finalize_set_lds<float>(int);
+template hipError_t finalize_set_lds<double>(int);
 
 template <class P>
 hipError_t launch_append(const Disch<P>* d_dev, int D, int grid, hipStream_t s) {
@@ -371,8 +363,8 @@ hipError_t launch_set_steps(const Disch<P>* d_dev, int D, int64_t n, hipStream_t
 
 template hipError_t launch_set_steps<float>(const Disch<float>*, int, int64_t, hipStream_t);
 template hipError_t launch_set_steps<double>(const Disch<double>*, int, int64_t, hipStream_t);
-template hipError_t launch_finalize<float>(const Disch<float>*, int, int, hipStream_t);
-template hipError_t launch_finalize<double>(const Disch<double>*, int, int, hipStream_t);
+template hipError_t launch_finalize<float>(const Disch<float>*, int, int, int, hipStream_t);
+template hipError_t launch_finalize<double>(const Disch<double>*, int, int, int, hipStream_t);
 template hipError_t launch_append<float>(const Disch<float>*, int, int, hipStream_t);
 template hipError_t launch_append<double>(const Disch<double>*, int, int, hipStream_t);
 template hipError_t launch_diag<float>(int64_t, const float*, const float*, float*, hipStream_t);

@@ -69,6 +69,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
         const uint32_t v = h[c];
         if (v) d.hist[(size_t)c * nt + t] = v;
       }
+      if (lane == 0) {
+        d.tile_rng[2 * t] = lo;
+        d.tile_rng[2 * t + 1] = hi;
+      }
     }
   }
 }
@@ -192,40 +196,63 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     const int src = st->buf, dst = src ^ 1;
     const int32_t* cell = d.cell[src];
     for (uint32_t t = gw; t < nt; t += nw) {
-      for (int c = lane; c <= nc; c += 64) run[c] = 0u;
+      // per-cell cursor = first destination of this tile's items of that cell
+      const int lo = d.tile_rng[2 * t], hi = d.tile_rng[2 * t + 1];
+      for (int c = lo + lane; c <= hi; c += 64) run[c] = d.hist[(size_t)c * nt + t];
       const uint32_t b = t * (uint32_t)kSortTile;
       const uint32_t e = min(n, b + (uint32_t)kSortTile);
-      for (uint32_t r = b; r < e; r += 64) {
-        const uint32_t i = r + (uint32_t)lane;
-        int key = nc;
-        if (i < e) {
-          const int c = cell[i];
-          key = c >= 0 ? c : nc;
-        }
-        const int k0 = __shfl(key, 0, 64);
-        uint64_t peers;
-        if (__ballot(key == k0) == ~0ull) {
-          peers = ~0ull;
-        } else {
-          peers = ~0ull;
-          for (int bit = 0; bit < nbits; ++bit) {
-            const bool on = (key >> bit) & 1;
-            const uint64_t m = __ballot(on);
-            peers &= on ? m : ~m;
+      constexpr int R = 4;  // rounds of 64 items whose loads are issued together
+      for (uint32_t r = b; r < e; r += 64u * R) {
+        int key[R];
+        P o_[R], x_[R], y_[R], z_[R];
+        uint32_t id_[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const uint32_t i = r + 64u * q + (uint32_t)lane;
+          key[q] = nc;
+          if (i < e) {
+            const int c = cell[i];
+            key[q] = c >= 0 ? c : nc;
+            o_[q] = d.off[src][i];
+            x_[q] = d.vx[src][i];
+            y_[q] = d.vy[src][i];
+            z_[q] = d.vz[src][i];
+            id_[q] = d.id[src][i];
           }
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        const uint32_t cntk = (uint32_t)__popcll(peers);
-        const uint32_t base = run[key];
-        if (rank == 0) run[key] = base + cntk;
-        if (key < nc) {
-          const uint32_t o = d.hist[(size_t)key * nt + t] + base + rank;
-          d.cell[dst][o] = key;
-          d.off[dst][o] = d.off[src][i];
-          d.vx[dst][o] = d.vx[src][i];
-          d.vy[dst][o] = d.vy[src][i];
-          d.vz[dst][o] = d.vz[src][i];
-          d.id[dst][o] = d.id[src][i];
+        uint32_t dest[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int k = key[q];
+          const int k0 = __shfl(k, 0, 64);
+          uint64_t peers = ~0ull;
+          if (__ballot(k == k0) != ~0ull) {
+            for (int bit = 0; bit < nbits; ++bit) {
+              const bool on = (k >> bit) & 1;
+              const uint64_t m = __ballot(on);
+              peers &= on ? m : ~m;
+            }
+          }
+          const uint32_t rank = (uint32_t)__popcll(peers & lt);
+          const uint32_t cntk = (uint32_t)__popcll(peers);
+          dest[q] = 0;
+          if (k < nc) {
+            const uint32_t base = run[k];
+            if (rank == 0) run[k] = base + cntk;
+            dest[q] = base + rank;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          if (key[q] < nc) {
+            const uint32_t o = dest[q];
+            d.cell[dst][o] = key[q];
+            d.off[dst][o] = o_[q];
+            d.vx[dst][o] = x_[q];
+            d.vy[dst][o] = y_[q];
+            d.vz[dst][o] = z_[q];
+            d.id[dst][o] = id_[q];
+          }
         }
       }
     }

@@ -26,7 +26,9 @@ KIND = {"elastic": 0, "excitation": 1, "ionization": 2}
 SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_discharge",
            "hd_step", "hd_moments", "hd_get_particles", "hd_get_push_field", "hd_free",
            "hd_batch_create", "hd_batch_step", "hd_batch_moments", "hd_batch_get_particles",
-           "hd_batch_free", "hd_diag_arith"]
+           "hd_batch_free", "hd_server_create", "hd_server_submit", "hd_server_poll",
+           "hd_server_stats", "hd_server_drain", "hd_server_free", "hd_profile_steps",
+           "hd_diag_arith"]
 
 
 class HdError(RuntimeError):
@@ -75,8 +77,24 @@ class MomentSet(C.Structure):
         ("eedf", _D),
         ("coll", C.c_uint64 * HD_MAX_CHANNELS), ("absorbed", C.c_uint64 * 2),
         ("emitted", C.c_uint64 * 2), ("created", C.c_uint64), ("e_overflow", C.c_uint64),
-        ("see_clamped", C.c_uint64), ("n_acc", C.c_uint64),
+        ("see_clamped", C.c_uint64), ("n_acc", C.c_uint64), ("pushed", C.c_uint64),
     ]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_slots", C.c_int32), ("sort_every", C.c_int32),
+                ("eedf_every", C.c_int32), ("max_cells", C.c_int32), ("max_energy", C.c_int32),
+                ("max_channels", C.c_int32), ("max_eedf_bins", C.c_int32),
+                ("allow_full_fluid", C.c_int32), ("reserved", C.c_int32),
+                ("hbm_budget_bytes", C.c_uint64)]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("queued", C.c_uint64), ("running", C.c_uint64), ("intervals", C.c_uint64),
+                ("particle_steps", C.c_uint64), ("bytes_in_use", C.c_uint64),
+                ("busy_s", C.c_double), ("wall_s", C.c_double), ("error", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -108,6 +126,16 @@ def lib():
             [C.c_int64, C.POINTER(C.c_int64)]
         L.hd_batch_free.argtypes = [vp]
         L.hd_diag_arith.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, C.POINTER(DeviceCtx)]
+        L.hd_profile_steps.argtypes = [vp, C.c_int64, vp]
+        L.hd_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(DeviceCtx),
+                                       C.POINTER(vp)]
+        L.hd_server_submit.argtypes = [vp, C.POINTER(Params), C.c_int64,
+                                       C.POINTER(C.c_uint64)]
+        L.hd_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32),
+                                     C.POINTER(MomentSet), vp]
+        L.hd_server_stats.argtypes = [vp, C.POINTER(ServerCounters)]
+        L.hd_server_drain.argtypes = [vp, C.c_double]
+        L.hd_server_free.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -187,7 +215,7 @@ class _Moments:
                    absorbed=np.array(m.absorbed[:], np.uint64),
                    emitted=np.array(m.emitted[:], np.uint64), created=int(m.created),
                    overflow=int(m.e_overflow), see_clamped=int(m.see_clamped),
-                   n_acc=int(m.n_acc))
+                   n_acc=int(m.n_acc), pushed=int(m.pushed))
         return out
 
 
@@ -227,6 +255,12 @@ class Discharge:
         ep = np.empty(self.nn, self.dt)
         _check(lib().hd_get_push_field(self.h, _ptr(ep)))
         return ep
+
+    def profile_steps(self, n: int) -> dict:
+        """Advance n real steps with per-kernel HIP events; mean ms per kernel."""
+        out = np.zeros(5)
+        _check(lib().hd_profile_steps(self.h, int(n), _ptr(out)))
+        return dict(zip(["electron", "finalize_field", "append", "sort", "step"], out.tolist()))
 
     def close(self):
         if getattr(self, "h", None):
@@ -279,6 +313,58 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             lib().hd_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Served job stream: hd_server_create / submit / poll / stats / drain / free."""
+
+    def __init__(self, precision=0, max_slots=64, sort_every=16, eedf_every=16, max_cells=4096,
+                 max_energy=4096, max_channels=3, max_eedf_bins=128, allow_full_fluid=False,
+                 hbm_budget_bytes=200 * 10 ** 9, stream=None, device=0):
+        cfg = ServerConfig(precision, max_slots, sort_every, eedf_every, max_cells, max_energy,
+                           max_channels, max_eedf_bins, int(allow_full_fluid), 0,
+                           int(hbm_budget_bytes))
+        self._ctx = _ctx(stream, device)
+        h = C.c_void_p()
+        _check(lib().hd_server_create(C.byref(cfg), C.byref(self._ctx), C.byref(h)))
+        self.h = h
+        self.jobs = {}
+
+    def submit(self, params: dict, n_steps: int) -> int:
+        P, keep = make_params(params)
+        jid = C.c_uint64()
+        _check(lib().hd_server_submit(self.h, C.byref(P), int(n_steps), C.byref(jid)))
+        self.jobs[jid.value] = dict(params)
+        return jid.value
+
+    def poll(self, job_id: int):
+        """(state, times[3], moments or None); state 0 queued, 1 running, 2 done, 3 failed."""
+        p = self.jobs[job_id]
+        M = _Moments(p["n_cells"] + 1, p["n_eedf_bins"], len(p["channels"]))
+        st = C.c_int32()
+        t = np.zeros(3)
+        _check(lib().hd_server_poll(self.h, C.c_uint64(job_id), C.byref(st), C.byref(M.m),
+                                    _ptr(t)))
+        return st.value, t, (M.result() if st.value == 2 else None)
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(lib().hd_server_stats(self.h, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in ServerCounters._fields_ if k != "reserved"}
+
+    def drain(self, timeout_s: float = 600.0):
+        _check(lib().hd_server_drain(self.h, float(timeout_s)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hd_server_free(self.h)
             self.h = None
 
     def __del__(self):

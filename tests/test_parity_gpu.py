@@ -43,6 +43,7 @@ def compare(dev_m, dev_p, orc: oracle.Oracle, dev_ep=None):
     assert dev_m["created"] == c["created"]
     assert dev_m["overflow"] == c["overflow"]
     assert dev_m["n_acc"] == c["n_acc"]
+    assert dev_m["pushed"] == c["pushed"]
     assert dev_m["step"] == orc.step_index
     a = orc.accum()
     np.testing.assert_array_equal(dev_m["eedf_counts"], a["eedf"])

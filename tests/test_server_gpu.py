@@ -1,0 +1,90 @@
+"""GPU tests of the served job stream (continuous batching): every job's
+result is bitwise the same alone, in the mix, and in the oracle; admission
+respects the device-memory budget; misfit jobs are rejected."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_02892_amd import hd, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("cnt", "n_i", "phi", "E", "gamma_i", "n_e_avg", "n_i_avg", "eedf_counts")
+
+
+def _job(n_cells, n_macro, seed, volt, model=0):
+    return W.small(precision=0, ion_model=model, n_cells=n_cells, n_macro=n_macro, seed=seed,
+                   v_amp_V=volt, t_e0_eV=8.0)
+
+
+def _same(a, b):
+    for k in KEYS:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    for k in ("coll", "absorbed", "emitted"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    for k in ("created", "overflow", "n_acc", "pushed", "step"):
+        assert a[k] == b[k], k
+
+
+def test_jobs_equal_alone_and_in_the_mix():
+    specs = [(64, 3000, 21, 150.0, 40), (128, 9000, 22, 300.0, 16), (96, 2500, 23, 80.0, 37),
+             (256, 20000, 24, 250.0, 64), (64, 1500, 25, 200.0, 5), (200, 7000, 26, 120.0, 50)]
+    srv = hd.Server(precision=0, max_slots=3, max_cells=256)
+    ids = []
+    for i, (nc, nm, seed, v, steps) in enumerate(specs):
+        ids.append((srv.submit(_job(nc, nm, seed, v), steps), nc, nm, seed, v, steps))
+        if i == 2:
+            time.sleep(0.05)  # later jobs arrive while the first ones run
+    srv.drain(300)
+    st = srv.stats()
+    assert st["completed"] == len(specs) and st["failed"] == 0 and st["error"] == 0
+    for jid, nc, nm, seed, v, steps in ids:
+        state, times, mix = srv.poll(jid)
+        assert state == 2 and times[1] >= times[2] >= 0
+        alone = hd.Discharge(_job(nc, nm, seed, v))
+        alone.step(steps)
+        _same(mix, alone.moments())
+        if nm <= 3000:
+            o = oracle.Oracle(_job(nc, nm, seed, v))
+            o.step(steps)
+            g = o.grid()
+            np.testing.assert_array_equal(mix["cnt"], g["cnt"])
+            np.testing.assert_array_equal(mix["E"], g["E"])
+            assert mix["pushed"] == o.counters()["pushed"]
+    srv.close()
+
+
+def test_admission_respects_budget():
+    p = _job(128, 8000, 31, 150.0)
+    one = hd.required_bytes(p)
+    srv = hd.Server(precision=0, max_slots=8, max_cells=128, hbm_budget_bytes=int(2.5 * one))
+    ids = [srv.submit(_job(128, 8000, 31 + k, 150.0), 48) for k in range(6)]
+    peak = 0
+    t_end = time.time() + 120
+    while time.time() < t_end:
+        s = srv.stats()
+        peak = max(peak, s["running"])
+        assert s["bytes_in_use"] <= 2.5 * one
+        if s["completed"] == len(ids):
+            break
+        time.sleep(0.002)
+    srv.drain(60)
+    assert srv.stats()["completed"] == len(ids)
+    assert peak <= 2
+    srv.close()
+
+
+def test_misfit_jobs_rejected():
+    srv = hd.Server(precision=0, max_slots=2, max_cells=128, hbm_budget_bytes=10 ** 9)
+    with pytest.raises(hd.HdError) as e:
+        srv.submit(_job(256, 1000, 1, 100.0), 10)  # more cells than the slots allow
+    assert e.value.code == -1
+    with pytest.raises(hd.HdError) as e:
+        srv.submit(W.small(precision=1, n_cells=64, n_macro=100), 10)
+    assert e.value.code == -1
+    with pytest.raises(hd.HdError) as e:
+        srv.submit(_job(128, 40_000_000, 1, 100.0), 10)  # alone larger than the budget
+    assert e.value.code == -2
+    srv.close()
