@@ -85,6 +85,100 @@ def cpu_baseline(p, steps: int, desc: str):
                       "single thread" % (desc, steps, n, dt)}
 
 
+def batched(a):
+    """Batched sweep: 64 independent discharges (64M electrons in total) in one
+    launch per phase, against the same discharges as separate handles (one
+    launch per discharge and phase, each on its own stream)."""
+    import torch
+
+    from paper_1508_02892_amd import hd, workloads as W
+    ps = W.c3(n_discharges=a.discharges, total_electrons=a.total_electrons)
+    print("bench: building batch of %d" % len(ps), file=sys.stderr, flush=True)
+    b = hd.Batch(ps, device=0)
+    b.step(a.warmup)
+    torch.cuda.synchronize()
+    p0 = sum(b.moments(i)["pushed"] for i in range(len(ps)))
+    t0 = time.perf_counter()
+    b.step(a.steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    p1 = sum(b.moments(i)["pushed"] for i in range(len(ps)))
+    value = (p1 - p0) / secs
+    b.close()
+    del b
+    sep = None
+    if not a.no_separate:
+        print("bench: separate handles", file=sys.stderr, flush=True)
+        hs = [hd.Discharge(p, device=0) for p in ps]
+        for h in hs:
+            h.step(a.warmup)
+        torch.cuda.synchronize()
+        q0 = sum(h.moments()["pushed"] for h in hs)
+        t0 = time.perf_counter()
+        for h in hs:
+            h.step(a.steps)
+        torch.cuda.synchronize()
+        s2 = time.perf_counter() - t0
+        q1 = sum(h.moments()["pushed"] for h in hs)
+        sep = {"value": (q1 - q0) / s2, "ms_per_step": s2 * 1e3 / a.steps}
+        for h in hs:
+            h.close()
+    line = {
+        "metric": "electron particle-steps/s (push+MCC+deposit), % HBM peak; p50/p99 job latency",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": secs * 1e3 / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched sweep: %d He discharges, gaps U(0.3,2) mm, 256-4096 "
+                               "cells, 100-400 V, %d FP32 electrons in total, DD ions, one "
+                               "launch per phase" % (len(ps), a.total_electrons)},
+        "one_launch_per_discharge": sep,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def served(a):
+    """Served job stream: Poisson arrivals of discharge jobs drawn like the
+    batched sweep, admitted by HBM budget into continuously batched slots;
+    reports aggregate particle-steps/s and p50/p99 submit-to-result latency."""
+    import numpy as np
+
+    from paper_1508_02892_amd import hd, workloads as W
+    jobs = W.c4_jobs(rate_per_s=a.rate, duration_s=a.duration, seed=4, size_scale=a.size_scale,
+                     steps_range=(a.min_steps, a.max_steps))
+    srv = hd.Server(precision=0, max_slots=a.slots, max_cells=4096,
+                    hbm_budget_bytes=int(a.budget_gb * 1e9))
+    print("bench: serving %d jobs" % len(jobs), file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ids = []
+    for j in jobs:
+        wait = t0 + j["arrival_s"] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        ids.append(srv.submit(j["params"], j["steps"]))
+    srv.drain(3600.0)
+    wall = time.perf_counter() - t0
+    lat = np.array([srv.poll(i)[1][1] for i in ids])
+    st = srv.stats()
+    srv.close()
+    line = {
+        "metric": "electron particle-steps/s (push+MCC+deposit), % HBM peak; p50/p99 job latency",
+        "value": st["particle_steps"] / wall, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": int(sum(j["steps"] for j in jobs)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served job stream: Poisson arrivals %.3g jobs/s for %.0f s, "
+                               "sizes log-uniform [2^18, 2^23] x %.3g electrons, %d-%d steps, "
+                               "%d slots, %.0f GB budget"
+                               % (a.rate, a.duration, a.size_scale, a.min_steps, a.max_steps,
+                                  a.slots, a.budget_gb),
+                   "jobs": len(jobs)},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "server": st,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,11 +192,25 @@ def main():
                     help="override the ion model of the workload (diagnostic variants)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration runs)")
+    ap.add_argument("--rate", type=float, default=2.0, help="served stream: jobs/s")
+    ap.add_argument("--duration", type=float, default=20.0, help="served stream: arrival window")
+    ap.add_argument("--size-scale", type=float, default=0.125)
+    ap.add_argument("--min-steps", type=int, default=2000)
+    ap.add_argument("--max-steps", type=int, default=4000)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--discharges", type=int, default=64, help="batched sweep size")
+    ap.add_argument("--total-electrons", type=int, default=1 << 26)
+    ap.add_argument("--no-separate", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
               "design is described in DESIGN.md and not measured" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.workload == "served":
+        return served(a)
+    if a.workload == "batched":
+        return batched(a)
 
     import torch
     from paper_1508_02892_amd import hd

@@ -523,7 +523,30 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
     double dpp = Lr[0] * rr;
     Lc[0] = cpp;
     Lr[0] = dpp;
-    for (int k = 1; k < m; ++k) {
+    // operands of kB rows are loaded ahead of their dependent eliminations
+    constexpr int kB = 8;
+    int k = 1;
+    for (; k + kB - 1 < m; k += kB) {
+      double ak[kB], bk[kB], ck[kB], rk[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        ak[q] = La[k + q];
+        bk[q] = Lb[k + q];
+        ck[q] = Lc[k + q];
+        rk[q] = Lr[k + q];
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        const double den = bk[q] - ak[q] * cpp;
+        const double num = rk[q] - ak[q] * dpp;
+        rr = 1.0 / den;
+        cpp = ck[q] * rr;
+        dpp = num * rr;
+        Lc[k + q] = cpp;
+        Lr[k + q] = dpp;
+      }
+    }
+    for (; k < m; ++k) {
       const double ak = La[k];
       const double den = Lb[k] - ak * cpp;
       const double num = Lr[k] - ak * dpp;
@@ -535,7 +558,21 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
     }
     double x = dpp;
     La[m - 1] = x;
-    for (int k = m - 2; k >= 0; --k) {
+    k = m - 2;
+    for (; k - kB + 1 >= 0; k -= kB) {
+      double ck[kB], rk[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        ck[q] = Lc[k - q];
+        rk[q] = Lr[k - q];
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        x = rk[q] - ck[q] * x;
+        La[k - q] = x;
+      }
+    }
+    for (; k >= 0; --k) {
       x = Lr[k] - Lc[k] * x;
       La[k] = x;
     }

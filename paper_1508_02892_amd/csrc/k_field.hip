@@ -143,15 +143,46 @@ __device__ void field(const Disch<P>& d, const int64_t* cn, double V, double* ld
   }
   __syncthreads();
   if (tid == 0 && m >= 1) {
+    // blocks of kB operands are loaded before their kB dependent steps so
+    // that LDS latency is paid once per block, not once per node
+    constexpr int kB = 16;
     double acc = g[1];
     y[1] = acc;
-    for (int j = 2; j <= m; ++j) {
+    int j = 2;
+    for (; j + kB - 1 <= m; j += kB) {
+      double gi[kB], ii[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        gi[q] = g[j + q];
+        ii[q] = ip[j + q];
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        acc = fma(acc, ii[q], gi[q]);
+        y[j + q] = acc;
+      }
+    }
+    for (; j <= m; ++j) {
       acc = fma(acc, ip[j], g[j]);
       y[j] = acc;
     }
     double x = acc;
     g[m] = x;
-    for (int j = m - 1; j >= 1; --j) {
+    j = m - 1;
+    for (; j - kB + 1 >= 1; j -= kB) {
+      double yi[kB], ii[kB];
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        yi[q] = y[j - q];
+        ii[q] = ip[j - q];
+      }
+#pragma unroll
+      for (int q = 0; q < kB; ++q) {
+        x = fma(ii[q], x, yi[q]);
+        g[j - q] = x;
+      }
+    }
+    for (; j >= 1; --j) {
       x = fma(ip[j], x, y[j]);
       g[j] = x;
     }
