@@ -94,6 +94,8 @@ def lib():
             L.orc_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
                                        C.c_int64, vp]
             L.orc_thomas.argtypes = [C.c_int] + [vp] * 5
+            L.orc_solve_tridiag.argtypes = [C.c_int] + [vp] * 5
+            L.orc_n_partitions.argtypes = [C.c_int]
             L.orc_field.argtypes = [vp, vp, vp, C.c_double, vp, vp]
             L.orc_fluid.argtypes = [vp] * 5
             L.orc_push.argtypes = [C.c_int, C.c_int64, vp, vp, vp, vp, C.c_int, C.c_double,
@@ -275,6 +277,17 @@ def thomas(a, b, c, d):
     x = np.empty(len(b))
     lib().orc_thomas(len(b), _p(a), _p(b), _p(c), _p(d), _p(x))
     return x
+
+
+def solve_tridiag(a, b, c, d):
+    a, b, c, d = (np.ascontiguousarray(v, np.float64) for v in (a, b, c, d))
+    x = np.empty(len(b))
+    lib().orc_solve_tridiag(len(b), _p(a), _p(b), _p(c), _p(d), _p(x))
+    return x
+
+
+def n_partitions(n):
+    return lib().orc_n_partitions(int(n))
 
 
 def push(precision, cell, off, vz, Ep, nc, kdz, steps):

@@ -177,8 +177,6 @@ struct Derived {
   double w;       // superparticle weight per unit electrode area [m^-2], Eq (1.2)
   std::vector<double> dV;     // control length of node j: dz inside, dz/2 at walls
   std::vector<double> scale;  // density per fixed-point count unit at node j
-  // Poisson: inverse pivots of the constant (-1, 2, -1) matrix
-  std::vector<double> ip;
   double kp;        // dz^2 / eps0
   double inv_dz, inv_2dz, hdz_eps;  // 1/dz, 1/(2 dz), dz/(2 eps0)
   double qm_dt;     // (-e/m_e) dt
@@ -223,17 +221,6 @@ bool derive(const orc_params& p, Derived& d) {
   d.dV[d.nc] = 0.5 * d.dz;
   d.scale.resize(d.nn);
   for (int j = 0; j < d.nn; ++j) d.scale[j] = std::ldexp(d.w, -32) / d.dV[j];
-  // Thomas factors of the interior Poisson matrix (unknowns j = 1..nc-1).
-  const int m = d.nc - 1;
-  d.ip.assign(d.nn, 0.0);
-  if (m >= 1) {
-    double den = 2.0;
-    d.ip[1] = 1.0 / den;
-    for (int j = 2; j <= m; ++j) {
-      den = 2.0 - d.ip[j - 1];
-      d.ip[j] = 1.0 / den;
-    }
-  }
   d.kp = d.dz * d.dz / kEps0;
   d.inv_dz = 1.0 / d.dz;
   d.inv_2dz = 0.5 / d.dz;
@@ -291,11 +278,13 @@ bool derive(const orc_params& p, Derived& d) {
 // Field solve (coupling through Poisson's equation, Sec. II.D).
 // rho_j = e (n_i,j - n_e,j);  -phi_{j-1} + 2 phi_j - phi_{j+1} = dz^2 rho_j / eps0
 // for the interior nodes, phi_0 = V(t_n) (powered electrode at z = 0) and
-// phi_N = 0 (grounded electrode at z = L).  Thomas elimination with the
-// constant pivots: y_j = (d_j + y_{j-1}) / b'_j and phi_j = y_j + phi_{j+1}/b'_j,
-// each written as one fused multiply-add.  E from centred differences inside
-// and from Gauss's law over the half cells at the walls.
+// phi_N = 0 (grounded electrode at z = L), solved by the partitioned
+// tridiagonal elimination.  E from centred differences inside and from
+// Gauss's law over the half cells at the walls.
 // ---------------------------------------------------------------------------
+void solve_tridiag(int n, const double* a, const double* b, const double* c, const double* d,
+                   double* x);
+
 void field_solve(const Derived& d, const int64_t* cnt, const double* ni, double V, double* ne_out,
                  double* rho, double* phi, double* E) {
   const int nc = d.nc, nn = d.nn;
@@ -307,16 +296,15 @@ void field_solve(const Derived& d, const int64_t* cnt, const double* ni, double 
   phi[nc] = 0.0;
   const int m = nc - 1;
   if (m >= 1) {
-    std::vector<double> y(nn, 0.0);
+    std::vector<double> a(m, -1.0), b(m, 2.0), c(m, -1.0), rhs(m), x(m);
     for (int j = 1; j <= m; ++j) {
       double dj = d.kp * rho[j];
       if (j == 1) dj = dj + phi[0];
       if (j == m) dj = dj + phi[nc];
-      const double g = dj * d.ip[j];
-      y[j] = (j == 1) ? g : std::fma(y[j - 1], d.ip[j], g);
+      rhs[j - 1] = dj;
     }
-    phi[m] = y[m];
-    for (int j = m - 1; j >= 1; --j) phi[j] = std::fma(d.ip[j], phi[j + 1], y[j]);
+    solve_tridiag(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+    for (int j = 1; j <= m; ++j) phi[j] = x[j - 1];
   }
   for (int j = 1; j < nc; ++j) E[j] = (phi[j - 1] - phi[j + 1]) * d.inv_2dz;
   E[0] = (phi[0] - phi[1]) * d.inv_dz - rho[0] * d.hdz_eps;
@@ -371,6 +359,77 @@ void thomas(int n, const double* a, const double* b, const double* c, const doub
   for (int j = n - 2; j >= 0; --j) x[j] = dp[j] - cp[j] * x[j + 1];
 }
 
+// Number of partitions of the partitioned tridiagonal solve for n unknowns:
+// the largest P <= 64 with 2 P^2 <= n (about sqrt(n/2)); 0 (plain Thomas)
+// below 8 unknowns.
+int n_partitions(int n) {
+  if (n < 8) return 0;
+  int P = 1;
+  while (P + 1 <= 64 && 2 * (P + 1) * (P + 1) <= n) ++P;
+  return P;
+}
+
+// Exact direct solve of a tridiagonal system by partitions (the elimination
+// behind the Thomas method, arranged so that the partitions are independent):
+// rows [s_p, e_p] with s_p = p n / P.  Inside a partition the interior rows
+// are eliminated forward, each expressed as x_i + a''_i x_s + c''_i x_{i+1} =
+// d''_i, then backward, x_i = D_i - A_i x_s - C_i x_e (in terms of the
+// partition's own first and last unknowns).  The first and last rows of every
+// partition then form a tridiagonal system in (x_s0, x_e0, x_s1, x_e1, ...),
+// solved by the Thomas method; the interior follows.
+void solve_tridiag(int n, const double* a, const double* b, const double* c, const double* d,
+                   double* x) {
+  const int P = n_partitions(n);
+  if (P == 0) {
+    thomas(n, a, b, c, d, x);
+    return;
+  }
+  std::vector<double> ap(n), cp(n), dp(n);  // a'', c'', d'' then A, C, D
+  std::vector<double> ra(2 * P), rb(2 * P), rc(2 * P), rd(2 * P), rx(2 * P);
+  for (int p = 0; p < P; ++p) {
+    const int s = (int)((int64_t)p * n / P);
+    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    // forward over the interior rows s+1 .. e-1
+    {
+      const int i = s + 1;
+      const double r = 1.0 / b[i];
+      ap[i] = a[i] * r;
+      cp[i] = c[i] * r;
+      dp[i] = d[i] * r;
+    }
+    for (int i = s + 2; i <= e - 1; ++i) {
+      const double r = 1.0 / (b[i] - a[i] * cp[i - 1]);
+      ap[i] = -(a[i] * ap[i - 1]) * r;
+      cp[i] = c[i] * r;
+      dp[i] = (d[i] - a[i] * dp[i - 1]) * r;
+    }
+    // backward: x_i = D_i - A_i x_s - C_i x_e (row e-1 keeps its values)
+    for (int i = e - 2; i >= s + 1; --i) {
+      dp[i] = dp[i] - cp[i] * dp[i + 1];
+      ap[i] = ap[i] - cp[i] * ap[i + 1];
+      cp[i] = -(cp[i] * cp[i + 1]);
+    }
+    // the partition's first and last rows, with x_{s+1} and x_{e-1} substituted
+    ra[2 * p] = a[s];
+    rb[2 * p] = b[s] - c[s] * ap[s + 1];
+    rc[2 * p] = -(c[s] * cp[s + 1]);
+    rd[2 * p] = d[s] - c[s] * dp[s + 1];
+    ra[2 * p + 1] = -(a[e] * ap[e - 1]);
+    rb[2 * p + 1] = b[e] - a[e] * cp[e - 1];
+    rc[2 * p + 1] = c[e];
+    rd[2 * p + 1] = d[e] - a[e] * dp[e - 1];
+  }
+  thomas(2 * P, ra.data(), rb.data(), rc.data(), rd.data(), rx.data());
+  for (int p = 0; p < P; ++p) {
+    const int s = (int)((int64_t)p * n / P);
+    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    const double xs = rx[2 * p], xe = rx[2 * p + 1];
+    x[s] = xs;
+    x[e] = xe;
+    for (int i = s + 1; i <= e - 1; ++i) x[i] = (dp[i] - ap[i] * xs) - cp[i] * xe;
+  }
+}
+
 // Full fluid (Sec. II.B): Eq (2.3) for Gamma^{n+1/2} with the lagged friction
 // frequency nu^n and semi-implicit advection, solved by the Thomas method;
 // Gamma at the wall nodes from the field-direction switch with mu = e/(M nu)
@@ -400,7 +459,7 @@ void fluid_full(const Derived& d, double nu_const, double* ni, const double* E, 
   }
   rhs[0] = rhs[0] - a[0] * gl;
   rhs[m - 1] = rhs[m - 1] - c[m - 1] * gr;
-  thomas(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+  solve_tridiag(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
   gam[0] = gl;
   gam[nc] = gr;
   for (int j = 1; j <= m; ++j) gam[j] = x[j - 1];
@@ -1058,6 +1117,14 @@ void orc_thomas(int n, const double* a, const double* b, const double* c, const 
                 double* x) {
   thomas(n, a, b, c, d, x);
 }
+
+// The partitioned tridiagonal solve used by the field and the full fluid.
+void orc_solve_tridiag(int n, const double* a, const double* b, const double* c, const double* d,
+                       double* x) {
+  solve_tridiag(n, a, b, c, d, x);
+}
+
+int orc_n_partitions(int n) { return n_partitions(n); }
 
 // Field solve for a discharge's geometry with externally given cnt, n_i, V.
 void orc_field(void* h, const int64_t* cnt, const double* ni, double V, double* phi, double* E) {

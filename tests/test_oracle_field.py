@@ -22,6 +22,49 @@ def test_thomas_matches_dense_solve(n):
     np.testing.assert_allclose(x, np.linalg.solve(A, d), rtol=1e-12, atol=1e-14)
 
 
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9, 17, 50, 127, 255, 1000, 2047, 4095, 9000])
+def test_partitioned_solve_matches_dense_solve(n):
+    rng = np.random.default_rng(1000 + n)
+    a = rng.normal(size=n)
+    c = rng.normal(size=n)
+    b = np.abs(a) + np.abs(c) + 0.5 + rng.random(n)
+    d = rng.normal(size=n)
+    x = oracle.solve_tridiag(a, b, c, d)
+    P = oracle.n_partitions(n)
+    assert P == 0 if n < 8 else (2 * P * P <= n and (P == 64 or 2 * (P + 1) ** 2 > n))
+    if n <= 2047:
+        A = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        ref = np.linalg.solve(A, d)
+    else:
+        from scipy.linalg import solve_banded
+        ab = np.zeros((3, n))
+        ab[0, 1:] = c[:-1]
+        ab[1] = b
+        ab[2, :-1] = a[1:]
+        ref = solve_banded((1, 1), ab, d)
+    np.testing.assert_allclose(x, ref, rtol=1e-11, atol=1e-13)
+    # the residual of the original system is at rounding level
+    r = b * x - d
+    r[1:] += a[1:] * x[:-1]
+    r[:-1] += c[:-1] * x[1:]
+    assert np.abs(r).max() < 1e-12 * (np.abs(d).max() + 1)
+
+
+def test_partitioned_solve_of_the_poisson_matrix():
+    # the (-1, 2, -1) matrix is the worst conditioned case the field uses
+    n = 2047
+    rng = np.random.default_rng(5)
+    d = rng.normal(size=n)
+    x = oracle.solve_tridiag(-np.ones(n), 2 * np.ones(n), -np.ones(n), d)
+    from scipy.linalg import solve_banded
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -1.0
+    ab[1] = 2.0
+    ab[2, :-1] = -1.0
+    np.testing.assert_allclose(x, solve_banded((1, 1), ab, d), rtol=1e-9,
+                               atol=1e-9 * np.abs(x).max())
+
+
 def _disch(nc, gap=1e-3):
     return oracle.Oracle(W.small(n_cells=nc, n_macro=0, gap_m=gap))
 
