@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--discharges", type=int, default=64, help="batched sweep size")
     ap.add_argument("--total-electrons", type=int, default=1 << 26)
     ap.add_argument("--no-separate", action="store_true")
+    ap.add_argument("--electrons", type=int, default=0,
+                    help="override the superparticle count (diagnostic variants)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
@@ -220,6 +222,10 @@ def main():
     if a.ion != "default":
         p["ion_model"] = 0 if a.ion == "dd" else 1
         desc += "; ion model overridden: %s" % ("drift-diffusion" if a.ion == "dd" else "full")
+    if a.electrons:
+        from paper_1508_02892_amd import workloads as W
+        p = W.scaled(p, a.electrons)
+        desc += "; electrons overridden: %d" % a.electrons
     dev = hd.Discharge(p, device=0)
     if a.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

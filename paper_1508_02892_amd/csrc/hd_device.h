@@ -140,6 +140,134 @@ __device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 
+// ---- tridiagonal systems --------------------------------------------------
+
+// Partitions of the exact partitioned tridiagonal solve for n unknowns: the
+// largest P <= 64 with 2 P^2 <= n, 0 (plain Thomas) below 8 unknowns.
+__host__ __device__ inline int tri_partitions(int n) {
+  if (n < 8) return 0;
+  int P = 1;
+  while (P + 1 <= 64 && 2 * (P + 1) * (P + 1) <= n) ++P;
+  return P;
+}
+constexpr int kTriRed = 128;  // max rows of the reduced system (2 x 64 partitions)
+
+// Thomas method for rows [0, n) of a x_{j-1} + b x_j + c x_{j+1} = d, one
+// reciprocal of the pivot per row; cp, dp are work arrays; single thread.
+__device__ inline void thomas_serial(int n, const double* a, const double* b, const double* c,
+                                     const double* d, double* cp, double* dp, double* x) {
+  double rr = 1.0 / b[0];
+  double cpp = c[0] * rr, dpp = d[0] * rr;
+  cp[0] = cpp;
+  dp[0] = dpp;
+  for (int j = 1; j < n; ++j) {
+    const double aj = a[j];
+    const double den = b[j] - aj * cpp;
+    const double num = d[j] - aj * dpp;
+    rr = 1.0 / den;
+    cpp = c[j] * rr;
+    dpp = num * rr;
+    cp[j] = cpp;
+    dp[j] = dpp;
+  }
+  double xv = dpp;
+  x[n - 1] = xv;
+  for (int j = n - 2; j >= 0; --j) {
+    xv = dp[j] - cp[j] * xv;
+    x[j] = xv;
+  }
+}
+
+// Exact partitioned solve of a_i x_{i-1} + b_i x_i + c_i x_{i+1} = d_i,
+// i < n, called by every thread of the workgroup (it synchronises inside).
+// Partition p = rows [p n / P, (p+1) n / P): lane p of wave 0 eliminates its
+// interior rows forward and backward so that each is x_i = D_i - A_i x_s -
+// C_i x_e in terms of the partition's first and last unknowns; the first and
+// last rows of all partitions form a 2P-row tridiagonal system solved by
+// lane 0; then every thread recovers interior unknowns.  a, c, d (LDS) are
+// overwritten with A, C, D; b receives the solution x.  red: 7 * kTriRed
+// doubles of LDS.
+__device__ inline void solve_tridiag_block(int n, double* a, double* b, double* c, double* d,
+                                           double* red) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int P = tri_partitions(n);
+  double* ra = red;
+  double* rb = ra + kTriRed;
+  double* rc = rb + kTriRed;
+  double* rd = rc + kTriRed;
+  double* rx = rd + kTriRed;
+  double* rcp = rx + kTriRed;
+  double* rdp = rcp + kTriRed;
+  __syncthreads();
+  if (P == 0) {
+    if (tid == 0) {
+      for (int i = 0; i < n; ++i) rd[i] = d[i];
+      thomas_serial(n, a, b, c, rd, rcp, rdp, b);
+    }
+    __syncthreads();
+    return;
+  }
+  if (tid < P) {
+    const int p = tid;
+    const int s = (int)((int64_t)p * n / P);
+    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    // forward over the interior rows s+1 .. e-1
+    int i = s + 1;
+    double rr = 1.0 / b[i];
+    double ap = a[i] * rr, cp = c[i] * rr, dp = d[i] * rr;
+    a[i] = ap;
+    c[i] = cp;
+    d[i] = dp;
+    for (i = s + 2; i <= e - 1; ++i) {
+      const double ai = a[i], bi = b[i], ci = c[i], di = d[i];
+      rr = 1.0 / (bi - ai * cp);
+      ap = -(ai * ap) * rr;
+      cp = ci * rr;
+      dp = (di - ai * dp) * rr;
+      a[i] = ap;
+      c[i] = cp;
+      d[i] = dp;
+    }
+    // backward: x_i = D_i - A_i x_s - C_i x_e
+    for (i = e - 2; i >= s + 1; --i) {
+      const double ci = c[i];
+      dp = d[i] - ci * dp;
+      ap = a[i] - ci * ap;
+      cp = -(ci * cp);
+      d[i] = dp;
+      a[i] = ap;
+      c[i] = cp;
+    }
+    // first and last rows with x_{s+1}, x_{e-1} substituted
+    ra[2 * p] = a[s];
+    rb[2 * p] = b[s] - c[s] * a[s + 1];
+    rc[2 * p] = -(c[s] * c[s + 1]);
+    rd[2 * p] = d[s] - c[s] * d[s + 1];
+    ra[2 * p + 1] = -(a[e] * a[e - 1]);
+    rb[2 * p + 1] = b[e] - a[e] * c[e - 1];
+    rc[2 * p + 1] = c[e];
+    rd[2 * p + 1] = d[e] - a[e] * d[e - 1];
+  }
+  __syncthreads();
+  if (tid == 0) thomas_serial(2 * P, ra, rb, rc, rd, rcp, rdp, rx);
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    const int p = (int)(((int64_t)(i + 1) * P - 1) / n);
+    const int s = (int)((int64_t)p * n / P);
+    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    const double xs = rx[2 * p], xe = rx[2 * p + 1];
+    double xi;
+    if (i == s)
+      xi = xs;
+    else if (i == e)
+      xi = xe;
+    else
+      xi = (d[i] - a[i] * xs) - c[i] * xe;
+    b[i] = xi;
+  }
+  __syncthreads();
+}
+
 // Relaxed device-scope load (bypasses a possibly stale per-CU cache line).
 template <class T>
 __device__ __forceinline__ T load_dev(const T* p) {

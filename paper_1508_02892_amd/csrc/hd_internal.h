@@ -8,14 +8,15 @@
 namespace hd {
 
 constexpr int kMaxK = 16;          // collision channels
-constexpr int kThreads = 256;      // electron-kernel workgroup
+constexpr int kThreads = 256;      // append workgroup
 constexpr int kPerThread = 4;      // particles per thread per chunk (vector loads)
-constexpr int kTile = kThreads * kPerThread;  // particles per chunk
-constexpr int kQueue = 256;        // collision-queue entries per round
+constexpr int kElecThreads = 512;  // electron-kernel workgroup (8 waves)
+constexpr int kTile = kElecThreads * kPerThread;  // particles per chunk
+constexpr int kSub = 64 * kPerThread;  // particles of one wave in a chunk (a sub-chunk)
 constexpr int kSeeMax = 4096;      // secondaries per wall per step
 constexpr int kSphereTries = 64;   // bound of the rejection loops
 constexpr int kSortTile = 4096;    // items per sort tile (one wave)
-constexpr int kFinThreads = 256;   // field/finalize workgroup
+constexpr int kFinThreads = 1024;  // field/finalize workgroup
 
 // Mutable per-discharge scalars.  They live in device memory so that a
 // captured sequence of launches can advance without host involvement.
@@ -28,7 +29,7 @@ struct State {
   uint32_t id_base;      // id of this step's first appended particle
   uint32_t n_kids;       // children created this step
   uint32_t n_see[2];     // secondaries emitted this step (left, right)
-  uint32_t n_chunks;     // chunks processed by the last electron launch
+  uint32_t n_chunks;     // sub-chunks processed by the last electron launch
   int32_t buf;           // current particle buffer (0/1)
   int32_t cbuf;          // cnt buffer holding the deposit of the current step
   int32_t error;         // sticky error (HD_E* code)
@@ -52,7 +53,7 @@ struct Disch {
   int32_t nc, nn, ne, K;
   int32_t nbins, sort_every, eedf_every, ion_model;
   uint32_t capacity;        // slots per particle buffer (multiple of kTile)
-  uint32_t cap_chunks;      // capacity / kTile
+  uint32_t cap_sub;         // capacity / kSub
   uint32_t sort_tiles_max;  // capacity / kSortTile (rounded up)
   uint32_t pad0;
   uint64_t seed;
@@ -76,14 +77,14 @@ struct Disch {
   P* vy[2];
   P* vz[2];
   uint32_t* id[2];
-  // children staging: chunk k writes its children at [k*kTile, ...)
+  // children staging: sub-chunk k writes its children at [k*kSub, ...)
   int32_t* kc;
   P* koff;
   P* kvx;
   P* kvy;
   P* kvz;
-  uint32_t* chunk_kids;  // [cap_chunks]
-  uint32_t* chunk_base;  // [cap_chunks]
+  uint32_t* chunk_kids;  // [cap_sub] children per sub-chunk
+  uint32_t* chunk_base;  // [cap_sub] their offset among the step's children
   // secondaries of this step: side s at [s*kSeeMax, ...)
   int32_t* sc;
   P* soff;

@@ -24,12 +24,12 @@ namespace hd {
 
 // kernel-side entry points (k_electron.hip, k_field.hip, k_sort.hip)
 template <class P>
-size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn);
+size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max);
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
-                                int nb1_max, int fluid_nn, hipStream_t s);
+                                int nb1_max, int fluid_nn, int K_max, hipStream_t s);
 template <class P>
-int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int D);
+int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D);
 template <class P>
 hipError_t finalize_set_lds(int nn_max);
 template <class P>
@@ -189,8 +189,8 @@ Offsets<P> layout(const hd_params& p, int64_t volt_len) {
   o.kvx = L.take(C * sizeof(P));
   o.kvy = L.take(C * sizeof(P));
   o.kvz = L.take(C * sizeof(P));
-  o.chunk_kids = L.take(C / kTile * 4);
-  o.chunk_base = L.take(C / kTile * 4);
+  o.chunk_kids = L.take(C / kSub * 4);
+  o.chunk_base = L.take(C / kSub * 4);
   o.sc = L.take(2 * kSeeMax * 4);
   o.soff = L.take(2 * kSeeMax * sizeof(P));
   o.svx = L.take(2 * kSeeMax * sizeof(P));
@@ -437,7 +437,7 @@ struct BatchBase {
   int device = 0;
   int sort_every = 16;
   int grid_e = 0, grid_a = 0, grid_s = 0;
-  int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0, fluid_nn = 0;
+  int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0, fluid_nn = 0, K_max = 1;
   int64_t host_step = 0;  // steps enqueued (all discharges advance together)
   hipGraphExec_t graph = nullptr;
   bool graph_ok = true;   // capture supported
@@ -521,7 +521,7 @@ struct Batch : BatchBase {
     Disch<P>& d = h.dd;
     const size_t C = round_capacity(h.p.capacity);
     d.capacity = (uint32_t)h.p.capacity;  // limit; buffers are rounded up to C
-    d.cap_chunks = (uint32_t)(C / kTile);
+    d.cap_sub = (uint32_t)(C / kSub);
     d.sort_tiles_max = (uint32_t)(C / kSortTile);
     for (int i = 0; i < 2; ++i) {
       d.cell[i] = (int32_t*)(b + o.cell[i]);
@@ -587,6 +587,7 @@ struct Batch : BatchBase {
       }
       h.p.channels = h.ch.empty() ? nullptr : h.ch.data();
       tab_max = std::max(tab_max, h.p.n_energy * std::max(1, h.p.n_channels));
+      K_max = std::max(K_max, h.p.n_channels);
       nn_max = std::max(nn_max, h.p.n_cells + 1);
       nc_max = std::max(nc_max, h.p.n_cells);
       nb1_max = std::max(nb1_max, h.p.n_eedf_bins + 1);
@@ -596,7 +597,7 @@ struct Batch : BatchBase {
     // launch geometry
     hipDeviceProp_t prop;
     HD_TRY(hipGetDeviceProperties(&prop, device));
-    const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn);
+    const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max);
     if (lds > (size_t)prop.sharedMemPerBlock)
       return fail(HD_EINVAL, "electron kernel needs " + std::to_string(lds) +
                                  " B of LDS, device allows " +
@@ -605,7 +606,7 @@ struct Batch : BatchBase {
     if (slds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "sort LDS too large");
     HD_TRY(sort_set_lds<P>(nc_max));
     HD_TRY(finalize_set_lds<P>(nn_max));
-    int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, D);
+    int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     const int cus = prop.multiProcessorCount;
     grid_e = D + cus * occ;
@@ -669,7 +670,7 @@ struct Batch : BatchBase {
   std::vector<double*> extra;
 
   hipError_t enqueue_step(bool with_sort) {
-    hipError_t e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, stream);
+    hipError_t e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
     if (e != hipSuccess) return e;
     e = launch_finalize<P>(d_desc, D, 0, nn_max, stream);
     if (e != hipSuccess) return e;
@@ -841,7 +842,7 @@ struct Batch : BatchBase {
       sorted[(size_t)s] = srt;
       err = hipEventRecord(e[0], stream);
       if (err == hipSuccess)
-        err = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, stream);
+        err = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
       if (err == hipSuccess) err = hipEventRecord(e[1], stream);
       if (err == hipSuccess) err = hipEventRecord(e[2], stream);
       if (err == hipSuccess) err = launch_finalize<P>(d_desc, D, 0, nn_max, stream);
@@ -944,7 +945,7 @@ struct Server : ServerBase {
   std::vector<Job*> slot_job;
   std::vector<int64_t> slot_done;  // steps completed by the job in the slot
   int grid_e = 0, grid_a = 0, grid_s = 0, tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0,
-      fluid_nn = 0;
+      fluid_nn = 0, K_max = 1;
   hipGraphExec_t graph = nullptr;
   std::mutex mu;
   std::condition_variable cv;
@@ -991,17 +992,18 @@ struct Server : ServerBase {
       stream = own_stream;
     }
     tab_max = cfg.max_energy * std::max(1, cfg.max_channels);
+    K_max = std::max(1, cfg.max_channels);
     nn_max = cfg.max_cells + 1;
     nc_max = cfg.max_cells;
     nb1_max = cfg.max_eedf_bins + 1;
     fluid_nn = cfg.allow_full_fluid ? nn_max : 0;
     hipDeviceProp_t prop;
     HD_TRY(hipGetDeviceProperties(&prop, device));
-    const size_t lds = electron_lds_bytes<P>(S, tab_max, nn_max, nb1_max, fluid_nn);
+    const size_t lds = electron_lds_bytes<P>(S, tab_max, nn_max, nb1_max, fluid_nn, K_max);
     if (lds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "slot caps exceed LDS");
     HD_TRY(sort_set_lds<P>(nc_max));
     HD_TRY(finalize_set_lds<P>(nn_max));
-    const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, S);
+    const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, S);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     grid_e = S + prop.multiProcessorCount * occ;
     grid_a = prop.multiProcessorCount;
@@ -1019,7 +1021,7 @@ struct Server : ServerBase {
     HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int s = 0; s < cfg.sort_every && e == hipSuccess; ++s) {
-      e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, stream);
+      e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
       if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, stream);
       if (e == hipSuccess) e = launch_append<P>(d_desc, S, grid_a, stream);
       if (e == hipSuccess && s == cfg.sort_every - 1)

@@ -18,14 +18,20 @@ namespace hd {
 namespace {
 
 constexpr double kECharge = 1.602176634e-19;
+constexpr int kWaves = kElecThreads / 64;      // waves per workgroup
+constexpr int kWQ = 128;                   // per-wave collision queue entries
+constexpr int kTabLds = 1024;              // collision-table rows kept in LDS (0 .. 102.3 eV
+                                           // at 10 points per eV); higher rows via the cache
 
+// A collision waiting to be scattered.  meta: bits 0-7 channel, bit 8 set if
+// a child is created, bits 16-23 the child's index within the sub-chunk.
 template <class P>
 struct QEntry {
   P vx, vy, vz, off;
   uint32_t id;
   int32_t c;
-  int32_t ch;
-  int32_t kid;  // child slot in the chunk's staging area, -1 if none
+  uint32_t slot;
+  uint32_t meta;
 };
 
 struct ElecArgs {
@@ -34,10 +40,11 @@ struct ElecArgs {
   int nn_max;     // max nodes
   int nb1_max;    // max eedf bins + 1
   int fluid_nn;   // max nodes of a full-fluid discharge (its solver lives in LDS), 0 if none
+  int K_max;      // max channels
 };
 
 struct Lds {
-  uint32_t tab, bins, q, eedf, ctr, pre, wsum, total;
+  uint32_t tab, bins, q, eedf, ctr, pre, total;
 };
 
 // LDS counters: [0, kMaxK) collisions per channel, then these.
@@ -46,16 +53,19 @@ enum { kCtrAbsL = kMaxK, kCtrAbsR, kCtrCreated, kCtrOverflow, kCtrPushed, kCtrN 
 template <class P>
 __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
   auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
+  // min(ne, kTabLds) * K of any discharge is at most this
+  const uint32_t tab_lds = (uint32_t)a.tab_max < (uint32_t)(kTabLds * a.K_max)
+                               ? (uint32_t)a.tab_max : (uint32_t)(kTabLds * a.K_max);
   Lds L;
   L.tab = 0;
-  L.bins = al(L.tab + (uint32_t)a.tab_max * (uint32_t)sizeof(P));
+  L.bins = al(L.tab + tab_lds * (uint32_t)sizeof(P));
   L.q = al(L.bins + (uint32_t)a.nn_max * 8u);
-  L.eedf = al(L.q + (uint32_t)kQueue * (uint32_t)sizeof(QEntry<P>));
+  L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
   L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
   L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
-  L.wsum = al(L.pre + (uint32_t)(a.D + 1) * 4u);
-  L.total = al(L.wsum + 16u * 4u);
-  const uint32_t fluid = 4u * (uint32_t)a.fluid_nn * 8u;  // a, b, c/c', r/d' of Eq (2.3)
+  L.total = al(L.pre + (uint32_t)(a.D + 1) * 4u);
+  // a, b, c, r of Eq (2.3) and the reduced system of the partitioned solve
+  const uint32_t fluid = a.fluid_nn ? (4u * (uint32_t)a.fluid_nn + 7u * (uint32_t)kTriRed) * 8u : 0u;
   if (fluid > L.total) L.total = al(fluid);
   return L;
 }
@@ -86,65 +96,104 @@ __device__ __forceinline__ int eedf_bin(P vx, P vy, P vz, const Disch<P>& d) {
   return (x < (P)d.nbins) ? (int)x : d.nbins;
 }
 
-// Scattering of one queued collision (elastic / excitation / ionization).
+__device__ __forceinline__ void lds_add_i64(int64_t* p, uint64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+
+// Everything a workgroup needs while working on one discharge.
 template <class P>
-__device__ void handle(const Disch<P>& d, QEntry<P>& e, uint32_t lc, uint32_t step, bool sample,
-                       int64_t* bins, uint32_t* eedf, uint32_t* ctr) {
-  Stream s(d.seed, kTagElectron, e.id, step);
+struct Seg {
+  const P* tab;       // LDS rows [0, tab_rows)
+  int tab_rows;
+  int64_t* bins;      // LDS deposit grid
+  uint32_t* eedf;     // LDS histogram
+  uint32_t* ctr;      // LDS counters
+  uint32_t step;
+  uint32_t n_main;
+  int buf;
+  bool sample;
+};
+
+// Scattering of one queued collision (elastic / excitation / ionization).
+// The particle's new velocity goes straight to its slot; an ionization's new
+// electron goes to the staging area of its sub-chunk, with its deposit, ion
+// source and EEDF sample.
+template <class P>
+__device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
+  Stream s(d.seed, kTagElectron, e.id, g.step);
   for (int w = 0; w < Uni<P>::kWords; ++w) (void)s.word();  // R used by the null test
+  const int ch = (int)(e.meta & 0xFFu);
   const P vx = e.vx, vy = e.vy, vz = e.vz;
   const P v2 = (vx * vx + vy * vy) + vz * vz;
   const P en = d.KE * v2;
-  const int kind = d.kind[e.ch];
-  P nx, ny, nz;
+  const int kind = d.kind[ch];
+  P nx, ny, nz, ox, oy, oz;
   if (kind == 0) {
     sphere<P>(s, nx, ny, nz);
     const P vm = sqrt(v2);
     const P cosx = ((vx * nx + vy * ny) + vz * nz) / vm;
     const P fac = (P)1 - d.delta * ((P)1 - cosx);
     const P vn = sqrt(v2 * fac);
-    e.vx = vn * nx;
-    e.vy = vn * ny;
-    e.vz = vn * nz;
+    ox = vn * nx;
+    oy = vn * ny;
+    oz = vn * nz;
   } else if (kind == 1) {
     sphere<P>(s, nx, ny, nz);
-    P er = en - d.thr[e.ch];
+    P er = en - d.thr[ch];
     if (er < (P)0) er = (P)0;
     const P vn = sqrt(er * d.invKE);
-    e.vx = vn * nx;
-    e.vy = vn * ny;
-    e.vz = vn * nz;
+    ox = vn * nx;
+    oy = vn * ny;
+    oz = vn * nz;
   } else {
     sphere<P>(s, nx, ny, nz);
     const P us = Uni<P>::get(s);
-    P er = en - d.thr[e.ch];
+    P er = en - d.thr[ch];
     if (er < (P)0) er = (P)0;
     const P es = us * er;
     const P ep = er - es;
     const P vn = sqrt(ep * d.invKE);
-    e.vx = vn * nx;
-    e.vy = vn * ny;
-    e.vz = vn * nz;
+    ox = vn * nx;
+    oy = vn * ny;
+    oz = vn * nz;
     P mx, my, mz;
     sphere<P>(s, mx, my, mz);
     const P vc = sqrt(es * d.invKE);
     const P cvx = vc * mx, cvy = vc * my, cvz = vc * mz;
-    const uint32_t slot = lc * (uint32_t)kTile + (uint32_t)e.kid;
-    d.kc[slot] = e.c;
-    d.koff[slot] = e.off;
-    d.kvx[slot] = cvx;
-    d.kvy[slot] = cvy;
-    d.kvz[slot] = cvz;
+    const uint32_t kslot = e.slot / (uint32_t)kSub * (uint32_t)kSub + (e.meta >> 16);
+    d.kc[kslot] = e.c;
+    d.koff[kslot] = e.off;
+    d.kvx[kslot] = cvx;
+    d.kvy[kslot] = cvy;
+    d.kvz[kslot] = cvz;
     const int64_t W1 = cic_w1<P>(e.off);
     const int64_t W0 = ((int64_t)1 << 32) - W1;
-    atomicAdd(reinterpret_cast<unsigned long long*>(&bins[e.c]), (unsigned long long)W0);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&bins[e.c + 1]), (unsigned long long)W1);
+    lds_add_i64(&g.bins[e.c], (uint64_t)W0);
+    lds_add_i64(&g.bins[e.c + 1], (uint64_t)W1);
     atomic_add_i64(&d.ion_src[e.c], W0);
     atomic_add_i64(&d.ion_src[e.c + 1], W1);
-    if (sample) atomicAdd(&eedf[eedf_bin<P>(cvx, cvy, cvz, d)], 1u);
-    atomicAdd(&ctr[kCtrCreated], 1u);
+    if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(cvx, cvy, cvz, d)], 1u);
+    atomicAdd(&g.ctr[kCtrCreated], 1u);
   }
-  atomicAdd(&ctr[e.ch], 1u);
+  d.vx[g.buf][e.slot] = ox;
+  d.vy[g.buf][e.slot] = oy;
+  d.vz[g.buf][e.slot] = oz;
+  if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(ox, oy, oz, d)], 1u);
+  atomicAdd(&g.ctr[ch], 1u);
+}
+
+// One wave scatters the first n (<= 64) queue entries, then moves the rest
+// (< 64) to the front.  The queue belongs to this wave alone.
+template <class P>
+__device__ __forceinline__ void drain(const Disch<P>& d, const Seg<P>& g, QEntry<P>* q,
+                                      uint32_t& qn, uint32_t n) {
+  const uint32_t lane = (uint32_t)(threadIdx.x & 63);
+  if (lane < n) handle<P>(d, g, q[lane]);
+  const uint32_t rest = qn - n;
+  QEntry<P> t;
+  if (lane < rest) t = q[n + lane];
+  if (lane < rest) q[lane] = t;
+  qn = rest;
 }
 
 // The four consecutive slots a thread owns in a chunk.
@@ -166,11 +215,45 @@ __device__ __forceinline__ void load_slots(const Disch<P>& d, int buf, uint32_t 
   ld4(d.id[buf] + i0, s.id);
 }
 
-// One chunk of kTile consecutive particle slots.
+// Channel of a collision candidate: the first k whose interpolated cumulative
+// probability exceeds R (-1: null collision).
 template <class P>
-__device__ void chunk(const Disch<P>& d, uint32_t lc, uint32_t step, uint32_t n_main, int buf,
-                      bool sample, const P* tab, int64_t* bins, QEntry<P>* q, uint32_t* eedf,
-                      uint32_t* ctr, uint32_t* wsum, Slots<P>& in) {
+__device__ __forceinline__ int select_channel(const Disch<P>& d, const Seg<P>& g, P u0, P vx, P vy,
+                                              P vz, uint32_t& n_ovf) {
+  const int K = d.K;
+  const P v2 = (vx * vx + vy * vy) + vz * vz;
+  const P en = d.KE * v2;
+  const P sx = en * d.inv_dE;
+  int i;
+  P t;
+  if (sx >= (P)(d.ne - 1)) {
+    i = d.ne - 2;
+    t = (P)1;
+    n_ovf += 1;
+  } else {
+    i = (int)sx;
+    t = sx - (P)i;
+  }
+  auto scan = [&](const P* ra) {
+    for (int k = 0; k < K; ++k) {
+      const P pa = ra[k];
+      const P pb = ra[K + k];
+      const P pk = pa + t * (pb - pa);
+      if (u0 < pk) return k;
+    }
+    return -1;
+  };
+  // rows i and i+1 from LDS when both are there, else through the cache
+  if (i + 1 < g.tab_rows) return scan(g.tab + i * K);
+  return scan(d.tab + (size_t)i * K);
+}
+
+// One wave's 256 slots of a chunk: push, removal, null-collision test and
+// channel, deposit at x^{n+1}, write-back; collisions are queued.  No
+// workgroup barrier is involved.
+template <class P>
+__device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, Slots<P>& in,
+                           QEntry<P>* q, uint32_t& qn) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
@@ -181,22 +264,22 @@ __device__ void chunk(const Disch<P>& d, uint32_t lc, uint32_t step, uint32_t n_
   P (&vz)[4] = in.vz;
   uint32_t (&id)[4] = in.id;
   const P* Ep = d.Ep;
-  const int K = d.K;
   int ch[4];
   bool alive[4];
-  uint32_t n_absl = 0, n_absr = 0, n_ovf = 0, n_push = 0;
+  uint32_t n_absl = 0, n_absr = 0, n_ovf = 0;
+  uint32_t n_push = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     ch[j] = -1;
-    alive[j] = (i0 + (uint32_t)j < n_main) && (c[j] >= 0);
-    n_push += (uint32_t)__popcll(__ballot(alive[j]));
+    alive[j] = (i0 + (uint32_t)j < g.n_main) && (c[j] >= 0);
+    n_push += alive[j] ? 1u : 0u;
     if (alive[j]) {
       // leapfrog push, linear gather of E' = (-e/m_e) dt E
       const P e0 = Ep[c[j]];
       const P e1 = Ep[c[j] + 1];
       const P t1 = e1 - e0;
-      const P g = e0 + off[j] * t1;
-      vz[j] = vz[j] + g;
+      const P gg = e0 + off[j] * t1;
+      vz[j] = vz[j] + gg;
       const P s = off[j] + vz[j] * d.kdz;
       const P f = floor(s);
       if (!(f >= (P)(-c[j]))) {
@@ -221,123 +304,38 @@ __device__ void chunk(const Disch<P>& d, uint32_t lc, uint32_t step, uint32_t n_
     if (alive[j]) {
       // null-collision test with one Philox block of stream (tag 0, id, step)
       uint32_t w0, w1, w2, w3;
-      philox4x32_10(id[j], step, 0u, kTagElectron, (uint32_t)d.seed, (uint32_t)(d.seed >> 32), w0,
-                    w1, w2, w3);
+      philox4x32_10(id[j], g.step, 0u, kTagElectron, (uint32_t)d.seed, (uint32_t)(d.seed >> 32),
+                    w0, w1, w2, w3);
       P u0;
       if constexpr (sizeof(P) == 4)
         u0 = (P)u01_f32(w0);
       else
         u0 = (P)u01_f64(w0, w1);
-      if (u0 < d.Pmax) {
-        const P v2 = (vx[j] * vx[j] + vy[j] * vy[j]) + vz[j] * vz[j];
-        const P en = d.KE * v2;
-        const P sx = en * d.inv_dE;
-        int i;
-        P t;
-        if (sx >= (P)(d.ne - 1)) {
-          i = d.ne - 2;
-          t = (P)1;
-          n_ovf += 1;
-        } else {
-          i = (int)sx;
-          t = sx - (P)i;
-        }
-        const P* ra = tab + i * K;
-        for (int k = 0; k < K; ++k) {
-          const P pa = ra[k];
-          const P pb = ra[K + k];
-          const P pk = pa + t * (pb - pa);
-          if (u0 < pk) {
-            ch[j] = k;
-            break;
-          }
-        }
-      }
+      if (u0 < d.Pmax) ch[j] = select_channel<P>(d, g, u0, vx[j], vy[j], vz[j], n_ovf);
     }
   }
-  // event counters (rare): one LDS atomic per thread with events
-  if (n_absl) atomicAdd(&ctr[kCtrAbsL], n_absl);
-  if (n_absr) atomicAdd(&ctr[kCtrAbsR], n_absr);
-  if (n_ovf) atomicAdd(&ctr[kCtrOverflow], n_ovf);
-  if (lane == 0 && n_push) atomicAdd(&ctr[kCtrPushed], n_push);
-
-  // collision queue positions and child slots, in particle order
-  bool col[4], ion[4];
-  const uint64_t lt = lanemask_lt();
-  uint32_t pc = 0, pi = 0, tc = 0, ti = 0, ncol = 0;
+  // event counters: one LDS atomic per wave
+  {
+    uint32_t v[4] = {n_absl, n_absr, n_ovf, n_push};
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    col[j] = ch[j] >= 0;
-    ion[j] = col[j] && d.kind[ch[j]] == 2;
-    ncol += col[j] ? 1u : 0u;
-    const uint64_t mc = __ballot(col[j]);
-    const uint64_t mi = __ballot(ion[j]);
-    pc += (uint32_t)__popcll(mc & lt);
-    pi += (uint32_t)__popcll(mi & lt);
-    tc += (uint32_t)__popcll(mc);
-    ti += (uint32_t)__popcll(mi);
-  }
-  if (lane == 0) wsum[wv] = tc | (ti << 16);
-  __syncthreads();
-  uint32_t TC = 0, TI = 0, qpos = pc, kpos = pi;
+    for (int k = 0; k < 4; ++k) {
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) {
-    const uint32_t v = wsum[w];
-    const uint32_t a = v & 0xFFFFu, b = v >> 16;
-    if (w < wv) {
-      qpos += a;
-      kpos += b;
+      for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
     }
-    TC += a;
-    TI += b;
-  }
-  for (uint32_t r0 = 0; r0 < TC; r0 += (uint32_t)kQueue) {
-    uint32_t qi = qpos, ki = kpos;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (col[j]) {
-        if (qi >= r0 && qi < r0 + (uint32_t)kQueue) {
-          QEntry<P>& e = q[qi - r0];
-          e.vx = vx[j];
-          e.vy = vy[j];
-          e.vz = vz[j];
-          e.off = off[j];
-          e.id = id[j];
-          e.c = c[j];
-          e.ch = ch[j];
-          e.kid = ion[j] ? (int32_t)ki : -1;
-        }
-        qi += 1;
-        ki += ion[j] ? 1u : 0u;
-      }
+    if (lane == 0) {
+      if (v[0]) atomicAdd(&g.ctr[kCtrAbsL], v[0]);
+      if (v[1]) atomicAdd(&g.ctr[kCtrAbsR], v[1]);
+      if (v[2]) atomicAdd(&g.ctr[kCtrOverflow], v[2]);
+      if (v[3]) atomicAdd(&g.ctr[kCtrPushed], v[3]);
     }
-    __syncthreads();
-    const uint32_t nr = min((uint32_t)kQueue, TC - r0);
-    for (uint32_t e = (uint32_t)tid; e < nr; e += (uint32_t)kThreads)
-      handle<P>(d, q[e], lc, step, sample, bins, eedf, ctr);
-    __syncthreads();
-    qi = qpos;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (col[j]) {
-        if (qi >= r0 && qi < r0 + (uint32_t)kQueue) {
-          const QEntry<P>& e = q[qi - r0];
-          vx[j] = e.vx;
-          vy[j] = e.vy;
-          vz[j] = e.vz;
-        }
-        qi += 1;
-      }
-    }
-    __syncthreads();
   }
-  // deposit at x^{n+1} (consecutive equal cells merged in registers), EEDF
+  // deposit at x^{n+1}: runs of equal cells merged per thread, then one wave
+  // sum when the whole wave sits in one cell (sorted particles)
   int rc = -1;
   uint64_t a0 = 0, a1 = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (!alive[j]) continue;
-    if (sample) atomicAdd(&eedf[eedf_bin<P>(vx[j], vy[j], vz[j], d)], 1u);
     const int64_t W1 = cic_w1<P>(off[j]);
     const int64_t W0 = ((int64_t)1 << 32) - W1;
     if (c[j] == rc) {
@@ -345,68 +343,120 @@ __device__ void chunk(const Disch<P>& d, uint32_t lc, uint32_t step, uint32_t n_
       a1 += (uint64_t)W1;
     } else {
       if (rc >= 0) {
-        atomicAdd(reinterpret_cast<unsigned long long*>(&bins[rc]), (unsigned long long)a0);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&bins[rc + 1]), (unsigned long long)a1);
+        lds_add_i64(&g.bins[rc], a0);
+        lds_add_i64(&g.bins[rc + 1], a1);
       }
       rc = c[j];
       a0 = (uint64_t)W0;
       a1 = (uint64_t)W1;
     }
   }
-  if (rc >= 0) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(&bins[rc]), (unsigned long long)a0);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&bins[rc + 1]), (unsigned long long)a1);
+  const uint64_t act = __ballot(rc >= 0);
+  if (act) {
+    const int lead = __ffsll((unsigned long long)act) - 1;
+    const int rl = __shfl(rc, lead, 64);
+    if (__ballot(rc >= 0 && rc != rl) == 0) {
+      uint64_t s0 = rc >= 0 ? a0 : 0, s1 = rc >= 0 ? a1 : 0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+      }
+      if (lane == lead) {
+        lds_add_i64(&g.bins[rl], s0);
+        lds_add_i64(&g.bins[rl + 1], s1);
+      }
+    } else if (rc >= 0) {
+      lds_add_i64(&g.bins[rc], a0);
+      lds_add_i64(&g.bins[rc + 1], a1);
+    }
   }
-  // write back; vx, vy change only in collisions
-  st4(d.cell[buf] + i0, c);
-  st4(d.off[buf] + i0, off);
-  st4(d.vz[buf] + i0, vz);
-  if (ncol) {
-    st4(d.vx[buf] + i0, vx);
-    st4(d.vy[buf] + i0, vy);
+  // write back (vx, vy unchanged; collided particles get theirs when scattered)
+  st4(d.cell[g.buf] + i0, c);
+  st4(d.off[g.buf] + i0, off);
+  st4(d.vz[g.buf] + i0, vz);
+  // EEDF of the survivors that did not collide
+  if (g.sample) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (alive[j] && ch[j] < 0) atomicAdd(&g.eedf[eedf_bin<P>(vx[j], vy[j], vz[j], d)], 1u);
   }
-  if (tid == 0) d.chunk_kids[lc] = TI;
+  // children are numbered in particle order within the sub-chunk
+  const uint64_t lt = lanemask_lt();
+  uint32_t kid = 0, nk = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bool ion = ch[j] >= 0 && d.kind[ch[j]] == 2;
+    const uint64_t m = __ballot(ion);
+    kid += (uint32_t)__popcll(m & lt);
+    nk += (uint32_t)__popcll(m);
+  }
+  if (lane == 0) d.chunk_kids[lc * (uint32_t)kWaves + (uint32_t)wv] = nk;
+  // queue the collisions, one slot index j at a time, and scatter in 64s
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bool col = ch[j] >= 0;
+    const uint64_t m = __ballot(col);
+    if (m == 0) continue;
+    if (col) {
+      const bool ion = d.kind[ch[j]] == 2;
+      QEntry<P>& e = q[qn + (uint32_t)__popcll(m & lt)];
+      e.vx = vx[j];
+      e.vy = vy[j];
+      e.vz = vz[j];
+      e.off = off[j];
+      e.id = id[j];
+      e.c = c[j];
+      e.slot = i0 + (uint32_t)j;
+      e.meta = (uint32_t)ch[j] | (ion ? (0x100u | (kid << 16)) : 0u);
+      kid += ion ? 1u : 0u;
+    }
+    qn += (uint32_t)__popcll(m);
+    if (qn >= 64u) drain<P>(d, g, q, qn, 64u);
+  }
 }
 
 template <class P>
 __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned char* smem,
                         const Lds& L) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wv = tid >> 6;
   P* tab = reinterpret_cast<P*>(smem + L.tab);
-  int64_t* bins = reinterpret_cast<int64_t*>(smem + L.bins);
-  QEntry<P>* q = reinterpret_cast<QEntry<P>*>(smem + L.q);
-  uint32_t* eedf = reinterpret_cast<uint32_t*>(smem + L.eedf);
-  uint32_t* ctr = reinterpret_cast<uint32_t*>(smem + L.ctr);
-  uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + L.wsum);
-  const int tabN = d.ne * d.K;
-  for (int i = tid; i < tabN; i += kThreads) tab[i] = d.tab[i];
-  for (int i = tid; i < d.nn; i += kThreads) bins[i] = 0;
-  for (int i = tid; i <= d.nbins; i += kThreads) eedf[i] = 0;
-  if (tid < kCtrN) ctr[tid] = 0;
+  Seg<P> g;
+  g.tab = tab;
+  g.tab_rows = d.ne < kTabLds ? d.ne : kTabLds;
+  g.bins = reinterpret_cast<int64_t*>(smem + L.bins);
+  g.eedf = reinterpret_cast<uint32_t*>(smem + L.eedf);
+  g.ctr = reinterpret_cast<uint32_t*>(smem + L.ctr);
+  QEntry<P>* q = reinterpret_cast<QEntry<P>*>(smem + L.q) + (size_t)wv * kWQ;
+  const int tabN = g.tab_rows * d.K;
+  for (int i = tid; i < tabN; i += kElecThreads) tab[i] = d.tab[i];
+  for (int i = tid; i < d.nn; i += kElecThreads) g.bins[i] = 0;
+  for (int i = tid; i <= d.nbins; i += kElecThreads) g.eedf[i] = 0;
+  if (tid < kCtrN) g.ctr[tid] = 0;
   State* st = d.st;
-  const uint32_t step = (uint32_t)st->step;
-  const bool sample = ((st->step + 1) % d.eedf_every) == 0;
-  const uint32_t n_main = st->n_main;
-  const int buf = st->buf;
+  g.step = (uint32_t)st->step;
+  g.sample = ((st->step + 1) % d.eedf_every) == 0;
+  g.n_main = st->n_main;
+  g.buf = st->buf;
   int64_t* cnt = d.cnt[st->cbuf ^ 1];
   __syncthreads();
-  // the next chunk's slots are loaded before the current one is processed
-  Slots<P> cur, nxt;
-  load_slots<P>(d, buf, lc0, cur);
+  uint32_t qn = 0;
   for (uint32_t lc = lc0; lc < lc1; ++lc) {
-    if (lc + 1 < lc1) load_slots<P>(d, buf, lc + 1, nxt);
-    chunk<P>(d, lc, step, n_main, buf, sample, tab, bins, q, eedf, ctr, wsum, cur);
-    cur = nxt;
+    Slots<P> cur;
+    load_slots<P>(d, g.buf, lc, cur);
+    wave_chunk<P>(d, g, lc, cur, q, qn);
   }
+  if (qn) drain<P>(d, g, q, qn, qn);
   __syncthreads();
-  for (int i = tid; i < d.nn; i += kThreads) {
-    const int64_t v = bins[i];
+  for (int i = tid; i < d.nn; i += kElecThreads) {
+    const int64_t v = g.bins[i];
     if (v) atomic_add_i64(&cnt[i], v);
   }
-  if (sample)
-    for (int i = tid; i <= d.nbins; i += kThreads)
-      if (eedf[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&d.eedf[i]),
-                             (unsigned long long)eedf[i]);
+  if (g.sample)
+    for (int i = tid; i <= d.nbins; i += kElecThreads)
+      if (g.eedf[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&d.eedf[i]),
+                               (unsigned long long)g.eedf[i]);
+  const uint32_t* ctr = g.ctr;
   if (tid < d.K && ctr[tid]) atomicAdd(reinterpret_cast<unsigned long long*>(&st->coll[tid]),
                                        (unsigned long long)ctr[tid]);
   if (tid == kCtrAbsL && ctr[tid])
@@ -435,175 +485,119 @@ __device__ __forceinline__ double ion_temperature(const Disch<P>& d, double mu, 
 
 // Drift-diffusion, explicit: Eq (2.5) with Eqs (2.7)-(2.8) and central
 // differences, field-switched drift flux at the walls, then Eq (2.4) with
-// half cells at the walls.
+// half cells at the walls.  Gamma goes through LDS; n is updated in place
+// after a barrier (each node then reads only its own old density).
 template <class P>
-__device__ void fluid_dd(const Disch<P>& d) {
+__device__ void fluid_dd(const Disch<P>& d, double* lds) {
   const int tid = threadIdx.x, nc = d.nc, nn = d.nn;
-  double* ni = d.ni;
-  double* gam = d.gam;
-  const double* E = d.E;
-  double* n0 = d.scratch;
+  double* __restrict__ ni = d.ni;
+  const double* __restrict__ E = d.E;
+  double* G = lds;
   const double mu = d.mu;
-  for (int j = tid; j < nn; j += kThreads) n0[j] = ni[j];
-  __syncthreads();
-  for (int j = tid; j < nn; j += kThreads) {
+  for (int j = tid; j < nn; j += kElecThreads) {
     double g;
     if (j == 0) {
-      g = (mu * n0[0]) * dmin0(E[0]);
+      g = (mu * ni[0]) * dmin0(E[0]);
     } else if (j == nc) {
-      g = (mu * n0[nc]) * dmax0(E[nc]);
+      g = (mu * ni[nc]) * dmax0(E[nc]);
     } else {
-      const double T = ion_temperature(d, mu, E[j]);
+      const double nl = ni[j - 1], nj = ni[j], nr = ni[j + 1], ej = E[j];
+      const double T = ion_temperature(d, mu, ej);
       const double Dc = (mu * T) / kECharge;
-      g = (mu * n0[j]) * E[j] - (Dc * (n0[j + 1] - n0[j - 1])) * d.inv_2dz;
+      g = (mu * nj) * ej - (Dc * (nr - nl)) * d.inv_2dz;
     }
-    gam[j] = g;
+    G[j] = g;
   }
   __syncthreads();
-  for (int j = tid; j < nn; j += kThreads) {
+  for (int j = tid; j < nn; j += kElecThreads) {
     double v;
     if (j == 0)
-      v = n0[0] - d.dt_dz * (gam[1] - gam[0]);
+      v = ni[0] - d.dt_dz * (G[1] - G[0]);
     else if (j == nc)
-      v = n0[nc] - d.dt_dz * (gam[nc] - gam[nc - 1]);
+      v = ni[nc] - d.dt_dz * (G[nc] - G[nc - 1]);
     else
-      v = n0[j] - d.dt_2dz * (gam[j + 1] - gam[j - 1]);
+      v = ni[j] - d.dt_2dz * (G[j + 1] - G[j - 1]);
     ni[j] = v;
+    d.gam[j] = G[j];
   }
   if (tid == 0) {
-    d.st->wall[0] = gam[0];
-    d.st->wall[1] = gam[nc];
+    d.st->wall[0] = G[0];
+    d.st->wall[1] = G[nc];
   }
+  __syncthreads();
 }
 
 // Full fluid: Eq (2.3) for Gamma^{n+1/2} with lagged nu and semi-implicit
 // advection (tridiagonal; Thomas method, one reciprocal per row), drift wall
-// fluxes with mu = e/(M nu) (Eq 2.6), then Eq (2.4).
+// fluxes with mu = e/(M nu) (Eq 2.6), then Eq (2.4).  Each row reads the
+// old n, Gamma and E of its neighbours directly; the coefficients live in
+// LDS for the serial elimination.
+template <class P>
+__device__ __forceinline__ double lagged_u(const Disch<P>& d, double n, double g) {
+  return (n > d.nfloor) ? g / n : 0.0;
+}
+
 template <class P>
 __device__ void fluid_full(const Disch<P>& d, double* lds) {
   const int tid = threadIdx.x, nc = d.nc, nn = d.nn, m = nc - 1;
-  double* ni = d.ni;
-  double* gam = d.gam;
-  const double* E = d.E;
-  double* n0 = d.scratch;
-  double* g0 = n0 + nn;
-  double* u = g0 + nn;
-  double* T = u + nn;
+  double* __restrict__ ni = d.ni;
+  double* __restrict__ gam = d.gam;
+  const double* __restrict__ E = d.E;
   const double nu = d.nu, mu = d.mu_full;
-  for (int j = tid; j < nn; j += kThreads) {
-    const double nj = ni[j], gj = gam[j];
-    n0[j] = nj;
-    g0[j] = gj;
-    u[j] = (nj > d.nfloor) ? gj / nj : 0.0;
-    T[j] = ion_temperature(d, mu, E[j]);
-  }
-  __syncthreads();
-  // tridiagonal coefficients in LDS so that the serial elimination reads
-  // its operands at LDS latency; c and r are overwritten by c' and d'
   double* La = lds;
   double* Lb = La + nn;
   double* Lc = Lb + nn;
   double* Lr = Lc + nn;
-  for (int j = 1 + tid; j <= m; j += kThreads) {
+  for (int j = 1 + tid; j <= m; j += kElecThreads) {
+    const double nl = ni[j - 1], nj = ni[j], nr = ni[j + 1];
+    const double gl_ = gam[j - 1], gj = gam[j], gr_ = gam[j + 1];
+    const double el = E[j - 1], ej = E[j], er = E[j + 1];
+    const double ul = lagged_u(d, nl, gl_), ur = lagged_u(d, nr, gr_);
+    const double Tl = ion_temperature(d, mu, el), Tr = ion_temperature(d, mu, er);
     const int k = j - 1;
-    La[k] = -d.dt_2dz * u[j - 1];
+    La[k] = -d.dt_2dz * ul;
     Lb[k] = 1.0 + nu * d.hdt;
-    Lc[k] = d.dt_2dz * u[j + 1];
-    Lr[k] = (g0[j] * (1.0 - nu * d.hdt) + (d.e_M_dt * n0[j]) * E[j]) -
-            d.dt_2dzM * (n0[j + 1] * T[j + 1] - n0[j - 1] * T[j - 1]);
+    Lc[k] = d.dt_2dz * ur;
+    Lr[k] = (gj * (1.0 - nu * d.hdt) + (d.e_M_dt * nj) * ej) - d.dt_2dzM * (nr * Tr - nl * Tl);
   }
+  const double gl = (mu * ni[0]) * dmin0(E[0]);
+  const double gr = (mu * ni[nc]) * dmax0(E[nc]);
   __syncthreads();
-  const double gl = (mu * n0[0]) * dmin0(E[0]);
-  const double gr = (mu * n0[nc]) * dmax0(E[nc]);
   if (tid == 0) {
     Lr[0] = Lr[0] - La[0] * gl;
     Lr[m - 1] = Lr[m - 1] - Lc[m - 1] * gr;
-    double rr = 1.0 / Lb[0];
-    double cpp = Lc[0] * rr;
-    double dpp = Lr[0] * rr;
-    Lc[0] = cpp;
-    Lr[0] = dpp;
-    // operands of kB rows are loaded ahead of their dependent eliminations
-    constexpr int kB = 8;
-    int k = 1;
-    for (; k + kB - 1 < m; k += kB) {
-      double ak[kB], bk[kB], ck[kB], rk[kB];
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        ak[q] = La[k + q];
-        bk[q] = Lb[k + q];
-        ck[q] = Lc[k + q];
-        rk[q] = Lr[k + q];
-      }
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        const double den = bk[q] - ak[q] * cpp;
-        const double num = rk[q] - ak[q] * dpp;
-        rr = 1.0 / den;
-        cpp = ck[q] * rr;
-        dpp = num * rr;
-        Lc[k + q] = cpp;
-        Lr[k + q] = dpp;
-      }
-    }
-    for (; k < m; ++k) {
-      const double ak = La[k];
-      const double den = Lb[k] - ak * cpp;
-      const double num = Lr[k] - ak * dpp;
-      rr = 1.0 / den;
-      cpp = Lc[k] * rr;
-      dpp = num * rr;
-      Lc[k] = cpp;
-      Lr[k] = dpp;
-    }
-    double x = dpp;
-    La[m - 1] = x;
-    k = m - 2;
-    for (; k - kB + 1 >= 0; k -= kB) {
-      double ck[kB], rk[kB];
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        ck[q] = Lc[k - q];
-        rk[q] = Lr[k - q];
-      }
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        x = rk[q] - ck[q] * x;
-        La[k - q] = x;
-      }
-    }
-    for (; k >= 0; --k) {
-      x = Lr[k] - Lc[k] * x;
-      La[k] = x;
-    }
     d.st->wall[0] = gl;
     d.st->wall[1] = gr;
   }
-  __syncthreads();
-  for (int j = tid; j < nn; j += kThreads) gam[j] = (j == 0) ? gl : (j == nc) ? gr : La[j - 1];
-  __syncthreads();
-  for (int j = tid; j < nn; j += kThreads) {
+  solve_tridiag_block(m, La, Lb, Lc, Lr, lds + 4 * nn);  // Gamma^{n+1/2} -> Lb
+  for (int j = tid; j < nn; j += kElecThreads) {
+    // Gamma^{n+1/2} at j-1, j, j+1 (walls: gl, gr) and the continuity update
+    auto G = [&](int i) { return i == 0 ? gl : (i == nc ? gr : Lb[i - 1]); };
     double v;
     if (j == 0)
-      v = n0[0] - d.dt_dz * (gam[1] - gam[0]);
+      v = ni[0] - d.dt_dz * (G(1) - G(0));
     else if (j == nc)
-      v = n0[nc] - d.dt_dz * (gam[nc] - gam[nc - 1]);
+      v = ni[nc] - d.dt_dz * (G(nc) - G(nc - 1));
     else
-      v = n0[j] - d.dt_2dz * (gam[j + 1] - gam[j - 1]);
+      v = ni[j] - d.dt_2dz * (G(j + 1) - G(j - 1));
     ni[j] = v;
+    gam[j] = G(j);
   }
+  __syncthreads();
 }
 
+// Blocks [0, D) advance the ion fluid of discharge blockIdx.x; the others
+// share the particle chunks of all discharges in contiguous segments.
 template <class P>
-__global__ __launch_bounds__(kThreads) void k_electron(const Disch<P>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, const ElecArgs& a,
+                                              unsigned char* smem) {
   const int D = a.D;
   const int tid = threadIdx.x;
   if ((int)blockIdx.x < D) {
     const Disch<P>& d = ds[blockIdx.x];
     if (d.st->steps_left > 0) {
       if (d.ion_model == 0)
-        fluid_dd<P>(d);
+        fluid_dd<P>(d, reinterpret_cast<double*>(smem));
       else
         fluid_full<P>(d, reinterpret_cast<double*>(smem));
     }
@@ -611,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_electron(const Disch<P>* __restric
   }
   const Lds L = lds_layout<P>(a);
   uint32_t* pre = reinterpret_cast<uint32_t*>(smem + L.pre);
-  for (int i = tid; i < D; i += kThreads) {
+  for (int i = tid; i < D; i += kElecThreads) {
     const State* st = ds[i].st;
     pre[i + 1] = (st->steps_left > 0) ? (st->n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile : 0u;
   }
@@ -636,42 +630,66 @@ __global__ __launch_bounds__(kThreads) void k_electron(const Disch<P>* __restric
   }
 }
 
+// FP32: at most 128 VGPRs so that four waves share each SIMD.
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_electron_f32(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float>(ds, a, smem);
+}
+
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64(const Disch<double>* __restrict__ ds,
+                                                               ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double>(ds, a, smem);
+}
+
+template <class P>
+struct ElecKernel;
+template <>
+struct ElecKernel<float> {
+  static constexpr auto fn = k_electron_f32;
+};
+template <>
+struct ElecKernel<double> {
+  static constexpr auto fn = k_electron_f64;
+};
+
 }  // namespace
 
 template <class P>
-size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn) {
-  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn};
+size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max) {
+  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max};
   return lds_layout<P>(a).total;
 }
 
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
-                                int nb1_max, int fluid_nn, hipStream_t s) {
-  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn};
+                                int nb1_max, int fluid_nn, int K_max, hipStream_t s) {
+  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max};
   const size_t lds = lds_layout<P>(a).total;
-  hipLaunchKernelGGL(k_electron<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, a);
+  hipLaunchKernelGGL(ElecKernel<P>::fn, dim3(grid), dim3(kElecThreads), lds, s, d_dev, a);
   return hipGetLastError();
 }
 
 template <class P>
-int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int D) {
+int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D) {
   int nb = 0;
-  const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn);
-  if (hipFuncSetAttribute((const void*)k_electron<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max);
+  if (hipFuncSetAttribute((const void*)ElecKernel<P>::fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_electron<P>, kThreads, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ElecKernel<P>::fn, kElecThreads, lds) != hipSuccess)
     return 0;
   return nb;
 }
 
-template size_t electron_lds_bytes<float>(int, int, int, int, int);
-template size_t electron_lds_bytes<double>(int, int, int, int, int);
+template size_t electron_lds_bytes<float>(int, int, int, int, int, int);
+template size_t electron_lds_bytes<double>(int, int, int, int, int, int);
 template hipError_t launch_electron_impl<float>(const Disch<float>*, int, int, int, int, int, int,
-                                                hipStream_t);
+                                                int, hipStream_t);
 template hipError_t launch_electron_impl<double>(const Disch<double>*, int, int, int, int, int,
-                                                 int, hipStream_t);
-template int electron_occupancy<float>(int, int, int, int, int);
-template int electron_occupancy<double>(int, int, int, int, int);
+                                                 int, int, hipStream_t);
+template int electron_occupancy<float>(int, int, int, int, int, int);
+template int electron_occupancy<double>(int, int, int, int, int, int);
 
 }  // namespace hd

@@ -119,89 +119,42 @@ __device__ __forceinline__ double scale_of(const Disch<P>& d, int j) {
 // the constant inverse pivots, one fused multiply-add per sweep step), E from
 // centred differences inside and Gauss's law over the wall half cells, and
 // E' = (-e/m_e) dt E rounded to the particle precision.
-// The serial sweeps read their operands (g_j = d_j/b'_j, 1/b'_j, y_j) from
-// LDS; lds holds 3 * nn doubles.
+// The interior system (-1, 2, -1) is solved by the partitioned elimination;
+// lds holds 4 * nn + 7 * kTriRed doubles.
 template <class P>
 __device__ void field(const Disch<P>& d, const int64_t* cn, double V, double* lds) {
   const int tid = threadIdx.x, nc = d.nc, nn = d.nn, m = nc - 1;
   double* rho = d.scratch;
-  double* g = lds;         // g_j, then phi_j
-  double* ip = lds + nn;   // 1 / b'_j
-  double* y = ip + nn;     // forward-sweep values
+  double* A = lds;        // rows r = j - 1 of the interior unknowns j = 1 .. m
+  double* B = A + nn;     // receives phi_j at r = j - 1
+  double* Cc = B + nn;
+  double* Dd = Cc + nn;
+  double* red = Dd + nn;
   for (int j = tid; j < nn; j += kFinThreads) {
     const double ne = (double)load_dev(&cn[j]) * scale_of(d, j);
     const double r = kECharge * (d.ni[j] - ne);
     rho[j] = r;
-    const double ipj = d.ip[j];
-    ip[j] = ipj;
     if (j >= 1 && j <= m) {
       double dj = d.kp * r;
       if (j == 1) dj = dj + V;
       if (j == m) dj = dj + 0.0;
-      g[j] = dj * ipj;
+      A[j - 1] = -1.0;
+      B[j - 1] = 2.0;
+      Cc[j - 1] = -1.0;
+      Dd[j - 1] = dj;
     }
   }
-  __syncthreads();
-  if (tid == 0 && m >= 1) {
-    // blocks of kB operands are loaded before their kB dependent steps so
-    // that LDS latency is paid once per block, not once per node
-    constexpr int kB = 16;
-    double acc = g[1];
-    y[1] = acc;
-    int j = 2;
-    for (; j + kB - 1 <= m; j += kB) {
-      double gi[kB], ii[kB];
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        gi[q] = g[j + q];
-        ii[q] = ip[j + q];
-      }
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        acc = fma(acc, ii[q], gi[q]);
-        y[j + q] = acc;
-      }
-    }
-    for (; j <= m; ++j) {
-      acc = fma(acc, ip[j], g[j]);
-      y[j] = acc;
-    }
-    double x = acc;
-    g[m] = x;
-    j = m - 1;
-    for (; j - kB + 1 >= 1; j -= kB) {
-      double yi[kB], ii[kB];
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        yi[q] = y[j - q];
-        ii[q] = ip[j - q];
-      }
-#pragma unroll
-      for (int q = 0; q < kB; ++q) {
-        x = fma(ii[q], x, yi[q]);
-        g[j - q] = x;
-      }
-    }
-    for (; j >= 1; --j) {
-      x = fma(ip[j], x, y[j]);
-      g[j] = x;
-    }
-  }
-  if (tid == 0) {
-    g[0] = V;
-    g[nc] = 0.0;
-  }
-  __syncthreads();
-  const double* phi = g;
+  solve_tridiag_block(m, A, B, Cc, Dd, red);
+  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : B[j - 1]); };
   for (int j = tid; j < nn; j += kFinThreads) {
     double e;
     if (j == 0)
-      e = (phi[0] - phi[1]) * d.inv_dz - rho[0] * d.hdz_eps;
+      e = (phi(0) - phi(1)) * d.inv_dz - rho[0] * d.hdz_eps;
     else if (j == nc)
-      e = (phi[nc - 1] - phi[nc]) * d.inv_dz + rho[nc] * d.hdz_eps;
+      e = (phi(nc - 1) - phi(nc)) * d.inv_dz + rho[nc] * d.hdz_eps;
     else
-      e = (phi[j - 1] - phi[j + 1]) * d.inv_2dz;
-    d.phi[j] = phi[j];
+      e = (phi(j - 1) - phi(j + 1)) * d.inv_2dz;
+    d.phi[j] = phi(j);
     d.E[j] = e;
     d.Ep[j] = (P)(d.qm_dt * e);
   }
@@ -221,18 +174,38 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     const int cb = st->cbuf ^ 1;  // deposit of this step
     int64_t* cn = d.cnt[cb];
     const uint32_t n_main = st->n_main;
-    const uint32_t nch = (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile;
-    // offsets of the staged children, chunk by chunk
-    uint32_t run = 0;
-    for (uint32_t b0 = 0; b0 < nch; b0 += (uint32_t)kFinThreads) {
-      const uint32_t k = b0 + (uint32_t)tid;
-      const uint32_t v = (k < nch) ? d.chunk_kids[k] : 0u;
+    // sub-chunks the electron kernel wrote child counts for (whole chunks)
+    const uint32_t nch = (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile * (uint32_t)(kTile / kSub);
+    // offsets of the staged children: tiles of kFinThreads x 16 sub-chunks,
+    // each thread reading and writing 16 consecutive counts as four 16-byte
+    // vectors (nch is a multiple of 4)
+    uint32_t n_kids = 0;
+    for (uint32_t t0 = 0; t0 < nch; t0 += (uint32_t)kFinThreads * 16u) {
+      const uint32_t k0 = t0 + (uint32_t)tid * 16u;
+      uint4 v[4];
+      uint32_t loc = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v[q] = make_uint4(0u, 0u, 0u, 0u);
+        if (k0 + 4u * (uint32_t)q < nch)
+          v[q] = *reinterpret_cast<const uint4*>(d.chunk_kids + k0 + 4u * (uint32_t)q);
+        loc += (v[q].x + v[q].y) + (v[q].z + v[q].w);
+      }
       uint32_t tot;
-      const uint32_t ex = block_scan(v, sh, &tot);
-      if (k < nch) d.chunk_base[k] = run + ex;
-      run += tot;
+      uint32_t run = n_kids + block_scan(loc, sh, &tot);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint4 b;
+        b.x = run;
+        b.y = b.x + v[q].x;
+        b.z = b.y + v[q].y;
+        b.w = b.z + v[q].z;
+        run = b.w + v[q].w;
+        if (k0 + 4u * (uint32_t)q < nch)
+          *reinterpret_cast<uint4*>(d.chunk_base + k0 + 4u * (uint32_t)q) = b;
+      }
+      n_kids += tot;
     }
-    const uint32_t n_kids = run;
     // emission from the wall fluxes of this step's fluid update
     if (tid < 2) {
       const double g = st->wall[tid];
@@ -290,7 +263,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   for (int j = tid; j < d.nn; j += kFinThreads) nxt[j] = 0;
 }
 
-// Append this step's children (in chunk order, i.e. parent order), then the
+// Append this step's children (in sub-chunk order, i.e. parent order), then the
 // left and right secondaries, with consecutive ids.
 template <class P>
 __global__ __launch_bounds__(kThreads) void k_append(const Disch<P>* __restrict__ ds, int D) {
@@ -306,7 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_append(const Disch<P>* __restrict_
       if (k == 0) continue;
       const uint32_t cb = d.chunk_base[lc];
       for (uint32_t t = (uint32_t)tid; t < k; t += (uint32_t)kThreads) {
-        const uint32_t src = lc * (uint32_t)kTile + t;
+        const uint32_t src = lc * (uint32_t)kSub + t;
         const uint32_t dst = base + cb + t;
         d.cell[buf][dst] = d.kc[src];
         d.off[buf][dst] = d.koff[src];
@@ -358,7 +331,7 @@ __global__ void k_diag(int64_t n, const P* a, const P* b, P* out) {
 template <class P>
 hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_max,
                            hipStream_t s) {
-  const size_t lds = (size_t)3 * (size_t)nn_max * 8u;
+  const size_t lds = ((size_t)4 * (size_t)nn_max + 7u * kTriRed) * 8u;
   hipLaunchKernelGGL(k_finalize<P>, dim3(D), dim3(kFinThreads), lds, s, d_dev, field_only);
   return hipGetLastError();
 }
@@ -366,7 +339,7 @@ hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_
 template <class P>
 hipError_t finalize_set_lds(int nn_max) {
   return hipFuncSetAttribute((const void*)k_finalize<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             3 * nn_max * 8);
+                             (4 * nn_max + 7 * kTriRed) * 8);
 }
 
 template hipError_t finalize_set_lds<float>(int);
