@@ -130,6 +130,56 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// Global-memory pointers: particle arrays are reached through the discharge
+// descriptor, so the compiler cannot infer their address space by itself;
+// typed pointers give plain global loads and stores instead of flat ones.
+template <class T>
+using Gp = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ Gp<T>* gptr(T* p) {
+  return (Gp<T>*)p;
+}
+template <class T>
+__device__ __forceinline__ void gld4(const Gp<T>* p, T (&o)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    typedef __attribute__((ext_vector_type(4))) T v4;
+    const v4 t = *reinterpret_cast<const Gp<v4>*>(p);
+    o[0] = t[0];
+    o[1] = t[1];
+    o[2] = t[2];
+    o[3] = t[3];
+  } else {
+    typedef __attribute__((ext_vector_type(2))) T v2;
+    const v2 a = *reinterpret_cast<const Gp<v2>*>(p);
+    const v2 b = *reinterpret_cast<const Gp<v2>*>(p + 2);
+    o[0] = a[0];
+    o[1] = a[1];
+    o[2] = b[0];
+    o[3] = b[1];
+  }
+}
+template <class T>
+__device__ __forceinline__ void gst4(Gp<T>* p, const T (&o)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    typedef __attribute__((ext_vector_type(4))) T v4;
+    v4 t;
+    t[0] = o[0];
+    t[1] = o[1];
+    t[2] = o[2];
+    t[3] = o[3];
+    *reinterpret_cast<Gp<v4>*>(p) = t;
+  } else {
+    typedef __attribute__((ext_vector_type(2))) T v2;
+    v2 a, b;
+    a[0] = o[0];
+    a[1] = o[1];
+    b[0] = o[2];
+    b[1] = o[3];
+    *reinterpret_cast<Gp<v2>*>(p) = a;
+    *reinterpret_cast<Gp<v2>*>(p + 2) = b;
+  }
+}
+
 // Fixed-point cloud-in-cell weight on node c+1: rint(off * 2^32).
 template <class P>
 __device__ __forceinline__ int64_t cic_w1(P off) {
@@ -153,14 +203,44 @@ __host__ __device__ inline int tri_partitions(int n) {
 constexpr int kTriRed = 128;  // max rows of the reduced system (2 x 64 partitions)
 
 // Thomas method for rows [0, n) of a x_{j-1} + b x_j + c x_{j+1} = d, one
-// reciprocal of the pivot per row; cp, dp are work arrays; single thread.
+// reciprocal of the pivot per row; cp, dp are work arrays.  Rows are read
+// and written in full batches of B (LDS latency off the dependent chain).
+// Every lane that calls it computes the same values (callers run it on a
+// whole wave so that the running values stay in vector registers).
+template <int B>
 __device__ inline void thomas_serial(int n, const double* a, const double* b, const double* c,
                                      const double* d, double* cp, double* dp, double* x) {
   double rr = 1.0 / b[0];
   double cpp = c[0] * rr, dpp = d[0] * rr;
   cp[0] = cpp;
   dp[0] = dpp;
-  for (int j = 1; j < n; ++j) {
+  int j = 1;
+  for (; j + B <= n; j += B) {
+    double av[B], bv[B], cv[B], dv[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      av[u] = a[j + u];
+      bv[u] = b[j + u];
+      cv[u] = c[j + u];
+      dv[u] = d[j + u];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const double den = bv[u] - av[u] * cpp;
+      const double num = dv[u] - av[u] * dpp;
+      rr = 1.0 / den;
+      cpp = cv[u] * rr;
+      dpp = num * rr;
+      cv[u] = cpp;
+      dv[u] = dpp;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      cp[j + u] = cv[u];
+      dp[j + u] = dv[u];
+    }
+  }
+  for (; j < n; ++j) {
     const double aj = a[j];
     const double den = b[j] - aj * cpp;
     const double num = d[j] - aj * dpp;
@@ -172,7 +252,23 @@ __device__ inline void thomas_serial(int n, const double* a, const double* b, co
   }
   double xv = dpp;
   x[n - 1] = xv;
-  for (int j = n - 2; j >= 0; --j) {
+  j = n - 2;
+  for (; j - B >= -1; j -= B) {
+    double cv[B], dv[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      cv[u] = cp[j - u];
+      dv[u] = dp[j - u];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      xv = dv[u] - cv[u] * xv;
+      dv[u] = xv;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) x[j - u] = dv[u];
+  }
+  for (; j >= 0; --j) {
     xv = dp[j] - cp[j] * xv;
     x[j] = xv;
   }
@@ -184,12 +280,15 @@ __device__ inline void thomas_serial(int n, const double* a, const double* b, co
 // interior rows forward and backward so that each is x_i = D_i - A_i x_s -
 // C_i x_e in terms of the partition's first and last unknowns; the first and
 // last rows of all partitions form a 2P-row tridiagonal system solved by
-// lane 0; then every thread recovers interior unknowns.  a, c, d (LDS) are
+// wave 0; then every thread recovers interior unknowns.  a, c, d (LDS) are
 // overwritten with A, C, D; b receives the solution x.  red: 7 * kTriRed
-// doubles of LDS.
+// doubles of LDS.  B: rows per batch of the serial sweeps.
+template <int B = 4>
 __device__ inline void solve_tridiag_block(int n, double* a, double* b, double* c, double* d,
                                            double* red) {
   const int tid = threadIdx.x, nt = blockDim.x;
+  // 0, but not known to be: keeps wave-0 serial values in vector registers
+  const int zo = (int)(threadIdx.x / blockDim.x);
   const int P = tri_partitions(n);
   double* ra = red;
   double* rb = ra + kTriRed;
@@ -200,17 +299,18 @@ __device__ inline void solve_tridiag_block(int n, double* a, double* b, double* 
   double* rdp = rcp + kTriRed;
   __syncthreads();
   if (P == 0) {
-    if (tid == 0) {
-      for (int i = 0; i < n; ++i) rd[i] = d[i];
-      thomas_serial(n, a, b, c, rd, rcp, rdp, b);
+    if (tid < 64) {
+      if (tid == 0)
+        for (int i = 0; i < n; ++i) rd[i] = d[i];
+      thomas_serial<B>(n, a + zo, b + zo, c + zo, rd + zo, rcp + zo, rdp + zo, b + zo);
     }
     __syncthreads();
     return;
   }
   if (tid < P) {
     const int p = tid;
-    const int s = (int)((int64_t)p * n / P);
-    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    const int s = p * n / P;
+    const int e = (p + 1) * n / P - 1;
     // forward over the interior rows s+1 .. e-1
     int i = s + 1;
     double rr = 1.0 / b[i];
@@ -218,7 +318,34 @@ __device__ inline void solve_tridiag_block(int n, double* a, double* b, double* 
     a[i] = ap;
     c[i] = cp;
     d[i] = dp;
-    for (i = s + 2; i <= e - 1; ++i) {
+    for (i = s + 2; i + B <= e; i += B) {
+      double av[B], bv[B], cv[B], dv[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        av[u] = a[i + u];
+        bv[u] = b[i + u];
+        cv[u] = c[i + u];
+        dv[u] = d[i + u];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const double ai = av[u];
+        rr = 1.0 / (bv[u] - ai * cp);
+        ap = -(ai * ap) * rr;
+        cp = cv[u] * rr;
+        dp = (dv[u] - ai * dp) * rr;
+        av[u] = ap;
+        cv[u] = cp;
+        dv[u] = dp;
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        a[i + u] = av[u];
+        c[i + u] = cv[u];
+        d[i + u] = dv[u];
+      }
+    }
+    for (; i <= e - 1; ++i) {
       const double ai = a[i], bi = b[i], ci = c[i], di = d[i];
       rr = 1.0 / (bi - ai * cp);
       ap = -(ai * ap) * rr;
@@ -229,7 +356,32 @@ __device__ inline void solve_tridiag_block(int n, double* a, double* b, double* 
       d[i] = dp;
     }
     // backward: x_i = D_i - A_i x_s - C_i x_e
-    for (i = e - 2; i >= s + 1; --i) {
+    for (i = e - 2; i - B >= s; i -= B) {
+      double av[B], cv[B], dv[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        av[u] = a[i - u];
+        cv[u] = c[i - u];
+        dv[u] = d[i - u];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const double ci = cv[u];
+        dp = dv[u] - ci * dp;
+        ap = av[u] - ci * ap;
+        cp = -(ci * cp);
+        dv[u] = dp;
+        av[u] = ap;
+        cv[u] = cp;
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        d[i - u] = dv[u];
+        a[i - u] = av[u];
+        c[i - u] = cv[u];
+      }
+    }
+    for (; i >= s + 1; --i) {
       const double ci = c[i];
       dp = d[i] - ci * dp;
       ap = a[i] - ci * ap;
@@ -249,12 +401,13 @@ __device__ inline void solve_tridiag_block(int n, double* a, double* b, double* 
     rd[2 * p + 1] = d[e] - a[e] * d[e - 1];
   }
   __syncthreads();
-  if (tid == 0) thomas_serial(2 * P, ra, rb, rc, rd, rcp, rdp, rx);
+  if (tid < 64)
+    thomas_serial<B>(2 * P, ra + zo, rb + zo, rc + zo, rd + zo, rcp + zo, rdp + zo, rx + zo);
   __syncthreads();
   for (int i = tid; i < n; i += nt) {
-    const int p = (int)(((int64_t)(i + 1) * P - 1) / n);
-    const int s = (int)((int64_t)p * n / P);
-    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    const int p = ((i + 1) * P - 1) / n;
+    const int s = p * n / P;
+    const int e = (p + 1) * n / P - 1;
     const double xs = rx[2 * p], xe = rx[2 * p + 1];
     double xi;
     if (i == s)

@@ -14,6 +14,8 @@ constexpr int kElecThreads = 512;  // electron-kernel workgroup (8 waves)
 constexpr int kTile = kElecThreads * kPerThread;  // particles per chunk
 constexpr int kSub = 64 * kPerThread;  // particles of one wave in a chunk (a sub-chunk)
 constexpr int kSeeMax = 4096;      // secondaries per wall per step
+constexpr int kMaxCells = 4096;    // cells per discharge
+constexpr int kMaxNodes = kMaxCells + 1;
 constexpr int kSphereTries = 64;   // bound of the rejection loops
 constexpr int kSortTile = 4096;    // items per sort tile (one wave)
 constexpr int kFinThreads = 1024;  // field/finalize workgroup

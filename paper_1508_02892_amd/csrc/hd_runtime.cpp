@@ -117,7 +117,7 @@ bool validate(const hd_params* p, std::string& why) {
   if (p->precision != HD_FP32 && p->precision != HD_FP64) return (why = "precision"), false;
   if (p->ion_model != HD_ION_DD_CONST_MU && p->ion_model != HD_ION_FULL_CONST_NU)
     return (why = "ion_model"), false;
-  if (p->n_cells < 2 || p->n_cells > 4096) return (why = "n_cells out of [2, 4096]"), false;
+  if (p->n_cells < 2 || p->n_cells > kMaxCells) return (why = "n_cells out of [2, 4096]"), false;
   if (p->n_energy < 2 || p->n_energy > (1 << 20)) return (why = "n_energy"), false;
   if (p->n_channels < 0 || p->n_channels > HD_MAX_CHANNELS) return (why = "n_channels"), false;
   if (p->n_channels > 0 && !p->channels) return (why = "channels missing"), false;
@@ -1372,7 +1372,7 @@ int hd_server_create(const hd_server_config* cfg, const hd_device_ctx* ctx, hd_s
   if (!cfg || !out) return hd::fail(HD_EINVAL, "null argument");
   if ((cfg->precision != HD_FP32 && cfg->precision != HD_FP64) || cfg->max_slots < 1 ||
       cfg->max_slots > 1024 || cfg->sort_every < 1 || cfg->eedf_every < 1 ||
-      cfg->max_cells < 2 || cfg->max_cells > 4096 || cfg->max_energy < 2 ||
+      cfg->max_cells < 2 || cfg->max_cells > hd::kMaxCells || cfg->max_energy < 2 ||
       cfg->max_channels < 0 || cfg->max_channels > HD_MAX_CHANNELS || cfg->max_eedf_bins < 1 ||
       cfg->hbm_budget_bytes == 0)
     return hd::fail(HD_EINVAL, "invalid server configuration");

@@ -26,7 +26,7 @@ constexpr int kTabLds = 1024;              // collision-table rows kept in LDS (
 // A collision waiting to be scattered.  meta: bits 0-7 channel, bit 8 set if
 // a child is created, bits 16-23 the child's index within the sub-chunk.
 template <class P>
-struct QEntry {
+struct alignas(16) QEntry {
   P vx, vy, vz, off;
   uint32_t id;
   int32_t c;
@@ -44,7 +44,7 @@ struct ElecArgs {
 };
 
 struct Lds {
-  uint32_t tab, bins, q, eedf, ctr, pre, total;
+  uint32_t tab, ep, bins, q, eedf, ctr, pre, total;
 };
 
 // LDS counters: [0, kMaxK) collisions per channel, then these.
@@ -58,7 +58,8 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
                                ? (uint32_t)a.tab_max : (uint32_t)(kTabLds * a.K_max);
   Lds L;
   L.tab = 0;
-  L.bins = al(L.tab + tab_lds * (uint32_t)sizeof(P));
+  L.ep = al(L.tab + tab_lds * (uint32_t)sizeof(P));
+  L.bins = al(L.ep + (uint32_t)a.nn_max * (uint32_t)sizeof(P));
   L.q = al(L.bins + (uint32_t)a.nn_max * 8u);
   L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
   L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
@@ -89,30 +90,40 @@ __device__ __forceinline__ void sphere(Stream& s, P& nx, P& ny, P& nz) {
   nz = (P)1;
 }
 
-template <class P>
-__device__ __forceinline__ int eedf_bin(P vx, P vy, P vz, const Disch<P>& d) {
-  const P en = d.KE * ((vx * vx + vy * vy) + vz * vz);
-  const P x = en * d.keedf;
-  return (x < (P)d.nbins) ? (int)x : d.nbins;
-}
-
 __device__ __forceinline__ void lds_add_i64(int64_t* p, uint64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 
-// Everything a workgroup needs while working on one discharge.
+// What a workgroup needs while working on one discharge, read once from the
+// descriptor: LDS arrays, the particle arrays of the current buffer and the
+// constants of the push, the null-collision test and the EEDF.
 template <class P>
 struct Seg {
-  const P* tab;       // LDS rows [0, tab_rows)
-  int tab_rows;
+  const P* tab;       // LDS rows [0, tab_rows) of the cumulative probabilities
+  const P* ep;        // LDS copy of E' = (-e/m_e) dt E at the nodes
   int64_t* bins;      // LDS deposit grid
   uint32_t* eedf;     // LDS histogram
   uint32_t* ctr;      // LDS counters
-  uint32_t step;
-  uint32_t n_main;
-  int buf;
+  const Gp<P>* tab_g; // full table
+  Gp<int32_t>* cell;
+  Gp<P>* off;
+  Gp<P>* vx;
+  Gp<P>* vy;
+  Gp<P>* vz;
+  Gp<uint32_t>* id;
+  P kdz, Pmax, KE, inv_dE, keedf;
+  int tab_rows, nc, ne, K, nbins;
+  uint32_t ion_mask;  // bit k: channel k is an ionization
+  uint32_t seed_lo, seed_hi, step, n_main;
   bool sample;
 };
+
+template <class P>
+__device__ __forceinline__ int eedf_bin(P vx, P vy, P vz, const Seg<P>& g) {
+  const P en = g.KE * ((vx * vx + vy * vy) + vz * vz);
+  const P x = en * g.keedf;
+  return (x < (P)g.nbins) ? (int)x : g.nbins;
+}
 
 // Scattering of one queued collision (elastic / excitation / ionization).
 // The particle's new velocity goes straight to its slot; an ionization's new
@@ -161,24 +172,24 @@ __device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
     const P vc = sqrt(es * d.invKE);
     const P cvx = vc * mx, cvy = vc * my, cvz = vc * mz;
     const uint32_t kslot = e.slot / (uint32_t)kSub * (uint32_t)kSub + (e.meta >> 16);
-    d.kc[kslot] = e.c;
-    d.koff[kslot] = e.off;
-    d.kvx[kslot] = cvx;
-    d.kvy[kslot] = cvy;
-    d.kvz[kslot] = cvz;
+    gptr(d.kc)[kslot] = e.c;
+    gptr(d.koff)[kslot] = e.off;
+    gptr(d.kvx)[kslot] = cvx;
+    gptr(d.kvy)[kslot] = cvy;
+    gptr(d.kvz)[kslot] = cvz;
     const int64_t W1 = cic_w1<P>(e.off);
     const int64_t W0 = ((int64_t)1 << 32) - W1;
     lds_add_i64(&g.bins[e.c], (uint64_t)W0);
     lds_add_i64(&g.bins[e.c + 1], (uint64_t)W1);
     atomic_add_i64(&d.ion_src[e.c], W0);
     atomic_add_i64(&d.ion_src[e.c + 1], W1);
-    if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(cvx, cvy, cvz, d)], 1u);
+    if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(cvx, cvy, cvz, g)], 1u);
     atomicAdd(&g.ctr[kCtrCreated], 1u);
   }
-  d.vx[g.buf][e.slot] = ox;
-  d.vy[g.buf][e.slot] = oy;
-  d.vz[g.buf][e.slot] = oz;
-  if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(ox, oy, oz, d)], 1u);
+  g.vx[e.slot] = ox;
+  g.vy[e.slot] = oy;
+  g.vz[e.slot] = oz;
+  if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(ox, oy, oz, g)], 1u);
   atomicAdd(&g.ctr[ch], 1u);
 }
 
@@ -196,45 +207,26 @@ __device__ __forceinline__ void drain(const Disch<P>& d, const Seg<P>& g, QEntry
   qn = rest;
 }
 
-// The four consecutive slots a thread owns in a chunk.
-template <class P>
-struct Slots {
-  int32_t c[4];
-  P off[4], vx[4], vy[4], vz[4];
-  uint32_t id[4];
-};
-
-template <class P>
-__device__ __forceinline__ void load_slots(const Disch<P>& d, int buf, uint32_t lc, Slots<P>& s) {
-  const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)threadIdx.x * (uint32_t)kPerThread;
-  ld4(d.cell[buf] + i0, s.c);
-  ld4(d.off[buf] + i0, s.off);
-  ld4(d.vx[buf] + i0, s.vx);
-  ld4(d.vy[buf] + i0, s.vy);
-  ld4(d.vz[buf] + i0, s.vz);
-  ld4(d.id[buf] + i0, s.id);
-}
-
 // Channel of a collision candidate: the first k whose interpolated cumulative
 // probability exceeds R (-1: null collision).
 template <class P>
-__device__ __forceinline__ int select_channel(const Disch<P>& d, const Seg<P>& g, P u0, P vx, P vy,
-                                              P vz, uint32_t& n_ovf) {
-  const int K = d.K;
+__device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy, P vz,
+                                              uint32_t& n_ovf) {
+  const int K = g.K;
   const P v2 = (vx * vx + vy * vy) + vz * vz;
-  const P en = d.KE * v2;
-  const P sx = en * d.inv_dE;
+  const P en = g.KE * v2;
+  const P sx = en * g.inv_dE;
   int i;
   P t;
-  if (sx >= (P)(d.ne - 1)) {
-    i = d.ne - 2;
+  if (sx >= (P)(g.ne - 1)) {
+    i = g.ne - 2;
     t = (P)1;
     n_ovf += 1;
   } else {
     i = (int)sx;
     t = sx - (P)i;
   }
-  auto scan = [&](const P* ra) {
+  auto scan = [&](auto ra) {
     for (int k = 0; k < K; ++k) {
       const P pa = ra[k];
       const P pb = ra[K + k];
@@ -245,75 +237,72 @@ __device__ __forceinline__ int select_channel(const Disch<P>& d, const Seg<P>& g
   };
   // rows i and i+1 from LDS when both are there, else through the cache
   if (i + 1 < g.tab_rows) return scan(g.tab + i * K);
-  return scan(d.tab + (size_t)i * K);
+  return scan(g.tab_g + (size_t)i * K);
 }
 
 // One wave's 256 slots of a chunk: push, removal, null-collision test and
 // channel, deposit at x^{n+1}, write-back; collisions are queued.  No
 // workgroup barrier is involved.
 template <class P>
-__device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, Slots<P>& in,
-                           QEntry<P>* q, uint32_t& qn) {
+__device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEntry<P>* q,
+                           uint32_t& qn) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
-  int32_t (&c)[4] = in.c;
-  P (&off)[4] = in.off;
-  P (&vx)[4] = in.vx;
-  P (&vy)[4] = in.vy;
-  P (&vz)[4] = in.vz;
-  uint32_t (&id)[4] = in.id;
-  const P* Ep = d.Ep;
+  int32_t c[4];
+  P off[4], vx[4], vy[4], vz[4];
+  uint32_t id[4];
+  gld4(g.cell + i0, c);
+  gld4(g.off + i0, off);
+  gld4(g.vz + i0, vz);
+  gld4(g.id + i0, id);
+  gld4(g.vx + i0, vx);
+  gld4(g.vy + i0, vy);
   int ch[4];
   bool alive[4];
   uint32_t n_absl = 0, n_absr = 0, n_ovf = 0;
   uint32_t n_push = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
+    // leapfrog push with the linear gather of E', written with selects
+    // (dead slots keep their contents)
+    const bool live = (i0 + (uint32_t)j < g.n_main) && (c[j] >= 0);
+    const int32_t cc = live ? c[j] : 0;
+    const P e0 = g.ep[cc];
+    const P e1 = g.ep[cc + 1];
+    const P t1 = e1 - e0;
+    const P gg = e0 + off[j] * t1;
+    const P vzn = vz[j] + gg;
+    const P s = off[j] + vzn * g.kdz;
+    const P f = floor(s);
+    const bool outl = !(f >= (P)(-cc));
+    const bool outr = !outl && (f >= (P)(g.nc - cc));
+    const bool stay = live && !outl && !outr;
+    const P on0 = s - f;
+    const bool wrap = on0 == (P)1;
+    const int32_t cn = cc + (stay ? (int32_t)f : 0) + (wrap ? 1 : 0);
+    n_push += live ? 1u : 0u;
+    n_absl += (live && outl) ? 1u : 0u;
+    n_absr += (live && outr) ? 1u : 0u;
+    vz[j] = live ? vzn : vz[j];
+    c[j] = stay ? cn : (live ? -1 : c[j]);
+    off[j] = stay ? (wrap ? (P)0 : on0) : off[j];
+    alive[j] = stay;
+    // null-collision test with one Philox block of stream (tag 0, id, step)
+    uint32_t w0, w1, w2, w3;
+    philox4x32_10(id[j], g.step, 0u, kTagElectron, g.seed_lo, g.seed_hi, w0, w1, w2, w3);
+    P u0;
+    if constexpr (sizeof(P) == 4)
+      u0 = (P)u01_f32(w0);
+    else
+      u0 = (P)u01_f64(w0, w1);
     ch[j] = -1;
-    alive[j] = (i0 + (uint32_t)j < g.n_main) && (c[j] >= 0);
-    n_push += alive[j] ? 1u : 0u;
-    if (alive[j]) {
-      // leapfrog push, linear gather of E' = (-e/m_e) dt E
-      const P e0 = Ep[c[j]];
-      const P e1 = Ep[c[j] + 1];
-      const P t1 = e1 - e0;
-      const P gg = e0 + off[j] * t1;
-      vz[j] = vz[j] + gg;
-      const P s = off[j] + vz[j] * d.kdz;
-      const P f = floor(s);
-      if (!(f >= (P)(-c[j]))) {
-        c[j] = -1;
-        alive[j] = false;
-        n_absl += 1;
-      } else if (f >= (P)(d.nc - c[j])) {
-        c[j] = -1;
-        alive[j] = false;
-        n_absr += 1;
-      } else {
-        int32_t cn = c[j] + (int32_t)f;
-        P on = s - f;
-        if (on == (P)1) {
-          cn = cn + 1;
-          on = (P)0;
-        }
-        c[j] = cn;
-        off[j] = on;
-      }
-    }
-    if (alive[j]) {
-      // null-collision test with one Philox block of stream (tag 0, id, step)
-      uint32_t w0, w1, w2, w3;
-      philox4x32_10(id[j], g.step, 0u, kTagElectron, (uint32_t)d.seed, (uint32_t)(d.seed >> 32),
-                    w0, w1, w2, w3);
-      P u0;
-      if constexpr (sizeof(P) == 4)
-        u0 = (P)u01_f32(w0);
-      else
-        u0 = (P)u01_f64(w0, w1);
-      if (u0 < d.Pmax) ch[j] = select_channel<P>(d, g, u0, vx[j], vy[j], vz[j], n_ovf);
-    }
+    if (stay && u0 < g.Pmax) ch[j] = select_channel<P>(g, u0, vx[j], vy[j], vz[j], n_ovf);
   }
+  // write back (vx, vy unchanged; collided particles get theirs when scattered)
+  gst4(g.cell + i0, c);
+  gst4(g.off + i0, off);
+  gst4(g.vz + i0, vz);
   // event counters: one LDS atomic per wave
   {
     uint32_t v[4] = {n_absl, n_absr, n_ovf, n_push};
@@ -371,27 +360,23 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, Slot
       lds_add_i64(&g.bins[rc + 1], a1);
     }
   }
-  // write back (vx, vy unchanged; collided particles get theirs when scattered)
-  st4(d.cell[g.buf] + i0, c);
-  st4(d.off[g.buf] + i0, off);
-  st4(d.vz[g.buf] + i0, vz);
   // EEDF of the survivors that did not collide
   if (g.sample) {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (alive[j] && ch[j] < 0) atomicAdd(&g.eedf[eedf_bin<P>(vx[j], vy[j], vz[j], d)], 1u);
+      if (alive[j] && ch[j] < 0) atomicAdd(&g.eedf[eedf_bin<P>(vx[j], vy[j], vz[j], g)], 1u);
   }
   // children are numbered in particle order within the sub-chunk
   const uint64_t lt = lanemask_lt();
   uint32_t kid = 0, nk = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const bool ion = ch[j] >= 0 && d.kind[ch[j]] == 2;
+    const bool ion = ch[j] >= 0 && ((g.ion_mask >> ch[j]) & 1u);
     const uint64_t m = __ballot(ion);
     kid += (uint32_t)__popcll(m & lt);
     nk += (uint32_t)__popcll(m);
   }
-  if (lane == 0) d.chunk_kids[lc * (uint32_t)kWaves + (uint32_t)wv] = nk;
+  if (lane == 0) gptr(d.chunk_kids)[lc * (uint32_t)kWaves + (uint32_t)wv] = nk;
   // queue the collisions, one slot index j at a time, and scatter in 64s
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -399,7 +384,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, Slot
     const uint64_t m = __ballot(col);
     if (m == 0) continue;
     if (col) {
-      const bool ion = d.kind[ch[j]] == 2;
+      const bool ion = (g.ion_mask >> ch[j]) & 1u;
       QEntry<P>& e = q[qn + (uint32_t)__popcll(m & lt)];
       e.vx = vx[j];
       e.vy = vy[j];
@@ -421,31 +406,53 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
                         const Lds& L) {
   const int tid = threadIdx.x, wv = tid >> 6;
   P* tab = reinterpret_cast<P*>(smem + L.tab);
+  P* ep = reinterpret_cast<P*>(smem + L.ep);
+  State* st = d.st;
   Seg<P> g;
   g.tab = tab;
-  g.tab_rows = d.ne < kTabLds ? d.ne : kTabLds;
+  g.ep = ep;
   g.bins = reinterpret_cast<int64_t*>(smem + L.bins);
   g.eedf = reinterpret_cast<uint32_t*>(smem + L.eedf);
   g.ctr = reinterpret_cast<uint32_t*>(smem + L.ctr);
+  g.tab_g = gptr(d.tab);
+  const int buf = st->buf;
+  g.cell = gptr(d.cell[buf]);
+  g.off = gptr(d.off[buf]);
+  g.vx = gptr(d.vx[buf]);
+  g.vy = gptr(d.vy[buf]);
+  g.vz = gptr(d.vz[buf]);
+  g.id = gptr(d.id[buf]);
+  g.kdz = d.kdz;
+  g.Pmax = d.Pmax;
+  g.KE = d.KE;
+  g.inv_dE = d.inv_dE;
+  g.keedf = d.keedf;
+  g.tab_rows = d.ne < kTabLds ? d.ne : kTabLds;
+  g.nc = d.nc;
+  g.ne = d.ne;
+  g.K = d.K;
+  g.nbins = d.nbins;
+  uint32_t im = 0;
+  for (int k = 0; k < d.K; ++k) im |= (d.kind[k] == 2 ? 1u : 0u) << k;
+  g.ion_mask = im;
+  g.seed_lo = (uint32_t)d.seed;
+  g.seed_hi = (uint32_t)(d.seed >> 32);
+  g.step = (uint32_t)st->step;
+  g.n_main = st->n_main;
+  g.sample = ((st->step + 1) % d.eedf_every) == 0;
   QEntry<P>* q = reinterpret_cast<QEntry<P>*>(smem + L.q) + (size_t)wv * kWQ;
   const int tabN = g.tab_rows * d.K;
   for (int i = tid; i < tabN; i += kElecThreads) tab[i] = d.tab[i];
-  for (int i = tid; i < d.nn; i += kElecThreads) g.bins[i] = 0;
+  for (int i = tid; i < d.nn; i += kElecThreads) {
+    g.bins[i] = 0;
+    ep[i] = d.Ep[i];
+  }
   for (int i = tid; i <= d.nbins; i += kElecThreads) g.eedf[i] = 0;
   if (tid < kCtrN) g.ctr[tid] = 0;
-  State* st = d.st;
-  g.step = (uint32_t)st->step;
-  g.sample = ((st->step + 1) % d.eedf_every) == 0;
-  g.n_main = st->n_main;
-  g.buf = st->buf;
   int64_t* cnt = d.cnt[st->cbuf ^ 1];
   __syncthreads();
   uint32_t qn = 0;
-  for (uint32_t lc = lc0; lc < lc1; ++lc) {
-    Slots<P> cur;
-    load_slots<P>(d, g.buf, lc, cur);
-    wave_chunk<P>(d, g, lc, cur, q, qn);
-  }
+  for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P>(d, g, lc, q, qn);
   if (qn) drain<P>(d, g, q, qn, qn);
   __syncthreads();
   for (int i = tid; i < d.nn; i += kElecThreads) {
@@ -569,7 +576,7 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
     d.st->wall[0] = gl;
     d.st->wall[1] = gr;
   }
-  solve_tridiag_block(m, La, Lb, Lc, Lr, lds + 4 * nn);  // Gamma^{n+1/2} -> Lb
+  solve_tridiag_block<2>(m, La, Lb, Lc, Lr, lds + 4 * nn);  // Gamma^{n+1/2} -> Lb
   for (int j = tid; j < nn; j += kElecThreads) {
     // Gamma^{n+1/2} at j-1, j, j+1 (walls: gl, gr) and the continuity update
     auto G = [&](int i) { return i == 0 ? gl : (i == nc ? gr : Lb[i - 1]); };

@@ -42,7 +42,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 // cosine law, uniform azimuth, partial first flight.  Written to the
 // emission buffer and deposited.
 template <class P>
-__device__ void emit(const Disch<P>& d, int side, double F, uint32_t step, int64_t* cn,
+__device__ void emit(const Disch<P>& d, int side, double F, uint32_t step, int64_t* cn_lds,
                      uint32_t* n_out, uint64_t* emitted, uint64_t* absorbed, uint64_t* clamped) {
   Stream s(d.seed, kTagEmission, (uint32_t)side, step);
   const double X = ((d.gamma_see * F) * d.dt) / d.w;
@@ -103,8 +103,8 @@ __device__ void emit(const Disch<P>& d, int side, double F, uint32_t step, int64
     d.svz[idx] = (P)(side == 0 ? vz : -vz);
     const int64_t W1 = cic_w1<P>(off);
     const int64_t W0 = ((int64_t)1 << 32) - W1;
-    atomic_add_i64(&cn[c], W0);
-    atomic_add_i64(&cn[c + 1], W1);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&cn_lds[c]), (unsigned long long)W0);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&cn_lds[c + 1]), (unsigned long long)W1);
     m += 1;
   }
   *n_out = m;
@@ -115,117 +115,417 @@ __device__ __forceinline__ double scale_of(const Disch<P>& d, int j) {
   return (j == 0 || j == d.nc) ? d.scale_wall : d.scale_in;
 }
 
-// Poisson's equation with phi_0 = V(t), phi_N = 0 (Thomas elimination with
-// the constant inverse pivots, one fused multiply-add per sweep step), E from
-// centred differences inside and Gauss's law over the wall half cells, and
-// E' = (-e/m_e) dt E rounded to the particle precision.
-// The interior system (-1, 2, -1) is solved by the partitioned elimination;
-// lds holds 4 * nn + 7 * kTriRed doubles.
-template <class P>
-__device__ void field(const Disch<P>& d, const int64_t* cn, double V, double* lds) {
-  const int tid = threadIdx.x, nc = d.nc, nn = d.nn, m = nc - 1;
-  double* rho = d.scratch;
-  double* A = lds;        // rows r = j - 1 of the interior unknowns j = 1 .. m
-  double* B = A + nn;     // receives phi_j at r = j - 1
-  double* Cc = B + nn;
-  double* Dd = Cc + nn;
-  double* red = Dd + nn;
-  for (int j = tid; j < nn; j += kFinThreads) {
-    const double ne = (double)load_dev(&cn[j]) * scale_of(d, j);
-    const double r = kECharge * (d.ni[j] - ne);
-    rho[j] = r;
-    if (j >= 1 && j <= m) {
-      double dj = d.kp * r;
-      if (j == 1) dj = dj + V;
-      if (j == m) dj = dj + 0.0;
-      A[j - 1] = -1.0;
-      B[j - 1] = 2.0;
-      Cc[j - 1] = -1.0;
-      Dd[j - 1] = dj;
+// ---- Poisson solve with precomputed elimination factors --------------------
+// The interior rows of Poisson's equation are the constant (-1, 2, -1), so in
+// the partitioned elimination every pivot reciprocal and every eliminated
+// coefficient depends only on a row's position inside its partition and on
+// the partition's length (n / P rounded down or up).  They are computed once,
+// by the same operations in the same order as the general elimination, and
+// each step runs only the right-hand-side recurrences, which gives the same
+// result bit for bit without a division on the serial path.
+constexpr double kPa = -1.0, kPb = 2.0, kPc = -1.0;
+constexpr int kFacMax = 1280;  // doubles; at most 18 P + 42 for P >= 1, 2 n for n < 8
+
+// Offsets (in doubles) of the factor tables for n unknowns.
+struct PoisFac {
+  int n, P, L0, Lmax, size;
+  int fr, fc, xa, xc, ra, rr, rc;
+};
+
+__device__ inline PoisFac pois_fac(int n) {
+  PoisFac f;
+  f.n = n;
+  f.P = tri_partitions(n);
+  if (f.P == 0) {  // plain Thomas: reciprocal pivots and eliminated c per row
+    f.L0 = f.Lmax = 0;
+    f.fr = 0;
+    f.fc = n;
+    f.xa = f.xc = f.ra = f.rr = f.rc = 2 * n;
+    f.size = 2 * n;
+    return f;
+  }
+  f.L0 = n / f.P;
+  f.Lmax = f.L0 + 1;
+  f.fr = 0;                   // forward reciprocal pivot at local row k
+  f.fc = f.Lmax;              // forward eliminated c at k
+  f.xa = 2 * f.Lmax;          // final A at k, lengths L0 and L0 + 1
+  f.xc = 4 * f.Lmax;          // final C at k, lengths L0 and L0 + 1
+  f.ra = 6 * f.Lmax;          // reduced system: sub-diagonal,
+  f.rr = f.ra + 2 * f.P;      //   reciprocal pivots,
+  f.rc = f.rr + 2 * f.P;      //   eliminated super-diagonal
+  f.size = f.rc + 2 * f.P;
+  return f;
+}
+
+// One thread: the factors of the (-1, 2, -1) system into t.
+__device__ void pois_factor(const PoisFac& f, double* t) {
+  const double a = kPa, b = kPb, c = kPc;
+  if (f.P == 0) {
+    double rr = 1.0 / b;
+    double cp = c * rr;
+    t[f.fr] = rr;
+    t[f.fc] = cp;
+    for (int j = 1; j < f.n; ++j) {
+      const double den = b - a * cp;
+      rr = 1.0 / den;
+      cp = c * rr;
+      t[f.fr + j] = rr;
+      t[f.fc + j] = cp;
+    }
+    return;
+  }
+  const int Lm = f.Lmax;
+  // forward elimination of the interior rows k = 1 .. Lmax - 2 (identical
+  // in every partition); forward A and C go to both length classes
+  double r = 1.0 / b, ap = a * r, cp = c * r;
+  for (int k = 1; k <= Lm - 2; ++k) {
+    if (k > 1) {
+      r = 1.0 / (b - a * cp);
+      ap = -(a * ap) * r;
+      cp = c * r;
+    }
+    t[f.fr + k] = r;
+    t[f.fc + k] = cp;
+    t[f.xa + k] = ap;
+    t[f.xa + Lm + k] = ap;
+    t[f.xc + k] = cp;
+    t[f.xc + Lm + k] = cp;
+  }
+  // backward elimination for partitions of length L0 and L0 + 1
+  for (int cls = 0; cls < 2; ++cls) {
+    const int L = f.L0 + cls;
+    double* xa = t + f.xa + cls * Lm;
+    double* xc = t + f.xc + cls * Lm;
+    double bap = xa[L - 2], bcp = xc[L - 2];
+    for (int k = L - 3; k >= 1; --k) {
+      const double ci = t[f.fc + k];
+      bap = xa[k] - ci * bap;
+      bcp = -(ci * bcp);
+      xa[k] = bap;
+      xc[k] = bcp;
     }
   }
-  solve_tridiag_block(m, A, B, Cc, Dd, red);
-  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : B[j - 1]); };
-  for (int j = tid; j < nn; j += kFinThreads) {
-    double e;
-    if (j == 0)
-      e = (phi(0) - phi(1)) * d.inv_dz - rho[0] * d.hdz_eps;
-    else if (j == nc)
-      e = (phi(nc - 1) - phi(nc)) * d.inv_dz + rho[nc] * d.hdz_eps;
-    else
-      e = (phi(j - 1) - phi(j + 1)) * d.inv_2dz;
-    d.phi[j] = phi(j);
-    d.E[j] = e;
-    d.Ep[j] = (P)(d.qm_dt * e);
+  // the reduced system of first and last rows, and its Thomas factors
+  double rcp = 0.0;
+  for (int j = 0; j < 2 * f.P; ++j) {
+    const int p = j >> 1;
+    const int s = p * f.n / f.P;
+    const int e = (p + 1) * f.n / f.P - 1;
+    const int L = e - s + 1;
+    const double* xa = t + f.xa + (L - f.L0) * Lm;
+    const double* xc = t + f.xc + (L - f.L0) * Lm;
+    double ra, rb, rc;
+    if ((j & 1) == 0) {
+      ra = a;
+      rb = b - c * xa[1];
+      rc = -(c * xc[1]);
+    } else {
+      ra = -(a * xa[L - 2]);
+      rb = b - a * xc[L - 2];
+      rc = c;
+    }
+    double rr;
+    if (j == 0) {
+      rr = 1.0 / rb;
+    } else {
+      const double den = rb - ra * rcp;
+      rr = 1.0 / den;
+    }
+    rcp = rc * rr;
+    t[f.ra + j] = ra;
+    t[f.rr + j] = rr;
+    t[f.rc + j] = rcp;
   }
 }
 
+// Solve of the (-1, 2, -1) system for the right-hand side d (LDS, n rows),
+// overwritten by the solution; t: factor tables (LDS); red: 2 * kTriRed
+// doubles of LDS.  Called by every thread of the workgroup.
+//
+// The serial sweeps read and write rows in full batches of kB (no per-row
+// predication, LDS latency off the dependent chain).  The serial parts run
+// on all of wave 0 with an offset zo that is 0 but not known to be, so the
+// running values stay in vector registers.
+__device__ void pois_solve(const PoisFac& f, const double* t, double* d, double* red) {
+  constexpr int kB = 8;
+  const int tid = threadIdx.x, nt = blockDim.x, n = f.n, P = f.P;
+  const int zo = (int)(threadIdx.x / blockDim.x);
+  const double a = kPa, c = kPc;
+  __syncthreads();
+  if (P == 0) {
+    if (tid < 64) {
+      const double* fr = t + f.fr + zo;
+      const double* fc = t + f.fc + zo;
+      double* dd = d + zo;
+      double dp = dd[0] * fr[0];
+      dd[0] = dp;
+      for (int j = 1; j < n; ++j) {
+        dp = (dd[j] - a * dp) * fr[j];
+        dd[j] = dp;
+      }
+      double x = dp;
+      for (int j = n - 2; j >= 0; --j) {
+        x = dd[j] - fc[j] * x;
+        dd[j] = x;
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  double* rd = red;
+  double* rx = red + kTriRed;
+  if (tid < P) {
+    const int p = tid;
+    const int s = p * n / P;
+    const int e = (p + 1) * n / P - 1;
+    const double* fr = t + f.fr - s;  // fr[i] = factor of local row i - s
+    const double* fc = t + f.fc - s;
+    int i = s + 1;
+    double dp = d[i] * fr[i];
+    d[i] = dp;
+    for (i = s + 2; i + kB <= e; i += kB) {  // rows i .. i + kB - 1 <= e - 1
+      double dv[kB], tv[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        dv[u] = d[i + u];
+        tv[u] = fr[i + u];
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        dp = (dv[u] - a * dp) * tv[u];
+        dv[u] = dp;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) d[i + u] = dv[u];
+    }
+    for (; i <= e - 1; ++i) {
+      dp = (d[i] - a * dp) * fr[i];
+      d[i] = dp;
+    }
+    for (i = e - 2; i - kB >= s; i -= kB) {  // rows i .. i - kB + 1 >= s + 1
+      double dv[kB], tv[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        dv[u] = d[i - u];
+        tv[u] = fc[i - u];
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        dp = dv[u] - tv[u] * dp;
+        dv[u] = dp;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) d[i - u] = dv[u];
+    }
+    for (; i >= s + 1; --i) {
+      dp = d[i] - fc[i] * dp;
+      d[i] = dp;
+    }
+    rd[2 * p] = d[s] - c * d[s + 1];
+    rd[2 * p + 1] = d[e] - a * d[e - 1];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int n2 = 2 * P;
+    const double* ra = t + f.ra + zo;
+    const double* rr = t + f.rr + zo;
+    const double* rc = t + f.rc + zo;
+    const double* rdz = rd + zo;
+    double* rxz = rx + zo;
+    double dp = rdz[0] * rr[0];
+    rxz[0] = dp;
+    int j = 1;
+    for (; j + kB <= n2; j += kB) {
+      double dv[kB], av[kB], rv[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        dv[u] = rdz[j + u];
+        av[u] = ra[j + u];
+        rv[u] = rr[j + u];
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        dp = (dv[u] - av[u] * dp) * rv[u];
+        dv[u] = dp;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) rxz[j + u] = dv[u];
+    }
+    for (; j < n2; ++j) {
+      dp = (rdz[j] - ra[j] * dp) * rr[j];
+      rxz[j] = dp;
+    }
+    double x = dp;
+    j = n2 - 2;
+    for (; j - kB >= -1; j -= kB) {  // rows j .. j - kB + 1 >= 0
+      double dv[kB], cv[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        dv[u] = rxz[j - u];
+        cv[u] = rc[j - u];
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        x = dv[u] - cv[u] * x;
+        dv[u] = x;
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) rxz[j - u] = dv[u];
+    }
+    for (; j >= 0; --j) {
+      x = rxz[j] - rc[j] * x;
+      rxz[j] = x;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) {
+    const int p = ((i + 1) * P - 1) / n;
+    const int s = p * n / P;
+    const int e = (p + 1) * n / P - 1;
+    const double xs = rx[2 * p], xe = rx[2 * p + 1];
+    double xi;
+    if (i == s) {
+      xi = xs;
+    } else if (i == e) {
+      xi = xe;
+    } else {
+      const int o = (e - s + 1 - f.L0) * f.Lmax + (i - s);
+      xi = (d[i] - t[f.xa + o] * xs) - t[f.xc + o] * xe;
+    }
+    d[i] = xi;
+  }
+  __syncthreads();
+}
+
+// LDS of the finalize kernel (doubles): the solution, this step's deposit,
+// the reduced system and the factor tables.
+__host__ __device__ constexpr size_t finalize_lds_doubles(int nn_max) {
+  return 2u * (size_t)nn_max + 2u * kTriRed + kFacMax;
+}
+
+// Nodes per finalize thread (at most 4097 nodes).
+constexpr int kNodeSlots = (kMaxNodes + kFinThreads - 1) / kFinThreads;
+// Child counts per thread per scan tile, in 16-byte vectors.
+constexpr int kScanVec = 8;
+constexpr uint32_t kScanTile = (uint32_t)kFinThreads * kScanVec * 4u;
+
+// End of a step (field_only == 0) and the field of the next one.  Global
+// inputs are loaded together up front so that the kernel pays few memory
+// round trips: the state, this step's deposit, n_i and the ion sources,
+// the first tile of child counts, the factor tables and V(t).
 template <class P>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __restrict__ ds,
                                                           int field_only) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Disch<P>& d = ds[blockIdx.x];
-  State* st = d.st;
-  const int tid = threadIdx.x;
+  Gp<State>* st = gptr(d.st);
+  const int tid = threadIdx.x, nn = d.nn, nc = d.nc, m = nc - 1;
+  double* X = reinterpret_cast<double*>(smem);         // interior rows j - 1
+  int64_t* CN = reinterpret_cast<int64_t*>(X + nn);     // deposit of the step
+  double* red = reinterpret_cast<double*>(CN + nn);
+  double* T = red + 2 * kTriRed;
   __shared__ uint32_t sh[kWaves + 1];
   __shared__ uint32_t sh_see[2];
+  // state snapshot
+  const int64_t steps_left = st->steps_left;
+  const int64_t step0 = st->step;
+  const int cbuf0 = st->cbuf;
+  const uint32_t n_main = st->n_main;
+  const uint32_t next_id = st->next_id;
+  const double wall_g = tid < 2 ? st->wall[tid] : 0.0;
+  if (!field_only && steps_left <= 0) return;
+  const int64_t step1 = field_only ? step0 : step0 + 1;
+  const int cur = field_only ? cbuf0 : (cbuf0 ^ 1);
+  Gp<int64_t>* cn = gptr(d.cnt[cur]);
+  const Gp<double>* volt = gptr(d.volt);
+  const double V = (step1 < d.volt_len) ? volt[step1] : 0.0;
+  // first tile of child counts (whole chunks, a multiple of 4 sub-chunks)
+  const uint32_t nch =
+      field_only ? 0u : (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile * (uint32_t)(kTile / kSub);
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const Gp<u32x4>* kids4 = reinterpret_cast<const Gp<u32x4>*>(gptr(d.chunk_kids));
+  u32x4 kv[kScanVec];
+  auto load_tile = [&](uint32_t t0) {
+    const uint32_t q0 = (t0 >> 2) + (uint32_t)tid * kScanVec;
+#pragma unroll
+    for (int q = 0; q < kScanVec; ++q)
+      kv[q] = (4u * (q0 + (uint32_t)q) < nch) ? kids4[q0 + (uint32_t)q] : u32x4{0u, 0u, 0u, 0u};
+  };
+  load_tile(0);
+  // per-node inputs: deposit to LDS, n_i with this step's ion sources
+  const Gp<double>* gni = gptr(d.ni);
+  const Gp<int64_t>* gsrc = gptr(d.ion_src);
+  double niv[kNodeSlots];
+#pragma unroll
+  for (int u = 0; u < kNodeSlots; ++u) {
+    const int j = tid + u * kFinThreads;
+    niv[u] = 0.0;
+    if (j < nn) {
+      CN[j] = load_dev(&d.cnt[cur][j]);
+      const double n0 = gni[j];
+      niv[u] = field_only ? n0 : n0 + (double)gsrc[j] * scale_of(d, j);
+    }
+  }
+  // factor tables of the Poisson solve
+  const PoisFac f = pois_fac(m);
+  Gp<double>* gtab = gptr(d.scratch);
+  if (field_only) {
+    if (tid == 0) pois_factor(f, T);
+  } else {
+    for (int i = tid; i < f.size; i += kFinThreads) T[i] = gtab[i];
+  }
   if (!field_only) {
-    if (st->steps_left <= 0) return;
-    const int cb = st->cbuf ^ 1;  // deposit of this step
-    int64_t* cn = d.cnt[cb];
-    const uint32_t n_main = st->n_main;
-    // sub-chunks the electron kernel wrote child counts for (whole chunks)
-    const uint32_t nch = (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile * (uint32_t)(kTile / kSub);
-    // offsets of the staged children: tiles of kFinThreads x 16 sub-chunks,
-    // each thread reading and writing 16 consecutive counts as four 16-byte
-    // vectors (nch is a multiple of 4)
+    // offsets of the staged children
     uint32_t n_kids = 0;
-    for (uint32_t t0 = 0; t0 < nch; t0 += (uint32_t)kFinThreads * 16u) {
-      const uint32_t k0 = t0 + (uint32_t)tid * 16u;
-      uint4 v[4];
+    Gp<u32x4>* base4 = reinterpret_cast<Gp<u32x4>*>(gptr(d.chunk_base));
+    for (uint32_t t0 = 0; t0 < nch; t0 += kScanTile) {
+      if (t0 > 0) load_tile(t0);
       uint32_t loc = 0;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        v[q] = make_uint4(0u, 0u, 0u, 0u);
-        if (k0 + 4u * (uint32_t)q < nch)
-          v[q] = *reinterpret_cast<const uint4*>(d.chunk_kids + k0 + 4u * (uint32_t)q);
-        loc += (v[q].x + v[q].y) + (v[q].z + v[q].w);
-      }
+      for (int q = 0; q < kScanVec; ++q) loc += (kv[q].x + kv[q].y) + (kv[q].z + kv[q].w);
       uint32_t tot;
       uint32_t run = n_kids + block_scan(loc, sh, &tot);
+      const uint32_t q0 = (t0 >> 2) + (uint32_t)tid * kScanVec;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint4 b;
+      for (int q = 0; q < kScanVec; ++q) {
+        u32x4 b;
         b.x = run;
-        b.y = b.x + v[q].x;
-        b.z = b.y + v[q].y;
-        b.w = b.z + v[q].z;
-        run = b.w + v[q].w;
-        if (k0 + 4u * (uint32_t)q < nch)
-          *reinterpret_cast<uint4*>(d.chunk_base + k0 + 4u * (uint32_t)q) = b;
+        b.y = b.x + kv[q].x;
+        b.z = b.y + kv[q].y;
+        b.w = b.z + kv[q].z;
+        run = b.w + kv[q].w;
+        if (4u * (q0 + (uint32_t)q) < nch) base4[q0 + (uint32_t)q] = b;
       }
       n_kids += tot;
     }
+    __syncthreads();  // CN complete before emission deposits into it
     // emission from the wall fluxes of this step's fluid update
     if (tid < 2) {
-      const double g = st->wall[tid];
-      const double F = tid == 0 ? ((-g < 0.0) ? 0.0 : -g) : ((g < 0.0) ? 0.0 : g);
+      const double F = tid == 0 ? ((-wall_g < 0.0) ? 0.0 : -wall_g) : ((wall_g < 0.0) ? 0.0 : wall_g);
       uint64_t em = 0, ab = 0, cl = 0;
       uint32_t n = 0;
-      emit<P>(d, tid, F, (uint32_t)st->step, cn, &n, &em, &ab, &cl);
+      emit<P>(d, tid, F, (uint32_t)step0, CN, &n, &em, &ab, &cl);
       sh_see[tid] = n;
-      if (em) atomicAdd(reinterpret_cast<unsigned long long*>(&st->emitted[tid]), (unsigned long long)em);
-      if (ab) atomicAdd(reinterpret_cast<unsigned long long*>(&st->absorbed[tid]), (unsigned long long)ab);
-      if (cl) atomicAdd(reinterpret_cast<unsigned long long*>(&st->see_clamped), (unsigned long long)cl);
+      if (em) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->emitted[tid]), (unsigned long long)em);
+      if (ab) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->absorbed[tid]), (unsigned long long)ab);
+      if (cl) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->see_clamped), (unsigned long long)cl);
     }
     __syncthreads();
-    // ion sources of the step, run averages
-    for (int j = tid; j < d.nn; j += kFinThreads) {
-      const double nj = d.ni[j] + (double)d.ion_src[j] * scale_of(d, j);
-      d.ni[j] = nj;
-      d.ion_src[j] = 0;
-      d.acc_cnt[j] += (uint64_t)load_dev(&cn[j]);
-      d.acc_ni[j] += nj;
+    // ion sources of the step, the final deposit, run averages
+    Gp<double>* wni = gptr(d.ni);
+    Gp<int64_t>* wsrc = gptr(d.ion_src);
+    Gp<double>* acc_ni = gptr(d.acc_ni);
+#pragma unroll
+    for (int u = 0; u < kNodeSlots; ++u) {
+      const int j = tid + u * kFinThreads;
+      if (j < nn) {
+        const int64_t c = CN[j];
+        wni[j] = niv[u];
+        wsrc[j] = 0;
+        cn[j] = c;
+        atomicAdd(reinterpret_cast<unsigned long long*>(&d.acc_cnt[j]), (unsigned long long)c);
+        acc_ni[j] = acc_ni[j] + niv[u];
+      }
     }
     if (tid == 0) {
       const uint32_t ns0 = sh_see[0], ns1 = sh_see[1];
@@ -240,67 +540,119 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
         st->steps_left = 0;
       } else {
         st->append_base = n_main;
-        st->id_base = st->next_id;
+        st->id_base = next_id;
         st->n_main = n_main + (uint32_t)n_app;
-        st->next_id = st->next_id + (uint32_t)n_app;
+        st->next_id = next_id + (uint32_t)n_app;
         st->append_pending = n_app > 0 ? 1 : 0;
-        st->steps_left = st->steps_left - 1;
+        st->steps_left = steps_left - 1;
       }
-      st->step = st->step + 1;
-      st->n_acc = st->n_acc + 1;
-      st->sort_due = (st->step % d.sort_every) == 0 ? 1 : 0;
-      st->cbuf = cb;
+      st->step = step1;
+      atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->n_acc), 1ull);
+      st->sort_due = (step1 % d.sort_every) == 0 ? 1 : 0;
+      st->cbuf = cur;
     }
-    __syncthreads();
   }
-  // field of the (new) current step
-  const int cur = st->cbuf;
-  const int64_t step = st->step;
-  const double V = (step < d.volt_len) ? d.volt[step] : 0.0;
-  field<P>(d, d.cnt[cur], V, reinterpret_cast<double*>(smem));
-  // clear the deposit target of the next step
-  int64_t* nxt = d.cnt[cur ^ 1];
-  for (int j = tid; j < d.nn; j += kFinThreads) nxt[j] = 0;
+  __syncthreads();
+  // Poisson's equation with phi_0 = V(t), phi_N = 0 for the interior nodes
+  double rho[kNodeSlots];
+#pragma unroll
+  for (int u = 0; u < kNodeSlots; ++u) {
+    const int j = tid + u * kFinThreads;
+    rho[u] = 0.0;
+    if (j < nn) {
+      const double ne = (double)CN[j] * scale_of(d, j);
+      const double r = kECharge * (niv[u] - ne);
+      rho[u] = r;
+      if (j >= 1 && j <= m) {
+        double dj = d.kp * r;
+        if (j == 1) dj = dj + V;
+        if (j == m) dj = dj + 0.0;
+        X[j - 1] = dj;
+      }
+    }
+  }
+  pois_solve(f, T, X, red);
+  if (field_only)
+    for (int i = tid; i < f.size; i += kFinThreads) gtab[i] = T[i];
+  // E from centred differences inside and Gauss's law over the wall half
+  // cells; E' = (-e/m_e) dt E rounded to the particle precision
+  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : X[j - 1]); };
+  Gp<double>* gphi = gptr(d.phi);
+  Gp<double>* gE = gptr(d.E);
+  Gp<P>* gEp = gptr(d.Ep);
+  Gp<int64_t>* nxt = gptr(d.cnt[cur ^ 1]);
+#pragma unroll
+  for (int u = 0; u < kNodeSlots; ++u) {
+    const int j = tid + u * kFinThreads;
+    if (j < nn) {
+      double e;
+      if (j == 0)
+        e = (phi(0) - phi(1)) * d.inv_dz - rho[u] * d.hdz_eps;
+      else if (j == nc)
+        e = (phi(nc - 1) - phi(nc)) * d.inv_dz + rho[u] * d.hdz_eps;
+      else
+        e = (phi(j - 1) - phi(j + 1)) * d.inv_2dz;
+      gphi[j] = phi(j);
+      gE[j] = e;
+      gEp[j] = (P)(d.qm_dt * e);
+      nxt[j] = 0;  // deposit target of the next step
+    }
+  }
 }
 
 // Append this step's children (in sub-chunk order, i.e. parent order), then the
-// left and right secondaries, with consecutive ids.
+// left and right secondaries, with consecutive ids.  Each wave takes 64
+// consecutive sub-chunks and copies the children of each non-empty one with
+// all of its lanes.
+template <class P>
+__device__ __forceinline__ void append_one(const Disch<P>& d, int buf, uint32_t src_c, uint32_t dst,
+                                           uint32_t id, const Gp<int32_t>* sc, const Gp<P>* so,
+                                           const Gp<P>* sx, const Gp<P>* sy, const Gp<P>* sz) {
+  gptr(d.cell[buf])[dst] = sc[src_c];
+  gptr(d.off[buf])[dst] = so[src_c];
+  gptr(d.vx[buf])[dst] = sx[src_c];
+  gptr(d.vy[buf])[dst] = sy[src_c];
+  gptr(d.vz[buf])[dst] = sz[src_c];
+  gptr(d.id[buf])[dst] = id;
+}
+
 template <class P>
 __global__ __launch_bounds__(kThreads) void k_append(const Disch<P>* __restrict__ ds, int D) {
-  const int tid = threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = (blockIdx.x * (uint32_t)kThreads + threadIdx.x) >> 6;
+  const uint32_t nwaves = gridDim.x * (uint32_t)(kThreads / 64);
+  const uint32_t gid = blockIdx.x * (uint32_t)kThreads + threadIdx.x;
+  const uint32_t gsz = gridDim.x * (uint32_t)kThreads;
   for (int di = 0; di < D; ++di) {
     const Disch<P>& d = ds[di];
-    const State* st = d.st;
+    const Gp<State>* st = gptr(d.st);
     if (!st->append_pending) continue;
     const int buf = st->buf;
     const uint32_t nch = st->n_chunks, base = st->append_base, idb = st->id_base;
-    for (uint32_t lc = blockIdx.x; lc < nch; lc += gridDim.x) {
-      const uint32_t k = d.chunk_kids[lc];
-      if (k == 0) continue;
-      const uint32_t cb = d.chunk_base[lc];
-      for (uint32_t t = (uint32_t)tid; t < k; t += (uint32_t)kThreads) {
-        const uint32_t src = lc * (uint32_t)kSub + t;
-        const uint32_t dst = base + cb + t;
-        d.cell[buf][dst] = d.kc[src];
-        d.off[buf][dst] = d.koff[src];
-        d.vx[buf][dst] = d.kvx[src];
-        d.vy[buf][dst] = d.kvy[src];
-        d.vz[buf][dst] = d.kvz[src];
-        d.id[buf][dst] = idb + cb + t;
+    const uint32_t nk = st->n_kids, n0 = st->n_see[0], n1 = st->n_see[1];
+    const Gp<uint32_t>* kids = gptr(d.chunk_kids);
+    const Gp<uint32_t>* cbase = gptr(d.chunk_base);
+    for (uint32_t k0 = wave * 64u; k0 < nch; k0 += nwaves * 64u) {
+      const uint32_t k = k0 + lane;
+      const uint32_t cnt = k < nch ? kids[k] : 0u;
+      uint64_t live = __ballot(cnt != 0u);
+      if (live == 0) continue;
+      const uint32_t cb = cnt ? cbase[k] : 0u;
+      while (live) {
+        const int l = __ffsll((unsigned long long)live) - 1;
+        live &= live - 1;
+        const uint32_t n = (uint32_t)__shfl((int)cnt, l, 64);
+        const uint32_t b = (uint32_t)__shfl((int)cb, l, 64);
+        const uint32_t src0 = (k0 + (uint32_t)l) * (uint32_t)kSub;
+        for (uint32_t t = lane; t < n; t += 64u)
+          append_one<P>(d, buf, src0 + t, base + b + t, idb + b + t, gptr(d.kc), gptr(d.koff),
+                        gptr(d.kvx), gptr(d.kvy), gptr(d.kvz));
       }
     }
-    if ((int)blockIdx.x == di % (int)gridDim.x) {
-      const uint32_t nk = st->n_kids, n0 = st->n_see[0], n1 = st->n_see[1];
-      for (uint32_t t = (uint32_t)tid; t < n0 + n1; t += (uint32_t)kThreads) {
-        const uint32_t src = t < n0 ? t : (uint32_t)kSeeMax + (t - n0);
-        const uint32_t dst = base + nk + t;
-        d.cell[buf][dst] = d.sc[src];
-        d.off[buf][dst] = d.soff[src];
-        d.vx[buf][dst] = d.svx[src];
-        d.vy[buf][dst] = d.svy[src];
-        d.vz[buf][dst] = d.svz[src];
-        d.id[buf][dst] = idb + nk + t;
-      }
+    for (uint32_t t = gid; t < n0 + n1; t += gsz) {
+      const uint32_t src = t < n0 ? t : (uint32_t)kSeeMax + (t - n0);
+      append_one<P>(d, buf, src, base + nk + t, idb + nk + t, gptr(d.sc), gptr(d.soff),
+                    gptr(d.svx), gptr(d.svy), gptr(d.svz));
     }
   }
 }
@@ -331,7 +683,7 @@ __global__ void k_diag(int64_t n, const P* a, const P* b, P* out) {
 template <class P>
 hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_max,
                            hipStream_t s) {
-  const size_t lds = ((size_t)4 * (size_t)nn_max + 7u * kTriRed) * 8u;
+  const size_t lds = finalize_lds_doubles(nn_max) * 8u;
   hipLaunchKernelGGL(k_finalize<P>, dim3(D), dim3(kFinThreads), lds, s, d_dev, field_only);
   return hipGetLastError();
 }
@@ -339,7 +691,7 @@ hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_
 template <class P>
 hipError_t finalize_set_lds(int nn_max) {
   return hipFuncSetAttribute((const void*)k_finalize<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (4 * nn_max + 7 * kTriRed) * 8);
+                             (int)(finalize_lds_doubles(nn_max) * 8u));
 }
 
 template hipError_t finalize_set_lds<float>(int);
