@@ -186,6 +186,20 @@ __device__ __forceinline__ int64_t cic_w1(P off) {
   return (int64_t)rint(off * (P)4294967296.0);
 }
 
+// The same weight as an unsigned value: below 2^32 for FP32 (off < 1 has at
+// most 24 significant bits, so rint(off 2^32) <= 2^32 - 2^8) and at most
+// 2^32 for FP64.
+__device__ __forceinline__ uint64_t cic_w1u_f32(float off) {
+  return (uint64_t)(uint32_t)rintf(off * 4294967296.0f);
+}
+template <class P>
+__device__ __forceinline__ uint64_t cic_w1u(P off) {
+  if constexpr (sizeof(P) == 4)
+    return cic_w1u_f32(off);
+  else
+    return (uint64_t)rint(off * (P)4294967296.0);
+}
+
 __device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }

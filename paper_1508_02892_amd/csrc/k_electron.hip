@@ -208,44 +208,52 @@ __device__ __forceinline__ void drain(const Disch<P>& d, const Seg<P>& g, QEntry
 }
 
 // Channel of a collision candidate: the first k whose interpolated cumulative
-// probability exceeds R (-1: null collision).
+// probability exceeds R (-1: null collision).  All K comparisons are made and
+// the first true one is taken, so the loop has the same trip count on every
+// lane.
 template <class P>
 __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy, P vz,
-                                              uint32_t& n_ovf) {
+                                              bool& ovf) {
   const int K = g.K;
   const P v2 = (vx * vx + vy * vy) + vz * vz;
   const P en = g.KE * v2;
   const P sx = en * g.inv_dE;
   int i;
   P t;
-  if (sx >= (P)(g.ne - 1)) {
+  ovf = sx >= (P)(g.ne - 1);
+  if (ovf) {
     i = g.ne - 2;
     t = (P)1;
-    n_ovf += 1;
   } else {
     i = (int)sx;
     t = sx - (P)i;
   }
   auto scan = [&](auto ra) {
+    uint32_t hit = 0;
     for (int k = 0; k < K; ++k) {
       const P pa = ra[k];
       const P pb = ra[K + k];
       const P pk = pa + t * (pb - pa);
-      if (u0 < pk) return k;
+      hit |= (u0 < pk ? 1u : 0u) << k;
     }
-    return -1;
+    return hit ? __builtin_ctz(hit) : -1;
   };
   // rows i and i+1 from LDS when both are there, else through the cache
   if (i + 1 < g.tab_rows) return scan(g.tab + i * K);
   return scan(g.tab_g + (size_t)i * K);
 }
 
-// One wave's 256 slots of a chunk: push, removal, null-collision test and
-// channel, deposit at x^{n+1}, write-back; collisions are queued.  No
-// workgroup barrier is involved.
+// Event counts of one wave, accumulated over a segment (wave-uniform).
+struct WaveCounts {
+  uint32_t absl = 0, absr = 0, ovf = 0, pushed = 0;
+};
+
+// One wave's 256 slots of a chunk: push, removal and write-back, then the
+// null-collision test and channel, the deposit at x^{n+1}; collisions are
+// queued.  No workgroup barrier is involved.
 template <class P>
 __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEntry<P>* q,
-                           uint32_t& qn) {
+                           uint32_t& qn, WaveCounts& wc) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
@@ -258,10 +266,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   gld4(g.id + i0, id);
   gld4(g.vx + i0, vx);
   gld4(g.vy + i0, vy);
-  int ch[4];
   bool alive[4];
-  uint32_t n_absl = 0, n_absr = 0, n_ovf = 0;
-  uint32_t n_push = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     // leapfrog push with the linear gather of E', written with selects
@@ -281,13 +286,22 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     const P on0 = s - f;
     const bool wrap = on0 == (P)1;
     const int32_t cn = cc + (stay ? (int32_t)f : 0) + (wrap ? 1 : 0);
-    n_push += live ? 1u : 0u;
-    n_absl += (live && outl) ? 1u : 0u;
-    n_absr += (live && outr) ? 1u : 0u;
+    wc.pushed += (uint32_t)__popcll(__ballot(live));
+    wc.absl += (uint32_t)__popcll(__ballot(live && outl));
+    wc.absr += (uint32_t)__popcll(__ballot(live && outr));
     vz[j] = live ? vzn : vz[j];
     c[j] = stay ? cn : (live ? -1 : c[j]);
     off[j] = stay ? (wrap ? (P)0 : on0) : off[j];
     alive[j] = stay;
+  }
+  // write back (vx, vy unchanged; collided particles get theirs when
+  // scattered); issued early so that they retire behind the Philox work
+  gst4(g.cell + i0, c);
+  gst4(g.off + i0, off);
+  gst4(g.vz + i0, vz);
+  int ch[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
     // null-collision test with one Philox block of stream (tag 0, id, step)
     uint32_t w0, w1, w2, w3;
     philox4x32_10(id[j], g.step, 0u, kTagElectron, g.seed_lo, g.seed_hi, w0, w1, w2, w3);
@@ -297,47 +311,32 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     else
       u0 = (P)u01_f64(w0, w1);
     ch[j] = -1;
-    if (stay && u0 < g.Pmax) ch[j] = select_channel<P>(g, u0, vx[j], vy[j], vz[j], n_ovf);
+    bool ovf = false;
+    if (alive[j] && u0 < g.Pmax) ch[j] = select_channel<P>(g, u0, vx[j], vy[j], vz[j], ovf);
+    wc.ovf += (uint32_t)__popcll(__ballot(ovf));
   }
-  // write back (vx, vy unchanged; collided particles get theirs when scattered)
-  gst4(g.cell + i0, c);
-  gst4(g.off + i0, off);
-  gst4(g.vz + i0, vz);
-  // event counters: one LDS atomic per wave
-  {
-    uint32_t v[4] = {n_absl, n_absr, n_ovf, n_push};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
-    }
-    if (lane == 0) {
-      if (v[0]) atomicAdd(&g.ctr[kCtrAbsL], v[0]);
-      if (v[1]) atomicAdd(&g.ctr[kCtrAbsR], v[1]);
-      if (v[2]) atomicAdd(&g.ctr[kCtrOverflow], v[2]);
-      if (v[3]) atomicAdd(&g.ctr[kCtrPushed], v[3]);
-    }
-  }
-  // deposit at x^{n+1}: runs of equal cells merged per thread, then one wave
-  // sum when the whole wave sits in one cell (sorted particles)
+  // deposit at x^{n+1}.  W0 + W1 = 2^32 per particle, so a run of m
+  // particles in one cell adds m 2^32 - sum W1 to its left node and sum W1
+  // to its right node.  Runs of equal cells are merged per thread, then over
+  // the wave when the whole wave sits in one cell (sorted particles).
   int rc = -1;
-  uint64_t a0 = 0, a1 = 0;
+  uint64_t a1 = 0;
+  uint32_t m = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (!alive[j]) continue;
-    const int64_t W1 = cic_w1<P>(off[j]);
-    const int64_t W0 = ((int64_t)1 << 32) - W1;
+    const uint64_t W1 = cic_w1u<P>(off[j]);
     if (c[j] == rc) {
-      a0 += (uint64_t)W0;
-      a1 += (uint64_t)W1;
+      a1 += W1;
+      m += 1;
     } else {
       if (rc >= 0) {
-        lds_add_i64(&g.bins[rc], a0);
+        lds_add_i64(&g.bins[rc], ((uint64_t)m << 32) - a1);
         lds_add_i64(&g.bins[rc + 1], a1);
       }
       rc = c[j];
-      a0 = (uint64_t)W0;
-      a1 = (uint64_t)W1;
+      a1 = W1;
+      m = 1;
     }
   }
   const uint64_t act = __ballot(rc >= 0);
@@ -345,18 +344,19 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     const int lead = __ffsll((unsigned long long)act) - 1;
     const int rl = __shfl(rc, lead, 64);
     if (__ballot(rc >= 0 && rc != rl) == 0) {
-      uint64_t s0 = rc >= 0 ? a0 : 0, s1 = rc >= 0 ? a1 : 0;
+      uint64_t s1 = rc >= 0 ? a1 : 0;
+      uint32_t sm = rc >= 0 ? m : 0;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
-        s0 += __shfl_xor(s0, o, 64);
         s1 += __shfl_xor(s1, o, 64);
+        sm += __shfl_xor(sm, o, 64);
       }
       if (lane == lead) {
-        lds_add_i64(&g.bins[rl], s0);
+        lds_add_i64(&g.bins[rl], ((uint64_t)sm << 32) - s1);
         lds_add_i64(&g.bins[rl + 1], s1);
       }
     } else if (rc >= 0) {
-      lds_add_i64(&g.bins[rc], a0);
+      lds_add_i64(&g.bins[rc], ((uint64_t)m << 32) - a1);
       lds_add_i64(&g.bins[rc + 1], a1);
     }
   }
@@ -372,20 +372,20 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const bool ion = ch[j] >= 0 && ((g.ion_mask >> ch[j]) & 1u);
-    const uint64_t m = __ballot(ion);
-    kid += (uint32_t)__popcll(m & lt);
-    nk += (uint32_t)__popcll(m);
+    const uint64_t mk = __ballot(ion);
+    kid += (uint32_t)__popcll(mk & lt);
+    nk += (uint32_t)__popcll(mk);
   }
   if (lane == 0) gptr(d.chunk_kids)[lc * (uint32_t)kWaves + (uint32_t)wv] = nk;
   // queue the collisions, one slot index j at a time, and scatter in 64s
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const bool col = ch[j] >= 0;
-    const uint64_t m = __ballot(col);
-    if (m == 0) continue;
+    const uint64_t mk = __ballot(col);
+    if (mk == 0) continue;
     if (col) {
       const bool ion = (g.ion_mask >> ch[j]) & 1u;
-      QEntry<P>& e = q[qn + (uint32_t)__popcll(m & lt)];
+      QEntry<P>& e = q[qn + (uint32_t)__popcll(mk & lt)];
       e.vx = vx[j];
       e.vy = vy[j];
       e.vz = vz[j];
@@ -396,7 +396,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
       e.meta = (uint32_t)ch[j] | (ion ? (0x100u | (kid << 16)) : 0u);
       kid += ion ? 1u : 0u;
     }
-    qn += (uint32_t)__popcll(m);
+    qn += (uint32_t)__popcll(mk);
     if (qn >= 64u) drain<P>(d, g, q, qn, 64u);
   }
 }
@@ -452,8 +452,15 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   int64_t* cnt = d.cnt[st->cbuf ^ 1];
   __syncthreads();
   uint32_t qn = 0;
-  for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P>(d, g, lc, q, qn);
+  WaveCounts wc;
+  for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P>(d, g, lc, q, qn, wc);
   if (qn) drain<P>(d, g, q, qn, qn);
+  if ((tid & 63) == 0) {
+    if (wc.absl) atomicAdd(&g.ctr[kCtrAbsL], wc.absl);
+    if (wc.absr) atomicAdd(&g.ctr[kCtrAbsR], wc.absr);
+    if (wc.ovf) atomicAdd(&g.ctr[kCtrOverflow], wc.ovf);
+    if (wc.pushed) atomicAdd(&g.ctr[kCtrPushed], wc.pushed);
+  }
   __syncthreads();
   for (int i = tid; i < d.nn; i += kElecThreads) {
     const int64_t v = g.bins[i];
