@@ -611,7 +611,7 @@ struct Batch : BatchBase {
     const int cus = prop.multiProcessorCount;
     grid_e = D + cus * occ;
     grid_a = cus;
-    grid_s = cus * 2;
+    grid_s = cus * 4;
     // per-discharge state
     for (int i = 0; i < n; ++i) {
       Prepared pr;
@@ -1007,7 +1007,7 @@ struct Server : ServerBase {
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     grid_e = S + prop.multiProcessorCount * occ;
     grid_a = prop.multiProcessorCount;
-    grid_s = prop.multiProcessorCount * 2;
+    grid_s = prop.multiProcessorCount * 4;
     HD_TRY(hipMalloc((void**)&d_idle, sizeof(State)));
     HD_TRY(hipMemset(d_idle, 0, sizeof(State)));
     HD_TRY(hipMalloc((void**)&d_desc, sizeof(Disch<P>) * S));

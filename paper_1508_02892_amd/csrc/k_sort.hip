@@ -1,13 +1,14 @@
 // Compaction and stable counting sort of the particle slots by cell, run every
 // sort_every steps so that deposits of a workgroup fall on few nodes.
 //
-// Tiles of kSortTile consecutive slots are owned by one wave each.  A tile's
-// per-cell counts go to a bin-major matrix hist[c * nt + t]; an exclusive scan
-// of that matrix in its flat order gives, for every (cell, tile), the first
-// destination slot, so holes are dropped and equal cells keep their order.
-// Within a tile, the rank of an item among earlier items of the same cell
-// comes from wave ballots over the key bits plus a per-cell running count in
-// LDS; rounds of 64 items are processed in order.
+// Tiles of kSortTile consecutive slots.  A tile's per-cell counts go to a
+// bin-major matrix hist[c * nt + t]; an exclusive scan of that matrix in its
+// flat order gives, for every (cell, tile), the first destination slot, so
+// holes are dropped and equal cells keep their order.  The scatter gives a
+// tile to a workgroup: each wave counts its quarter of the tile, a per-cell
+// prefix over the waves gives each wave its own cursors, and the rank of an
+// item among earlier items of the same cell comes from wave ballots over the
+// key bits, in rounds of 64 items processed in order.
 #include "hd_device.h"
 
 namespace hd {
@@ -25,18 +26,22 @@ __device__ __forceinline__ uint32_t n_tiles(const Disch<P>& d) {
 
 template <class P>
 __global__ __launch_bounds__(kThreads) void k_sort_clear(const Disch<P>* __restrict__ ds, int D) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const uint64_t gid = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+  const uint64_t gsz = (uint64_t)gridDim.x * kThreads;
   for (int di = 0; di < D; ++di) {
     const Disch<P>& d = ds[di];
     if (!d.st->sort_due) continue;
     const uint64_t n = (uint64_t)d.nc * n_tiles(d);
-    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * kThreads)
-      d.hist[i] = 0u;
+    Gp<u32x4>* h4 = reinterpret_cast<Gp<u32x4>*>(gptr(d.hist));
+    for (uint64_t i = gid; i < n / 4; i += gsz) h4[i] = u32x4{0u, 0u, 0u, 0u};
+    for (uint64_t i = (n / 4) * 4 + gid; i < n; i += gsz) gptr(d.hist)[i] = 0u;
   }
 }
 
 template <class P>
-__global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restrict__ ds, int D) {
+__global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restrict__ ds, int D,
+                                                         int stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t gw = blockIdx.x * kWavesPerBlock + wv, nw = gridDim.x * kWavesPerBlock;
@@ -46,19 +51,28 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
     if (!st->sort_due) continue;
     const uint32_t n = st->n_main, nt = n_tiles(d);
     const int nc = d.nc;
-    uint32_t* h = reinterpret_cast<uint32_t*>(smem) + (size_t)wv * (size_t)(nc + 1);
-    const int32_t* cell = d.cell[st->buf];
+    // each wave owns stride (>= nc + 1) words for the whole launch
+    uint32_t* h = reinterpret_cast<uint32_t*>(smem) + (size_t)wv * (size_t)stride;
+    const Gp<int32_t>* cell = gptr(d.cell[st->buf]);
+    Gp<uint32_t>* hist = gptr(d.hist);
+    for (int c = lane; c < nc; c += 64) h[c] = 0u;
     for (uint32_t t = gw; t < nt; t += nw) {
-      for (int c = lane; c < nc; c += 64) h[c] = 0u;
       int lo = nc, hi = -1;
       const uint32_t b = t * (uint32_t)kSortTile;
       const uint32_t e = min(n, b + (uint32_t)kSortTile);
-      for (uint32_t i = b + (uint32_t)lane; i < e; i += 64) {
-        const int c = cell[i];
-        if (c >= 0) {
-          atomicAdd(&h[c], 1u);
-          lo = min(lo, c);
-          hi = max(hi, c);
+      // 4 consecutive slots per lane per 256-slot round (slot counts are
+      // multiples of 4 up to the capacity, so the vector load stays inside)
+      for (uint32_t i = b + 4u * (uint32_t)lane; i < e; i += 256u) {
+        int32_t c4[4];
+        gld4(cell + i, c4);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int c = c4[k];
+          if (i + (uint32_t)k < e && c >= 0) {
+            atomicAdd(&h[c], 1u);
+            lo = min(lo, c);
+            hi = max(hi, c);
+          }
         }
       }
       for (int o = 32; o > 0; o >>= 1) {
@@ -67,12 +81,48 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
       }
       for (int c = lo + lane; c <= hi; c += 64) {
         const uint32_t v = h[c];
-        if (v) d.hist[(size_t)c * nt + t] = v;
+        if (v) hist[(size_t)c * nt + t] = v;
+        h[c] = 0u;
       }
       if (lane == 0) {
-        d.tile_rng[2 * t] = lo;
-        d.tile_rng[2 * t + 1] = hi;
+        gptr(d.tile_rng)[2 * t] = lo;
+        gptr(d.tile_rng)[2 * t + 1] = hi;
       }
+    }
+  }
+}
+
+// kScanItems consecutive matrix entries from base (a multiple of 16), as
+// 16-byte vectors where the whole vector lies below n.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void load_items(const Gp<uint32_t>* h, uint64_t base, uint64_t n,
+                                           uint32_t (&v)[kScanItems]) {
+#pragma unroll
+  for (int q = 0; q < kScanItems / 4; ++q) {
+    const uint64_t i = base + 4u * (uint64_t)q;
+    if (i + 4 <= n) {
+      const u32x4 x = *reinterpret_cast<const Gp<u32x4>*>(h + i);
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[4 * q + k] = (i + k < n) ? h[i + k] : 0u;
+    }
+  }
+}
+__device__ __forceinline__ void store_items(Gp<uint32_t>* h, uint64_t base, uint64_t n,
+                                            const uint32_t (&v)[kScanItems]) {
+#pragma unroll
+  for (int q = 0; q < kScanItems / 4; ++q) {
+    const uint64_t i = base + 4u * (uint64_t)q;
+    if (i + 4 <= n) {
+      *reinterpret_cast<Gp<u32x4>*>(h + i) = u32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (i + k < n) h[i + k] = v[4 * q + k];
     }
   }
 }
@@ -126,8 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const Disch<P>* __rest
     for (uint32_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
       uint32_t v[kScanItems];
       const uint64_t base = (uint64_t)blk * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
-#pragma unroll
-      for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? d.hist[base + k] : 0u;
+      load_items(gptr(d.hist), base, n, v);
       const uint32_t tot = block_excl_scan(v, sh);
       if (threadIdx.x == 0) d.bin_start[blk] = tot;
     }
@@ -168,22 +217,22 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restri
     for (uint32_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
       uint32_t v[kScanItems];
       const uint64_t base = (uint64_t)blk * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
-#pragma unroll
-      for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < n) ? d.hist[base + k] : 0u;
+      load_items(gptr(d.hist), base, n, v);
       (void)block_excl_scan(v, sh);
       const uint32_t off = d.bin_start[blk];
 #pragma unroll
-      for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) d.hist[base + k] = v[k] + off;
+      for (int k = 0; k < kScanItems; ++k) v[k] += off;
+      store_items(gptr(d.hist), base, n, v);
     }
   }
 }
 
 template <class P>
-__global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __restrict__ ds, int D) {
+__global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __restrict__ ds, int D,
+                                                           int stride) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint32_t gw = blockIdx.x * kWavesPerBlock + wv, nw = gridDim.x * kWavesPerBlock;
   const uint64_t lt = lanemask_lt();
   for (int di = 0; di < D; ++di) {
     const Disch<P>& d = ds[di];
@@ -192,15 +241,46 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     const uint32_t n = st->n_main, nt = n_tiles(d);
     const int nc = d.nc;
     const int nbits = 32 - __clz((uint32_t)nc);  // keys 0 .. nc (nc marks a hole)
-    uint32_t* run = reinterpret_cast<uint32_t*>(smem) + (size_t)wv * (size_t)(nc + 1);
+    // run[w][c - lo]: cursor of wave w for cell c
+    uint32_t* run = reinterpret_cast<uint32_t*>(smem);
     const int src = st->buf, dst = src ^ 1;
-    const int32_t* cell = d.cell[src];
-    for (uint32_t t = gw; t < nt; t += nw) {
-      // per-cell cursor = first destination of this tile's items of that cell
-      const int lo = d.tile_rng[2 * t], hi = d.tile_rng[2 * t + 1];
-      for (int c = lo + lane; c <= hi; c += 64) run[c] = d.hist[(size_t)c * nt + t];
-      const uint32_t b = t * (uint32_t)kSortTile;
-      const uint32_t e = min(n, b + (uint32_t)kSortTile);
+    const Gp<int32_t>* cell = gptr(d.cell[src]);
+    const Gp<P>* s_off = gptr(d.off[src]);
+    const Gp<P>* s_vx = gptr(d.vx[src]);
+    const Gp<P>* s_vy = gptr(d.vy[src]);
+    const Gp<P>* s_vz = gptr(d.vz[src]);
+    const Gp<uint32_t>* s_id = gptr(d.id[src]);
+    Gp<int32_t>* d_cell = gptr(d.cell[dst]);
+    Gp<P>* d_off = gptr(d.off[dst]);
+    Gp<P>* d_vx = gptr(d.vx[dst]);
+    Gp<P>* d_vy = gptr(d.vy[dst]);
+    Gp<P>* d_vz = gptr(d.vz[dst]);
+    Gp<uint32_t>* d_id = gptr(d.id[dst]);
+    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+      const int lo = gptr(d.tile_rng)[2 * t], hi = gptr(d.tile_rng)[2 * t + 1];
+      const int span = hi - lo + 1;  // 0 for a tile of holes only
+      const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
+      const uint32_t e = min(n, b + kQuarter);
+      uint32_t* myrun = run + wv * stride;
+      // counts of this wave's quarter
+      for (int c = lane; c < span; c += 64) myrun[c] = 0u;
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t i = b + (uint32_t)lane; i < e; i += 64u) {
+        const int c = cell[i];
+        if (c >= 0) atomicAdd(&myrun[c - lo], 1u);
+      }
+      __syncthreads();
+      // cursors: the tile's first slot for the cell, then the earlier waves
+      for (int c = threadIdx.x; c < span; c += kThreads) {
+        uint32_t r = gptr(d.hist)[(size_t)(lo + c) * nt + t];
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+          const uint32_t k = run[w * stride + c];
+          run[w * stride + c] = r;
+          r += k;
+        }
+      }
+      __syncthreads();
       constexpr int R = 4;  // rounds of 64 items whose loads are issued together
       for (uint32_t r = b; r < e; r += 64u * R) {
         int key[R];
@@ -213,11 +293,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
           if (i < e) {
             const int c = cell[i];
             key[q] = c >= 0 ? c : nc;
-            o_[q] = d.off[src][i];
-            x_[q] = d.vx[src][i];
-            y_[q] = d.vy[src][i];
-            z_[q] = d.vz[src][i];
-            id_[q] = d.id[src][i];
+            o_[q] = s_off[i];
+            x_[q] = s_vx[i];
+            y_[q] = s_vy[i];
+            z_[q] = s_vz[i];
+            id_[q] = s_id[i];
           }
         }
         uint32_t dest[R];
@@ -237,8 +317,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
           const uint32_t cntk = (uint32_t)__popcll(peers);
           dest[q] = 0;
           if (k < nc) {
-            const uint32_t base = run[k];
-            if (rank == 0) run[k] = base + cntk;
+            const uint32_t base = myrun[k - lo];
+            if (rank == 0) myrun[k - lo] = base + cntk;
             dest[q] = base + rank;
           }
         }
@@ -246,15 +326,16 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
         for (int q = 0; q < R; ++q) {
           if (key[q] < nc) {
             const uint32_t o = dest[q];
-            d.cell[dst][o] = key[q];
-            d.off[dst][o] = o_[q];
-            d.vx[dst][o] = x_[q];
-            d.vy[dst][o] = y_[q];
-            d.vz[dst][o] = z_[q];
-            d.id[dst][o] = id_[q];
+            d_cell[o] = key[q];
+            d_off[o] = o_[q];
+            d_vx[o] = x_[q];
+            d_vy[o] = y_[q];
+            d_vz[o] = z_[q];
+            d_id[o] = id_[q];
           }
         }
       }
+      __syncthreads();  // cursors are rewritten for the next tile
     }
   }
 }
@@ -276,11 +357,11 @@ template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
   const size_t lds = (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u;
   hipLaunchKernelGGL(k_sort_clear<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
-  hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D);
+  hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_scan_reduce<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
   hipLaunchKernelGGL(k_scan_top<P>, dim3(D), dim3(kThreads), 0, s, d_dev);
   hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
-  hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D);
+  hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
   return hipGetLastError();
 }
