@@ -16,6 +16,7 @@ constexpr int kSub = 64 * kPerThread;  // particles of one wave in a chunk (a su
 constexpr int kSeeMax = 4096;      // secondaries per wall per step
 constexpr int kMaxCells = 4096;    // cells per discharge
 constexpr int kMaxNodes = kMaxCells + 1;
+constexpr int kMaxSegs = 4096;    // particle workgroups of one electron launch
 constexpr int kSphereTries = 64;   // bound of the rejection loops
 constexpr int kSortTile = 4096;    // items per sort tile (one wave)
 constexpr int kFinThreads = 1024;  // field/finalize workgroup
@@ -32,6 +33,8 @@ struct State {
   uint32_t n_kids;       // children created this step
   uint32_t n_see[2];     // secondaries emitted this step (left, right)
   uint32_t n_chunks;     // sub-chunks processed by the last electron launch
+  uint32_t seg_off;      // launch-wide index of this discharge's first chunk (last launch)
+  uint32_t seg_per;      // chunks per particle workgroup (last launch)
   int32_t buf;           // current particle buffer (0/1)
   int32_t cbuf;          // cnt buffer holding the deposit of the current step
   int32_t error;         // sticky error (HD_E* code)
@@ -86,7 +89,8 @@ struct Disch {
   P* kvy;
   P* kvz;
   uint32_t* chunk_kids;  // [cap_sub] children per sub-chunk
-  uint32_t* chunk_base;  // [cap_sub] their offset among the step's children
+  uint32_t* chunk_base;  // [cap_sub] their offset among the children of the sub-chunk's workgroup
+  uint32_t* seg;         // [kMaxSegs] children per particle workgroup, then their offsets
   // secondaries of this step: side s at [s*kSeeMax, ...)
   int32_t* sc;
   P* soff;

@@ -163,7 +163,7 @@ struct Layout {
 template <class P>
 struct Offsets {
   size_t cell[2], off[2], vx[2], vy[2], vz[2], id[2];
-  size_t kc, koff, kvx, kvy, kvz, chunk_kids, chunk_base;
+  size_t kc, koff, kvx, kvy, kvz, chunk_kids, chunk_base, seg;
   size_t sc, soff, svx, svy, svz;
   size_t cnt[2], ion_src, ni, gam, phi, E, Ep, scratch, acc_cnt, acc_ni, eedf;
   size_t ip, tab, hist, parts, tile_rng, st, volt;
@@ -191,6 +191,7 @@ Offsets<P> layout(const hd_params& p, int64_t volt_len) {
   o.kvz = L.take(C * sizeof(P));
   o.chunk_kids = L.take(C / kSub * 4);
   o.chunk_base = L.take(C / kSub * 4);
+  o.seg = L.take((size_t)kMaxSegs * 4);
   o.sc = L.take(2 * kSeeMax * 4);
   o.soff = L.take(2 * kSeeMax * sizeof(P));
   o.svx = L.take(2 * kSeeMax * sizeof(P));
@@ -539,6 +540,7 @@ struct Batch : BatchBase {
     d.kvz = (P*)(b + o.kvz);
     d.chunk_kids = (uint32_t*)(b + o.chunk_kids);
     d.chunk_base = (uint32_t*)(b + o.chunk_base);
+    d.seg = (uint32_t*)(b + o.seg);
     d.sc = (int32_t*)(b + o.sc);
     d.soff = (P*)(b + o.soff);
     d.svx = (P*)(b + o.svx);
@@ -609,7 +611,7 @@ struct Batch : BatchBase {
     int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     const int cus = prop.multiProcessorCount;
-    grid_e = D + cus * occ;
+    grid_e = D + std::min(cus * occ, (int)kMaxSegs);
     grid_a = cus;
     grid_s = cus * 4;
     // per-discharge state
@@ -1005,7 +1007,7 @@ struct Server : ServerBase {
     HD_TRY(finalize_set_lds<P>(nn_max));
     const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, S);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
-    grid_e = S + prop.multiProcessorCount * occ;
+    grid_e = S + std::min(prop.multiProcessorCount * occ, (int)kMaxSegs);
     grid_a = prop.multiProcessorCount;
     grid_s = prop.multiProcessorCount * 4;
     HD_TRY(hipMalloc((void**)&d_idle, sizeof(State)));

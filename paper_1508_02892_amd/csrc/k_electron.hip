@@ -401,9 +401,36 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   }
 }
 
+// Block-wide exclusive scan of one value per thread (kElecThreads); writes
+// the total to *total.  sh: kWaves words of LDS.
+__device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const uint32_t s = sh[w];
+    if (w < wv) base += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// Chunks [lc0, lc1) of discharge d by particle workgroup pb; chunk0 is the
+// launch-wide index of the discharge's first chunk and per the chunks per
+// workgroup.
 template <class P>
 __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned char* smem,
-                        const Lds& L) {
+                        const Lds& L, uint32_t pb, uint32_t chunk0, uint32_t per) {
   const int tid = threadIdx.x, wv = tid >> 6;
   P* tab = reinterpret_cast<P*>(smem + L.tab);
   P* ep = reinterpret_cast<P*>(smem + L.ep);
@@ -483,6 +510,30 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->overflow), (unsigned long long)ctr[tid]);
   if (tid == kCtrPushed && ctr[tid])
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->pushed), (unsigned long long)ctr[tid]);
+  // offsets of the segment's children relative to the segment (exclusive
+  // scan of the sub-chunk counts written above) and the segment's total
+  {
+    __shared__ uint32_t sh[kWaves];
+    const uint32_t k0 = lc0 * (uint32_t)kWaves, k1 = lc1 * (uint32_t)kWaves;
+    const Gp<uint32_t>* kids = gptr(d.chunk_kids);
+    Gp<uint32_t>* kbase = gptr(d.chunk_base);
+    uint32_t carry = 0;
+    for (uint32_t kb = k0; kb < k1; kb += (uint32_t)kElecThreads) {
+      const uint32_t k = kb + (uint32_t)tid;
+      const uint32_t v = k < k1 ? kids[k] : 0u;
+      uint32_t tot;
+      const uint32_t ex = wg_scan(v, sh, &tot);
+      if (k < k1) kbase[k] = carry + ex;
+      carry += tot;
+    }
+    if (tid == 0) {
+      gptr(d.seg)[pb] = carry;
+      if (lc0 == 0) {
+        st->seg_off = chunk0;
+        st->seg_per = per;
+      }
+    }
+  }
   __syncthreads();
 }
 
@@ -638,7 +689,7 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
   while (pre[di + 1] <= g0) ++di;
   while (g0 < g1) {
     const uint32_t end = min(g1, pre[di + 1]);
-    segment<P>(ds[di], g0 - pre[di], end - pre[di], smem, L);
+    segment<P>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
     g0 = end;
     ++di;
   }

@@ -1,5 +1,6 @@
 // End of a time step and field of the next one, one workgroup per discharge:
-// offsets of the staged ionization children (exclusive scan over chunks),
+// offsets of the staged ionization children (exclusive scan over the electron
+// launch's per-workgroup totals),
 // ion-induced secondary emission (Sec. II.D), ion sources of the step
 // (G^n in Eq 2.4), run averages, append bookkeeping, then the Poisson solve
 // of the coupling (Sec. II.D) for the next step.  A second kernel appends the
@@ -405,9 +406,6 @@ __host__ __device__ constexpr size_t finalize_lds_doubles(int nn_max) {
 
 // Nodes per finalize thread (at most 4097 nodes).
 constexpr int kNodeSlots = (kMaxNodes + kFinThreads - 1) / kFinThreads;
-// Child counts per thread per scan tile, in 16-byte vectors.
-constexpr int kScanVec = 8;
-constexpr uint32_t kScanTile = (uint32_t)kFinThreads * kScanVec * 4u;
 
 // End of a step (field_only == 0) and the field of the next one.  Global
 // inputs are loaded together up front so that the kernel pays few memory
@@ -439,19 +437,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   Gp<int64_t>* cn = gptr(d.cnt[cur]);
   const Gp<double>* volt = gptr(d.volt);
   const double V = (step1 < d.volt_len) ? volt[step1] : 0.0;
-  // first tile of child counts (whole chunks, a multiple of 4 sub-chunks)
-  const uint32_t nch =
-      field_only ? 0u : (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile * (uint32_t)(kTile / kSub);
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  const Gp<u32x4>* kids4 = reinterpret_cast<const Gp<u32x4>*>(gptr(d.chunk_kids));
-  u32x4 kv[kScanVec];
-  auto load_tile = [&](uint32_t t0) {
-    const uint32_t q0 = (t0 >> 2) + (uint32_t)tid * kScanVec;
-#pragma unroll
-    for (int q = 0; q < kScanVec; ++q)
-      kv[q] = (4u * (q0 + (uint32_t)q) < nch) ? kids4[q0 + (uint32_t)q] : u32x4{0u, 0u, 0u, 0u};
-  };
-  load_tile(0);
+  // the electron launch's per-workgroup child totals of this discharge
+  const uint32_t nchunk = field_only ? 0u : (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile;
+  const uint32_t nch = nchunk * (uint32_t)(kTile / kSub);  // sub-chunks
+  const uint32_t seg_off = st->seg_off, seg_per = st->seg_per;
+  const uint32_t pb0 = nchunk ? seg_off / seg_per : 0u;
+  const uint32_t pb1 = nchunk ? (seg_off + nchunk - 1u) / seg_per + 1u : 0u;  // exclusive
+  Gp<uint32_t>* gseg = gptr(d.seg);
+  uint32_t segv = (pb0 + (uint32_t)tid < pb1) ? gseg[pb0 + (uint32_t)tid] : 0u;
   // per-node inputs: deposit to LDS, n_i with this step's ion sources
   const Gp<double>* gni = gptr(d.ni);
   const Gp<int64_t>* gsrc = gptr(d.ion_src);
@@ -475,27 +468,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     for (int i = tid; i < f.size; i += kFinThreads) T[i] = gtab[i];
   }
   if (!field_only) {
-    // offsets of the staged children
+    // offsets of the staged children: exclusive scan of the workgroup totals
     uint32_t n_kids = 0;
-    Gp<u32x4>* base4 = reinterpret_cast<Gp<u32x4>*>(gptr(d.chunk_base));
-    for (uint32_t t0 = 0; t0 < nch; t0 += kScanTile) {
-      if (t0 > 0) load_tile(t0);
-      uint32_t loc = 0;
-#pragma unroll
-      for (int q = 0; q < kScanVec; ++q) loc += (kv[q].x + kv[q].y) + (kv[q].z + kv[q].w);
+    for (uint32_t t0 = pb0; t0 < pb1; t0 += (uint32_t)kFinThreads) {
+      if (t0 > pb0) segv = (t0 + (uint32_t)tid < pb1) ? gseg[t0 + (uint32_t)tid] : 0u;
       uint32_t tot;
-      uint32_t run = n_kids + block_scan(loc, sh, &tot);
-      const uint32_t q0 = (t0 >> 2) + (uint32_t)tid * kScanVec;
-#pragma unroll
-      for (int q = 0; q < kScanVec; ++q) {
-        u32x4 b;
-        b.x = run;
-        b.y = b.x + kv[q].x;
-        b.z = b.y + kv[q].y;
-        b.w = b.z + kv[q].z;
-        run = b.w + kv[q].w;
-        if (4u * (q0 + (uint32_t)q) < nch) base4[q0 + (uint32_t)q] = b;
-      }
+      const uint32_t ex = block_scan(segv, sh, &tot);
+      if (t0 + (uint32_t)tid < pb1) gseg[t0 + (uint32_t)tid] = n_kids + ex;
       n_kids += tot;
     }
     __syncthreads();  // CN complete before emission deposits into it
@@ -601,7 +580,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
 }
 
 // Append this step's children (in sub-chunk order, i.e. parent order), then the
-// left and right secondaries, with consecutive ids.  Each wave takes 64
+// left and right secondaries, with consecutive ids.  A sub-chunk's children
+// start at its workgroup's offset (from the finalize scan) plus its own offset
+// inside the workgroup (from the electron launch).  Each wave takes 64
 // consecutive sub-chunks and copies the children of each non-empty one with
 // all of its lanes.
 template <class P>
@@ -630,14 +611,18 @@ __global__ __launch_bounds__(kThreads) void k_append(const Disch<P>* __restrict_
     const int buf = st->buf;
     const uint32_t nch = st->n_chunks, base = st->append_base, idb = st->id_base;
     const uint32_t nk = st->n_kids, n0 = st->n_see[0], n1 = st->n_see[1];
+    const uint32_t soff = st->seg_off, sper = st->seg_per;
     const Gp<uint32_t>* kids = gptr(d.chunk_kids);
     const Gp<uint32_t>* cbase = gptr(d.chunk_base);
+    const Gp<uint32_t>* sbase = gptr(d.seg);
     for (uint32_t k0 = wave * 64u; k0 < nch; k0 += nwaves * 64u) {
       const uint32_t k = k0 + lane;
       const uint32_t cnt = k < nch ? kids[k] : 0u;
       uint64_t live = __ballot(cnt != 0u);
       if (live == 0) continue;
-      const uint32_t cb = cnt ? cbase[k] : 0u;
+      // offset = the workgroup's among all children + the sub-chunk's in it
+      const uint32_t cb =
+          cnt ? sbase[(soff + k / (uint32_t)(kTile / kSub)) / sper] + cbase[k] : 0u;
       while (live) {
         const int l = __ffsll((unsigned long long)live) - 1;
         live &= live - 1;

@@ -60,14 +60,22 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
       int lo = nc, hi = -1;
       const uint32_t b = t * (uint32_t)kSortTile;
       const uint32_t e = min(n, b + (uint32_t)kSortTile);
-      // 4 consecutive slots per lane per 256-slot round (slot counts are
-      // multiples of 4 up to the capacity, so the vector load stays inside)
-      for (uint32_t i = b + 4u * (uint32_t)lane; i < e; i += 256u) {
-        int32_t c4[4];
-        gld4(cell + i, c4);
+      // 4 consecutive slots per lane per 256-slot round, all 16 rounds of
+      // the tile loaded before they are counted (the capacity is a multiple
+      // of the tile, so every vector load stays inside the array)
+      constexpr int kRounds = kSortTile / 256;
+      int32_t c4[kRounds][4];
+#pragma unroll
+      for (int q = 0; q < kRounds; ++q) {
+        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+        if (i < e) gld4(cell + i, c4[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < kRounds; ++q) {
+        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const int c = c4[k];
+          const int c = c4[q][k];
           if (i + (uint32_t)k < e && c >= 0) {
             atomicAdd(&h[c], 1u);
             lo = min(lo, c);
@@ -265,23 +273,42 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
       // counts of this wave's quarter
       for (int c = lane; c < span; c += 64) myrun[c] = 0u;
       __builtin_amdgcn_wave_barrier();
-      for (uint32_t i = b + (uint32_t)lane; i < e; i += 64u) {
-        const int c = cell[i];
-        if (c >= 0) atomicAdd(&myrun[c - lo], 1u);
-      }
-      __syncthreads();
-      // cursors: the tile's first slot for the cell, then the earlier waves
-      for (int c = threadIdx.x; c < span; c += kThreads) {
-        uint32_t r = gptr(d.hist)[(size_t)(lo + c) * nt + t];
+      {
+        constexpr int kRounds = (int)(kQuarter / 256u);
+        int32_t c4[kRounds][4];
 #pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-          const uint32_t k = run[w * stride + c];
-          run[w * stride + c] = r;
-          r += k;
+        for (int q = 0; q < kRounds; ++q) {
+          const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+          if (i < e) gld4(cell + i, c4[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < kRounds; ++q) {
+          const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (i + (uint32_t)k < e && c4[q][k] >= 0) atomicAdd(&myrun[c4[q][k] - lo], 1u);
         }
       }
       __syncthreads();
-      constexpr int R = 4;  // rounds of 64 items whose loads are issued together
+      // cursors: the tile's first slot for the cell, then the earlier waves
+      // (only cells present in the tile: the range can be wide and sparse)
+      for (int c = threadIdx.x; c < span; c += kThreads) {
+        uint32_t k[kWavesPerBlock], tot = 0;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+          k[w] = run[w * stride + c];
+          tot += k[w];
+        }
+        if (tot == 0) continue;
+        uint32_t r = gptr(d.hist)[(size_t)(lo + c) * nt + t];
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+          run[w * stride + c] = r;
+          r += k[w];
+        }
+      }
+      __syncthreads();
+      constexpr int R = 8;  // rounds of 64 items whose loads are issued together
       for (uint32_t r = b; r < e; r += 64u * R) {
         int key[R];
         P o_[R], x_[R], y_[R], z_[R];
