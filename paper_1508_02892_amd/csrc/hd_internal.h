@@ -35,6 +35,8 @@ struct State {
   uint32_t n_chunks;     // sub-chunks processed by the last electron launch
   uint32_t seg_off;      // launch-wide index of this discharge's first chunk (last launch)
   uint32_t seg_per;      // chunks per particle workgroup (last launch)
+  int32_t fin_ready;     // set by the end-of-step workgroup once its offsets are published
+  uint32_t app_done;     // append workgroups finished with this discharge (this launch)
   int32_t buf;           // current particle buffer (0/1)
   int32_t cbuf;          // cnt buffer holding the deposit of the current step
   int32_t error;         // sticky error (HD_E* code)
@@ -122,9 +124,7 @@ struct Disch {
 namespace hd {
 template <class P>
 hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_max,
-                           hipStream_t s);
-template <class P>
-hipError_t launch_append(const Disch<P>* d_dev, int D, int grid, hipStream_t s);
+                           int app_blocks, hipStream_t s);
 template <class P>
 hipError_t launch_diag(int64_t n, const P* a, const P* b, P* out, hipStream_t s);
 }  // namespace hd

@@ -612,7 +612,7 @@ struct Batch : BatchBase {
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     const int cus = prop.multiProcessorCount;
     grid_e = D + std::min(cus * occ, (int)kMaxSegs);
-    grid_a = cus;
+    grid_a = std::max(1, cus / 4);
     grid_s = cus * 4;
     // per-discharge state
     for (int i = 0; i < n; ++i) {
@@ -624,7 +624,7 @@ struct Batch : BatchBase {
     }
     HD_TRY(hipMalloc((void**)&d_desc, sizeof(Disch<P>) * D));
     HD_TRY(upload_desc());
-    HD_TRY(launch_finalize<P>(d_desc, D, 1, nn_max, stream));
+    HD_TRY(launch_finalize<P>(d_desc, D, 1, nn_max, 0, stream));
     HD_TRY(hipStreamSynchronize(stream));
     return HD_OK;
   }
@@ -674,9 +674,7 @@ struct Batch : BatchBase {
   hipError_t enqueue_step(bool with_sort) {
     hipError_t e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
     if (e != hipSuccess) return e;
-    e = launch_finalize<P>(d_desc, D, 0, nn_max, stream);
-    if (e != hipSuccess) return e;
-    e = launch_append<P>(d_desc, D, grid_a, stream);
+    e = launch_finalize<P>(d_desc, D, 0, nn_max, grid_a, stream);
     if (e != hipSuccess) return e;
     if (with_sort) e = launch_sort_impl<P>(d_desc, D, grid_s, nc_max, stream);
     return e;
@@ -847,10 +845,10 @@ struct Batch : BatchBase {
         err = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
       if (err == hipSuccess) err = hipEventRecord(e[1], stream);
       if (err == hipSuccess) err = hipEventRecord(e[2], stream);
-      if (err == hipSuccess) err = launch_finalize<P>(d_desc, D, 0, nn_max, stream);
+      if (err == hipSuccess) err = launch_finalize<P>(d_desc, D, 0, nn_max, grid_a, stream);
       if (err == hipSuccess) err = hipEventRecord(e[3], stream);
+      // the append runs inside the end-of-step launch: its slot reads ~0
       if (err == hipSuccess) err = hipEventRecord(e[4], stream);
-      if (err == hipSuccess) err = launch_append<P>(d_desc, D, grid_a, stream);
       if (err == hipSuccess) err = hipEventRecord(e[5], stream);
       if (err == hipSuccess) err = hipEventRecord(e[6], stream);
       if (err == hipSuccess && srt) err = launch_sort_impl<P>(d_desc, D, grid_s, nc_max, stream);
@@ -977,9 +975,10 @@ struct Server : ServerBase {
     if (own_stream) (void)hipStreamDestroy(own_stream);
   }
 
-  Disch<P> idle_entry() const {
+  // An empty slot: no cells, no particles, its own idle state.
+  Disch<P> idle_entry(int slot) const {
     Disch<P> e{};
-    e.st = d_idle;
+    e.st = d_idle + slot;
     return e;
   }
 
@@ -1008,15 +1007,16 @@ struct Server : ServerBase {
     const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, S);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     grid_e = S + std::min(prop.multiProcessorCount * occ, (int)kMaxSegs);
-    grid_a = prop.multiProcessorCount;
+    grid_a = std::max(1, prop.multiProcessorCount / 4);
     grid_s = prop.multiProcessorCount * 4;
-    HD_TRY(hipMalloc((void**)&d_idle, sizeof(State)));
-    HD_TRY(hipMemset(d_idle, 0, sizeof(State)));
+    HD_TRY(hipMalloc((void**)&d_idle, sizeof(State) * (size_t)S));
+    HD_TRY(hipMemset(d_idle, 0, sizeof(State) * (size_t)S));
     HD_TRY(hipMalloc((void**)&d_desc, sizeof(Disch<P>) * S));
     hs.resize(S);
     slot_job.assign(S, nullptr);
     slot_done.assign(S, 0);
-    std::vector<Disch<P>> v(S, idle_entry());
+    std::vector<Disch<P>> v;
+    for (int i = 0; i < S; ++i) v.push_back(idle_entry(i));
     HD_TRY(hipMemcpy(d_desc, v.data(), sizeof(Disch<P>) * S, hipMemcpyHostToDevice));
     // capture one interval of sort_every steps over all slots
     hipGraph_t g = nullptr;
@@ -1024,8 +1024,7 @@ struct Server : ServerBase {
     hipError_t e = hipSuccess;
     for (int s = 0; s < cfg.sort_every && e == hipSuccess; ++s) {
       e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
-      if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, stream);
-      if (e == hipSuccess) e = launch_append<P>(d_desc, S, grid_a, stream);
+      if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, grid_a, stream);
       if (e == hipSuccess && s == cfg.sort_every - 1)
         e = launch_sort_impl<P>(d_desc, S, grid_s, nc_max, stream);
     }
@@ -1093,7 +1092,7 @@ struct Server : ServerBase {
     int rc = B::upload_state(h, pr, stream);
     if (rc) return rc;
     HD_TRY(hipMemcpyAsync(d_desc + slot, &h.dd, sizeof(Disch<P>), hipMemcpyHostToDevice, stream));
-    HD_TRY(launch_finalize<P>(d_desc + slot, 1, 1, nn_max, stream));
+    HD_TRY(launch_finalize<P>(d_desc + slot, 1, 1, nn_max, 0, stream));
     const int64_t n = job->n_steps;
     HD_TRY(hipMemcpyAsync(&h.dd.st->steps_left, &n, sizeof(int64_t), hipMemcpyHostToDevice,
                           stream));
@@ -1132,7 +1131,7 @@ struct Server : ServerBase {
     m.eedf_counts = r.eedf_counts.data();
     m.eedf = r.eedf.data();
     const int rc = B::fill_moments(h, st, &m);
-    const Disch<P> ie = idle_entry();
+    const Disch<P> ie = idle_entry(slot);
     HD_TRY(hipMemcpy(d_desc + slot, &ie, sizeof(Disch<P>), hipMemcpyHostToDevice));
     (void)hipFree(h.base);
     h.base = nullptr;

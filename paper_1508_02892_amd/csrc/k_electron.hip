@@ -211,10 +211,10 @@ __device__ __forceinline__ void drain(const Disch<P>& d, const Seg<P>& g, QEntry
 // probability exceeds R (-1: null collision).  All K comparisons are made and
 // the first true one is taken, so the loop has the same trip count on every
 // lane.
-template <class P>
+template <class P, int KC>
 __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy, P vz,
                                               bool& ovf) {
-  const int K = g.K;
+  const int K = KC > 0 ? KC : g.K;  // KC: channel count fixed at compile time (0: any)
   const P v2 = (vx * vx + vy * vy) + vz * vz;
   const P en = g.KE * v2;
   const P sx = en * g.inv_dE;
@@ -230,11 +230,25 @@ __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy,
   }
   auto scan = [&](auto ra) {
     uint32_t hit = 0;
-    for (int k = 0; k < K; ++k) {
-      const P pa = ra[k];
-      const P pb = ra[K + k];
-      const P pk = pa + t * (pb - pa);
-      hit |= (u0 < pk ? 1u : 0u) << k;
+    if constexpr (KC > 0) {
+      P pa[KC], pb[KC];
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        pa[k] = ra[k];
+        pb[k] = ra[KC + k];
+      }
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        const P pk = pa[k] + t * (pb[k] - pa[k]);
+        hit |= (u0 < pk ? 1u : 0u) << k;
+      }
+    } else {
+      for (int k = 0; k < K; ++k) {
+        const P pa = ra[k];
+        const P pb = ra[K + k];
+        const P pk = pa + t * (pb - pa);
+        hit |= (u0 < pk ? 1u : 0u) << k;
+      }
     }
     return hit ? __builtin_ctz(hit) : -1;
   };
@@ -251,7 +265,7 @@ struct WaveCounts {
 // One wave's 256 slots of a chunk: push, removal and write-back, then the
 // null-collision test and channel, the deposit at x^{n+1}; collisions are
 // queued.  No workgroup barrier is involved.
-template <class P>
+template <class P, int KC>
 __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEntry<P>* q,
                            uint32_t& qn, WaveCounts& wc) {
   const int tid = threadIdx.x;
@@ -312,7 +326,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
       u0 = (P)u01_f64(w0, w1);
     ch[j] = -1;
     bool ovf = false;
-    if (alive[j] && u0 < g.Pmax) ch[j] = select_channel<P>(g, u0, vx[j], vy[j], vz[j], ovf);
+    if (alive[j] && u0 < g.Pmax) ch[j] = select_channel<P, KC>(g, u0, vx[j], vy[j], vz[j], ovf);
     wc.ovf += (uint32_t)__popcll(__ballot(ovf));
   }
   // deposit at x^{n+1}.  W0 + W1 = 2^32 per particle, so a run of m
@@ -480,7 +494,10 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   __syncthreads();
   uint32_t qn = 0;
   WaveCounts wc;
-  for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P>(d, g, lc, q, qn, wc);
+  if (g.K == 3)  // elastic, excitation, ionization: the common case, unrolled
+    for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P, 3>(d, g, lc, q, qn, wc);
+  else
+    for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P, 0>(d, g, lc, q, qn, wc);
   if (qn) drain<P>(d, g, q, qn, qn);
   if ((tid & 63) == 0) {
     if (wc.absl) atomicAdd(&g.ctr[kCtrAbsL], wc.absl);

@@ -3,8 +3,9 @@
 // launch's per-workgroup totals),
 // ion-induced secondary emission (Sec. II.D), ion sources of the step
 // (G^n in Eq 2.4), run averages, append bookkeeping, then the Poisson solve
-// of the coupling (Sec. II.D) for the next step.  A second kernel appends the
-// children and secondaries to the particle arrays in canonical order.
+// of the coupling (Sec. II.D) for the next step.  Further workgroups of the
+// same launch append the children and secondaries to the particle arrays in
+// canonical order while the field is solved.
 #include "hd_device.h"
 
 namespace hd {
@@ -411,10 +412,113 @@ constexpr int kNodeSlots = (kMaxNodes + kFinThreads - 1) / kFinThreads;
 // inputs are loaded together up front so that the kernel pays few memory
 // round trips: the state, this step's deposit, n_i and the ion sources,
 // the first tile of child counts, the factor tables and V(t).
+// ---- append, in the workgroups of the end-of-step launch after the first D
+// Append this step's children (in sub-chunk order, i.e. parent order), then the
+// left and right secondaries, with consecutive ids.  A sub-chunk's children
+// start at its workgroup's offset (from the end-of-step scan) plus its own
+// offset inside the workgroup (from the electron launch).  Each wave takes 64
+// consecutive sub-chunks and copies the children of each non-empty one with
+// all of its lanes.  The workgroups wait (bounded) for the discharge's
+// end-of-step workgroup to publish its offsets; the last one to finish
+// re-arms the flag for the next launch.
+constexpr int kSpinMax = 1 << 17;  // ~0.2 s: a backstop, never reached in a correct run
+
+__device__ __forceinline__ void publish_ready(State* st) {
+  __hip_atomic_store(&st->fin_ready, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <class P>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __restrict__ ds,
+__device__ __forceinline__ void append_one(const Disch<P>& d, int buf, uint32_t src_c, uint32_t dst,
+                                           uint32_t id, const Gp<int32_t>* sc, const Gp<P>* so,
+                                           const Gp<P>* sx, const Gp<P>* sy, const Gp<P>* sz) {
+  gptr(d.cell[buf])[dst] = sc[src_c];
+  gptr(d.off[buf])[dst] = so[src_c];
+  gptr(d.vx[buf])[dst] = sx[src_c];
+  gptr(d.vy[buf])[dst] = sy[src_c];
+  gptr(d.vz[buf])[dst] = sz[src_c];
+  gptr(d.id[buf])[dst] = id;
+}
+
+template <class P>
+__device__ void append_blocks(const Disch<P>* __restrict__ ds, int D) {
+  __shared__ int ok;
+  __shared__ int gave_up;  // a wait timed out: wait for no further discharge
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  if (tid == 0) gave_up = 0;
+  const uint32_t ab = blockIdx.x - (uint32_t)D, nab = gridDim.x - (uint32_t)D;
+  const uint32_t wave = (ab * (uint32_t)kFinThreads + tid) >> 6;
+  const uint32_t nwaves = nab * (uint32_t)(kFinThreads / 64);
+  const uint32_t gid = ab * (uint32_t)kFinThreads + tid, gsz = nab * (uint32_t)kFinThreads;
+  for (int di = 0; di < D; ++di) {
+    const Disch<P>& d = ds[di];
+    State* st = d.st;
+    if (tid == 0) {
+      // relaxed polling (an acquire per poll would invalidate the caches of
+      // the whole XCD each time), then one acquire for the workgroup
+      int it = gave_up ? kSpinMax : 0;
+      while (it < kSpinMax &&
+             __hip_atomic_load(&st->fin_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        __builtin_amdgcn_s_sleep(2);
+        ++it;
+      }
+      ok = it < kSpinMax;
+      if (!ok) gave_up = 1;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (!ok) {
+      if (tid == 0) st->error = -6;  // the end-of-step workgroup never published
+    } else if (st->append_pending) {
+      const int buf = st->buf;
+      const uint32_t nch = st->n_chunks, base = st->append_base, idb = st->id_base;
+      const uint32_t nk = st->n_kids, n0 = st->n_see[0], n1 = st->n_see[1];
+      const uint32_t soff = st->seg_off, sper = st->seg_per;
+      const Gp<uint32_t>* kids = gptr(d.chunk_kids);
+      const Gp<uint32_t>* cbase = gptr(d.chunk_base);
+      const Gp<uint32_t>* sbase = gptr(d.seg);
+      for (uint32_t k0 = wave * 64u; k0 < nch; k0 += nwaves * 64u) {
+        const uint32_t k = k0 + lane;
+        const uint32_t cnt = k < nch ? kids[k] : 0u;
+        uint64_t live = __ballot(cnt != 0u);
+        if (live == 0) continue;
+        // offset = the workgroup's among all children + the sub-chunk's in it
+        const uint32_t cb =
+            cnt ? sbase[(soff + k / (uint32_t)(kTile / kSub)) / sper] + cbase[k] : 0u;
+        while (live) {
+          const int l = __ffsll((unsigned long long)live) - 1;
+          live &= live - 1;
+          const uint32_t n = (uint32_t)__shfl((int)cnt, l, 64);
+          const uint32_t b = (uint32_t)__shfl((int)cb, l, 64);
+          const uint32_t src0 = (k0 + (uint32_t)l) * (uint32_t)kSub;
+          for (uint32_t t = lane; t < n; t += 64u)
+            append_one<P>(d, buf, src0 + t, base + b + t, idb + b + t, gptr(d.kc), gptr(d.koff),
+                          gptr(d.kvx), gptr(d.kvy), gptr(d.kvz));
+        }
+      }
+      for (uint32_t t = gid; t < n0 + n1; t += gsz) {
+        const uint32_t src = t < n0 ? t : (uint32_t)kSeeMax + (t - n0);
+        append_one<P>(d, buf, src, base + nk + t, idb + nk + t, gptr(d.sc), gptr(d.soff),
+                      gptr(d.svx), gptr(d.svy), gptr(d.svz));
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      if (atomicAdd(&st->app_done, 1u) == nab - 1u) {  // the last: re-arm for the next launch
+        st->app_done = 0u;
+        __hip_atomic_store(&st->fin_ready, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+template <class P>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __restrict__ ds, int D,
                                                           int field_only) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if ((int)blockIdx.x >= D) {
+    append_blocks<P>(ds, D);
+    return;
+  }
   const Disch<P>& d = ds[blockIdx.x];
   Gp<State>* st = gptr(d.st);
   const int tid = threadIdx.x, nn = d.nn, nc = d.nc, m = nc - 1;
@@ -424,14 +528,56 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   double* T = red + 2 * kTriRed;
   __shared__ uint32_t sh[kWaves + 1];
   __shared__ uint32_t sh_see[2];
-  // state snapshot
+  // Global inputs are requested before any of them is used: the state, both
+  // deposit buffers (the state says which is this step's), n_i, the ion
+  // sources, the run sums of n_i and the Poisson factor tables.
   const int64_t steps_left = st->steps_left;
   const int64_t step0 = st->step;
   const int cbuf0 = st->cbuf;
   const uint32_t n_main = st->n_main;
   const uint32_t next_id = st->next_id;
+  const uint32_t seg_off = st->seg_off, seg_per = st->seg_per;
   const double wall_g = tid < 2 ? st->wall[tid] : 0.0;
-  if (!field_only && steps_left <= 0) return;
+  const Gp<int64_t>* gc0 = gptr(d.cnt[0]);
+  const Gp<int64_t>* gc1 = gptr(d.cnt[1]);
+  const Gp<double>* gni = gptr(d.ni);
+  const Gp<int64_t>* gsrc = gptr(d.ion_src);
+  Gp<double>* acc_ni = gptr(d.acc_ni);
+  int64_t c0v[kNodeSlots], c1v[kNodeSlots], srcv[kNodeSlots];
+  double n0v[kNodeSlots], accv[kNodeSlots];
+#pragma unroll
+  for (int u = 0; u < kNodeSlots; ++u) {
+    const int j = tid + u * kFinThreads;
+    c0v[u] = c1v[u] = srcv[u] = 0;
+    n0v[u] = accv[u] = 0.0;
+    if (j < nn) {
+      c0v[u] = gc0[j];
+      c1v[u] = gc1[j];
+      n0v[u] = gni[j];
+      if (!field_only) {
+        srcv[u] = gsrc[j];
+        accv[u] = acc_ni[j];
+      }
+    }
+  }
+  const PoisFac f = pois_fac(m);
+  Gp<double>* gtab = gptr(d.scratch);
+  constexpr int kTabSlots = (kFacMax + kFinThreads - 1) / kFinThreads;
+  double tv[kTabSlots];
+  if (!field_only) {
+#pragma unroll
+    for (int u = 0; u < kTabSlots; ++u) {
+      const int i = tid + u * kFinThreads;
+      tv[u] = i < f.size ? gtab[i] : 0.0;
+    }
+  }
+  if (!field_only && steps_left <= 0) {
+    if (tid == 0) {  // nothing completed: nothing to append
+      st->append_pending = 0;
+      publish_ready(d.st);
+    }
+    return;
+  }
   const int64_t step1 = field_only ? step0 : step0 + 1;
   const int cur = field_only ? cbuf0 : (cbuf0 ^ 1);
   Gp<int64_t>* cn = gptr(d.cnt[cur]);
@@ -440,32 +586,29 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   // the electron launch's per-workgroup child totals of this discharge
   const uint32_t nchunk = field_only ? 0u : (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile;
   const uint32_t nch = nchunk * (uint32_t)(kTile / kSub);  // sub-chunks
-  const uint32_t seg_off = st->seg_off, seg_per = st->seg_per;
   const uint32_t pb0 = nchunk ? seg_off / seg_per : 0u;
   const uint32_t pb1 = nchunk ? (seg_off + nchunk - 1u) / seg_per + 1u : 0u;  // exclusive
   Gp<uint32_t>* gseg = gptr(d.seg);
   uint32_t segv = (pb0 + (uint32_t)tid < pb1) ? gseg[pb0 + (uint32_t)tid] : 0u;
-  // per-node inputs: deposit to LDS, n_i with this step's ion sources
-  const Gp<double>* gni = gptr(d.ni);
-  const Gp<int64_t>* gsrc = gptr(d.ion_src);
+  // this step's deposit to LDS; n_i with this step's ion sources
   double niv[kNodeSlots];
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
     const int j = tid + u * kFinThreads;
     niv[u] = 0.0;
     if (j < nn) {
-      CN[j] = load_dev(&d.cnt[cur][j]);
-      const double n0 = gni[j];
-      niv[u] = field_only ? n0 : n0 + (double)gsrc[j] * scale_of(d, j);
+      CN[j] = cur ? c1v[u] : c0v[u];
+      niv[u] = field_only ? n0v[u] : n0v[u] + (double)srcv[u] * scale_of(d, j);
     }
   }
-  // factor tables of the Poisson solve
-  const PoisFac f = pois_fac(m);
-  Gp<double>* gtab = gptr(d.scratch);
   if (field_only) {
     if (tid == 0) pois_factor(f, T);
   } else {
-    for (int i = tid; i < f.size; i += kFinThreads) T[i] = gtab[i];
+#pragma unroll
+    for (int u = 0; u < kTabSlots; ++u) {
+      const int i = tid + u * kFinThreads;
+      if (i < f.size) T[i] = tv[u];
+    }
   }
   if (!field_only) {
     // offsets of the staged children: exclusive scan of the workgroup totals
@@ -493,7 +636,6 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     // ion sources of the step, the final deposit, run averages
     Gp<double>* wni = gptr(d.ni);
     Gp<int64_t>* wsrc = gptr(d.ion_src);
-    Gp<double>* acc_ni = gptr(d.acc_ni);
 #pragma unroll
     for (int u = 0; u < kNodeSlots; ++u) {
       const int j = tid + u * kFinThreads;
@@ -503,7 +645,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
         wsrc[j] = 0;
         cn[j] = c;
         atomicAdd(reinterpret_cast<unsigned long long*>(&d.acc_cnt[j]), (unsigned long long)c);
-        acc_ni[j] = acc_ni[j] + niv[u];
+        acc_ni[j] = accv[u] + niv[u];
       }
     }
     if (tid == 0) {
@@ -532,6 +674,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     }
   }
   __syncthreads();
+  // the append workgroups of this launch may start (they run beside the
+  // field solve)
+  if (!field_only && tid == 0) publish_ready(d.st);
   // Poisson's equation with phi_0 = V(t), phi_N = 0 for the interior nodes
   double rho[kNodeSlots];
 #pragma unroll
@@ -579,69 +724,6 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   }
 }
 
-// Append this step's children (in sub-chunk order, i.e. parent order), then the
-// left and right secondaries, with consecutive ids.  A sub-chunk's children
-// start at its workgroup's offset (from the finalize scan) plus its own offset
-// inside the workgroup (from the electron launch).  Each wave takes 64
-// consecutive sub-chunks and copies the children of each non-empty one with
-// all of its lanes.
-template <class P>
-__device__ __forceinline__ void append_one(const Disch<P>& d, int buf, uint32_t src_c, uint32_t dst,
-                                           uint32_t id, const Gp<int32_t>* sc, const Gp<P>* so,
-                                           const Gp<P>* sx, const Gp<P>* sy, const Gp<P>* sz) {
-  gptr(d.cell[buf])[dst] = sc[src_c];
-  gptr(d.off[buf])[dst] = so[src_c];
-  gptr(d.vx[buf])[dst] = sx[src_c];
-  gptr(d.vy[buf])[dst] = sy[src_c];
-  gptr(d.vz[buf])[dst] = sz[src_c];
-  gptr(d.id[buf])[dst] = id;
-}
-
-template <class P>
-__global__ __launch_bounds__(kThreads) void k_append(const Disch<P>* __restrict__ ds, int D) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = (blockIdx.x * (uint32_t)kThreads + threadIdx.x) >> 6;
-  const uint32_t nwaves = gridDim.x * (uint32_t)(kThreads / 64);
-  const uint32_t gid = blockIdx.x * (uint32_t)kThreads + threadIdx.x;
-  const uint32_t gsz = gridDim.x * (uint32_t)kThreads;
-  for (int di = 0; di < D; ++di) {
-    const Disch<P>& d = ds[di];
-    const Gp<State>* st = gptr(d.st);
-    if (!st->append_pending) continue;
-    const int buf = st->buf;
-    const uint32_t nch = st->n_chunks, base = st->append_base, idb = st->id_base;
-    const uint32_t nk = st->n_kids, n0 = st->n_see[0], n1 = st->n_see[1];
-    const uint32_t soff = st->seg_off, sper = st->seg_per;
-    const Gp<uint32_t>* kids = gptr(d.chunk_kids);
-    const Gp<uint32_t>* cbase = gptr(d.chunk_base);
-    const Gp<uint32_t>* sbase = gptr(d.seg);
-    for (uint32_t k0 = wave * 64u; k0 < nch; k0 += nwaves * 64u) {
-      const uint32_t k = k0 + lane;
-      const uint32_t cnt = k < nch ? kids[k] : 0u;
-      uint64_t live = __ballot(cnt != 0u);
-      if (live == 0) continue;
-      // offset = the workgroup's among all children + the sub-chunk's in it
-      const uint32_t cb =
-          cnt ? sbase[(soff + k / (uint32_t)(kTile / kSub)) / sper] + cbase[k] : 0u;
-      while (live) {
-        const int l = __ffsll((unsigned long long)live) - 1;
-        live &= live - 1;
-        const uint32_t n = (uint32_t)__shfl((int)cnt, l, 64);
-        const uint32_t b = (uint32_t)__shfl((int)cb, l, 64);
-        const uint32_t src0 = (k0 + (uint32_t)l) * (uint32_t)kSub;
-        for (uint32_t t = lane; t < n; t += 64u)
-          append_one<P>(d, buf, src0 + t, base + b + t, idb + b + t, gptr(d.kc), gptr(d.koff),
-                        gptr(d.kvx), gptr(d.kvy), gptr(d.kvz));
-      }
-    }
-    for (uint32_t t = gid; t < n0 + n1; t += gsz) {
-      const uint32_t src = t < n0 ? t : (uint32_t)kSeeMax + (t - n0);
-      append_one<P>(d, buf, src, base + nk + t, idb + nk + t, gptr(d.sc), gptr(d.soff),
-                    gptr(d.svx), gptr(d.svy), gptr(d.svz));
-    }
-  }
-}
-
 // Arms every discharge of a batch for n more steps (discharges in an error
 // state stay idle).
 template <class P>
@@ -665,11 +747,14 @@ __global__ void k_diag(int64_t n, const P* a, const P* b, P* out) {
 
 }  // namespace
 
+// field_only: the field of the current state (at set-up), no step ends and
+// no append workgroups.  Otherwise app_blocks (>= 1) workgroups append.
 template <class P>
 hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_max,
-                           hipStream_t s) {
+                           int app_blocks, hipStream_t s) {
   const size_t lds = finalize_lds_doubles(nn_max) * 8u;
-  hipLaunchKernelGGL(k_finalize<P>, dim3(D), dim3(kFinThreads), lds, s, d_dev, field_only);
+  const int grid = D + (field_only ? 0 : app_blocks);
+  hipLaunchKernelGGL(k_finalize<P>, dim3(grid), dim3(kFinThreads), lds, s, d_dev, D, field_only);
   return hipGetLastError();
 }
 
@@ -681,12 +766,6 @@ hipError_t finalize_set_lds(int nn_max) {
 
 template hipError_t finalize_set_lds<float>(int);
 template hipError_t finalize_set_lds<double>(int);
-
-template <class P>
-hipError_t launch_append(const Disch<P>* d_dev, int D, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_append<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
-  return hipGetLastError();
-}
 
 template <class P>
 hipError_t launch_diag(int64_t n, const P* a, const P* b, P* out, hipStream_t s) {
@@ -704,10 +783,8 @@ hipError_t launch_set_steps(const Disch<P>* d_dev, int D, int64_t n, hipStream_t
 
 template hipError_t launch_set_steps<float>(const Disch<float>*, int, int64_t, hipStream_t);
 template hipError_t launch_set_steps<double>(const Disch<double>*, int, int64_t, hipStream_t);
-template hipError_t launch_finalize<float>(const Disch<float>*, int, int, int, hipStream_t);
-template hipError_t launch_finalize<double>(const Disch<double>*, int, int, int, hipStream_t);
-template hipError_t launch_append<float>(const Disch<float>*, int, int, hipStream_t);
-template hipError_t launch_append<double>(const Disch<double>*, int, int, hipStream_t);
+template hipError_t launch_finalize<float>(const Disch<float>*, int, int, int, int, hipStream_t);
+template hipError_t launch_finalize<double>(const Disch<double>*, int, int, int, int, hipStream_t);
 template hipError_t launch_diag<float>(int64_t, const float*, const float*, float*, hipStream_t);
 template hipError_t launch_diag<double>(int64_t, const double*, const double*, double*,
                                         hipStream_t);
