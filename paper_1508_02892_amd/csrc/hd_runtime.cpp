@@ -979,6 +979,8 @@ struct Server : ServerBase {
   Disch<P> idle_entry(int slot) const {
     Disch<P> e{};
     e.st = d_idle + slot;
+    e.sort_every = 1;  // never used (the state is idle), but no interval is 0
+    e.eedf_every = 1;
     return e;
   }
 
@@ -1045,6 +1047,7 @@ struct Server : ServerBase {
     if (n < 1) return fail(HD_EINVAL, "n_steps must be positive");
     if (p->precision != cfg.precision || p->sort_every != cfg.sort_every ||
         p->eedf_every != cfg.eedf_every || p->n_cells > cfg.max_cells ||
+        p->n_energy > cfg.max_energy || p->n_channels > cfg.max_channels ||
         p->n_energy * std::max(1, p->n_channels) > tab_max ||
         p->n_eedf_bins > cfg.max_eedf_bins ||
         (p->ion_model == HD_ION_FULL_CONST_NU && !cfg.allow_full_fluid))

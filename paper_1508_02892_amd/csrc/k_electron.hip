@@ -706,7 +706,9 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
   while (pre[di + 1] <= g0) ++di;
   while (g0 < g1) {
     const uint32_t end = min(g1, pre[di + 1]);
-    segment<P>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
+    // a discharge with no chunks (idle, or an empty slot whose descriptor
+    // has no arrays) between two others gets no segment
+    if (end > g0) segment<P>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
     g0 = end;
     ++di;
   }

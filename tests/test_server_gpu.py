@@ -88,3 +88,27 @@ def test_misfit_jobs_rejected():
         srv.submit(_job(128, 40_000_000, 1, 100.0), 10)  # alone larger than the budget
     assert e.value.code == -2
     srv.close()
+
+
+def test_idle_slot_between_active_jobs():
+    """A short job retires and leaves its slot empty between two running
+    ones; the large job makes every particle workgroup take several chunks,
+    so one workgroup's range runs from the first job over the empty slot
+    into the third.  All jobs must equal their runs alone."""
+    specs = [(96, 1500, 41, 150.0, 48),       # slot 0: one chunk
+             (64, 3000, 42, 200.0, 10),       # slot 1: retires after the first interval
+             (128, 3000000, 43, 250.0, 48)]   # slot 2: > 1,024 chunks
+    srv = hd.Server(precision=0, max_slots=3, max_cells=256)
+    ids = [(srv.submit(_job(nc, nm, seed, v), steps), nc, nm, seed, v, steps)
+           for nc, nm, seed, v, steps in specs]
+    srv.drain(300)
+    st = srv.stats()
+    assert st["completed"] == len(specs) and st["failed"] == 0 and st["error"] == 0
+    for jid, nc, nm, seed, v, steps in ids:
+        state, _, mix = srv.poll(jid)
+        assert state == 2
+        alone = hd.Discharge(_job(nc, nm, seed, v))
+        alone.step(steps)
+        _same(mix, alone.moments())
+        alone.close()
+    srv.close()
