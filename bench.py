@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--profile-steps", type=int, default=64)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ion", choices=["default", "dd", "full"], default="default",
                     help="override the ion model of the workload (diagnostic variants)")
