@@ -95,6 +95,7 @@ def lib():
                                        C.c_int64, vp]
             L.orc_thomas.argtypes = [C.c_int] + [vp] * 5
             L.orc_solve_tridiag.argtypes = [C.c_int] + [vp] * 5
+            L.orc_solve_tridiag_fma.argtypes = [C.c_int] + [vp] * 5
             L.orc_n_partitions.argtypes = [C.c_int]
             L.orc_field.argtypes = [vp, vp, vp, C.c_double, vp, vp]
             L.orc_fluid.argtypes = [vp] * 5
@@ -283,6 +284,15 @@ def solve_tridiag(a, b, c, d):
     a, b, c, d = (np.ascontiguousarray(v, np.float64) for v in (a, b, c, d))
     x = np.empty(len(b))
     lib().orc_solve_tridiag(len(b), _p(a), _p(b), _p(c), _p(d), _p(x))
+    return x
+
+
+def solve_tridiag_fma(a, b, c, d):
+    """The partitioned solve with the right-hand side carried by fused
+    multiply-adds (the field's solver)."""
+    a, b, c, d = (np.ascontiguousarray(v, np.float64) for v in (a, b, c, d))
+    x = np.empty(len(b))
+    lib().orc_solve_tridiag_fma(len(b), _p(a), _p(b), _p(c), _p(d), _p(x))
     return x
 
 

@@ -279,11 +279,14 @@ bool derive(const orc_params& p, Derived& d) {
 // rho_j = e (n_i,j - n_e,j);  -phi_{j-1} + 2 phi_j - phi_{j+1} = dz^2 rho_j / eps0
 // for the interior nodes, phi_0 = V(t_n) (powered electrode at z = 0) and
 // phi_N = 0 (grounded electrode at z = L), solved by the partitioned
-// tridiagonal elimination.  E from centred differences inside and from
+// tridiagonal elimination with the right-hand side carried by fused
+// multiply-adds.  E from centred differences inside and from
 // Gauss's law over the half cells at the walls.
 // ---------------------------------------------------------------------------
 void solve_tridiag(int n, const double* a, const double* b, const double* c, const double* d,
                    double* x);
+void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
+                       const double* d, double* x);
 
 void field_solve(const Derived& d, const int64_t* cnt, const double* ni, double V, double* ne_out,
                  double* rho, double* phi, double* E) {
@@ -303,7 +306,7 @@ void field_solve(const Derived& d, const int64_t* cnt, const double* ni, double 
       if (j == m) dj = dj + phi[nc];
       rhs[j - 1] = dj;
     }
-    solve_tridiag(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+    solve_tridiag_fma(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
     for (int j = 1; j <= m; ++j) phi[j] = x[j - 1];
   }
   for (int j = 1; j < nc; ++j) E[j] = (phi[j - 1] - phi[j + 1]) * d.inv_2dz;
@@ -427,6 +430,76 @@ void solve_tridiag(int n, const double* a, const double* b, const double* c, con
     x[s] = xs;
     x[e] = xe;
     for (int i = s + 1; i <= e - 1; ++i) x[i] = (dp[i] - ap[i] * xs) - cp[i] * xe;
+  }
+}
+
+// The same two solvers with the right-hand side carried by fused
+// multiply-adds: every step of a sweep over the right-hand side is one
+// rounding.  Forward, d'_i = fma(-(a_i r_i), d'_{i-1}, d_i r_i) with r_i the
+// reciprocal pivot; backward, d'_i = fma(-c'_i, d'_{i+1}, d'_i); the reduced
+// system and the recovery of the interior likewise.  The pivots and the
+// eliminated a'', c'' are computed exactly as above.
+void thomas_fma(int n, const double* a, const double* b, const double* c, const double* dd,
+                double* x) {
+  std::vector<double> cp(n), dp(n);
+  for (int j = 0; j < n; ++j) {
+    double den = b[j];
+    if (j > 0) den = b[j] - a[j] * cp[j - 1];
+    const double r = 1.0 / den;
+    cp[j] = c[j] * r;
+    dp[j] = j > 0 ? std::fma(-(a[j] * r), dp[j - 1], dd[j] * r) : dd[j] * r;
+  }
+  x[n - 1] = dp[n - 1];
+  for (int j = n - 2; j >= 0; --j) x[j] = std::fma(-cp[j], x[j + 1], dp[j]);
+}
+
+void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
+                       const double* d, double* x) {
+  const int P = n_partitions(n);
+  if (P == 0) {
+    thomas_fma(n, a, b, c, d, x);
+    return;
+  }
+  std::vector<double> ap(n), cp(n), dp(n);
+  std::vector<double> ra(2 * P), rb(2 * P), rc(2 * P), rd(2 * P), rx(2 * P);
+  for (int p = 0; p < P; ++p) {
+    const int s = (int)((int64_t)p * n / P);
+    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    {
+      const int i = s + 1;
+      const double r = 1.0 / b[i];
+      ap[i] = a[i] * r;
+      cp[i] = c[i] * r;
+      dp[i] = d[i] * r;
+    }
+    for (int i = s + 2; i <= e - 1; ++i) {
+      const double r = 1.0 / (b[i] - a[i] * cp[i - 1]);
+      ap[i] = -(a[i] * ap[i - 1]) * r;
+      cp[i] = c[i] * r;
+      dp[i] = std::fma(-(a[i] * r), dp[i - 1], d[i] * r);
+    }
+    for (int i = e - 2; i >= s + 1; --i) {
+      dp[i] = std::fma(-cp[i], dp[i + 1], dp[i]);
+      ap[i] = ap[i] - cp[i] * ap[i + 1];
+      cp[i] = -(cp[i] * cp[i + 1]);
+    }
+    ra[2 * p] = a[s];
+    rb[2 * p] = b[s] - c[s] * ap[s + 1];
+    rc[2 * p] = -(c[s] * cp[s + 1]);
+    rd[2 * p] = std::fma(-c[s], dp[s + 1], d[s]);
+    ra[2 * p + 1] = -(a[e] * ap[e - 1]);
+    rb[2 * p + 1] = b[e] - a[e] * cp[e - 1];
+    rc[2 * p + 1] = c[e];
+    rd[2 * p + 1] = std::fma(-a[e], dp[e - 1], d[e]);
+  }
+  thomas_fma(2 * P, ra.data(), rb.data(), rc.data(), rd.data(), rx.data());
+  for (int p = 0; p < P; ++p) {
+    const int s = (int)((int64_t)p * n / P);
+    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    const double xs = rx[2 * p], xe = rx[2 * p + 1];
+    x[s] = xs;
+    x[e] = xe;
+    for (int i = s + 1; i <= e - 1; ++i) x[i] = std::fma(-cp[i], xe, std::fma(-ap[i], xs, dp[i]));
   }
 }
 
@@ -1122,6 +1195,11 @@ void orc_thomas(int n, const double* a, const double* b, const double* c, const 
 void orc_solve_tridiag(int n, const double* a, const double* b, const double* c, const double* d,
                        double* x) {
   solve_tridiag(n, a, b, c, d, x);
+}
+
+void orc_solve_tridiag_fma(int n, const double* a, const double* b, const double* c, const double* d,
+                       double* x) {
+  solve_tridiag_fma(n, a, b, c, d, x);
 }
 
 int orc_n_partitions(int n) { return n_partitions(n); }

@@ -152,7 +152,7 @@ __device__ inline PoisFac pois_fac(int n) {
   f.fc = f.Lmax;              // forward eliminated c at k
   f.xa = 2 * f.Lmax;          // final A at k, lengths L0 and L0 + 1
   f.xc = 4 * f.Lmax;          // final C at k, lengths L0 and L0 + 1
-  f.ra = 6 * f.Lmax;          // reduced system: sub-diagonal,
+  f.ra = 6 * f.Lmax;          // reduced system: -(sub-diagonal x reciprocal pivot),
   f.rr = f.ra + 2 * f.P;      //   reciprocal pivots,
   f.rc = f.rr + 2 * f.P;      //   eliminated super-diagonal
   f.size = f.rc + 2 * f.P;
@@ -234,7 +234,7 @@ __device__ void pois_factor(const PoisFac& f, double* t) {
       rr = 1.0 / den;
     }
     rcp = rc * rr;
-    t[f.ra + j] = ra;
+    t[f.ra + j] = -(ra * rr);  // multiplier of the previous row in the reduced sweep
     t[f.rr + j] = rr;
     t[f.rc + j] = rcp;
   }
@@ -242,12 +242,15 @@ __device__ void pois_factor(const PoisFac& f, double* t) {
 
 // Solve of the (-1, 2, -1) system for the right-hand side d (LDS, n rows),
 // overwritten by the solution; t: factor tables (LDS); red: 2 * kTriRed
-// doubles of LDS.  Called by every thread of the workgroup.
+// doubles of LDS.  Called by every thread of the workgroup.  The right-hand
+// side is carried by fused multiply-adds, one rounding per row of a sweep:
+// forward d'_i = fma(-(a r_i), d'_{i-1}, d_i r_i), backward
+// d'_i = fma(-c'_i, d'_{i+1}, d'_i), the reduced system likewise.
 //
 // The serial sweeps read and write rows in full batches of kB (no per-row
-// predication, LDS latency off the dependent chain).  The serial parts run
-// on all of wave 0 with an offset zo that is 0 but not known to be, so the
-// running values stay in vector registers.
+// predication, LDS latency and the products d_i r_i off the dependent
+// chain).  The serial parts run on all of wave 0 with an offset zo that is 0
+// but not known to be, so the running values stay in vector registers.
 __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double* red) {
   constexpr int kB = 8;
   const int tid = threadIdx.x, nt = blockDim.x, n = f.n, P = f.P;
@@ -262,12 +265,12 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
       double dp = dd[0] * fr[0];
       dd[0] = dp;
       for (int j = 1; j < n; ++j) {
-        dp = (dd[j] - a * dp) * fr[j];
+        dp = fma(-(a * fr[j]), dp, dd[j] * fr[j]);
         dd[j] = dp;
       }
       double x = dp;
       for (int j = n - 2; j >= 0; --j) {
-        x = dd[j] - fc[j] * x;
+        x = fma(-fc[j], x, dd[j]);
         dd[j] = x;
       }
     }
@@ -286,50 +289,52 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
     double dp = d[i] * fr[i];
     d[i] = dp;
     for (i = s + 2; i + kB <= e; i += kB) {  // rows i .. i + kB - 1 <= e - 1
-      double dv[kB], tv[kB];
+      double dv[kB], mv[kB];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
-        dv[u] = d[i + u];
-        tv[u] = fr[i + u];
+        const double r = fr[i + u];
+        dv[u] = d[i + u] * r;
+        mv[u] = -(a * r);
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
-        dp = (dv[u] - a * dp) * tv[u];
+        dp = fma(mv[u], dp, dv[u]);
         dv[u] = dp;
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) d[i + u] = dv[u];
     }
     for (; i <= e - 1; ++i) {
-      dp = (d[i] - a * dp) * fr[i];
+      const double r = fr[i];
+      dp = fma(-(a * r), dp, d[i] * r);
       d[i] = dp;
     }
     for (i = e - 2; i - kB >= s; i -= kB) {  // rows i .. i - kB + 1 >= s + 1
-      double dv[kB], tv[kB];
+      double dv[kB], cv[kB];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
         dv[u] = d[i - u];
-        tv[u] = fc[i - u];
+        cv[u] = -fc[i - u];
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
-        dp = dv[u] - tv[u] * dp;
+        dp = fma(cv[u], dp, dv[u]);
         dv[u] = dp;
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) d[i - u] = dv[u];
     }
     for (; i >= s + 1; --i) {
-      dp = d[i] - fc[i] * dp;
+      dp = fma(-fc[i], dp, d[i]);
       d[i] = dp;
     }
-    rd[2 * p] = d[s] - c * d[s + 1];
-    rd[2 * p + 1] = d[e] - a * d[e - 1];
+    rd[2 * p] = fma(-c, d[s + 1], d[s]);
+    rd[2 * p + 1] = fma(-a, d[e - 1], d[e]);
   }
   __syncthreads();
   if (tid < 64) {
     const int n2 = 2 * P;
-    const double* ra = t + f.ra + zo;
+    const double* rm = t + f.ra + zo;
     const double* rr = t + f.rr + zo;
     const double* rc = t + f.rc + zo;
     const double* rdz = rd + zo;
@@ -338,23 +343,22 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
     rxz[0] = dp;
     int j = 1;
     for (; j + kB <= n2; j += kB) {
-      double dv[kB], av[kB], rv[kB];
+      double dv[kB], mv[kB];
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
-        dv[u] = rdz[j + u];
-        av[u] = ra[j + u];
-        rv[u] = rr[j + u];
+        dv[u] = rdz[j + u] * rr[j + u];
+        mv[u] = rm[j + u];
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
-        dp = (dv[u] - av[u] * dp) * rv[u];
+        dp = fma(mv[u], dp, dv[u]);
         dv[u] = dp;
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) rxz[j + u] = dv[u];
     }
     for (; j < n2; ++j) {
-      dp = (rdz[j] - ra[j] * dp) * rr[j];
+      dp = fma(rm[j], dp, rdz[j] * rr[j]);
       rxz[j] = dp;
     }
     double x = dp;
@@ -364,18 +368,18 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
         dv[u] = rxz[j - u];
-        cv[u] = rc[j - u];
+        cv[u] = -rc[j - u];
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) {
-        x = dv[u] - cv[u] * x;
+        x = fma(cv[u], x, dv[u]);
         dv[u] = x;
       }
 #pragma unroll
       for (int u = 0; u < kB; ++u) rxz[j - u] = dv[u];
     }
     for (; j >= 0; --j) {
-      x = rxz[j] - rc[j] * x;
+      x = fma(-rc[j], x, rxz[j]);
       rxz[j] = x;
     }
   }
@@ -392,7 +396,7 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
       xi = xe;
     } else {
       const int o = (e - s + 1 - f.L0) * f.Lmax + (i - s);
-      xi = (d[i] - t[f.xa + o] * xs) - t[f.xc + o] * xe;
+      xi = fma(-t[f.xc + o], xe, fma(-t[f.xa + o], xs, d[i]));
     }
     d[i] = xi;
   }

@@ -50,6 +50,44 @@ def test_partitioned_solve_matches_dense_solve(n):
     assert np.abs(r).max() < 1e-12 * (np.abs(d).max() + 1)
 
 
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 9, 17, 50, 127, 255, 1000, 2047, 4095, 9000])
+def test_fma_partitioned_solve_matches_banded_solve(n):
+    # the field's solver: same elimination, right-hand side by fused
+    # multiply-adds; it must solve the system as exactly as the plain one
+    rng = np.random.default_rng(3000 + n)
+    a = rng.normal(size=n)
+    c = rng.normal(size=n)
+    b = np.abs(a) + np.abs(c) + 0.5 + rng.random(n)
+    d = rng.normal(size=n)
+    x = oracle.solve_tridiag_fma(a, b, c, d)
+    from scipy.linalg import solve_banded
+    ab = np.zeros((3, n))
+    ab[0, 1:] = c[:-1]
+    ab[1] = b
+    ab[2, :-1] = a[1:]
+    np.testing.assert_allclose(x, solve_banded((1, 1), ab, d), rtol=1e-11, atol=1e-13)
+    r = b * x - d
+    r[1:] += a[1:] * x[:-1]
+    r[:-1] += c[:-1] * x[1:]
+    assert np.abs(r).max() < 1e-12 * (np.abs(d).max() + 1)
+    # and it differs from the plain solve only by rounding
+    np.testing.assert_allclose(x, oracle.solve_tridiag(a, b, c, d), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [3, 8, 63, 2047])
+def test_fma_solve_of_the_poisson_matrix(n):
+    rng = np.random.default_rng(7 + n)
+    d = rng.normal(size=n)
+    x = oracle.solve_tridiag_fma(-np.ones(n), 2 * np.ones(n), -np.ones(n), d)
+    from scipy.linalg import solve_banded
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -1.0
+    ab[1] = 2.0
+    ab[2, :-1] = -1.0
+    np.testing.assert_allclose(x, solve_banded((1, 1), ab, d), rtol=1e-9,
+                               atol=1e-9 * np.abs(x).max())
+
+
 def test_partitioned_solve_of_the_poisson_matrix():
     # the (-1, 2, -1) matrix is the worst conditioned case the field uses
     n = 2047
