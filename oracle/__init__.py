@@ -97,6 +97,9 @@ def lib():
             L.orc_solve_tridiag.argtypes = [C.c_int] + [vp] * 5
             L.orc_solve_tridiag_fma.argtypes = [C.c_int] + [vp] * 5
             L.orc_n_partitions.argtypes = [C.c_int]
+            for f in ("orc_fit_ln", "orc_fit_exp", "orc_mobility_fit", "orc_nu_fit"):
+                getattr(L, f).restype = C.c_double
+                getattr(L, f).argtypes = [C.c_double]
             L.orc_field.argtypes = [vp, vp, vp, C.c_double, vp, vp]
             L.orc_fluid.argtypes = [vp] * 5
             L.orc_push.argtypes = [C.c_int, C.c_int64, vp, vp, vp, vp, C.c_int, C.c_double,
@@ -298,6 +301,26 @@ def solve_tridiag_fma(a, b, c, d):
 
 def n_partitions(n):
     return lib().orc_n_partitions(int(n))
+
+
+def fit_ln(x):
+    """Natural logarithm as the fitted-transport formulas evaluate it."""
+    return lib().orc_fit_ln(float(x))
+
+
+def fit_exp(y):
+    """Exponential as the fitted-transport formulas evaluate it."""
+    return lib().orc_fit_exp(float(y))
+
+
+def mobility_fit(E):
+    """He+ mobility in He at 1 atm as a function of the field (Table 2) [m^2/(V s)]."""
+    return lib().orc_mobility_fit(float(E))
+
+
+def nu_fit(u):
+    """He+ momentum-exchange frequency as a function of the drift speed (Table 3) [1/s]."""
+    return lib().orc_nu_fit(float(u))
 
 
 def push(precision, cell, off, vz, Ep, nc, kdz, steps):

@@ -70,7 +70,8 @@ typedef struct orc_channel {
 
 typedef struct orc_params {
   int32_t precision;  // 0: float particles, 1: double particles
-  int32_t ion_model;  // 0: drift-diffusion, constant mobility; 1: full fluid, constant nu
+  int32_t ion_model;  // 0/1: drift-diffusion / full fluid with constant mu / nu;
+                      // 2/3: the same with the fitted mu(E) / nu(u) of Tables 2 / 3
   int32_t n_cells;
   int32_t n_energy;
   int32_t n_channels;
@@ -204,7 +205,7 @@ bool derive(const orc_params& p, Derived& d) {
   if (p.n_cells < 2 || p.n_energy < 2 || p.n_channels < 0 || p.n_channels > kMaxChannels ||
       p.sort_every < 1 || p.eedf_every < 1 || p.n_eedf_bins < 1 || p.n_macro < 0 ||
       !(p.gap_m > 0) || !(p.dt_s > 0) || !(p.inv_de_per_eV > 0) || !(p.load_hi > p.load_lo) ||
-      p.load_lo < 0 || p.load_hi > 1 || (p.ion_model != 0 && p.ion_model != 1) ||
+      p.load_lo < 0 || p.load_hi > 1 || (p.ion_model < 0 || p.ion_model > 3) ||
       (p.precision != 0 && p.precision != 1) || (p.n_channels > 0 && !p.channels)) {
     g_err = "invalid parameters";
     return false;
@@ -315,6 +316,82 @@ void field_solve(const Derived& d, const int64_t* cnt, const double* ni, double 
 }
 
 // ---------------------------------------------------------------------------
+// Fitted He+ transport in He at atmospheric pressure (Sec. III): the mobility
+// as a function of |E| (Table 2) and the momentum-exchange frequency as a
+// function of |u| (Table 3), each with its branch change where the table puts
+// it (both fits jump slightly there).  The non-integer powers use the
+// logarithm and exponential below, written out so that every implementation
+// that takes the same steps rounds the same way.
+// ---------------------------------------------------------------------------
+// ln x, x > 0 finite: x = m 2^k with m in [sqrt(1/2), sqrt(2)); ln m =
+// 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.172, by the odd series to s^21.
+double fit_ln(double x) {
+  int k = 0;
+  double m = std::frexp(x, &k);  // m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    k = k - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double q = 1.0 / 21.0;
+  q = q * z + 1.0 / 19.0;
+  q = q * z + 1.0 / 17.0;
+  q = q * z + 1.0 / 15.0;
+  q = q * z + 1.0 / 13.0;
+  q = q * z + 1.0 / 11.0;
+  q = q * z + 1.0 / 9.0;
+  q = q * z + 1.0 / 7.0;
+  q = q * z + 1.0 / 5.0;
+  q = q * z + 1.0 / 3.0;
+  q = q * z + 1.0;
+  return (double)k * 0.69314718055994530942 + (2.0 * s) * q;
+}
+
+// exp y, |y| < 700: y = k ln2 + r with k = rint(y / ln2) and ln2 in two parts
+// (the first exact in k ln2 for |k| < 2^11), exp r by its Taylor series to
+// r^14 (|r| <= 0.347), then the power of two.
+double fit_exp(double y) {
+  const double k = std::rint(y * 1.44269504088896340736);
+  const double r = (y - k * 6.93147180369123816490e-01) - k * 1.90821492927058770002e-10;
+  double q = 1.0 / 87178291200.0;
+  q = q * r + 1.0 / 6227020800.0;
+  q = q * r + 1.0 / 479001600.0;
+  q = q * r + 1.0 / 39916800.0;
+  q = q * r + 1.0 / 3628800.0;
+  q = q * r + 1.0 / 362880.0;
+  q = q * r + 1.0 / 40320.0;
+  q = q * r + 1.0 / 5040.0;
+  q = q * r + 1.0 / 720.0;
+  q = q * r + 1.0 / 120.0;
+  q = q * r + 1.0 / 24.0;
+  q = q * r + 1.0 / 6.0;
+  q = q * r + 1.0 / 2.0;
+  q = q * r + 1.0;
+  q = q * r + 1.0;
+  return std::ldexp(q, (int)k);
+}
+
+// x^y for x >= 0 (0^y = 0 for the positive exponents used here).
+double fit_pow(double x, double y) { return x > 0.0 ? fit_exp(y * fit_ln(x)) : 0.0; }
+
+// Table 2: mu = 1e-3 (1.18 - 0.185 |E|/E0) below E0 = 1.47e6 V/m, 1e-3 0.94
+// (E0/|E|)^0.3 from E0 on [m^2/(V s)].
+double mobility_fit(double E) {
+  const double a = std::fabs(E), E0 = 1.47e6;
+  if (a < E0) return 1e-3 * (1.18 - 0.185 * (a / E0));
+  return 1e-3 * (0.94 * fit_pow(E0 / a, 0.3));
+}
+
+// Table 3: nu = 1e10 (2.07 + 0.88 (|u|/u0)^1.89) below u0 = 2e3 m/s, 1e10
+// (1.54 + 1.36 |u|/u0) from u0 on [1/s].
+double nu_fit(double u) {
+  const double a = std::fabs(u), u0 = 2e3;
+  if (a < u0) return 1e10 * (2.07 + 0.88 * fit_pow(a / u0, 1.89));
+  return 1e10 * (1.54 + 1.36 * (a / u0));
+}
+
+// ---------------------------------------------------------------------------
 // Ion fluid.  Temperature from Eq (2.8), diffusion coefficient from Eq (2.7).
 // ---------------------------------------------------------------------------
 inline double ion_temperature(const Derived& d, double mu, double E) {
@@ -326,16 +403,19 @@ inline double ion_temperature(const Derived& d, double mu, double E) {
 // differences, wall fluxes by the field-direction switch (drift only), and the
 // continuity update of Eq (2.4) with half cells at the walls.  Returns the wall
 // fluxes Gamma_0 and Gamma_N in gw[0], gw[1]; gam receives Gamma^n.
-void fluid_dd(const Derived& d, double mu, double* ni, const double* E, double* gam, double gw[2]) {
+// fit != 0: the mobility of Table 2 at each node's field, else mu_const.
+void fluid_dd(const Derived& d, double mu_const, int fit, double* ni, const double* E, double* gam,
+              double gw[2]) {
   const int nc = d.nc, nn = d.nn;
-  std::vector<double> n0(ni, ni + nn);
+  std::vector<double> n0(ni, ni + nn), mu(nn);
+  for (int j = 0; j < nn; ++j) mu[j] = fit ? mobility_fit(E[j]) : mu_const;
   for (int j = 1; j < nc; ++j) {
-    const double T = ion_temperature(d, mu, E[j]);
-    const double D = mu * T / kE;
-    gam[j] = mu * n0[j] * E[j] - D * (n0[j + 1] - n0[j - 1]) * d.inv_2dz;
+    const double T = ion_temperature(d, mu[j], E[j]);
+    const double D = mu[j] * T / kE;
+    gam[j] = mu[j] * n0[j] * E[j] - D * (n0[j + 1] - n0[j - 1]) * d.inv_2dz;
   }
-  gam[0] = mu * n0[0] * std::min(E[0], 0.0);
-  gam[nc] = mu * n0[nc] * std::max(E[nc], 0.0);
+  gam[0] = mu[0] * n0[0] * std::min(E[0], 0.0);
+  gam[nc] = mu[nc] * n0[nc] * std::max(E[nc], 0.0);
   for (int j = 1; j < nc; ++j) ni[j] = n0[j] - d.dt_2dz * (gam[j + 1] - gam[j - 1]);
   ni[0] = n0[0] - d.dt_dz * (gam[1] - gam[0]);
   ni[nc] = n0[nc] - d.dt_dz * (gam[nc] - gam[nc - 1]);
@@ -508,14 +588,15 @@ void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
 // Gamma at the wall nodes from the field-direction switch with mu = e/(M nu)
 // (Eq (2.6)); then Eq (2.4) with G^n applied by the caller.  gam holds
 // Gamma^{n-1/2} on entry and Gamma^{n+1/2} on exit.
-void fluid_full(const Derived& d, double nu_const, double* ni, const double* E, double* gam,
-                double gw[2]) {
+// fit != 0: the frequency of Table 3 at each node's lagged u, else nu_const.
+void fluid_full(const Derived& d, double nu_const, int fit, double* ni, const double* E,
+                double* gam, double gw[2]) {
   const int nc = d.nc, nn = d.nn;
   std::vector<double> n0(ni, ni + nn), g0(gam, gam + nn), u(nn), T(nn), nu(nn), mu(nn);
   for (int j = 0; j < nn; ++j) {
-    nu[j] = nu_const;
-    mu[j] = kE / (d.M * nu[j]);
     u[j] = (n0[j] > d.nfloor) ? g0[j] / n0[j] : 0.0;
+    nu[j] = fit ? nu_fit(u[j]) : nu_const;
+    mu[j] = kE / (d.M * nu[j]);
     T[j] = ion_temperature(d, mu[j], E[j]);
   }
   const double gl = mu[0] * n0[0] * std::min(E[0], 0.0);
@@ -937,10 +1018,10 @@ struct Discharge : Base {
     field();
     for (int j = 0; j < d.nn; ++j) Ep[j] = (P)(d.qm_dt * E[j]);
     double gw[2];
-    if (p.ion_model == 0)
-      fluid_dd(d, p.mu_const, ni.data(), E.data(), gam.data(), gw);
+    if (p.ion_model == 0 || p.ion_model == 2)
+      fluid_dd(d, p.mu_const, p.ion_model == 2, ni.data(), E.data(), gam.data(), gw);
     else
-      fluid_full(d, p.nu_const, ni.data(), E.data(), gam.data(), gw);
+      fluid_full(d, p.nu_const, p.ion_model == 3, ni.data(), E.data(), gam.data(), gw);
     std::vector<int64_t> nxt(d.nn, 0);
     std::vector<Particle<P>> kids;
     const bool sample = ((step + 1) % p.eedf_every) == 0;
@@ -1197,6 +1278,11 @@ void orc_solve_tridiag(int n, const double* a, const double* b, const double* c,
   solve_tridiag(n, a, b, c, d, x);
 }
 
+double orc_fit_ln(double x) { return fit_ln(x); }
+double orc_fit_exp(double y) { return fit_exp(y); }
+double orc_mobility_fit(double E) { return mobility_fit(E); }
+double orc_nu_fit(double u) { return nu_fit(u); }
+
 void orc_solve_tridiag_fma(int n, const double* a, const double* b, const double* c, const double* d,
                        double* x) {
   solve_tridiag_fma(n, a, b, c, d, x);
@@ -1215,10 +1301,10 @@ void orc_field(void* h, const int64_t* cnt, const double* ni, double V, double* 
 // One ion-fluid update in place (n_i, Gamma) with a given E; returns wall fluxes.
 void orc_fluid(void* h, double* ni, double* gam, const double* E, double* gw) {
   Base* b = static_cast<Base*>(h);
-  if (b->p.ion_model == 0)
-    fluid_dd(b->d, b->p.mu_const, ni, E, gam, gw);
+  if (b->p.ion_model == 0 || b->p.ion_model == 2)
+    fluid_dd(b->d, b->p.mu_const, b->p.ion_model == 2, ni, E, gam, gw);
   else
-    fluid_full(b->d, b->p.nu_const, ni, E, gam, gw);
+    fluid_full(b->d, b->p.nu_const, b->p.ion_model == 3, ni, E, gam, gw);
 }
 
 // Push n particles (precision 0: float arrays, 1: double arrays) through

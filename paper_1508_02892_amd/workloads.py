@@ -27,7 +27,7 @@ HE_AMU = 4.002602
 N_GAS_1ATM = 2.45e25
 
 FP32, FP64 = 0, 1
-ION_DD, ION_FULL = 0, 1
+ION_DD, ION_FULL, ION_DD_FIT, ION_FULL_FIT = 0, 1, 2, 3
 
 
 def energy_grid(n_energy: int = 4096, inv_de_per_eV: float = 10.0) -> np.ndarray:
