@@ -188,7 +188,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=64)
     ap.add_argument("--cpu-steps", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--ion", choices=["default", "dd", "full"], default="default",
+    ap.add_argument("--ion", choices=["default", "dd", "full", "dd-fit", "full-fit"],
+                    default="default",
                     help="override the ion model of the workload (diagnostic variants)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration runs)")
@@ -220,8 +221,12 @@ def main():
     torch.cuda.set_device(0)
     p, desc = workload(a.workload)
     if a.ion != "default":
-        p["ion_model"] = 0 if a.ion == "dd" else 1
-        desc += "; ion model overridden: %s" % ("drift-diffusion" if a.ion == "dd" else "full")
+        p["ion_model"], name = {
+            "dd": (0, "drift-diffusion, constant mobility"),
+            "full": (1, "full fluid, constant nu"),
+            "dd-fit": (2, "drift-diffusion, mobility of Table 2"),
+            "full-fit": (3, "full fluid, nu of Table 3")}[a.ion]
+        desc += "; ion model overridden: %s" % name
     if a.electrons:
         from paper_1508_02892_amd import workloads as W
         p = W.scaled(p, a.electrons)

@@ -47,10 +47,20 @@ enum hd_status {
 
 enum hd_precision { HD_FP32 = 0, HD_FP64 = 1 };
 
-/* Ion model: drift-diffusion with constant mobility (Sec. II.C, explicit
- * option) or the full fluid with inertia and constant momentum-exchange
- * frequency (Sec. II.B, Eq 2.3 solved by the Thomas method). */
-enum hd_ion_model { HD_ION_DD_CONST_MU = 0, HD_ION_FULL_CONST_NU = 1 };
+/* Ion model: drift-diffusion (Sec. II.C, explicit option) or the full fluid
+ * with inertia (Sec. II.B, Eq 2.3 solved by a tridiagonal solve), each with a
+ * constant transport coefficient (mu_const / nu_const) or with the fitted
+ * He+-in-He coefficients at atmospheric pressure: the mobility as a function
+ * of the local |E| (Table 2) for drift-diffusion, the momentum-exchange
+ * frequency as a function of the lagged local |u| (Table 3) for the full
+ * fluid, with mu = e/(M nu) in the wall fluxes and Eq (2.8).  The fitted
+ * models ignore mu_const / nu_const. */
+enum hd_ion_model {
+  HD_ION_DD_CONST_MU = 0,
+  HD_ION_FULL_CONST_NU = 1,
+  HD_ION_DD_FIT_MU = 2,
+  HD_ION_FULL_FIT_NU = 3
+};
 
 /* Electron-neutral reaction kinds (Table 1: R1 elastic, R2 ionization,
  * R3 excitation). */

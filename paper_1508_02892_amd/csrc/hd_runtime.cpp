@@ -111,11 +111,14 @@ struct HostStream {
   }
 };
 
+// Ion models that solve Eq (2.3) (tridiagonal scratch in LDS).
+bool full_fluid(int32_t m) { return m == HD_ION_FULL_CONST_NU || m == HD_ION_FULL_FIT_NU; }
+
 bool validate(const hd_params* p, std::string& why) {
   if (!p) return (why = "null params"), false;
   if (p->abi_version != HD_ABI_VERSION) return (why = "abi_version mismatch"), false;
   if (p->precision != HD_FP32 && p->precision != HD_FP64) return (why = "precision"), false;
-  if (p->ion_model != HD_ION_DD_CONST_MU && p->ion_model != HD_ION_FULL_CONST_NU)
+  if (p->ion_model < HD_ION_DD_CONST_MU || p->ion_model > HD_ION_FULL_FIT_NU)
     return (why = "ion_model"), false;
   if (p->n_cells < 2 || p->n_cells > kMaxCells) return (why = "n_cells out of [2, 4096]"), false;
   if (p->n_energy < 2 || p->n_energy > (1 << 20)) return (why = "n_energy"), false;
@@ -593,7 +596,7 @@ struct Batch : BatchBase {
       nn_max = std::max(nn_max, h.p.n_cells + 1);
       nc_max = std::max(nc_max, h.p.n_cells);
       nb1_max = std::max(nb1_max, h.p.n_eedf_bins + 1);
-      if (h.p.ion_model == HD_ION_FULL_CONST_NU) fluid_nn = std::max(fluid_nn, h.p.n_cells + 1);
+      if (full_fluid(h.p.ion_model)) fluid_nn = std::max(fluid_nn, h.p.n_cells + 1);
     }
     sort_every = hs[0].p.sort_every;
     // launch geometry
@@ -1050,7 +1053,7 @@ struct Server : ServerBase {
         p->n_energy > cfg.max_energy || p->n_channels > cfg.max_channels ||
         p->n_energy * std::max(1, p->n_channels) > tab_max ||
         p->n_eedf_bins > cfg.max_eedf_bins ||
-        (p->ion_model == HD_ION_FULL_CONST_NU && !cfg.allow_full_fluid))
+        (full_fluid(p->ion_model) && !cfg.allow_full_fluid))
       return fail(HD_EINVAL, "job does not fit the server's slot configuration");
     auto job = std::make_unique<Job>();
     job->p = *p;

@@ -11,6 +11,7 @@
 // order, by a ballot prefix sum) so that the rare scattering work runs on
 // fully occupied lanes; children of ionizations are staged per chunk in
 // parent order.
+#include "hd.h"
 #include "hd_device.h"
 
 namespace hd {
@@ -565,25 +566,84 @@ __device__ __forceinline__ double ion_temperature(const Disch<P>& d, double mu, 
   return d.TN + d.kappa * (x * x);
 }
 
+// Fitted He+ transport in He at atmospheric pressure (Sec. III): mobility
+// versus |E| (Table 2, branch change at E0 = 1.47e6 V/m) and momentum-exchange
+// frequency versus |u| (Table 3, branch change at u0 = 2e3 m/s).  The
+// non-integer powers go through fit_log / fit_exp, whose steps are fixed so
+// that any implementation of the same steps rounds identically: ln x by
+// binary-exponent reduction of x to m in [sqrt(1/2), sqrt(2)) and the atanh
+// series of s = (m - 1)/(m + 1) through s^21; exp y by Cody-Waite reduction
+// y = k ln2 + r (ln2 split into a head exact in k ln2 and a tail) and the
+// Taylor series of e^r through r^14, scaled by 2^k.
+__device__ __forceinline__ double fit_log(double x) {
+  int e;
+  double m = frexp(x, &e);  // x = m 2^e, m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double acc = 1.0 / 21.0;
+#pragma unroll
+  for (int odd = 19; odd >= 1; odd -= 2) acc = acc * s2 + 1.0 / (double)odd;
+  return (double)e * 0.69314718055994530942 + (2.0 * s) * acc;
+}
+
+__device__ __forceinline__ double fit_exp(double y) {
+  const double k = rint(y * 1.44269504088896340736);
+  const double r = (y - k * 6.93147180369123816490e-01) - k * 1.90821492927058770002e-10;
+  double fact[15];  // n! for n = 0..14, exact in double
+  fact[0] = 1.0;
+#pragma unroll
+  for (int n = 1; n <= 14; ++n) fact[n] = fact[n - 1] * (double)n;
+  double acc = 1.0 / fact[14];
+#pragma unroll
+  for (int n = 13; n >= 0; --n) acc = acc * r + 1.0 / fact[n];
+  return ldexp(acc, (int)k);
+}
+
+__device__ __forceinline__ double fit_pow(double x, double y) {
+  return x > 0.0 ? fit_exp(y * fit_log(x)) : 0.0;
+}
+
+// Table 2 [m^2/(V s)]
+__device__ __forceinline__ double mobility_fit(double E) {
+  const double a = fabs(E), E0 = 1.47e6;
+  if (a < E0) return 1e-3 * (1.18 - 0.185 * (a / E0));
+  return 1e-3 * (0.94 * fit_pow(E0 / a, 0.3));
+}
+
+// Table 3 [1/s]
+__device__ __forceinline__ double nu_fit(double u) {
+  const double a = fabs(u), u0 = 2e3;
+  if (a < u0) return 1e10 * (2.07 + 0.88 * fit_pow(a / u0, 1.89));
+  return 1e10 * (1.54 + 1.36 * (a / u0));
+}
+
 // Drift-diffusion, explicit: Eq (2.5) with Eqs (2.7)-(2.8) and central
 // differences, field-switched drift flux at the walls, then Eq (2.4) with
-// half cells at the walls.  Gamma goes through LDS; n is updated in place
-// after a barrier (each node then reads only its own old density).
+// half cells at the walls.  The mobility is constant or, with the fitted
+// transport, Table 2 at each node's own field.  Gamma goes through LDS; n is
+// updated in place after a barrier (each node then reads only its own old
+// density).
 template <class P>
 __device__ void fluid_dd(const Disch<P>& d, double* lds) {
   const int tid = threadIdx.x, nc = d.nc, nn = d.nn;
   double* __restrict__ ni = d.ni;
   const double* __restrict__ E = d.E;
   double* G = lds;
-  const double mu = d.mu;
+  const bool fit = d.ion_model == HD_ION_DD_FIT_MU;
   for (int j = tid; j < nn; j += kElecThreads) {
+    const double ej = E[j];
+    const double mu = fit ? mobility_fit(ej) : d.mu;
     double g;
     if (j == 0) {
-      g = (mu * ni[0]) * dmin0(E[0]);
+      g = (mu * ni[0]) * dmin0(ej);
     } else if (j == nc) {
-      g = (mu * ni[nc]) * dmax0(E[nc]);
+      g = (mu * ni[nc]) * dmax0(ej);
     } else {
-      const double nl = ni[j - 1], nj = ni[j], nr = ni[j + 1], ej = E[j];
+      const double nl = ni[j - 1], nj = ni[j], nr = ni[j + 1];
       const double T = ion_temperature(d, mu, ej);
       const double Dc = (mu * T) / kECharge;
       g = (mu * nj) * ej - (Dc * (nr - nl)) * d.inv_2dz;
@@ -610,10 +670,12 @@ __device__ void fluid_dd(const Disch<P>& d, double* lds) {
 }
 
 // Full fluid: Eq (2.3) for Gamma^{n+1/2} with lagged nu and semi-implicit
-// advection (tridiagonal; Thomas method, one reciprocal per row), drift wall
-// fluxes with mu = e/(M nu) (Eq 2.6), then Eq (2.4).  Each row reads the
-// old n, Gamma and E of its neighbours directly; the coefficients live in
-// LDS for the serial elimination.
+// advection (tridiagonal, partitioned solve), drift wall fluxes with
+// mu = e/(M nu) (Eq 2.6), then Eq (2.4).  nu is constant or, with the fitted
+// transport, Table 3 at each node's lagged u.  Each row reads the old n,
+// Gamma and E of its neighbours directly and re-derives their nu (the
+// per-node values would not fit in LDS beside the coefficients at the
+// largest grids); the coefficients live in LDS for the solve.
 template <class P>
 __device__ __forceinline__ double lagged_u(const Disch<P>& d, double n, double g) {
   return (n > d.nfloor) ? g / n : 0.0;
@@ -625,7 +687,9 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
   double* __restrict__ ni = d.ni;
   double* __restrict__ gam = d.gam;
   const double* __restrict__ E = d.E;
-  const double nu = d.nu, mu = d.mu_full;
+  const bool fit = d.ion_model == HD_ION_FULL_FIT_NU;
+  // mu = e/(M nu) at a node with lagged speed u
+  auto mu_at = [&](double u) { return fit ? kECharge / (d.M * nu_fit(u)) : d.mu_full; };
   double* La = lds;
   double* Lb = La + nn;
   double* Lc = Lb + nn;
@@ -635,15 +699,16 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
     const double gl_ = gam[j - 1], gj = gam[j], gr_ = gam[j + 1];
     const double el = E[j - 1], ej = E[j], er = E[j + 1];
     const double ul = lagged_u(d, nl, gl_), ur = lagged_u(d, nr, gr_);
-    const double Tl = ion_temperature(d, mu, el), Tr = ion_temperature(d, mu, er);
+    const double nu = fit ? nu_fit(lagged_u(d, nj, gj)) : d.nu;
+    const double Tl = ion_temperature(d, mu_at(ul), el), Tr = ion_temperature(d, mu_at(ur), er);
     const int k = j - 1;
     La[k] = -d.dt_2dz * ul;
     Lb[k] = 1.0 + nu * d.hdt;
     Lc[k] = d.dt_2dz * ur;
     Lr[k] = (gj * (1.0 - nu * d.hdt) + (d.e_M_dt * nj) * ej) - d.dt_2dzM * (nr * Tr - nl * Tl);
   }
-  const double gl = (mu * ni[0]) * dmin0(E[0]);
-  const double gr = (mu * ni[nc]) * dmax0(E[nc]);
+  const double gl = (mu_at(lagged_u(d, ni[0], gam[0])) * ni[0]) * dmin0(E[0]);
+  const double gr = (mu_at(lagged_u(d, ni[nc], gam[nc])) * ni[nc]) * dmax0(E[nc]);
   __syncthreads();
   if (tid == 0) {
     Lr[0] = Lr[0] - La[0] * gl;
@@ -678,7 +743,7 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
   if ((int)blockIdx.x < D) {
     const Disch<P>& d = ds[blockIdx.x];
     if (d.st->steps_left > 0) {
-      if (d.ion_model == 0)
+      if (d.ion_model == HD_ION_DD_CONST_MU || d.ion_model == HD_ION_DD_FIT_MU)
         fluid_dd<P>(d, reinterpret_cast<double*>(smem));
       else
         fluid_full<P>(d, reinterpret_cast<double*>(smem));

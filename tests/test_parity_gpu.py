@@ -90,7 +90,7 @@ def test_initial_state_matches(precision, model):
     compare(dev.moments(), dev.particles(), orc, dev.push_field())
 
 
-@pytest.mark.parametrize("precision,model", [(1, 0), (0, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("precision,model", [(1, 0), (0, 0), (0, 1), (1, 1), (0, 2), (1, 3)])
 def test_steps_match_small(precision, model):
     # 5,000 electrons = 4 full chunks and a ragged one; 40 steps cross two sorts
     # and two EEDF samples, single steps and captured intervals.
@@ -109,6 +109,46 @@ def test_ionization_emission_and_walls_match(precision, model):
     dev, orc = run_pair(_hot(precision, model), 48, chunks=[3, 16, 29])
     c = orc.counters()
     assert c["created"] > 0 and c["emitted"].sum() > 0 and c["absorbed"].sum() > 0
+
+
+def _fit_case(precision, model):
+    base = dict(precision=precision, ion_model=model, n_cells=64, n_macro=20_000, t_e0_eV=50.0,
+                phase_rad=np.pi / 2, gamma_see=1.0, load_lo=0.0, load_hi=1.0)
+    if model == W.ION_DD_FIT:
+        # the vacuum field sits just above the Table 2 branch field; the
+        # space charge of the escaping electrons pulls part of the gap below
+        return W.small(v_amp_V=184.0, n_e0_m3=1e19, **base), [1, 15, 32]
+    # the ions accelerate through the Table 3 branch speed near step 160
+    return W.small(v_amp_V=4000.0, mu_const=8e-3, **base), [1, 31, 64, 128]
+
+
+@pytest.mark.parametrize("precision,model", [(0, W.ION_DD_FIT), (1, W.ION_FULL_FIT),
+                                             (0, W.ION_FULL_FIT), (1, W.ION_DD_FIT)])
+def test_fitted_transport_matches(precision, model):
+    p, chunks = _fit_case(precision, model)
+    dev, orc = run_pair(p, sum(chunks), chunks=chunks)
+    g = orc.grid()
+    if model == W.ION_DD_FIT:
+        a, x0 = np.abs(g["E"]), 1.47e6
+    else:
+        n = g["n_i"]
+        a = np.abs(np.where(n > orc.derived()["nfloor"], g["gamma"] / np.maximum(n, 1e-300), 0.0))
+        x0 = 2e3
+    # both branches of the fit were taken on the last step
+    assert (a < x0).sum() >= 5 and (a >= x0).sum() >= 5
+
+
+def test_mixed_ion_models_in_one_batch():
+    # one launch advances constant and fitted, drift-diffusion and full fluids
+    ps = [_fit_case(0, m)[0] for m in (W.ION_DD_FIT, W.ION_FULL_FIT)]
+    ps = [_hot(0, W.ION_DD, seed=40), _hot(0, W.ION_FULL, seed=41)] + ps
+    b = hd.Batch(ps)
+    b.step(7)
+    b.step(16)
+    for i, p in enumerate(ps):
+        orc = oracle.Oracle(p)
+        orc.step(23)
+        compare(b.moments(i), b.particles(i), orc)
 
 
 def test_many_chunks_per_workgroup_and_sparse_eedf():

@@ -87,6 +87,31 @@ def test_misfit_jobs_rejected():
     with pytest.raises(hd.HdError) as e:
         srv.submit(_job(128, 40_000_000, 1, 100.0), 10)  # alone larger than the budget
     assert e.value.code == -2
+    for model in (W.ION_FULL, W.ION_FULL_FIT):  # slots without the full fluid's LDS
+        with pytest.raises(hd.HdError) as e:
+            srv.submit(_job(64, 1000, 1, 100.0, model), 10)
+        assert e.value.code == -1
+    srv.close()
+
+
+def test_all_ion_models_in_the_mix():
+    specs = [(64, 3000, 51, 150.0, 30, W.ION_DD), (96, 2500, 52, 200.0, 20, W.ION_FULL),
+             (128, 4000, 53, 250.0, 40, W.ION_DD_FIT), (80, 3500, 54, 300.0, 25, W.ION_FULL_FIT)]
+    srv = hd.Server(precision=0, max_slots=4, max_cells=256, allow_full_fluid=True)
+    ids = [(srv.submit(_job(nc, nm, seed, v, model), steps), nc, nm, seed, v, steps, model)
+           for nc, nm, seed, v, steps, model in specs]
+    srv.drain(300)
+    st = srv.stats()
+    assert st["completed"] == len(specs) and st["failed"] == 0 and st["error"] == 0
+    for jid, nc, nm, seed, v, steps, model in ids:
+        state, _, mix = srv.poll(jid)
+        assert state == 2
+        o = oracle.Oracle(_job(nc, nm, seed, v, model))
+        o.step(steps)
+        g = o.grid()
+        for k, ok in (("cnt", "cnt"), ("n_i", "n_i"), ("E", "E"), ("gamma_i", "gamma")):
+            np.testing.assert_array_equal(mix[k], g[ok], err_msg=k)
+        assert mix["pushed"] == o.counters()["pushed"]
     srv.close()
 
 
