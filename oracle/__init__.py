@@ -60,6 +60,7 @@ class _Params(C.Structure):
         ("gamma_see", C.c_double), ("e_sec_eV", C.c_double),
         ("m_ion_amu", C.c_double), ("mu_const", C.c_double), ("nu_const", C.c_double),
         ("dt_s", C.c_double), ("inv_de_per_eV", C.c_double), ("eedf_emax_eV", C.c_double),
+        ("power_W_m2", C.c_double), ("power_alpha", C.c_double),
         ("channels", C.POINTER(_Channel)),
     ]
 
@@ -89,6 +90,7 @@ def lib():
             L.orc_get_accum.argtypes = [vp, vp, vp, vp]
             L.orc_get_derived.argtypes = [vp, vp]
             L.orc_get_table.argtypes = [vp, vp]
+            L.orc_get_power.argtypes = [vp, vp]
             L.orc_last_error.restype = C.c_char_p
             L.orc_philox4x32_10.argtypes = [vp, vp, vp]
             L.orc_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
@@ -219,6 +221,14 @@ class Oracle:
         keys = ["dz", "w", "nu_max", "Pmax", "KE", "invKE", "kdz", "delta", "keedf", "qm_dt",
                 "kappa", "TN", "M", "nfloor"]
         return dict(zip(keys, v.tolist()))
+
+    def power(self) -> dict:
+        """Drive state: amplitude of the coming levels, P_abs of the last RF
+        period [W/m^2], completed periods, steps per period, running sum."""
+        v = np.empty(5)
+        lib().orc_get_power(self.h, _p(v))
+        return {"volt_amp": v[0], "p_abs": v[1], "rf_periods": int(v[2]), "rf_steps": int(v[3]),
+                "pw_sum": v[4]}
 
     def table(self) -> np.ndarray:
         t = np.empty(self.params["n_energy"] * self.K)

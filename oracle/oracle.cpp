@@ -89,6 +89,8 @@ typedef struct orc_params {
   double dt_s;
   double inv_de_per_eV;
   double eedf_emax_eV;
+  double power_W_m2;   // P_0 of Eq 2.9 per electrode area; 0: fixed amplitude
+  double power_alpha;  // alpha of Eq 2.9
   const orc_channel* channels;
 } orc_params;
 
@@ -206,7 +208,10 @@ bool derive(const orc_params& p, Derived& d) {
       p.sort_every < 1 || p.eedf_every < 1 || p.n_eedf_bins < 1 || p.n_macro < 0 ||
       !(p.gap_m > 0) || !(p.dt_s > 0) || !(p.inv_de_per_eV > 0) || !(p.load_hi > p.load_lo) ||
       p.load_lo < 0 || p.load_hi > 1 || (p.ion_model < 0 || p.ion_model > 3) ||
-      (p.precision != 0 && p.precision != 1) || (p.n_channels > 0 && !p.channels)) {
+      (p.precision != 0 && p.precision != 1) || (p.n_channels > 0 && !p.channels) ||
+      !(p.power_W_m2 >= 0) || !std::isfinite(p.power_W_m2) || !(p.power_alpha >= 0) ||
+      !std::isfinite(p.power_alpha) ||
+      (p.power_W_m2 > 0 && !(p.f_rf_Hz > 0 && 1.0 / (p.f_rf_Hz * p.dt_s) >= 1.5))) {
     g_err = "invalid parameters";
     return false;
   }
@@ -846,6 +851,13 @@ struct Base {
   std::vector<double> acc_ni;
   uint64_t n_acc = 0;
   Counters ctr;
+  // RF drive and absorbed power (Sec. II.D, Eq 2.9)
+  int64_t rf_steps = 0;     // steps per RF period, round(1/(f dt)); 0: none
+  double amp = 0.0;         // amplitude for the levels after the current one
+  double V_cur = 0.0;       // electrode voltage of the current level
+  double pw_sum = 0.0;      // the current period's sum of interval powers
+  double p_abs = 0.0;       // P_abs of the last completed period
+  int64_t rf_periods = 0;
   virtual ~Base() {}
   virtual int do_step() = 0;
   virtual int64_t count() const = 0;
@@ -854,13 +866,51 @@ struct Base {
   virtual void set_particles(int64_t, const int32_t*, const void*, const void*, const void*,
                              const void*, const uint32_t*) = 0;
 
-  double volt(int64_t n) const {
+  // V(t_n) = U sin(2 pi f t_n + phase) at z = 0; this is the sine factor.
+  double wave(int64_t n) const {
     const double two_pi_f = 2.0 * kPi * p.f_rf_Hz;
     const double t = (double)n * p.dt_s;
-    return p.v_amp_V * std::sin(two_pi_f * t + p.phase_rad);
+    return std::sin(two_pi_f * t + p.phase_rad);
+  }
+  void init_drive() {
+    if (p.f_rf_Hz > 0) {
+      const double r = 1.0 / (p.f_rf_Hz * p.dt_s);
+      rf_steps = r < 4.0e18 ? (int64_t)std::llround(r) : 0;
+    }
+    amp = p.v_amp_V;
+    V_cur = amp * wave(0);
   }
   void field() {
-    field_solve(d, cnt.data(), ni.data(), volt(step), ne.data(), rho.data(), phi.data(), E.data());
+    field_solve(d, cnt.data(), ni.data(), V_cur, ne.data(), rho.data(), phi.data(), E.data());
+  }
+
+  // After step n (step already advanced to n+1): the power delivered at the
+  // driven electrode z = 0 over [t_n, t_n+1] is the mean voltage times the
+  // total current density there: conduction e (Gamma_i - Gamma_e), with the
+  // ion wall flux gi0 of the step and Gamma_e from the electrons emitted
+  // minus absorbed at z = 0 during the step, plus displacement eps0 dE_0/dt.
+  // It is added to the period containing t_n+1; a period ends at the levels
+  // that are multiples of rf_steps, and its mean is P_abs of Eq 2.9, which
+  // rescales the amplitude of the following levels when P_0 > 0.
+  void power_step(double gi0, uint64_t abs_before, uint64_t emi_before) {
+    const double e0_old = E[0];  // field of level n (solved at the step's start)
+    const double v_old = V_cur;
+    const double v_new = amp * wave(step);
+    field_solve(d, cnt.data(), ni.data(), v_new, ne.data(), rho.data(), phi.data(), E.data());
+    const double dn =
+        (double)(ctr.emitted[0] - emi_before) - (double)(ctr.absorbed[0] - abs_before);
+    const double ge = (d.w * dn) / p.dt_s;
+    const double jc = kE * (gi0 - ge);
+    const double jd = kEps0 * ((E[0] - e0_old) / p.dt_s);
+    pw_sum = pw_sum + (0.5 * (v_old + v_new)) * (jc + jd);
+    V_cur = v_new;
+    if (rf_steps > 0 && step % rf_steps == 0) {
+      const double pa = pw_sum / (double)rf_steps;
+      p_abs = pa;
+      rf_periods += 1;
+      if (p.power_W_m2 > 0) amp = amp * (1.0 - p.power_alpha * ((pa - p.power_W_m2) / p.power_W_m2));
+      pw_sum = 0.0;
+    }
   }
 };
 
@@ -886,6 +936,7 @@ struct Discharge : Base {
     acc_ni.assign(nn, 0.0);
     eedf.assign((size_t)p.n_eedf_bins + 1, 0);
     load();
+    init_drive();
     // Ions start equal to the deposited electron density, so the net charge
     // is exactly zero at t = 0; Gamma^{-1/2} = 0.
     for (int j = 0; j < nn; ++j) ni[j] = (double)cnt[j] * d.scale[j];
@@ -1015,6 +1066,7 @@ struct Discharge : Base {
   //  by cell.
   int do_step() override {
     const uint32_t n = (uint32_t)step;
+    const uint64_t abs_before = ctr.absorbed[0], emi_before = ctr.emitted[0];
     field();
     for (int j = 0; j < d.nn; ++j) Ep[j] = (P)(d.qm_dt * E[j]);
     double gw[2];
@@ -1080,6 +1132,7 @@ struct Discharge : Base {
                        [](const Particle<P>& x, const Particle<P>& y) { return x.c < y.c; });
       parts.swap(live);
     }
+    power_step(gw[0], abs_before, emi_before);
     return 0;
   }
 
@@ -1097,7 +1150,7 @@ struct Discharge : Base {
   }
   void get_ep(void* out) const override {
     std::vector<double> ne2(d.nn), rho2(d.nn), phi2(d.nn), E2(d.nn);
-    field_solve(d, cnt.data(), ni.data(), volt(step), ne2.data(), rho2.data(), phi2.data(),
+    field_solve(d, cnt.data(), ni.data(), V_cur, ne2.data(), rho2.data(), phi2.data(),
                 E2.data());
     for (int j = 0; j < d.nn; ++j) ((P*)out)[j] = (P)(d.qm_dt * E2[j]);
   }
@@ -1203,7 +1256,7 @@ void orc_get_grid(void* h, int64_t* cnt, double* ni, double* gam, double* ne, do
   Base* b = static_cast<Base*>(h);
   const int nn = b->d.nn;
   std::vector<double> ne2(nn), rho2(nn), phi2(nn), E2(nn);
-  field_solve(b->d, b->cnt.data(), b->ni.data(), b->volt(b->step), ne2.data(), rho2.data(),
+  field_solve(b->d, b->cnt.data(), b->ni.data(), b->V_cur, ne2.data(), rho2.data(),
               phi2.data(), E2.data());
   for (int j = 0; j < nn; ++j) {
     if (cnt) cnt[j] = b->cnt[j];
@@ -1276,6 +1329,17 @@ void orc_thomas(int n, const double* a, const double* b, const double* c, const 
 void orc_solve_tridiag(int n, const double* a, const double* b, const double* c, const double* d,
                        double* x) {
   solve_tridiag(n, a, b, c, d, x);
+}
+
+// [amplitude U of the coming levels, P_abs of the last period, completed
+//  periods, steps per period, the current period's running sum]
+void orc_get_power(void* h, double* out) {
+  Base* b = static_cast<Base*>(h);
+  out[0] = b->amp;
+  out[1] = b->p_abs;
+  out[2] = (double)b->rf_periods;
+  out[3] = (double)b->rf_steps;
+  out[4] = b->pw_sum;
 }
 
 double orc_fit_ln(double x) { return fit_ln(x); }

@@ -67,6 +67,7 @@ def base_params(**over) -> dict:
         gamma_see=0.1, e_sec_eV=2.0,
         m_ion_amu=HE_AMU, mu_const=1.0e-3, nu_const=3e9,
         dt_s=2e-14, inv_de_per_eV=10.0, eedf_emax_eV=50.0,
+        power_W_m2=0.0, power_alpha=0.0,
         capacity=0,
     )
     p.update(over)

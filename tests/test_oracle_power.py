@@ -1,0 +1,129 @@
+"""Pins of the oracle's absorbed power and power control (Sec. II.D, Eq 2.9):
+a vacuum gap absorbs no power over whole periods, a resistive ion load
+absorbs the ohmic power, the total current at the driven electrode
+equals the one at the grounded electrode (so every term of the conduction
+and displacement currents carries the right sign and scale), and the
+amplitude update of Eq 2.9 settles at the amplitude that delivers P_0."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_02892_amd import workloads as W
+
+E_CH = 1.602176634e-19
+EPS0 = 8.8541878128e-12
+
+
+def _gap(nt=1000, dt=1e-12, v=100.0, phase=0.0, nc=64, **kw):
+    # no electrons and (unless set) no ions: n_macro = 0; RF period nt steps
+    return W.small(n_cells=nc, n_macro=0, gap_m=1e-3, dt_s=dt, f_rf_Hz=1.0 / (nt * dt),
+                   v_amp_V=v, phase_rad=phase, **kw)
+
+
+@pytest.mark.parametrize("phase", [0.0, 0.7])
+def test_vacuum_gap_absorbs_nothing(phase):
+    # purely displacement current: the period sum of V eps0 dE/dt telescopes
+    p = _gap(phase=phase)
+    o = oracle.Oracle(p)
+    assert o.power()["rf_steps"] == 1000
+    reactive = EPS0 * (2 * math.pi * p["f_rf_Hz"]) * 100.0 ** 2 / (2 * 1e-3)  # ~2.8e5 W/m^2
+    for k in range(1, 3):
+        o.step(1000)
+        pw = o.power()
+        assert pw["rf_periods"] == k
+        assert abs(pw["p_abs"]) < 1e-10 * reactive
+        assert pw["volt_amp"] == 100.0
+
+
+def _resistive(mu=1e-5, n=1e15, nc=64, **kw):
+    o = oracle.Oracle(_gap(mu_const=mu, nc=nc, **kw))
+    o.set_ions(np.full(nc + 1, n), np.zeros(nc + 1))
+    return o
+
+
+def test_resistive_ion_load_absorbs_ohmic_power():
+    # Uniform ions, constant mobility, no electrons: a resistor of
+    # conductivity e mu n.  Current continuity carries the bulk current
+    # e mu n V/L to the electrode (the wall flux is one-sided, the space
+    # charge of the wall half cell supplies the rest as displacement
+    # current), so the delivered power is e mu n V0^2 / (2L), reached to
+    # first order in the cell size (the wall half cells).
+    mu, n, V0, L = 1e-5, 1e15, 100.0, 1e-3
+    ohmic = E_CH * mu * n * V0 ** 2 / (2 * L)
+    err = {}
+    for nc in (64, 256):
+        o = _resistive(mu, n, nc=nc, v=V0)
+        o.step(2000)
+        err[nc] = abs(o.power()["p_abs"] / ohmic - 1)
+    assert err[256] < 3e-3
+    assert 3.0 < err[64] / err[256] < 5.0
+
+
+def _k_eff(mu, n, v):
+    # delivered power per squared amplitude of the resistive load near v (the
+    # ions' own space-charge field adds a small term linear in the amplitude)
+    o = _resistive(mu, n, v=v)
+    o.step(2000)
+    return o.power()["p_abs"] / v ** 2
+
+
+def test_period_boundary_keeps_its_amplitude():
+    # the level that closes a period is still driven with that period's
+    # amplitude; the next one already with the updated amplitude
+    o = _resistive(v=100.0, power_W_m2=1e-3, power_alpha=0.3)
+    o.step(999)
+    assert o.power()["volt_amp"] == 100.0
+    o.step(1)
+    pw = o.power()
+    assert pw["rf_periods"] == 1 and pw["volt_amp"] != 100.0
+    wave = math.sin(2 * math.pi * (1e9 * (1000 * 1e-12)))
+    assert o.grid()["phi"][0] == pytest.approx(100.0 * wave, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("start", [0.5, 1.6])
+def test_power_control_settles_at_target(start):
+    # P = k U^2 for the resistive load, so Eq 2.9 converges to U* = sqrt(P0/k)
+    # (the error shrinks by |1 - 2 alpha| per period)
+    mu, n, P0 = 1e-5, 1e15, 2e-3
+    u_star = math.sqrt(P0 / _k_eff(mu, n, 50.0))
+    o = _resistive(mu, n, v=start * u_star, power_W_m2=P0, power_alpha=0.3)
+    for _ in range(16):
+        o.step(1000)
+    pw = o.power()
+    assert pw["rf_periods"] == 16
+    assert pw["volt_amp"] == pytest.approx(u_star, rel=1e-3)
+    assert pw["p_abs"] == pytest.approx(P0, rel=2e-3)
+
+
+@pytest.mark.parametrize("model", [W.ION_DD, W.ION_FULL])
+def test_total_current_is_the_same_at_both_electrodes(model):
+    # Discrete Gauss over the gap makes eps0 (E_N - E_0) the enclosed charge,
+    # which changes only by the wall fluxes of ions and electrons; so the
+    # total current e (Gamma_i - Gamma_e) + eps0 dE/dt at z = 0 (from the
+    # power sum) must equal the one at z = L (from the right-wall counters,
+    # the ion flux and E_N), step by step, with ionization and emission on.
+    p = W.small(precision=1, ion_model=model, n_cells=64, n_macro=20_000, t_e0_eV=50.0,
+                v_amp_V=2000.0, phase_rad=math.pi / 2, gamma_see=1.0, load_lo=0.0,
+                load_hi=1.0, mu_const=8e-3)
+    o = oracle.Oracle(p)
+    w, dt = o.derived()["w"], p["dt_s"]
+    g0, c0, pw0 = o.grid(), o.counters(), o.power()
+    seen_e = 0
+    for _ in range(40):
+        o.step(1)
+        g1, c1, pw1 = o.grid(), o.counters(), o.power()
+        vm = 0.5 * (g0["phi"][0] + g1["phi"][0])
+        J0 = (pw1["pw_sum"] - pw0["pw_sum"]) / vm
+        d_abs = int(c1["absorbed"][1]) - int(c0["absorbed"][1])
+        d_emi = int(c1["emitted"][1]) - int(c0["emitted"][1])
+        seen_e += d_abs + d_emi
+        ge_N = w * (d_abs - d_emi) / dt  # electrons moving in +z at z = L
+        jc = E_CH * (g1["gamma"][-1] - ge_N)
+        jd = EPS0 * (g1["E"][-1] - g0["E"][-1]) / dt
+        JL = jc + jd
+        scale = abs(jc) + abs(jd) + abs(EPS0 * (g1["E"][0] - g0["E"][0]) / dt)
+        assert abs(J0 - JL) <= 1e-7 * scale  # the field solve rounds at ~1e-9
+        g0, c0, pw0 = g1, c1, pw1
+    assert seen_e > 0
