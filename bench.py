@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--ion", choices=["default", "dd", "full", "dd-fit", "full-fit"],
                     default="default",
                     help="override the ion model of the workload (diagnostic variants)")
+    ap.add_argument("--power-w-m2", type=float, default=0.0,
+                    help="enable power control (Eq 2.9) with this P_0 per electrode area")
+    ap.add_argument("--power-alpha", type=float, default=0.05)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration runs)")
     ap.add_argument("--rate", type=float, default=2.0, help="served stream: jobs/s")
@@ -227,6 +230,9 @@ def main():
             "dd-fit": (2, "drift-diffusion, mobility of Table 2"),
             "full-fit": (3, "full fluid, nu of Table 3")}[a.ion]
         desc += "; ion model overridden: %s" % name
+    if a.power_w_m2 > 0:
+        p["power_W_m2"], p["power_alpha"] = a.power_w_m2, a.power_alpha
+        desc += "; power control P_0 = %g W/m^2, alpha = %g" % (a.power_w_m2, a.power_alpha)
     if a.electrons:
         from paper_1508_02892_amd import workloads as W
         p = W.scaled(p, a.electrons)

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define HD_ABI_VERSION 1
+#define HD_ABI_VERSION 2
 
 enum hd_status {
   HD_OK = 0,
@@ -96,7 +96,8 @@ typedef struct hd_params {
   double n_gas_m3, t_gas_K, m_gas_amu;
   /* geometry */
   double gap_m;
-  /* drive: V(t) = v_amp_V sin(2 pi f_rf_Hz t + phase_rad) at z = 0 */
+  /* drive: V(t_n) = U sin(2 pi f_rf_Hz t_n + phase_rad) at z = 0, t_n = n dt_s,
+     U = v_amp_V unless power control (below) adjusts it */
   double v_amp_V, f_rf_Hz, phase_rad;
   /* electron load: uniform in [load_lo L, load_hi L), Maxwellian t_e0_eV;
      superparticle weight from Eq 1.2 */
@@ -109,6 +110,18 @@ typedef struct hd_params {
   double dt_s;
   double inv_de_per_eV;  /* collision-table points per eV                    */
   double eedf_emax_eV;
+  /* Power control (Sec. II.D, Eq 2.9).  An RF period is round(1/(f_rf_Hz
+     dt_s)) steps.  Every step adds to the period's sum the power delivered
+     at z = 0 over [t_n, t_n+1]: (V_n + V_n+1)/2 times the current density
+     e (Gamma_i - Gamma_e) + eps0 (E_0^{n+1} - E_0^n)/dt_s, with Gamma_i the
+     ion wall flux of the step and Gamma_e = w (emitted - absorbed electrons
+     at z = 0 in the step)/dt_s; the interval counts for the period that
+     holds t_n+1.  P_abs = sum / steps per period.  With power_W_m2 > 0 the
+     amplitude of the next period is U (1 - power_alpha (P_abs - P_0)/P_0),
+     P_0 = power_W_m2; with 0 the amplitude stays v_amp_V (P_abs is still
+     reported).  power_W_m2 > 0 needs a period of at least 2 steps. */
+  double power_W_m2;     /* P_0 / S, prescribed absorbed power [W/m^2], >= 0 */
+  double power_alpha;    /* alpha of Eq 2.9, >= 0                            */
   const hd_xs_channel* channels; /* n_channels entries, caller-owned, copied */
 } hd_params;
 
@@ -151,6 +164,9 @@ typedef struct hd_moment_set {
   uint64_t n_acc;          /* steps in the averages                          */
   uint64_t pushed;         /* particle-steps: live electrons pushed, summed
                               over all steps so far                          */
+  double volt_amp;         /* drive amplitude U of the coming steps [V]      */
+  double p_abs;            /* P_abs of the last completed RF period [W/m^2]  */
+  int64_t rf_periods;      /* completed RF periods                           */
 } hd_moment_set;
 
 typedef struct hd_batch hd_batch;

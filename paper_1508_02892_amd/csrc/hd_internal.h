@@ -52,6 +52,13 @@ struct State {
   uint64_t see_clamped;
   uint64_t n_acc;
   uint64_t pushed;  // live particles pushed (particle-steps) since creation
+  // RF drive and absorbed power (Eq 2.9)
+  double volt_amp;     // amplitude of the current RF period [V]
+  double pw_sum;       // sum over the current period's steps of V J [W/m^2]
+  double p_abs;        // period-averaged absorbed power of the last period [W/m^2]
+  int64_t rf_periods;  // completed RF periods
+  uint64_t pw_abs0;    // electrons absorbed at z = 0 up to the end of the last step
+  uint64_t pw_emi0;    // secondaries emitted at z = 0 up to the end of the last step
 };
 
 // Immutable constants and device pointers of one discharge.
@@ -72,11 +79,13 @@ struct Disch {
   double dz, L, w, kp, inv_dz, inv_2dz, hdz_eps, qm_dt, scale_in, scale_wall;
   double mu, nu, mu_full, TN, kappa, M, dt, dt_2dz, dt_dz, e_M_dt, dt_2dzM, hdt, nfloor;
   double gamma_see, see_v;  // emission coefficient and speed sqrt(E_sec 2e/m_e)
+  double power_P0, power_alpha;  // Eq 2.9 (power_P0 = 0: fixed amplitude)
+  int64_t rf_steps;              // steps per RF period (0: no period ends)
   int64_t volt_len;
   // tables
   const double* ip;    // [nn] inverse Thomas pivots of the Poisson matrix
   const P* tab;        // [ne*K] cumulative collision probabilities
-  const double* volt;  // [volt_len] electrode voltage per step
+  const double* volt;  // [volt_len] unit drive waveform sin(2 pi f t_n + phase) per step
   // particles: two buffers for out-of-place sorting
   int32_t* cell[2];
   P* off[2];

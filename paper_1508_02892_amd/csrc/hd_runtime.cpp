@@ -111,6 +111,13 @@ struct HostStream {
   }
 };
 
+// Steps per RF period, round(1 / (f dt)); 0 without a drive frequency.
+int64_t rf_steps_of(const hd_params& p) {
+  if (!(p.f_rf_Hz > 0)) return 0;
+  const double r = 1.0 / (p.f_rf_Hz * p.dt_s);
+  return r < 4.0e18 ? (int64_t)std::llround(r) : 0;
+}
+
 // Ion models that solve Eq (2.3) (tridiagonal scratch in LDS).
 bool full_fluid(int32_t m) { return m == HD_ION_FULL_CONST_NU || m == HD_ION_FULL_FIT_NU; }
 
@@ -145,6 +152,11 @@ bool validate(const hd_params* p, std::string& why) {
     return (why = "gas / ion parameters"), false;
   if (p->ion_model == HD_ION_FULL_CONST_NU && !(p->nu_const > 0)) return (why = "nu_const"), false;
   if (!(p->gamma_see >= 0) || !(p->e_sec_eV >= 0)) return (why = "emission parameters"), false;
+  if (!(p->power_W_m2 >= 0) || !std::isfinite(p->power_W_m2) || !(p->power_alpha >= 0) ||
+      !std::isfinite(p->power_alpha))
+    return (why = "power control parameters"), false;
+  if (p->power_W_m2 > 0 && rf_steps_of(*p) < 2)
+    return (why = "power control needs an RF period of at least 2 steps"), false;
   return true;
 }
 
@@ -294,6 +306,10 @@ void derive(Host<P>& h, std::vector<double>& ip, std::vector<P>& tab) {
   d.dt_2dzM = p.dt_s / (2.0 * dz * d.M);
   d.hdt = 0.5 * p.dt_s;
   d.nfloor = 1e-10 * p.n_e0_m3;
+  // drive: steps per RF period and the power control of Eq 2.9
+  d.rf_steps = rf_steps_of(p);
+  d.power_P0 = p.power_W_m2;
+  d.power_alpha = p.power_alpha;
   // emission
   d.gamma_see = p.gamma_see;
   const double invKE = 2.0 * kE / kMe;
@@ -423,10 +439,12 @@ void load(const hd_params& p, double dz, Loaded<P>& out) {
   }
 }
 
+// Unit drive waveform at step n; the device scales it by the amplitude of
+// the RF period (v_amp_V, or the power-controlled value of Eq 2.9).
 double volt_at(const hd_params& p, int64_t n) {
   const double two_pi_f = 2.0 * kPi * p.f_rf_Hz;
   const double t = (double)n * p.dt_s;
-  return p.v_amp_V * std::sin(two_pi_f * t + p.phase_rad);
+  return std::sin(two_pi_f * t + p.phase_rad);
 }
 
 }  // namespace
@@ -516,6 +534,7 @@ struct Batch : BatchBase {
     State st{};
     st.n_main = (uint32_t)N;
     st.next_id = (uint32_t)N;
+    st.volt_amp = h.p.v_amp_V;
     HD_TRY(hipMemcpyAsync(d.st, &st, sizeof(State), hipMemcpyHostToDevice, stream));
     return HD_OK;
   }
@@ -771,6 +790,9 @@ struct Batch : BatchBase {
     m->see_clamped = st.see_clamped;
     m->n_acc = st.n_acc;
     m->pushed = st.pushed;
+    m->volt_amp = st.volt_amp;
+    m->p_abs = st.p_abs;
+    m->rf_periods = st.rf_periods;
     std::vector<int64_t> cnt(nn);
     HD_TRY(hipMemcpy(cnt.data(), d.cnt[st.cbuf], nn * 8, hipMemcpyDeviceToHost));
     int64_t tot = 0;

@@ -13,6 +13,7 @@ namespace hd {
 namespace {
 
 constexpr double kECharge = 1.602176634e-19;
+constexpr double kEps0 = 8.8541878128e-12;
 constexpr int kWaves = kFinThreads / 64;
 
 // Block-wide exclusive scan of one value per thread; returns the prefix and
@@ -542,6 +543,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   const uint32_t next_id = st->next_id;
   const uint32_t seg_off = st->seg_off, seg_per = st->seg_per;
   const double wall_g = tid < 2 ? st->wall[tid] : 0.0;
+  const double amp = st->volt_amp;
   const Gp<int64_t>* gc0 = gptr(d.cnt[0]);
   const Gp<int64_t>* gc1 = gptr(d.cnt[1]);
   const Gp<double>* gni = gptr(d.ni);
@@ -586,7 +588,17 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   const int cur = field_only ? cbuf0 : (cbuf0 ^ 1);
   Gp<int64_t>* cn = gptr(d.cnt[cur]);
   const Gp<double>* volt = gptr(d.volt);
-  const double V = (step1 < d.volt_len) ? volt[step1] : 0.0;
+  const double V = amp * ((step1 < d.volt_len) ? volt[step1] : 0.0);
+  // absorbed-power bookkeeping inputs (thread 0): the field and voltage of
+  // the level this step started from and the electron counts at z = 0
+  double e0_old = 0.0, v_old = 0.0;
+  uint64_t abs0 = 0, emi0 = 0;
+  if (!field_only && tid == 0) {
+    e0_old = gptr(d.E)[0];
+    v_old = gptr(d.phi)[0];
+    abs0 = st->absorbed[0];
+    emi0 = st->emitted[0];
+  }
   // the electron launch's per-workgroup child totals of this discharge
   const uint32_t nchunk = field_only ? 0u : (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile;
   const uint32_t nch = nchunk * (uint32_t)(kTile / kSub);  // sub-chunks
@@ -631,6 +643,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       uint64_t em = 0, ab = 0, cl = 0;
       uint32_t n = 0;
       emit<P>(d, tid, F, (uint32_t)step0, CN, &n, &em, &ab, &cl);
+      abs0 += ab;  // thread 0: totals at z = 0 after this step
+      emi0 += em;
       sh_see[tid] = n;
       if (em) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->emitted[tid]), (unsigned long long)em);
       if (ab) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->absorbed[tid]), (unsigned long long)ab);
@@ -709,6 +723,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   Gp<double>* gE = gptr(d.E);
   Gp<P>* gEp = gptr(d.Ep);
   Gp<int64_t>* nxt = gptr(d.cnt[cur ^ 1]);
+  double e0_new = 0.0;
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
     const int j = tid + u * kFinThreads;
@@ -724,7 +739,31 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       gE[j] = e;
       gEp[j] = (P)(d.qm_dt * e);
       nxt[j] = 0;  // deposit target of the next step
+      if (j == 0) e0_new = e;
     }
+  }
+  if (!field_only && tid == 0) {
+    // Power delivered at the driven electrode over [t_n, t_n+1] (Eq 2.9's
+    // integrand): conduction current e (Gamma_i - Gamma_e) from the ion wall
+    // flux and the electrons that left / entered through z = 0 this step,
+    // plus the displacement current eps0 dE/dt, times the mean voltage.
+    // The interval belongs to the period that contains t_n+1; when that
+    // level ends a period, the period's mean sets the next amplitude.
+    const double dn = (double)(emi0 - st->pw_emi0) - (double)(abs0 - st->pw_abs0);
+    const double ge = (d.w * dn) / d.dt;
+    const double jc = kECharge * (wall_g - ge);
+    const double jd = kEps0 * ((e0_new - e0_old) / d.dt);
+    double sum = st->pw_sum + (0.5 * (v_old + V)) * (jc + jd);
+    st->pw_abs0 = abs0;
+    st->pw_emi0 = emi0;
+    if (d.rf_steps > 0 && step1 % d.rf_steps == 0) {
+      const double pa = sum / (double)d.rf_steps;
+      st->p_abs = pa;
+      st->rf_periods = st->rf_periods + 1;
+      if (d.power_P0 > 0.0) st->volt_amp = amp * (1.0 - d.power_alpha * ((pa - d.power_P0) / d.power_P0));
+      sum = 0.0;
+    }
+    st->pw_sum = sum;
   }
 }
 

@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhd.so")
 
-HD_ABI_VERSION = 1
+HD_ABI_VERSION = 2
 HD_MAX_CHANNELS = 16
 STATUS = {0: "HD_OK", -1: "HD_EINVAL", -2: "HD_ENOMEM", -3: "HD_EDEVICE", -4: "HD_ECAPACITY",
           -5: "HD_ENUMERIC", -6: "HD_ESTATE"}
@@ -56,6 +56,7 @@ class Params(C.Structure):
         ("load_hi", C.c_double), ("gamma_see", C.c_double), ("e_sec_eV", C.c_double),
         ("m_ion_amu", C.c_double), ("mu_const", C.c_double), ("nu_const", C.c_double),
         ("dt_s", C.c_double), ("inv_de_per_eV", C.c_double), ("eedf_emax_eV", C.c_double),
+        ("power_W_m2", C.c_double), ("power_alpha", C.c_double),
         ("channels", C.POINTER(XsChannel)),
     ]
 
@@ -78,6 +79,7 @@ class MomentSet(C.Structure):
         ("coll", C.c_uint64 * HD_MAX_CHANNELS), ("absorbed", C.c_uint64 * 2),
         ("emitted", C.c_uint64 * 2), ("created", C.c_uint64), ("e_overflow", C.c_uint64),
         ("see_clamped", C.c_uint64), ("n_acc", C.c_uint64), ("pushed", C.c_uint64),
+        ("volt_amp", C.c_double), ("p_abs", C.c_double), ("rf_periods", C.c_int64),
     ]
 
 
@@ -215,7 +217,8 @@ class _Moments:
                    absorbed=np.array(m.absorbed[:], np.uint64),
                    emitted=np.array(m.emitted[:], np.uint64), created=int(m.created),
                    overflow=int(m.e_overflow), see_clamped=int(m.see_clamped),
-                   n_acc=int(m.n_acc), pushed=int(m.pushed))
+                   n_acc=int(m.n_acc), pushed=int(m.pushed), volt_amp=float(m.volt_amp),
+                   p_abs=float(m.p_abs), rf_periods=int(m.rf_periods))
         return out
 
 

@@ -45,6 +45,10 @@ def compare(dev_m, dev_p, orc: oracle.Oracle, dev_ep=None):
     assert dev_m["n_acc"] == c["n_acc"]
     assert dev_m["pushed"] == c["pushed"]
     assert dev_m["step"] == orc.step_index
+    pw = orc.power()
+    assert dev_m["volt_amp"] == pw["volt_amp"]
+    assert dev_m["p_abs"] == pw["p_abs"]
+    assert dev_m["rf_periods"] == pw["rf_periods"]
     a = orc.accum()
     np.testing.assert_array_equal(dev_m["eedf_counts"], a["eedf"])
     if c["n_acc"]:
@@ -136,6 +140,18 @@ def test_fitted_transport_matches(precision, model):
         x0 = 2e3
     # both branches of the fit were taken on the last step
     assert (a < x0).sum() >= 5 and (a >= x0).sum() >= 5
+
+
+@pytest.mark.parametrize("precision,model", [(0, W.ION_FULL), (1, W.ION_DD), (0, W.ION_DD_FIT)])
+def test_power_control_matches(precision, model):
+    # RF periods of 20 steps, so that five amplitude updates (Eq 2.9) feed
+    # back into the field within 100 steps; ionization, emission and wall
+    # losses all carry current.  Zero phase puts the period ends at V = 0.
+    p = _hot(precision, model, f_rf_Hz=1.0 / (20 * 2e-14), power_W_m2=1e6, power_alpha=0.1)
+    p["phase_rad"] = 0.0
+    dev, orc = run_pair(p, 100, chunks=[7, 13, 20, 40, 20])
+    pw = orc.power()
+    assert pw["rf_periods"] == 5 and pw["volt_amp"] != p["v_amp_V"] and pw["p_abs"] != 0.0
 
 
 def test_mixed_ion_models_in_one_batch():
