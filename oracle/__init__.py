@@ -13,6 +13,7 @@ the uniform energy grid E_i = i / inv_de_per_eV.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import threading
@@ -91,6 +92,14 @@ def lib():
             L.orc_get_derived.argtypes = [vp, vp]
             L.orc_get_table.argtypes = [vp, vp]
             L.orc_get_power.argtypes = [vp, vp]
+            L.orc_swarm_create.restype = vp
+            L.orc_swarm_create.argtypes = [C.POINTER(_SwarmParams)]
+            L.orc_swarm_free.argtypes = [vp]
+            L.orc_swarm_run.argtypes = [vp, C.c_int64, C.c_int]
+            L.orc_swarm_get.argtypes = [vp, C.c_int] + [vp] * 5
+            L.orc_swarm_sums.argtypes = [vp, C.c_int, vp]
+            L.orc_normal_pairs.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                           C.c_int, vp]
             L.orc_last_error.restype = C.c_char_p
             L.orc_philox4x32_10.argtypes = [vp, vp, vp]
             L.orc_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
@@ -117,6 +126,17 @@ def lib():
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class _SwarmParams(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("n_fields", C.c_int32), ("n_energy", C.c_int32),
+        ("pad", C.c_int32), ("n_ions", C.c_int64), ("seed", C.c_uint64),
+        ("n_gas_m3", C.c_double), ("t_gas_K", C.c_double), ("m_ion_amu", C.c_double),
+        ("m_gas_amu", C.c_double), ("t_i0_K", C.c_double), ("dt_s", C.c_double),
+        ("inv_de_per_eV", C.c_double),
+        ("rate_m3_s", C.POINTER(C.c_double)), ("e0_V_m", C.POINTER(C.c_double)),
+    ]
 
 
 def pdtype(precision: int):
@@ -270,6 +290,73 @@ class Oracle:
                            int(cap))
         return {"cell": c[:m], "off": arrs[0][:m], "vx": arrs[1][:m], "vy": arrs[2][:m],
                 "vz": arrs[3][:m]}
+
+
+class Swarm:
+    """The auxiliary ion swarm advanced by the CPU oracle (one swarm per E_0)."""
+
+    def __init__(self, params: dict):
+        L = lib()
+        self.params = dict(params)
+        self._rate = np.ascontiguousarray(params["rate_m3_s"], np.float64)
+        self._e0 = np.ascontiguousarray(params["e0_V_m"], np.float64)
+        P = _SwarmParams()
+        for name, _ in _SwarmParams._fields_:
+            if name in ("pad", "rate_m3_s", "e0_V_m", "n_energy", "n_fields"):
+                continue
+            setattr(P, name, params[name])
+        P.n_energy = len(self._rate)
+        P.n_fields = len(self._e0)
+        P.rate_m3_s = self._rate.ctypes.data_as(C.POINTER(C.c_double))
+        P.e0_V_m = self._e0.ctypes.data_as(C.POINTER(C.c_double))
+        self._P = P
+        self.h = L.orc_swarm_create(C.byref(P))
+        if not self.h:
+            raise ValueError("oracle: " + L.orc_last_error().decode())
+        self.dt = pdtype(params["precision"])
+        self.n = int(params["n_ions"])
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_swarm_free(h)
+            self.h = None
+
+    def run(self, n: int, accumulate: bool = False):
+        lib().orc_swarm_run(self.h, int(n), int(bool(accumulate)))
+
+    def ions(self, f: int) -> dict:
+        out = {k: np.empty(self.n, self.dt) for k in ("vx", "vy", "vz")}
+        out["acc_vz"] = np.empty(self.n)
+        out["acc_v2"] = np.empty(self.n)
+        lib().orc_swarm_get(self.h, int(f), *[_p(out[k]) for k in ("vx", "vy", "vz", "acc_vz",
+                                                                   "acc_v2")])
+        return out
+
+    def sums(self, f: int) -> dict:
+        v = np.empty(6)
+        lib().orc_swarm_sums(self.h, int(f), _p(v))
+        return {"sum_vz": v[0], "sum_v2": v[1], "n_acc": int(v[2]), "collisions": int(v[3]),
+                "overflow": int(v[4]), "step": int(v[5])}
+
+    def result(self, f: int) -> dict:
+        """Drift, mean energy, mobility u/E_0 and, from Eq (2.6), nu = e/(M mu)."""
+        s = self.sums(f)
+        m = s["n_acc"] * self.n
+        M = self.params["m_ion_amu"] * 1.66053906660e-27
+        e = 1.602176634e-19
+        u = s["sum_vz"] / m
+        E0 = float(self._e0[f])
+        return {"drift": u, "mean_energy_eV": 0.5 * M * s["sum_v2"] / m / e,
+                "mobility": u / E0 if E0 else math.nan,
+                "nu": e * E0 / (M * u) if u else math.nan, "collisions": s["collisions"],
+                "overflow": s["overflow"]}
+
+
+def normal_pairs(seed, tag, id_, step, n):
+    o = np.empty(2 * n)
+    lib().orc_normal_pairs(seed, tag, id_, step, n, _p(o))
+    return o
 
 
 def philox4x32_10(ctr, key):

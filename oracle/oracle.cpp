@@ -94,6 +94,24 @@ typedef struct orc_params {
   const orc_channel* channels;
 } orc_params;
 
+// Auxiliary ion swarm (Sec. II.C): one ion species in a uniform field E_0
+// and a Maxwellian background gas, isotropic scattering in the centre of
+// mass, no positions (a periodic domain in a uniform field).
+typedef struct orc_swarm_params {
+  int32_t precision;  // 0: float velocities, 1: double
+  int32_t n_fields;   // independent swarms, one per E_0
+  int32_t n_energy;   // rate-coefficient table points
+  int32_t pad;
+  int64_t n_ions;     // ions per swarm
+  uint64_t seed;
+  double n_gas_m3, t_gas_K, m_ion_amu, m_gas_amu;
+  double t_i0_K;         // initial ion temperature
+  double dt_s;
+  double inv_de_per_eV;  // table on relative (centre-of-mass) energies i / inv_de_per_eV
+  const double* rate_m3_s;  // [n_energy] k = Q_m g at those energies
+  const double* e0_V_m;     // [n_fields]
+} orc_swarm_params;
+
 }  // extern "C"
 
 namespace {
@@ -169,7 +187,13 @@ template <class P> P uniform(Stream& s);
 template <> float uniform<float>(Stream& s) { return uniform_f32(s); }
 template <> double uniform<double>(Stream& s) { return uniform_f64(s); }
 
-enum Tag : uint32_t { kTagElectron = 0, kTagLoad = 1, kTagEmission = 2 };
+enum Tag : uint32_t {
+  kTagElectron = 0,
+  kTagLoad = 1,
+  kTagEmission = 2,
+  kTagSwarm = 3,      // swarm steps; + 16 x field index
+  kTagSwarmLoad = 4   // swarm initial velocities; + 16 x field index
+};
 
 // ---------------------------------------------------------------------------
 // Derived constants, computed once in FP64 from the parameters.
@@ -1209,6 +1233,226 @@ Base* make(const orc_params* pp) {
   return b;
 }
 
+
+// ---------------------------------------------------------------------------
+// Auxiliary ion Monte Carlo (Sec. II.C): the ions of one species under a
+// prescribed uniform field E_0, colliding with a background gas of
+// temperature T_N by the null-collision method with sampled targets, reach a
+// stationary drift u; the mobility is u / E_0 and Eq (2.6) gives the
+// momentum-exchange frequency.  The domain is periodic and the field
+// uniform, so positions never enter.  Isotropic scattering in the centre of
+// mass with the cross section Q_m = Q_i + 2 Q_b (Sec. III); the caller gives
+// the rate coefficient k = Q_m g tabulated on the relative energy
+// M_r g^2 / (2e).
+// ---------------------------------------------------------------------------
+
+// Two standard normal deviates by Marsaglia's polar method (FP64 uniforms,
+// the logarithm above); (0, 0) if no point falls in the disk in
+// kSphereTries tries.
+void normal_pair(Stream& st, double& g0, double& g1) {
+  for (int t = 0; t < kSphereTries; ++t) {
+    const double a = 2.0 * uniform_f64(st) - 1.0;
+    const double b = 2.0 * uniform_f64(st) - 1.0;
+    const double q = a * a + b * b;
+    if (q < 1.0 && q > 0.0) {
+      const double f = std::sqrt((-2.0 * fit_ln(q)) / q);
+      g0 = a * f;
+      g1 = b * f;
+      return;
+    }
+  }
+  g0 = 0.0;
+  g1 = 0.0;
+}
+
+// Three Cartesian components of a Maxwellian velocity of thermal speed vth
+// (two polar pairs, the fourth deviate unused), rounded to P.
+template <class P>
+void maxwellian(Stream& st, double vth, P v[3]) {
+  double g[4];
+  normal_pair(st, g[0], g[1]);
+  normal_pair(st, g[2], g[3]);
+  for (int k = 0; k < 3; ++k) v[k] = (P)(vth * g[k]);
+}
+
+struct SwarmBase {
+  orc_swarm_params p;
+  std::vector<double> rate, e0;
+  int64_t step = 0;
+  std::vector<uint64_t> coll, over;
+  std::vector<int64_t> n_acc;  // accumulated steps (the same for every field)
+  virtual ~SwarmBase() {}
+  virtual void run(int64_t n, int accumulate) = 0;
+  virtual void get(int f, void* vx, void* vy, void* vz, double* avz, double* av2) const = 0;
+  virtual double sum_vz(int f) const = 0;
+  virtual double sum_v2(int f) const = 0;
+};
+
+template <class P>
+struct Swarm : SwarmBase {
+  double M = 0, MN = 0, vth_n = 0, vth_i0 = 0, Pmax64 = 0, nu_max = 0;
+  P Pmax = 0, KEr = 0, inv_dE = 0, m1 = 0, m2 = 0;
+  std::vector<P> a;    // [n_fields] velocity gain per step e E_0 dt / M
+  std::vector<P> tab;  // [n_energy] Pmax nu(eps_i) / nu_max
+  std::vector<P> vx, vy, vz;           // [n_fields * n_ions]
+  std::vector<double> avz, av2;        // per-ion sums of v_z and |v|^2 over accumulated steps
+
+  bool init() {
+    const int ne = p.n_energy;
+    M = p.m_ion_amu * kAmu;
+    MN = p.m_gas_amu * kAmu;
+    const double Mr = (M * MN) / (M + MN);
+    vth_n = std::sqrt(kKb * p.t_gas_K / MN);
+    vth_i0 = std::sqrt(kKb * p.t_i0_K / M);
+    std::vector<double> nu(ne);
+    nu_max = 0.0;
+    for (int i = 0; i < ne; ++i) {
+      nu[i] = p.n_gas_m3 * rate[i];
+      if (nu[i] > nu_max) nu_max = nu[i];
+    }
+    Pmax64 = 1.0 - std::exp(-nu_max * p.dt_s);
+    tab.resize(ne);
+    for (int i = 0; i < ne; ++i) tab[i] = (P)(nu_max > 0 ? Pmax64 * (nu[i] / nu_max) : 0.0);
+    Pmax = (P)Pmax64;
+    KEr = (P)(Mr / (2.0 * kE));
+    inv_dE = (P)p.inv_de_per_eV;
+    m1 = (P)(M / (M + MN));
+    m2 = (P)(MN / (M + MN));
+    a.resize(p.n_fields);
+    for (int f = 0; f < p.n_fields; ++f) a[f] = (P)(((kE * e0[f]) * p.dt_s) / M);
+    const size_t n = (size_t)p.n_fields * (size_t)p.n_ions;
+    vx.resize(n);
+    vy.resize(n);
+    vz.resize(n);
+    avz.assign(n, 0.0);
+    av2.assign(n, 0.0);
+    coll.assign(p.n_fields, 0);
+    over.assign(p.n_fields, 0);
+    n_acc.assign(p.n_fields, 0);
+    // initial Maxwellian at T_i0: stream (kTagSwarmLoad + 16 f, id = ion, step 0)
+    for (int f = 0; f < p.n_fields; ++f)
+      for (int64_t i = 0; i < p.n_ions; ++i) {
+        Stream st(p.seed, kTagSwarmLoad + 16u * (uint32_t)f, (uint32_t)i, 0);
+        P v[3];
+        maxwellian<P>(st, vth_i0, v);
+        const size_t k = (size_t)f * (size_t)p.n_ions + (size_t)i;
+        vx[k] = v[0];
+        vy[k] = v[1];
+        vz[k] = v[2];
+      }
+    return true;
+  }
+
+  // One step of one ion: acceleration by the field, then the null-collision
+  // test u0 < P_max; for a candidate a gas atom's velocity is drawn from the
+  // Maxwellian at T_N, and the collision is real when u0 falls below
+  // P_max nu(eps)/nu_max at the pair's relative energy eps = M_r g^2/(2e)
+  // (linear interpolation in the table, the last interval beyond its end).
+  // A real collision turns the relative velocity to a uniformly random
+  // direction of the same length, keeping the centre-of-mass velocity.
+  void ion_step(int f, size_t k, uint32_t id) {
+    Stream st(p.seed, kTagSwarm + 16u * (uint32_t)f, id, (uint32_t)step);
+    vz[k] = vz[k] + a[f];
+    const P u0 = uniform<P>(st);
+    if (u0 < Pmax) {
+      P t3[3];
+      maxwellian<P>(st, vth_n, t3);
+      const P gx = vx[k] - t3[0], gy = vy[k] - t3[1], gz = vz[k] - t3[2];
+      const P g2 = (gx * gx + gy * gy) + gz * gz;
+      const P eps = KEr * g2;
+      const P s = eps * inv_dE;
+      int i;
+      P t;
+      if (s >= (P)(p.n_energy - 1)) {
+        i = p.n_energy - 2;
+        t = (P)1;
+        over[f] += 1;
+      } else {
+        i = (int)s;
+        t = s - (P)i;
+      }
+      const P pc = tab[i] + t * (tab[i + 1] - tab[i]);
+      if (u0 < pc) {
+        P n[3];
+        sphere<P>(st, n);
+        const P gm = std::sqrt(g2);
+        const P r = m2 * gm;
+        vx[k] = (m1 * vx[k] + m2 * t3[0]) + r * n[0];
+        vy[k] = (m1 * vy[k] + m2 * t3[1]) + r * n[1];
+        vz[k] = (m1 * vz[k] + m2 * t3[2]) + r * n[2];
+        coll[f] += 1;
+      }
+    }
+  }
+
+  void run(int64_t n, int accumulate) override {
+    for (int64_t s = 0; s < n; ++s) {
+      for (int f = 0; f < p.n_fields; ++f) {
+        for (int64_t i = 0; i < p.n_ions; ++i) {
+          const size_t k = (size_t)f * (size_t)p.n_ions + (size_t)i;
+          ion_step(f, k, (uint32_t)i);
+          if (accumulate) {
+            const double x = (double)vx[k], y = (double)vy[k], z = (double)vz[k];
+            avz[k] = avz[k] + z;
+            av2[k] = av2[k] + ((x * x + y * y) + z * z);
+          }
+        }
+        if (accumulate) n_acc[f] += 1;
+      }
+      step += 1;
+    }
+  }
+
+  void get(int f, void* ox, void* oy, void* oz, double* oa, double* ob) const override {
+    for (int64_t i = 0; i < p.n_ions; ++i) {
+      const size_t k = (size_t)f * (size_t)p.n_ions + (size_t)i;
+      if (ox) ((P*)ox)[i] = vx[k];
+      if (oy) ((P*)oy)[i] = vy[k];
+      if (oz) ((P*)oz)[i] = vz[k];
+      if (oa) oa[i] = avz[k];
+      if (ob) ob[i] = av2[k];
+    }
+  }
+  double sum_vz(int f) const override {
+    double s = 0.0;
+    for (int64_t i = 0; i < p.n_ions; ++i) s += avz[(size_t)f * (size_t)p.n_ions + (size_t)i];
+    return s;
+  }
+  double sum_v2(int f) const override {
+    double s = 0.0;
+    for (int64_t i = 0; i < p.n_ions; ++i) s += av2[(size_t)f * (size_t)p.n_ions + (size_t)i];
+    return s;
+  }
+};
+
+SwarmBase* make_swarm(const orc_swarm_params* pp) {
+  if (!pp || pp->n_fields < 1 || pp->n_energy < 2 || pp->n_ions < 1 || !pp->rate_m3_s ||
+      !pp->e0_V_m || !(pp->dt_s > 0) || !(pp->inv_de_per_eV > 0) || !(pp->m_ion_amu > 0) ||
+      !(pp->m_gas_amu > 0) || !(pp->n_gas_m3 >= 0) || !(pp->t_gas_K >= 0) || !(pp->t_i0_K >= 0) ||
+      (pp->precision != 0 && pp->precision != 1)) {
+    g_err = "invalid swarm parameters";
+    return nullptr;
+  }
+  for (int i = 0; i < pp->n_energy; ++i)
+    if (!(pp->rate_m3_s[i] >= 0) || !std::isfinite(pp->rate_m3_s[i])) {
+      g_err = "rate coefficients must be finite and non-negative";
+      return nullptr;
+    }
+  SwarmBase* b = pp->precision == 0 ? (SwarmBase*)new Swarm<float>() : (SwarmBase*)new Swarm<double>();
+  b->p = *pp;
+  b->rate.assign(pp->rate_m3_s, pp->rate_m3_s + pp->n_energy);
+  b->e0.assign(pp->e0_V_m, pp->e0_V_m + pp->n_fields);
+  b->p.rate_m3_s = b->rate.data();
+  b->p.e0_V_m = b->e0.data();
+  const bool ok = pp->precision == 0 ? static_cast<Swarm<float>*>(b)->init()
+                                     : static_cast<Swarm<double>*>(b)->init();
+  if (!ok) {
+    delete b;
+    return nullptr;
+  }
+  return b;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1340,6 +1584,31 @@ void orc_get_power(void* h, double* out) {
   out[2] = (double)b->rf_periods;
   out[3] = (double)b->rf_steps;
   out[4] = b->pw_sum;
+}
+
+void* orc_swarm_create(const orc_swarm_params* p) { return make_swarm(p); }
+void orc_swarm_free(void* h) { delete static_cast<SwarmBase*>(h); }
+void orc_swarm_run(void* h, int64_t n, int accumulate) {
+  static_cast<SwarmBase*>(h)->run(n, accumulate);
+}
+void orc_swarm_get(void* h, int f, void* vx, void* vy, void* vz, double* avz, double* av2) {
+  static_cast<SwarmBase*>(h)->get(f, vx, vy, vz, avz, av2);
+}
+// [sum of v_z, sum of |v|^2 over ions and accumulated steps, accumulated
+//  steps, collisions, table overflows, step index]
+void orc_swarm_sums(void* h, int f, double* out) {
+  SwarmBase* b = static_cast<SwarmBase*>(h);
+  out[0] = b->sum_vz(f);
+  out[1] = b->sum_v2(f);
+  out[2] = (double)b->n_acc[f];
+  out[3] = (double)b->coll[f];
+  out[4] = (double)b->over[f];
+  out[5] = (double)b->step;
+}
+// normal deviates of stream (seed, tag, id, step): n pairs
+void orc_normal_pairs(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step, int n, double* out) {
+  Stream st(seed, tag, id, step);
+  for (int k = 0; k < n; ++k) normal_pair(st, out[2 * k], out[2 * k + 1]);
 }
 
 double orc_fit_ln(double x) { return fit_ln(x); }

@@ -185,3 +185,45 @@ def small(precision: int = FP64, ion_model: int = ION_DD, n_cells: int = 64,
              gap_m=0.5e-3 * n_cells / 256.0)
     p.update(over)
     return base_params(**p)
+
+
+# ---------------------------------------------------------------------------
+# Auxiliary ion swarm (He+ in He): the isotropic-scattering cross section
+# Q_m = Q_i + 2 Q_b of Sec. III as a rate coefficient k = Q_m g on the
+# centre-of-mass energy eps = M_r g^2 / (2e).
+# ---------------------------------------------------------------------------
+AMU = 1.66053906660e-27
+E_CHARGE = 1.602176634e-19
+
+
+def he_ion_q(eps):
+    """Q_i and Q_b [m^2] of He+ on He at centre-of-mass energy eps [eV] > 0."""
+    eps = np.asarray(eps, np.float64)
+    qi = 7.63e-20 / np.sqrt(eps)
+    qb = 1e-19 / ((eps / 1000.0) ** 0.15 * (1.0 + eps / 1000.0) ** 0.25 * (1.0 + 5.0 / eps) ** 0.15)
+    return qi, qb
+
+
+def he_ion_rate(n_energy: int = 4096, inv_de_per_eV: float = 400.0) -> np.ndarray:
+    """k(eps_i) = (Q_i + 2 Q_b) g on eps_i = i / inv_de_per_eV; at eps = 0 the
+    limit (Q_i g is constant, Q_b g vanishes)."""
+    Mr = HE_AMU * AMU / 2.0
+    eps = np.arange(n_energy, dtype=np.float64) / inv_de_per_eV
+    k = np.empty(n_energy)
+    k[0] = 7.63e-20 * np.sqrt(2.0 * E_CHARGE / Mr)
+    qi, qb = he_ion_q(eps[1:])
+    g = np.sqrt(2.0 * E_CHARGE * eps[1:] / Mr)
+    k[1:] = (qi + 2.0 * qb) * g
+    return k
+
+
+def swarm_params(e0_V_m, n_ions: int = 2048, precision: int = FP32, seed: int = 7,
+                 **over) -> dict:
+    """He+ swarms in He at 1 atm and 300 K, one per field value."""
+    p = dict(precision=precision, n_ions=n_ions, seed=seed, n_gas_m3=N_GAS_1ATM, t_gas_K=300.0,
+             m_ion_amu=HE_AMU, m_gas_amu=HE_AMU, t_i0_K=300.0, dt_s=5e-13, inv_de_per_eV=400.0,
+             e0_V_m=np.asarray(e0_V_m, np.float64))
+    p.update(over)
+    if "rate_m3_s" not in p:
+        p["rate_m3_s"] = he_ion_rate(4096, p["inv_de_per_eV"])
+    return p
