@@ -136,6 +136,62 @@ def batched(a):
     print(json.dumps(line), flush=True)
 
 
+def swarm(a):
+    """Auxiliary ion swarm (Sec. II.C): 16 He+ swarms of 2^20 ions in fields
+    log-spaced over 1e5 .. 1e7 V/m, 2 ns to the stationary drift, then 2 ns
+    averaged; value = ion-steps/s of the averaged run."""
+    import torch
+
+    import numpy as np
+    from paper_1508_02892_amd import hd, workloads as W
+    p = W.swarm_bench()
+    n_ion_steps = len(p["e0_V_m"]) * p["n_ions"]
+    s = hd.Swarm(p, device=0)
+    print("bench: swarm warmup %d steps" % W.SWARM_WARM, file=sys.stderr, flush=True)
+    s.run(W.SWARM_WARM)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(W.SWARM_AVG, accumulate=True)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    res = s.results()
+    e0 = 1.47e6
+    table2 = [1e-3 * (1.18 - 0.185 * r["e0_V_m"] / e0) if r["e0_V_m"] < e0 else
+              1e-3 * 0.94 * (e0 / r["e0_V_m"]) ** 0.3 for r in res]
+    line = {
+        "metric": "ion-steps/s (auxiliary ion Monte Carlo, accelerate + null-collision MCC)",
+        "value": n_ion_steps * W.SWARM_AVG / secs, "unit": "ion-steps/s", "n_gpus": 1,
+        "steps": W.SWARM_AVG, "warmup": W.SWARM_WARM, "ms_per_step": secs * 1e3 / W.SWARM_AVG,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ion swarm: He+ in He 1 atm 300 K, Q_m = Q_i + 2 Q_b, %d fields "
+                               "1e5..1e7 V/m, %d ions each, dt 0.5 ps"
+                               % (len(p["e0_V_m"]), p["n_ions"])},
+        "mobility_vs_table2": [[r["e0_V_m"], r["mobility_m2_Vs"], t]
+                               for r, t in zip(res, table2)],
+        "nu_s": [r["nu_s"] for r in res],
+        "table_overflow_per_collision": sum(r["overflow"] for r in res) /
+        max(1, sum(r["collisions"] for r in res)),
+    }
+    if not a.no_cpu:
+        import oracle
+        q = dict(p, n_ions=4096)
+        orc = oracle.Swarm(q)
+        t1 = time.perf_counter()
+        orc.run(W.SWARM_WARM)
+        orc.run(W.SWARM_AVG, accumulate=True)
+        dt = time.perf_counter() - t1
+        n = 4096 * len(p["e0_V_m"]) * (W.SWARM_WARM + W.SWARM_AVG)
+        line["cpu_baseline"] = {"value": n / dt, "unit": "ion-steps/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": "the same 16 fields with 4,096 ions each, %d steps "
+                                          "(%d ion-steps, %.1f s), single thread"
+                                          % (W.SWARM_WARM + W.SWARM_AVG, n, dt)}
+    s.close()
+    del np
+    print(json.dumps(line), flush=True)
+
+
 def served(a):
     """Served job stream: Poisson arrivals of discharge jobs drawn like the
     batched sweep, admitted by HBM budget into continuously batched slots;
@@ -217,6 +273,8 @@ def main():
         return served(a)
     if a.workload == "batched":
         return batched(a)
+    if a.workload == "swarm":
+        return swarm(a)
 
     import torch
     from paper_1508_02892_amd import hd

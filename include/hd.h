@@ -282,6 +282,77 @@ int hd_server_drain(hd_server* s, double timeout_s);
  * NULL-safe. */
 int hd_server_free(hd_server* s);
 
+/* ---- auxiliary ion swarm (Sec. II.C) ------------------------------------ */
+
+/* The Monte Carlo the paper uses to obtain ion mobilities and
+ * momentum-exchange frequencies: ions of one species in a prescribed uniform
+ * field E0 collide with a background gas at temperature t_gas_K.  The
+ * domain is periodic and the field uniform, so only velocities are
+ * followed.  Each step: v_z += e E0 dt / M; then the null-collision test
+ * u0 < P_max = 1 - exp(-nu_max dt) with u0 from the stream (seed, tag
+ * 3 + 16 f, ion, step); a candidate draws a gas atom from the Maxwellian
+ * (two polar pairs of FP64 normal deviates) and collides when u0 <
+ * P_max nu(eps)/nu_max at the pair's centre-of-mass energy eps = M_r g^2/(2e)
+ * (nu = n_gas k, k linearly interpolated in the table, the last interval
+ * beyond its end: counted as overflow); a collision keeps the centre-of-mass
+ * velocity and turns the relative velocity to a uniformly random direction
+ * (isotropic scattering with Q_m = Q_i + 2 Q_b for He+ in He, Sec. III).
+ * Initial velocities: Maxwellian at t_i0_K (stream tag 4 + 16 f, step 0).
+ * The mean v_z over the accumulated ion-steps is the drift u; the mobility
+ * is u/E0 and Eq (2.6) gives nu = e E0/(M u). */
+typedef struct hd_swarm_params {
+  int32_t abi_version;     /* must be HD_ABI_VERSION                         */
+  int32_t precision;       /* enum hd_precision: ion velocities and collision math */
+  int32_t n_fields;        /* independent swarms, one per entry of e0_V_m (>= 1) */
+  int32_t n_energy;        /* rate-table points, 2 .. 4096                   */
+  int64_t n_ions;          /* ions per swarm; n_fields * n_ions <= 2^31      */
+  uint64_t seed;           /* Philox key                                     */
+  double n_gas_m3, t_gas_K, m_ion_amu, m_gas_amu;
+  double t_i0_K;           /* initial ion temperature                        */
+  double dt_s;
+  double inv_de_per_eV;    /* table points per eV of centre-of-mass energy   */
+  const double* rate_m3_s; /* [n_energy] k(eps_i) = Q_m(eps_i) g(eps_i) at
+                              eps_i = i / inv_de_per_eV, g the relative speed
+                              with M_r g^2 / (2e) = eps_i [m^3/s];
+                              caller-owned, copied                           */
+  const double* e0_V_m;    /* [n_fields] field values [V/m]; caller-owned, copied */
+} hd_swarm_params;
+
+/* Results of one swarm over the accumulated steps (see hd_swarm_run). */
+typedef struct hd_swarm_result {
+  double e0_V_m;
+  double drift_m_s;        /* mean v_z over ions and accumulated steps       */
+  double mean_energy_eV;   /* mean M |v|^2 / (2e)                            */
+  double mobility_m2_Vs;   /* drift / E0 (0 for E0 = 0)                      */
+  double nu_s;             /* Eq (2.6): e E0 / (M drift) (0 for zero drift)  */
+  uint64_t collisions;     /* real collisions since creation                 */
+  uint64_t overflow;       /* candidates above the table's last point        */
+  int64_t samples;         /* ion-steps in the averages                      */
+} hd_swarm_result;
+
+typedef struct hd_swarm hd_swarm;
+
+/* Validates, copies the tables, allocates device state and draws the
+ * initial velocities.  Synchronous.  *out is set only on HD_OK. */
+int hd_swarm_create(const hd_swarm_params* params, const hd_device_ctx* ctx, hd_swarm** out);
+
+/* Enqueues n_steps >= 0 steps of every ion; with accumulate != 0 each of
+ * these steps adds v_z and |v|^2 of every ion to its running sums (the
+ * averages of hd_swarm_results).  Returns without waiting. */
+int hd_swarm_run(hd_swarm* h, int64_t n_steps, int32_t accumulate);
+
+/* Waits and writes n_fields results (caller-owned array). */
+int hd_swarm_results(hd_swarm* h, hd_swarm_result* out);
+
+/* Waits and copies the ions of swarm `field`: velocities (float for HD_FP32,
+ * double for HD_FP64) and the running sums of v_z and |v|^2 (double), each
+ * array n_ions long (cap >= n_ions); any pointer may be NULL. */
+int hd_swarm_get_ions(hd_swarm* h, int32_t field, void* vx, void* vy, void* vz, double* acc_vz,
+                      double* acc_v2, int64_t cap);
+
+/* Releases device state.  NULL-safe. */
+int hd_swarm_free(hd_swarm* h);
+
 /* ---- diagnostics -------------------------------------------------------- */
 
 /* Advances the discharge by n_steps > 0 real steps launched one kernel at a

@@ -131,7 +131,7 @@ def _p(a):
 class _SwarmParams(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("n_fields", C.c_int32), ("n_energy", C.c_int32),
-        ("pad", C.c_int32), ("n_ions", C.c_int64), ("seed", C.c_uint64),
+        ("pad", C.c_int32), ("n_ions", C.c_int64), ("id0", C.c_int64), ("seed", C.c_uint64),
         ("n_gas_m3", C.c_double), ("t_gas_K", C.c_double), ("m_ion_amu", C.c_double),
         ("m_gas_amu", C.c_double), ("t_i0_K", C.c_double), ("dt_s", C.c_double),
         ("inv_de_per_eV", C.c_double),
@@ -304,7 +304,7 @@ class Swarm:
         for name, _ in _SwarmParams._fields_:
             if name in ("pad", "rate_m3_s", "e0_V_m", "n_energy", "n_fields"):
                 continue
-            setattr(P, name, params[name])
+            setattr(P, name, params.get(name, 0) if name == "id0" else params[name])
         P.n_energy = len(self._rate)
         P.n_fields = len(self._e0)
         P.rate_m3_s = self._rate.ctypes.data_as(C.POINTER(C.c_double))

@@ -103,6 +103,7 @@ typedef struct orc_swarm_params {
   int32_t n_energy;   // rate-coefficient table points
   int32_t pad;
   int64_t n_ions;     // ions per swarm
+  int64_t id0;        // stream id of the first ion (a window of a larger swarm)
   uint64_t seed;
   double n_gas_m3, t_gas_K, m_ion_amu, m_gas_amu;
   double t_i0_K;         // initial ion temperature
@@ -1332,7 +1333,7 @@ struct Swarm : SwarmBase {
     // initial Maxwellian at T_i0: stream (kTagSwarmLoad + 16 f, id = ion, step 0)
     for (int f = 0; f < p.n_fields; ++f)
       for (int64_t i = 0; i < p.n_ions; ++i) {
-        Stream st(p.seed, kTagSwarmLoad + 16u * (uint32_t)f, (uint32_t)i, 0);
+        Stream st(p.seed, kTagSwarmLoad + 16u * (uint32_t)f, (uint32_t)(p.id0 + i), 0);
         P v[3];
         maxwellian<P>(st, vth_i0, v);
         const size_t k = (size_t)f * (size_t)p.n_ions + (size_t)i;
@@ -1363,7 +1364,7 @@ struct Swarm : SwarmBase {
       const P s = eps * inv_dE;
       int i;
       P t;
-      if (s >= (P)(p.n_energy - 1)) {
+      if (!(s < (P)(p.n_energy - 1))) {  // beyond the table (or not a number)
         i = p.n_energy - 2;
         t = (P)1;
         over[f] += 1;
@@ -1390,7 +1391,7 @@ struct Swarm : SwarmBase {
       for (int f = 0; f < p.n_fields; ++f) {
         for (int64_t i = 0; i < p.n_ions; ++i) {
           const size_t k = (size_t)f * (size_t)p.n_ions + (size_t)i;
-          ion_step(f, k, (uint32_t)i);
+          ion_step(f, k, (uint32_t)(p.id0 + i));
           if (accumulate) {
             const double x = (double)vx[k], y = (double)vy[k], z = (double)vz[k];
             avz[k] = avz[k] + z;
@@ -1429,6 +1430,7 @@ SwarmBase* make_swarm(const orc_swarm_params* pp) {
   if (!pp || pp->n_fields < 1 || pp->n_energy < 2 || pp->n_ions < 1 || !pp->rate_m3_s ||
       !pp->e0_V_m || !(pp->dt_s > 0) || !(pp->inv_de_per_eV > 0) || !(pp->m_ion_amu > 0) ||
       !(pp->m_gas_amu > 0) || !(pp->n_gas_m3 >= 0) || !(pp->t_gas_K >= 0) || !(pp->t_i0_K >= 0) ||
+      pp->id0 < 0 || pp->id0 + pp->n_ions > ((int64_t)1 << 32) ||
       (pp->precision != 0 && pp->precision != 1)) {
     g_err = "invalid swarm parameters";
     return nullptr;

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhd.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["k_electron.hip", "k_field.hip", "k_sort.hip", "hd_runtime.cpp"]
+SOURCES = ["k_electron.hip", "k_field.hip", "k_sort.hip", "k_swarm.hip", "hd_runtime.cpp"]
 HEADERS = ["hd_internal.h", "hd_device.h"]
 
 FLAGS = [

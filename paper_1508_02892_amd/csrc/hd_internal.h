@@ -127,6 +127,29 @@ struct Disch {
   State* st;
 };
 
+// Auxiliary ion swarm: n_fields independent swarms of n_ions ions, ion i of
+// swarm f at index f * n_ions + i of every array.
+constexpr int kSwarmThreads = 256;
+constexpr int kSwarmMaxEnergy = 4096;  // rate-table points held in LDS (32 KB in FP64)
+template <class P>
+struct SwarmDev {
+  int32_t n_fields, ne;
+  int64_t n_ions;
+  uint64_t seed;
+  P Pmax, KEr, inv_dE, m1, m2;  // null-collision bound, M_r/(2e), points per eV, mass ratios
+  double vth_n, vth_i0;         // thermal speeds of gas atoms and of the initial ions
+  const P* a;                   // [n_fields] velocity gain per step e E0 dt / M
+  const P* tab;                 // [ne] P_max nu(eps_i) / nu_max
+  P* vx;
+  P* vy;
+  P* vz;
+  double* avz;    // per-ion sums of v_z over accumulated steps
+  double* av2;    // per-ion sums of |v|^2
+  uint64_t* coll;  // [n_fields]
+  uint64_t* over;  // [n_fields]
+  double* sums;    // [2 n_fields] sums over ions of avz and av2
+};
+
 }  // namespace hd
 
 // Launch wrappers implemented in the kernel translation units.
@@ -136,4 +159,11 @@ hipError_t launch_finalize(const Disch<P>* d_dev, int D, int field_only, int nn_
                            int app_blocks, hipStream_t s);
 template <class P>
 hipError_t launch_diag(int64_t n, const P* a, const P* b, P* out, hipStream_t s);
+template <class P>
+hipError_t launch_swarm_init(const SwarmDev<P>& w, hipStream_t s);
+template <class P>
+hipError_t launch_swarm_step(const SwarmDev<P>& w, uint32_t step0, int n_steps, int accumulate,
+                             hipStream_t s);
+template <class P>
+hipError_t launch_swarm_reduce(const SwarmDev<P>& w, hipStream_t s);
 }  // namespace hd

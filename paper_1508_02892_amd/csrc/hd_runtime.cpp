@@ -1295,6 +1295,185 @@ struct Server : ServerBase {
   }
 };
 
+
+// ---------------------------------------------------------------------------
+// Auxiliary ion swarm (Sec. II.C).
+// ---------------------------------------------------------------------------
+struct SwarmBase {
+  virtual ~SwarmBase() {}
+  virtual int run(int64_t n, int accumulate) = 0;
+  virtual int results(hd_swarm_result* out) = 0;
+  virtual int ions(int f, void* vx, void* vy, void* vz, double* avz, double* av2, int64_t cap) = 0;
+};
+
+namespace {
+
+bool swarm_valid(const hd_swarm_params* p, std::string& why) {
+  if (!p) return (why = "null params"), false;
+  if (p->abi_version != HD_ABI_VERSION) return (why = "abi_version mismatch"), false;
+  if (p->precision != HD_FP32 && p->precision != HD_FP64) return (why = "precision"), false;
+  if (p->n_fields < 1 || p->n_ions < 1 || (int64_t)p->n_fields * p->n_ions > ((int64_t)1 << 31) ||
+      p->n_ions > ((int64_t)1 << 32) - 1)
+    return (why = "n_fields * n_ions must lie in [1, 2^31]"), false;
+  if (p->n_energy < 2 || p->n_energy > kSwarmMaxEnergy)
+    return (why = "n_energy out of [2, 4096]"), false;
+  if (!p->rate_m3_s || !p->e0_V_m) return (why = "rate table or field list missing"), false;
+  for (int i = 0; i < p->n_energy; ++i)
+    if (!(p->rate_m3_s[i] >= 0) || !std::isfinite(p->rate_m3_s[i]))
+      return (why = "rate coefficients must be finite and non-negative"), false;
+  for (int f = 0; f < p->n_fields; ++f)
+    if (!std::isfinite(p->e0_V_m[f])) return (why = "fields must be finite"), false;
+  if (!(p->dt_s > 0) || !(p->inv_de_per_eV > 0) || !(p->m_ion_amu > 0) || !(p->m_gas_amu > 0) ||
+      !(p->n_gas_m3 >= 0) || !(p->t_gas_K >= 0) || !(p->t_i0_K >= 0))
+    return (why = "gas, mass, time step or energy grid"), false;
+  return true;
+}
+
+template <class P>
+struct SwarmImpl : SwarmBase {
+  hd_swarm_params p{};
+  std::vector<double> rate, e0;
+  double M = 0;
+  hipStream_t stream = nullptr, own_stream = nullptr;
+  int device = 0;
+  unsigned char* base = nullptr;
+  SwarmDev<P> w{};
+  int64_t step = 0, n_acc = 0;
+
+  ~SwarmImpl() override {
+    if (base) (void)hipFree(base);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+  }
+
+  int create(const hd_swarm_params* pp, const hd_device_ctx* ctx) {
+    p = *pp;
+    rate.assign(pp->rate_m3_s, pp->rate_m3_s + pp->n_energy);
+    e0.assign(pp->e0_V_m, pp->e0_V_m + pp->n_fields);
+    p.rate_m3_s = rate.data();
+    p.e0_V_m = e0.data();
+    stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+    device = ctx ? ctx->device : 0;
+    HD_TRY(hipSetDevice(device));
+    if (!stream) {
+      HD_TRY(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+      stream = own_stream;
+    }
+    // constants: the same formulas as the oracle, FP64 then rounded to P
+    const int ne = p.n_energy, D = p.n_fields;
+    M = p.m_ion_amu * kAmu;
+    const double MN = p.m_gas_amu * kAmu;
+    const double Mr = (M * MN) / (M + MN);
+    std::vector<double> nu(ne);
+    double nu_max = 0.0;
+    for (int i = 0; i < ne; ++i) {
+      nu[i] = p.n_gas_m3 * rate[i];
+      if (nu[i] > nu_max) nu_max = nu[i];
+    }
+    const double Pmax = 1.0 - std::exp(-nu_max * p.dt_s);
+    std::vector<P> tab(ne), acc(D);
+    for (int i = 0; i < ne; ++i) tab[i] = (P)(nu_max > 0 ? Pmax * (nu[i] / nu_max) : 0.0);
+    for (int f = 0; f < D; ++f) acc[f] = (P)(((kE * e0[f]) * p.dt_s) / M);
+    w.n_fields = D;
+    w.ne = ne;
+    w.n_ions = p.n_ions;
+    w.seed = p.seed;
+    w.Pmax = (P)Pmax;
+    w.KEr = (P)(Mr / (2.0 * kE));
+    w.inv_dE = (P)p.inv_de_per_eV;
+    w.m1 = (P)(M / (M + MN));
+    w.m2 = (P)(MN / (M + MN));
+    w.vth_n = std::sqrt(kKb * p.t_gas_K / MN);
+    w.vth_i0 = std::sqrt(kKb * p.t_i0_K / M);
+    // one device block: a, tab, vx, vy, vz, avz, av2, coll, over, sums
+    const size_t n = (size_t)D * (size_t)p.n_ions;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off = align_up(off + bytes, 256);
+      return o;
+    };
+    const size_t o_a = take(D * sizeof(P)), o_tab = take(ne * sizeof(P));
+    const size_t o_vx = take(n * sizeof(P)), o_vy = take(n * sizeof(P)), o_vz = take(n * sizeof(P));
+    const size_t o_az = take(n * 8), o_a2 = take(n * 8);
+    const size_t o_c = take(D * 8), o_o = take(D * 8), o_s = take(2 * D * 8);
+    if (hipMalloc((void**)&base, off) != hipSuccess) {
+      base = nullptr;
+      return fail(HD_ENOMEM, "swarm allocation of " + std::to_string(off) + " bytes failed");
+    }
+    w.a = (const P*)(base + o_a);
+    w.tab = (const P*)(base + o_tab);
+    w.vx = (P*)(base + o_vx);
+    w.vy = (P*)(base + o_vy);
+    w.vz = (P*)(base + o_vz);
+    w.avz = (double*)(base + o_az);
+    w.av2 = (double*)(base + o_a2);
+    w.coll = (uint64_t*)(base + o_c);
+    w.over = (uint64_t*)(base + o_o);
+    w.sums = (double*)(base + o_s);
+    HD_TRY(hipMemsetAsync(base + o_c, 0, o_s - o_c + 2 * D * 8, stream));
+    HD_TRY(hipMemcpyAsync(base + o_a, acc.data(), D * sizeof(P), hipMemcpyHostToDevice, stream));
+    HD_TRY(hipMemcpyAsync(base + o_tab, tab.data(), ne * sizeof(P), hipMemcpyHostToDevice, stream));
+    HD_TRY(launch_swarm_init<P>(w, stream));
+    HD_TRY(hipStreamSynchronize(stream));
+    return HD_OK;
+  }
+
+  int run(int64_t n, int accumulate) override {
+    if (n < 0) return fail(HD_EINVAL, "n_steps must be non-negative");
+    HD_TRY(hipSetDevice(device));
+    constexpr int64_t kChunk = 256;  // steps per launch
+    for (int64_t done = 0; done < n; done += kChunk) {
+      const int k = (int)std::min<int64_t>(kChunk, n - done);
+      HD_TRY(launch_swarm_step<P>(w, (uint32_t)(step + done), k, accumulate ? 1 : 0, stream));
+    }
+    step += n;
+    if (accumulate) n_acc += n;
+    return HD_OK;
+  }
+
+  int results(hd_swarm_result* out) override {
+    if (!out) return fail(HD_EINVAL, "null output");
+    const int D = p.n_fields;
+    HD_TRY(hipSetDevice(device));
+    HD_TRY(launch_swarm_reduce<P>(w, stream));
+    std::vector<double> sums(2 * D);
+    std::vector<uint64_t> coll(D), over(D);
+    HD_TRY(hipMemcpyAsync(sums.data(), w.sums, 2 * D * 8, hipMemcpyDeviceToHost, stream));
+    HD_TRY(hipMemcpyAsync(coll.data(), w.coll, D * 8, hipMemcpyDeviceToHost, stream));
+    HD_TRY(hipMemcpyAsync(over.data(), w.over, D * 8, hipMemcpyDeviceToHost, stream));
+    HD_TRY(hipStreamSynchronize(stream));
+    const int64_t samples = n_acc * p.n_ions;
+    for (int f = 0; f < D; ++f) {
+      hd_swarm_result& r = out[f];
+      r.e0_V_m = e0[f];
+      r.drift_m_s = samples ? sums[2 * f] / (double)samples : 0.0;
+      r.mean_energy_eV = samples ? ((0.5 * M) * (sums[2 * f + 1] / (double)samples)) / kE : 0.0;
+      r.mobility_m2_Vs = e0[f] != 0.0 ? r.drift_m_s / e0[f] : 0.0;
+      r.nu_s = r.drift_m_s != 0.0 ? (kE * e0[f]) / (M * r.drift_m_s) : 0.0;
+      r.collisions = coll[f];
+      r.overflow = over[f];
+      r.samples = samples;
+    }
+    return HD_OK;
+  }
+
+  int ions(int f, void* vx, void* vy, void* vz, double* avz, double* av2, int64_t cap) override {
+    if (f < 0 || f >= p.n_fields) return fail(HD_EINVAL, "field index out of range");
+    if (cap < p.n_ions) return fail(HD_EINVAL, "cap < n_ions");
+    HD_TRY(hipSetDevice(device));
+    const size_t n = (size_t)p.n_ions, o = (size_t)f * n;
+    if (vx) HD_TRY(hipMemcpyAsync(vx, w.vx + o, n * sizeof(P), hipMemcpyDeviceToHost, stream));
+    if (vy) HD_TRY(hipMemcpyAsync(vy, w.vy + o, n * sizeof(P), hipMemcpyDeviceToHost, stream));
+    if (vz) HD_TRY(hipMemcpyAsync(vz, w.vz + o, n * sizeof(P), hipMemcpyDeviceToHost, stream));
+    if (avz) HD_TRY(hipMemcpyAsync(avz, w.avz + o, n * 8, hipMemcpyDeviceToHost, stream));
+    if (av2) HD_TRY(hipMemcpyAsync(av2, w.av2 + o, n * 8, hipMemcpyDeviceToHost, stream));
+    HD_TRY(hipStreamSynchronize(stream));
+    return HD_OK;
+  }
+};
+
+}  // namespace
+
 }  // namespace hd
 
 // ---------------------------------------------------------------------------
@@ -1526,6 +1705,56 @@ int hd_diag_arith(int32_t precision, int64_t n, const void* a, const void* b, vo
   if (e == hipSuccess) e = hipMemcpy(out, dout, 4 * n * es, hipMemcpyDeviceToHost);
   cleanup();
   if (e != hipSuccess) return hd::fail(HD_EDEVICE, hipGetErrorString(e));
+  return HD_OK;
+}
+
+struct hd_swarm {
+  hd::SwarmBase* impl;
+};
+
+int hd_swarm_create(const hd_swarm_params* params, const hd_device_ctx* ctx, hd_swarm** out) {
+  if (!out) return hd::fail(HD_EINVAL, "null out");
+  std::string why;
+  if (!hd::swarm_valid(params, why)) return hd::fail(HD_EINVAL, why);
+  hd::SwarmBase* b = nullptr;
+  int rc;
+  if (params->precision == HD_FP32) {
+    auto* x = new hd::SwarmImpl<float>();
+    rc = x->create(params, ctx);
+    b = x;
+  } else {
+    auto* x = new hd::SwarmImpl<double>();
+    rc = x->create(params, ctx);
+    b = x;
+  }
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = new hd_swarm{b};
+  return HD_OK;
+}
+
+int hd_swarm_run(hd_swarm* h, int64_t n_steps, int32_t accumulate) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return h->impl->run(n_steps, accumulate);
+}
+
+int hd_swarm_results(hd_swarm* h, hd_swarm_result* out) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return h->impl->results(out);
+}
+
+int hd_swarm_get_ions(hd_swarm* h, int32_t field, void* vx, void* vy, void* vz, double* acc_vz,
+                      double* acc_v2, int64_t cap) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return h->impl->ions(field, vx, vy, vz, acc_vz, acc_v2, cap);
+}
+
+int hd_swarm_free(hd_swarm* h) {
+  if (!h) return HD_OK;
+  delete h->impl;
+  delete h;
   return HD_OK;
 }
 

@@ -72,25 +72,6 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
   return L;
 }
 
-template <class P>
-__device__ __forceinline__ void sphere(Stream& s, P& nx, P& ny, P& nz) {
-  for (int t = 0; t < kSphereTries; ++t) {
-    const P a = (P)2 * Uni<P>::get(s) - (P)1;
-    const P b = (P)2 * Uni<P>::get(s) - (P)1;
-    const P q = a * a + b * b;
-    if (q < (P)1) {
-      const P r = (P)2 * sqrt((P)1 - q);
-      nx = a * r;
-      ny = b * r;
-      nz = (P)1 - (P)2 * q;
-      return;
-    }
-  }
-  nx = (P)0;
-  ny = (P)0;
-  nz = (P)1;
-}
-
 __device__ __forceinline__ void lds_add_i64(int64_t* p, uint64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
@@ -569,40 +550,7 @@ __device__ __forceinline__ double ion_temperature(const Disch<P>& d, double mu, 
 // Fitted He+ transport in He at atmospheric pressure (Sec. III): mobility
 // versus |E| (Table 2, branch change at E0 = 1.47e6 V/m) and momentum-exchange
 // frequency versus |u| (Table 3, branch change at u0 = 2e3 m/s).  The
-// non-integer powers go through fit_log / fit_exp, whose steps are fixed so
-// that any implementation of the same steps rounds identically: ln x by
-// binary-exponent reduction of x to m in [sqrt(1/2), sqrt(2)) and the atanh
-// series of s = (m - 1)/(m + 1) through s^21; exp y by Cody-Waite reduction
-// y = k ln2 + r (ln2 split into a head exact in k ln2 and a tail) and the
-// Taylor series of e^r through r^14, scaled by 2^k.
-__device__ __forceinline__ double fit_log(double x) {
-  int e;
-  double m = frexp(x, &e);  // x = m 2^e, m in [1/2, 1)
-  if (m < 0.70710678118654752440) {
-    m = m * 2.0;
-    e = e - 1;
-  }
-  const double s = (m - 1.0) / (m + 1.0);
-  const double s2 = s * s;
-  double acc = 1.0 / 21.0;
-#pragma unroll
-  for (int odd = 19; odd >= 1; odd -= 2) acc = acc * s2 + 1.0 / (double)odd;
-  return (double)e * 0.69314718055994530942 + (2.0 * s) * acc;
-}
-
-__device__ __forceinline__ double fit_exp(double y) {
-  const double k = rint(y * 1.44269504088896340736);
-  const double r = (y - k * 6.93147180369123816490e-01) - k * 1.90821492927058770002e-10;
-  double fact[15];  // n! for n = 0..14, exact in double
-  fact[0] = 1.0;
-#pragma unroll
-  for (int n = 1; n <= 14; ++n) fact[n] = fact[n - 1] * (double)n;
-  double acc = 1.0 / fact[14];
-#pragma unroll
-  for (int n = 13; n >= 0; --n) acc = acc * r + 1.0 / fact[n];
-  return ldexp(acc, (int)k);
-}
-
+// non-integer powers go through fit_log / fit_exp.
 __device__ __forceinline__ double fit_pow(double x, double y) {
   return x > 0.0 ? fit_exp(y * fit_log(x)) : 0.0;
 }

@@ -28,7 +28,8 @@ SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_disc
            "hd_batch_create", "hd_batch_step", "hd_batch_moments", "hd_batch_get_particles",
            "hd_batch_free", "hd_server_create", "hd_server_submit", "hd_server_poll",
            "hd_server_stats", "hd_server_drain", "hd_server_free", "hd_profile_steps",
-           "hd_diag_arith"]
+           "hd_diag_arith", "hd_swarm_create", "hd_swarm_run", "hd_swarm_results",
+           "hd_swarm_get_ions", "hd_swarm_free"]
 
 
 class HdError(RuntimeError):
@@ -80,6 +81,24 @@ class MomentSet(C.Structure):
         ("emitted", C.c_uint64 * 2), ("created", C.c_uint64), ("e_overflow", C.c_uint64),
         ("see_clamped", C.c_uint64), ("n_acc", C.c_uint64), ("pushed", C.c_uint64),
         ("volt_amp", C.c_double), ("p_abs", C.c_double), ("rf_periods", C.c_int64),
+    ]
+
+
+class SwarmParams(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("precision", C.c_int32), ("n_fields", C.c_int32),
+        ("n_energy", C.c_int32), ("n_ions", C.c_int64), ("seed", C.c_uint64),
+        ("n_gas_m3", C.c_double), ("t_gas_K", C.c_double), ("m_ion_amu", C.c_double),
+        ("m_gas_amu", C.c_double), ("t_i0_K", C.c_double), ("dt_s", C.c_double),
+        ("inv_de_per_eV", C.c_double), ("rate_m3_s", _D), ("e0_V_m", _D),
+    ]
+
+
+class SwarmResult(C.Structure):
+    _fields_ = [
+        ("e0_V_m", C.c_double), ("drift_m_s", C.c_double), ("mean_energy_eV", C.c_double),
+        ("mobility_m2_Vs", C.c_double), ("nu_s", C.c_double), ("collisions", C.c_uint64),
+        ("overflow", C.c_uint64), ("samples", C.c_int64),
     ]
 
 
@@ -138,6 +157,12 @@ def lib():
         L.hd_server_stats.argtypes = [vp, C.POINTER(ServerCounters)]
         L.hd_server_drain.argtypes = [vp, C.c_double]
         L.hd_server_free.argtypes = [vp]
+        L.hd_swarm_create.argtypes = [C.POINTER(SwarmParams), C.POINTER(DeviceCtx),
+                                      C.POINTER(vp)]
+        L.hd_swarm_run.argtypes = [vp, C.c_int64, C.c_int32]
+        L.hd_swarm_results.argtypes = [vp, C.POINTER(SwarmResult)]
+        L.hd_swarm_get_ions.argtypes = [vp, C.c_int32] + [vp] * 5 + [C.c_int64]
+        L.hd_swarm_free.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -386,3 +411,59 @@ def diag_arith(precision: int, a, b) -> np.ndarray:
     ctx = _ctx()
     _check(lib().hd_diag_arith(precision, len(a), _ptr(a), _ptr(b), _ptr(out), C.byref(ctx)))
     return out
+
+
+class Swarm:
+    """Auxiliary ion swarms (one per field value): hd_swarm_create / run /
+    results / get_ions / free."""
+
+    def __init__(self, params: dict, stream=None, device: int = 0):
+        self.params = dict(params)
+        self._rate = np.ascontiguousarray(params["rate_m3_s"], np.float64)
+        self._e0 = np.ascontiguousarray(params["e0_V_m"], np.float64)
+        P = SwarmParams()
+        P.abi_version = HD_ABI_VERSION
+        for name, _ in SwarmParams._fields_:
+            if name in ("abi_version", "rate_m3_s", "e0_V_m", "n_energy", "n_fields"):
+                continue
+            setattr(P, name, params[name])
+        P.n_energy = len(self._rate)
+        P.n_fields = len(self._e0)
+        P.rate_m3_s = self._rate.ctypes.data_as(_D)
+        P.e0_V_m = self._e0.ctypes.data_as(_D)
+        self._P = P
+        self._ctx = _ctx(stream, device)
+        h = C.c_void_p()
+        _check(lib().hd_swarm_create(C.byref(P), C.byref(self._ctx), C.byref(h)))
+        self.h = h
+        self.n = int(params["n_ions"])
+        self.D = len(self._e0)
+        self.dt = pdtype(params["precision"])
+
+    def run(self, n: int, accumulate: bool = False):
+        _check(lib().hd_swarm_run(self.h, int(n), int(bool(accumulate))))
+
+    def results(self) -> list:
+        out = (SwarmResult * self.D)()
+        _check(lib().hd_swarm_results(self.h, out))
+        return [{k: getattr(r, k) for k, _ in SwarmResult._fields_} for r in out]
+
+    def ions(self, f: int) -> dict:
+        o = {k: np.empty(self.n, self.dt) for k in ("vx", "vy", "vz")}
+        o["acc_vz"] = np.empty(self.n)
+        o["acc_v2"] = np.empty(self.n)
+        _check(lib().hd_swarm_get_ions(self.h, int(f), *[_ptr(o[k]) for k in
+                                                          ("vx", "vy", "vz", "acc_vz", "acc_v2")],
+                                       self.n))
+        return o
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().hd_swarm_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -227,3 +227,14 @@ def swarm_params(e0_V_m, n_ions: int = 2048, precision: int = FP32, seed: int = 
     if "rate_m3_s" not in p:
         p["rate_m3_s"] = he_ion_rate(4096, p["inv_de_per_eV"])
     return p
+
+
+# The swarm measurement: 16 fields log-spaced over 1e5 .. 1e7 V/m (the range
+# of Table 2), 2^20 He+ ions each, 2 ns to reach the stationary drift, then
+# 2 ns averaged (Sec. II.C: "after several nanoseconds").
+SWARM_WARM, SWARM_AVG = 4096, 4096
+
+
+def swarm_bench(**over) -> dict:
+    return swarm_params(np.logspace(5.0, 7.0, 16), n_ions=1 << 20, precision=FP32, seed=11,
+                        **over)

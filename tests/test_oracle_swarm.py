@@ -101,3 +101,19 @@ def test_regenerates_tables_2_and_3(E0):
     assert r["mobility"] == pytest.approx(mu_t, rel=0.05)
     assert r["nu"] == pytest.approx(nu_t, rel=0.05)
     assert r["overflow"] == 0
+
+
+def test_window_of_ion_ids_reproduces_those_ions():
+    # ions are independent: a swarm of ions [id0, id0 + n) equals that slice
+    # of a larger swarm bit for bit (used to check sampled ions at full size)
+    p = W.swarm_params([0.0, 2e6], n_ions=40)
+    full = oracle.Swarm(p)
+    full.run(50)
+    full.run(60, accumulate=True)
+    part = oracle.Swarm(dict(p, n_ions=7, id0=30))
+    part.run(50)
+    part.run(60, accumulate=True)
+    for f in range(2):
+        a, b = full.ions(f), part.ions(f)
+        for k in a:
+            np.testing.assert_array_equal(a[k][30:37], b[k])
