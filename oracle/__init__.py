@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-KIND = {"elastic": 0, "excitation": 1, "ionization": 2}
+KIND = {"elastic": 0, "excitation": 1, "ionization": 2, "attachment": 3}
 N_COUNTERS = 25
 MAX_CHANNELS = 16
 
@@ -43,15 +43,23 @@ def build(force: bool = False) -> str:
 
 
 class _Channel(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("threshold_eV", C.c_double),
-                ("sigma_m2", C.POINTER(C.c_double))]
+    _fields_ = [("kind", C.c_int32), ("product", C.c_int32), ("threshold_eV", C.c_double),
+                ("sigma_m2", C.POINTER(C.c_double)), ("target_fraction", C.c_double),
+                ("target_mass_amu", C.c_double)]
+
+
+class _Species(C.Structure):
+    _fields_ = [("charge", C.c_int32), ("n_mu", C.c_int32), ("m_amu", C.c_double),
+                ("en_lo_Td", C.c_double), ("en_hi_Td", C.c_double),
+                ("mu_m2_Vs", C.POINTER(C.c_double)), ("init_fraction", C.c_double)]
 
 
 class _Params(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("ion_model", C.c_int32), ("n_cells", C.c_int32),
         ("n_energy", C.c_int32), ("n_channels", C.c_int32), ("sort_every", C.c_int32),
-        ("eedf_every", C.c_int32), ("n_eedf_bins", C.c_int32), ("n_macro", C.c_int64),
+        ("eedf_every", C.c_int32), ("n_eedf_bins", C.c_int32), ("n_species", C.c_int32),
+        ("pad", C.c_int32), ("n_macro", C.c_int64),
         ("seed", C.c_uint64),
         ("n_gas_m3", C.c_double), ("t_gas_K", C.c_double), ("m_gas_amu", C.c_double),
         ("gap_m", C.c_double),
@@ -62,7 +70,7 @@ class _Params(C.Structure):
         ("m_ion_amu", C.c_double), ("mu_const", C.c_double), ("nu_const", C.c_double),
         ("dt_s", C.c_double), ("inv_de_per_eV", C.c_double), ("eedf_emax_eV", C.c_double),
         ("power_W_m2", C.c_double), ("power_alpha", C.c_double),
-        ("channels", C.POINTER(_Channel)),
+        ("channels", C.POINTER(_Channel)), ("species", C.POINTER(_Species)),
     ]
 
 
@@ -92,6 +100,10 @@ def lib():
             L.orc_get_derived.argtypes = [vp, vp]
             L.orc_get_table.argtypes = [vp, vp]
             L.orc_get_power.argtypes = [vp, vp]
+            L.orc_get_species.argtypes = [vp, C.c_int, vp, vp]
+            L.orc_species_mobility.restype = C.c_double
+            L.orc_species_mobility.argtypes = [vp, C.c_int, C.c_double]
+            L.orc_fluid_species.argtypes = [vp, C.c_int] + [vp] * 4
             L.orc_swarm_create.restype = vp
             L.orc_swarm_create.argtypes = [C.POINTER(_SwarmParams)]
             L.orc_swarm_free.argtypes = [vp]
@@ -157,15 +169,32 @@ class Oracle:
         arr = (_Channel * max(1, len(chans)))()
         for k, ch in enumerate(chans):
             arr[k].kind = KIND[ch["kind"]] if isinstance(ch["kind"], str) else int(ch["kind"])
+            arr[k].product = int(ch.get("product", 0))
             arr[k].threshold_eV = float(ch.get("threshold_eV", 0.0))
             arr[k].sigma_m2 = self._sig[k].ctypes.data_as(C.POINTER(C.c_double))
+            arr[k].target_fraction = float(ch.get("target_fraction", 1.0))
+            arr[k].target_mass_amu = float(ch.get("target_mass_amu", 0.0))
         self._chans = arr
+        species = params.get("species", [])
+        self._mu = [np.ascontiguousarray(q["mu_m2_Vs"], np.float64) for q in species]
+        sarr = (_Species * max(1, len(species)))()
+        for k, q in enumerate(species):
+            sarr[k].charge = int(q["charge"])
+            sarr[k].n_mu = len(self._mu[k])
+            sarr[k].m_amu = float(q["m_amu"])
+            sarr[k].en_lo_Td = float(q["en_lo_Td"])
+            sarr[k].en_hi_Td = float(q["en_hi_Td"])
+            sarr[k].mu_m2_Vs = self._mu[k].ctypes.data_as(C.POINTER(C.c_double))
+            sarr[k].init_fraction = float(q.get("init_fraction", 0.0))
+        self._species = sarr
         P = _Params()
         for name, ctype in _Params._fields_:
-            if name == "channels":
+            if name in ("channels", "species", "pad", "n_species"):
                 continue
             setattr(P, name, params[name] if name != "n_channels" else len(chans))
+        P.n_species = len(species)
         P.channels = C.cast(arr, C.POINTER(_Channel))
+        P.species = C.cast(sarr, C.POINTER(_Species))
         self._P = P
         self.h = L.orc_create(C.byref(P))
         if not self.h:
@@ -241,6 +270,23 @@ class Oracle:
         keys = ["dz", "w", "nu_max", "Pmax", "KE", "invKE", "kdz", "delta", "keedf", "qm_dt",
                 "kappa", "TN", "M", "nfloor"]
         return dict(zip(keys, v.tolist()))
+
+    def species(self, s: int) -> dict:
+        """Density and flux of ion species s."""
+        n, g = np.empty(self.nn), np.empty(self.nn)
+        lib().orc_get_species(self.h, int(s), _p(n), _p(g))
+        return {"n": n, "gamma": g}
+
+    def species_mobility(self, s: int, E: float) -> float:
+        return lib().orc_species_mobility(self.h, int(s), float(E))
+
+    def fluid_species(self, s, ni, gam, E):
+        ni = np.array(ni, np.float64)
+        gam = np.array(gam, np.float64)
+        E = np.ascontiguousarray(E, np.float64)
+        gw = np.empty(2)
+        lib().orc_fluid_species(self.h, int(s), _p(ni), _p(gam), _p(E), _p(gw))
+        return ni, gam, gw
 
     def power(self) -> dict:
         """Drive state: amplitude of the coming levels, P_abs of the last RF

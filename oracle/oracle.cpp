@@ -62,22 +62,37 @@ extern "C" {
 // Mirrors the parameters of the discharge problem (see the header comment of
 // oracle/__init__.py for the field meanings).  This struct is the oracle's own.
 typedef struct orc_channel {
-  int32_t kind;  // 0 elastic, 1 excitation, 2 ionization
-  int32_t pad;
+  int32_t kind;     // 0 elastic, 1 excitation, 2 ionization, 3 attachment
+  int32_t product;  // ion species that receives the ion of an ionization / attachment
   double threshold_eV;
   const double* sigma_m2;  // n_energy values at E_i = i / inv_de_per_eV
+  double target_fraction;  // share of n_gas_m3 that is this channel's target
+  double target_mass_amu;  // target mass for the elastic recoil (0: m_gas_amu)
 } orc_channel;
+
+// One ion species of the multi-species drift-diffusion model (ion model 4).
+typedef struct orc_species {
+  int32_t charge;  // +1 or -1
+  int32_t n_mu;    // mobility table points
+  double m_amu;
+  double en_lo_Td, en_hi_Td;  // table abscissae, log-spaced E/N [Td]
+  const double* mu_m2_Vs;     // [n_mu]
+  double init_fraction;       // initial density / initial electron density
+} orc_species;
 
 typedef struct orc_params {
   int32_t precision;  // 0: float particles, 1: double particles
   int32_t ion_model;  // 0/1: drift-diffusion / full fluid with constant mu / nu;
-                      // 2/3: the same with the fitted mu(E) / nu(u) of Tables 2 / 3
+                      // 2/3: the same with the fitted mu(E) / nu(u) of Tables 2 / 3;
+                      // 4: drift-diffusion of n_species species with tabulated mu(E/N)
   int32_t n_cells;
   int32_t n_energy;
   int32_t n_channels;
   int32_t sort_every;
   int32_t eedf_every;
   int32_t n_eedf_bins;
+  int32_t n_species;  // ion model 4 only
+  int32_t pad;
   int64_t n_macro;
   uint64_t seed;
   double n_gas_m3, t_gas_K, m_gas_amu;
@@ -92,6 +107,7 @@ typedef struct orc_params {
   double power_W_m2;   // P_0 of Eq 2.9 per electrode area; 0: fixed amplitude
   double power_alpha;  // alpha of Eq 2.9
   const orc_channel* channels;
+  const orc_species* species;
 } orc_params;
 
 // Auxiliary ion swarm (Sec. II.C): one ion species in a uniform field E_0
@@ -226,19 +242,85 @@ struct Derived {
   double kdz;       // dt/dz
   double delta;     // 2 m_e / M_gas
   double keedf;     // n_bins / E_max
+  std::vector<double> delta_k;  // per channel: 2 m_e / M_target (elastic recoil)
+  // ion species of model 4 (one entry, unused, for models 0-3)
+  struct Species {
+    int Z = 1;           // charge number
+    double kappa = 0.0;  // Eq (2.8) factor with this species' mass
+    int n = 0;           // mobility table points
+    double lo = 0.0, L0 = 0.0, inv_dL = 0.0;  // table start [Td], ln of it, points per ln unit
+    std::vector<double> mu;
+    double frac = 0.0;   // initial density / initial electron density
+  };
+  int S = 1;
+  std::vector<Species> sp;
+  double n_gas = 0.0;
 };
 
 bool derive(const orc_params& p, Derived& d) {
   if (p.n_cells < 2 || p.n_energy < 2 || p.n_channels < 0 || p.n_channels > kMaxChannels ||
       p.sort_every < 1 || p.eedf_every < 1 || p.n_eedf_bins < 1 || p.n_macro < 0 ||
       !(p.gap_m > 0) || !(p.dt_s > 0) || !(p.inv_de_per_eV > 0) || !(p.load_hi > p.load_lo) ||
-      p.load_lo < 0 || p.load_hi > 1 || (p.ion_model < 0 || p.ion_model > 3) ||
+      p.load_lo < 0 || p.load_hi > 1 || (p.ion_model < 0 || p.ion_model > 4) ||
       (p.precision != 0 && p.precision != 1) || (p.n_channels > 0 && !p.channels) ||
       !(p.power_W_m2 >= 0) || !std::isfinite(p.power_W_m2) || !(p.power_alpha >= 0) ||
       !std::isfinite(p.power_alpha) ||
       (p.power_W_m2 > 0 && !(p.f_rf_Hz > 0 && 1.0 / (p.f_rf_Hz * p.dt_s) >= 1.5))) {
     g_err = "invalid parameters";
     return false;
+  }
+  // ion species (model 4) and the products of ionization and attachment
+  d.n_gas = p.n_gas_m3;
+  if (p.ion_model == 4) {
+    if (p.n_species < 1 || p.n_species > 4 || !p.species) {
+      g_err = "ion model 4 needs 1 to 4 species";
+      return false;
+    }
+    d.S = p.n_species;
+  } else if (p.n_species != 0) {
+    g_err = "species are for ion model 4 only";
+    return false;
+  } else {
+    d.S = 1;
+  }
+  d.sp.assign(d.S, Derived::Species());
+  const double mNg = p.m_gas_amu * kAmu;
+  if (p.ion_model == 4)
+    for (int s = 0; s < d.S; ++s) {
+      const orc_species& q = p.species[s];
+      if ((q.charge != 1 && q.charge != -1) || q.n_mu < 2 || q.n_mu > 256 || !q.mu_m2_Vs ||
+          !(q.m_amu > 0) || !(q.en_lo_Td > 0) || !(q.en_hi_Td > q.en_lo_Td) ||
+          !(q.init_fraction >= 0) || !std::isfinite(q.init_fraction)) {
+        g_err = "invalid ion species";
+        return false;
+      }
+      Derived::Species& sp = d.sp[s];
+      sp.Z = q.charge;
+      const double Ms = q.m_amu * kAmu;
+      sp.kappa = (Ms + mNg) / (5.0 * Ms + 3.0 * mNg) * mNg;
+      sp.n = q.n_mu;
+      sp.lo = q.en_lo_Td;
+      sp.L0 = std::log(q.en_lo_Td);
+      sp.inv_dL = (double)(q.n_mu - 1) / (std::log(q.en_hi_Td) - sp.L0);
+      sp.mu.assign(q.mu_m2_Vs, q.mu_m2_Vs + q.n_mu);
+      for (double m : sp.mu)
+        if (!(m >= 0) || !std::isfinite(m)) {
+          g_err = "invalid ion species";
+          return false;
+        }
+      sp.frac = q.init_fraction;
+    }
+  for (int k = 0; k < p.n_channels; ++k) {
+    const orc_channel& c = p.channels[k];
+    const bool makes_ion = c.kind == 2 || c.kind == 3;
+    if (c.kind < 0 || c.kind > 3 || !(c.target_fraction >= 0) ||
+        !std::isfinite(c.target_fraction) || !(c.target_mass_amu >= 0) ||
+        (makes_ion && (c.product < 0 || c.product >= d.S)) ||
+        (c.kind == 2 && p.ion_model == 4 && d.sp[c.product].Z != 1) ||
+        (c.kind == 3 && (p.ion_model != 4 || d.sp[c.product].Z != -1))) {
+      g_err = "invalid channel";
+      return false;
+    }
   }
   d.nc = p.n_cells;
   d.nn = p.n_cells + 1;
@@ -283,7 +365,7 @@ bool derive(const orc_params& p, Derived& d) {
         g_err = "cross section must be finite and non-negative";
         return false;
       }
-      nu[(size_t)i * K + k] = p.n_gas_m3 * s * v;
+      nu[(size_t)i * K + k] = (p.n_gas_m3 * p.channels[k].target_fraction) * s * v;
       tot += nu[(size_t)i * K + k];
     }
     if (tot > d.nu_max) d.nu_max = tot;
@@ -301,6 +383,12 @@ bool derive(const orc_params& p, Derived& d) {
   d.invKE = 2.0 * kE / kMe;
   d.kdz = p.dt_s / d.dz;
   d.delta = 2.0 * kMe / (p.m_gas_amu * kAmu);
+  d.delta_k.assign(K, 0.0);
+  for (int k = 0; k < K; ++k) {
+    const double mt = p.channels[k].target_mass_amu > 0 ? p.channels[k].target_mass_amu
+                                                         : p.m_gas_amu;
+    d.delta_k[k] = 2.0 * kMe / (mt * kAmu);
+  }
   d.keedf = (double)p.n_eedf_bins / p.eedf_emax_eV;
   return true;
 }
@@ -446,6 +534,45 @@ void fluid_dd(const Derived& d, double mu_const, int fit, double* ni, const doub
   }
   gam[0] = mu[0] * n0[0] * std::min(E[0], 0.0);
   gam[nc] = mu[nc] * n0[nc] * std::max(E[nc], 0.0);
+  for (int j = 1; j < nc; ++j) ni[j] = n0[j] - d.dt_2dz * (gam[j + 1] - gam[j - 1]);
+  ni[0] = n0[0] - d.dt_dz * (gam[1] - gam[0]);
+  ni[nc] = n0[nc] - d.dt_dz * (gam[nc] - gam[nc - 1]);
+  gw[0] = gam[0];
+  gw[1] = gam[nc];
+}
+
+// Mobility of a species at field E from its table on log-spaced E/N
+// (Td = 1e-21 V m^2): linear in ln(E/N) between points, the end values
+// outside the table.
+double species_mobility(const Derived& d, const Derived::Species& sp, double E) {
+  const double x = (std::fabs(E) / d.n_gas) * 1e21;
+  if (!(x > sp.lo)) return sp.mu[0];
+  const double u = (fit_ln(x) - sp.L0) * sp.inv_dL;
+  if (!(u > 0.0)) return sp.mu[0];
+  if (!(u < (double)(sp.n - 1))) return sp.mu[sp.n - 1];
+  const int k = (int)u;
+  const double t = u - (double)k;
+  return sp.mu[k] + t * (sp.mu[k + 1] - sp.mu[k]);
+}
+
+// Drift-diffusion of one species of charge number Z (Sec. II.C, Eq (2.5)
+// with Z): Gamma_j = Z mu_j n_j E_j - D_j (n_{j+1} - n_{j-1}) / (2 dz),
+// D_j = mu_j T_j / e, T_j from Eq (2.8) with the species' mass; at the walls
+// the drift flux is kept only when it points into the wall; then Eq (2.4).
+void fluid_species(const Derived& d, const Derived::Species& sp, double* ni, const double* E,
+                   double* gam, double gw[2]) {
+  const int nc = d.nc, nn = d.nn;
+  std::vector<double> n0(ni, ni + nn), mu(nn);
+  for (int j = 0; j < nn; ++j) mu[j] = species_mobility(d, sp, E[j]);
+  for (int j = 1; j < nc; ++j) {
+    const double x = mu[j] * std::fabs(E[j]);
+    const double T = d.TN + sp.kappa * (x * x);
+    const double D = mu[j] * T / kE;
+    const double zm = (double)sp.Z * mu[j];
+    gam[j] = (zm * n0[j]) * E[j] - (D * (n0[j + 1] - n0[j - 1])) * d.inv_2dz;
+  }
+  gam[0] = std::min((((double)sp.Z * mu[0]) * n0[0]) * E[0], 0.0);
+  gam[nc] = std::max((((double)sp.Z * mu[nc]) * n0[nc]) * E[nc], 0.0);
   for (int j = 1; j < nc; ++j) ni[j] = n0[j] - d.dt_2dz * (gam[j + 1] - gam[j - 1]);
   ni[0] = n0[0] - d.dt_dz * (gam[1] - gam[0]);
   ni[nc] = n0[nc] - d.dt_dz * (gam[nc] - gam[nc - 1]);
@@ -670,7 +797,9 @@ template <class P>
 struct PConst {
   P Pmax, KE, invKE, inv_dE, kdz, delta, keedf;
   P thr[kMaxChannels];
+  P delta_k[kMaxChannels];
   int kind[kMaxChannels];
+  int product[kMaxChannels];
   int K, ne, nbins, nc;
   std::vector<P> tab;  // (ne x K) cumulative probabilities rounded to P
 };
@@ -691,6 +820,8 @@ void make_pconst(const orc_params& p, const Derived& d, PConst<P>& q) {
   for (int k = 0; k < q.K; ++k) {
     q.thr[k] = (P)p.channels[k].threshold_eV;
     q.kind[k] = p.channels[k].kind;
+    q.product[k] = p.channels[k].product;
+    q.delta_k[k] = (P)d.delta_k[k];
   }
   q.tab.resize(d.cum.size());
   for (size_t i = 0; i < d.cum.size(); ++i) q.tab[i] = (P)d.cum[i];
@@ -748,6 +879,7 @@ struct Mcc {
   int channel = -1;     // -1: no collision (null or not a candidate)
   bool overflow = false;
   bool child = false;
+  bool attached = false;
   Particle<P> kid;
 };
 
@@ -795,11 +927,14 @@ Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step
     sphere(st, n);
     const P vm = std::sqrt(v2);
     const P cosx = ((pt.vx * n[0] + pt.vy * n[1]) + pt.vz * n[2]) / vm;
-    const P fac = (P)1 - q.delta * ((P)1 - cosx);
+    const P fac = (P)1 - q.delta_k[ch] * ((P)1 - cosx);
     const P vn = std::sqrt(v2 * fac);
     pt.vx = vn * n[0];
     pt.vy = vn * n[1];
     pt.vz = vn * n[2];
+  } else if (kind == 3) {
+    // attachment: the electron is lost to a negative ion at its position
+    r.attached = true;
   } else if (kind == 1) {
     sphere(st, n);
     P er = en - q.thr[ch];
@@ -905,8 +1040,23 @@ struct Base {
     amp = p.v_amp_V;
     V_cur = amp * wave(0);
   }
+  // Ion charge density / e at the nodes: n_i itself for one species, else
+  // sum_s Z_s n_s (species in order).  ni and gam hold the species one
+  // after another (nn values each).
+  std::vector<double> net_of(const std::vector<double>& a) const {
+    const int nn = d.nn;
+    if (p.ion_model != 4) return std::vector<double>(a.begin(), a.begin() + nn);
+    std::vector<double> out(nn);
+    for (int j = 0; j < nn; ++j) {
+      double v = (double)d.sp[0].Z * a[j];
+      for (int q = 1; q < d.S; ++q) v = v + (double)d.sp[q].Z * a[(size_t)q * nn + j];
+      out[j] = v;
+    }
+    return out;
+  }
   void field() {
-    field_solve(d, cnt.data(), ni.data(), V_cur, ne.data(), rho.data(), phi.data(), E.data());
+    const std::vector<double> nq = net_of(ni);
+    field_solve(d, cnt.data(), nq.data(), V_cur, ne.data(), rho.data(), phi.data(), E.data());
   }
 
   // After step n (step already advanced to n+1): the power delivered at the
@@ -921,7 +1071,8 @@ struct Base {
     const double e0_old = E[0];  // field of level n (solved at the step's start)
     const double v_old = V_cur;
     const double v_new = amp * wave(step);
-    field_solve(d, cnt.data(), ni.data(), v_new, ne.data(), rho.data(), phi.data(), E.data());
+    const std::vector<double> nq = net_of(ni);
+    field_solve(d, cnt.data(), nq.data(), v_new, ne.data(), rho.data(), phi.data(), E.data());
     const double dn =
         (double)(ctr.emitted[0] - emi_before) - (double)(ctr.absorbed[0] - abs_before);
     const double ge = (d.w * dn) / p.dt_s;
@@ -949,9 +1100,9 @@ struct Discharge : Base {
     make_pconst(p, d, q);
     const int nn = d.nn;
     cnt.assign(nn, 0);
-    ion_src.assign(nn, 0);
-    ni.assign(nn, 0.0);
-    gam.assign(nn, 0.0);
+    ion_src.assign((size_t)d.S * nn, 0);
+    ni.assign((size_t)d.S * nn, 0.0);
+    gam.assign((size_t)d.S * nn, 0.0);
     ne.assign(nn, 0.0);
     rho.assign(nn, 0.0);
     phi.assign(nn, 0.0);
@@ -964,7 +1115,11 @@ struct Discharge : Base {
     init_drive();
     // Ions start equal to the deposited electron density, so the net charge
     // is exactly zero at t = 0; Gamma^{-1/2} = 0.
+    // With several species, species s starts at init_fraction_s times it.
     for (int j = 0; j < nn; ++j) ni[j] = (double)cnt[j] * d.scale[j];
+    if (p.ion_model == 4)
+      for (int q = d.S - 1; q >= 0; --q)
+        for (int j = 0; j < nn; ++j) ni[(size_t)q * nn + j] = d.sp[q].frac * ni[j];
     return true;
   }
 
@@ -1095,10 +1250,29 @@ struct Discharge : Base {
     field();
     for (int j = 0; j < d.nn; ++j) Ep[j] = (P)(d.qm_dt * E[j]);
     double gw[2];
+    double see_flux[2];  // positive-ion flux into each wall (emission)
     if (p.ion_model == 0 || p.ion_model == 2)
       fluid_dd(d, p.mu_const, p.ion_model == 2, ni.data(), E.data(), gam.data(), gw);
-    else
+    else if (p.ion_model == 1 || p.ion_model == 3)
       fluid_full(d, p.nu_const, p.ion_model == 3, ni.data(), E.data(), gam.data(), gw);
+    if (p.ion_model != 4) {
+      see_flux[0] = std::max(-gw[0], 0.0);
+      see_flux[1] = std::max(gw[1], 0.0);
+    } else {
+      // every species in order; gw is the net charge flux sum_s Z_s Gamma_s
+      gw[0] = gw[1] = 0.0;
+      see_flux[0] = see_flux[1] = 0.0;
+      for (int q = 0; q < d.S; ++q) {
+        double g2[2];
+        fluid_species(d, d.sp[q], &ni[(size_t)q * d.nn], E.data(), &gam[(size_t)q * d.nn], g2);
+        gw[0] = gw[0] + (double)d.sp[q].Z * g2[0];
+        gw[1] = gw[1] + (double)d.sp[q].Z * g2[1];
+        if (d.sp[q].Z > 0) {
+          see_flux[0] = see_flux[0] + std::max(-g2[0], 0.0);
+          see_flux[1] = see_flux[1] + std::max(g2[1], 0.0);
+        }
+      }
+    }
     std::vector<int64_t> nxt(d.nn, 0);
     std::vector<Particle<P>> kids;
     const bool sample = ((step + 1) % p.eedf_every) == 0;
@@ -1115,19 +1289,24 @@ struct Discharge : Base {
       Mcc<P> r = collide<P>(pt, q, p.seed, n);
       if (r.overflow) ctr.overflow += 1;
       if (r.channel >= 0) ctr.coll[r.channel] += 1;
+      if (r.attached) {  // the negative ion takes the electron's place and charge
+        deposit<P>(pt.c, pt.off, &ion_src[(size_t)q.product[r.channel] * d.nn]);
+        pt.c = -1;
+        continue;
+      }
       deposit<P>(pt.c, pt.off, nxt.data());
       if (sample) eedf[eedf_bin(pt, q)] += 1;
       if (r.child) {
         deposit<P>(r.kid.c, r.kid.off, nxt.data());
-        deposit<P>(r.kid.c, r.kid.off, ion_src.data());
+        deposit<P>(r.kid.c, r.kid.off, &ion_src[(size_t)q.product[r.channel] * d.nn]);
         if (sample) eedf[eedf_bin(r.kid, q)] += 1;
         ctr.created += 1;
         kids.push_back(r.kid);
       }
     }
     std::vector<Particle<P>> see[2];
-    emit(0, std::max(-gw[0], 0.0), n, see[0]);
-    emit(1, std::max(gw[1], 0.0), n, see[1]);
+    emit(0, see_flux[0], n, see[0]);
+    emit(1, see_flux[1], n, see[1]);
     for (int s = 0; s < 2; ++s)
       for (auto& e : see[s]) deposit<P>(e.c, e.off, nxt.data());
     for (auto& e : kids) {
@@ -1140,11 +1319,16 @@ struct Discharge : Base {
         parts.push_back(e);
       }
     cnt.swap(nxt);
+    for (int q2 = 0; q2 < d.S; ++q2)
+      for (int j = 0; j < d.nn; ++j) {
+        const size_t k = (size_t)q2 * d.nn + j;
+        ni[k] = ni[k] + (double)ion_src[k] * d.scale[j];
+        ion_src[k] = 0;
+      }
+    const std::vector<double> nq = net_of(ni);
     for (int j = 0; j < d.nn; ++j) {
-      ni[j] = ni[j] + (double)ion_src[j] * d.scale[j];
-      ion_src[j] = 0;
       acc_cnt[j] += (uint64_t)cnt[j];
-      acc_ni[j] += ni[j];
+      acc_ni[j] += nq[j];
     }
     n_acc += 1;
     step += 1;
@@ -1175,7 +1359,8 @@ struct Discharge : Base {
   }
   void get_ep(void* out) const override {
     std::vector<double> ne2(d.nn), rho2(d.nn), phi2(d.nn), E2(d.nn);
-    field_solve(d, cnt.data(), ni.data(), V_cur, ne2.data(), rho2.data(), phi2.data(),
+    const std::vector<double> nq = net_of(ni);
+    field_solve(d, cnt.data(), nq.data(), V_cur, ne2.data(), rho2.data(), phi2.data(),
                 E2.data());
     for (int j = 0; j < d.nn; ++j) ((P*)out)[j] = (P)(d.qm_dt * E2[j]);
   }
@@ -1502,12 +1687,13 @@ void orc_get_grid(void* h, int64_t* cnt, double* ni, double* gam, double* ne, do
   Base* b = static_cast<Base*>(h);
   const int nn = b->d.nn;
   std::vector<double> ne2(nn), rho2(nn), phi2(nn), E2(nn);
-  field_solve(b->d, b->cnt.data(), b->ni.data(), b->V_cur, ne2.data(), rho2.data(),
+  const std::vector<double> nq = b->net_of(b->ni), gq = b->net_of(b->gam);
+  field_solve(b->d, b->cnt.data(), nq.data(), b->V_cur, ne2.data(), rho2.data(),
               phi2.data(), E2.data());
   for (int j = 0; j < nn; ++j) {
     if (cnt) cnt[j] = b->cnt[j];
-    if (ni) ni[j] = b->ni[j];
-    if (gam) gam[j] = b->gam[j];
+    if (ni) ni[j] = nq[j];
+    if (gam) gam[j] = gq[j];
     if (ne) ne[j] = ne2[j];
     if (phi) phi[j] = phi2[j];
     if (E) E[j] = E2[j];
@@ -1529,6 +1715,27 @@ void orc_get_counters(void* h, uint64_t* out) {
   out[22] = b->ctr.see_clamped;
   out[23] = b->n_acc;
   out[24] = b->ctr.pushed;
+}
+
+// Density and flux of ion species s (ion model 4; s = 0 otherwise).
+void orc_get_species(void* h, int s, double* ni, double* gam) {
+  Base* b = static_cast<Base*>(h);
+  const int nn = b->d.nn;
+  for (int j = 0; j < nn; ++j) {
+    if (ni) ni[j] = b->ni[(size_t)s * nn + j];
+    if (gam) gam[j] = b->gam[(size_t)s * nn + j];
+  }
+}
+
+// Mobility of species s at field E, and one drift-diffusion update of that
+// species alone (in place) with a given E; returns its wall fluxes.
+double orc_species_mobility(void* h, int s, double E) {
+  Base* b = static_cast<Base*>(h);
+  return species_mobility(b->d, b->d.sp[s], E);
+}
+void orc_fluid_species(void* h, int s, double* ni, double* gam, const double* E, double* gw) {
+  Base* b = static_cast<Base*>(h);
+  fluid_species(b->d, b->d.sp[s], ni, E, gam, gw);
 }
 
 void orc_get_accum(void* h, uint64_t* acc_cnt, double* acc_ni, uint64_t* eedf) {

@@ -27,7 +27,7 @@ HE_AMU = 4.002602
 N_GAS_1ATM = 2.45e25
 
 FP32, FP64 = 0, 1
-ION_DD, ION_FULL, ION_DD_FIT, ION_FULL_FIT = 0, 1, 2, 3
+ION_DD, ION_FULL, ION_DD_FIT, ION_FULL_FIT, ION_SPECIES = 0, 1, 2, 3, 4
 
 
 def energy_grid(n_energy: int = 4096, inv_de_per_eV: float = 10.0) -> np.ndarray:
@@ -238,3 +238,96 @@ SWARM_WARM, SWARM_AVG = 4096, 4096
 def swarm_bench(**over) -> dict:
     return swarm_params(np.logspace(5.0, 7.0, 16), n_ions=1 << 20, precision=FP32, seed=11,
                         **over)
+
+
+# ---------------------------------------------------------------------------
+# Complex chemistry: He with a 0.5 % O2-like molecular admixture.  Twelve
+# synthetic channels (elastic on each target, six molecular excitations,
+# dissociative-like attachment, three ionizations) and four drift-diffusion
+# ion species with tabulated mobilities mu(E/N).
+# ---------------------------------------------------------------------------
+O2_AMU, O_AMU = 31.998, 15.999
+X_O2 = 0.005  # molecular fraction of the gas
+SPECIES_NAMES = ("He+", "He2+", "O2+", "O-")
+
+
+def _lotz(E, thr, peak_eV, peak_m2):
+    """Ionization shape s p e ln(x) x^-p, x = E/thr, peaking at peak_eV."""
+    p = 1.0 / math.log(peak_eV / thr)
+    out = np.zeros_like(E)
+    above = E > thr
+    x = E[above] / thr
+    out[above] = peak_m2 * p * math.e * np.log(x) * x ** (-p)
+    return out
+
+
+def chem_channels(n_energy: int = 4096, inv_de_per_eV: float = 10.0) -> list:
+    """The twelve channels; product = ion species index (0 He+, 1 He2+, 2 O2+, 3 O-)."""
+    E = energy_grid(n_energy, inv_de_per_eV)
+    fHe, fO2 = 1.0 - X_O2, X_O2
+    ch = [{"kind": "elastic", "threshold_eV": 0.0, "sigma_m2": np.full(n_energy, 5e-20),
+           "target_fraction": fHe, "target_mass_amu": HE_AMU},
+          {"kind": "elastic", "threshold_eV": 0.0, "sigma_m2": np.full(n_energy, 9e-20),
+           "target_fraction": fO2, "target_mass_amu": O2_AMU}]
+    for k in range(6):
+        thr = 0.2 * 50.0 ** (k / 5.0)
+        peak = 2e-21 * 0.7 ** k
+        sig = np.zeros(n_energy)
+        rise = (E >= thr) & (E < 1.5 * thr)
+        sig[rise] = peak * (E[rise] - thr) / (0.5 * thr)
+        tail = E >= 1.5 * thr
+        sig[tail] = peak * 1.5 * thr / E[tail]
+        ch.append({"kind": "excitation", "threshold_eV": thr, "sigma_m2": sig,
+                   "target_fraction": fO2, "target_mass_amu": O2_AMU})
+    fwhm = 2.0
+    att = 1e-22 * np.exp(-4.0 * math.log(2.0) * ((E - 6.5) / fwhm) ** 2)
+    ch.append({"kind": "attachment", "threshold_eV": 0.0, "sigma_m2": att, "product": 3,
+               "target_fraction": fO2, "target_mass_amu": O2_AMU})
+    ch.append({"kind": "ionization", "threshold_eV": 24.6,
+               "sigma_m2": _lotz(E, 24.6, 120.0, 3.5e-21), "product": 0,
+               "target_fraction": fHe, "target_mass_amu": HE_AMU})
+    ch.append({"kind": "ionization", "threshold_eV": 12.1,
+               "sigma_m2": _lotz(E, 12.1, 80.0, 2.5e-20), "product": 2,
+               "target_fraction": fO2, "target_mass_amu": O2_AMU})
+    ch.append({"kind": "ionization", "threshold_eV": 18.0,
+               "sigma_m2": _lotz(E, 18.0, 60.0, 1e-22), "product": 1,
+               "target_fraction": fHe, "target_mass_amu": HE_AMU})
+    return ch
+
+
+def chem_species(seed: int = 2, n_mu: int = 64) -> list:
+    """He+, He2+, O2+ and O- with mu(E/N) = mu0 (E/N)^-a on n_mu log-spaced
+    points over 1..1000 Td, (mu0, a) drawn from a seeded generator, entries
+    rounded to float32; He+ starts equal to the electron density."""
+    rng = np.random.default_rng(seed)
+    x = np.logspace(0.0, 3.0, n_mu)
+    out = []
+    for k, (name, Z, m) in enumerate(zip(SPECIES_NAMES, (1, 1, 1, -1),
+                                         (HE_AMU, 2 * HE_AMU, O2_AMU, O_AMU))):
+        mu0 = rng.uniform(0.8e-3, 2.5e-3)
+        a = rng.uniform(0.0, 0.5)
+        mu = (mu0 * x ** (-a)).astype(np.float32).astype(np.float64)
+        out.append({"name": name, "charge": Z, "m_amu": m, "en_lo_Td": 1.0, "en_hi_Td": 1000.0,
+                    "mu_m2_Vs": mu, "init_fraction": 1.0 if k == 0 else 0.0})
+    return out
+
+
+def c2(**over) -> dict:
+    """Complex chemistry: 1 mm, 1,024 cells, 4,194,304 FP32 electrons, 300 V,
+    twelve channels, four drift-diffusion ion species, 10,000 steps."""
+    p = dict(precision=FP32, ion_model=ION_SPECIES, n_cells=1024, n_macro=4194304, gap_m=1e-3,
+             v_amp_V=300.0, load_lo=0.2, load_hi=0.8, gamma_see=0.1,
+             channels=chem_channels(), species=chem_species())
+    p.update(over)
+    return base_params(**p)
+
+
+C2_STEPS = 10000
+
+
+def small_chem(precision: int = FP64, n_cells: int = 64, n_macro: int = 4096, **over) -> dict:
+    """A few-second complex-chemistry case for parity tests."""
+    p = dict(precision=precision, ion_model=ION_SPECIES, n_cells=n_cells, n_macro=n_macro,
+             gap_m=0.5e-3 * n_cells / 256.0, channels=chem_channels(), species=chem_species())
+    p.update(over)
+    return base_params(**p)

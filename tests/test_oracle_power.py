@@ -97,16 +97,28 @@ def test_power_control_settles_at_target(start):
     assert pw["p_abs"] == pytest.approx(P0, rel=2e-3)
 
 
-@pytest.mark.parametrize("model", [W.ION_DD, W.ION_FULL])
+def chem_boosted():
+    """The complex chemistry with attachment 1,000 times stronger."""
+    ch = W.chem_channels()
+    ch[8] = dict(ch[8], sigma_m2=ch[8]["sigma_m2"] * 1e3)
+    return ch
+
+
+@pytest.mark.parametrize("model", [W.ION_DD, W.ION_FULL, W.ION_SPECIES])
 def test_total_current_is_the_same_at_both_electrodes(model):
     # Discrete Gauss over the gap makes eps0 (E_N - E_0) the enclosed charge,
     # which changes only by the wall fluxes of ions and electrons; so the
     # total current e (Gamma_i - Gamma_e) + eps0 dE/dt at z = 0 (from the
     # power sum) must equal the one at z = L (from the right-wall counters,
-    # the ion flux and E_N), step by step, with ionization and emission on.
-    p = W.small(precision=1, ion_model=model, n_cells=64, n_macro=20_000, t_e0_eV=50.0,
-                v_amp_V=2000.0, phase_rad=math.pi / 2, gamma_see=1.0, load_lo=0.0,
-                load_hi=1.0, mu_const=8e-3)
+    # the net ion flux and E_N), step by step, with ionization and emission
+    # on (and, for the chemistry, attachment into the negative ion: charge
+    # moves from electrons to ions without a current).
+    kw = dict(precision=1, ion_model=model, n_cells=64, n_macro=20_000, t_e0_eV=50.0,
+              v_amp_V=2000.0, phase_rad=math.pi / 2, gamma_see=1.0, load_lo=0.0,
+              load_hi=1.0, mu_const=8e-3)
+    if model == W.ION_SPECIES:
+        kw.update(channels=chem_boosted(), species=W.chem_species(), t_e0_eV=8.0)
+    p = W.small(**kw)
     o = oracle.Oracle(p)
     w, dt = o.derived()["w"], p["dt_s"]
     g0, c0, pw0 = o.grid(), o.counters(), o.power()
@@ -127,3 +139,5 @@ def test_total_current_is_the_same_at_both_electrodes(model):
         assert abs(J0 - JL) <= 1e-7 * scale  # the field solve rounds at ~1e-9
         g0, c0, pw0 = g1, c1, pw1
     assert seen_e > 0
+    if model == W.ION_SPECIES:
+        assert o.counters()["coll"][8] > 0 and o.species(3)["n"].any()
