@@ -66,6 +66,9 @@ def workload(name: str):
     if name == "c1":
         return W.c1(), ("single large discharge: He 1 atm, 1 mm, 2048 cells, 250 V, "
                         "8,388,608 FP32 electrons, full ion fluid, sort every 16")
+    if name == "c2":
+        return W.c2(), ("complex chemistry: He + 0.5% O2-like, 1 mm, 1024 cells, 300 V, "
+                        "4,194,304 FP32 electrons, 12 channels with attachment, 4 DD ion species")
     if name == "c0":
         return W.c0(), ("small plain discharge: He 1 atm, 0.5 mm, 256 cells, 150 V, "
                         "16,384 FP64 electrons, drift-diffusion ions")

@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define HD_ABI_VERSION 2
+#define HD_ABI_VERSION 3
 
 enum hd_status {
   HD_OK = 0,
@@ -59,23 +59,54 @@ enum hd_ion_model {
   HD_ION_DD_CONST_MU = 0,
   HD_ION_FULL_CONST_NU = 1,
   HD_ION_DD_FIT_MU = 2,
-  HD_ION_FULL_FIT_NU = 3
+  HD_ION_FULL_FIT_NU = 3,
+  HD_ION_DD_SPECIES = 4   /* several drift-diffusion species, see hd_ion_species */
 };
 
 /* Electron-neutral reaction kinds (Table 1: R1 elastic, R2 ionization,
- * R3 excitation). */
-enum hd_xs_kind { HD_XS_ELASTIC = 0, HD_XS_EXCITATION = 1, HD_XS_IONIZATION = 2 };
+ * R3 excitation), and attachment: the electron is lost to a negative ion
+ * (the removal of Sec. II.D applied to attachment). */
+enum hd_xs_kind {
+  HD_XS_ELASTIC = 0,
+  HD_XS_EXCITATION = 1,
+  HD_XS_IONIZATION = 2,
+  HD_XS_ATTACHMENT = 3
+};
 
 #define HD_MAX_CHANNELS 16
+#define HD_MAX_SPECIES 4
 
 /* One electron-neutral channel.  sigma_m2 holds n_energy cross sections [m^2]
- * on the uniform grid E_i = i / inv_de_per_eV (caller-owned, copied). */
+ * on the uniform grid E_i = i / inv_de_per_eV (caller-owned, copied).  The
+ * channel's collision frequency is (n_gas_m3 target_fraction) sigma v. */
 typedef struct hd_xs_channel {
   int32_t kind;          /* enum hd_xs_kind                                  */
-  int32_t reserved;
+  int32_t product;       /* ion species that receives the ion of an
+                            ionization (charge +1) or attachment (charge -1);
+                            0 for the single-species ion models            */
   double threshold_eV;   /* energy lost in excitation / ionization           */
   const double* sigma_m2;
+  double target_fraction; /* share of n_gas_m3 that is this channel's target,
+                             in [0, inf) (1: the whole gas)                  */
+  double target_mass_amu; /* target mass of the elastic recoil 2 m_e / M
+                             (0: m_gas_amu)                                 */
 } hd_xs_channel;
+
+/* One ion species of HD_ION_DD_SPECIES: drift-diffusion (Sec. II.C, Eq 2.5
+ * with the charge sign) with a mobility tabulated against E/N on n_mu
+ * log-spaced points from en_lo_Td to en_hi_Td (1 Td = 1e-21 V m^2),
+ * interpolated linearly in ln(E/N) and held at the end values outside;
+ * Eq (2.8) with the species' mass; the wall flux is kept only when the
+ * drift points into the wall.  The species starts at init_fraction times
+ * the initial electron density. */
+typedef struct hd_ion_species {
+  int32_t charge;        /* +1 or -1                                         */
+  int32_t n_mu;          /* 2 .. 256                                         */
+  double m_amu;
+  double en_lo_Td, en_hi_Td;
+  const double* mu_m2_Vs; /* [n_mu] (caller-owned, copied)                   */
+  double init_fraction;
+} hd_ion_species;
 
 /* Problem statement of one discharge (caller-owned, copied at creation). */
 typedef struct hd_params {
@@ -88,7 +119,7 @@ typedef struct hd_params {
   int32_t sort_every;    /* compaction + stable cell sort every this many steps */
   int32_t eedf_every;    /* EEDF sample every this many steps                */
   int32_t n_eedf_bins;   /* EEDF bins over [0, eedf_emax_eV)                 */
-  int32_t reserved;
+  int32_t n_species;     /* HD_ION_DD_SPECIES: 1 .. HD_MAX_SPECIES; else 0   */
   int64_t n_macro;       /* N_0 initial electron superparticles              */
   int64_t capacity;      /* particle slots reserved (>= n_macro)             */
   uint64_t seed;         /* Philox key                                       */
@@ -123,6 +154,7 @@ typedef struct hd_params {
   double power_W_m2;     /* P_0 / S, prescribed absorbed power [W/m^2], >= 0 */
   double power_alpha;    /* alpha of Eq 2.9, >= 0                            */
   const hd_xs_channel* channels; /* n_channels entries, caller-owned, copied */
+  const hd_ion_species* species; /* n_species entries, caller-owned, copied  */
 } hd_params;
 
 /* Device context.  stream: a hipStream_t (NULL = the default stream).
@@ -146,12 +178,16 @@ typedef struct hd_moment_set {
   int32_t n_eedf_bins;
   int32_t error;           /* device-side sticky error (0 = none)            */
   double* n_e;             /* [n_nodes] electron density of the current step */
-  double* n_i;             /* [n_nodes] ion density                          */
+  double* n_i;             /* [n_nodes] ion charge density / e: n_i, or with
+                              several species sum_s charge_s n_s           */
   double* phi;             /* [n_nodes] potential of the current step [V]    */
   double* E;               /* [n_nodes] field of the current step [V/m]      */
-  double* gamma_i;         /* [n_nodes] last ion flux [m^-2 s^-1]            */
+  double* gamma_i;         /* [n_nodes] last ion flux [m^-2 s^-1] (several
+                              species: sum_s charge_s Gamma_s)              */
   double* n_e_avg;         /* [n_nodes] average of n_e over completed steps  */
   double* n_i_avg;         /* [n_nodes] average of n_i over completed steps  */
+  double* n_species;       /* [n_species * n_nodes] species densities, or NULL */
+  double* gamma_species;   /* [n_species * n_nodes] species fluxes, or NULL  */
   int64_t* cnt;            /* [n_nodes] fixed-point deposit (2^32 per particle) */
   uint64_t* eedf_counts;   /* [n_eedf_bins + 1], last entry = overflow       */
   double* eedf;            /* [n_eedf_bins] normalised: sum f dE = 1         */

@@ -20,6 +20,8 @@ constexpr int kMaxSegs = 4096;    // particle workgroups of one electron launch
 constexpr int kSphereTries = 64;   // bound of the rejection loops
 constexpr int kSortTile = 4096;    // items per sort tile (one wave)
 constexpr int kFinThreads = 1024;  // field/finalize workgroup
+constexpr int kMaxSpecies = 4;     // ion species of the multi-species model
+constexpr int kMaxMu = 256;        // mobility-table points per species
 
 // Mutable per-discharge scalars.  They live in device memory so that a
 // captured sequence of launches can advance without host involvement.
@@ -44,6 +46,8 @@ struct State {
   int32_t append_pending;  // set by the finalize kernel when particles are to be appended
   uint32_t n_live_sorted;  // live particles counted by the sort
   double wall[2];        // ion wall fluxes Gamma_0, Gamma_N of the last fluid update
+                         // (several species: the net charge flux sum_s Z_s Gamma_s)
+  double see_flux[2];    // several species: positive-ion flux into each wall
   uint64_t coll[kMaxK];
   uint64_t absorbed[2];
   uint64_t emitted[2];
@@ -74,12 +78,22 @@ struct Disch {
   // electron constants rounded to P
   P Pmax, KE, invKE, inv_dE, kdz, delta, keedf;
   P thr[kMaxK];
+  P delta_k[kMaxK];      // elastic recoil 2 m_e / M_target per channel
   int32_t kind[kMaxK];
+  int32_t product[kMaxK];  // ion species of an ionization / attachment
   // FP64 constants of the field, fluid and emission
   double dz, L, w, kp, inv_dz, inv_2dz, hdz_eps, qm_dt, scale_in, scale_wall;
   double mu, nu, mu_full, TN, kappa, M, dt, dt_2dz, dt_dz, e_M_dt, dt_2dzM, hdt, nfloor;
   double gamma_see, see_v;  // emission coefficient and speed sqrt(E_sec 2e/m_e)
   double power_P0, power_alpha;  // Eq 2.9 (power_P0 = 0: fixed amplitude)
+  // ion species (S = 1 for the single-species models: Z = +1)
+  int32_t S;
+  int32_t Z[kMaxSpecies];
+  int32_t n_mu[kMaxSpecies];
+  double kappa_s[kMaxSpecies];                // Eq (2.8) factor per species
+  double mu_lo[kMaxSpecies], mu_L0[kMaxSpecies], mu_inv_dL[kMaxSpecies];
+  const double* mu_tab;                       // [S * kMaxMu] mobility tables
+  double n_gas;
   int64_t rf_steps;              // steps per RF period (0: no period ends)
   int64_t volt_len;
   // tables
@@ -110,9 +124,9 @@ struct Disch {
   P* svz;
   // grids
   int64_t* cnt[2];
-  int64_t* ion_src;
-  double* ni;
-  double* gam;
+  int64_t* ion_src;  // [S * nn]
+  double* ni;        // [S * nn]
+  double* gam;       // [S * nn]
   double* phi;
   double* E;
   P* Ep;

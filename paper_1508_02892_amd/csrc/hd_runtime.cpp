@@ -125,16 +125,42 @@ bool validate(const hd_params* p, std::string& why) {
   if (!p) return (why = "null params"), false;
   if (p->abi_version != HD_ABI_VERSION) return (why = "abi_version mismatch"), false;
   if (p->precision != HD_FP32 && p->precision != HD_FP64) return (why = "precision"), false;
-  if (p->ion_model < HD_ION_DD_CONST_MU || p->ion_model > HD_ION_FULL_FIT_NU)
+  if (p->ion_model < HD_ION_DD_CONST_MU || p->ion_model > HD_ION_DD_SPECIES)
     return (why = "ion_model"), false;
+  const bool multi = p->ion_model == HD_ION_DD_SPECIES;
+  if (multi && (p->n_species < 1 || p->n_species > HD_MAX_SPECIES || !p->species))
+    return (why = "HD_ION_DD_SPECIES needs 1 .. 4 species"), false;
+  if (!multi && p->n_species != 0) return (why = "species are for HD_ION_DD_SPECIES"), false;
+  if (multi)
+    for (int q = 0; q < p->n_species; ++q) {
+      const hd_ion_species& sp = p->species[q];
+      if ((sp.charge != 1 && sp.charge != -1) || sp.n_mu < 2 || sp.n_mu > kMaxMu ||
+          !sp.mu_m2_Vs || !(sp.m_amu > 0) || !(sp.en_lo_Td > 0) ||
+          !(sp.en_hi_Td > sp.en_lo_Td) || !std::isfinite(sp.en_hi_Td) ||
+          !(sp.init_fraction >= 0) || !std::isfinite(sp.init_fraction))
+        return (why = "ion species " + std::to_string(q)), false;
+      for (int i = 0; i < sp.n_mu; ++i)
+        if (!(sp.mu_m2_Vs[i] >= 0) || !std::isfinite(sp.mu_m2_Vs[i]))
+          return (why = "mobility table of species " + std::to_string(q)), false;
+    }
   if (p->n_cells < 2 || p->n_cells > kMaxCells) return (why = "n_cells out of [2, 4096]"), false;
   if (p->n_energy < 2 || p->n_energy > (1 << 20)) return (why = "n_energy"), false;
   if (p->n_channels < 0 || p->n_channels > HD_MAX_CHANNELS) return (why = "n_channels"), false;
   if (p->n_channels > 0 && !p->channels) return (why = "channels missing"), false;
   for (int k = 0; k < p->n_channels; ++k) {
     const hd_xs_channel& c = p->channels[k];
-    if (c.kind < HD_XS_ELASTIC || c.kind > HD_XS_IONIZATION || !c.sigma_m2)
+    if (c.kind < HD_XS_ELASTIC || c.kind > HD_XS_ATTACHMENT || !c.sigma_m2 ||
+        !(c.target_fraction >= 0) || !std::isfinite(c.target_fraction) ||
+        !(c.target_mass_amu >= 0) || !std::isfinite(c.target_mass_amu))
       return (why = "channel " + std::to_string(k)), false;
+    const int S = multi ? p->n_species : 1;
+    if ((c.kind == HD_XS_IONIZATION || c.kind == HD_XS_ATTACHMENT) &&
+        (c.product < 0 || c.product >= S))
+      return (why = "channel " + std::to_string(k) + ": product species"), false;
+    if (c.kind == HD_XS_IONIZATION && multi && p->species[c.product].charge != 1)
+      return (why = "channel " + std::to_string(k) + ": ionization makes a positive ion"), false;
+    if (c.kind == HD_XS_ATTACHMENT && (!multi || p->species[c.product].charge != -1))
+      return (why = "channel " + std::to_string(k) + ": attachment makes a negative ion"), false;
     for (int i = 0; i < p->n_energy; ++i)
       if (!(c.sigma_m2[i] >= 0) || !std::isfinite(c.sigma_m2[i]))
         return (why = "cross section must be finite and non-negative"), false;
@@ -180,7 +206,7 @@ struct Offsets {
   size_t cell[2], off[2], vx[2], vy[2], vz[2], id[2];
   size_t kc, koff, kvx, kvy, kvz, chunk_kids, chunk_base, seg;
   size_t sc, soff, svx, svy, svz;
-  size_t cnt[2], ion_src, ni, gam, phi, E, Ep, scratch, acc_cnt, acc_ni, eedf;
+  size_t cnt[2], ion_src, ni, gam, mu, phi, E, Ep, scratch, acc_cnt, acc_ni, eedf;
   size_t ip, tab, hist, parts, tile_rng, st, volt;
   size_t total;
 };
@@ -214,9 +240,11 @@ Offsets<P> layout(const hd_params& p, int64_t volt_len) {
   o.svz = L.take(2 * kSeeMax * sizeof(P));
   o.cnt[0] = L.take(nn * 8);
   o.cnt[1] = L.take(nn * 8);
-  o.ion_src = L.take(nn * 8);
-  o.ni = L.take(nn * 8);
-  o.gam = L.take(nn * 8);
+  const size_t S = p.ion_model == HD_ION_DD_SPECIES ? (size_t)p.n_species : 1;
+  o.ion_src = L.take(S * nn * 8);
+  o.ni = L.take(S * nn * 8);
+  o.gam = L.take(S * nn * 8);
+  o.mu = L.take(S * kMaxMu * 8);
   o.phi = L.take(nn * 8);
   o.E = L.take(nn * 8);
   o.Ep = L.take(nn * sizeof(P));
@@ -243,6 +271,8 @@ struct Host {
   hd_params p{};
   std::vector<hd_xs_channel> ch;
   std::vector<std::vector<double>> sig;
+  std::vector<hd_ion_species> sp;
+  std::vector<std::vector<double>> mu;
   Disch<P> dd{};             // host copy of the device descriptor
   unsigned char* base = nullptr;
   size_t bytes = 0;
@@ -323,7 +353,8 @@ void derive(Host<P>& h, std::vector<double>& ip, std::vector<P>& tab) {
     const double v = std::sqrt(2.0 * kE * Ei / kMe);
     double tot = 0.0;
     for (int k = 0; k < K; ++k) {
-      nu[(size_t)i * K + k] = p.n_gas_m3 * p.channels[k].sigma_m2[i] * v;
+      nu[(size_t)i * K + k] =
+          (p.n_gas_m3 * p.channels[k].target_fraction) * p.channels[k].sigma_m2[i] * v;
       tot += nu[(size_t)i * K + k];
     }
     if (tot > nu_max) nu_max = tot;
@@ -343,6 +374,31 @@ void derive(Host<P>& h, std::vector<double>& ip, std::vector<P>& tab) {
   d.inv_dE = (P)p.inv_de_per_eV;
   d.kdz = (P)(p.dt_s / dz);
   d.delta = (P)(2.0 * kMe / (p.m_gas_amu * kAmu));
+  for (int k = 0; k < K; ++k) {
+    const double mt = p.channels[k].target_mass_amu > 0 ? p.channels[k].target_mass_amu
+                                                         : p.m_gas_amu;
+    d.delta_k[k] = (P)(2.0 * kMe / (mt * kAmu));
+    d.product[k] = p.channels[k].product;
+  }
+  // ion species: one of charge +1 for the single-species models
+  d.n_gas = p.n_gas_m3;
+  const double mNs = p.m_gas_amu * kAmu;
+  if (p.ion_model == HD_ION_DD_SPECIES) {
+    d.S = p.n_species;
+    for (int q = 0; q < d.S; ++q) {
+      const hd_ion_species& sp = p.species[q];
+      const double Ms = sp.m_amu * kAmu;
+      d.Z[q] = sp.charge;
+      d.n_mu[q] = sp.n_mu;
+      d.kappa_s[q] = (Ms + mNs) / (5.0 * Ms + 3.0 * mNs) * mNs;
+      d.mu_lo[q] = sp.en_lo_Td;
+      d.mu_L0[q] = std::log(sp.en_lo_Td);
+      d.mu_inv_dL[q] = (double)(sp.n_mu - 1) / (std::log(sp.en_hi_Td) - d.mu_L0[q]);
+    }
+  } else {
+    d.S = 1;
+    d.Z[0] = 1;
+  }
   h.keedf = (double)p.n_eedf_bins / p.eedf_emax_eV;
   d.keedf = (P)h.keedf;
   for (int k = 0; k < kMaxK; ++k) {
@@ -486,7 +542,7 @@ struct Batch : BatchBase {
   // Host-side preparation of one discharge (no device calls): derived
   // constants, tables, the initial load and the voltage table.
   struct Prepared {
-    std::vector<double> ip, ni, vt;
+    std::vector<double> ip, ni, vt, mu;
     std::vector<P> tab;
     Loaded<P> ld;
   };
@@ -494,10 +550,18 @@ struct Batch : BatchBase {
     derive<P>(h, pr.ip, pr.tab);
     h.volt_len = volt_len;
     load<P>(h.p, h.dd.dz, pr.ld);
-    const int nn = h.dd.nn;
-    pr.ni.resize(nn);
+    const int nn = h.dd.nn, S = h.dd.S;
+    pr.ni.assign((size_t)S * nn, 0.0);
     for (int j = 0; j < nn; ++j)
       pr.ni[j] = (double)pr.ld.cnt[j] * ((j == 0 || j == h.dd.nc) ? h.scale_wall : h.scale_in);
+    // several species: species q starts at init_fraction_q of the electrons
+    if (h.p.ion_model == HD_ION_DD_SPECIES)
+      for (int q = S - 1; q >= 0; --q)
+        for (int j = 0; j < nn; ++j)
+          pr.ni[(size_t)q * nn + j] = h.p.species[q].init_fraction * pr.ni[j];
+    pr.mu.assign((size_t)S * kMaxMu, 0.0);
+    for (int q = 0; q < h.p.n_species; ++q)
+      std::copy(h.mu[q].begin(), h.mu[q].end(), pr.mu.begin() + (size_t)q * kMaxMu);
     pr.vt.resize(volt_len);
     for (int64_t s = 0; s < volt_len; ++s) pr.vt[s] = volt_at(h.p, s);
   }
@@ -525,7 +589,9 @@ struct Batch : BatchBase {
       HD_TRY(hipMemcpyAsync(d.id[0], ld.id.data(), N * 4, hipMemcpyHostToDevice, stream));
     }
     HD_TRY(hipMemcpyAsync(d.cnt[0], ld.cnt.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
-    HD_TRY(hipMemcpyAsync(d.ni, pr.ni.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
+    HD_TRY(hipMemcpyAsync(d.ni, pr.ni.data(), pr.ni.size() * 8, hipMemcpyHostToDevice, stream));
+    HD_TRY(hipMemcpyAsync((void*)d.mu_tab, pr.mu.data(), pr.mu.size() * 8, hipMemcpyHostToDevice,
+                          stream));
     HD_TRY(hipMemcpyAsync((void*)d.ip, pr.ip.data(), d.nn * 8, hipMemcpyHostToDevice, stream));
     HD_TRY(hipMemcpyAsync((void*)d.tab, pr.tab.data(), pr.tab.size() * sizeof(P),
                           hipMemcpyHostToDevice, stream));
@@ -571,6 +637,7 @@ struct Batch : BatchBase {
     d.ion_src = (int64_t*)(b + o.ion_src);
     d.ni = (double*)(b + o.ni);
     d.gam = (double*)(b + o.gam);
+    d.mu_tab = (const double*)(b + o.mu);
     d.phi = (double*)(b + o.phi);
     d.E = (double*)(b + o.E);
     d.Ep = (P*)(b + o.Ep);
@@ -610,6 +677,14 @@ struct Batch : BatchBase {
         h.ch[k].sigma_m2 = h.sig[k].data();
       }
       h.p.channels = h.ch.empty() ? nullptr : h.ch.data();
+      h.sp.resize(h.p.n_species);
+      h.mu.resize(h.p.n_species);
+      for (int q = 0; q < h.p.n_species; ++q) {
+        h.mu[q].assign(h.p.species[q].mu_m2_Vs, h.p.species[q].mu_m2_Vs + h.p.species[q].n_mu);
+        h.sp[q] = h.p.species[q];
+        h.sp[q].mu_m2_Vs = h.mu[q].data();
+      }
+      h.p.species = h.sp.empty() ? nullptr : h.sp.data();
       tab_max = std::max(tab_max, h.p.n_energy * std::max(1, h.p.n_channels));
       K_max = std::max(K_max, h.p.n_channels);
       nn_max = std::max(nn_max, h.p.n_cells + 1);
@@ -802,10 +877,32 @@ struct Batch : BatchBase {
     if (m->cnt) std::copy(cnt.begin(), cnt.end(), m->cnt);
     if (m->n_e)
       for (int j = 0; j < nn; ++j) m->n_e[j] = (double)cnt[j] * sc(j);
-    if (m->n_i) HD_TRY(hipMemcpy(m->n_i, d.ni, nn * 8, hipMemcpyDeviceToHost));
+    // ion charge density and flux: species 0 alone, or sum_s Z_s x_s
+    const int S = d.S;
+    auto net = [&](const double* src, double* out) -> int {
+      std::vector<double> a((size_t)S * nn);
+      HD_TRY(hipMemcpy(a.data(), src, a.size() * 8, hipMemcpyDeviceToHost));
+      for (int j = 0; j < nn; ++j) {
+        double v = (double)d.Z[0] * a[j];
+        for (int q = 1; q < S; ++q) v = v + (double)d.Z[q] * a[(size_t)q * nn + j];
+        out[j] = v;
+      }
+      return HD_OK;
+    };
+    if (m->n_i) {
+      if (S == 1) HD_TRY(hipMemcpy(m->n_i, d.ni, nn * 8, hipMemcpyDeviceToHost));
+      else if (int r = net(d.ni, m->n_i)) return r;
+    }
+    if (m->gamma_i) {
+      if (S == 1) HD_TRY(hipMemcpy(m->gamma_i, d.gam, nn * 8, hipMemcpyDeviceToHost));
+      else if (int r = net(d.gam, m->gamma_i)) return r;
+    }
+    if (m->n_species)
+      HD_TRY(hipMemcpy(m->n_species, d.ni, (size_t)S * nn * 8, hipMemcpyDeviceToHost));
+    if (m->gamma_species)
+      HD_TRY(hipMemcpy(m->gamma_species, d.gam, (size_t)S * nn * 8, hipMemcpyDeviceToHost));
     if (m->phi) HD_TRY(hipMemcpy(m->phi, d.phi, nn * 8, hipMemcpyDeviceToHost));
     if (m->E) HD_TRY(hipMemcpy(m->E, d.E, nn * 8, hipMemcpyDeviceToHost));
-    if (m->gamma_i) HD_TRY(hipMemcpy(m->gamma_i, d.gam, nn * 8, hipMemcpyDeviceToHost));
     if (m->n_e_avg) {
       std::vector<uint64_t> a(nn);
       HD_TRY(hipMemcpy(a.data(), d.acc_cnt, nn * 8, hipMemcpyDeviceToHost));
@@ -1075,7 +1172,8 @@ struct Server : ServerBase {
         p->n_energy > cfg.max_energy || p->n_channels > cfg.max_channels ||
         p->n_energy * std::max(1, p->n_channels) > tab_max ||
         p->n_eedf_bins > cfg.max_eedf_bins ||
-        (full_fluid(p->ion_model) && !cfg.allow_full_fluid))
+        (full_fluid(p->ion_model) && !cfg.allow_full_fluid) ||
+        p->ion_model == HD_ION_DD_SPECIES)
       return fail(HD_EINVAL, "job does not fit the server's slot configuration");
     auto job = std::make_unique<Job>();
     job->p = *p;

@@ -96,6 +96,7 @@ struct Seg {
   P kdz, Pmax, KE, inv_dE, keedf;
   int tab_rows, nc, ne, K, nbins;
   uint32_t ion_mask;  // bit k: channel k is an ionization
+  uint32_t att_mask;  // bit k: channel k is an attachment
   uint32_t seed_lo, seed_hi, step, n_main;
   bool sample;
 };
@@ -107,11 +108,13 @@ __device__ __forceinline__ int eedf_bin(P vx, P vy, P vz, const Seg<P>& g) {
   return (x < (P)g.nbins) ? (int)x : g.nbins;
 }
 
-// Scattering of one queued collision (elastic / excitation / ionization).
-// The particle's new velocity goes straight to its slot; an ionization's new
-// electron goes to the staging area of its sub-chunk, with its deposit, ion
-// source and EEDF sample.
-template <class P>
+// Scattering of one queued collision (elastic / excitation / ionization /
+// attachment).  The particle's new velocity goes straight to its slot; an
+// ionization's new electron goes to the staging area of its sub-chunk, with
+// its deposit, ion source (of the channel's product species) and EEDF
+// sample; an attached electron's slot becomes a hole and its charge joins
+// the negative-ion source at its position (it was not deposited).
+template <class P, bool ATT>
 __device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
   Stream s(d.seed, kTagElectron, e.id, g.step);
   for (int w = 0; w < Uni<P>::kWords; ++w) (void)s.word();  // R used by the null test
@@ -121,11 +124,21 @@ __device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
   const P en = d.KE * v2;
   const int kind = d.kind[ch];
   P nx, ny, nz, ox, oy, oz;
+  if (ATT && kind == 3) {
+    const int64_t W1 = cic_w1<P>(e.off);
+    const int64_t W0 = ((int64_t)1 << 32) - W1;
+    int64_t* src = d.ion_src + (size_t)d.product[ch] * (size_t)d.nn;
+    atomic_add_i64(&src[e.c], W0);
+    atomic_add_i64(&src[e.c + 1], W1);
+    g.cell[e.slot] = -1;
+    atomicAdd(&g.ctr[ch], 1u);
+    return;
+  }
   if (kind == 0) {
     sphere<P>(s, nx, ny, nz);
     const P vm = sqrt(v2);
     const P cosx = ((vx * nx + vy * ny) + vz * nz) / vm;
-    const P fac = (P)1 - d.delta * ((P)1 - cosx);
+    const P fac = (P)1 - d.delta_k[ch] * ((P)1 - cosx);
     const P vn = sqrt(v2 * fac);
     ox = vn * nx;
     oy = vn * ny;
@@ -163,8 +176,9 @@ __device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
     const int64_t W0 = ((int64_t)1 << 32) - W1;
     lds_add_i64(&g.bins[e.c], (uint64_t)W0);
     lds_add_i64(&g.bins[e.c + 1], (uint64_t)W1);
-    atomic_add_i64(&d.ion_src[e.c], W0);
-    atomic_add_i64(&d.ion_src[e.c + 1], W1);
+    int64_t* src = d.ion_src + (size_t)d.product[ch] * (size_t)d.nn;
+    atomic_add_i64(&src[e.c], W0);
+    atomic_add_i64(&src[e.c + 1], W1);
     if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(cvx, cvy, cvz, g)], 1u);
     atomicAdd(&g.ctr[kCtrCreated], 1u);
   }
@@ -177,11 +191,11 @@ __device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
 
 // One wave scatters the first n (<= 64) queue entries, then moves the rest
 // (< 64) to the front.  The queue belongs to this wave alone.
-template <class P>
+template <class P, bool ATT>
 __device__ __forceinline__ void drain(const Disch<P>& d, const Seg<P>& g, QEntry<P>* q,
                                       uint32_t& qn, uint32_t n) {
   const uint32_t lane = (uint32_t)(threadIdx.x & 63);
-  if (lane < n) handle<P>(d, g, q[lane]);
+  if (lane < n) handle<P, ATT>(d, g, q[lane]);
   const uint32_t rest = qn - n;
   QEntry<P> t;
   if (lane < rest) t = q[n + lane];
@@ -310,6 +324,11 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     bool ovf = false;
     if (alive[j] && u0 < g.Pmax) ch[j] = select_channel<P, KC>(g, u0, vx[j], vy[j], vz[j], ovf);
     wc.ovf += (uint32_t)__popcll(__ballot(ovf));
+    // an attached electron leaves before the deposit (its charge goes to
+    // the negative ion when the collision is handled); the three-channel
+    // path serves only tables without attachment
+    if constexpr (KC == 0)
+      if (g.att_mask && ch[j] >= 0 && ((g.att_mask >> ch[j]) & 1u)) alive[j] = false;
   }
   // deposit at x^{n+1}.  W0 + W1 = 2^32 per particle, so a run of m
   // particles in one cell adds m 2^32 - sum W1 to its left node and sum W1
@@ -393,7 +412,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
       kid += ion ? 1u : 0u;
     }
     qn += (uint32_t)__popcll(mk);
-    if (qn >= 64u) drain<P>(d, g, q, qn, 64u);
+    if (qn >= 64u) drain<P, KC == 0>(d, g, q, qn, 64u);
   }
 }
 
@@ -458,6 +477,9 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   uint32_t im = 0;
   for (int k = 0; k < d.K; ++k) im |= (d.kind[k] == 2 ? 1u : 0u) << k;
   g.ion_mask = im;
+  uint32_t am = 0;
+  for (int k = 0; k < d.K; ++k) am |= (d.kind[k] == 3 ? 1u : 0u) << k;
+  g.att_mask = am;
   g.seed_lo = (uint32_t)d.seed;
   g.seed_hi = (uint32_t)(d.seed >> 32);
   g.step = (uint32_t)st->step;
@@ -476,11 +498,13 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   __syncthreads();
   uint32_t qn = 0;
   WaveCounts wc;
-  if (g.K == 3)  // elastic, excitation, ionization: the common case, unrolled
+  if (g.K == 3 && g.att_mask == 0) {  // elastic, excitation, ionization: unrolled
     for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P, 3>(d, g, lc, q, qn, wc);
-  else
+    if (qn) drain<P, false>(d, g, q, qn, qn);
+  } else {
     for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P, 0>(d, g, lc, q, qn, wc);
-  if (qn) drain<P>(d, g, q, qn, qn);
+    if (qn) drain<P, true>(d, g, q, qn, qn);
+  }
   if ((tid & 63) == 0) {
     if (wc.absl) atomicAdd(&g.ctr[kCtrAbsL], wc.absl);
     if (wc.absr) atomicAdd(&g.ctr[kCtrAbsR], wc.absr);
@@ -681,6 +705,86 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
   __syncthreads();
 }
 
+// Several drift-diffusion species (ion model 4): the mobility of species q
+// at field E from its table on log-spaced E/N, linear in ln(E/N), end values
+// outside.
+template <class P>
+__device__ __forceinline__ double species_mu(const Disch<P>& d, int q, double E) {
+  const double* tab = d.mu_tab + (size_t)q * kMaxMu;
+  const double x = (fabs(E) / d.n_gas) * 1e21;
+  if (!(x > d.mu_lo[q])) return tab[0];
+  const double u = (fit_log(x) - d.mu_L0[q]) * d.mu_inv_dL[q];
+  if (!(u > 0.0)) return tab[0];
+  const int n = d.n_mu[q];
+  if (!(u < (double)(n - 1))) return tab[n - 1];
+  const int k = (int)u;
+  const double t = u - (double)k;
+  return tab[k] + t * (tab[k + 1] - tab[k]);
+}
+
+// Each species in turn: Gamma_j = Z mu n_j E_j - D_j (n_{j+1} - n_{j-1})/(2 dz)
+// with D = mu T / e and T from Eq (2.8) with the species' mass; at the walls
+// the drift flux only when it points into the wall; then Eq (2.4).  The
+// net charge flux sum_s Z_s Gamma_s at the walls goes to the state (absorbed
+// power) and the positive-ion flux into each wall (emission).
+template <class P>
+__device__ void fluid_species(const Disch<P>& d, double* lds) {
+  const int tid = threadIdx.x, nc = d.nc, nn = d.nn;
+  const double* __restrict__ E = d.E;
+  double* G = lds;
+  double w0 = 0.0, w1 = 0.0, f0 = 0.0, f1 = 0.0;
+  for (int q = 0; q < d.S; ++q) {
+    double* __restrict__ ni = d.ni + (size_t)q * nn;
+    double* __restrict__ gam = d.gam + (size_t)q * nn;
+    const double Zd = (double)d.Z[q];
+    const double kap = d.kappa_s[q];
+    for (int j = tid; j < nn; j += kElecThreads) {
+      const double ej = E[j];
+      const double mu = species_mu(d, q, ej);
+      double g;
+      if (j == 0) {
+        g = dmin0(((Zd * mu) * ni[0]) * ej);
+      } else if (j == nc) {
+        g = dmax0(((Zd * mu) * ni[nc]) * ej);
+      } else {
+        const double nl = ni[j - 1], nj = ni[j], nr = ni[j + 1];
+        const double x = mu * fabs(ej);
+        const double T = d.TN + kap * (x * x);
+        const double Dc = (mu * T) / kECharge;
+        g = ((Zd * mu) * nj) * ej - (Dc * (nr - nl)) * d.inv_2dz;
+      }
+      G[j] = g;
+    }
+    __syncthreads();
+    for (int j = tid; j < nn; j += kElecThreads) {
+      double v;
+      if (j == 0)
+        v = ni[0] - d.dt_dz * (G[1] - G[0]);
+      else if (j == nc)
+        v = ni[nc] - d.dt_dz * (G[nc] - G[nc - 1]);
+      else
+        v = ni[j] - d.dt_2dz * (G[j + 1] - G[j - 1]);
+      ni[j] = v;
+      gam[j] = G[j];
+    }
+    if (tid == 0) {
+      w0 = w0 + Zd * G[0];
+      w1 = w1 + Zd * G[nc];
+      if (d.Z[q] > 0) {
+        f0 = f0 + dmax0(-G[0]);
+        f1 = f1 + dmax0(G[nc]);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    d.st->wall[0] = w0;
+    d.st->wall[1] = w1;
+    d.st->see_flux[0] = f0;
+    d.st->see_flux[1] = f1;
+  }
+}
+
 // Blocks [0, D) advance the ion fluid of discharge blockIdx.x; the others
 // share the particle chunks of all discharges in contiguous segments.
 template <class P>
@@ -691,7 +795,9 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
   if ((int)blockIdx.x < D) {
     const Disch<P>& d = ds[blockIdx.x];
     if (d.st->steps_left > 0) {
-      if (d.ion_model == HD_ION_DD_CONST_MU || d.ion_model == HD_ION_DD_FIT_MU)
+      if (d.ion_model == HD_ION_DD_SPECIES)
+        fluid_species<P>(d, reinterpret_cast<double*>(smem));
+      else if (d.ion_model == HD_ION_DD_CONST_MU || d.ion_model == HD_ION_DD_FIT_MU)
         fluid_dd<P>(d, reinterpret_cast<double*>(smem));
       else
         fluid_full<P>(d, reinterpret_cast<double*>(smem));

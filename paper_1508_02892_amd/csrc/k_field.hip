@@ -6,6 +6,7 @@
 // of the coupling (Sec. II.D) for the next step.  Further workgroups of the
 // same launch append the children and secondaries to the particle arrays in
 // canonical order while the field is solved.
+#include "hd.h"
 #include "hd_device.h"
 
 namespace hd {
@@ -606,15 +607,33 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   const uint32_t pb1 = nchunk ? (seg_off + nchunk - 1u) / seg_per + 1u : 0u;  // exclusive
   Gp<uint32_t>* gseg = gptr(d.seg);
   uint32_t segv = (pb0 + (uint32_t)tid < pb1) ? gseg[pb0 + (uint32_t)tid] : 0u;
-  // this step's deposit to LDS; n_i with this step's ion sources
-  double niv[kNodeSlots];
+  // this step's deposit to LDS; n_i with this step's ion sources; with
+  // several species the others are updated here too and netv is the ion
+  // charge density sum_s Z_s n_s (species in order)
+  double niv[kNodeSlots], netv[kNodeSlots];
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
     const int j = tid + u * kFinThreads;
     niv[u] = 0.0;
+    netv[u] = 0.0;
     if (j < nn) {
       CN[j] = cur ? c1v[u] : c0v[u];
       niv[u] = field_only ? n0v[u] : n0v[u] + (double)srcv[u] * scale_of(d, j);
+      netv[u] = niv[u];
+      if (d.S > 1) {
+        double net = (double)d.Z[0] * niv[u];
+        for (int q = 1; q < d.S; ++q) {
+          const size_t k = (size_t)q * (size_t)nn + (size_t)j;
+          double nq = gni[k];
+          if (!field_only) {
+            nq = nq + (double)gsrc[k] * scale_of(d, j);
+            gptr(d.ni)[k] = nq;
+            gptr(d.ion_src)[k] = 0;
+          }
+          net = net + (double)d.Z[q] * nq;
+        }
+        netv[u] = net;
+      }
     }
   }
   if (field_only) {
@@ -639,7 +658,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     __syncthreads();  // CN complete before emission deposits into it
     // emission from the wall fluxes of this step's fluid update
     if (tid < 2) {
-      const double F = tid == 0 ? ((-wall_g < 0.0) ? 0.0 : -wall_g) : ((wall_g < 0.0) ? 0.0 : wall_g);
+      double F = tid == 0 ? ((-wall_g < 0.0) ? 0.0 : -wall_g) : ((wall_g < 0.0) ? 0.0 : wall_g);
+      if (d.ion_model == HD_ION_DD_SPECIES) F = st->see_flux[tid];  // positive ions only
       uint64_t em = 0, ab = 0, cl = 0;
       uint32_t n = 0;
       emit<P>(d, tid, F, (uint32_t)step0, CN, &n, &em, &ab, &cl);
@@ -663,7 +683,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
         wsrc[j] = 0;
         cn[j] = c;
         atomicAdd(reinterpret_cast<unsigned long long*>(&d.acc_cnt[j]), (unsigned long long)c);
-        acc_ni[j] = accv[u] + niv[u];
+        acc_ni[j] = accv[u] + netv[u];
       }
     }
     if (tid == 0) {
@@ -703,7 +723,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     rho[u] = 0.0;
     if (j < nn) {
       const double ne = (double)CN[j] * scale_of(d, j);
-      const double r = kECharge * (niv[u] - ne);
+      const double r = kECharge * (netv[u] - ne);
       rho[u] = r;
       if (j >= 1 && j <= m) {
         double dj = d.kp * r;

@@ -16,11 +16,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhd.so")
 
-HD_ABI_VERSION = 2
+HD_ABI_VERSION = 3
 HD_MAX_CHANNELS = 16
 STATUS = {0: "HD_OK", -1: "HD_EINVAL", -2: "HD_ENOMEM", -3: "HD_EDEVICE", -4: "HD_ECAPACITY",
           -5: "HD_ENUMERIC", -6: "HD_ESTATE"}
-KIND = {"elastic": 0, "excitation": 1, "ionization": 2}
+KIND = {"elastic": 0, "excitation": 1, "ionization": 2, "attachment": 3}
 
 # Every entry point declared in include/hd.h.
 SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_discharge",
@@ -39,8 +39,15 @@ class HdError(RuntimeError):
 
 
 class XsChannel(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("threshold_eV", C.c_double),
-                ("sigma_m2", C.POINTER(C.c_double))]
+    _fields_ = [("kind", C.c_int32), ("product", C.c_int32), ("threshold_eV", C.c_double),
+                ("sigma_m2", C.POINTER(C.c_double)), ("target_fraction", C.c_double),
+                ("target_mass_amu", C.c_double)]
+
+
+class IonSpecies(C.Structure):
+    _fields_ = [("charge", C.c_int32), ("n_mu", C.c_int32), ("m_amu", C.c_double),
+                ("en_lo_Td", C.c_double), ("en_hi_Td", C.c_double),
+                ("mu_m2_Vs", C.POINTER(C.c_double)), ("init_fraction", C.c_double)]
 
 
 class Params(C.Structure):
@@ -48,7 +55,7 @@ class Params(C.Structure):
         ("abi_version", C.c_int32), ("precision", C.c_int32), ("ion_model", C.c_int32),
         ("n_cells", C.c_int32), ("n_energy", C.c_int32), ("n_channels", C.c_int32),
         ("sort_every", C.c_int32), ("eedf_every", C.c_int32), ("n_eedf_bins", C.c_int32),
-        ("reserved", C.c_int32), ("n_macro", C.c_int64), ("capacity", C.c_int64),
+        ("n_species", C.c_int32), ("n_macro", C.c_int64), ("capacity", C.c_int64),
         ("seed", C.c_uint64),
         ("n_gas_m3", C.c_double), ("t_gas_K", C.c_double), ("m_gas_amu", C.c_double),
         ("gap_m", C.c_double),
@@ -58,7 +65,7 @@ class Params(C.Structure):
         ("m_ion_amu", C.c_double), ("mu_const", C.c_double), ("nu_const", C.c_double),
         ("dt_s", C.c_double), ("inv_de_per_eV", C.c_double), ("eedf_emax_eV", C.c_double),
         ("power_W_m2", C.c_double), ("power_alpha", C.c_double),
-        ("channels", C.POINTER(XsChannel)),
+        ("channels", C.POINTER(XsChannel)), ("species", C.POINTER(IonSpecies)),
     ]
 
 
@@ -75,7 +82,8 @@ class MomentSet(C.Structure):
         ("n_nodes", C.c_int32), ("n_channels", C.c_int32), ("n_eedf_bins", C.c_int32),
         ("error", C.c_int32),
         ("n_e", _D), ("n_i", _D), ("phi", _D), ("E", _D), ("gamma_i", _D), ("n_e_avg", _D),
-        ("n_i_avg", _D), ("cnt", C.POINTER(C.c_int64)), ("eedf_counts", C.POINTER(C.c_uint64)),
+        ("n_i_avg", _D), ("n_species", _D), ("gamma_species", _D),
+        ("cnt", C.POINTER(C.c_int64)), ("eedf_counts", C.POINTER(C.c_uint64)),
         ("eedf", _D),
         ("coll", C.c_uint64 * HD_MAX_CHANNELS), ("absorbed", C.c_uint64 * 2),
         ("emitted", C.c_uint64 * 2), ("created", C.c_uint64), ("e_overflow", C.c_uint64),
@@ -189,17 +197,35 @@ def make_params(p: dict):
         s = np.ascontiguousarray(ch["sigma_m2"], dtype=np.float64)
         keep.append(s)
         arr[k].kind = KIND[ch["kind"]] if isinstance(ch["kind"], str) else int(ch["kind"])
+        arr[k].product = int(ch.get("product", 0))
         arr[k].threshold_eV = float(ch.get("threshold_eV", 0.0))
         arr[k].sigma_m2 = s.ctypes.data_as(_D)
+        arr[k].target_fraction = float(ch.get("target_fraction", 1.0))
+        arr[k].target_mass_amu = float(ch.get("target_mass_amu", 0.0))
     keep.append(arr)
+    species = p.get("species", [])
+    sarr = (IonSpecies * max(1, len(species)))()
+    for k, q in enumerate(species):
+        mu = np.ascontiguousarray(q["mu_m2_Vs"], dtype=np.float64)
+        keep.append(mu)
+        sarr[k].charge = int(q["charge"])
+        sarr[k].n_mu = len(mu)
+        sarr[k].m_amu = float(q["m_amu"])
+        sarr[k].en_lo_Td = float(q["en_lo_Td"])
+        sarr[k].en_hi_Td = float(q["en_hi_Td"])
+        sarr[k].mu_m2_Vs = mu.ctypes.data_as(_D)
+        sarr[k].init_fraction = float(q.get("init_fraction", 0.0))
+    keep.append(sarr)
     P = Params()
     P.abi_version = HD_ABI_VERSION
     for name, _ in Params._fields_:
-        if name in ("abi_version", "reserved", "channels", "n_channels"):
+        if name in ("abi_version", "channels", "n_channels", "species", "n_species"):
             continue
         setattr(P, name, p[name])
     P.n_channels = len(chans)
     P.channels = C.cast(arr, C.POINTER(XsChannel))
+    P.n_species = len(species)
+    P.species = C.cast(sarr, C.POINTER(IonSpecies))
     return P, keep
 
 
@@ -223,9 +249,11 @@ def required_bytes(p: dict) -> int:
 
 
 class _Moments:
-    def __init__(self, nn, nb, K):
+    def __init__(self, nn, nb, K, S=1):
         self.arrs = {k: np.zeros(nn) for k in ("n_e", "n_i", "phi", "E", "gamma_i", "n_e_avg",
                                                  "n_i_avg")}
+        self.arrs["n_species"] = np.zeros(S * nn)
+        self.arrs["gamma_species"] = np.zeros(S * nn)
         self.arrs["cnt"] = np.zeros(nn, np.int64)
         self.arrs["eedf_counts"] = np.zeros(nb + 1, np.uint64)
         self.arrs["eedf"] = np.zeros(nb)
@@ -264,7 +292,8 @@ class Discharge:
         _check(lib().hd_step(self.h, int(n)))
 
     def moments(self) -> dict:
-        M = _Moments(self.nn, self.params["n_eedf_bins"], len(self.params["channels"]))
+        M = _Moments(self.nn, self.params["n_eedf_bins"], len(self.params["channels"]),
+                     max(1, len(self.params.get("species", []))))
         _check(lib().hd_moments(self.h, C.byref(M.m)))
         return M.result()
 
@@ -321,7 +350,8 @@ class Batch:
 
     def moments(self, i: int) -> dict:
         p = self.params[i]
-        M = _Moments(p["n_cells"] + 1, p["n_eedf_bins"], len(p["channels"]))
+        M = _Moments(p["n_cells"] + 1, p["n_eedf_bins"], len(p["channels"]),
+                     max(1, len(p.get("species", []))))
         _check(lib().hd_batch_moments(self.h, int(i), C.byref(M.m)))
         return M.result()
 
@@ -375,7 +405,8 @@ class Server:
     def poll(self, job_id: int):
         """(state, times[3], moments or None); state 0 queued, 1 running, 2 done, 3 failed."""
         p = self.jobs[job_id]
-        M = _Moments(p["n_cells"] + 1, p["n_eedf_bins"], len(p["channels"]))
+        M = _Moments(p["n_cells"] + 1, p["n_eedf_bins"], len(p["channels"]),
+                     max(1, len(p.get("species", []))))
         st = C.c_int32()
         t = np.zeros(3)
         _check(lib().hd_server_poll(self.h, C.c_uint64(job_id), C.byref(st), C.byref(M.m),

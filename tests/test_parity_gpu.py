@@ -34,6 +34,13 @@ def compare(dev_m, dev_p, orc: oracle.Oracle, dev_ep=None):
     for k in ("n_i", "phi", "E"):
         np.testing.assert_array_equal(dev_m[k], g[k], err_msg=k)
     np.testing.assert_array_equal(dev_m["gamma_i"], g["gamma"], err_msg="gamma")
+    S = len(orc.params.get("species", []))
+    for q in range(S):
+        sp = orc.species(q)
+        np.testing.assert_array_equal(dev_m["n_species"][q * orc.nn:(q + 1) * orc.nn], sp["n"],
+                                      err_msg="n of species %d" % q)
+        np.testing.assert_array_equal(dev_m["gamma_species"][q * orc.nn:(q + 1) * orc.nn],
+                                      sp["gamma"], err_msg="gamma of species %d" % q)
     if dev_ep is not None:
         np.testing.assert_array_equal(dev_ep, g["Ep"], err_msg="Ep")
     c = orc.counters()
@@ -154,10 +161,45 @@ def test_power_control_matches(precision, model):
     assert pw["rf_periods"] == 5 and pw["volt_amp"] != p["v_amp_V"] and pw["p_abs"] != 0.0
 
 
+def _chem_case(precision, **kw):
+    # the complex chemistry with attachment 1,000 times stronger, so that
+    # electrons attach within a few dozen steps; hot enough to ionize He and
+    # the admixture
+    ch = W.chem_channels()
+    ch[8] = dict(ch[8], sigma_m2=ch[8]["sigma_m2"] * 1e3)
+    base = dict(precision=precision, n_cells=64, n_macro=20_000, t_e0_eV=8.0, v_amp_V=2000.0,
+                phase_rad=np.pi / 2, gamma_see=1.0, load_lo=0.0, load_hi=1.0, channels=ch)
+    base.update(kw)
+    return W.small_chem(**base)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_complex_chemistry_matches(precision):
+    # twelve channels (the generic channel path), attachment into O-,
+    # ionization into He+, He2+ and O2+, four drift-diffusion species
+    p = _chem_case(precision)
+    dev, orc = run_pair(p, 48, chunks=[1, 15, 32])
+    c = orc.counters()
+    assert c["coll"][8] > 0 and c["coll"][9] > 0 and c["coll"][10] > 0
+    assert orc.species(3)["n"].any() and orc.species(2)["n"].any()
+
+
+def test_c2_full_size_first_steps_match():
+    # the complex-chemistry workload at full size: 4,194,304 FP32 electrons,
+    # 1,024 cells, 17 steps including one compaction + sort
+    p = W.c2()
+    dev = hd.Discharge(p)
+    orc = oracle.Oracle(p)
+    compare(dev.moments(), dev.particles(), orc, dev.push_field())
+    dev.step(17)
+    orc.step(17)
+    compare(dev.moments(), dev.particles(), orc, dev.push_field())
+
+
 def test_mixed_ion_models_in_one_batch():
     # one launch advances constant and fitted, drift-diffusion and full fluids
     ps = [_fit_case(0, m)[0] for m in (W.ION_DD_FIT, W.ION_FULL_FIT)]
-    ps = [_hot(0, W.ION_DD, seed=40), _hot(0, W.ION_FULL, seed=41)] + ps
+    ps = [_hot(0, W.ION_DD, seed=40), _hot(0, W.ION_FULL, seed=41)] + ps + [_chem_case(0, seed=44)]
     b = hd.Batch(ps)
     b.step(7)
     b.step(16)
