@@ -120,6 +120,7 @@ def lib():
             L.orc_solve_tridiag.argtypes = [C.c_int] + [vp] * 5
             L.orc_solve_tridiag_fma.argtypes = [C.c_int] + [vp] * 5
             L.orc_n_partitions.argtypes = [C.c_int]
+            L.orc_field_partitions.argtypes = [C.c_int]
             for f in ("orc_fit_ln", "orc_fit_exp", "orc_mobility_fit", "orc_nu_fit"):
                 getattr(L, f).restype = C.c_double
                 getattr(L, f).argtypes = [C.c_double]
@@ -444,6 +445,11 @@ def solve_tridiag_fma(a, b, c, d):
 
 def n_partitions(n):
     return lib().orc_n_partitions(int(n))
+
+
+def field_partitions(n):
+    """Partitions of one level of the field's solver (0: Thomas)."""
+    return lib().orc_field_partitions(int(n))
 
 
 def fit_ln(x):

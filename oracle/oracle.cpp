@@ -690,9 +690,15 @@ void thomas_fma(int n, const double* a, const double* b, const double* c, const 
   for (int j = n - 2; j >= 0; --j) x[j] = std::fma(-cp[j], x[j + 1], dp[j]);
 }
 
+// Partitions of the field's solver at one level: P = min(64, n/8) (at least
+// 8 rows each); below 16 rows the Thomas method.  The reduced system of the
+// partitions' first and last rows (2P rows) is solved the same way, so the
+// longest chain of dependent rows is a few dozen instead of hundreds.
+int field_partitions(int n) { return n < 16 ? 0 : std::min(64, n / 8); }
+
 void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
                        const double* d, double* x) {
-  const int P = n_partitions(n);
+  const int P = field_partitions(n);
   if (P == 0) {
     thomas_fma(n, a, b, c, d, x);
     return;
@@ -729,7 +735,7 @@ void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
     rc[2 * p + 1] = c[e];
     rd[2 * p + 1] = std::fma(-a[e], dp[e - 1], d[e]);
   }
-  thomas_fma(2 * P, ra.data(), rb.data(), rc.data(), rd.data(), rx.data());
+  solve_tridiag_fma(2 * P, ra.data(), rb.data(), rc.data(), rd.data(), rx.data());
   for (int p = 0; p < P; ++p) {
     const int s = (int)((int64_t)p * n / P);
     const int e = (int)((int64_t)(p + 1) * n / P) - 1;
@@ -1819,6 +1825,8 @@ void orc_normal_pairs(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step, i
   Stream st(seed, tag, id, step);
   for (int k = 0; k < n; ++k) normal_pair(st, out[2 * k], out[2 * k + 1]);
 }
+
+int orc_field_partitions(int n) { return field_partitions(n); }
 
 double orc_fit_ln(double x) { return fit_ln(x); }
 double orc_fit_exp(double y) { return fit_exp(y); }

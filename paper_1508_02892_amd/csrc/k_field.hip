@@ -120,49 +120,144 @@ __device__ __forceinline__ double scale_of(const Disch<P>& d, int j) {
 }
 
 // ---- Poisson solve with precomputed elimination factors --------------------
-// The interior rows of Poisson's equation are the constant (-1, 2, -1), so in
-// the partitioned elimination every pivot reciprocal and every eliminated
-// coefficient depends only on a row's position inside its partition and on
-// the partition's length (n / P rounded down or up).  They are computed once,
-// by the same operations in the same order as the general elimination, and
-// each step runs only the right-hand-side recurrences, which gives the same
-// result bit for bit without a division on the serial path.
+// The partitioned elimination: level 0 splits the n interior rows into P
+// partitions (P = min(64, n/8), Thomas below 16 rows), eliminates each
+// partition's interior rows forward and backward, and leaves a reduced
+// system of the partitions' first and last rows (2P rows), which is solved
+// the same way (level 1, 2, ...) down to a Thomas solve; the solutions then
+// flow back up.  Level 0's matrix is the constant (-1, 2, -1), so its pivot
+// reciprocals and eliminated coefficients depend only on a row's place in
+// its partition and on the partition's length (n / P rounded down or up);
+// the reduced systems are general but also constant in time.  All factors
+// are computed once, by the same operations in the same order as the
+// general elimination, and each step runs only the right-hand-side
+// recurrences (same results bit for bit, no division on the serial path).
 constexpr double kPa = -1.0, kPb = 2.0, kPc = -1.0;
-constexpr int kFacMax = 1280;  // doubles; at most 18 P + 42 for P >= 1, 2 n for n < 8
+constexpr int kFacMax = 2048;   // doubles of factor tables (n <= 4095 needs at most 1528)
+constexpr int kPoisLevels = 3;  // reduced levels below level 0 (enough for n <= 4095)
+constexpr int kPoisRed = 6 * kTriRed;  // doubles of LDS: reduced levels' values (factor scratch at set-up)
 
-// Offsets (in doubles) of the factor tables for n unknowns.
+__host__ __device__ inline int field_partitions(int n) { return n < 16 ? 0 : (n / 8 < 64 ? n / 8 : 64); }
+
+// Offsets (in doubles) of the factor tables for n unknowns.  Level 0:
+// forward reciprocal pivot and eliminated c at local row k (fr, fc), final
+// A and C for both partition lengths (xa, xc).  Reduced level k (rows ln[k],
+// partitions lp[k], 0 = Thomas) at lt[k]: per row R (reciprocal pivot), M
+// (-(a r)), F (forward eliminated c), XA, XC (final A, C), NA (-a), NC (-c)
+// for a partitioned level (7 columns), R, M, CP for a Thomas level (3).
 struct PoisFac {
   int n, P, L0, Lmax, size;
-  int fr, fc, xa, xc, ra, rr, rc;
+  int fr, fc, xa, xc;
+  int nl;  // reduced levels (the last is a Thomas level)
+  int ln[kPoisLevels], lp[kPoisLevels], lt[kPoisLevels];
 };
 
 __device__ inline PoisFac pois_fac(int n) {
   PoisFac f;
   f.n = n;
-  f.P = tri_partitions(n);
+  f.P = field_partitions(n);
+  f.nl = 0;
   if (f.P == 0) {  // plain Thomas: reciprocal pivots and eliminated c per row
     f.L0 = f.Lmax = 0;
     f.fr = 0;
     f.fc = n;
-    f.xa = f.xc = f.ra = f.rr = f.rc = 2 * n;
+    f.xa = f.xc = 2 * n;
     f.size = 2 * n;
     return f;
   }
   f.L0 = n / f.P;
   f.Lmax = f.L0 + 1;
-  f.fr = 0;                   // forward reciprocal pivot at local row k
-  f.fc = f.Lmax;              // forward eliminated c at k
-  f.xa = 2 * f.Lmax;          // final A at k, lengths L0 and L0 + 1
-  f.xc = 4 * f.Lmax;          // final C at k, lengths L0 and L0 + 1
-  f.ra = 6 * f.Lmax;          // reduced system: -(sub-diagonal x reciprocal pivot),
-  f.rr = f.ra + 2 * f.P;      //   reciprocal pivots,
-  f.rc = f.rr + 2 * f.P;      //   eliminated super-diagonal
-  f.size = f.rc + 2 * f.P;
+  f.fr = 0;
+  f.fc = f.Lmax;
+  f.xa = 2 * f.Lmax;
+  f.xc = 4 * f.Lmax;
+  int off = 6 * f.Lmax, rows = 2 * f.P;
+  bool done = false;
+#pragma unroll
+  for (int k = 0; k < kPoisLevels; ++k) {  // constant indices: the arrays stay in registers
+    f.ln[k] = f.lp[k] = f.lt[k] = 0;
+    if (!done) {
+      const int q = field_partitions(rows);
+      f.ln[k] = rows;
+      f.lp[k] = q;
+      f.lt[k] = off;
+      off += (q ? 7 : 3) * rows;
+      f.nl = k + 1;
+      if (q == 0)
+        done = true;
+      else
+        rows = 2 * q;
+    }
+  }
+  f.size = off;
   return f;
 }
 
-// One thread: the factors of the (-1, 2, -1) system into t.
-__device__ void pois_factor(const PoisFac& f, double* t) {
+// Factors of a general tridiagonal level (rows n, partitions P; P = 0:
+// Thomas) with matrix a, b, c (LDS scratch), written at t + off; for a
+// partitioned level the next level's matrix goes to na, nb, nc.
+__device__ void level_factor(int n, int P, const double* a, const double* b, const double* c,
+                             double* t, double* na, double* nb, double* nc) {
+  double* R = t;
+  double* M = t + n;
+  if (P == 0) {
+    double* CP = t + 2 * n;
+    double cp = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double den = b[j];
+      if (j > 0) den = b[j] - a[j] * cp;
+      const double r = 1.0 / den;
+      cp = c[j] * r;
+      R[j] = r;
+      M[j] = -(a[j] * r);
+      CP[j] = cp;
+    }
+    return;
+  }
+  double* F = t + 2 * n;
+  double* XA = t + 3 * n;
+  double* XC = t + 4 * n;
+  double* NA = t + 5 * n;
+  double* NC = t + 6 * n;
+  for (int j = 0; j < n; ++j) {
+    NA[j] = -a[j];
+    NC[j] = -c[j];
+  }
+  for (int p = 0; p < P; ++p) {
+    const int s = (int)((int64_t)p * n / P);
+    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
+    {
+      const int i = s + 1;
+      const double r = 1.0 / b[i];
+      R[i] = r;
+      XA[i] = a[i] * r;
+      XC[i] = c[i] * r;
+      F[i] = XC[i];
+    }
+    for (int i = s + 2; i <= e - 1; ++i) {
+      const double r = 1.0 / (b[i] - a[i] * XC[i - 1]);
+      XA[i] = -(a[i] * XA[i - 1]) * r;
+      XC[i] = c[i] * r;
+      F[i] = XC[i];
+      R[i] = r;
+      M[i] = -(a[i] * r);
+    }
+    for (int i = e - 2; i >= s + 1; --i) {
+      XA[i] = XA[i] - XC[i] * XA[i + 1];
+      XC[i] = -(XC[i] * XC[i + 1]);
+    }
+    na[2 * p] = a[s];
+    nb[2 * p] = b[s] - c[s] * XA[s + 1];
+    nc[2 * p] = -(c[s] * XC[s + 1]);
+    na[2 * p + 1] = -(a[e] * XA[e - 1]);
+    nb[2 * p + 1] = b[e] - a[e] * XC[e - 1];
+    nc[2 * p + 1] = c[e];
+  }
+}
+
+// One thread: all factors for n unknowns into t; scr: 6 * kTriRed doubles
+// of LDS for the reduced matrices.
+__device__ void pois_factor(const PoisFac& f, double* t, double* scr) {
   const double a = kPa, b = kPb, c = kPc;
   if (f.P == 0) {
     double rr = 1.0 / b;
@@ -179,8 +274,8 @@ __device__ void pois_factor(const PoisFac& f, double* t) {
     return;
   }
   const int Lm = f.Lmax;
-  // forward elimination of the interior rows k = 1 .. Lmax - 2 (identical
-  // in every partition); forward A and C go to both length classes
+  // level 0: forward elimination of the interior rows k = 1 .. Lmax - 2
+  // (identical in every partition); forward A and C to both length classes
   double r = 1.0 / b, ap = a * r, cp = c * r;
   for (int k = 1; k <= Lm - 2; ++k) {
     if (k > 1) {
@@ -209,51 +304,163 @@ __device__ void pois_factor(const PoisFac& f, double* t) {
       xc[k] = bcp;
     }
   }
-  // the reduced system of first and last rows, and its Thomas factors
-  double rcp = 0.0;
+  // level 1's matrix: the first and last rows of every partition
+  double* ma = scr;
+  double* mb = scr + kTriRed;
+  double* mc = scr + 2 * kTriRed;
   for (int j = 0; j < 2 * f.P; ++j) {
     const int p = j >> 1;
-    const int s = p * f.n / f.P;
-    const int e = (p + 1) * f.n / f.P - 1;
+    const int s = (int)((int64_t)p * f.n / f.P);
+    const int e = (int)((int64_t)(p + 1) * f.n / f.P) - 1;
     const int L = e - s + 1;
     const double* xa = t + f.xa + (L - f.L0) * Lm;
     const double* xc = t + f.xc + (L - f.L0) * Lm;
-    double ra, rb, rc;
     if ((j & 1) == 0) {
-      ra = a;
-      rb = b - c * xa[1];
-      rc = -(c * xc[1]);
+      ma[j] = a;
+      mb[j] = b - c * xa[1];
+      mc[j] = -(c * xc[1]);
     } else {
-      ra = -(a * xa[L - 2]);
-      rb = b - a * xc[L - 2];
-      rc = c;
+      ma[j] = -(a * xa[L - 2]);
+      mb[j] = b - a * xc[L - 2];
+      mc[j] = c;
     }
-    double rr;
-    if (j == 0) {
-      rr = 1.0 / rb;
-    } else {
-      const double den = rb - ra * rcp;
-      rr = 1.0 / den;
+  }
+  // the reduced levels, each building the next level's matrix
+#pragma unroll
+  for (int k = 0; k < kPoisLevels; ++k) {
+    if (k < f.nl) {
+      double* na = scr + 3 * kTriRed;
+      double* nb = scr + 4 * kTriRed;
+      double* nc = scr + 5 * kTriRed;
+      level_factor(f.ln[k], f.lp[k], ma, mb, mc, t + f.lt[k], na, nb, nc);
+      for (int j = 0; j < 2 * f.lp[k]; ++j) {
+        ma[j] = na[j];
+        mb[j] = nb[j];
+        mc[j] = nc[j];
+      }
     }
-    rcp = rc * rr;
-    t[f.ra + j] = -(ra * rr);  // multiplier of the previous row in the reduced sweep
-    t[f.rr + j] = rr;
-    t[f.rc + j] = rcp;
   }
 }
 
-// Solve of the (-1, 2, -1) system for the right-hand side d (LDS, n rows),
-// overwritten by the solution; t: factor tables (LDS); red: 2 * kTriRed
-// doubles of LDS.  Called by every thread of the workgroup.  The right-hand
-// side is carried by fused multiply-adds, one rounding per row of a sweep:
-// forward d'_i = fma(-(a r_i), d'_{i-1}, d_i r_i), backward
-// d'_i = fma(-c'_i, d'_{i+1}, d'_i), the reduced system likewise.
+// Forward right-hand-side recurrence dp_i = fma(M_i, dp_{i-1}, D_i R_i) over
+// rows i0 .. i1 (D in place), in batches of 8 rows whose loads are issued
+// together (LDS latency off the dependent chain).
+__device__ __forceinline__ double fwd_rows(double dp, int i0, int i1, const double* R,
+                                           const double* M, double* D) {
+  constexpr int kB = 8;
+  int i = i0;
+  for (; i + kB - 1 <= i1; i += kB) {
+    double dv[kB], mv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dv[u] = D[i + u] * R[i + u];
+      mv[u] = M[i + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dp = fma(mv[u], dp, dv[u]);
+      dv[u] = dp;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) D[i + u] = dv[u];
+  }
+  for (; i <= i1; ++i) {
+    dp = fma(M[i], dp, D[i] * R[i]);
+    D[i] = dp;
+  }
+  return dp;
+}
+
+// Backward recurrence dp_i = fma(-F_i, dp_{i+1}, D_i) over rows i1 down to i0.
+__device__ __forceinline__ double bwd_rows(double dp, int i1, int i0, const double* F,
+                                           double* D) {
+  constexpr int kB = 8;
+  int i = i1;
+  for (; i - kB + 1 >= i0; i -= kB) {
+    double dv[kB], cv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dv[u] = D[i - u];
+      cv[u] = -F[i - u];
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dp = fma(cv[u], dp, dv[u]);
+      dv[u] = dp;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) D[i - u] = dv[u];
+  }
+  for (; i >= i0; --i) {
+    dp = fma(-F[i], dp, D[i]);
+    D[i] = dp;
+  }
+  return dp;
+}
+
+// Right-hand-side sweeps of one partitioned reduced level on lanes p < P of
+// the calling wave: D (n values) is swept in place, the next level's
+// right-hand side goes to Dn.  (n <= 128: products p n fit in 32 bits.)
+__device__ __forceinline__ void level_sweep(int n, int P, const double* t, double* D,
+                                            double* Dn, int lane) {
+  if (lane >= P) return;
+  const double* R = t;
+  const double* M = t + n;
+  const double* F = t + 2 * n;
+  const double* NA = t + 5 * n;
+  const double* NC = t + 6 * n;
+  const int s = lane * n / P;
+  const int e = (lane + 1) * n / P - 1;
+  double dp = D[s + 1] * R[s + 1];
+  D[s + 1] = dp;
+  dp = fwd_rows(dp, s + 2, e - 1, R, M, D);
+  bwd_rows(dp, e - 2, s + 1, F, D);
+  Dn[2 * lane] = fma(NC[s], D[s + 1], D[s]);
+  Dn[2 * lane + 1] = fma(NA[e], D[e - 1], D[e]);
+}
+
+// The solution of a partitioned reduced level from its partitions' first
+// and last unknowns X (2P values): written to Xo (n values) by the wave.
+__device__ __forceinline__ void level_recover(int n, int P, const double* t, const double* D,
+                                              const double* X, double* Xo, int lane) {
+  const double* XA = t + 3 * n;
+  const double* XC = t + 4 * n;
+  for (int i = lane; i < n; i += 64) {
+    const int p = ((i + 1) * P - 1) / n;
+    const int s = p * n / P;
+    const int e = (p + 1) * n / P - 1;
+    const double xs = X[2 * p], xe = X[2 * p + 1];
+    double xi;
+    if (i == s)
+      xi = xs;
+    else if (i == e)
+      xi = xe;
+    else
+      xi = fma(-XC[i], xe, fma(-XA[i], xs, D[i]));
+    Xo[i] = xi;
+  }
+}
+
+// Orders the calling wave's LDS writes before its later reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Solve of the (-1, 2, -1) system for the right-hand side d (LDS, row i at
+// pois_slot(i), worked in place), the solution to out (n rows); t: factor
+// tables (LDS); red: kPoisRed doubles of LDS.  Called by every thread of the workgroup; levels below 0 run on
+// wave 0 alone.  The right-hand side is carried by fused multiply-adds, one
+// rounding per row of a sweep: forward d'_i = fma(-(a r_i), d'_{i-1},
+// d_i r_i), backward d'_i = fma(-c'_i, d'_{i+1}, d'_i).
 //
-// The serial sweeps read and write rows in full batches of kB (no per-row
+// Level 0's sweeps read and write rows in full batches of kB (no per-row
 // predication, LDS latency and the products d_i r_i off the dependent
-// chain).  The serial parts run on all of wave 0 with an offset zo that is 0
-// but not known to be, so the running values stay in vector registers.
-__device__ void pois_solve(const PoisFac& f, const double* t, double* d, double* red) {
+// chain).  Serial Thomas work runs on all of wave 0 with an offset zo that
+// is 0 but not known to be, so the running values stay in vector registers.
+__device__ void pois_solve(const PoisFac& f, const double* t, double* d, double* red,
+                           double* out) {
   constexpr int kB = 8;
   const int tid = threadIdx.x, nt = blockDim.x, n = f.n, P = f.P;
   const int zo = (int)(threadIdx.x / blockDim.x);
@@ -277,115 +484,116 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
       }
     }
     __syncthreads();
+    for (int i = tid; i < n; i += nt) out[i] = d[i];
+    __syncthreads();
     return;
   }
-  double* rd = red;
-  double* rx = red + kTriRed;
-  if (tid < P) {
-    const int p = tid;
-    const int s = p * n / P;
-    const int e = (p + 1) * n / P - 1;
-    const double* fr = t + f.fr - s;  // fr[i] = factor of local row i - s
-    const double* fc = t + f.fc - s;
-    int i = s + 1;
-    double dp = d[i] * fr[i];
-    d[i] = dp;
-    for (i = s + 2; i + kB <= e; i += kB) {  // rows i .. i + kB - 1 <= e - 1
-      double dv[kB], mv[kB];
+  // reduced levels' right-hand sides and solutions: level k's D at Dk[k],
+  // its solution at Xk[k] (constant indices only: registers, not scratch)
+  double* Dk[kPoisLevels];
+  double* Xk[kPoisLevels];
+  {
+    int o = 0;
 #pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        const double r = fr[i + u];
-        dv[u] = d[i + u] * r;
-        mv[u] = -(a * r);
-      }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        dp = fma(mv[u], dp, dv[u]);
-        dv[u] = dp;
-      }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) d[i + u] = dv[u];
+    for (int k = 0; k < kPoisLevels; ++k) {
+      Dk[k] = red + o;
+      o += f.ln[k];
+      Xk[k] = red + o;
+      o += f.ln[k];
     }
-    for (; i <= e - 1; ++i) {
-      const double r = fr[i];
-      dp = fma(-(a * r), dp, d[i] * r);
-      d[i] = dp;
-    }
-    for (i = e - 2; i - kB >= s; i -= kB) {  // rows i .. i - kB + 1 >= s + 1
-      double dv[kB], cv[kB];
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        dv[u] = d[i - u];
-        cv[u] = -fc[i - u];
-      }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        dp = fma(cv[u], dp, dv[u]);
-        dv[u] = dp;
-      }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) d[i - u] = dv[u];
-    }
-    for (; i >= s + 1; --i) {
-      dp = fma(-fc[i], dp, d[i]);
-      d[i] = dp;
-    }
-    rd[2 * p] = fma(-c, d[s + 1], d[s]);
-    rd[2 * p + 1] = fma(-a, d[e - 1], d[e]);
   }
-  __syncthreads();
   if (tid < 64) {
-    const int n2 = 2 * P;
-    const double* rm = t + f.ra + zo;
-    const double* rr = t + f.rr + zo;
-    const double* rc = t + f.rc + zo;
-    const double* rdz = rd + zo;
-    double* rxz = rx + zo;
-    double dp = rdz[0] * rr[0];
-    rxz[0] = dp;
-    int j = 1;
-    for (; j + kB <= n2; j += kB) {
-      double dv[kB], mv[kB];
+    const int lane = tid;
+    if (lane < P) {  // level 0: one partition per lane
+      const int p = lane;
+      const int s = p * n / P;
+      const int e = (p + 1) * n / P - 1;
+      const double* fr = t + f.fr - s;  // fr[i] = factor of local row i - s
+      const double* fc = t + f.fc - s;
+      double* dd = d + p;  // partition p's rows sit p doubles higher (spreads the lanes over LDS banks)
+      int i = s + 1;
+      double dp = dd[i] * fr[i];
+      dd[i] = dp;
+      for (i = s + 2; i + kB <= e; i += kB) {  // rows i .. i + kB - 1 <= e - 1
+        double dv[kB], mv[kB];
 #pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        dv[u] = rdz[j + u] * rr[j + u];
-        mv[u] = rm[j + u];
+        for (int u = 0; u < kB; ++u) {
+          const double r = fr[i + u];
+          dv[u] = dd[i + u] * r;
+          mv[u] = -(a * r);
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          dp = fma(mv[u], dp, dv[u]);
+          dv[u] = dp;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) dd[i + u] = dv[u];
       }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        dp = fma(mv[u], dp, dv[u]);
-        dv[u] = dp;
+      for (; i <= e - 1; ++i) {
+        const double r = fr[i];
+        dp = fma(-(a * r), dp, dd[i] * r);
+        dd[i] = dp;
       }
+      for (i = e - 2; i - kB >= s; i -= kB) {  // rows i .. i - kB + 1 >= s + 1
+        double dv[kB], cv[kB];
 #pragma unroll
-      for (int u = 0; u < kB; ++u) rxz[j + u] = dv[u];
+        for (int u = 0; u < kB; ++u) {
+          dv[u] = dd[i - u];
+          cv[u] = -fc[i - u];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          dp = fma(cv[u], dp, dv[u]);
+          dv[u] = dp;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) dd[i - u] = dv[u];
+      }
+      for (; i >= s + 1; --i) {
+        dp = fma(-fc[i], dp, dd[i]);
+        dd[i] = dp;
+      }
+      Dk[0][2 * p] = fma(-c, dd[s + 1], dd[s]);
+      Dk[0][2 * p + 1] = fma(-a, dd[e - 1], dd[e]);
     }
-    for (; j < n2; ++j) {
-      dp = fma(rm[j], dp, rdz[j] * rr[j]);
-      rxz[j] = dp;
-    }
-    double x = dp;
-    j = n2 - 2;
-    for (; j - kB >= -1; j -= kB) {  // rows j .. j - kB + 1 >= 0
-      double dv[kB], cv[kB];
+    wave_sync();
+    // down the partitioned reduced levels to the Thomas level (the last)
 #pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        dv[u] = rxz[j - u];
-        cv[u] = -rc[j - u];
+    for (int k = 0; k + 1 < kPoisLevels; ++k) {
+      if (k < f.nl - 1) {
+        level_sweep(f.ln[k], f.lp[k], t + f.lt[k], Dk[k], Dk[k + 1], lane);
+        wave_sync();
       }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        x = fma(cv[u], x, dv[u]);
-        dv[u] = x;
-      }
-#pragma unroll
-      for (int u = 0; u < kB; ++u) rxz[j - u] = dv[u];
     }
-    for (; j >= 0; --j) {
-      x = fma(-rc[j], x, rxz[j]);
-      rxz[j] = x;
+#pragma unroll
+    for (int k = 0; k < kPoisLevels; ++k) {
+      if (k == f.nl - 1) {  // Thomas level, on every lane (the same values)
+        const int m2 = f.ln[k];
+        const double* R = t + f.lt[k] + zo;
+        const double* M = R + m2;
+        const double* CP = R + 2 * m2;
+        double* X = Xk[k] + zo;
+        const double* D = Dk[k] + zo;
+        for (int j = 0; j < m2; ++j) X[j] = D[j];
+        double dp = X[0] * R[0];
+        X[0] = dp;
+        dp = fwd_rows(dp, 1, m2 - 1, R, M, X);
+        bwd_rows(dp, m2 - 2, 0, CP, X);
+      }
+    }
+    wave_sync();
+    // back up the partitioned reduced levels
+#pragma unroll
+    for (int k = kPoisLevels - 2; k >= 0; --k) {
+      if (k < f.nl - 1) {
+        level_recover(f.ln[k], f.lp[k], t + f.lt[k], Dk[k], Xk[k + 1], Xk[k], lane);
+        wave_sync();
+      }
     }
   }
   __syncthreads();
+  const double* rx = Xk[0];
   for (int i = tid; i < n; i += nt) {
     const int p = ((i + 1) * P - 1) / n;
     const int s = p * n / P;
@@ -398,17 +606,23 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
       xi = xe;
     } else {
       const int o = (e - s + 1 - f.L0) * f.Lmax + (i - s);
-      xi = fma(-t[f.xc + o], xe, fma(-t[f.xa + o], xs, d[i]));
+      xi = fma(-t[f.xc + o], xe, fma(-t[f.xa + o], xs, d[i + p]));
     }
-    d[i] = xi;
+    out[i] = xi;
   }
   __syncthreads();
+}
+
+// Place of interior row i in the solver's right-hand-side array: partition p
+// of level 0 sits p doubles higher.
+__device__ __forceinline__ int pois_slot(const PoisFac& f, int i) {
+  return f.P ? i + ((i + 1) * f.P - 1) / f.n : i;
 }
 
 // LDS of the finalize kernel (doubles): the solution, this step's deposit,
 // the reduced system and the factor tables.
 __host__ __device__ constexpr size_t finalize_lds_doubles(int nn_max) {
-  return 2u * (size_t)nn_max + 2u * kTriRed + kFacMax;
+  return 2u * (size_t)nn_max + 64u + (size_t)kPoisRed + kFacMax;
 }
 
 // Nodes per finalize thread (at most 4097 nodes).
@@ -529,9 +743,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   Gp<State>* st = gptr(d.st);
   const int tid = threadIdx.x, nn = d.nn, nc = d.nc, m = nc - 1;
   double* X = reinterpret_cast<double*>(smem);         // interior rows j - 1
-  int64_t* CN = reinterpret_cast<int64_t*>(X + nn);     // deposit of the step
+  int64_t* CN = reinterpret_cast<int64_t*>(X + nn + 64);  // deposit of the step
+  double* S = reinterpret_cast<double*>(CN);            // then the solution (rows j - 1)
   double* red = reinterpret_cast<double*>(CN + nn);
-  double* T = red + 2 * kTriRed;
+  double* T = red + kPoisRed;
   __shared__ uint32_t sh[kWaves + 1];
   __shared__ uint32_t sh_see[2];
   // Global inputs are requested before any of them is used: the state, both
@@ -592,13 +807,18 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   const double V = amp * ((step1 < d.volt_len) ? volt[step1] : 0.0);
   // absorbed-power bookkeeping inputs (thread 0): the field and voltage of
   // the level this step started from and the electron counts at z = 0
-  double e0_old = 0.0, v_old = 0.0;
-  uint64_t abs0 = 0, emi0 = 0;
+  double e0_old = 0.0, v_old = 0.0, pw_sum = 0.0;
+  uint64_t abs0 = 0, emi0 = 0, abs_prev = 0, emi_prev = 0;
+  int64_t periods = 0;
   if (!field_only && tid == 0) {
     e0_old = gptr(d.E)[0];
     v_old = gptr(d.phi)[0];
     abs0 = st->absorbed[0];
     emi0 = st->emitted[0];
+    abs_prev = st->pw_abs0;
+    emi_prev = st->pw_emi0;
+    pw_sum = st->pw_sum;
+    periods = st->rf_periods;
   }
   // the electron launch's per-workgroup child totals of this discharge
   const uint32_t nchunk = field_only ? 0u : (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile;
@@ -637,7 +857,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     }
   }
   if (field_only) {
-    if (tid == 0) pois_factor(f, T);
+    if (tid == 0) pois_factor(f, T, red);
   } else {
 #pragma unroll
     for (int u = 0; u < kTabSlots; ++u) {
@@ -729,16 +949,16 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
         double dj = d.kp * r;
         if (j == 1) dj = dj + V;
         if (j == m) dj = dj + 0.0;
-        X[j - 1] = dj;
+        X[pois_slot(f, j - 1)] = dj;
       }
     }
   }
-  pois_solve(f, T, X, red);
+  pois_solve(f, T, X, red, S);
   if (field_only)
     for (int i = tid; i < f.size; i += kFinThreads) gtab[i] = T[i];
   // E from centred differences inside and Gauss's law over the wall half
   // cells; E' = (-e/m_e) dt E rounded to the particle precision
-  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : X[j - 1]); };
+  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : S[j - 1]); };
   Gp<double>* gphi = gptr(d.phi);
   Gp<double>* gE = gptr(d.E);
   Gp<P>* gEp = gptr(d.Ep);
@@ -769,17 +989,17 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     // plus the displacement current eps0 dE/dt, times the mean voltage.
     // The interval belongs to the period that contains t_n+1; when that
     // level ends a period, the period's mean sets the next amplitude.
-    const double dn = (double)(emi0 - st->pw_emi0) - (double)(abs0 - st->pw_abs0);
+    const double dn = (double)(emi0 - emi_prev) - (double)(abs0 - abs_prev);
     const double ge = (d.w * dn) / d.dt;
     const double jc = kECharge * (wall_g - ge);
     const double jd = kEps0 * ((e0_new - e0_old) / d.dt);
-    double sum = st->pw_sum + (0.5 * (v_old + V)) * (jc + jd);
+    double sum = pw_sum + (0.5 * (v_old + V)) * (jc + jd);
     st->pw_abs0 = abs0;
     st->pw_emi0 = emi0;
     if (d.rf_steps > 0 && step1 % d.rf_steps == 0) {
       const double pa = sum / (double)d.rf_steps;
       st->p_abs = pa;
-      st->rf_periods = st->rf_periods + 1;
+      st->rf_periods = periods + 1;
       if (d.power_P0 > 0.0) st->volt_amp = amp * (1.0 - d.power_alpha * ((pa - d.power_P0) / d.power_P0));
       sum = 0.0;
     }

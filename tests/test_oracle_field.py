@@ -74,7 +74,21 @@ def test_fma_partitioned_solve_matches_banded_solve(n):
     np.testing.assert_allclose(x, oracle.solve_tridiag(a, b, c, d), rtol=1e-12, atol=1e-14)
 
 
-@pytest.mark.parametrize("n", [3, 8, 63, 2047])
+def test_field_solver_levels():
+    # P = min(64, n/8) partitions per level, the reduced system (2P rows)
+    # solved the same way, Thomas below 16 rows: 2047 unknowns take levels
+    # of 64, 16 and 4 partitions and an 8-row Thomas solve
+    sizes, n = [], 2047
+    while oracle.field_partitions(n):
+        P = oracle.field_partitions(n)
+        assert P == min(64, n // 8) and n >= 16
+        sizes.append(P)
+        n = 2 * P
+    assert sizes == [64, 16, 4] and n == 8
+    assert oracle.field_partitions(15) == 0 and oracle.field_partitions(16) == 2
+
+
+@pytest.mark.parametrize("n", [3, 8, 15, 16, 63, 130, 1023, 2047, 4095])
 def test_fma_solve_of_the_poisson_matrix(n):
     rng = np.random.default_rng(7 + n)
     d = rng.normal(size=n)
