@@ -15,31 +15,9 @@ namespace {
 
 constexpr double kECharge = 1.602176634e-19;
 constexpr double kEps0 = 8.8541878128e-12;
-constexpr int kWaves = kFinThreads / 64;
 
-// Block-wide exclusive scan of one value per thread; returns the prefix and
-// writes the block total to *total.  sh must hold kWaves + 1 words.
-__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wv] = x;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const uint32_t s = sh[w];
-    if (w < wv) base += s;
-    tot += s;
-  }
-  __syncthreads();
-  *total = tot;
-  return base + x - v;
-}
+// Windows of 64 x kScanWin workgroup totals scanned by one wave per pass.
+constexpr int kScanWin = 16;
 
 // Secondary electrons of one wall (side 0: z = 0, side 1: z = L) for ion
 // flux F: int(X) + Bernoulli(X - int(X)) superparticles, X = gamma F dt / w;
@@ -147,6 +125,7 @@ __host__ __device__ inline int field_partitions(int n) { return n < 16 ? 0 : (n 
 // for a partitioned level (7 columns), R, M, CP for a Thomas level (3).
 struct PoisFac {
   int n, P, L0, Lmax, size;
+  float inv_n, inv_P;  // 1 / n, 1 / P rounded to FP32 (partition of a row, its start)
   int fr, fc, xa, xc;
   int nl;  // reduced levels (the last is a Thomas level)
   int ln[kPoisLevels], lp[kPoisLevels], lt[kPoisLevels];
@@ -155,7 +134,9 @@ struct PoisFac {
 __device__ inline PoisFac pois_fac(int n) {
   PoisFac f;
   f.n = n;
+  f.inv_n = 1.0f / (float)n;
   f.P = field_partitions(n);
+  f.inv_P = f.P ? 1.0f / (float)f.P : 0.0f;
   f.nl = 0;
   if (f.P == 0) {  // plain Thomas: reciprocal pivots and eliminated c per row
     f.L0 = f.Lmax = 0;
@@ -342,19 +323,48 @@ __device__ void pois_factor(const PoisFac& f, double* t, double* scr) {
   }
 }
 
-// Forward right-hand-side recurrence dp_i = fma(M_i, dp_{i-1}, D_i R_i) over
-// rows i0 .. i1 (D in place), in batches of 8 rows whose loads are issued
-// together (LDS latency off the dependent chain).
-__device__ __forceinline__ double fwd_rows(double dp, int i0, int i1, const double* R,
-                                           const double* M, double* D) {
-  constexpr int kB = 8;
-  int i = i0;
-  for (; i + kB - 1 <= i1; i += kB) {
+// Partition of level-0 row i, floor(((i + 1) P - 1) / n), evaluated as
+// floor(((i + 1) P - 1/2) / n) in FP32: the half keeps the quotient at least
+// 1/(2n) >= 2^-13 from an integer while the two roundings move it by at most
+// P 2^-23 <= 2^-17 (n <= 4095, P <= 64), so the floor is exact.
+__device__ __forceinline__ int pois_part(const PoisFac& f, int i) {
+  return (int)(((float)((i + 1) * f.P) - 0.5f) * f.inv_n);
+}
+
+// First row of level-0 partition p, floor(p n / P), evaluated as
+// floor((p n + 1/2) / P) in FP32 (the same argument: the quotient stays at
+// least 1/(2P) >= 2^-7 from an integer).
+__device__ __forceinline__ int pois_start(const PoisFac& f, int p) {
+  return (int)(((float)(p * f.n) + 0.5f) * f.inv_P);
+}
+
+// Place of interior row i in the solver's array: partition p of level 0 sits
+// p doubles higher (the 64 lanes of a sweep, one partition each, then fall
+// in different LDS banks).  Holds the right-hand side, then the solution.
+__device__ __forceinline__ int pois_slot(const PoisFac& f, int i) {
+  return f.P ? i + pois_part(f, i) : i;
+}
+
+// Right-hand-side sweeps of one partition of a level: D[k] is row s + k (L
+// rows, lane-dependent); forward v_1 = v_1 r_1, v_k = fma(m_k, v_{k-1},
+// v_k r_k) for k = 2 .. L - 2; backward v_k = fma(f_k, v_{k+1}, v_k) for
+// k = L - 3 .. 1 (f_k = -c'_k); D swept in place.  Rows go in batches of 8
+// whose loads are issued together, so LDS latency is paid per batch, not per
+// row; the batch at a sweep's end may reach past the partition: its extra
+// rows are loaded (the arrays are padded for it) but neither computed into
+// the chain (selects) nor stored.  Returns the forward value of row L - 2.
+constexpr int kB = 8;
+template <class FR, class FM, class FF>
+__device__ __forceinline__ double part_sweep(double* D, int L, FR r, FM m, FF fneg) {
+  double dp = D[1] * r(1);
+  D[1] = dp;
+  int k = 2;
+  for (; k + kB - 1 <= L - 2; k += kB) {
     double dv[kB], mv[kB];
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
-      dv[u] = D[i + u] * R[i + u];
-      mv[u] = M[i + u];
+      dv[u] = D[k + u] * r(k + u);
+      mv[u] = m(k + u);
     }
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
@@ -362,83 +372,167 @@ __device__ __forceinline__ double fwd_rows(double dp, int i0, int i1, const doub
       dv[u] = dp;
     }
 #pragma unroll
-    for (int u = 0; u < kB; ++u) D[i + u] = dv[u];
+    for (int u = 0; u < kB; ++u) D[k + u] = dv[u];
   }
-  for (; i <= i1; ++i) {
-    dp = fma(M[i], dp, D[i] * R[i]);
-    D[i] = dp;
-  }
-  return dp;
-}
-
-// Backward recurrence dp_i = fma(-F_i, dp_{i+1}, D_i) over rows i1 down to i0.
-__device__ __forceinline__ double bwd_rows(double dp, int i1, int i0, const double* F,
-                                           double* D) {
-  constexpr int kB = 8;
-  int i = i1;
-  for (; i - kB + 1 >= i0; i -= kB) {
-    double dv[kB], cv[kB];
+  if (k <= L - 2) {  // rows k .. L - 2 (fewer than kB)
+    double dv[kB], mv[kB];
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
-      dv[u] = D[i - u];
-      cv[u] = -F[i - u];
+      dv[u] = D[k + u] * r(k + u);
+      mv[u] = m(k + u);
     }
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
+      const double nv = fma(mv[u], dp, dv[u]);
+      dp = (k + u <= L - 2) ? nv : dp;
+      dv[u] = nv;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (k + u <= L - 2) D[k + u] = dv[u];
+  }
+  const double vf = dp;
+  // backward in batches [1 + kB j, kB + kB j]; the top one holds row L - 3
+  int j = (L - 4) / kB;
+  {
+    const int b = 1 + kB * j;
+    double dv[kB], cv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dv[u] = D[b + u];
+      cv[u] = fneg(b + u);
+    }
+#pragma unroll
+    for (int u = kB - 1; u >= 0; --u) {
+      const double nv = fma(cv[u], dp, dv[u]);
+      const bool ok = b + u <= L - 3;
+      dp = ok ? nv : dp;
+      dv[u] = nv;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (b + u <= L - 3) D[b + u] = dv[u];
+  }
+  for (--j; j >= 0; --j) {
+    const int b = 1 + kB * j;
+    double dv[kB], cv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dv[u] = D[b + u];
+      cv[u] = fneg(b + u);
+    }
+#pragma unroll
+    for (int u = kB - 1; u >= 0; --u) {
       dp = fma(cv[u], dp, dv[u]);
       dv[u] = dp;
     }
 #pragma unroll
-    for (int u = 0; u < kB; ++u) D[i - u] = dv[u];
+    for (int u = 0; u < kB; ++u) D[b + u] = dv[u];
   }
-  for (; i >= i0; --i) {
-    dp = fma(-F[i], dp, D[i]);
-    D[i] = dp;
-  }
-  return dp;
+  return vf;
 }
 
-// Right-hand-side sweeps of one partitioned reduced level on lanes p < P of
-// the calling wave: D (n values) is swept in place, the next level's
-// right-hand side goes to Dn.  (n <= 128: products p n fit in 32 bits.)
-__device__ __forceinline__ void level_sweep(int n, int P, const double* t, double* D,
-                                            double* Dn, int lane) {
-  if (lane >= P) return;
+// Thomas sweeps of m rows (the same on every lane), in place: x_0 = d_0 r_0,
+// x_j = fma(m_j, x_{j-1}, d_j r_j), then x_j = fma(-cp_j, x_{j+1}, x_j);
+// batches of 8 as above.
+template <class FR, class FM, class FC>
+__device__ __forceinline__ void thomas_sweep(double* X, int m, FR r, FM mm, FC cp) {
+  double dp = X[0] * r(0);
+  X[0] = dp;
+  for (int k = 1; k <= m - 1; k += kB) {
+    double dv[kB], mv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dv[u] = X[k + u] * r(k + u);
+      mv[u] = mm(k + u);
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const double nv = fma(mv[u], dp, dv[u]);
+      dp = (k + u <= m - 1) ? nv : dp;
+      dv[u] = nv;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (k + u <= m - 1) X[k + u] = dv[u];
+  }
+  for (int b = ((m - 2) / kB) * kB; b >= 0; b -= kB) {  // batches [b, b + kB) from the top
+    double dv[kB], cv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      dv[u] = X[b + u];
+      cv[u] = -cp(b + u);
+    }
+#pragma unroll
+    for (int u = kB - 1; u >= 0; --u) {
+      const double nv = fma(cv[u], dp, dv[u]);
+      const bool ok = b + u <= m - 2;
+      dp = ok ? nv : dp;
+      dv[u] = nv;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (b + u <= m - 2) X[b + u] = dv[u];
+  }
+}
+
+// Level 0 on lane p (partition rows s .. s + L - 1 at dd[0 ..]): swept in
+// place, the reduced right-hand side to Dn.
+__device__ __forceinline__ void level0_sweep(const PoisFac& f, const double* t, double* dd, int L,
+                                             double* Dn, int p) {
+  const double a = kPa, c = kPc;
+  const double* fr = t + f.fr;
+  const double* fc = t + f.fc;
+  const double d0 = dd[0], de = dd[L - 1];
+  const double vf = part_sweep(
+      dd, L, [&](int k) { return fr[k]; }, [&](int k) { return -(a * fr[k]); },
+      [&](int k) { return -fc[k]; });
+  Dn[2 * p] = fma(-c, dd[1], d0);
+  Dn[2 * p + 1] = fma(-a, vf, de);
+}
+
+// A partitioned reduced level (n rows, P partitions, factors at t) on lane
+// p < P: D swept in place, the next level's right-hand side to Dn.
+__device__ __forceinline__ void level_sweep(int n, int P, const double* t, double* D, double* Dn,
+                                            int p) {
   const double* R = t;
   const double* M = t + n;
   const double* F = t + 2 * n;
   const double* NA = t + 5 * n;
   const double* NC = t + 6 * n;
-  const int s = lane * n / P;
-  const int e = (lane + 1) * n / P - 1;
-  double dp = D[s + 1] * R[s + 1];
-  D[s + 1] = dp;
-  dp = fwd_rows(dp, s + 2, e - 1, R, M, D);
-  bwd_rows(dp, e - 2, s + 1, F, D);
-  Dn[2 * lane] = fma(NC[s], D[s + 1], D[s]);
-  Dn[2 * lane + 1] = fma(NA[e], D[e - 1], D[e]);
+  const int s = p * n / P;
+  const int e = (p + 1) * n / P - 1;
+  const double d0 = D[s], de = D[e];
+  const double vf = part_sweep(
+      D + s, e - s + 1, [&](int k) { return R[s + k]; }, [&](int k) { return M[s + k]; },
+      [&](int k) { return -F[s + k]; });
+  Dn[2 * p] = fma(NC[s], D[s + 1], d0);
+  Dn[2 * p + 1] = fma(NA[e], vf, de);
 }
 
-// The solution of a partitioned reduced level from its partitions' first
-// and last unknowns X (2P values): written to Xo (n values) by the wave.
+// The solution of a partitioned reduced level on lane p < P from its
+// partition's end values X[2p], X[2p + 1], written to Xo.
 __device__ __forceinline__ void level_recover(int n, int P, const double* t, const double* D,
-                                              const double* X, double* Xo, int lane) {
+                                              const double* X, double* Xo, int p) {
   const double* XA = t + 3 * n;
   const double* XC = t + 4 * n;
-  for (int i = lane; i < n; i += 64) {
-    const int p = ((i + 1) * P - 1) / n;
-    const int s = p * n / P;
-    const int e = (p + 1) * n / P - 1;
-    const double xs = X[2 * p], xe = X[2 * p + 1];
-    double xi;
-    if (i == s)
-      xi = xs;
-    else if (i == e)
-      xi = xe;
-    else
-      xi = fma(-XC[i], xe, fma(-XA[i], xs, D[i]));
-    Xo[i] = xi;
+  const int s = p * n / P;
+  const int e = (p + 1) * n / P - 1;
+  const double xs = X[2 * p], xe = X[2 * p + 1];
+  for (int i = s + 1; i <= e - 1; i += kB) {
+    double w[kB], xa[kB], xc[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      w[u] = D[i + u];
+      xa[u] = XA[i + u];
+      xc[u] = XC[i + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (i + u <= e - 1) Xo[i + u] = fma(-xc[u], xe, fma(-xa[u], xs, w[u]));
   }
+  Xo[s] = xs;
+  Xo[e] = xe;
 }
 
 // Orders the calling wave's LDS writes before its later reads by other lanes.
@@ -448,156 +542,96 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Solve of the (-1, 2, -1) system for the right-hand side d (LDS, row i at
-// pois_slot(i), worked in place), the solution to out (n rows); t: factor
-// tables (LDS); red: kPoisRed doubles of LDS.  Called by every thread of the workgroup; levels below 0 run on
-// wave 0 alone.  The right-hand side is carried by fused multiply-adds, one
-// rounding per row of a sweep: forward d'_i = fma(-(a r_i), d'_{i-1},
-// d_i r_i), backward d'_i = fma(-c'_i, d'_{i+1}, d'_i).
-//
-// Level 0's sweeps read and write rows in full batches of kB (no per-row
-// predication, LDS latency and the products d_i r_i off the dependent
-// chain).  Serial Thomas work runs on all of wave 0 with an offset zo that
-// is 0 but not known to be, so the running values stay in vector registers.
-__device__ void pois_solve(const PoisFac& f, const double* t, double* d, double* red,
-                           double* out) {
-  constexpr int kB = 8;
-  const int tid = threadIdx.x, nt = blockDim.x, n = f.n, P = f.P;
+// Solve of the (-1, 2, -1) system, in two parts around a workgroup barrier:
+// pois_sweeps (wave 0) and pois_recover (every thread).  The right-hand side
+// is in d (row i at pois_slot(i)) and is replaced by the solution in the same
+// places; t: factor tables (LDS); red: kPoisRed doubles of LDS.  The sweeps
+// run one partition per lane, level by level, down to a Thomas level and
+// back up; level 0's interior unknowns are then recovered by every thread.
+// The right-hand side is carried by fused multiply-adds, one rounding per
+// row of a sweep: forward d'_i = fma(-(a r_i), d'_{i-1}, d_i r_i), backward
+// d'_i = fma(-c'_i, d'_{i+1}, d'_i).  Thomas work runs on all of wave 0 with
+// an offset zo that is 0 but not known to be, so it stays in vector
+// registers.
+struct PoisLv {
+  double* D[kPoisLevels];  // right-hand side of reduced level k
+  double* X[kPoisLevels];  // its solution
+};
+
+__device__ __forceinline__ PoisLv pois_levels(const PoisFac& f, double* red) {
+  PoisLv v;
+  int o = 0;
+#pragma unroll
+  for (int k = 0; k < kPoisLevels; ++k) {  // constant indices only: registers, not scratch
+    v.D[k] = red + o;
+    o += f.ln[k];
+    v.X[k] = red + o;
+    o += f.ln[k];
+  }
+  return v;
+}
+
+__device__ void pois_sweeps(const PoisFac& f, const double* t, double* d, double* red) {
+  const int lane = threadIdx.x, n = f.n, P = f.P;
   const int zo = (int)(threadIdx.x / blockDim.x);
-  const double a = kPa, c = kPc;
-  __syncthreads();
-  if (P == 0) {
-    if (tid < 64) {
-      const double* fr = t + f.fr + zo;
-      const double* fc = t + f.fc + zo;
-      double* dd = d + zo;
-      double dp = dd[0] * fr[0];
-      dd[0] = dp;
-      for (int j = 1; j < n; ++j) {
-        dp = fma(-(a * fr[j]), dp, dd[j] * fr[j]);
-        dd[j] = dp;
-      }
-      double x = dp;
-      for (int j = n - 2; j >= 0; --j) {
-        x = fma(-fc[j], x, dd[j]);
-        dd[j] = x;
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += nt) out[i] = d[i];
-    __syncthreads();
+  const double a = kPa;
+  if (P == 0) {  // n < 16: plain Thomas
+    thomas_sweep(
+        d + zo, n, [&](int j) { return t[f.fr + zo + j]; },
+        [&](int j) { return -(a * t[f.fr + zo + j]); }, [&](int j) { return t[f.fc + zo + j]; });
     return;
   }
-  // reduced levels' right-hand sides and solutions: level k's D at Dk[k],
-  // its solution at Xk[k] (constant indices only: registers, not scratch)
-  double* Dk[kPoisLevels];
-  double* Xk[kPoisLevels];
-  {
-    int o = 0;
+  const PoisLv lv = pois_levels(f, red);
+  if (lane < P) {  // level 0: one partition per lane
+    const int s = lane * n / P;
+    const int L = (lane + 1) * n / P - s;
+    level0_sweep(f, t, d + s + lane, L, lv.D[0], lane);
+  }
+  wave_sync();
+  // down the partitioned reduced levels to the Thomas level (the last)
 #pragma unroll
-    for (int k = 0; k < kPoisLevels; ++k) {
-      Dk[k] = red + o;
-      o += f.ln[k];
-      Xk[k] = red + o;
-      o += f.ln[k];
+  for (int k = 0; k + 1 < kPoisLevels; ++k) {
+    if (k < f.nl - 1) {
+      if (lane < f.lp[k]) level_sweep(f.ln[k], f.lp[k], t + f.lt[k], lv.D[k], lv.D[k + 1], lane);
+      wave_sync();
     }
   }
-  if (tid < 64) {
-    const int lane = tid;
-    if (lane < P) {  // level 0: one partition per lane
-      const int p = lane;
-      const int s = p * n / P;
-      const int e = (p + 1) * n / P - 1;
-      const double* fr = t + f.fr - s;  // fr[i] = factor of local row i - s
-      const double* fc = t + f.fc - s;
-      double* dd = d + p;  // partition p's rows sit p doubles higher (spreads the lanes over LDS banks)
-      int i = s + 1;
-      double dp = dd[i] * fr[i];
-      dd[i] = dp;
-      for (i = s + 2; i + kB <= e; i += kB) {  // rows i .. i + kB - 1 <= e - 1
-        double dv[kB], mv[kB];
 #pragma unroll
-        for (int u = 0; u < kB; ++u) {
-          const double r = fr[i + u];
-          dv[u] = dd[i + u] * r;
-          mv[u] = -(a * r);
-        }
-#pragma unroll
-        for (int u = 0; u < kB; ++u) {
-          dp = fma(mv[u], dp, dv[u]);
-          dv[u] = dp;
-        }
-#pragma unroll
-        for (int u = 0; u < kB; ++u) dd[i + u] = dv[u];
-      }
-      for (; i <= e - 1; ++i) {
-        const double r = fr[i];
-        dp = fma(-(a * r), dp, dd[i] * r);
-        dd[i] = dp;
-      }
-      for (i = e - 2; i - kB >= s; i -= kB) {  // rows i .. i - kB + 1 >= s + 1
-        double dv[kB], cv[kB];
-#pragma unroll
-        for (int u = 0; u < kB; ++u) {
-          dv[u] = dd[i - u];
-          cv[u] = -fc[i - u];
-        }
-#pragma unroll
-        for (int u = 0; u < kB; ++u) {
-          dp = fma(cv[u], dp, dv[u]);
-          dv[u] = dp;
-        }
-#pragma unroll
-        for (int u = 0; u < kB; ++u) dd[i - u] = dv[u];
-      }
-      for (; i >= s + 1; --i) {
-        dp = fma(-fc[i], dp, dd[i]);
-        dd[i] = dp;
-      }
-      Dk[0][2 * p] = fma(-c, dd[s + 1], dd[s]);
-      Dk[0][2 * p + 1] = fma(-a, dd[e - 1], dd[e]);
-    }
-    wave_sync();
-    // down the partitioned reduced levels to the Thomas level (the last)
-#pragma unroll
-    for (int k = 0; k + 1 < kPoisLevels; ++k) {
-      if (k < f.nl - 1) {
-        level_sweep(f.ln[k], f.lp[k], t + f.lt[k], Dk[k], Dk[k + 1], lane);
-        wave_sync();
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kPoisLevels; ++k) {
-      if (k == f.nl - 1) {  // Thomas level, on every lane (the same values)
-        const int m2 = f.ln[k];
-        const double* R = t + f.lt[k] + zo;
-        const double* M = R + m2;
-        const double* CP = R + 2 * m2;
-        double* X = Xk[k] + zo;
-        const double* D = Dk[k] + zo;
-        for (int j = 0; j < m2; ++j) X[j] = D[j];
-        double dp = X[0] * R[0];
-        X[0] = dp;
-        dp = fwd_rows(dp, 1, m2 - 1, R, M, X);
-        bwd_rows(dp, m2 - 2, 0, CP, X);
-      }
-    }
-    wave_sync();
-    // back up the partitioned reduced levels
-#pragma unroll
-    for (int k = kPoisLevels - 2; k >= 0; --k) {
-      if (k < f.nl - 1) {
-        level_recover(f.ln[k], f.lp[k], t + f.lt[k], Dk[k], Xk[k + 1], Xk[k], lane);
-        wave_sync();
-      }
+  for (int k = 0; k < kPoisLevels; ++k) {
+    if (k == f.nl - 1) {  // Thomas level, on every lane (the same values)
+      const int m2 = f.ln[k];
+      const double* R = t + f.lt[k] + zo;
+      const double* M = R + m2;
+      const double* CP = R + 2 * m2;
+      double* X = lv.X[k] + zo;
+      const double* D = lv.D[k] + zo;
+      for (int j = 0; j < m2; ++j) X[j] = D[j];
+      thomas_sweep(
+          X, m2, [&](int j) { return R[j]; }, [&](int j) { return M[j]; },
+          [&](int j) { return CP[j]; });
     }
   }
-  __syncthreads();
-  const double* rx = Xk[0];
-  for (int i = tid; i < n; i += nt) {
-    const int p = ((i + 1) * P - 1) / n;
-    const int s = p * n / P;
-    const int e = (p + 1) * n / P - 1;
+  wave_sync();
+  // back up the partitioned reduced levels
+#pragma unroll
+  for (int k = kPoisLevels - 2; k >= 0; --k) {
+    if (k < f.nl - 1) {
+      if (lane < f.lp[k])
+        level_recover(f.ln[k], f.lp[k], t + f.lt[k], lv.D[k], lv.X[k + 1], lv.X[k], lane);
+      wave_sync();
+    }
+  }
+}
+
+// Level 0's interior unknowns from their partition's end values, in place.
+__device__ void pois_recover(const PoisFac& f, const double* t, double* d, double* red) {
+  if (f.P == 0) return;
+  const int n = f.n;
+  const double* rx = pois_levels(f, red).X[0];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int p = pois_part(f, i);
+    const int s = pois_start(f, p);
+    const int e = pois_start(f, p + 1) - 1;
     const double xs = rx[2 * p], xe = rx[2 * p + 1];
     double xi;
     if (i == s) {
@@ -608,21 +642,14 @@ __device__ void pois_solve(const PoisFac& f, const double* t, double* d, double*
       const int o = (e - s + 1 - f.L0) * f.Lmax + (i - s);
       xi = fma(-t[f.xc + o], xe, fma(-t[f.xa + o], xs, d[i + p]));
     }
-    out[i] = xi;
+    d[i + p] = xi;
   }
-  __syncthreads();
 }
 
-// Place of interior row i in the solver's right-hand-side array: partition p
-// of level 0 sits p doubles higher.
-__device__ __forceinline__ int pois_slot(const PoisFac& f, int i) {
-  return f.P ? i + ((i + 1) * f.P - 1) / f.n : i;
-}
-
-// LDS of the finalize kernel (doubles): the solution, this step's deposit,
-// the reduced system and the factor tables.
+// LDS of the finalize kernel (doubles): the solution, this step's deposit
+// and its emission part, the reduced system and the factor tables.
 __host__ __device__ constexpr size_t finalize_lds_doubles(int nn_max) {
-  return 2u * (size_t)nn_max + 64u + (size_t)kPoisRed + kFacMax;
+  return 3u * (size_t)nn_max + 64u + (size_t)kPoisRed + kFacMax;
 }
 
 // Nodes per finalize thread (at most 4097 nodes).
@@ -742,13 +769,18 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   const Disch<P>& d = ds[blockIdx.x];
   Gp<State>* st = gptr(d.st);
   const int tid = threadIdx.x, nn = d.nn, nc = d.nc, m = nc - 1;
-  double* X = reinterpret_cast<double*>(smem);         // interior rows j - 1
+  // the wave index as a uniform value, so that branches on it stay branches
+  // (registers live in one wave's path are not kept through another's)
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int kLastWave = kFinThreads / 64 - 1;
+  double* X = reinterpret_cast<double*>(smem);         // interior rows (pois_slot), right-hand side then solution
   int64_t* CN = reinterpret_cast<int64_t*>(X + nn + 64);  // deposit of the step
-  double* S = reinterpret_cast<double*>(CN);            // then the solution (rows j - 1)
-  double* red = reinterpret_cast<double*>(CN + nn);
+  int64_t* EN = CN + nn;                                   // its emission part
+  double* red = reinterpret_cast<double*>(EN + nn);
   double* T = red + kPoisRed;
-  __shared__ uint32_t sh[kWaves + 1];
   __shared__ uint32_t sh_see[2];
+  __shared__ double sh_pw[4];  // power bookkeeping of the step (thread 0)
+  __shared__ int64_t sh_per;
   // Global inputs are requested before any of them is used: the state, both
   // deposit buffers (the state says which is this step's), n_i, the ion
   // sources, the run sums of n_i and the Poisson factor tables.
@@ -826,7 +858,11 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   const uint32_t pb0 = nchunk ? seg_off / seg_per : 0u;
   const uint32_t pb1 = nchunk ? (seg_off + nchunk - 1u) / seg_per + 1u : 0u;  // exclusive
   Gp<uint32_t>* gseg = gptr(d.seg);
-  uint32_t segv = (pb0 + (uint32_t)tid < pb1) ? gseg[pb0 + (uint32_t)tid] : 0u;
+  // Emission deposits into a grid of its own (EN, zeroed here), so that it
+  // can run beside the deposit's other updates; this step's final deposit
+  // is CN + EN.
+  if (!field_only)
+    for (int j = tid; j < nn; j += kFinThreads) EN[j] = 0;
   // this step's deposit to LDS; n_i with this step's ion sources; with
   // several species the others are updated here too and netv is the ion
   // charge density sum_s Z_s n_s (species in order)
@@ -854,6 +890,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
         }
         netv[u] = net;
       }
+      accv[u] = accv[u] + netv[u];  // the run sum after this step
     }
   }
   if (field_only) {
@@ -865,86 +902,68 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       if (i < f.size) T[i] = tv[u];
     }
   }
-  if (!field_only) {
-    // offsets of the staged children: exclusive scan of the workgroup totals
-    uint32_t n_kids = 0;
-    for (uint32_t t0 = pb0; t0 < pb1; t0 += (uint32_t)kFinThreads) {
-      if (t0 > pb0) segv = (t0 + (uint32_t)tid < pb1) ? gseg[t0 + (uint32_t)tid] : 0u;
-      uint32_t tot;
-      const uint32_t ex = block_scan(segv, sh, &tot);
-      if (t0 + (uint32_t)tid < pb1) gseg[t0 + (uint32_t)tid] = n_kids + ex;
-      n_kids += tot;
-    }
-    __syncthreads();  // CN complete before emission deposits into it
-    // emission from the wall fluxes of this step's fluid update
-    if (tid < 2) {
-      double F = tid == 0 ? ((-wall_g < 0.0) ? 0.0 : -wall_g) : ((wall_g < 0.0) ? 0.0 : wall_g);
-      if (d.ion_model == HD_ION_DD_SPECIES) F = st->see_flux[tid];  // positive ions only
-      uint64_t em = 0, ab = 0, cl = 0;
-      uint32_t n = 0;
-      emit<P>(d, tid, F, (uint32_t)step0, CN, &n, &em, &ab, &cl);
-      abs0 += ab;  // thread 0: totals at z = 0 after this step
+  __syncthreads();
+  // emission from the wall fluxes of this step's fluid update (wave 0)
+  if (!field_only && tid < 2) {
+    double F = tid == 0 ? ((-wall_g < 0.0) ? 0.0 : -wall_g) : ((wall_g < 0.0) ? 0.0 : wall_g);
+    if (d.ion_model == HD_ION_DD_SPECIES) F = st->see_flux[tid];  // positive ions only
+    uint64_t em = 0, ab = 0, cl = 0;
+    uint32_t n = 0;
+    emit<P>(d, tid, F, (uint32_t)step0, EN, &n, &em, &ab, &cl);
+    sh_see[tid] = n;
+    if (tid == 0) {
+      // Power delivered at the driven electrode over [t_n, t_n+1] (Eq 2.9's
+      // integrand): conduction current e (Gamma_i - Gamma_e) from the ion
+      // wall flux and the electrons that left / entered through z = 0 this
+      // step, plus the displacement current eps0 dE/dt (finished once E is
+      // known), times the mean voltage.
+      abs0 += ab;  // totals at z = 0 after this step
       emi0 += em;
-      sh_see[tid] = n;
-      if (em) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->emitted[tid]), (unsigned long long)em);
-      if (ab) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->absorbed[tid]), (unsigned long long)ab);
-      if (cl) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->see_clamped), (unsigned long long)cl);
+      const double dn = (double)(emi0 - emi_prev) - (double)(abs0 - abs_prev);
+      const double ge = (d.w * dn) / d.dt;
+      sh_pw[0] = pw_sum;
+      sh_pw[1] = 0.5 * (v_old + V);
+      sh_pw[2] = kECharge * (wall_g - ge);
+      sh_pw[3] = e0_old;
+      sh_per = periods;
+      st->pw_abs0 = abs0;
+      st->pw_emi0 = emi0;
     }
-    __syncthreads();
-    // ion sources of the step, the final deposit, run averages
+    if (em) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->emitted[tid]), (unsigned long long)em);
+    if (ab) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->absorbed[tid]), (unsigned long long)ab);
+    if (cl) atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->see_clamped), (unsigned long long)cl);
+  }
+  __syncthreads();
+  // ion sources of the step, the final deposit, run averages: written by
+  // wave 0 now, by the other waves while wave 0 sweeps
+  auto grid_out = [&]() {
     Gp<double>* wni = gptr(d.ni);
     Gp<int64_t>* wsrc = gptr(d.ion_src);
 #pragma unroll
     for (int u = 0; u < kNodeSlots; ++u) {
       const int j = tid + u * kFinThreads;
       if (j < nn) {
-        const int64_t c = CN[j];
+        const int64_t c = CN[j] + EN[j];
         wni[j] = niv[u];
         wsrc[j] = 0;
         cn[j] = c;
         atomicAdd(reinterpret_cast<unsigned long long*>(&d.acc_cnt[j]), (unsigned long long)c);
-        acc_ni[j] = accv[u] + netv[u];
+        acc_ni[j] = accv[u];
       }
     }
-    if (tid == 0) {
-      const uint32_t ns0 = sh_see[0], ns1 = sh_see[1];
-      const uint64_t n_app = (uint64_t)n_kids + ns0 + ns1;
-      st->n_chunks = nch;
-      st->n_kids = n_kids;
-      st->n_see[0] = ns0;
-      st->n_see[1] = ns1;
-      if ((uint64_t)n_main + n_app > (uint64_t)d.capacity) {
-        st->error = -4;  // capacity exceeded
-        st->append_pending = 0;
-        st->steps_left = 0;
-      } else {
-        st->append_base = n_main;
-        st->id_base = next_id;
-        st->n_main = n_main + (uint32_t)n_app;
-        st->next_id = next_id + (uint32_t)n_app;
-        st->append_pending = n_app > 0 ? 1 : 0;
-        st->steps_left = steps_left - 1;
-      }
-      st->step = step1;
-      atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->n_acc), 1ull);
-      st->sort_due = (step1 % d.sort_every) == 0 ? 1 : 0;
-      st->cbuf = cur;
-    }
-  }
-  __syncthreads();
-  // the append workgroups of this launch may start (they run beside the
-  // field solve)
-  if (!field_only && tid == 0) publish_ready(d.st);
+  };
+  if (!field_only && wave == 0) grid_out();
   // Poisson's equation with phi_0 = V(t), phi_N = 0 for the interior nodes
-  double rho[kNodeSlots];
+  double rho_0 = 0.0, rho_n = 0.0;  // charge density at the walls (nodes 0 and nc)
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
     const int j = tid + u * kFinThreads;
-    rho[u] = 0.0;
     if (j < nn) {
-      const double ne = (double)CN[j] * scale_of(d, j);
+      const int64_t c = field_only ? CN[j] : CN[j] + EN[j];
+      const double ne = (double)c * scale_of(d, j);
       const double r = kECharge * (netv[u] - ne);
-      rho[u] = r;
+      if (j == 0) rho_0 = r;
+      if (j == nc) rho_n = r;
       if (j >= 1 && j <= m) {
         double dj = d.kp * r;
         if (j == 1) dj = dj + V;
@@ -953,12 +972,74 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       }
     }
   }
-  pois_solve(f, T, X, red, S);
+  // offsets of the staged children: exclusive scan of the electron launch's
+  // per-workgroup totals, by the last wave alone while wave 0 sweeps; then
+  // the append bookkeeping
+  auto children = [&]() {
+    const uint32_t lane = (uint32_t)tid & 63u;
+    uint32_t n_kids = 0;
+    for (uint32_t t0 = pb0; t0 < pb1; t0 += 64u * kScanWin) {
+      uint32_t v[kScanWin];
+#pragma unroll
+      for (int w = 0; w < kScanWin; ++w) {
+        const uint32_t k = t0 + 64u * (uint32_t)w + lane;
+        v[w] = k < pb1 ? gseg[k] : 0u;
+      }
+#pragma unroll
+      for (int w = 0; w < kScanWin; ++w) {
+        uint32_t x = v[w];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(x, o, 64);
+          if ((int)lane >= o) x += y;
+        }
+        const uint32_t k = t0 + 64u * (uint32_t)w + lane;
+        if (k < pb1) gseg[k] = n_kids + x - v[w];
+        n_kids += (uint32_t)__shfl((int)x, 63, 64);
+      }
+    }
+    if (lane != 0) return;
+    const uint32_t ns0 = sh_see[0], ns1 = sh_see[1];
+    const uint64_t n_app = (uint64_t)n_kids + ns0 + ns1;
+    st->n_chunks = nch;
+    st->n_kids = n_kids;
+    st->n_see[0] = ns0;
+    st->n_see[1] = ns1;
+    if ((uint64_t)n_main + n_app > (uint64_t)d.capacity) {
+      st->error = -4;  // capacity exceeded
+      st->append_pending = 0;
+      st->steps_left = 0;
+    } else {
+      st->append_base = n_main;
+      st->id_base = next_id;
+      st->n_main = n_main + (uint32_t)n_app;
+      st->next_id = next_id + (uint32_t)n_app;
+      st->append_pending = n_app > 0 ? 1 : 0;
+      st->steps_left = steps_left - 1;
+    }
+    st->step = step1;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->n_acc), 1ull);
+    st->sort_due = (step1 % d.sort_every) == 0 ? 1 : 0;
+    st->cbuf = cur;
+    // the append workgroups of this launch may start (they run beside the
+    // field solve)
+    publish_ready(d.st);
+  };
+  __syncthreads();
+  if (wave == 0) {
+    pois_sweeps(f, T, X, red);
+  } else if (!field_only) {
+    grid_out();
+    if (wave == kLastWave) children();
+  }
+  __syncthreads();
+  pois_recover(f, T, X, red);
+  __syncthreads();
   if (field_only)
     for (int i = tid; i < f.size; i += kFinThreads) gtab[i] = T[i];
   // E from centred differences inside and Gauss's law over the wall half
   // cells; E' = (-e/m_e) dt E rounded to the particle precision
-  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : S[j - 1]); };
+  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : X[pois_slot(f, j - 1)]); };
   Gp<double>* gphi = gptr(d.phi);
   Gp<double>* gE = gptr(d.E);
   Gp<P>* gEp = gptr(d.Ep);
@@ -970,9 +1051,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     if (j < nn) {
       double e;
       if (j == 0)
-        e = (phi(0) - phi(1)) * d.inv_dz - rho[u] * d.hdz_eps;
+        e = (phi(0) - phi(1)) * d.inv_dz - rho_0 * d.hdz_eps;
       else if (j == nc)
-        e = (phi(nc - 1) - phi(nc)) * d.inv_dz + rho[u] * d.hdz_eps;
+        e = (phi(nc - 1) - phi(nc)) * d.inv_dz + rho_n * d.hdz_eps;
       else
         e = (phi(j - 1) - phi(j + 1)) * d.inv_2dz;
       gphi[j] = phi(j);
@@ -983,23 +1064,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     }
   }
   if (!field_only && tid == 0) {
-    // Power delivered at the driven electrode over [t_n, t_n+1] (Eq 2.9's
-    // integrand): conduction current e (Gamma_i - Gamma_e) from the ion wall
-    // flux and the electrons that left / entered through z = 0 this step,
-    // plus the displacement current eps0 dE/dt, times the mean voltage.
     // The interval belongs to the period that contains t_n+1; when that
     // level ends a period, the period's mean sets the next amplitude.
-    const double dn = (double)(emi0 - emi_prev) - (double)(abs0 - abs_prev);
-    const double ge = (d.w * dn) / d.dt;
-    const double jc = kECharge * (wall_g - ge);
-    const double jd = kEps0 * ((e0_new - e0_old) / d.dt);
-    double sum = pw_sum + (0.5 * (v_old + V)) * (jc + jd);
-    st->pw_abs0 = abs0;
-    st->pw_emi0 = emi0;
+    const double jd = kEps0 * ((e0_new - sh_pw[3]) / d.dt);
+    double sum = sh_pw[0] + sh_pw[1] * (sh_pw[2] + jd);
     if (d.rf_steps > 0 && step1 % d.rf_steps == 0) {
       const double pa = sum / (double)d.rf_steps;
       st->p_abs = pa;
-      st->rf_periods = periods + 1;
+      st->rf_periods = sh_per + 1;
       if (d.power_P0 > 0.0) st->volt_amp = amp * (1.0 - d.power_alpha * ((pa - d.power_P0) / d.power_P0));
       sum = 0.0;
     }
