@@ -121,6 +121,7 @@ def lib():
             L.orc_solve_tridiag_fma.argtypes = [C.c_int] + [vp] * 5
             L.orc_n_partitions.argtypes = [C.c_int]
             L.orc_field_partitions.argtypes = [C.c_int]
+            L.orc_pcr_fma.argtypes = [C.c_int] + [vp] * 5
             for f in ("orc_fit_ln", "orc_fit_exp", "orc_mobility_fit", "orc_nu_fit"):
                 getattr(L, f).restype = C.c_double
                 getattr(L, f).argtypes = [C.c_double]
@@ -448,8 +449,16 @@ def n_partitions(n):
 
 
 def field_partitions(n):
-    """Partitions of one level of the field's solver (0: Thomas)."""
+    """Partitions of the field's solver (0: Thomas)."""
     return lib().orc_field_partitions(int(n))
+
+
+def pcr_fma(a, b, c, d):
+    """Parallel cyclic reduction (the field's reduced-system solver)."""
+    a, b, c, d = (np.ascontiguousarray(v, np.float64) for v in (a, b, c, d))
+    x = np.empty(len(b))
+    lib().orc_pcr_fma(len(b), _p(a), _p(b), _p(c), _p(d), _p(x))
+    return x
 
 
 def fit_ln(x):

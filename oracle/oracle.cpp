@@ -690,10 +690,44 @@ void thomas_fma(int n, const double* a, const double* b, const double* c, const 
   for (int j = n - 2; j >= 0; --j) x[j] = std::fma(-cp[j], x[j + 1], dp[j]);
 }
 
-// Partitions of the field's solver at one level: P = min(64, n/8) (at least
-// 8 rows each); below 16 rows the Thomas method.  The reduced system of the
-// partitions' first and last rows (2P rows) is solved the same way, so the
-// longest chain of dependent rows is a few dozen instead of hundreds.
+// Parallel cyclic reduction (Hockney and Jesshope): at stride s = 1, 2, 4,
+// ... while s < m, every row i is combined with rows i - s and i + s, which
+// moves its couplings to i - 2s and i + 2s; once s >= m each row holds one
+// unknown, x_i = d_i (1 / b_i).  Each step uses the previous step's
+// coefficients of all rows; a missing neighbour (i - s < 0 or i + s >= m)
+// enters with multiplier 0 and value 0.  With alpha_i = -a_i / b_{i-s},
+// gamma_i = -c_i / b_{i+s}:  a'_i = alpha_i a_{i-s}, c'_i = gamma_i c_{i+s},
+// b'_i = (b_i + alpha_i c_{i-s}) + gamma_i a_{i+s} and
+// d'_i = fma(gamma_i, d_{i+s}, fma(alpha_i, d_{i-s}, d_i)).
+void pcr_fma(int m, const double* a, const double* b, const double* c, const double* d,
+             double* x) {
+  std::vector<double> A(a, a + m), B(b, b + m), C(c, c + m), Dv(d, d + m);
+  A[0] = 0.0;
+  C[m - 1] = 0.0;
+  std::vector<double> A2(m), B2(m), C2(m), D2(m);
+  for (int s = 1; s < m; s *= 2) {
+    for (int i = 0; i < m; ++i) {
+      const bool lo = i - s >= 0, hi = i + s < m;
+      const double al = lo ? -A[i] / B[i - s] : 0.0;
+      const double ga = hi ? -C[i] / B[i + s] : 0.0;
+      A2[i] = lo ? al * A[i - s] : 0.0;
+      C2[i] = hi ? ga * C[i + s] : 0.0;
+      B2[i] = (B[i] + (lo ? al * C[i - s] : 0.0)) + (hi ? ga * A[i + s] : 0.0);
+      D2[i] = std::fma(ga, hi ? Dv[i + s] : 0.0, std::fma(al, lo ? Dv[i - s] : 0.0, Dv[i]));
+    }
+    A.swap(A2);
+    B.swap(B2);
+    C.swap(C2);
+    Dv.swap(D2);
+  }
+  for (int i = 0; i < m; ++i) x[i] = Dv[i] * (1.0 / B[i]);
+}
+
+// Partitions of the field's solver: P = min(64, n/8) (at least 8 rows
+// each); below 16 rows the Thomas method.  The reduced system of the
+// partitions' first and last rows (2P rows) is solved by parallel cyclic
+// reduction, a few steps of independent row updates instead of a chain of
+// 2P dependent rows.
 int field_partitions(int n) { return n < 16 ? 0 : std::min(64, n / 8); }
 
 void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
@@ -735,7 +769,7 @@ void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
     rc[2 * p + 1] = c[e];
     rd[2 * p + 1] = std::fma(-a[e], dp[e - 1], d[e]);
   }
-  solve_tridiag_fma(2 * P, ra.data(), rb.data(), rc.data(), rd.data(), rx.data());
+  pcr_fma(2 * P, ra.data(), rb.data(), rc.data(), rd.data(), rx.data());
   for (int p = 0; p < P; ++p) {
     const int s = (int)((int64_t)p * n / P);
     const int e = (int)((int64_t)(p + 1) * n / P) - 1;
@@ -1827,6 +1861,10 @@ void orc_normal_pairs(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step, i
 }
 
 int orc_field_partitions(int n) { return field_partitions(n); }
+void orc_pcr_fma(int m, const double* a, const double* b, const double* c, const double* d,
+                 double* x) {
+  pcr_fma(m, a, b, c, d, x);
+}
 
 double orc_fit_ln(double x) { return fit_ln(x); }
 double orc_fit_exp(double y) { return fit_exp(y); }

@@ -98,37 +98,40 @@ __device__ __forceinline__ double scale_of(const Disch<P>& d, int j) {
 }
 
 // ---- Poisson solve with precomputed elimination factors --------------------
-// The partitioned elimination: level 0 splits the n interior rows into P
-// partitions (P = min(64, n/8), Thomas below 16 rows), eliminates each
-// partition's interior rows forward and backward, and leaves a reduced
-// system of the partitions' first and last rows (2P rows), which is solved
-// the same way (level 1, 2, ...) down to a Thomas solve; the solutions then
-// flow back up.  Level 0's matrix is the constant (-1, 2, -1), so its pivot
+// The n interior rows split into P partitions (P = min(64, n/8), plain
+// Thomas below 16 rows); each partition's interior rows are eliminated
+// forward and backward, which leaves a reduced system of the partitions'
+// first and last rows (2P rows).  That system is solved by parallel cyclic
+// reduction: at stride s = 1, 2, 4, ... every row is combined with rows
+// i - s and i + s (multipliers alpha_i = -a_i / b_{i-s}, gamma_i =
+// -c_i / b_{i+s}, a missing neighbour entering with 0), and after
+// ceil(log2 2P) steps x_i = d_i (1 / b_i).  The interior unknowns then
+// follow from the partitions' end values.  The matrix is the constant
+// (-1, 2, -1), so every factor is constant in time: the partitions' pivot
 // reciprocals and eliminated coefficients depend only on a row's place in
-// its partition and on the partition's length (n / P rounded down or up);
-// the reduced systems are general but also constant in time.  All factors
-// are computed once, by the same operations in the same order as the
-// general elimination, and each step runs only the right-hand-side
-// recurrences (same results bit for bit, no division on the serial path).
+// its partition and on the partition's length (n / P rounded down or up),
+// and the reduction's multipliers only on the row and the step.  They are
+// computed once, by the same operations in the same order as the general
+// method, and each step runs only the right-hand-side recurrences (same
+// results bit for bit, no division on the serial path).
 constexpr double kPa = -1.0, kPb = 2.0, kPc = -1.0;
-constexpr int kFacMax = 2048;   // doubles of factor tables (n <= 4095 needs at most 1528)
-constexpr int kPoisLevels = 3;  // reduced levels below level 0 (enough for n <= 4095)
-constexpr int kPoisRed = 6 * kTriRed;  // doubles of LDS: reduced levels' values (factor scratch at set-up)
+constexpr int kPcrSteps = 7;  // ceil(log2 128): the reduced system has at most 2 x 64 rows
+constexpr int kFacMax = 6 * 64 + (2 * kPcrSteps + 1) * kTriRed;  // doubles of factor tables
+constexpr int kPoisRed = 6 * kTriRed;  // doubles of LDS: reduced system (matrix scratch at set-up)
 
 __host__ __device__ inline int field_partitions(int n) { return n < 16 ? 0 : (n / 8 < 64 ? n / 8 : 64); }
 
-// Offsets (in doubles) of the factor tables for n unknowns.  Level 0:
-// forward reciprocal pivot and eliminated c at local row k (fr, fc), final
-// A and C for both partition lengths (xa, xc).  Reduced level k (rows ln[k],
-// partitions lp[k], 0 = Thomas) at lt[k]: per row R (reciprocal pivot), M
-// (-(a r)), F (forward eliminated c), XA, XC (final A, C), NA (-a), NC (-c)
-// for a partitioned level (7 columns), R, M, CP for a Thomas level (3).
+// Offsets (in doubles) of the factor tables for n unknowns: forward
+// reciprocal pivot and eliminated c at local row k (fr, fc), final A and C
+// for both partition lengths (xa, xc); the reduction's multipliers alpha and
+// gamma of step k, row i at pal + k m2 + i and pga + k m2 + i, and 1 / b_i
+// of the last step at prb (m2 = 2P rows, ns steps).  For P = 0 the plain
+// Thomas factors of all n rows at fr and fc.
 struct PoisFac {
   int n, P, L0, Lmax, size;
   float inv_n, inv_P;  // 1 / n, 1 / P rounded to FP32 (partition of a row, its start)
   int fr, fc, xa, xc;
-  int nl;  // reduced levels (the last is a Thomas level)
-  int ln[kPoisLevels], lp[kPoisLevels], lt[kPoisLevels];
+  int m2, ns, pal, pga, prb;
 };
 
 __device__ inline PoisFac pois_fac(int n) {
@@ -137,12 +140,14 @@ __device__ inline PoisFac pois_fac(int n) {
   f.inv_n = 1.0f / (float)n;
   f.P = field_partitions(n);
   f.inv_P = f.P ? 1.0f / (float)f.P : 0.0f;
-  f.nl = 0;
-  if (f.P == 0) {  // plain Thomas: reciprocal pivots and eliminated c per row
+  f.m2 = 2 * f.P;
+  f.ns = 0;
+  for (int s = 1; s < f.m2; s *= 2) ++f.ns;
+  if (f.P == 0) {
     f.L0 = f.Lmax = 0;
     f.fr = 0;
     f.fc = n;
-    f.xa = f.xc = 2 * n;
+    f.xa = f.xc = f.pal = f.pga = f.prb = 2 * n;
     f.size = 2 * n;
     return f;
   }
@@ -152,92 +157,15 @@ __device__ inline PoisFac pois_fac(int n) {
   f.fc = f.Lmax;
   f.xa = 2 * f.Lmax;
   f.xc = 4 * f.Lmax;
-  int off = 6 * f.Lmax, rows = 2 * f.P;
-  bool done = false;
-#pragma unroll
-  for (int k = 0; k < kPoisLevels; ++k) {  // constant indices: the arrays stay in registers
-    f.ln[k] = f.lp[k] = f.lt[k] = 0;
-    if (!done) {
-      const int q = field_partitions(rows);
-      f.ln[k] = rows;
-      f.lp[k] = q;
-      f.lt[k] = off;
-      off += (q ? 7 : 3) * rows;
-      f.nl = k + 1;
-      if (q == 0)
-        done = true;
-      else
-        rows = 2 * q;
-    }
-  }
-  f.size = off;
+  f.pal = 6 * f.Lmax;
+  f.pga = f.pal + f.ns * f.m2;
+  f.prb = f.pga + f.ns * f.m2;
+  f.size = f.prb + f.m2;
   return f;
 }
 
-// Factors of a general tridiagonal level (rows n, partitions P; P = 0:
-// Thomas) with matrix a, b, c (LDS scratch), written at t + off; for a
-// partitioned level the next level's matrix goes to na, nb, nc.
-__device__ void level_factor(int n, int P, const double* a, const double* b, const double* c,
-                             double* t, double* na, double* nb, double* nc) {
-  double* R = t;
-  double* M = t + n;
-  if (P == 0) {
-    double* CP = t + 2 * n;
-    double cp = 0.0;
-    for (int j = 0; j < n; ++j) {
-      double den = b[j];
-      if (j > 0) den = b[j] - a[j] * cp;
-      const double r = 1.0 / den;
-      cp = c[j] * r;
-      R[j] = r;
-      M[j] = -(a[j] * r);
-      CP[j] = cp;
-    }
-    return;
-  }
-  double* F = t + 2 * n;
-  double* XA = t + 3 * n;
-  double* XC = t + 4 * n;
-  double* NA = t + 5 * n;
-  double* NC = t + 6 * n;
-  for (int j = 0; j < n; ++j) {
-    NA[j] = -a[j];
-    NC[j] = -c[j];
-  }
-  for (int p = 0; p < P; ++p) {
-    const int s = (int)((int64_t)p * n / P);
-    const int e = (int)((int64_t)(p + 1) * n / P) - 1;
-    {
-      const int i = s + 1;
-      const double r = 1.0 / b[i];
-      R[i] = r;
-      XA[i] = a[i] * r;
-      XC[i] = c[i] * r;
-      F[i] = XC[i];
-    }
-    for (int i = s + 2; i <= e - 1; ++i) {
-      const double r = 1.0 / (b[i] - a[i] * XC[i - 1]);
-      XA[i] = -(a[i] * XA[i - 1]) * r;
-      XC[i] = c[i] * r;
-      F[i] = XC[i];
-      R[i] = r;
-      M[i] = -(a[i] * r);
-    }
-    for (int i = e - 2; i >= s + 1; --i) {
-      XA[i] = XA[i] - XC[i] * XA[i + 1];
-      XC[i] = -(XC[i] * XC[i + 1]);
-    }
-    na[2 * p] = a[s];
-    nb[2 * p] = b[s] - c[s] * XA[s + 1];
-    nc[2 * p] = -(c[s] * XC[s + 1]);
-    na[2 * p + 1] = -(a[e] * XA[e - 1]);
-    nb[2 * p + 1] = b[e] - a[e] * XC[e - 1];
-    nc[2 * p + 1] = c[e];
-  }
-}
-
 // One thread: all factors for n unknowns into t; scr: 6 * kTriRed doubles
-// of LDS for the reduced matrices.
+// of LDS for the reduced matrix.
 __device__ void pois_factor(const PoisFac& f, double* t, double* scr) {
   const double a = kPa, b = kPb, c = kPc;
   if (f.P == 0) {
@@ -255,8 +183,8 @@ __device__ void pois_factor(const PoisFac& f, double* t, double* scr) {
     return;
   }
   const int Lm = f.Lmax;
-  // level 0: forward elimination of the interior rows k = 1 .. Lmax - 2
-  // (identical in every partition); forward A and C to both length classes
+  // forward elimination of the interior rows k = 1 .. Lmax - 2 (identical in
+  // every partition); forward A and C to both length classes
   double r = 1.0 / b, ap = a * r, cp = c * r;
   for (int k = 1; k <= Lm - 2; ++k) {
     if (k > 1) {
@@ -285,11 +213,15 @@ __device__ void pois_factor(const PoisFac& f, double* t, double* scr) {
       xc[k] = bcp;
     }
   }
-  // level 1's matrix: the first and last rows of every partition
-  double* ma = scr;
-  double* mb = scr + kTriRed;
-  double* mc = scr + 2 * kTriRed;
-  for (int j = 0; j < 2 * f.P; ++j) {
+  // the reduced system's matrix: the first and last rows of every partition
+  const int m = f.m2;
+  double* A = scr;
+  double* B = scr + kTriRed;
+  double* C = scr + 2 * kTriRed;
+  double* A2 = scr + 3 * kTriRed;
+  double* B2 = scr + 4 * kTriRed;
+  double* C2 = scr + 5 * kTriRed;
+  for (int j = 0; j < m; ++j) {
     const int p = j >> 1;
     const int s = (int)((int64_t)p * f.n / f.P);
     const int e = (int)((int64_t)(p + 1) * f.n / f.P) - 1;
@@ -297,30 +229,37 @@ __device__ void pois_factor(const PoisFac& f, double* t, double* scr) {
     const double* xa = t + f.xa + (L - f.L0) * Lm;
     const double* xc = t + f.xc + (L - f.L0) * Lm;
     if ((j & 1) == 0) {
-      ma[j] = a;
-      mb[j] = b - c * xa[1];
-      mc[j] = -(c * xc[1]);
+      A[j] = a;
+      B[j] = b - c * xa[1];
+      C[j] = -(c * xc[1]);
     } else {
-      ma[j] = -(a * xa[L - 2]);
-      mb[j] = b - a * xc[L - 2];
-      mc[j] = c;
+      A[j] = -(a * xa[L - 2]);
+      B[j] = b - a * xc[L - 2];
+      C[j] = c;
     }
   }
-  // the reduced levels, each building the next level's matrix
-#pragma unroll
-  for (int k = 0; k < kPoisLevels; ++k) {
-    if (k < f.nl) {
-      double* na = scr + 3 * kTriRed;
-      double* nb = scr + 4 * kTriRed;
-      double* nc = scr + 5 * kTriRed;
-      level_factor(f.ln[k], f.lp[k], ma, mb, mc, t + f.lt[k], na, nb, nc);
-      for (int j = 0; j < 2 * f.lp[k]; ++j) {
-        ma[j] = na[j];
-        mb[j] = nb[j];
-        mc[j] = nc[j];
-      }
+  A[0] = 0.0;
+  C[m - 1] = 0.0;
+  // the reduction's multipliers, step by step
+  int k = 0;
+  for (int s = 1; s < m; s *= 2, ++k) {
+    for (int i = 0; i < m; ++i) {
+      const bool lo = i - s >= 0, hi = i + s < m;
+      const double al = lo ? -A[i] / B[i - s] : 0.0;
+      const double ga = hi ? -C[i] / B[i + s] : 0.0;
+      A2[i] = lo ? al * A[i - s] : 0.0;
+      C2[i] = hi ? ga * C[i + s] : 0.0;
+      B2[i] = (B[i] + (lo ? al * C[i - s] : 0.0)) + (hi ? ga * A[i + s] : 0.0);
+      t[f.pal + k * m + i] = al;
+      t[f.pga + k * m + i] = ga;
+    }
+    for (int i = 0; i < m; ++i) {
+      A[i] = A2[i];
+      B[i] = B2[i];
+      C[i] = C2[i];
     }
   }
+  for (int i = 0; i < m; ++i) t[f.prb + i] = 1.0 / B[i];
 }
 
 // Partition of level-0 row i, floor(((i + 1) P - 1) / n), evaluated as
@@ -491,50 +430,6 @@ __device__ __forceinline__ void level0_sweep(const PoisFac& f, const double* t, 
   Dn[2 * p + 1] = fma(-a, vf, de);
 }
 
-// A partitioned reduced level (n rows, P partitions, factors at t) on lane
-// p < P: D swept in place, the next level's right-hand side to Dn.
-__device__ __forceinline__ void level_sweep(int n, int P, const double* t, double* D, double* Dn,
-                                            int p) {
-  const double* R = t;
-  const double* M = t + n;
-  const double* F = t + 2 * n;
-  const double* NA = t + 5 * n;
-  const double* NC = t + 6 * n;
-  const int s = p * n / P;
-  const int e = (p + 1) * n / P - 1;
-  const double d0 = D[s], de = D[e];
-  const double vf = part_sweep(
-      D + s, e - s + 1, [&](int k) { return R[s + k]; }, [&](int k) { return M[s + k]; },
-      [&](int k) { return -F[s + k]; });
-  Dn[2 * p] = fma(NC[s], D[s + 1], d0);
-  Dn[2 * p + 1] = fma(NA[e], vf, de);
-}
-
-// The solution of a partitioned reduced level on lane p < P from its
-// partition's end values X[2p], X[2p + 1], written to Xo.
-__device__ __forceinline__ void level_recover(int n, int P, const double* t, const double* D,
-                                              const double* X, double* Xo, int p) {
-  const double* XA = t + 3 * n;
-  const double* XC = t + 4 * n;
-  const int s = p * n / P;
-  const int e = (p + 1) * n / P - 1;
-  const double xs = X[2 * p], xe = X[2 * p + 1];
-  for (int i = s + 1; i <= e - 1; i += kB) {
-    double w[kB], xa[kB], xc[kB];
-#pragma unroll
-    for (int u = 0; u < kB; ++u) {
-      w[u] = D[i + u];
-      xa[u] = XA[i + u];
-      xc[u] = XC[i + u];
-    }
-#pragma unroll
-    for (int u = 0; u < kB; ++u)
-      if (i + u <= e - 1) Xo[i + u] = fma(-xc[u], xe, fma(-xa[u], xs, w[u]));
-  }
-  Xo[s] = xs;
-  Xo[e] = xe;
-}
-
 // Orders the calling wave's LDS writes before its later reads by other lanes.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -545,89 +440,61 @@ __device__ __forceinline__ void wave_sync() {
 // Solve of the (-1, 2, -1) system, in two parts around a workgroup barrier:
 // pois_sweeps (wave 0) and pois_recover (every thread).  The right-hand side
 // is in d (row i at pois_slot(i)) and is replaced by the solution in the same
-// places; t: factor tables (LDS); red: kPoisRed doubles of LDS.  The sweeps
-// run one partition per lane, level by level, down to a Thomas level and
-// back up; level 0's interior unknowns are then recovered by every thread.
-// The right-hand side is carried by fused multiply-adds, one rounding per
-// row of a sweep: forward d'_i = fma(-(a r_i), d'_{i-1}, d_i r_i), backward
-// d'_i = fma(-c'_i, d'_{i+1}, d'_i).  Thomas work runs on all of wave 0 with
-// an offset zo that is 0 but not known to be, so it stays in vector
-// registers.
-struct PoisLv {
-  double* D[kPoisLevels];  // right-hand side of reduced level k
-  double* X[kPoisLevels];  // its solution
-};
-
-__device__ __forceinline__ PoisLv pois_levels(const PoisFac& f, double* red) {
-  PoisLv v;
-  int o = 0;
-#pragma unroll
-  for (int k = 0; k < kPoisLevels; ++k) {  // constant indices only: registers, not scratch
-    v.D[k] = red + o;
-    o += f.ln[k];
-    v.X[k] = red + o;
-    o += f.ln[k];
-  }
-  return v;
-}
-
+// places; t: factor tables (LDS); red: kPoisRed doubles of LDS (the reduced
+// system's right-hand side at [0, 2P), its solution at kTriRed, the
+// reduction's exchange buffer at 2 kTriRed).  The partitions' sweeps run one
+// partition per lane, the reduction runs rows i and i + 64 on lane i, and
+// the interior unknowns are recovered by every thread.  The right-hand side
+// is carried by fused multiply-adds, one rounding per row of a sweep:
+// forward d'_i = fma(-(a r_i), d'_{i-1}, d_i r_i), backward d'_i =
+// fma(-c'_i, d'_{i+1}, d'_i), reduction d'_i = fma(gamma_i, d_{i+s},
+// fma(alpha_i, d_{i-s}, d_i)).
 __device__ void pois_sweeps(const PoisFac& f, const double* t, double* d, double* red) {
   const int lane = threadIdx.x, n = f.n, P = f.P;
-  const int zo = (int)(threadIdx.x / blockDim.x);
   const double a = kPa;
-  if (P == 0) {  // n < 16: plain Thomas
+  if (P == 0) {  // n < 16: plain Thomas, on all of wave 0 (the same values)
+    const int zo = (int)(threadIdx.x / blockDim.x);
     thomas_sweep(
         d + zo, n, [&](int j) { return t[f.fr + zo + j]; },
         [&](int j) { return -(a * t[f.fr + zo + j]); }, [&](int j) { return t[f.fc + zo + j]; });
     return;
   }
-  const PoisLv lv = pois_levels(f, red);
-  if (lane < P) {  // level 0: one partition per lane
-    const int s = lane * n / P;
-    const int L = (lane + 1) * n / P - s;
-    level0_sweep(f, t, d + s + lane, L, lv.D[0], lane);
+  if (lane < P) {  // one partition per lane
+    const int s = pois_start(f, lane);
+    const int L = pois_start(f, lane + 1) - s;
+    level0_sweep(f, t, d + s + lane, L, red, lane);
   }
   wave_sync();
-  // down the partitioned reduced levels to the Thomas level (the last)
-#pragma unroll
-  for (int k = 0; k + 1 < kPoisLevels; ++k) {
-    if (k < f.nl - 1) {
-      if (lane < f.lp[k]) level_sweep(f.ln[k], f.lp[k], t + f.lt[k], lv.D[k], lv.D[k + 1], lane);
-      wave_sync();
-    }
+  // parallel cyclic reduction of the 2P rows: rows r0 = lane, r1 = lane + 64
+  const int m = f.m2, r0 = lane, r1 = lane + 64;
+  const bool v0 = r0 < m, v1 = r1 < m;
+  const int i0 = v0 ? r0 : 0, i1 = v1 ? r1 : 0;  // table rows (clamped)
+  double* ex = red + 2 * kTriRed;
+  double d0 = red[i0], d1 = red[i1];
+  for (int k = 0, s = 1; k < f.ns; ++k, s *= 2) {
+    ex[r0] = d0;
+    ex[r1] = d1;
+    const double al0 = t[f.pal + k * m + i0], ga0 = t[f.pga + k * m + i0];
+    const double al1 = t[f.pal + k * m + i1], ga1 = t[f.pga + k * m + i1];
+    wave_sync();
+    const double dm0 = r0 - s >= 0 ? ex[v0 && r0 - s >= 0 ? r0 - s : 0] : 0.0;
+    const double dp0 = r0 + s < m ? ex[r0 + s < m ? r0 + s : 0] : 0.0;
+    const double dm1 = r1 - s >= 0 && v1 ? ex[v1 ? r1 - s : 0] : 0.0;
+    const double dp1 = r1 + s < m ? ex[r1 + s < m ? r1 + s : 0] : 0.0;
+    d0 = fma(ga0, dp0, fma(al0, dm0, d0));
+    d1 = fma(ga1, dp1, fma(al1, dm1, d1));
+    wave_sync();
   }
-#pragma unroll
-  for (int k = 0; k < kPoisLevels; ++k) {
-    if (k == f.nl - 1) {  // Thomas level, on every lane (the same values)
-      const int m2 = f.ln[k];
-      const double* R = t + f.lt[k] + zo;
-      const double* M = R + m2;
-      const double* CP = R + 2 * m2;
-      double* X = lv.X[k] + zo;
-      const double* D = lv.D[k] + zo;
-      for (int j = 0; j < m2; ++j) X[j] = D[j];
-      thomas_sweep(
-          X, m2, [&](int j) { return R[j]; }, [&](int j) { return M[j]; },
-          [&](int j) { return CP[j]; });
-    }
-  }
-  wave_sync();
-  // back up the partitioned reduced levels
-#pragma unroll
-  for (int k = kPoisLevels - 2; k >= 0; --k) {
-    if (k < f.nl - 1) {
-      if (lane < f.lp[k])
-        level_recover(f.ln[k], f.lp[k], t + f.lt[k], lv.D[k], lv.X[k + 1], lv.X[k], lane);
-      wave_sync();
-    }
-  }
+  double* xr = red + kTriRed;
+  if (v0) xr[r0] = d0 * t[f.prb + r0];
+  if (v1) xr[r1] = d1 * t[f.prb + r1];
 }
 
-// Level 0's interior unknowns from their partition's end values, in place.
-__device__ void pois_recover(const PoisFac& f, const double* t, double* d, double* red) {
+// The interior unknowns from their partition's end values, in place.
+__device__ void pois_recover(const PoisFac& f, const double* t, double* d, const double* red) {
   if (f.P == 0) return;
   const int n = f.n;
-  const double* rx = pois_levels(f, red).X[0];
+  const double* rx = red + kTriRed;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int p = pois_part(f, i);
     const int s = pois_start(f, p);
@@ -978,25 +845,29 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   auto children = [&]() {
     const uint32_t lane = (uint32_t)tid & 63u;
     uint32_t n_kids = 0;
+    // windows of 64 kScanWin totals; lane l takes kScanWin consecutive ones
+    // (a serial scan in registers), then one wave scan of the lane sums
     for (uint32_t t0 = pb0; t0 < pb1; t0 += 64u * kScanWin) {
+      const uint32_t k0 = t0 + lane * (uint32_t)kScanWin;
       uint32_t v[kScanWin];
 #pragma unroll
-      for (int w = 0; w < kScanWin; ++w) {
-        const uint32_t k = t0 + 64u * (uint32_t)w + lane;
-        v[w] = k < pb1 ? gseg[k] : 0u;
+      for (int w = 0; w < kScanWin; ++w) v[w] = k0 + (uint32_t)w < pb1 ? gseg[k0 + (uint32_t)w] : 0u;
+      uint32_t sum = 0;
+#pragma unroll
+      for (int w = 0; w < kScanWin; ++w) sum += v[w];
+      uint32_t x = sum;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if ((int)lane >= o) x += y;
       }
+      uint32_t run = n_kids + x - sum;  // exclusive prefix of this lane's first total
 #pragma unroll
       for (int w = 0; w < kScanWin; ++w) {
-        uint32_t x = v[w];
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t y = __shfl_up(x, o, 64);
-          if ((int)lane >= o) x += y;
-        }
-        const uint32_t k = t0 + 64u * (uint32_t)w + lane;
-        if (k < pb1) gseg[k] = n_kids + x - v[w];
-        n_kids += (uint32_t)__shfl((int)x, 63, 64);
+        if (k0 + (uint32_t)w < pb1) gseg[k0 + (uint32_t)w] = run;
+        run += v[w];
       }
+      n_kids += (uint32_t)__shfl((int)x, 63, 64);
     }
     if (lane != 0) return;
     const uint32_t ns0 = sh_see[0], ns1 = sh_see[1];

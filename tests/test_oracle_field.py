@@ -74,18 +74,52 @@ def test_fma_partitioned_solve_matches_banded_solve(n):
     np.testing.assert_allclose(x, oracle.solve_tridiag(a, b, c, d), rtol=1e-12, atol=1e-14)
 
 
-def test_field_solver_levels():
-    # P = min(64, n/8) partitions per level, the reduced system (2P rows)
-    # solved the same way, Thomas below 16 rows: 2047 unknowns take levels
-    # of 64, 16 and 4 partitions and an 8-row Thomas solve
-    sizes, n = [], 2047
-    while oracle.field_partitions(n):
+def test_field_solver_partitions():
+    # P = min(64, n/8) partitions of at least 8 rows, Thomas below 16 rows;
+    # the reduced system has 2P rows
+    for n in (15, 16, 23, 130, 511, 512, 1023, 2047, 4095):
         P = oracle.field_partitions(n)
-        assert P == min(64, n // 8) and n >= 16
-        sizes.append(P)
-        n = 2 * P
-    assert sizes == [64, 16, 4] and n == 8
-    assert oracle.field_partitions(15) == 0 and oracle.field_partitions(16) == 2
+        assert P == (0 if n < 16 else min(64, n // 8))
+        if P:
+            assert n // P >= 8 and 2 * P <= 128
+
+
+def _banded(a, b, c, d):
+    from scipy.linalg import solve_banded
+    n = len(b)
+    ab = np.zeros((3, n))
+    ab[0, 1:] = c[:-1]
+    ab[1] = b
+    ab[2, :-1] = a[1:]
+    return solve_banded((1, 1), ab, d)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8, 17, 64, 100, 127, 128])
+def test_cyclic_reduction_matches_banded_solve(m):
+    # random diagonally dominant systems of every size class (powers of two
+    # and ragged); a[0] and c[m-1] are ignored
+    rng = np.random.default_rng(100 + m)
+    a = rng.uniform(-1, 1, m)
+    c = rng.uniform(-1, 1, m)
+    b = np.abs(a) + np.abs(c) + rng.uniform(0.5, 2.0, m)
+    d = rng.normal(size=m)
+    x = oracle.pcr_fma(a, b, c, d)
+    a0, c0 = a.copy(), c.copy()
+    a0[0] = 0.0
+    c0[-1] = 0.0
+    np.testing.assert_allclose(x, _banded(a0, b, c0, d), rtol=1e-12, atol=1e-13)
+
+
+def test_cyclic_reduction_of_the_poisson_matrix():
+    # the (-1, 2, -1) matrix of 128 rows, a known solution
+    m = 128
+    rng = np.random.default_rng(5)
+    xs = rng.normal(size=m)
+    d = 2 * xs
+    d[1:] -= xs[:-1]
+    d[:-1] -= xs[1:]
+    x = oracle.pcr_fma(-np.ones(m), 2 * np.ones(m), -np.ones(m), d)
+    np.testing.assert_allclose(x, xs, rtol=0, atol=1e-9 * np.abs(xs).max())
 
 
 @pytest.mark.parametrize("n", [3, 8, 15, 16, 63, 130, 1023, 2047, 4095])
