@@ -519,8 +519,12 @@ __host__ __device__ constexpr size_t finalize_lds_doubles(int nn_max) {
   return 3u * (size_t)nn_max + 64u + (size_t)kPoisRed + kFacMax;
 }
 
-// Nodes per finalize thread (at most 4097 nodes).
-constexpr int kNodeSlots = (kMaxNodes + kFinThreads - 1) / kFinThreads;
+// Grid nodes belong to the threads of waves 1 .. 15 of the end-of-step
+// workgroup (wave 0 keeps the serial work: emission, sweeps); node j of
+// thread t >= 64 is j = (t - 64) + u kNodeThreads; nodes per thread for at
+// most 4097 nodes.
+constexpr int kNodeThreads = kFinThreads - 64;
+constexpr int kNodeSlots = (kMaxNodes + kNodeThreads - 1) / kNodeThreads;
 
 // End of a step (field_only == 0) and the field of the next one.  Global
 // inputs are loaded together up front so that the kernel pays few memory
@@ -640,6 +644,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   // (registers live in one wave's path are not kept through another's)
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr int kLastWave = kFinThreads / 64 - 1;
+  const bool node = wave > 0;     // owns grid nodes
+  const int nt = tid - 64;        // its index among the node threads
   double* X = reinterpret_cast<double*>(smem);         // interior rows (pois_slot), right-hand side then solution
   int64_t* CN = reinterpret_cast<int64_t*>(X + nn + 64);  // deposit of the step
   int64_t* EN = CN + nn;                                   // its emission part
@@ -668,10 +674,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   double n0v[kNodeSlots], accv[kNodeSlots];
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
-    const int j = tid + u * kFinThreads;
+    const int j = nt + u * kNodeThreads;
     c0v[u] = c1v[u] = srcv[u] = 0;
     n0v[u] = accv[u] = 0.0;
-    if (j < nn) {
+    if (node && j < nn) {
       c0v[u] = gc0[j];
       c1v[u] = gc1[j];
       n0v[u] = gni[j];
@@ -728,18 +734,17 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   // Emission deposits into a grid of its own (EN, zeroed here), so that it
   // can run beside the deposit's other updates; this step's final deposit
   // is CN + EN.
-  if (!field_only)
-    for (int j = tid; j < nn; j += kFinThreads) EN[j] = 0;
+
   // this step's deposit to LDS; n_i with this step's ion sources; with
   // several species the others are updated here too and netv is the ion
   // charge density sum_s Z_s n_s (species in order)
   double niv[kNodeSlots], netv[kNodeSlots];
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
-    const int j = tid + u * kFinThreads;
+    const int j = nt + u * kNodeThreads;
     niv[u] = 0.0;
     netv[u] = 0.0;
-    if (j < nn) {
+    if (node && j < nn) {
       CN[j] = cur ? c1v[u] : c0v[u];
       niv[u] = field_only ? n0v[u] : n0v[u] + (double)srcv[u] * scale_of(d, j);
       netv[u] = niv[u];
@@ -769,8 +774,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       if (i < f.size) T[i] = tv[u];
     }
   }
-  __syncthreads();
-  // emission from the wall fluxes of this step's fluid update (wave 0)
+  // emission from the wall fluxes of this step's fluid update (wave 0,
+  // which zeroes the emission grid first and owns no nodes, so it starts as
+  // soon as the state has arrived)
+  if (!field_only && wave == 0) {
+    for (int j = tid; j < nn; j += 64) EN[j] = 0;
+    wave_sync();
+  }
   if (!field_only && tid < 2) {
     double F = tid == 0 ? ((-wall_g < 0.0) ? 0.0 : -wall_g) : ((wall_g < 0.0) ? 0.0 : wall_g);
     if (d.ion_model == HD_ION_DD_SPECIES) F = st->see_flux[tid];  // positive ions only
@@ -802,14 +812,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   }
   __syncthreads();
   // ion sources of the step, the final deposit, run averages: written by
-  // wave 0 now, by the other waves while wave 0 sweeps
+  // the node waves while wave 0 sweeps
   auto grid_out = [&]() {
     Gp<double>* wni = gptr(d.ni);
     Gp<int64_t>* wsrc = gptr(d.ion_src);
 #pragma unroll
     for (int u = 0; u < kNodeSlots; ++u) {
-      const int j = tid + u * kFinThreads;
-      if (j < nn) {
+      const int j = nt + u * kNodeThreads;
+      if (node && j < nn) {
         const int64_t c = CN[j] + EN[j];
         wni[j] = niv[u];
         wsrc[j] = 0;
@@ -819,13 +829,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       }
     }
   };
-  if (!field_only && wave == 0) grid_out();
   // Poisson's equation with phi_0 = V(t), phi_N = 0 for the interior nodes
   double rho_0 = 0.0, rho_n = 0.0;  // charge density at the walls (nodes 0 and nc)
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
-    const int j = tid + u * kFinThreads;
-    if (j < nn) {
+    const int j = nt + u * kNodeThreads;
+    if (node && j < nn) {
       const int64_t c = field_only ? CN[j] : CN[j] + EN[j];
       const double ne = (double)c * scale_of(d, j);
       const double r = kECharge * (netv[u] - ne);
@@ -900,8 +909,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   if (wave == 0) {
     pois_sweeps(f, T, X, red);
   } else if (!field_only) {
-    grid_out();
     if (wave == kLastWave) children();
+    grid_out();
   }
   __syncthreads();
   pois_recover(f, T, X, red);
@@ -918,8 +927,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   double e0_new = 0.0;
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
-    const int j = tid + u * kFinThreads;
-    if (j < nn) {
+    const int j = nt + u * kNodeThreads;
+    if (node && j < nn) {
       double e;
       if (j == 0)
         e = (phi(0) - phi(1)) * d.inv_dz - rho_0 * d.hdz_eps;
@@ -934,7 +943,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       if (j == 0) e0_new = e;
     }
   }
-  if (!field_only && tid == 0) {
+  if (!field_only && tid == 64) {  // the owner of node 0
     // The interval belongs to the period that contains t_n+1; when that
     // level ends a period, the period's mean sets the next amplitude.
     const double jd = kEps0 * ((e0_new - sh_pw[3]) / d.dt);
