@@ -258,6 +258,48 @@ struct WaveCounts {
   uint32_t absl = 0, absr = 0, ovf = 0, pushed = 0;
 };
 
+// Sum over the 64 lanes of a wave without LDS: DPP row shifts by 1, 2, 4 and
+// 8 leave each 16-lane row's sum in its last lane (a source outside the row
+// reads 0), and the four row sums are read out and added as scalars.  A
+// shuffle would be one LDS permute per step.  Integer sums: exact.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_shr(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+#define HD_ROW_STEP(C)                                                   \
+  {                                                                      \
+    const uint64_t y = ((uint64_t)dpp_shr<C>(hi) << 32) | dpp_shr<C>(lo); \
+    const uint64_t z = (((uint64_t)hi << 32) | lo) + y;                  \
+    lo = (uint32_t)z;                                                    \
+    hi = (uint32_t)(z >> 32);                                            \
+  }
+  HD_ROW_STEP(0x111)  // row_shr:1
+  HD_ROW_STEP(0x112)  // row_shr:2
+  HD_ROW_STEP(0x114)  // row_shr:4
+  HD_ROW_STEP(0x118)  // row_shr:8
+#undef HD_ROW_STEP
+  uint64_t t = 0;
+#pragma unroll
+  for (int r = 15; r < 64; r += 16)
+    t += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, r) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)lo, r);
+  return t;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x += dpp_shr<0x111>(x);
+  x += dpp_shr<0x112>(x);
+  x += dpp_shr<0x114>(x);
+  x += dpp_shr<0x118>(x);
+  uint32_t t = 0;
+#pragma unroll
+  for (int r = 15; r < 64; r += 16) t += (uint32_t)__builtin_amdgcn_readlane((int)x, r);
+  return t;
+}
+
 // One wave's 256 slots of a chunk: push, removal and write-back, then the
 // null-collision test and channel, the deposit at x^{n+1}; collisions are
 // queued.  No workgroup barrier is involved.
@@ -357,15 +399,10 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   const uint64_t act = __ballot(rc >= 0);
   if (act) {
     const int lead = __ffsll((unsigned long long)act) - 1;
-    const int rl = __shfl(rc, lead, 64);
+    const int rl = __builtin_amdgcn_readlane(rc, lead);
     if (__ballot(rc >= 0 && rc != rl) == 0) {
-      uint64_t s1 = rc >= 0 ? a1 : 0;
-      uint32_t sm = rc >= 0 ? m : 0;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        s1 += __shfl_xor(s1, o, 64);
-        sm += __shfl_xor(sm, o, 64);
-      }
+      const uint64_t s1 = wave_sum_u64(rc >= 0 ? a1 : 0);
+      const uint32_t sm = wave_sum_u32(rc >= 0 ? m : 0);
       if (lane == lead) {
         lds_add_i64(&g.bins[rl], ((uint64_t)sm << 32) - s1);
         lds_add_i64(&g.bins[rl + 1], s1);
