@@ -145,6 +145,72 @@ template <class T>
 __device__ __forceinline__ Gp<T>* gptr(T* p) {
   return (Gp<T>*)p;
 }
+// ---- wave reductions without LDS ------------------------------------------
+// DPP row shifts by 1, 2, 4 and 8 leave each 16-lane row's reduction in its
+// last lane (whose chain reads only lanes inside the row, so the value other
+// lanes get from outside the row never reaches it), and the four row results
+// are read out and combined as scalars.  A shuffle would be one LDS permute
+// per step.  Results are wave-uniform.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_shr(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+#define HD_ROW_STEP(C)                                                   \
+  {                                                                      \
+    const uint64_t y = ((uint64_t)dpp_shr<C>(hi) << 32) | dpp_shr<C>(lo); \
+    const uint64_t z = (((uint64_t)hi << 32) | lo) + y;                  \
+    lo = (uint32_t)z;                                                    \
+    hi = (uint32_t)(z >> 32);                                            \
+  }
+  HD_ROW_STEP(0x111)  // row_shr:1
+  HD_ROW_STEP(0x112)  // row_shr:2
+  HD_ROW_STEP(0x114)  // row_shr:4
+  HD_ROW_STEP(0x118)  // row_shr:8
+#undef HD_ROW_STEP
+  uint64_t t = 0;
+#pragma unroll
+  for (int r = 15; r < 64; r += 16)
+    t += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, r) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)lo, r);
+  return t;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x += dpp_shr<0x111>(x);
+  x += dpp_shr<0x112>(x);
+  x += dpp_shr<0x114>(x);
+  x += dpp_shr<0x118>(x);
+  uint32_t t = 0;
+#pragma unroll
+  for (int r = 15; r < 64; r += 16) t += (uint32_t)__builtin_amdgcn_readlane((int)x, r);
+  return t;
+}
+
+__device__ __forceinline__ int wave_min_i32(int x) {
+  x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x111, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x112, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x114, 0xf, 0xf, false));
+  x = min(x, __builtin_amdgcn_update_dpp(x, x, 0x118, 0xf, 0xf, false));
+  int t = __builtin_amdgcn_readlane(x, 15);
+  t = min(t, __builtin_amdgcn_readlane(x, 31));
+  t = min(t, __builtin_amdgcn_readlane(x, 47));
+  return min(t, __builtin_amdgcn_readlane(x, 63));
+}
+
+__device__ __forceinline__ int wave_max_i32(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x111, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x112, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x114, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x118, 0xf, 0xf, false));
+  int t = __builtin_amdgcn_readlane(x, 15);
+  t = max(t, __builtin_amdgcn_readlane(x, 31));
+  t = max(t, __builtin_amdgcn_readlane(x, 47));
+  return max(t, __builtin_amdgcn_readlane(x, 63));
+}
+
 template <class T>
 __device__ __forceinline__ void gld4(const Gp<T>* p, T (&o)[4]) {
   if constexpr (sizeof(T) == 4) {

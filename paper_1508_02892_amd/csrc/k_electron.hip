@@ -258,48 +258,6 @@ struct WaveCounts {
   uint32_t absl = 0, absr = 0, ovf = 0, pushed = 0;
 };
 
-// Sum over the 64 lanes of a wave without LDS: DPP row shifts by 1, 2, 4 and
-// 8 leave each 16-lane row's sum in its last lane (a source outside the row
-// reads 0), and the four row sums are read out and added as scalars.  A
-// shuffle would be one LDS permute per step.  Integer sums: exact.
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp_shr(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, true);
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
-  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-#define HD_ROW_STEP(C)                                                   \
-  {                                                                      \
-    const uint64_t y = ((uint64_t)dpp_shr<C>(hi) << 32) | dpp_shr<C>(lo); \
-    const uint64_t z = (((uint64_t)hi << 32) | lo) + y;                  \
-    lo = (uint32_t)z;                                                    \
-    hi = (uint32_t)(z >> 32);                                            \
-  }
-  HD_ROW_STEP(0x111)  // row_shr:1
-  HD_ROW_STEP(0x112)  // row_shr:2
-  HD_ROW_STEP(0x114)  // row_shr:4
-  HD_ROW_STEP(0x118)  // row_shr:8
-#undef HD_ROW_STEP
-  uint64_t t = 0;
-#pragma unroll
-  for (int r = 15; r < 64; r += 16)
-    t += ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, r) << 32) |
-         (uint32_t)__builtin_amdgcn_readlane((int)lo, r);
-  return t;
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
-  x += dpp_shr<0x111>(x);
-  x += dpp_shr<0x112>(x);
-  x += dpp_shr<0x114>(x);
-  x += dpp_shr<0x118>(x);
-  uint32_t t = 0;
-#pragma unroll
-  for (int r = 15; r < 64; r += 16) t += (uint32_t)__builtin_amdgcn_readlane((int)x, r);
-  return t;
-}
-
 // One wave's 256 slots of a chunk: push, removal and write-back, then the
 // null-collision test and channel, the deposit at x^{n+1}; collisions are
 // queued.  No workgroup barrier is involved.

@@ -70,6 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
         const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
         if (i < e) gld4(cell + i, c4[q]);
       }
+      // the tile's cell range first
 #pragma unroll
       for (int q = 0; q < kRounds; ++q) {
         const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
@@ -77,15 +78,42 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
         for (int k = 0; k < 4; ++k) {
           const int c = c4[q][k];
           if (i + (uint32_t)k < e && c >= 0) {
-            atomicAdd(&h[c], 1u);
             lo = min(lo, c);
             hi = max(hi, c);
           }
         }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o, 64));
-        hi = max(hi, __shfl_xor(hi, o, 64));
+      lo = wave_min_i32(lo);
+      hi = wave_max_i32(hi);
+      // Cells lo .. lo + 7 are counted in 8-bit fields of one register per
+      // lane (at most 64 items per lane), then in 16-bit fields summed over
+      // the wave (at most kSortTile per cell); other cells go straight to
+      // the wave's histogram.  With nearly sorted cells an atomic per item
+      // would have all 64 lanes on one address.
+      uint64_t a8 = 0;
+#pragma unroll
+      for (int q = 0; q < kRounds; ++q) {
+        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int c = c4[q][k];
+          if (i + (uint32_t)k < e && c >= 0) {
+            const uint32_t o = (uint32_t)(c - lo);
+            if (o < 8u)
+              a8 += 1ull << (8u * o);
+            else
+              atomicAdd(&h[c], 1u);
+          }
+        }
+      }
+      const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
+      const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
+                                       ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
+      const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
+                                       ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
+      if (lane < 8) {
+        const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
+        if (v) h[lo + lane] += v;
       }
       for (int c = lo + lane; c <= hi; c += 64) {
         const uint32_t v = h[c];
@@ -281,12 +309,30 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
           const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
           if (i < e) gld4(cell + i, c4[q]);
         }
+        // cells lo .. lo + 7 in packed fields as in the count (at most 16
+        // items per lane, kQuarter per cell), the others by atomics
+        uint64_t a8 = 0;
 #pragma unroll
         for (int q = 0; q < kRounds; ++q) {
           const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
 #pragma unroll
           for (int k = 0; k < 4; ++k)
-            if (i + (uint32_t)k < e && c4[q][k] >= 0) atomicAdd(&myrun[c4[q][k] - lo], 1u);
+            if (i + (uint32_t)k < e && c4[q][k] >= 0) {
+              const uint32_t o = (uint32_t)(c4[q][k] - lo);
+              if (o < 8u)
+                a8 += 1ull << (8u * o);
+              else
+                atomicAdd(&myrun[o], 1u);
+            }
+        }
+        const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
+        const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
+                                         ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
+        const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
+                                         ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
+        if (lane < 8) {
+          const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
+          if (v) myrun[lane] += v;
         }
       }
       __syncthreads();
@@ -331,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const int k = key[q];
-          const int k0 = __shfl(k, 0, 64);
+          const int k0 = __builtin_amdgcn_readfirstlane(k);
           uint64_t peers = ~0ull;
           if (__ballot(k == k0) != ~0ull) {
             for (int bit = 0; bit < nbits; ++bit) {
