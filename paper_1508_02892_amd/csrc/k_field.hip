@@ -262,7 +262,7 @@ __device__ void pois_factor(const PoisFac& f, double* t, double* scr) {
   for (int i = 0; i < m; ++i) t[f.prb + i] = 1.0 / B[i];
 }
 
-// Partition of level-0 row i, floor(((i + 1) P - 1) / n), evaluated as
+// Partition of interior row i, floor(((i + 1) P - 1) / n), evaluated as
 // floor(((i + 1) P - 1/2) / n) in FP32: the half keeps the quotient at least
 // 1/(2n) >= 2^-13 from an integer while the two roundings move it by at most
 // P 2^-23 <= 2^-17 (n <= 4095, P <= 64), so the floor is exact.
@@ -270,21 +270,21 @@ __device__ __forceinline__ int pois_part(const PoisFac& f, int i) {
   return (int)(((float)((i + 1) * f.P) - 0.5f) * f.inv_n);
 }
 
-// First row of level-0 partition p, floor(p n / P), evaluated as
+// First row of partition p, floor(p n / P), evaluated as
 // floor((p n + 1/2) / P) in FP32 (the same argument: the quotient stays at
 // least 1/(2P) >= 2^-7 from an integer).
 __device__ __forceinline__ int pois_start(const PoisFac& f, int p) {
   return (int)(((float)(p * f.n) + 0.5f) * f.inv_P);
 }
 
-// Place of interior row i in the solver's array: partition p of level 0 sits
+// Place of interior row i in the solver's array: partition p sits
 // p doubles higher (the 64 lanes of a sweep, one partition each, then fall
 // in different LDS banks).  Holds the right-hand side, then the solution.
 __device__ __forceinline__ int pois_slot(const PoisFac& f, int i) {
   return f.P ? i + pois_part(f, i) : i;
 }
 
-// Right-hand-side sweeps of one partition of a level: D[k] is row s + k (L
+// Right-hand-side sweeps of one partition: D[k] is row s + k (L
 // rows, lane-dependent); forward v_1 = v_1 r_1, v_k = fma(m_k, v_{k-1},
 // v_k r_k) for k = 2 .. L - 2; backward v_k = fma(f_k, v_{k+1}, v_k) for
 // k = L - 3 .. 1 (f_k = -c'_k); D swept in place.  Rows go in batches of 8
@@ -415,9 +415,9 @@ __device__ __forceinline__ void thomas_sweep(double* X, int m, FR r, FM mm, FC c
   }
 }
 
-// Level 0 on lane p (partition rows s .. s + L - 1 at dd[0 ..]): swept in
+// The partition of lane p (rows s .. s + L - 1 at dd[0 ..]): swept in
 // place, the reduced right-hand side to Dn.
-__device__ __forceinline__ void level0_sweep(const PoisFac& f, const double* t, double* dd, int L,
+__device__ __forceinline__ void partition_sweep(const PoisFac& f, const double* t, double* dd, int L,
                                              double* Dn, int p) {
   const double a = kPa, c = kPc;
   const double* fr = t + f.fr;
@@ -462,7 +462,7 @@ __device__ void pois_sweeps(const PoisFac& f, const double* t, double* d, double
   if (lane < P) {  // one partition per lane
     const int s = pois_start(f, lane);
     const int L = pois_start(f, lane + 1) - s;
-    level0_sweep(f, t, d + s + lane, L, red, lane);
+    partition_sweep(f, t, d + s + lane, L, red, lane);
   }
   wave_sync();
   // parallel cyclic reduction of the 2P rows: rows r0 = lane, r1 = lane + 64
