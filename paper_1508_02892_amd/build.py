@@ -28,6 +28,15 @@ FLAGS = [
 ]
 
 
+# Per-source additions.  The end-of-step kernel is one workgroup whose first
+# loads depend on its arguments: preloading them into scalar registers at
+# wave launch saves a memory round trip on its critical path (about 1 us per
+# step measured on the 8.4M-electron workload; no gain measured elsewhere).
+SOURCE_FLAGS = {
+    "k_field.hip": ["-mllvm", "-amdgpu-kernarg-preload-count=4"],
+}
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
         if c and os.path.exists(c):
@@ -37,7 +46,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + FLAGS + SOURCE_FLAGS.get(src, []) + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
