@@ -4,7 +4,10 @@
 // Tiles of kSortTile consecutive slots.  A tile's per-cell counts go to a
 // bin-major matrix hist[c * nt + t]; an exclusive scan of that matrix in its
 // flat order gives, for every (cell, tile), the first destination slot, so
-// holes are dropped and equal cells keep their order.  The scatter gives a
+// holes are dropped and equal cells keep their order.  The matrix is zero
+// between sorts (zeroed with the discharge's buffer; the scan leaves 0 in
+// empty entries and the scatter zeroes each entry it reads), so the counts
+// write only their nonzero entries and no clearing pass is needed.  The scatter gives a
 // tile to a workgroup: each wave counts its quarter of the tile, a per-cell
 // prefix over the waves gives each wave its own cursors, and the rank of an
 // item among earlier items of the same cell comes from wave ballots over the
@@ -22,21 +25,6 @@ constexpr int kWavesPerBlock = kThreads / 64;
 template <class P>
 __device__ __forceinline__ uint32_t n_tiles(const Disch<P>& d) {
   return (d.st->n_main + (uint32_t)kSortTile - 1u) / (uint32_t)kSortTile;
-}
-
-template <class P>
-__global__ __launch_bounds__(kThreads) void k_sort_clear(const Disch<P>* __restrict__ ds, int D) {
-  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  const uint64_t gid = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-  const uint64_t gsz = (uint64_t)gridDim.x * kThreads;
-  for (int di = 0; di < D; ++di) {
-    const Disch<P>& d = ds[di];
-    if (!d.st->sort_due) continue;
-    const uint64_t n = (uint64_t)d.nc * n_tiles(d);
-    Gp<u32x4>* h4 = reinterpret_cast<Gp<u32x4>*>(gptr(d.hist));
-    for (uint64_t i = gid; i < n / 4; i += gsz) h4[i] = u32x4{0u, 0u, 0u, 0u};
-    for (uint64_t i = (n / 4) * 4 + gid; i < n; i += gsz) gptr(d.hist)[i] = 0u;
-  }
 }
 
 template <class P>
@@ -220,45 +208,40 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const Disch<P>* __rest
 }
 
 template <class P>
-__global__ __launch_bounds__(kThreads) void k_scan_top(const Disch<P>* __restrict__ ds) {
-  __shared__ uint32_t sh[kWavesPerBlock];
-  const Disch<P>& d = ds[blockIdx.x];
-  State* st = d.st;
-  if (!st->sort_due) return;
-  const uint64_t n = (uint64_t)d.nc * n_tiles(d);
-  const uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
-  uint32_t run = 0;
-  for (uint32_t b0 = 0; b0 < nb; b0 += (uint32_t)kScanBlock) {
-    uint32_t v[kScanItems];
-    const uint32_t base = b0 + threadIdx.x * kScanItems;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) v[k] = (base + k < nb) ? d.bin_start[base + k] : 0u;
-    const uint32_t tot = block_excl_scan(v, sh);
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-      if (base + k < nb) d.bin_start[base + k] = v[k] + run;
-    run += tot;
-  }
-  if (threadIdx.x == 0) st->n_live_sorted = run;
-}
-
-template <class P>
 __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restrict__ ds, int D) {
   __shared__ uint32_t sh[kWavesPerBlock];
+  __shared__ uint32_t sh_off[kWavesPerBlock];
   for (int di = 0; di < D; ++di) {
     const Disch<P>& d = ds[di];
-    if (!d.st->sort_due) continue;
+    State* st = d.st;
+    if (!st->sort_due) continue;
     const uint64_t n = (uint64_t)d.nc * n_tiles(d);
     const uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
+    if (nb == 0 && blockIdx.x == 0 && threadIdx.x == 0) st->n_live_sorted = 0;
     for (uint32_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
       uint32_t v[kScanItems];
       const uint64_t base = (uint64_t)blk * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
       load_items(gptr(d.hist), base, n, v);
-      (void)block_excl_scan(v, sh);
-      const uint32_t off = d.bin_start[blk];
+      // the block's offset: the totals of the blocks before it (each block
+      // sums them itself instead of a separate pass scanning the totals)
+      uint32_t part = 0;
+      for (uint32_t b2 = threadIdx.x; b2 < blk; b2 += (uint32_t)kThreads) part += d.bin_start[b2];
+      part = wave_sum_u32(part);
+      if ((threadIdx.x & 63) == 0) sh_off[threadIdx.x >> 6] = part;
+      uint32_t cnt[kScanItems];
 #pragma unroll
-      for (int k = 0; k < kScanItems; ++k) v[k] += off;
+      for (int k = 0; k < kScanItems; ++k) cnt[k] = v[k];
+      const uint32_t tot = block_excl_scan(v, sh);  // its barriers also publish sh_off
+      uint32_t off = 0;
+#pragma unroll
+      for (int w = 0; w < kWavesPerBlock; ++w) off += sh_off[w];
+      if (blk == nb - 1 && threadIdx.x == 0) st->n_live_sorted = off + tot;
+      // an empty (cell, tile) keeps 0: no item reads its start, and the
+      // matrix is then zero again once the scatter has read the others
+#pragma unroll
+      for (int k = 0; k < kScanItems; ++k) v[k] = cnt[k] ? v[k] + off : 0u;
       store_items(gptr(d.hist), base, n, v);
+      __syncthreads();  // sh_off is rewritten for the next block
     }
   }
 }
@@ -347,6 +330,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
         }
         if (tot == 0) continue;
         uint32_t r = gptr(d.hist)[(size_t)(lo + c) * nt + t];
+        gptr(d.hist)[(size_t)(lo + c) * nt + t] = 0u;  // zero for the next sort's counts
 #pragma unroll
         for (int w = 0; w < kWavesPerBlock; ++w) {
           run[w * stride + c] = r;
@@ -429,10 +413,8 @@ __global__ void k_sort_finish(const Disch<P>* __restrict__ ds, int D) {
 template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
   const size_t lds = (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u;
-  hipLaunchKernelGGL(k_sort_clear<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
   hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_scan_reduce<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
-  hipLaunchKernelGGL(k_scan_top<P>, dim3(D), dim3(kThreads), 0, s, d_dev);
   hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
   hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
