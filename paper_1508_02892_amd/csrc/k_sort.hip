@@ -4,10 +4,12 @@
 // Tiles of kSortTile consecutive slots.  A tile's per-cell counts go to a
 // bin-major matrix hist[c * nt + t]; an exclusive scan of that matrix in its
 // flat order gives, for every (cell, tile), the first destination slot, so
-// holes are dropped and equal cells keep their order.  The matrix is zero
-// between sorts (zeroed with the discharge's buffer; the scan leaves 0 in
-// empty entries and the scatter zeroes each entry it reads), so the counts
-// write only their nonzero entries and no clearing pass is needed.  The scatter gives a
+// holes are dropped and equal cells keep their order.  The matrix and the
+// totals of its scan blocks are zero between sorts (zeroed with the
+// discharge's buffer; the scan leaves 0 in empty entries and the scatter
+// zeroes each entry it reads and the block totals), so the counts write
+// only their nonzero entries and add them to their block's total, and no
+// clearing or reduction pass is needed.  The scatter gives a
 // tile to a workgroup: each wave counts its quarter of the tile, a per-cell
 // prefix over the waves gives each wave its own cursors, and the rank of an
 // item among earlier items of the same cell comes from wave ballots over the
@@ -105,7 +107,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
       }
       for (int c = lo + lane; c <= hi; c += 64) {
         const uint32_t v = h[c];
-        if (v) hist[(size_t)c * nt + t] = v;
+        if (v) {
+          hist[(size_t)c * nt + t] = v;
+          // the total of the scan block holding this entry
+          atomicAdd(&d.bin_start[((size_t)c * nt + t) / (size_t)kScanBlock], v);
+        }
         h[c] = 0u;
       }
       if (lane == 0) {
@@ -190,24 +196,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t (&v)[kScanItems], u
 }
 
 template <class P>
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const Disch<P>* __restrict__ ds, int D) {
-  __shared__ uint32_t sh[kWavesPerBlock];
-  for (int di = 0; di < D; ++di) {
-    const Disch<P>& d = ds[di];
-    if (!d.st->sort_due) continue;
-    const uint64_t n = (uint64_t)d.nc * n_tiles(d);
-    const uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
-    for (uint32_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
-      uint32_t v[kScanItems];
-      const uint64_t base = (uint64_t)blk * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
-      load_items(gptr(d.hist), base, n, v);
-      const uint32_t tot = block_excl_scan(v, sh);
-      if (threadIdx.x == 0) d.bin_start[blk] = tot;
-    }
-  }
-}
-
-template <class P>
 __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restrict__ ds, int D) {
   __shared__ uint32_t sh[kWavesPerBlock];
   __shared__ uint32_t sh_off[kWavesPerBlock];
@@ -275,6 +263,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     Gp<P>* d_vy = gptr(d.vy[dst]);
     Gp<P>* d_vz = gptr(d.vz[dst]);
     Gp<uint32_t>* d_id = gptr(d.id[dst]);
+    {  // the scan blocks' totals are zero again for the next sort's counts
+      const uint32_t nb = (uint32_t)(((uint64_t)nc * nt + kScanBlock - 1) / kScanBlock);
+      for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nb; i += gridDim.x * kThreads) d.bin_start[i] = 0u;
+    }
     for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
       const int lo = gptr(d.tile_rng)[2 * t], hi = gptr(d.tile_rng)[2 * t + 1];
       const int span = hi - lo + 1;  // 0 for a tile of holes only
@@ -414,7 +406,6 @@ template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
   const size_t lds = (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u;
   hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
-  hipLaunchKernelGGL(k_scan_reduce<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
   hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
   hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
