@@ -439,8 +439,9 @@ __device__ __forceinline__ void wave_sync() {
 
 // Solve of the (-1, 2, -1) system, in two parts around a workgroup barrier:
 // pois_sweeps (wave 0) and pois_recover (every thread).  The right-hand side
-// is in d (row i at pois_slot(i)) and is replaced by the solution in the same
-// places; t: factor tables (LDS); red: kPoisRed doubles of LDS (the reduced
+// is in d (row i at pois_slot(i)) and is swept in place; the recovery writes
+// the solution in natural order; t: factor tables (LDS); red: kPoisRed
+// doubles of LDS (the reduced
 // system's right-hand side at [0, 2P), its solution at kTriRed, the
 // reduction's exchange buffer at 2 kTriRed).  The partitions' sweeps run one
 // partition per lane, the reduction runs rows i and i + 64 on lane i, and
@@ -490,10 +491,15 @@ __device__ void pois_sweeps(const PoisFac& f, const double* t, double* d, double
   if (v1) xr[r1] = d1 * t[f.prb + r1];
 }
 
-// The interior unknowns from their partition's end values, in place.
-__device__ void pois_recover(const PoisFac& f, const double* t, double* d, const double* red) {
-  if (f.P == 0) return;
+// The interior unknowns from their partition's end values, written in
+// natural order to x (row i at x[i]; x may not overlap d or red).
+__device__ void pois_recover(const PoisFac& f, const double* t, const double* d, const double* red,
+                             double* x) {
   const int n = f.n;
+  if (f.P == 0) {  // the plain Thomas solve left the solution in d
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = d[i];
+    return;
+  }
   const double* rx = red + kTriRed;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int p = pois_part(f, i);
@@ -509,7 +515,7 @@ __device__ void pois_recover(const PoisFac& f, const double* t, double* d, const
       const int o = (e - s + 1 - f.L0) * f.Lmax + (i - s);
       xi = fma(-t[f.xc + o], xe, fma(-t[f.xa + o], xs, d[i + p]));
     }
-    d[i + p] = xi;
+    x[i] = xi;
   }
 }
 
@@ -913,13 +919,16 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     grid_out();
   }
   __syncthreads();
-  pois_recover(f, T, X, red);
+  // the solution in natural order, over this step's deposit grid (no longer
+  // needed: the node waves stored it during the sweeps)
+  double* Phi = reinterpret_cast<double*>(CN);
+  pois_recover(f, T, X, red, Phi);
   __syncthreads();
   if (field_only)
     for (int i = tid; i < f.size; i += kFinThreads) gtab[i] = T[i];
   // E from centred differences inside and Gauss's law over the wall half
   // cells; E' = (-e/m_e) dt E rounded to the particle precision
-  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : X[pois_slot(f, j - 1)]); };
+  auto phi = [&](int j) { return j == 0 ? V : (j == nc ? 0.0 : Phi[j - 1]); };
   Gp<double>* gphi = gptr(d.phi);
   Gp<double>* gE = gptr(d.E);
   Gp<P>* gEp = gptr(d.Ep);
