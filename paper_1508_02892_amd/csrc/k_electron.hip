@@ -253,8 +253,10 @@ __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy,
   return scan(g.tab_g + (size_t)i * K);
 }
 
-// Event counts of one wave, accumulated over a segment (wave-uniform).
-struct WaveCounts {
+// Event counts of one wave, accumulated over a segment.  Each lane counts its
+// own particles (a vector add per event) instead of a ballot and popcount per
+// slot, whose 64-bit masks the compiler otherwise keeps in scalar registers.
+struct WaveCounts {  // per lane; summed over the wave once per segment
   uint32_t absl = 0, absr = 0, ovf = 0, pushed = 0;
 };
 
@@ -296,9 +298,9 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     const P on0 = s - f;
     const bool wrap = on0 == (P)1;
     const int32_t cn = cc + (stay ? (int32_t)f : 0) + (wrap ? 1 : 0);
-    wc.pushed += (uint32_t)__popcll(__ballot(live));
-    wc.absl += (uint32_t)__popcll(__ballot(live && outl));
-    wc.absr += (uint32_t)__popcll(__ballot(live && outr));
+    wc.pushed += live ? 1u : 0u;
+    wc.absl += (live && outl) ? 1u : 0u;
+    wc.absr += (live && outr) ? 1u : 0u;
     vz[j] = live ? vzn : vz[j];
     c[j] = stay ? cn : (live ? -1 : c[j]);
     off[j] = stay ? (wrap ? (P)0 : on0) : off[j];
@@ -323,7 +325,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     ch[j] = -1;
     bool ovf = false;
     if (alive[j] && u0 < g.Pmax) ch[j] = select_channel<P, KC>(g, u0, vx[j], vy[j], vz[j], ovf);
-    wc.ovf += (uint32_t)__popcll(__ballot(ovf));
+    wc.ovf += ovf ? 1u : 0u;
     // an attached electron leaves before the deposit (its charge goes to
     // the negative ion when the collision is handled); the three-channel
     // path serves only tables without attachment
@@ -500,6 +502,10 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
     for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P, 0>(d, g, lc, q, qn, wc);
     if (qn) drain<P, true>(d, g, q, qn, qn);
   }
+  wc.absl = wave_sum_u32(wc.absl);
+  wc.absr = wave_sum_u32(wc.absr);
+  wc.ovf = wave_sum_u32(wc.ovf);
+  wc.pushed = wave_sum_u32(wc.pushed);
   if ((tid & 63) == 0) {
     if (wc.absl) atomicAdd(&g.ctr[kCtrAbsL], wc.absl);
     if (wc.absr) atomicAdd(&g.ctr[kCtrAbsR], wc.absr);
