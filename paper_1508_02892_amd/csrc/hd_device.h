@@ -41,19 +41,59 @@ __device__ __forceinline__ void philox4x32_10(uint32_t x0, uint32_t x1, uint32_t
   o3 = x3;
 }
 
+// The same block for code that runs it on every lane of full waves: from
+// the third round on, hi(M*x) ^ x' ^ key is one three-input bitwise op
+// (truth table 0x96) instead of two xors.  The first two rounds keep plain
+// xors, where wave-uniform counter words and keys fold into scalar ops; so
+// does the plain version above, for code where most operands are uniform.
+__device__ __forceinline__ void philox4x32_10_v(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                uint32_t k0, uint32_t k1, uint32_t& o0,
+                                                uint32_t& o1, uint32_t& o2, uint32_t& o3) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+    uint32_t y0, y2;
+    if (r < 2) {
+      y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+      y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    } else {
+      y0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x1, k0, 0x96);
+      y2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x3, k1, 0x96);
+    }
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+  }
+  o0 = x0;
+  o1 = x1;
+  o2 = x2;
+  o3 = x3;
+}
+
 // Stream S(tag, id, step): Philox blocks with counter {id, step, b, tag} and
 // key {seed_lo, seed_hi}, words consumed in order.  The four words of the
 // current block are kept in registers as a shift queue (no dynamic indexing).
-struct Stream {
+// V selects the per-lane form of the block (for full waves of distinct ids).
+template <bool V = false>
+struct StreamT {
   uint32_t k0, k1, id, step, tag, blk;
   uint32_t w0, w1, w2, w3;
   int left;
-  __device__ __forceinline__ Stream(uint64_t seed, uint32_t tag_, uint32_t id_, uint32_t step_)
+  __device__ __forceinline__ StreamT(uint64_t seed, uint32_t tag_, uint32_t id_, uint32_t step_)
       : k0((uint32_t)seed), k1((uint32_t)(seed >> 32)), id(id_), step(step_), tag(tag_), blk(0),
         w0(0), w1(0), w2(0), w3(0), left(0) {}
   __device__ __forceinline__ uint32_t word() {
     if (left == 0) {
-      philox4x32_10(id, step, blk, tag, k0, k1, w0, w1, w2, w3);
+      if constexpr (V)
+        philox4x32_10_v(id, step, blk, tag, k0, k1, w0, w1, w2, w3);
+      else
+        philox4x32_10(id, step, blk, tag, k0, k1, w0, w1, w2, w3);
       blk += 1;
       left = 4;
     }
@@ -65,6 +105,7 @@ struct Stream {
     return r;
   }
 };
+using Stream = StreamT<false>;
 
 __device__ __forceinline__ float u01_f32(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 __device__ __forceinline__ double u01_f64(uint32_t hi, uint32_t lo) {
@@ -76,12 +117,14 @@ struct Uni;
 template <>
 struct Uni<float> {
   static constexpr int kWords = 1;
-  __device__ __forceinline__ static float get(Stream& s) { return u01_f32(s.word()); }
+  template <bool V>
+  __device__ __forceinline__ static float get(StreamT<V>& s) { return u01_f32(s.word()); }
 };
 template <>
 struct Uni<double> {
   static constexpr int kWords = 2;
-  __device__ __forceinline__ static double get(Stream& s) {
+  template <bool V>
+  __device__ __forceinline__ static double get(StreamT<V>& s) {
     const uint32_t hi = s.word();
     const uint32_t lo = s.word();
     return u01_f64(hi, lo);
@@ -518,8 +561,8 @@ __device__ __forceinline__ T load_dev(const T* p) {
 // Marsaglia (1972): a uniformly random unit vector (2a sqrt(1-q),
 // 2b sqrt(1-q), 1-2q) from a uniform point (a, b) of the unit disk,
 // q = a^2 + b^2; (0, 0, 1) after kSphereTries misses.
-template <class P>
-__device__ __forceinline__ void sphere(Stream& s, P& nx, P& ny, P& nz) {
+template <class P, bool V>
+__device__ __forceinline__ void sphere(StreamT<V>& s, P& nx, P& ny, P& nz) {
   for (int t = 0; t < kSphereTries; ++t) {
     const P a = (P)2 * Uni<P>::get(s) - (P)1;
     const P b = (P)2 * Uni<P>::get(s) - (P)1;

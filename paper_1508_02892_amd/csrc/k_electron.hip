@@ -116,7 +116,7 @@ __device__ __forceinline__ int eedf_bin(P vx, P vy, P vz, const Seg<P>& g) {
 // the negative-ion source at its position (it was not deposited).
 template <class P, bool ATT>
 __device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
-  Stream s(d.seed, kTagElectron, e.id, g.step);
+  StreamT<true> s(d.seed, kTagElectron, e.id, g.step);
   for (int w = 0; w < Uni<P>::kWords; ++w) (void)s.word();  // R used by the null test
   const int ch = (int)(e.meta & 0xFFu);
   const P vx = e.vx, vy = e.vy, vz = e.vz;
@@ -316,7 +316,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   for (int j = 0; j < 4; ++j) {
     // null-collision test with one Philox block of stream (tag 0, id, step)
     uint32_t w0, w1, w2, w3;
-    philox4x32_10(id[j], g.step, 0u, kTagElectron, g.seed_lo, g.seed_hi, w0, w1, w2, w3);
+    philox4x32_10_v(id[j], g.step, 0u, kTagElectron, g.seed_lo, g.seed_hi, w0, w1, w2, w3);
     P u0;
     if constexpr (sizeof(P) == 4)
       u0 = (P)u01_f32(w0);
