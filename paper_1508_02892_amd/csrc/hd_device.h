@@ -315,8 +315,13 @@ __device__ __forceinline__ uint64_t cic_w1u(P off) {
     return (uint64_t)rint(off * (P)4294967296.0);
 }
 
+// Relaxed device-scope add to a 64-bit word in global memory, issued as a
+// global (not flat) atomic: a flat operation counts on both the vector-memory
+// and the LDS counters, and while one is outstanding every wait for a load
+// has to be a wait for all of them.
 __device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) {
-  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+  __hip_atomic_fetch_add((Gp<unsigned long long>*)p, (unsigned long long)v,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---- tridiagonal systems --------------------------------------------------

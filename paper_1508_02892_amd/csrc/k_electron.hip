@@ -272,12 +272,30 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   int32_t c[4];
   P off[4], vx[4], vy[4], vz[4];
   uint32_t id[4];
+  // Drain the vector-memory counter (the previous chunk's stores) before the
+  // loads: with loads alone outstanding the counter retires in order, so
+  // each use below waits for its own load instead of for all of them.
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
+  gld4(g.id + i0, id);
+  __builtin_amdgcn_sched_barrier(0);  // keep the id load ahead of the others
   gld4(g.cell + i0, c);
   gld4(g.off + i0, off);
   gld4(g.vz + i0, vz);
-  gld4(g.id + i0, id);
   gld4(g.vx + i0, vx);
   gld4(g.vy + i0, vy);
+  // the null-collision numbers first: one Philox block of stream (tag 0,
+  // id, step) per slot needs only the ids, so it runs while the other
+  // particle arrays are still arriving
+  P u0[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t w0, w1, w2, w3;
+    philox4x32_10_v(id[j], g.step, 0u, kTagElectron, g.seed_lo, g.seed_hi, w0, w1, w2, w3);
+    if constexpr (sizeof(P) == 4)
+      u0[j] = (P)u01_f32(w0);
+    else
+      u0[j] = (P)u01_f64(w0, w1);
+  }
   bool alive[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -314,17 +332,10 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   int ch[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    // null-collision test with one Philox block of stream (tag 0, id, step)
-    uint32_t w0, w1, w2, w3;
-    philox4x32_10_v(id[j], g.step, 0u, kTagElectron, g.seed_lo, g.seed_hi, w0, w1, w2, w3);
-    P u0;
-    if constexpr (sizeof(P) == 4)
-      u0 = (P)u01_f32(w0);
-    else
-      u0 = (P)u01_f64(w0, w1);
+    // null-collision test
     ch[j] = -1;
     bool ovf = false;
-    if (alive[j] && u0 < g.Pmax) ch[j] = select_channel<P, KC>(g, u0, vx[j], vy[j], vz[j], ovf);
+    if (alive[j] && u0[j] < g.Pmax) ch[j] = select_channel<P, KC>(g, u0[j], vx[j], vy[j], vz[j], ovf);
     wc.ovf += ovf ? 1u : 0u;
     // an attached electron leaves before the deposit (its charge goes to
     // the negative ion when the collision is handled); the three-channel
