@@ -13,7 +13,8 @@ namespace {
 
 // Two standard normal deviates by Marsaglia's polar method from FP64
 // uniforms; (0, 0) after kSphereTries points outside the unit disk.
-__device__ __forceinline__ void normal_pair(Stream& st, double& g0, double& g1) {
+template <bool V>
+__device__ __forceinline__ void normal_pair(StreamT<V>& st, double& g0, double& g1) {
   for (int t = 0; t < kSphereTries; ++t) {
     const double a = 2.0 * Uni<double>::get(st) - 1.0;
     const double b = 2.0 * Uni<double>::get(st) - 1.0;
@@ -31,8 +32,8 @@ __device__ __forceinline__ void normal_pair(Stream& st, double& g0, double& g1) 
 
 // A Maxwellian velocity of thermal speed vth: three deviates of two polar
 // pairs (the fourth is drawn and dropped), rounded to P.
-template <class P>
-__device__ __forceinline__ void maxwellian(Stream& st, double vth, P& x, P& y, P& z) {
+template <class P, bool V>
+__device__ __forceinline__ void maxwellian(StreamT<V>& st, double vth, P& x, P& y, P& z) {
   double g0, g1, g2, g3;
   normal_pair(st, g0, g1);
   normal_pair(st, g2, g3);
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kSwarmThreads) void k_swarm_step(SwarmDev<P> w, uin
     const P top = (P)(w.ne - 1);
     const uint32_t tag = kTagSwarm + 16u * (uint32_t)f;
     for (int s = 0; s < n_steps; ++s) {
-      Stream st(w.seed, tag, (uint32_t)i, step0 + (uint32_t)s);
+      StreamT<true> st(w.seed, tag, (uint32_t)i, step0 + (uint32_t)s);  // one ion per lane
       vz = vz + acc;
       const P u0 = Uni<P>::get(st);
       if (u0 < Pmax) {
