@@ -239,7 +239,8 @@ __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy,
         hit |= (u0 < pk ? 1u : 0u) << k;
       }
     } else {
-      for (int k = 0; k < K; ++k) {
+#pragma unroll 4
+      for (int k = 0; k < K; ++k) {  // unrolled so that the row loads issue together
         const P pa = ra[k];
         const P pb = ra[K + k];
         const P pk = pa + t * (pb - pa);
