@@ -18,17 +18,30 @@
 //   philox4x32_10 ............ pinned (published known-answer vectors, rocRAND)
 //   uniform maps .............. pinned (exact bit patterns)
 //   initial load .............. pinned (exact charge, statistical moments)
-//   field solve (Poisson) ..... pinned (dense solve, linear/parabolic closed forms,
-//                               discrete Gauss law)
+//   field solve (Poisson) ..... pinned (Thomas vs dense solve, linear/parabolic
+//                               closed forms, discrete Gauss law); the
+//                               fixed-order solve within the conditioning
+//                               bound of Thomas
 //   push ...................... pinned (free streaming, uniform-field leapfrog)
 //   null-collision MCC ........ pinned (binomial collision counts, channel
 //                               fractions, energy bookkeeping, isotropy)
 //   CIC deposit ............... pinned (exact total, single-node case)
 //   DD ion fluid .............. pinned (conservation, centroid drift, Boltzmann
 //                               steady state)
-//   full ion fluid ............ pinned (closed-form relaxation, dense Thomas)
+//   full ion fluid ............ pinned (closed-form relaxation, Thomas vs dense;
+//                               fixed-order solve against Thomas)
+//   fitted transport .......... pinned (closed-form points, numpy's power; the
+//                               series log/exp within 1 ulp of numpy)
 //   secondary emission ........ pinned (mean count, cosine law)
 //   compaction + sort ......... pinned (equals a stable sort by cell)
+//   run averages .............. pinned (free-streaming closed form of the
+//                               accumulated deposit over levels 1..S; ion
+//                               content fed by ionization)
+//   literal sub-step order .... pinned (first-step difference = deposit of the
+//                               new electrons; per-step charge deficit)
+//   decision-locked replay .... pinned (its float run equals the plain float
+//                               run; the double run follows every decision)
+//   threaded particle loop .... pinned (bitwise equal runs on 1, 3, 8 threads)
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -52,6 +65,23 @@ constexpr int kMaxChannels = 16;
 constexpr int kSphereTries = 64;     // rejection-loop bound (probability of
                                      // exhausting it is (1-pi/4)^64 ~ 1e-43)
 constexpr int64_t kSeeMaxPerSide = 4096;
+
+// Arithmetic modes.  By default the oracle is the plain reference: the
+// tridiagonal systems of the field (Sec. II.D) and of Eq (2.3) by the Thomas
+// method the paper names for Eq (2.3), and x^y and ln x by the C library.
+// kFlagContract instead evaluates those three pieces in the fixed order of
+// operations that the GPU library also follows (partitioned elimination with
+// a cyclic-reduction reduced system and fused multiply-adds for the field,
+// partitioned elimination for Eq (2.3), ln and exp by written-out series), so
+// that whole runs can be compared bit for bit.  Both orders are exact up to
+// rounding; the plain path is what pins the other.
+constexpr int32_t kFlagContract = 1;
+// kFlagLiteralOrder: the electron sub-steps in the order Sec. II.A lists
+// them, push, removal, charge assignment, then the collisions, so that a
+// particle created by an ionization is first deposited one step after its
+// ion (and an attached electron is still deposited in the step it attaches).
+// The default deposits after the collisions.
+constexpr int32_t kFlagLiteralOrder = 2;
 
 thread_local std::string g_err;
 
@@ -92,7 +122,7 @@ typedef struct orc_params {
   int32_t eedf_every;
   int32_t n_eedf_bins;
   int32_t n_species;  // ion model 4 only
-  int32_t pad;
+  int32_t flags;      // kFlagContract | kFlagLiteralOrder (see below)
   int64_t n_macro;
   uint64_t seed;
   double n_gas_m3, t_gas_K, m_gas_amu;
@@ -117,7 +147,7 @@ typedef struct orc_swarm_params {
   int32_t precision;  // 0: float velocities, 1: double
   int32_t n_fields;   // independent swarms, one per E_0
   int32_t n_energy;   // rate-coefficient table points
-  int32_t pad;
+  int32_t flags;      // kFlagContract: the series logarithm in the normal deviates
   int64_t n_ions;     // ions per swarm
   int64_t id0;        // stream id of the first ion (a window of a larger swarm)
   uint64_t seed;
@@ -173,6 +203,7 @@ struct Stream {
   uint32_t ctr[4];
   uint32_t w[4];
   int pos;
+  bool narrow = false;  // double uniforms drawn like float ones (decision-locked replay)
   Stream(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step) {
     key[0] = (uint32_t)seed;
     key[1] = (uint32_t)(seed >> 32);
@@ -202,7 +233,9 @@ inline double uniform_f64(Stream& s) {
 }
 template <class P> P uniform(Stream& s);
 template <> float uniform<float>(Stream& s) { return uniform_f32(s); }
-template <> double uniform<double>(Stream& s) { return uniform_f64(s); }
+template <> double uniform<double>(Stream& s) {
+  return s.narrow ? (double)uniform_f32(s) : uniform_f64(s);
+}
 
 enum Tag : uint32_t {
   kTagElectron = 0,
@@ -255,6 +288,8 @@ struct Derived {
   int S = 1;
   std::vector<Species> sp;
   double n_gas = 0.0;
+  bool contract = false;  // kFlagContract
+  bool literal = false;   // kFlagLiteralOrder
 };
 
 bool derive(const orc_params& p, Derived& d) {
@@ -269,6 +304,12 @@ bool derive(const orc_params& p, Derived& d) {
     g_err = "invalid parameters";
     return false;
   }
+  if (p.flags & ~(kFlagContract | kFlagLiteralOrder)) {
+    g_err = "unknown flags";
+    return false;
+  }
+  d.contract = (p.flags & kFlagContract) != 0;
+  d.literal = (p.flags & kFlagLiteralOrder) != 0;
   // ion species (model 4) and the products of ionization and attachment
   d.n_gas = p.n_gas_m3;
   if (p.ion_model == 4) {
@@ -397,11 +438,13 @@ bool derive(const orc_params& p, Derived& d) {
 // Field solve (coupling through Poisson's equation, Sec. II.D).
 // rho_j = e (n_i,j - n_e,j);  -phi_{j-1} + 2 phi_j - phi_{j+1} = dz^2 rho_j / eps0
 // for the interior nodes, phi_0 = V(t_n) (powered electrode at z = 0) and
-// phi_N = 0 (grounded electrode at z = L), solved by the partitioned
-// tridiagonal elimination with the right-hand side carried by fused
-// multiply-adds.  E from centred differences inside and from
-// Gauss's law over the half cells at the walls.
+// phi_N = 0 (grounded electrode at z = L), solved by the Thomas method (or,
+// with kFlagContract, the partitioned elimination with the right-hand side
+// carried by fused multiply-adds).  E from centred differences inside and
+// from Gauss's law over the half cells at the walls.
 // ---------------------------------------------------------------------------
+void thomas(int n, const double* a, const double* b, const double* c, const double* dd,
+            double* x);
 void solve_tridiag(int n, const double* a, const double* b, const double* c, const double* d,
                    double* x);
 void solve_tridiag_fma(int n, const double* a, const double* b, const double* c,
@@ -425,7 +468,10 @@ void field_solve(const Derived& d, const int64_t* cnt, const double* ni, double 
       if (j == m) dj = dj + phi[nc];
       rhs[j - 1] = dj;
     }
-    solve_tridiag_fma(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+    if (d.contract)
+      solve_tridiag_fma(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+    else
+      thomas(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
     for (int j = 1; j <= m; ++j) phi[j] = x[j - 1];
   }
   for (int j = 1; j < nc; ++j) E[j] = (phi[j - 1] - phi[j + 1]) * d.inv_2dz;
@@ -490,22 +536,26 @@ double fit_exp(double y) {
   return std::ldexp(q, (int)k);
 }
 
-// x^y for x >= 0 (0^y = 0 for the positive exponents used here).
-double fit_pow(double x, double y) { return x > 0.0 ? fit_exp(y * fit_ln(x)) : 0.0; }
+// x^y for x >= 0 (0^y = 0 for the positive exponents used here): the C
+// library's pow, or with the contract the series above.
+double fit_pow(double x, double y, bool contract) {
+  if (!(x > 0.0)) return 0.0;
+  return contract ? fit_exp(y * fit_ln(x)) : std::pow(x, y);
+}
 
 // Table 2: mu = 1e-3 (1.18 - 0.185 |E|/E0) below E0 = 1.47e6 V/m, 1e-3 0.94
 // (E0/|E|)^0.3 from E0 on [m^2/(V s)].
-double mobility_fit(double E) {
+double mobility_fit(double E, bool contract) {
   const double a = std::fabs(E), E0 = 1.47e6;
   if (a < E0) return 1e-3 * (1.18 - 0.185 * (a / E0));
-  return 1e-3 * (0.94 * fit_pow(E0 / a, 0.3));
+  return 1e-3 * (0.94 * fit_pow(E0 / a, 0.3, contract));
 }
 
 // Table 3: nu = 1e10 (2.07 + 0.88 (|u|/u0)^1.89) below u0 = 2e3 m/s, 1e10
 // (1.54 + 1.36 |u|/u0) from u0 on [1/s].
-double nu_fit(double u) {
+double nu_fit(double u, bool contract) {
   const double a = std::fabs(u), u0 = 2e3;
-  if (a < u0) return 1e10 * (2.07 + 0.88 * fit_pow(a / u0, 1.89));
+  if (a < u0) return 1e10 * (2.07 + 0.88 * fit_pow(a / u0, 1.89, contract));
   return 1e10 * (1.54 + 1.36 * (a / u0));
 }
 
@@ -526,7 +576,7 @@ void fluid_dd(const Derived& d, double mu_const, int fit, double* ni, const doub
               double gw[2]) {
   const int nc = d.nc, nn = d.nn;
   std::vector<double> n0(ni, ni + nn), mu(nn);
-  for (int j = 0; j < nn; ++j) mu[j] = fit ? mobility_fit(E[j]) : mu_const;
+  for (int j = 0; j < nn; ++j) mu[j] = fit ? mobility_fit(E[j], d.contract) : mu_const;
   for (int j = 1; j < nc; ++j) {
     const double T = ion_temperature(d, mu[j], E[j]);
     const double D = mu[j] * T / kE;
@@ -547,7 +597,7 @@ void fluid_dd(const Derived& d, double mu_const, int fit, double* ni, const doub
 double species_mobility(const Derived& d, const Derived::Species& sp, double E) {
   const double x = (std::fabs(E) / d.n_gas) * 1e21;
   if (!(x > sp.lo)) return sp.mu[0];
-  const double u = (fit_ln(x) - sp.L0) * sp.inv_dL;
+  const double u = ((d.contract ? fit_ln(x) : std::log(x)) - sp.L0) * sp.inv_dL;
   if (!(u > 0.0)) return sp.mu[0];
   if (!(u < (double)(sp.n - 1))) return sp.mu[sp.n - 1];
   const int k = (int)u;
@@ -792,7 +842,7 @@ void fluid_full(const Derived& d, double nu_const, int fit, double* ni, const do
   std::vector<double> n0(ni, ni + nn), g0(gam, gam + nn), u(nn), T(nn), nu(nn), mu(nn);
   for (int j = 0; j < nn; ++j) {
     u[j] = (n0[j] > d.nfloor) ? g0[j] / n0[j] : 0.0;
-    nu[j] = fit ? nu_fit(u[j]) : nu_const;
+    nu[j] = fit ? nu_fit(u[j], d.contract) : nu_const;
     mu[j] = kE / (d.M * nu[j]);
     T[j] = ion_temperature(d, mu[j], E[j]);
   }
@@ -810,7 +860,10 @@ void fluid_full(const Derived& d, double nu_const, int fit, double* ni, const do
   }
   rhs[0] = rhs[0] - a[0] * gl;
   rhs[m - 1] = rhs[m - 1] - c[m - 1] * gr;
-  solve_tridiag(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+  if (d.contract)
+    solve_tridiag(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
+  else
+    thomas(m, a.data(), b.data(), c.data(), rhs.data(), x.data());
   gam[0] = gl;
   gam[nc] = gr;
   for (int j = 1; j <= m; ++j) gam[j] = x[j - 1];
@@ -842,6 +895,7 @@ struct PConst {
   int product[kMaxChannels];
   int K, ne, nbins, nc;
   std::vector<P> tab;  // (ne x K) cumulative probabilities rounded to P
+  bool narrow = false; // uniforms drawn as floats (the following run of a replay)
 };
 
 template <class P>
@@ -894,20 +948,46 @@ int push(int32_t& c, P& off, P& vz, const P* Ep, int nc, P kdz) {
 
 // Marsaglia (1972): a point on the unit sphere from a uniform point in the
 // unit disk, (2a sqrt(1-q), 2b sqrt(1-q), 1-2q) with q = a^2 + b^2.
+// Decision-locked replay: the run in float records every decision that
+// floating point takes (removal, channel, the accepted try of each disk
+// rejection, the number of secondaries, the sort order); the run in double
+// draws the same uniforms (Stream::narrow) and takes the recorded decisions
+// instead of its own, so that the two runs follow the same particles and
+// differ only by the rounding of their arithmetic.  Lock carries one
+// particle's decisions of the collision step.
+struct Lock {
+  bool follow = false;    // take the recorded decisions (else record them)
+  int channel = -1;       // -1: no collision
+  int tries[2] = {-1, -1};  // accepted try of the 1st / 2nd sphere, -1: none
+  int n_sphere = 0;       // spheres drawn so far in this collision
+  int flips = 0;          // decisions of the following run that differed
+};
+
 template <class P>
-void sphere(Stream& s, P n[3]) {
+void sphere(Stream& s, P n[3], Lock* lk = nullptr) {
+  const int idx = lk ? lk->n_sphere++ : 0;
+  const int forced = (lk && lk->follow) ? lk->tries[idx] : -2;
+  int took = -1;
   for (int t = 0; t < kSphereTries; ++t) {
     const P a = (P)2 * uniform<P>(s) - (P)1;
     const P b = (P)2 * uniform<P>(s) - (P)1;
     const P q = a * a + b * b;
-    if (q < (P)1) {
-      const P r = (P)2 * std::sqrt((P)1 - q);
+    const bool own = q < (P)1;
+    const bool take = forced == -2 ? own : t == forced;
+    if (forced != -2 && own != (t == forced) && t <= forced) lk->flips += 1;
+    if (take) {
+      P h = (P)1 - q;
+      if (h < (P)0) h = (P)0;  // a forced try a rounding outside the disk
+      const P r = (P)2 * std::sqrt(h);
       n[0] = a * r;
       n[1] = b * r;
       n[2] = (P)1 - (P)2 * q;
-      return;
+      took = t;
+      break;
     }
   }
+  if (lk && !lk->follow) lk->tries[idx] = took;
+  if (took >= 0) return;
   n[0] = (P)0;
   n[1] = (P)0;
   n[2] = (P)1;
@@ -931,11 +1011,19 @@ struct Mcc {
 // uniformly between the primary and a new electron created at the same place
 // (Sec. II.D).
 template <class P>
-Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step) {
+Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step,
+               Lock* lk = nullptr) {
   Mcc<P> r;
   Stream st(seed, kTagElectron, pt.id, step);
+  st.narrow = q.narrow;
   const P u0 = uniform<P>(st);
-  if (!(u0 < q.Pmax)) return r;
+  if (!(u0 < q.Pmax)) {
+    if (lk && lk->follow && lk->channel >= 0) lk->flips += 1;
+    if (!(lk && lk->follow && lk->channel >= 0)) {
+      if (lk) lk->channel = -1;
+      return r;
+    }
+  }
   const P v2 = (pt.vx * pt.vx + pt.vy * pt.vy) + pt.vz * pt.vz;
   const P en = q.KE * v2;
   const P s = en * q.inv_dE;
@@ -959,12 +1047,20 @@ Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step
       break;
     }
   }
+  if (lk) {
+    if (lk->follow) {
+      if (ch != lk->channel) lk->flips += 1;
+      ch = lk->channel;
+    } else {
+      lk->channel = ch;
+    }
+  }
   r.channel = ch;
   if (ch < 0) return r;
   const int kind = q.kind[ch];
   P n[3];
   if (kind == 0) {
-    sphere(st, n);
+    sphere(st, n, lk);
     const P vm = std::sqrt(v2);
     const P cosx = ((pt.vx * n[0] + pt.vy * n[1]) + pt.vz * n[2]) / vm;
     const P fac = (P)1 - q.delta_k[ch] * ((P)1 - cosx);
@@ -976,7 +1072,7 @@ Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step
     // attachment: the electron is lost to a negative ion at its position
     r.attached = true;
   } else if (kind == 1) {
-    sphere(st, n);
+    sphere(st, n, lk);
     P er = en - q.thr[ch];
     if (er < (P)0) er = (P)0;
     const P vn = std::sqrt(er * q.invKE);
@@ -984,7 +1080,7 @@ Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step
     pt.vy = vn * n[1];
     pt.vz = vn * n[2];
   } else {
-    sphere(st, n);
+    sphere(st, n, lk);
     const P us = uniform<P>(st);
     P er = en - q.thr[ch];
     if (er < (P)0) er = (P)0;
@@ -995,7 +1091,7 @@ Mcc<P> collide(Particle<P>& pt, const PConst<P>& q, uint64_t seed, uint32_t step
     pt.vy = vn * n[1];
     pt.vz = vn * n[2];
     P m2[3];
-    sphere(st, m2);
+    sphere(st, m2, lk);
     const P vc = std::sqrt(es * q.invKE);
     r.child = true;
     r.kid.c = pt.c;
@@ -1035,6 +1131,26 @@ struct Counters {
   uint64_t pushed = 0;  // particle-steps: live particles pushed
 };
 
+// Threads of the particle loop (1: the plain serial loop).
+int g_threads = 1;
+
+// The decisions of one step of a replay's recording run (see Lock), per
+// array slot where they concern a particle.
+struct Trace {
+  std::vector<int8_t> out;       // push result: 0 stays, 1 left through z = 0, 2 through z = L
+  std::vector<int8_t> chan;      // collision channel, -1 none
+  std::vector<int8_t> tries;     // accepted try of the first and second sphere, -1 none
+  int64_t see[2] = {0, 0};       // secondaries drawn per side
+  std::vector<int8_t> see_keep;  // per secondary (side s at s * 4096 + index): inside the gap
+  std::vector<uint32_t> order;   // slots kept by the sort, in their new order
+};
+
+// Decisions of a replay's following run that its own arithmetic would have
+// taken differently.
+struct Flips {
+  int64_t removal = 0, mcc = 0, emission = 0, sort = 0;
+};
+
 // ---------------------------------------------------------------------------
 // One discharge.
 // ---------------------------------------------------------------------------
@@ -1058,6 +1174,16 @@ struct Base {
   double pw_sum = 0.0;      // the current period's sum of interval powers
   double p_abs = 0.0;       // P_abs of the last completed period
   int64_t rf_periods = 0;
+  std::vector<int64_t> last_src;  // ion sources of the last step (fixed point)
+  Trace* rec = nullptr;           // replay: record this run's decisions here
+  const Trace* follow = nullptr;  // replay: take these decisions instead
+  Flips flips;
+  bool replay_failed = false;
+  int fail_replay(const char* why) {
+    g_err = why;
+    replay_failed = true;
+    return -1;
+  }
   virtual ~Base() {}
   virtual int do_step() = 0;
   virtual int64_t count() const = 0;
@@ -1141,6 +1267,7 @@ struct Discharge : Base {
     const int nn = d.nn;
     cnt.assign(nn, 0);
     ion_src.assign((size_t)d.S * nn, 0);
+    last_src.assign((size_t)d.S * nn, 0);
     ni.assign((size_t)d.S * nn, 0.0);
     gam.assign((size_t)d.S * nn, 0.0);
     ne.assign(nn, 0.0);
@@ -1220,6 +1347,11 @@ struct Discharge : Base {
     const double fl = std::floor(X);
     const double ub = uniform_f64(st);
     int64_t ns = (int64_t)fl + ((ub < X - fl) ? 1 : 0);
+    if (rec) rec->see[side] = ns;
+    if (follow && follow->see[side] != ns) {
+      flips.emission += 1;
+      ns = follow->see[side];
+    }
     if (ns > kSeeMaxPerSide) {
       ctr.see_clamped += (uint64_t)(ns - kSeeMaxPerSide);
       ns = kSeeMaxPerSide;
@@ -1251,17 +1383,29 @@ struct Discharge : Base {
       const double sc = z / d.dz;
       const double fc = std::floor(sc);
       ctr.emitted[side] += 1;
-      if (!(fc > -2147483648.0 && fc < 2147483647.0)) {  // outside any cell index
-        ctr.absorbed[side] += 1;
-        continue;
+      bool inside = fc > -2147483648.0 && fc < 2147483647.0;  // a cell index at all
+      int32_t c = 0;
+      P off = (P)0;
+      if (inside) {
+        c = (int32_t)fc;
+        off = (P)(sc - fc);
+        if (off == (P)1) {
+          c = c + 1;
+          off = (P)0;
+        }
+        inside = c >= 0 && c < d.nc;
       }
-      int32_t c = (int32_t)fc;
-      P off = (P)(sc - fc);
-      if (off == (P)1) {
-        c = c + 1;
-        off = (P)0;
+      const size_t slot = (size_t)side * (size_t)kSeeMaxPerSide + (size_t)s;
+      if (rec) rec->see_keep[slot] = inside ? 1 : 0;
+      if (follow && (follow->see_keep[slot] != 0) != inside) {
+        flips.emission += 1;
+        inside = !inside;
+        if (inside) {  // the recorded run kept it: place it at the wall
+          c = side == 0 ? 0 : d.nc - 1;
+          off = side == 0 ? (P)0 : std::nextafter((P)1, (P)0);
+        }
       }
-      if (c < 0 || c >= d.nc) {
+      if (!inside) {
         ctr.absorbed[side] += 1;
         continue;
       }
@@ -1273,6 +1417,82 @@ struct Discharge : Base {
       e.vz = (P)(side == 0 ? vz : -vz);
       e.id = 0;
       out.push_back(e);
+    }
+  }
+
+  // What one thread accumulates over its share of the particle array: the
+  // deposit and ion-source grids are integers and the counters are counts,
+  // so the sums over threads do not depend on how the array is split, and the
+  // children are concatenated in thread order, which is array order.
+  struct Local {
+    std::vector<int64_t> nxt, src;
+    std::vector<uint64_t> eedf;
+    std::vector<Particle<P>> kids;
+    Counters ctr;
+    int64_t flips_removal = 0, flips_mcc = 0;
+  };
+
+  // Sec. II.A for the slots [k0, k1) of the particle array in order: push,
+  // removal, collision and deposit of each live particle (by default the
+  // deposit follows the collision, so that an ionization's new electron is
+  // assigned in the same step as its ion; kFlagLiteralOrder assigns the
+  // charge before the collisions, as the section lists the sub-steps).
+  void electrons(size_t k0, size_t k1, uint32_t n, bool sample, Local& o) {
+    const bool lit = d.literal;
+    for (size_t k = k0; k < k1; ++k) {
+      Particle<P>& pt = parts[k];
+      if (pt.c < 0) continue;
+      o.ctr.pushed += 1;
+      int out = push<P>(pt.c, pt.off, pt.vz, Ep.data(), d.nc, q.kdz);
+      if (rec) rec->out[k] = (int8_t)out;
+      if (follow && follow->out[k] != out) {
+        o.flips_removal += 1;
+        if (follow->out[k] == 0) {  // the recorded run kept it: place it at the wall
+          pt.c = out == 1 ? 0 : d.nc - 1;
+          pt.off = out == 1 ? (P)0 : std::nextafter((P)1, (P)0);
+        }
+        out = follow->out[k];
+      }
+      if (out != 0) {
+        o.ctr.absorbed[out - 1] += 1;
+        pt.c = -1;
+        continue;
+      }
+      if (lit) deposit<P>(pt.c, pt.off, o.nxt.data());
+      Lock lk;
+      Lock* lkp = nullptr;
+      if (rec || follow) {
+        lkp = &lk;
+        if (follow) {
+          lk.follow = true;
+          lk.channel = follow->chan[k];
+          lk.tries[0] = follow->tries[2 * k];
+          lk.tries[1] = follow->tries[2 * k + 1];
+        }
+      }
+      Mcc<P> r = collide<P>(pt, q, p.seed, n, lkp);
+      if (rec) {
+        rec->chan[k] = (int8_t)lk.channel;
+        rec->tries[2 * k] = (int8_t)lk.tries[0];
+        rec->tries[2 * k + 1] = (int8_t)lk.tries[1];
+      }
+      if (follow) o.flips_mcc += lk.flips;
+      if (r.overflow) o.ctr.overflow += 1;
+      if (r.channel >= 0) o.ctr.coll[r.channel] += 1;
+      if (r.attached) {  // the negative ion takes the electron's place and charge
+        deposit<P>(pt.c, pt.off, &o.src[(size_t)q.product[r.channel] * d.nn]);
+        pt.c = -1;
+        continue;
+      }
+      if (!lit) deposit<P>(pt.c, pt.off, o.nxt.data());
+      if (sample) o.eedf[eedf_bin(pt, q)] += 1;
+      if (r.child) {
+        if (!lit) deposit<P>(r.kid.c, r.kid.off, o.nxt.data());
+        deposit<P>(r.kid.c, r.kid.off, &o.src[(size_t)q.product[r.channel] * d.nn]);
+        if (sample) o.eedf[eedf_bin(r.kid, q)] += 1;
+        o.ctr.created += 1;
+        o.kids.push_back(r.kid);
+      }
     }
   }
 
@@ -1313,36 +1533,38 @@ struct Discharge : Base {
         }
       }
     }
+    const bool sample = ((step + 1) % p.eedf_every) == 0;
+    const size_t N = parts.size();
+    if (rec) {
+      rec->out.assign(N, 0);
+      rec->chan.assign(N, -1);
+      rec->tries.assign(2 * N, -1);
+      rec->see_keep.assign(2 * (size_t)kSeeMaxPerSide, 0);
+    }
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(g_threads, (int64_t)(N / 4096 + 1)));
+    std::vector<Local> loc(T);
+    for (Local& o : loc) {
+      o.nxt.assign(d.nn, 0);
+      o.src.assign((size_t)d.S * d.nn, 0);
+      o.eedf.assign((size_t)p.n_eedf_bins + 1, 0);
+    }
+#pragma omp parallel for num_threads(T) schedule(static, 1)
+    for (int t = 0; t < T; ++t)
+      electrons(N * (size_t)t / (size_t)T, N * (size_t)(t + 1) / (size_t)T, n, sample, loc[t]);
     std::vector<int64_t> nxt(d.nn, 0);
     std::vector<Particle<P>> kids;
-    const bool sample = ((step + 1) % p.eedf_every) == 0;
-    for (size_t k = 0; k < parts.size(); ++k) {
-      Particle<P>& pt = parts[k];
-      if (pt.c < 0) continue;
-      ctr.pushed += 1;
-      const int out = push<P>(pt.c, pt.off, pt.vz, Ep.data(), d.nc, q.kdz);
-      if (out != 0) {
-        ctr.absorbed[out - 1] += 1;
-        pt.c = -1;
-        continue;
-      }
-      Mcc<P> r = collide<P>(pt, q, p.seed, n);
-      if (r.overflow) ctr.overflow += 1;
-      if (r.channel >= 0) ctr.coll[r.channel] += 1;
-      if (r.attached) {  // the negative ion takes the electron's place and charge
-        deposit<P>(pt.c, pt.off, &ion_src[(size_t)q.product[r.channel] * d.nn]);
-        pt.c = -1;
-        continue;
-      }
-      deposit<P>(pt.c, pt.off, nxt.data());
-      if (sample) eedf[eedf_bin(pt, q)] += 1;
-      if (r.child) {
-        deposit<P>(r.kid.c, r.kid.off, nxt.data());
-        deposit<P>(r.kid.c, r.kid.off, &ion_src[(size_t)q.product[r.channel] * d.nn]);
-        if (sample) eedf[eedf_bin(r.kid, q)] += 1;
-        ctr.created += 1;
-        kids.push_back(r.kid);
-      }
+    for (const Local& o : loc) {
+      for (int j = 0; j < d.nn; ++j) nxt[j] += o.nxt[j];
+      for (size_t j = 0; j < ion_src.size(); ++j) ion_src[j] += o.src[j];
+      for (size_t b = 0; b < eedf.size(); ++b) eedf[b] += o.eedf[b];
+      kids.insert(kids.end(), o.kids.begin(), o.kids.end());
+      for (int k = 0; k < kMaxChannels; ++k) ctr.coll[k] += o.ctr.coll[k];
+      for (int s = 0; s < 2; ++s) ctr.absorbed[s] += o.ctr.absorbed[s];
+      ctr.created += o.ctr.created;
+      ctr.overflow += o.ctr.overflow;
+      ctr.pushed += o.ctr.pushed;
+      flips.removal += o.flips_removal;
+      flips.mcc += o.flips_mcc;
     }
     std::vector<Particle<P>> see[2];
     emit(0, see_flux[0], n, see[0]);
@@ -1363,6 +1585,7 @@ struct Discharge : Base {
       for (int j = 0; j < d.nn; ++j) {
         const size_t k = (size_t)q2 * d.nn + j;
         ni[k] = ni[k] + (double)ion_src[k] * d.scale[j];
+        last_src[k] = ion_src[k];
         ion_src[k] = 0;
       }
     const std::vector<double> nq = net_of(ni);
@@ -1373,12 +1596,27 @@ struct Discharge : Base {
     n_acc += 1;
     step += 1;
     if (step % p.sort_every == 0) {
+      // drop the holes, then a stable sort by cell: the slots kept, in
+      // their new order (a replay's following run takes the recorded one)
+      std::vector<uint32_t> order;
+      if (follow) {
+        order = follow->order;
+        for (uint32_t k : order)
+          if (parts[k].c < 0) return fail_replay("replay order names a hole");
+      } else {
+        order.reserve(parts.size());
+        for (size_t k = 0; k < parts.size(); ++k)
+          if (parts[k].c >= 0) order.push_back((uint32_t)k);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t x, uint32_t y) { return parts[x].c < parts[y].c; });
+      }
+      if (rec) rec->order = order;
+      if (follow)
+        for (size_t i = 1; i < order.size(); ++i)
+          if (parts[order[i]].c < parts[order[i - 1]].c) flips.sort += 1;
       std::vector<Particle<P>> live;
-      live.reserve(parts.size());
-      for (auto& e : parts)
-        if (e.c >= 0) live.push_back(e);
-      std::stable_sort(live.begin(), live.end(),
-                       [](const Particle<P>& x, const Particle<P>& y) { return x.c < y.c; });
+      live.reserve(order.size());
+      for (uint32_t k : order) live.push_back(parts[k]);
       parts.swap(live);
     }
     power_step(gw[0], abs_before, emi_before);
@@ -1420,6 +1658,87 @@ struct Discharge : Base {
     }
   }
 };
+
+// Decision-locked replay of one discharge in float and in double (see
+// Lock): the float run records, the double run follows with the same
+// uniforms, so that the difference of their profiles is the rounding error
+// of the float particle arithmetic alone.
+struct Replay {
+  Base* f = nullptr;
+  Base* g = nullptr;
+  Trace tr;
+  ~Replay() {
+    delete f;
+    delete g;
+  }
+  // Give the double run the float run's state (particles converted exactly,
+  // grids, sums and counters copied), so that the next step measures the
+  // rounding of one step alone.
+  void sync() {
+    auto* F = static_cast<Discharge<float>*>(f);
+    auto* G = static_cast<Discharge<double>*>(g);
+    G->parts.resize(F->parts.size());
+    for (size_t k = 0; k < F->parts.size(); ++k) {
+      const Particle<float>& a = F->parts[k];
+      Particle<double>& b = G->parts[k];
+      b.c = a.c;
+      b.off = a.off;
+      b.vx = a.vx;
+      b.vy = a.vy;
+      b.vz = a.vz;
+      b.id = a.id;
+    }
+    G->cnt = F->cnt;
+    G->ion_src = F->ion_src;
+    G->ni = F->ni;
+    G->gam = F->gam;
+    G->ne = F->ne;
+    G->rho = F->rho;
+    G->phi = F->phi;
+    G->E = F->E;
+    G->acc_cnt = F->acc_cnt;
+    G->acc_ni = F->acc_ni;
+    G->eedf = F->eedf;
+    G->n_acc = F->n_acc;
+    G->ctr = F->ctr;
+    G->step = F->step;
+    G->next_id = F->next_id;
+    G->amp = F->amp;
+    G->V_cur = F->V_cur;
+    G->pw_sum = F->pw_sum;
+    G->p_abs = F->p_abs;
+    G->rf_periods = F->rf_periods;
+  }
+};
+
+Base* make(const orc_params* pp);
+
+Replay* make_replay(const orc_params* pp) {
+  if (!pp) return nullptr;
+  orc_params a = *pp, b = *pp;
+  a.precision = 0;
+  b.precision = 1;
+  Replay* r = new Replay();
+  r->f = make(&a);
+  r->g = r->f ? make(&b) : nullptr;
+  if (!r->g) {
+    delete r;
+    return nullptr;
+  }
+  auto* F = static_cast<Discharge<float>*>(r->f);
+  auto* G = static_cast<Discharge<double>*>(r->g);
+  G->q.narrow = true;
+  // the load sorted each run by its own cells; take the float run's order
+  std::vector<size_t> at(G->parts.size());
+  for (size_t k = 0; k < G->parts.size(); ++k) at[G->parts[k].id] = k;
+  std::vector<Particle<double>> v;
+  v.reserve(G->parts.size());
+  for (const auto& e : F->parts) v.push_back(G->parts[at[e.id]]);
+  G->parts.swap(v);
+  r->f->rec = &r->tr;
+  r->g->follow = &r->tr;
+  return r;
+}
 
 Base* make(const orc_params* pp) {
   if (!pp) {
@@ -1475,13 +1794,13 @@ Base* make(const orc_params* pp) {
 // Two standard normal deviates by Marsaglia's polar method (FP64 uniforms,
 // the logarithm above); (0, 0) if no point falls in the disk in
 // kSphereTries tries.
-void normal_pair(Stream& st, double& g0, double& g1) {
+void normal_pair(Stream& st, bool contract, double& g0, double& g1) {
   for (int t = 0; t < kSphereTries; ++t) {
     const double a = 2.0 * uniform_f64(st) - 1.0;
     const double b = 2.0 * uniform_f64(st) - 1.0;
     const double q = a * a + b * b;
     if (q < 1.0 && q > 0.0) {
-      const double f = std::sqrt((-2.0 * fit_ln(q)) / q);
+      const double f = std::sqrt((-2.0 * (contract ? fit_ln(q) : std::log(q))) / q);
       g0 = a * f;
       g1 = b * f;
       return;
@@ -1494,10 +1813,10 @@ void normal_pair(Stream& st, double& g0, double& g1) {
 // Three Cartesian components of a Maxwellian velocity of thermal speed vth
 // (two polar pairs, the fourth deviate unused), rounded to P.
 template <class P>
-void maxwellian(Stream& st, double vth, P v[3]) {
+void maxwellian(Stream& st, bool contract, double vth, P v[3]) {
   double g[4];
-  normal_pair(st, g[0], g[1]);
-  normal_pair(st, g[2], g[3]);
+  normal_pair(st, contract, g[0], g[1]);
+  normal_pair(st, contract, g[2], g[3]);
   for (int k = 0; k < 3; ++k) v[k] = (P)(vth * g[k]);
 }
 
@@ -1512,6 +1831,7 @@ struct SwarmBase {
   virtual void get(int f, void* vx, void* vy, void* vz, double* avz, double* av2) const = 0;
   virtual double sum_vz(int f) const = 0;
   virtual double sum_v2(int f) const = 0;
+  bool contract() const { return (p.flags & kFlagContract) != 0; }
 };
 
 template <class P>
@@ -1560,7 +1880,7 @@ struct Swarm : SwarmBase {
       for (int64_t i = 0; i < p.n_ions; ++i) {
         Stream st(p.seed, kTagSwarmLoad + 16u * (uint32_t)f, (uint32_t)(p.id0 + i), 0);
         P v[3];
-        maxwellian<P>(st, vth_i0, v);
+        maxwellian<P>(st, contract(), vth_i0, v);
         const size_t k = (size_t)f * (size_t)p.n_ions + (size_t)i;
         vx[k] = v[0];
         vy[k] = v[1];
@@ -1582,7 +1902,7 @@ struct Swarm : SwarmBase {
     const P u0 = uniform<P>(st);
     if (u0 < Pmax) {
       P t3[3];
-      maxwellian<P>(st, vth_n, t3);
+      maxwellian<P>(st, contract(), vth_n, t3);
       const P gx = vx[k] - t3[0], gy = vy[k] - t3[1], gz = vz[k] - t3[2];
       const P g2 = (gx * gx + gy * gy) + gz * gz;
       const P eps = KEr * g2;
@@ -1656,6 +1976,7 @@ SwarmBase* make_swarm(const orc_swarm_params* pp) {
       !pp->e0_V_m || !(pp->dt_s > 0) || !(pp->inv_de_per_eV > 0) || !(pp->m_ion_amu > 0) ||
       !(pp->m_gas_amu > 0) || !(pp->n_gas_m3 >= 0) || !(pp->t_gas_K >= 0) || !(pp->t_i0_K >= 0) ||
       pp->id0 < 0 || pp->id0 + pp->n_ions > ((int64_t)1 << 32) ||
+      (pp->flags & ~kFlagContract) != 0 ||
       (pp->precision != 0 && pp->precision != 1)) {
     g_err = "invalid swarm parameters";
     return nullptr;
@@ -1694,9 +2015,46 @@ void orc_free(void* h) { delete static_cast<Base*>(h); }
 
 int orc_step(void* h, int64_t n) {
   Base* b = static_cast<Base*>(h);
+  if (b->rec || b->follow) {
+    g_err = "a replay's runs advance through orc_replay_step";
+    return -1;
+  }
   for (int64_t i = 0; i < n; ++i)
     if (b->do_step() != 0) return -1;
   return 0;
+}
+
+void orc_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+int orc_get_threads(void) { return g_threads; }
+
+void orc_get_ion_sources(void* h, int64_t* out) {
+  const Base* b = static_cast<Base*>(h);
+  std::copy(b->last_src.begin(), b->last_src.end(), out);
+}
+
+void* orc_replay_create(const orc_params* p) { return make_replay(p); }
+void orc_replay_free(void* r) { delete static_cast<Replay*>(r); }
+// which = 0: the float run, 1: the double run (owned by the replay)
+void* orc_replay_run(void* r, int which) {
+  Replay* x = static_cast<Replay*>(r);
+  return which == 0 ? (void*)x->f : (void*)x->g;
+}
+int orc_replay_step(void* r, int64_t n) {
+  Replay* x = static_cast<Replay*>(r);
+  for (int64_t i = 0; i < n; ++i) {
+    if (x->f->do_step() != 0 || x->g->do_step() != 0) return -1;
+    if (x->g->replay_failed) return -1;
+  }
+  return 0;
+}
+void orc_replay_sync(void* r) { static_cast<Replay*>(r)->sync(); }
+// decisions the double run's own arithmetic took differently
+void orc_replay_flips(void* r, int64_t* out) {
+  const Flips& f = static_cast<Replay*>(r)->g->flips;
+  out[0] = f.removal;
+  out[1] = f.mcc;
+  out[2] = f.emission;
+  out[3] = f.sort;
 }
 
 int64_t orc_step_index(void* h) { return static_cast<Base*>(h)->step; }
@@ -1855,9 +2213,10 @@ void orc_swarm_sums(void* h, int f, double* out) {
   out[5] = (double)b->step;
 }
 // normal deviates of stream (seed, tag, id, step): n pairs
-void orc_normal_pairs(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step, int n, double* out) {
+void orc_normal_pairs(uint64_t seed, uint32_t tag, uint32_t id, uint32_t step, int n, int contract,
+                      double* out) {
   Stream st(seed, tag, id, step);
-  for (int k = 0; k < n; ++k) normal_pair(st, out[2 * k], out[2 * k + 1]);
+  for (int k = 0; k < n; ++k) normal_pair(st, contract != 0, out[2 * k], out[2 * k + 1]);
 }
 
 int orc_field_partitions(int n) { return field_partitions(n); }
@@ -1868,8 +2227,8 @@ void orc_pcr_fma(int m, const double* a, const double* b, const double* c, const
 
 double orc_fit_ln(double x) { return fit_ln(x); }
 double orc_fit_exp(double y) { return fit_exp(y); }
-double orc_mobility_fit(double E) { return mobility_fit(E); }
-double orc_nu_fit(double u) { return nu_fit(u); }
+double orc_mobility_fit(double E, int contract) { return mobility_fit(E, contract != 0); }
+double orc_nu_fit(double u, int contract) { return nu_fit(u, contract != 0); }
 
 void orc_solve_tridiag_fma(int n, const double* a, const double* b, const double* c, const double* d,
                        double* x) {

@@ -17,8 +17,9 @@ KB = 1.380649e-23
 M_HE = W.HE_AMU * 1.66053906660e-27
 
 
-def test_normal_deviates():
-    g = np.concatenate([oracle.normal_pairs(5, 4, i, 0, 50) for i in range(200)])
+@pytest.mark.parametrize("contract", [False, True])
+def test_normal_deviates(contract):
+    g = np.concatenate([oracle.normal_pairs(5, 4, i, 0, 50, contract) for i in range(200)])
     assert abs(g.mean()) < 5 / math.sqrt(len(g))
     assert abs(g.var() - 1) < 5 * math.sqrt(2 / len(g))
     assert stats.kstest(g, "norm").pvalue > 1e-4

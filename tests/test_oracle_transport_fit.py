@@ -42,8 +42,10 @@ def test_exp_matches_numpy():
     assert oracle.fit_exp(0.0) == 1.0
 
 
-def test_mobility_fit_closed_forms():
-    mu = oracle.mobility_fit
+@pytest.mark.parametrize("contract", [False, True])
+def test_mobility_fit_closed_forms(contract):
+    def mu(E):
+        return oracle.mobility_fit(E, contract)
     assert mu(0.0) == pytest.approx(1.18e-3, rel=1e-15)
     assert mu(E0 / 2) == pytest.approx(1.0875e-3, rel=1e-15)
     assert mu(np.nextafter(E0, 0.0)) == pytest.approx(0.995e-3, rel=1e-15)
@@ -55,13 +57,16 @@ def test_mobility_fit_closed_forms():
         assert mu(-E) == mu(E)
 
 
-def test_mobility_fit_matches_table_everywhere():
+@pytest.mark.parametrize("contract", [False, True])
+def test_mobility_fit_matches_table_everywhere(contract):
     for E in np.concatenate([np.linspace(0, 3 * E0, 301), np.logspace(2, 9, 141)]):
-        assert oracle.mobility_fit(E) == pytest.approx(_mu_table(E), rel=2e-15, abs=0), E
+        assert oracle.mobility_fit(E, contract) == pytest.approx(_mu_table(E), rel=2e-15, abs=0), E
 
 
-def test_nu_fit_closed_forms():
-    nu = oracle.nu_fit
+@pytest.mark.parametrize("contract", [False, True])
+def test_nu_fit_closed_forms(contract):
+    def nu(u):
+        return oracle.nu_fit(u, contract)
     assert nu(0.0) == pytest.approx(2.07e10, rel=1e-15)
     assert nu(np.nextafter(U0, 0.0)) == pytest.approx(2.95e10, rel=1e-14)
     # the high-speed branch starts at u0 with 1.54 + 1.36, a jump of 0.05 down
@@ -78,13 +83,15 @@ def test_fits_agree_with_eq_2_6_at_low_speed():
     assert E_CH / (M * oracle.mobility_fit(0.0)) == pytest.approx(oracle.nu_fit(0.0), rel=0.02)
 
 
-def test_nu_fit_matches_table_everywhere():
+@pytest.mark.parametrize("contract", [False, True])
+def test_nu_fit_matches_table_everywhere(contract):
     for u in np.concatenate([np.linspace(0, 3 * U0, 301), np.logspace(-3, 6, 181)]):
-        assert oracle.nu_fit(u) == pytest.approx(_nu_table(u), rel=2e-15, abs=0), u
+        assert oracle.nu_fit(u, contract) == pytest.approx(_nu_table(u), rel=2e-15, abs=0), u
 
 
-def _disch(model, nc=64, gap=1e-3, dt=2e-14, **kw):
-    return oracle.Oracle(W.small(ion_model=model, n_cells=nc, n_macro=0, gap_m=gap, dt_s=dt, **kw))
+def _disch(model, nc=64, gap=1e-3, dt=2e-14, contract=False, **kw):
+    return oracle.Oracle(W.small(ion_model=model, n_cells=nc, n_macro=0, gap_m=gap, dt_s=dt, **kw),
+                         contract=contract)
 
 
 @pytest.mark.parametrize("E", [4e5, 1.2e6, 3e6, 2e7])
@@ -114,13 +121,14 @@ def test_dd_fit_diffusion_uses_local_mobility():
     assert np.allclose(gam[1:-1], expect[1:-1], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("contract", [False, True])
 @pytest.mark.parametrize("E", [1e6, 7e6])
-def test_full_fit_reaches_steady_drift(E):
+def test_full_fit_reaches_steady_drift(E, contract):
     # In a uniform field and density the discrete Eq (2.3) has its fixed
     # point at u nu(u) = e E / M: one root below u0 (E = 1e6) and one above
     # (E = 7e6).
     nc, dt = 64, 2e-12
-    o = _disch(W.ION_FULL_FIT, nc=nc, dt=dt)
+    o = _disch(W.ION_FULL_FIT, nc=nc, dt=dt, contract=contract)
     M = W.HE_AMU * AMU
     target = E_CH * E / M
     u_star = brentq(lambda u: u * _nu_table(u) - target, 1.0, 1e6, xtol=1e-14, rtol=1e-15)
@@ -134,10 +142,11 @@ def test_full_fit_reaches_steady_drift(E):
     assert gam[mid] / n[mid] == pytest.approx(u_star, rel=1e-10)
 
 
+@pytest.mark.parametrize("contract", [False, True])
 @pytest.mark.parametrize("model", [W.ION_DD_FIT, W.ION_FULL_FIT])
-def test_fitted_models_conserve(model):
+def test_fitted_models_conserve(model, contract):
     nc = 80
-    o = _disch(model, nc=nc)
+    o = _disch(model, nc=nc, contract=contract)
     d = o.derived()
     rng = np.random.default_rng(7 + model)
     z = np.linspace(0, 1, nc + 1)

@@ -70,7 +70,7 @@ def compare(dev_m, dev_p, orc: oracle.Oracle, dev_ep=None):
 
 def run_pair(p, steps, chunks=None):
     dev = hd.Discharge(p)
-    orc = oracle.Oracle(p)
+    orc = oracle.Oracle(p, contract=True)
     compare(dev.moments(), dev.particles(), orc, dev.push_field())
     for n in (chunks or [steps]):
         dev.step(n)
@@ -97,7 +97,7 @@ def test_device_arithmetic_is_correctly_rounded(precision):
 def test_initial_state_matches(precision, model):
     p = W.small(precision=precision, ion_model=model, n_cells=64, n_macro=5000)
     dev = hd.Discharge(p)
-    orc = oracle.Oracle(p)
+    orc = oracle.Oracle(p, contract=True)
     compare(dev.moments(), dev.particles(), orc, dev.push_field())
 
 
@@ -189,7 +189,7 @@ def test_c2_full_size_first_steps_match():
     # 1,024 cells, 17 steps including one compaction + sort
     p = W.c2()
     dev = hd.Discharge(p)
-    orc = oracle.Oracle(p)
+    orc = oracle.Oracle(p, contract=True)
     compare(dev.moments(), dev.particles(), orc, dev.push_field())
     dev.step(17)
     orc.step(17)
@@ -204,7 +204,7 @@ def test_mixed_ion_models_in_one_batch():
     b.step(7)
     b.step(16)
     for i, p in enumerate(ps):
-        orc = oracle.Oracle(p)
+        orc = oracle.Oracle(p, contract=True)
         orc.step(23)
         compare(b.moments(i), b.particles(i), orc)
 
@@ -219,7 +219,7 @@ def test_many_chunks_per_workgroup_and_sparse_eedf():
 def test_c0_full_run_matches():
     p = W.c0()
     dev = hd.Discharge(p)
-    orc = oracle.Oracle(p)
+    orc = oracle.Oracle(p, contract=True)
     dev.step(W.C0_STEPS)
     orc.step(W.C0_STEPS)
     compare(dev.moments(), dev.particles(), orc, dev.push_field())
@@ -230,7 +230,7 @@ def test_c1_full_size_first_steps_match():
     # ion fluid, 2,048 cells; 17 steps include one compaction + sort
     p = W.c1()
     dev = hd.Discharge(p)
-    orc = oracle.Oracle(p)
+    orc = oracle.Oracle(p, contract=True)
     compare(dev.moments(), dev.particles(), orc, dev.push_field())
     dev.step(17)
     orc.step(17)
@@ -245,7 +245,7 @@ def test_batch_members_match_alone_and_oracle():
     b.step(5)
     b.step(30)
     for i, p in enumerate(ps):
-        orc = oracle.Oracle(p)
+        orc = oracle.Oracle(p, contract=True)
         orc.step(35)
         compare(b.moments(i), b.particles(i), orc)
 

@@ -47,7 +47,7 @@ def test_jobs_equal_alone_and_in_the_mix():
         alone.step(steps)
         _same(mix, alone.moments())
         if nm <= 3000:
-            o = oracle.Oracle(_job(nc, nm, seed, v))
+            o = oracle.Oracle(_job(nc, nm, seed, v), contract=True)
             o.step(steps)
             g = o.grid()
             np.testing.assert_array_equal(mix["cnt"], g["cnt"])
@@ -106,7 +106,7 @@ def test_all_ion_models_in_the_mix():
     for jid, nc, nm, seed, v, steps, model in ids:
         state, _, mix = srv.poll(jid)
         assert state == 2
-        o = oracle.Oracle(_job(nc, nm, seed, v, model))
+        o = oracle.Oracle(_job(nc, nm, seed, v, model), contract=True)
         o.step(steps)
         g = o.grid()
         for k, ok in (("cnt", "cnt"), ("n_i", "n_i"), ("E", "E"), ("gamma_i", "gamma")):

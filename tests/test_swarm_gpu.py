@@ -40,7 +40,7 @@ def test_swarm_matches_oracle(precision):
     # 3,000 ions per field: 11 full workgroups and a ragged one; 300 steps
     # cross the 256-step launch boundary; zero, low and high fields
     p = W.swarm_params([0.0, 1e6, 5e6], n_ions=3000, precision=precision)
-    dev, orc = hd.Swarm(p), oracle.Swarm(p)
+    dev, orc = hd.Swarm(p), oracle.Swarm(p, contract=True)
     _compare(dev, orc, 3)
     dev.run(300)
     orc.run(300)
@@ -54,7 +54,7 @@ def test_table_overflow_matches():
     # a table ending at 0.16 eV: many candidates fall beyond it
     p = W.swarm_params([3e6], n_ions=1000, precision=0,
                        rate_m3_s=W.he_ion_rate(64, 400.0))
-    dev, orc = hd.Swarm(p), oracle.Swarm(p)
+    dev, orc = hd.Swarm(p), oracle.Swarm(p, contract=True)
     dev.run(200, accumulate=True)
     orc.run(200, accumulate=True)
     _compare(dev, orc, 1)
@@ -75,7 +75,7 @@ def test_full_size_sampled_ions():
         for i in picks:
             # fields 0..f (the stream tag holds the field index), ion i only
             q = dict(p, n_ions=1, id0=i, e0_V_m=p["e0_V_m"][:f + 1])
-            orc = oracle.Swarm(q)
+            orc = oracle.Swarm(q, contract=True)
             orc.run(W.SWARM_WARM)
             orc.run(W.SWARM_AVG, accumulate=True)
             b = orc.ions(f)
