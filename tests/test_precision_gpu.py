@@ -1,92 +1,129 @@
-"""Precision contract of the FP32 path against the FP64 oracle.
+"""Precision contract of the FP32 device path against FP64.
 
-* Per-step error: from the same seeded load (the FP32 state is the FP64
-  state rounded), one step of the GPU in FP32 and of the oracle in FP64 must
-  give deposits, ion density, potential and field within 1e-5 of the profile's
-  scale.  (Collisions change velocities only, so one step's deposits are
-  still comparable; later steps diverge particle by particle.)
-* Statistical agreement: time-averaged electron/ion density profiles and the
-  EEDF of independent FP32 GPU and FP64 oracle ensembles agree within their
-  ensemble errors.
+* Decision-locked replay on the device: the device runs the discharge in
+  FP32; the oracle's replay runs it in float (bitwise the device's run,
+  checked at every step) and in double with every floating-point decision of
+  the float run imposed and the same uniforms drawn.  The device's profiles
+  are then compared with the double run's at every step: normwise
+  (max |x32 - x64| / max |x64|) within 1e-5 for every result, per step and
+  accumulated; element-wise (|x32 - x64| / max(|x64|, 1e-3 max|x64|)) the
+  test reports the values and bounds the densities and the potential.
+* Statistical agreement, free running: K = 8 seeds of the small plain
+  discharge (all 2,000 steps) on the device in FP32 against K = 8 other seeds
+  of the FP64 oracle.  Time-averaged electron and ion density per node by a
+  Welch t statistic with a Bonferroni bound, the EEDF per bin by its
+  seed-to-seed spread, and the mean energy within 1 %.
 """
+import math
+
 import numpy as np
 import pytest
+from scipy import stats
 
 import oracle
+from oracle.replay_errors import norm_err, rel_err
 from paper_1508_02892_amd import hd, workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5
 
-
-def _rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
-
-
-@pytest.mark.parametrize("model", [0, 1])
-def test_fp32_step_within_1e5_of_fp64_oracle(model):
-    base = dict(ion_model=model, n_cells=128, n_macro=60_000, t_e0_eV=6.0, v_amp_V=300.0,
-                phase_rad=0.7)
-    dev = hd.Discharge(W.small(precision=0, **base))
-    orc = oracle.Oracle(W.small(precision=1, **base))
-    for step in (0, 1):
-        if step:
+def test_fp32_device_against_fp64_by_locked_replay():
+    p = W.scaled(W.c1(), 1 << 18)  # 2,048 cells, full ion fluid, 262,144 electrons
+    steps = 200
+    dev = hd.Discharge(dict(p, precision=0))
+    oracle.set_threads(8)
+    try:
+        r = oracle.Replay(p, contract=True)
+        keys = {"n_e": "n_e", "n_i": "n_i", "gamma": "gamma_i", "phi": "phi", "E": "E"}
+        norm = dict.fromkeys(keys, 0.0)
+        elem = dict.fromkeys(keys, 0.0)
+        for n in range(steps):
             dev.step(1)
-            orc.step(1)
-        m = dev.moments()
-        g = orc.grid()
-        errs = {"cnt": _rel(m["cnt"], g["cnt"]), "n_i": _rel(m["n_i"], g["n_i"]),
-                "phi": _rel(m["phi"], g["phi"]), "E": _rel(m["E"], g["E"])}
-        print("FP32 vs FP64, step", step, errs)
-        for k, v in errs.items():
-            assert v <= TOL, (step, k, v)
+            r.step(1)
+            m = dev.moments()
+            gf, gd = r.f.grid(), r.d.grid()
+            np.testing.assert_array_equal(m["cnt"], gf["cnt"], err_msg="step %d" % n)
+            np.testing.assert_array_equal(m["phi"], gf["phi"], err_msg="step %d" % n)
+            for k, mk in keys.items():
+                ok = "gamma" if k == "gamma" else k
+                norm[k] = max(norm[k], norm_err(m[mk], gd[ok]))
+                elem[k] = max(elem[k], rel_err(m[mk], gd[ok]))
+    finally:
+        oracle.set_threads(1)
+    a = r.d.accum()
+    nacc = r.d.counters()["n_acc"]
+    m = dev.moments()
+    d = r.d.derived()
+    dV = np.full(r.d.nn, d["dz"])
+    dV[0] = dV[-1] = d["dz"] / 2
+    ne_avg64 = a["acc_cnt"].astype(np.float64) * (d["w"] * 2.0 ** -32) / dV / nacc
+    norm["n_e_avg"] = norm_err(m["n_e_avg"], ne_avg64)
+    norm["n_i_avg"] = norm_err(m["n_i_avg"], a["acc_ni"] / nacc)
+    elem["n_e_avg"] = rel_err(m["n_e_avg"], ne_avg64)
+    elem["n_i_avg"] = rel_err(m["n_i_avg"], a["acc_ni"] / nacc)
+    print("device FP32 vs FP64 replay over %d steps, normwise:" % steps, norm)
+    print("element-wise (floor 1e-3 of the max):", elem, "flips:", r.flips())
+    for k, v in norm.items():
+        assert v <= 1e-5, (k, v)
+    for k in ("n_i", "phi", "n_i_avg"):
+        assert elem[k] <= 1e-5, (k, elem[k])
+    dev.close()
 
 
 def _ensemble_gpu(p, seeds, steps):
+    b = hd.Batch([dict(p, seed=s, precision=0) for s in seeds])
+    b.step(steps)
     ne, ni, ee = [], [], []
-    for s in seeds:
-        d = hd.Discharge(dict(p, seed=s, precision=0))
-        d.step(steps)
-        m = d.moments()
+    for i in range(len(seeds)):
+        m = b.moments(i)
         ne.append(m["n_e_avg"])
         ni.append(m["n_i_avg"])
         ee.append(m["eedf_counts"].astype(np.float64))
-        d.close()
+    b.close()
     return np.array(ne), np.array(ni), np.array(ee)
 
 
 def _ensemble_oracle(p, seeds, steps):
     ne, ni, ee = [], [], []
-    for s in seeds:
-        o = oracle.Oracle(dict(p, seed=s, precision=1))
-        o.step(steps)
-        a = o.accum()
-        d = o.derived()
-        nn = p["n_cells"] + 1
-        dV = np.full(nn, d["dz"])
-        dV[0] = dV[-1] = d["dz"] / 2
-        n_acc = o.counters()["n_acc"]
-        ne.append(a["acc_cnt"].astype(np.float64) * (d["w"] * 2.0 ** -32) / dV / n_acc)
-        ni.append(a["acc_ni"] / n_acc)
-        ee.append(a["eedf"].astype(np.float64))
+    oracle.set_threads(8)
+    try:
+        for s in seeds:
+            o = oracle.Oracle(dict(p, seed=s, precision=1))
+            o.step(steps)
+            a = o.accum()
+            d = o.derived()
+            nn = p["n_cells"] + 1
+            dV = np.full(nn, d["dz"])
+            dV[0] = dV[-1] = d["dz"] / 2
+            n_acc = o.counters()["n_acc"]
+            ne.append(a["acc_cnt"].astype(np.float64) * (d["w"] * 2.0 ** -32) / dV / n_acc)
+            ni.append(a["acc_ni"] / n_acc)
+            ee.append(a["eedf"].astype(np.float64))
+    finally:
+        oracle.set_threads(1)
     return np.array(ne), np.array(ni), np.array(ee)
 
 
-def test_time_averages_agree_statistically():
-    p = W.small(n_cells=64, n_macro=20_000, t_e0_eV=4.0, v_amp_V=120.0, eedf_every=8,
-                load_lo=0.1, load_hi=0.9)
-    K, steps = 8, 400
+def test_time_averages_agree_statistically_full_small_case():
+    p = W.c0()
+    K, steps = 8, W.C0_STEPS
     g_ne, g_ni, g_ee = _ensemble_gpu(p, range(100, 100 + K), steps)
     o_ne, o_ni, o_ee = _ensemble_oracle(p, range(200, 200 + K), steps)
+    nodes = p["n_cells"] + 1
+    # Welch t per node; Bonferroni over both profiles at 1 % family-wise
+    alpha = 0.01 / (2 * nodes)
     for name, a, b in (("n_e", g_ne, o_ne), ("n_i", g_ni, o_ni)):
-        diff = a.mean(0) - b.mean(0)
-        se = np.sqrt(a.var(0, ddof=1) / K + b.var(0, ddof=1) / K) + 1e-9 * np.abs(b).max()
-        z = np.abs(diff) / se
-        print(name, "max z", z.max())
-        assert z.max() < 5.0, name
+        va, vb = a.var(0, ddof=1) / K, b.var(0, ddof=1) / K
+        se = np.sqrt(va + vb)
+        live = se > 1e-12 * np.abs(b).max()
+        t = np.abs(a.mean(0) - b.mean(0))[live] / se[live]
+        df = (va + vb) ** 2 / (va ** 2 / (K - 1) + vb ** 2 / (K - 1) + 1e-300)
+        bound = stats.t.ppf(1 - alpha / 2, df[live])
+        print(name, "max |t|", t.max(), "mean t^2", (t ** 2).mean())
+        assert (t <= bound).all(), name
+        # no systematic offset: the mean square of the t statistics stays near
+        # its expectation df/(df - 2) (about 1.2 at 14 degrees of freedom)
+        assert (t ** 2).mean() < 2.0, name
     # EEDF: samples within a run are correlated (the same particles every
     # eedf_every steps), so bins are compared by their seed-to-seed spread
     gf = g_ee / g_ee.sum(1, keepdims=True)
@@ -95,9 +132,10 @@ def test_time_averages_agree_statistically():
     m = (gf.mean(0) + of.mean(0)) > 1e-3
     z = np.abs(gf.mean(0) - of.mean(0))[m] / se[m]
     print("eedf bins", m.sum(), "max z", z.max())
-    assert z.max() < 5.0
+    assert z.max() < stats.t.ppf(1 - 0.01 / (2 * m.sum()), 2 * K - 2)
     centre = (np.arange(gf.shape[1] - 1) + 0.5) * p["eedf_emax_eV"] / p["n_eedf_bins"]
     ge = (gf[:, :-1] * centre).sum(1) / gf[:, :-1].sum(1)
     oe = (of[:, :-1] * centre).sum(1) / of[:, :-1].sum(1)
     print("mean energy", ge.mean(), oe.mean())
     assert abs(ge.mean() / oe.mean() - 1) < 0.01
+    assert math.isfinite(ge.mean())
