@@ -75,17 +75,72 @@ def workload(name: str):
     raise SystemExit("unknown workload " + name)
 
 
-def cpu_baseline(p, steps: int, desc: str):
+def host_info() -> dict:
+    """The host's core count and CPU model (lscpu), for the CPU baseline."""
+    info = {"nproc": os.cpu_count() or 0, "model": ""}
+    try:
+        sched = len(os.sched_getaffinity(0))
+        info["usable_cores"] = sched
+    except (AttributeError, OSError):
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                info["model"] = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(p, steps: int, desc: str, threads: int = 0):
+    """The plain oracle on this host: `steps` steps of the workload after its
+    load, on all usable cores (the particle loop split over threads with
+    per-thread integer grids, bitwise the single-thread run) and on one."""
     import oracle
-    orc = oracle.Oracle(p)
-    c0 = orc.counters()["pushed"]
-    t0 = time.perf_counter()
-    orc.step(steps)
-    dt = time.perf_counter() - t0
-    n = orc.counters()["pushed"] - c0
-    return {"value": n / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+    host = host_info()
+    all_cores = threads or host.get("usable_cores") or host["nproc"] or 1
+    rates = {}
+    for t in sorted({1, all_cores}, reverse=True):
+        oracle.set_threads(t)
+        try:
+            orc = oracle.Oracle(p)
+            c0 = orc.counters()["pushed"]
+            t0 = time.perf_counter()
+            orc.step(steps)
+            dt = time.perf_counter() - t0
+            n = orc.counters()["pushed"] - c0
+            rates[t] = (n / dt, n, dt)
+        finally:
+            oracle.set_threads(1)
+        del orc
+    v, n, dt = rates[all_cores]
+    return {"value": v, "unit": "particle-steps/s", "cores": all_cores, "kind": "oracle",
             "sample": "%s; %d steps after the initial load (%d particle-steps, %.1f s), "
-                      "single thread" % (desc, steps, n, dt)}
+                      "%d threads" % (desc, steps, n, dt, all_cores),
+            "single_thread_value": rates[1][0],
+            "host": host}
+
+
+def precision_leg() -> dict:
+    """Error of the FP32 particle arithmetic against FP64, per result, by
+    decision-locked replay on the CPU (the oracle's float run is bitwise the
+    device's): the large discharge's geometry with 65,536 electrons, 64
+    steps, each step from the float state and accumulated.  Normwise:
+    max |x32 - x64| / max |x64|; element-wise with a floor of 1e-3 of the
+    profile's largest value."""
+    from oracle.replay_errors import replay_errors
+    from paper_1508_02892_amd import workloads as W
+    p = W.scaled(W.c1(), 1 << 16)
+    th = os.cpu_count() or 1
+    out = {"sample": "2,048 cells, full ion fluid, 65,536 electrons, 64 steps"}
+    for name, per_step in (("per_step", True), ("accumulated", False)):
+        r = replay_errors(p, 64, threads=min(th, 16), per_step=per_step)
+        out[name] = {"normwise": r["normwise"], "elementwise": r["elementwise"],
+                     "flips": r["flips"]}
+    return out
 
 
 def batched(a):
@@ -267,6 +322,11 @@ def main():
     ap.add_argument("--no-separate", action="store_true")
     ap.add_argument("--electrons", type=int, default=0,
                     help="override the superparticle count (diagnostic variants)")
+    ap.add_argument("--launch", default="",
+                    help="launch shape variant,electron_groups,sort_groups,append_groups "
+                         "(0: default) instead of the autotuner")
+    ap.add_argument("--tune-steps", type=int, default=128,
+                    help="steps the autotuner may take (within the warmup); 0: no tuning")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
@@ -299,6 +359,14 @@ def main():
         p = W.scaled(p, a.electrons)
         desc += "; electrons overridden: %d" % a.electrons
     dev = hd.Discharge(p, device=0)
+    if a.launch:
+        v = [int(x) for x in a.launch.split(",")]
+        dev.set_launch(dict(zip(["electron_variant", "electron_groups", "sort_groups",
+                                 "append_groups"], v)))
+    elif a.tune_steps:
+        print("bench: autotuning over %d steps" % a.tune_steps, file=sys.stderr, flush=True)
+        dev.autotune(a.tune_steps)
+    launch = dev.get_launch()
     if a.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -350,10 +418,12 @@ def main():
                      "kernel": "k_electron", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": kms["electron"]},
         "kernel_ms": kms,
+        "launch": launch,
     }
     if not a.no_cpu:
         print("bench: cpu baseline (%d oracle steps)" % a.cpu_steps, file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(p, a.cpu_steps, desc)
+        line["fp32_vs_fp64"] = precision_leg()
     print(json.dumps(line), flush=True)
 
 

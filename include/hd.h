@@ -32,17 +32,25 @@
 extern "C" {
 #endif
 
-#define HD_ABI_VERSION 3
+#define HD_ABI_VERSION 4
 
 enum hd_status {
   HD_OK = 0,
   HD_EINVAL = -1,     /* invalid or inconsistent parameters / arguments      */
   HD_ENOMEM = -2,     /* device allocation failed or arena too small          */
   HD_EDEVICE = -3,    /* HIP runtime error (sticky for the handle)            */
-  HD_ECAPACITY = -4,  /* particle capacity exceeded; the step that overflowed
-                         was not appended, the handle refuses further steps   */
-  HD_ENUMERIC = -5,   /* non-finite field detected                            */
-  HD_ESTATE = -6      /* operation not valid in the handle's current state    */
+  HD_ECAPACITY = -4,  /* particle capacity exceeded.  One discharge: the handle
+                         is rolled back to the last complete step and
+                         hd_grow then continues the run (see hd_step).
+                         Batches and served jobs: the discharge stops.      */
+  HD_ENUMERIC = -5,   /* the field of the next step is not finite (checked at
+                         every node at the end of every step); the handle
+                         refuses further steps                               */
+  HD_ESTATE = -6,     /* operation not valid in the handle's current state    */
+  HD_ESYNC = -7       /* a bounded wait of one workgroup for another of the
+                         same launch ran out (the device did not keep the
+                         end-of-step workgroup resident beside the append
+                         workgroups); the handle refuses further steps      */
 };
 
 enum hd_precision { HD_FP32 = 0, HD_FP64 = 1 };
@@ -157,12 +165,22 @@ typedef struct hd_params {
   const hd_ion_species* species; /* n_species entries, caller-owned, copied  */
 } hd_params;
 
-/* Device context.  stream: a hipStream_t (NULL = the default stream).
- * device: HIP device ordinal. */
+/* Device context.  stream: a hipStream_t (NULL: the library creates a
+ * non-blocking stream of its own).  device: HIP device ordinal.  arena:
+ * device memory of the caller (on that device) from which a discharge or
+ * batch takes all of its device state instead of calling hipMalloc, at
+ * least the sum of hd_required_bytes of its discharges; runs past 32,768
+ * steps also take 8 bytes per step of the drive table from it, in doubling
+ * increments (HD_ENOMEM from hd_step when it is exhausted).  The caller
+ * keeps the arena alive and unused until the handle is freed.  NULL: the
+ * library allocates.  The server and the ion swarm take no arena
+ * (HD_EINVAL). */
 typedef struct hd_device_ctx {
   void* stream;
   int32_t device;
   int32_t reserved;
+  void* arena;
+  size_t arena_bytes;
 } hd_device_ctx;
 
 /* Moments of one discharge (Sec. III reports density profiles and the EEDF).
@@ -203,6 +221,10 @@ typedef struct hd_moment_set {
   double volt_amp;         /* drive amplitude U of the coming steps [V]      */
   double p_abs;            /* P_abs of the last completed RF period [W/m^2]  */
   int64_t rf_periods;      /* completed RF periods                           */
+  int64_t graph_steps;     /* steps of this handle replayed from captured
+                              launch graphs (the rest were launched one
+                              kernel at a time)                              */
+  int64_t rollbacks;       /* capacity overflows rolled back (hd_step)       */
 } hd_moment_set;
 
 typedef struct hd_batch hd_batch;
@@ -213,7 +235,11 @@ typedef struct hd_discharge hd_discharge;
 int32_t hd_abi_version(void);
 const char* hd_last_error(void);
 
-/* Device bytes one discharge with these parameters occupies (0 if invalid). */
+/* Device bytes one discharge with these parameters occupies: its state
+ * block (two particle buffers of `capacity` slots, staging, grids, tables,
+ * the drive table of the first 32,768 steps) and its descriptor (Sec. II.A
+ * particles and Secs. II.B-D grids); 0 if the parameters are invalid
+ * (hd_last_error says why). */
 size_t hd_required_bytes(const hd_params* params);
 
 /* ---- one discharge (Sec. II) -------------------------------------------- */
@@ -224,11 +250,27 @@ size_t hd_required_bytes(const hd_params* params);
 int hd_init_discharge(const hd_params* params, const hd_device_ctx* ctx, hd_discharge** out);
 
 /* Enqueues n_steps >= 0 time steps on the handle's stream and returns
- * without waiting.  Each step: ion fluid and electron push / removal /
- * null-collision MCC / CIC deposit, then emission, ion sources, averages,
- * appending, the field of the next step, and every sort_every steps a
- * compaction and stable cell sort. */
+ * without waiting.  Each step (Sec. II, the scheme's time step): the ion
+ * fluid (Eqs 2.3-2.8) and the electron push / removal / null-collision
+ * Monte Carlo / cloud-in-cell deposit (Sec. II.A), then emission and ion
+ * sources (Sec. II.D), run averages, appending, the field of the next step
+ * (Sec. II.D), and every sort_every steps a compaction and stable cell sort.
+ * Errors of earlier steps surface here or at the next synchronising call.
+ * Capacity: while a sort interval starts with the particle slots close to
+ * `capacity`, the handle keeps a checkpoint of that interval's start; if
+ * the interval then overflows, the next synchronising call restores the
+ * checkpoint, replays the steps before the overflowing one (bitwise the
+ * same run) and returns HD_ECAPACITY with the handle at the last complete
+ * step (hd_moments then reports it); hd_grow raises the capacity and
+ * hd_step continues.  Without a checkpoint the handle refuses further
+ * steps. */
 int hd_step(hd_discharge* h, int64_t n_steps);
+
+/* Raises the particle capacity of a discharge to new_capacity (>= the
+ * current one): reallocates its state block and copies the state
+ * (synchronous).  Clears a rolled-back HD_ECAPACITY.  With an arena, the
+ * new block is taken from the arena's unused part. */
+int hd_grow(hd_discharge* h, int64_t new_capacity);
 
 /* Waits for the handle's stream and fills *out (see hd_moment_set). */
 int hd_moments(hd_discharge* h, hd_moment_set* out);
@@ -244,7 +286,8 @@ int hd_get_particles(hd_discharge* h, int32_t* cell, void* off, void* vx, void* 
  * precision (float or double array of n_nodes), as used by the next push. */
 int hd_get_push_field(hd_discharge* h, void* ep);
 
-/* Releases device state.  NULL-safe. */
+/* Releases the device state of a discharge created by hd_init_discharge
+ * (the discharge of Sec. II) and waits for its stream.  NULL-safe. */
 int hd_free(hd_discharge* h);
 
 /* ---- many independent discharges in one launch per phase ---------------- */
@@ -259,6 +302,54 @@ int hd_batch_moments(hd_batch* b, int32_t index, hd_moment_set* out);
 int hd_batch_get_particles(hd_batch* b, int32_t index, int32_t* cell, void* off, void* vx,
                            void* vy, void* vz, uint32_t* id, int64_t cap, int64_t* n_out);
 int hd_batch_free(hd_batch* b);
+
+/* ---- launch shapes and the autotuner ------------------------------------- */
+
+/* How the kernels of one handle are launched.  No field changes any result:
+ * particles are processed in fixed chunks of 2,048 (eight waves of 256) and
+ * every order that reaches a result (deposit sums in 64-bit integers,
+ * children in parent order, stable sort tiles of 4,096) is independent of
+ * the launch shape, so results are bitwise identical under every valid
+ * configuration.  A value of 0 selects the default. */
+typedef struct hd_launch_config {
+  int32_t electron_variant; /* 0: each chunk of particles is loaded after the
+                               previous chunk's stores have drained (FP32:
+                               four waves per SIMD); 1: the next chunk's
+                               loads stay in flight while a chunk is worked
+                               on (FP32: three waves per SIMD)             */
+  int32_t electron_groups;  /* particle workgroups of the electron launch,
+                               1 .. 4096 (0: as many as fit on the device at
+                               once)                                       */
+  int32_t sort_groups;      /* workgroups of the sort's launches, 1 .. 65536
+                               (0: four per compute unit)                  */
+  int32_t append_groups;    /* workgroups that append new particles in the
+                               end-of-step launch, 1 .. compute units
+                               (0: a quarter of the compute units)         */
+} hd_launch_config;
+
+/* Current configuration with defaults resolved to actual counts. */
+int hd_batch_get_launch(hd_batch* b, hd_launch_config* out);
+/* Validates and applies cfg to the following steps (HD_EINVAL if out of
+ * range or if a variant cannot be resident with this batch's LDS needs). */
+int hd_batch_set_launch(hd_batch* b, const hd_launch_config* cfg);
+/* Autotuner.  Advances the batch by up to max_steps real steps (whole sort
+ * intervals, at least two), launched one kernel at a time with the
+ * candidate shapes taken in turn and timed with HIP events on the handle's
+ * stream: the electron variant and workgroup count, the sort's workgroup
+ * count and the append workgroups are each given the fastest mean.  The
+ * steps are ordinary steps of the run (the shapes do not change results).
+ * The choice is applied, written to *out (may be NULL) and kept in a
+ * process-wide cache keyed by the device and the batch's shape (precision,
+ * discharges, particle count to a power of two, largest grid, channels,
+ * ion models), which later handles with the same key start from.  If the
+ * environment names a file in HD_TUNE_CACHE, the cache is also read from
+ * and appended to that file. */
+int hd_batch_autotune(hd_batch* b, int64_t max_steps, hd_launch_config* out);
+
+/* The same for one discharge. */
+int hd_get_launch(hd_discharge* h, hd_launch_config* out);
+int hd_set_launch(hd_discharge* h, const hd_launch_config* cfg);
+int hd_autotune(hd_discharge* h, int64_t max_steps, hd_launch_config* out);
 
 /* ---- served job stream (continuous batching) ----------------------------- */
 
@@ -388,6 +479,7 @@ int hd_swarm_get_ions(hd_swarm* h, int32_t field, void* vx, void* vy, void* vz, 
 
 /* Releases device state.  NULL-safe. */
 int hd_swarm_free(hd_swarm* h);
+
 
 /* ---- diagnostics -------------------------------------------------------- */
 

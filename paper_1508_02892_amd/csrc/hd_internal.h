@@ -63,6 +63,13 @@ struct State {
   int64_t rf_periods;  // completed RF periods
   uint64_t pw_abs0;    // electrons absorbed at z = 0 up to the end of the last step
   uint64_t pw_emi0;    // secondaries emitted at z = 0 up to the end of the last step
+  // capacity checkpoints (rolling back an overflowing step)
+  int64_t error_step;  // the step in which the error arose
+  int64_t ckpt_step;   // the step at which the valid checkpoint was taken
+  int32_t ckpt_due;    // checkpoint the coming interval's start (close to capacity)
+  int32_t ckpt_valid;  // the checkpoint area holds the start of the current interval
+  uint32_t prev_n_main;  // slots in use at the last interval's start
+  uint32_t pad1;
 };
 
 // Immutable constants and device pointers of one discharge.
@@ -139,6 +146,11 @@ struct Disch {
   uint32_t* bin_start;  // scan partials
   int32_t* tile_rng;    // [2 * sort_tiles_max] lowest / highest live cell of each tile
   State* st;
+  // checkpoint area: a copy of the grid region (grid_bytes from cnt[0] on:
+  // deposits, ion sources, densities, fluxes, fields, run sums, EEDF) and,
+  // at ckpt + grid_bytes, of the State
+  unsigned char* ckpt;
+  uint64_t grid_bytes;
 };
 
 // Auxiliary ion swarm: n_fields independent swarms of n_ions ions, ion i of

@@ -12,6 +12,9 @@
 #include <memory>
 #include <mutex>
 #include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -27,15 +30,19 @@ template <class P>
 size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max);
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
-                                int nb1_max, int fluid_nn, int K_max, hipStream_t s);
+                                int nb1_max, int fluid_nn, int K_max, int variant, hipStream_t s);
 template <class P>
-int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D);
+int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D,
+                       int variant);
+int electron_variants();
 template <class P>
 hipError_t finalize_set_lds(int nn_max);
 template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s);
 template <class P>
 hipError_t sort_set_lds(int nc_max);
+template <class P>
+hipError_t launch_checkpoint(const Disch<P>* d_dev, int D, int restore, int grid, hipStream_t s);
 size_t sort_parts(size_t nc, size_t tiles);
 template <class P>
 hipError_t launch_set_steps(const Disch<P>* d_dev, int D, int64_t n, hipStream_t s);
@@ -207,7 +214,7 @@ struct Offsets {
   size_t kc, koff, kvx, kvy, kvz, chunk_kids, chunk_base, seg;
   size_t sc, soff, svx, svy, svz;
   size_t cnt[2], ion_src, ni, gam, mu, phi, E, Ep, scratch, acc_cnt, acc_ni, eedf;
-  size_t ip, tab, hist, parts, tile_rng, st, volt;
+  size_t ip, tab, hist, parts, tile_rng, st, volt, ckpt;
   size_t total;
 };
 
@@ -258,6 +265,7 @@ Offsets<P> layout(const hd_params& p, int64_t volt_len) {
   o.parts = L.take(sort_parts((size_t)p.n_cells, C / kSortTile) * 4);
   o.tile_rng = L.take(2 * (C / kSortTile) * 4);
   o.st = L.take(sizeof(State));
+  o.ckpt = L.take((o.ip - o.cnt[0]) + sizeof(State));
   o.volt = L.take((size_t)volt_len * 8);
   o.total = L.total;
   return o;
@@ -277,6 +285,7 @@ struct Host {
   unsigned char* base = nullptr;
   size_t bytes = 0;
   int64_t volt_len = 0;
+  int64_t volt_len0 = 0;     // entries of the drive table inside the block
   double* volt_dev = nullptr;
   int64_t host_step = 0;     // steps enqueued so far
   // derived FP64 values kept for moments
@@ -503,7 +512,90 @@ double volt_at(const hd_params& p, int64_t n) {
   return std::sin(two_pi_f * t + p.phase_rad);
 }
 
+// Launch shapes chosen by the autotuner, per device and batch shape, for the
+// life of the process (and, when HD_TUNE_CACHE names a file, across
+// processes: one line "key variant electron_groups sort_groups append_groups"
+// per choice, the last line of a key winning).
+std::mutex g_tune_mu;
+std::map<std::string, hd_launch_config> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("HD_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    std::istringstream ss(line);
+    std::string key;
+    hd_launch_config c{};
+    if (ss >> key >> c.electron_variant >> c.electron_groups >> c.sort_groups >> c.append_groups)
+      g_tune[key] = c;
+  }
+}
+
+bool tune_lookup(const std::string& key, hd_launch_config& out) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  out = it->second;
+  return true;
+}
+
+void tune_store(const std::string& key, const hd_launch_config& c) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  tune_load_locked();
+  g_tune[key] = c;
+  const char* path = std::getenv("HD_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << ' ' << c.electron_variant << ' ' << c.electron_groups << ' ' << c.sort_groups << ' '
+    << c.append_groups << '\n';
+}
+
 }  // namespace
+
+// Device memory of a handle: carved from the caller's arena when the device
+// context brings one (256-byte aligned, bump allocation, released with the
+// handle), else from hipMalloc.
+struct DevMem {
+  unsigned char* arena = nullptr;
+  size_t arena_bytes = 0, used = 0;
+  std::vector<void*> owned;  // hipMalloc'd blocks
+  int get(size_t n, void** p, const char* what) {
+    if (arena) {
+      const size_t o = align_up(used, 256);
+      if (o > arena_bytes || n > arena_bytes - o) {
+        *p = nullptr;
+        return fail(HD_ENOMEM, std::string("arena too small for ") + what + " (" +
+                                   std::to_string(o + n) + " bytes needed, " +
+                                   std::to_string(arena_bytes) + " given)");
+      }
+      *p = arena + o;
+      used = o + n;
+      return HD_OK;
+    }
+    if (hipMalloc(p, n) != hipSuccess) {
+      *p = nullptr;
+      return fail(HD_ENOMEM, std::string("hipMalloc failed for ") + what + " (" +
+                                 std::to_string(n) + " bytes)");
+    }
+    owned.push_back(*p);
+    return HD_OK;
+  }
+  void release(void* p) {
+    auto it = std::find(owned.begin(), owned.end(), p);
+    if (it == owned.end()) return;  // arena memory: returned with the handle
+    (void)hipFree(p);
+    owned.erase(it);
+  }
+  ~DevMem() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Batch of discharges advanced together.
@@ -516,7 +608,15 @@ struct BatchBase {
   int sort_every = 16;
   int grid_e = 0, grid_a = 0, grid_s = 0;
   int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0, fluid_nn = 0, K_max = 1;
+  int cus = 0;              // compute units of the device
+  int elec_variant = 0;     // electron kernel variant (hd_launch_config)
+  hd_launch_config launch{};  // the applied shapes, defaults resolved
+  std::string tune_key;     // the batch's key in the autotuner's cache
   int64_t host_step = 0;  // steps enqueued (all discharges advance together)
+  int64_t graph_steps = 0;  // of those, steps replayed from captured graphs
+  int64_t rollbacks = 0;    // capacity overflows rolled back
+  bool replaying = false;   // re-running the steps of a rolled-back interval
+  bool rolled_back = false; // stopped at an overflow; hd_grow clears it
   hipGraphExec_t graph = nullptr;
   bool graph_ok = true;   // capture supported
   int error = 0;
@@ -531,12 +631,10 @@ struct Batch : BatchBase {
   std::vector<Host<P>> hs;
   Disch<P>* d_desc = nullptr;
 
+  DevMem mem;
+
   ~Batch() override {
     if (graph) (void)hipGraphExecDestroy(graph);
-    for (double* p : extra) (void)hipFree(p);
-    for (auto& h : hs)
-      if (h.base) (void)hipFree(h.base);
-    if (d_desc) (void)hipFree(d_desc);
   }
 
   // Host-side preparation of one discharge (no device calls): derived
@@ -549,6 +647,7 @@ struct Batch : BatchBase {
   static void prepare_host(Host<P>& h, int64_t volt_len, Prepared& pr) {
     derive<P>(h, pr.ip, pr.tab);
     h.volt_len = volt_len;
+    h.volt_len0 = volt_len;
     load<P>(h.p, h.dd.dz, pr.ld);
     const int nn = h.dd.nn, S = h.dd.S;
     pr.ni.assign((size_t)S * nn, 0.0);
@@ -568,12 +667,12 @@ struct Batch : BatchBase {
 
   // Allocates the discharge's device block and uploads the prepared state
   // (enqueued on the stream; the caller synchronises).
-  static int upload_state(Host<P>& h, const Prepared& pr, hipStream_t stream) {
+  static int upload_state(Host<P>& h, const Prepared& pr, hipStream_t stream, DevMem& mem) {
     const Offsets<P> o = layout<P>(h.p, h.volt_len);
     h.bytes = o.total;
-    if (hipMalloc((void**)&h.base, h.bytes) != hipSuccess) {
+    if (int rc = mem.get(h.bytes, (void**)&h.base, "a discharge's state")) {
       h.base = nullptr;
-      return fail(HD_ENOMEM, "hipMalloc of " + std::to_string(h.bytes) + " bytes failed");
+      return rc;
     }
     fill_pointers(h, o);
     HD_TRY(hipMemsetAsync(h.base, 0, h.bytes, stream));
@@ -601,6 +700,11 @@ struct Batch : BatchBase {
     st.n_main = (uint32_t)N;
     st.next_id = (uint32_t)N;
     st.volt_amp = h.p.v_amp_V;
+    // the first interval is checkpointed when it starts close to capacity
+    // (the rule the sort applies to the later ones)
+    st.ckpt_due = (uint64_t)N + 2ull * kSeeMax * (uint64_t)h.p.sort_every >
+                  (uint64_t)h.p.capacity ? 1 : 0;
+    st.prev_n_main = (uint32_t)N;
     HD_TRY(hipMemcpyAsync(d.st, &st, sizeof(State), hipMemcpyHostToDevice, stream));
     return HD_OK;
   }
@@ -651,6 +755,8 @@ struct Batch : BatchBase {
     d.bin_start = (uint32_t*)(b + o.parts);
     d.tile_rng = (int32_t*)(b + o.tile_rng);
     d.st = (State*)(b + o.st);
+    d.ckpt = b + o.ckpt;
+    d.grid_bytes = o.ip - o.cnt[0];
     h.volt_dev = (double*)(b + o.volt);
     d.volt = h.volt_dev;
     d.volt_len = h.volt_len;
@@ -660,6 +766,11 @@ struct Batch : BatchBase {
     D = n;
     stream = ctx ? (hipStream_t)ctx->stream : nullptr;
     device = ctx ? ctx->device : 0;
+    if (ctx && ctx->arena) {
+      if ((uintptr_t)ctx->arena % 256 != 0) return fail(HD_EINVAL, "arena must be 256-byte aligned");
+      mem.arena = (unsigned char*)ctx->arena;
+      mem.arena_bytes = ctx->arena_bytes;
+    }
     HD_TRY(hipSetDevice(device));
     if (!stream) {  // the legacy default stream cannot be captured into a graph
       HD_TRY(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
@@ -705,24 +816,43 @@ struct Batch : BatchBase {
     if (slds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "sort LDS too large");
     HD_TRY(sort_set_lds<P>(nc_max));
     HD_TRY(finalize_set_lds<P>(nn_max));
-    int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D);
-    if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
-    const int cus = prop.multiProcessorCount;
-    grid_e = D + std::min(cus * occ, (int)kMaxSegs);
-    grid_a = std::max(1, cus / 4);
-    grid_s = cus * 4;
+    cus = prop.multiProcessorCount;
+    {
+      int64_t slots = 0;
+      for (const auto& h : hs) slots += h.p.capacity;
+      int lg = 0;
+      while (((int64_t)1 << lg) < slots) ++lg;
+      int models = 0;
+      for (const auto& h : hs) models |= 1 << h.p.ion_model;
+      std::ostringstream k;
+      k << prop.gcnArchName << ":" << cus << "/p" << precision << "/D" << D << "/n2^" << lg
+        << "/nc" << nc_max << "/K" << K_max << "/m" << models;
+      tune_key = k.str();
+    }
+    hd_launch_config lc{};
+    if (!tune_lookup(tune_key, lc) || apply_launch(lc) != HD_OK) {
+      lc = hd_launch_config{};
+      const int rc = apply_launch(lc);
+      if (rc) return rc;
+    }
     // per-discharge state
     for (int i = 0; i < n; ++i) {
       Prepared pr;
       prepare_host(hs[i], kVoltInitial, pr);
-      const int rc = upload_state(hs[i], pr, stream);
+      const int rc = upload_state(hs[i], pr, stream, mem);
       if (rc) return rc;
       HD_TRY(hipStreamSynchronize(stream));
     }
-    HD_TRY(hipMalloc((void**)&d_desc, sizeof(Disch<P>) * D));
+    if (int rc = mem.get(sizeof(Disch<P>) * D, (void**)&d_desc, "the discharge descriptors"))
+      return rc;
     HD_TRY(upload_desc());
     HD_TRY(launch_finalize<P>(d_desc, D, 1, nn_max, 0, stream));
     HD_TRY(hipStreamSynchronize(stream));
+    for (int i = 0; i < D; ++i) {  // the field of step 0 must be finite
+      State st;
+      HD_TRY(hipMemcpy(&st, hs[i].dd.st, sizeof(State), hipMemcpyDeviceToHost));
+      if (st.error) return fail(st.error, "discharge " + std::to_string(i) + ": " + error_text(st));
+    }
     return HD_OK;
   }
 
@@ -743,13 +873,11 @@ struct Batch : BatchBase {
       int64_t len = h.volt_len;
       while (len <= upto) len *= 2;
       double* nv = nullptr;
-      if (hipMalloc((void**)&nv, (size_t)len * 8) != hipSuccess)
-        return fail(HD_ENOMEM, "voltage table allocation failed");
+      // earlier tables stay allocated: launches already enqueued may read them
+      if (int rc = mem.get((size_t)len * 8, (void**)&nv, "the drive table")) return rc;
       std::vector<double> vt(len);
       for (int64_t s = 0; s < len; ++s) vt[s] = volt_at(h.p, s);
       HD_TRY(hipMemcpy(nv, vt.data(), (size_t)len * 8, hipMemcpyHostToDevice));
-      // the original table lives inside the discharge block; extra tables are kept here
-      extra.push_back(nv);
       h.volt_dev = nv;
       h.volt_len = len;
       h.dd.volt = nv;
@@ -766,10 +894,43 @@ struct Batch : BatchBase {
     }
     return HD_OK;
   }
-  std::vector<double*> extra;
 
-  hipError_t enqueue_step(bool with_sort) {
-    hipError_t e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
+  // Resolves and applies a launch configuration (0 fields: defaults).
+  int apply_launch(const hd_launch_config& in) {
+    hd_launch_config c = in;
+    if (c.electron_variant < 0 || c.electron_variant >= electron_variants())
+      return fail(HD_EINVAL, "electron_variant out of range");
+    const int occ =
+        electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, c.electron_variant);
+    if (occ < 1) return fail(HD_EINVAL, "this electron kernel variant cannot be resident");
+    if (c.electron_groups == 0) c.electron_groups = std::min(cus * occ, (int)kMaxSegs);
+    if (c.sort_groups == 0) c.sort_groups = cus * 4;
+    if (c.append_groups == 0) c.append_groups = std::max(1, cus / 4);
+    if (c.electron_groups < 1 || c.electron_groups > kMaxSegs)
+      return fail(HD_EINVAL, "electron_groups out of range");
+    if (c.sort_groups < 1 || c.sort_groups > 65536)
+      return fail(HD_EINVAL, "sort_groups out of range");
+    if (c.append_groups < 1 || c.append_groups > cus)
+      return fail(HD_EINVAL, "append_groups out of range");
+    elec_variant = c.electron_variant;
+    grid_e = D + c.electron_groups;
+    grid_s = c.sort_groups;
+    grid_a = c.append_groups;
+    launch = c;
+    if (graph) {  // captured with the old shapes
+      (void)hipGraphExecDestroy(graph);
+      graph = nullptr;
+    }
+    return HD_OK;
+  }
+
+  // One step; at an interval's start (ckpt) the checkpoint launch first.
+  hipError_t enqueue_step(bool with_sort, bool ckpt) {
+    hipError_t e = hipSuccess;
+    if (ckpt) e = launch_checkpoint<P>(d_desc, D, 0, std::max(1, cus * 2), stream);
+    if (e != hipSuccess) return e;
+    e = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max,
+                                elec_variant, stream);
     if (e != hipSuccess) return e;
     e = launch_finalize<P>(d_desc, D, 0, nn_max, grid_a, stream);
     if (e != hipSuccess) return e;
@@ -781,7 +942,8 @@ struct Batch : BatchBase {
     hipGraph_t g = nullptr;
     HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int s = 0; s < sort_every && e == hipSuccess; ++s) e = enqueue_step(s == sort_every - 1);
+    for (int s = 0; s < sort_every && e == hipSuccess; ++s)
+      e = enqueue_step(s == sort_every - 1, s == 0);
     hipError_t e2 = hipStreamEndCapture(stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
@@ -800,6 +962,8 @@ struct Batch : BatchBase {
   int step(int64_t n) {
     if (n < 0) return fail(HD_EINVAL, "n_steps < 0");
     if (error) return fail(error, "handle is in an error state");
+    if (rolled_back)
+      return fail(HD_ECAPACITY, "stopped at a capacity overflow: hd_grow first");
     if (n == 0) return HD_OK;
     const int64_t target = host_step + n;
     int rc = ensure_volt(target + 1);
@@ -815,9 +979,10 @@ struct Batch : BatchBase {
         }
         HD_TRY(hipGraphLaunch(graph, stream));
         host_step += sort_every;
+        graph_steps += sort_every;
       } else {
         const bool srt = ((host_step + 1) % sort_every) == 0;
-        HD_TRY(enqueue_step(srt));
+        HD_TRY(enqueue_step(srt, host_step % sort_every == 0 && !replaying));
         host_step += 1;
       }
     }
@@ -825,14 +990,119 @@ struct Batch : BatchBase {
   }
   bool use_graph = true;
 
+  static std::string error_text(const State& st) {
+    const std::string at = " in step " + std::to_string(st.error_step);
+    switch (st.error) {
+      case HD_ECAPACITY:
+        return "particle capacity exceeded" + at + " (no checkpoint of the interval: the handle stops)";
+      case HD_ENUMERIC:
+        return "the field after step " + std::to_string(st.error_step) + " is not finite";
+      case HD_ESYNC:
+        return "the append workgroups timed out waiting for the end-of-step workgroup";
+      default:
+        return "device reported error " + std::to_string(st.error);
+    }
+  }
+
   int sync_state(int i, State& st) {
     HD_TRY(hipStreamSynchronize(stream));
     HD_TRY(hipMemcpy(&st, hs[i].dd.st, sizeof(State), hipMemcpyDeviceToHost));
+    if (st.error == HD_ECAPACITY && D == 1 && st.ckpt_valid && st.ckpt_step <= st.error_step)
+      return rollback(st);
     if (st.error) {
       error = st.error;
-      return fail(st.error, "device reported error " + std::to_string(st.error) +
-                                " (particle capacity exceeded)");
+      return fail(st.error, error_text(st));
     }
+    return HD_OK;
+  }
+
+  // A capacity overflow of a single discharge with a checkpoint of its
+  // interval: restore the checkpoint and replay the steps before the
+  // overflowing one (the same launches, so the same run bit for bit); the
+  // handle then stands at the last complete step.
+  int rollback(State& st) {
+    const int64_t target = st.error_step;
+    HD_TRY(launch_checkpoint<P>(d_desc, D, 1, std::max(1, cus * 2), stream));
+    HD_TRY(hipStreamSynchronize(stream));
+    HD_TRY(hipMemcpy(&st, hs[0].dd.st, sizeof(State), hipMemcpyDeviceToHost));
+    host_step = st.step;
+    const int64_t n = target - host_step;
+    if (n > 0) {
+      HD_TRY(launch_set_steps<P>(d_desc, D, n, stream));
+      replaying = true;
+      hipError_t e = hipSuccess;
+      for (int64_t k = 0; k < n && e == hipSuccess; ++k) {
+        e = enqueue_step(((host_step + 1) % sort_every) == 0, false);
+        host_step += 1;
+      }
+      replaying = false;
+      HD_TRY(e);
+      HD_TRY(hipStreamSynchronize(stream));
+      HD_TRY(hipMemcpy(&st, hs[0].dd.st, sizeof(State), hipMemcpyDeviceToHost));
+    }
+    if (st.error || st.step != target) {
+      error = st.error ? st.error : HD_EDEVICE;
+      return fail(error, "rolling back the capacity overflow failed");
+    }
+    rollbacks += 1;
+    rolled_back = true;
+    return fail(HD_ECAPACITY, "particle capacity exceeded in step " + std::to_string(target) +
+                                  "; rolled back to the end of step " + std::to_string(target - 1) +
+                                  " (hd_grow, then hd_step)");
+  }
+
+  // Raises the capacity of a single discharge: a new block of the larger
+  // layout, the live state copied over, the old block released.
+  int grow(int64_t cap) {
+    if (D != 1) return fail(HD_EINVAL, "hd_grow is for single discharges");
+    if (error) return fail(error, "handle is in an error state");
+    Host<P>& h = hs[0];
+    if (cap < h.p.capacity) return fail(HD_EINVAL, "new capacity below the current one");
+    hd_params p2 = h.p;
+    p2.capacity = cap;
+    std::string why;
+    if (!validate(&p2, why)) return fail(HD_EINVAL, why);
+    HD_TRY(hipStreamSynchronize(stream));
+    State st;
+    HD_TRY(hipMemcpy(&st, h.dd.st, sizeof(State), hipMemcpyDeviceToHost));
+    const Offsets<P> oo = layout<P>(h.p, h.volt_len0), on = layout<P>(p2, h.volt_len0);
+    unsigned char* nb = nullptr;
+    if (int rc = mem.get(on.total, (void**)&nb, "the grown state")) return rc;
+    unsigned char* ob = h.base;
+    HD_TRY(hipMemsetAsync(nb, 0, on.total, stream));
+    const size_t n = st.n_main, b = (size_t)st.buf;
+    auto cp = [&](size_t dst, size_t src, size_t bytes) {
+      return hipMemcpyAsync(nb + dst, ob + src, bytes, hipMemcpyDeviceToDevice, stream);
+    };
+    HD_TRY(cp(on.cell[b], oo.cell[b], n * 4));
+    HD_TRY(cp(on.off[b], oo.off[b], n * sizeof(P)));
+    HD_TRY(cp(on.vx[b], oo.vx[b], n * sizeof(P)));
+    HD_TRY(cp(on.vy[b], oo.vy[b], n * sizeof(P)));
+    HD_TRY(cp(on.vz[b], oo.vz[b], n * sizeof(P)));
+    HD_TRY(cp(on.id[b], oo.id[b], n * 4));
+    // grids, run sums and tables keep their internal layout
+    HD_TRY(cp(on.cnt[0], oo.cnt[0], oo.hist - oo.cnt[0]));
+    HD_TRY(cp(on.volt, oo.volt, (size_t)h.volt_len0 * 8));
+    st.ckpt_valid = 0;
+    st.ckpt_due = (uint64_t)n + 2ull * kSeeMax * (uint64_t)sort_every > (uint64_t)cap ? 1 : 0;
+    HD_TRY(hipMemcpyAsync(nb + on.st, &st, sizeof(State), hipMemcpyHostToDevice, stream));
+    HD_TRY(hipStreamSynchronize(stream));
+    double* ext = h.volt_dev != (double*)(ob + oo.volt) ? h.volt_dev : nullptr;
+    h.p.capacity = cap;
+    h.base = nb;
+    h.bytes = on.total;
+    fill_pointers(h, on);
+    if (ext) {  // an extended drive table stays where it is
+      h.volt_dev = ext;
+      h.dd.volt = ext;
+    }
+    HD_TRY(upload_desc());
+    mem.release(ob);
+    if (graph) {
+      (void)hipGraphExecDestroy(graph);
+      graph = nullptr;
+    }
+    rolled_back = false;
     return HD_OK;
   }
 
@@ -841,6 +1111,8 @@ struct Batch : BatchBase {
     State st;
     const int rc = sync_state(i, st);
     const int rc2 = fill_moments(hs[i], st, m);
+    m->graph_steps = graph_steps;
+    m->rollbacks = rollbacks;
     return rc ? rc : rc2;
   }
 
@@ -868,6 +1140,8 @@ struct Batch : BatchBase {
     m->volt_amp = st.volt_amp;
     m->p_abs = st.p_abs;
     m->rf_periods = st.rf_periods;
+    m->graph_steps = 0;
+    m->rollbacks = 0;
     std::vector<int64_t> cnt(nn);
     HD_TRY(hipMemcpy(cnt.data(), d.cnt[st.cbuf], nn * 8, hipMemcpyDeviceToHost));
     int64_t tot = 0;
@@ -962,9 +1236,12 @@ struct Batch : BatchBase {
       hipEvent_t* e = &ev[(size_t)s * 8];
       const bool srt = ((host_step + 1) % sort_every) == 0;
       sorted[(size_t)s] = srt;
-      err = hipEventRecord(e[0], stream);
+      if (host_step % sort_every == 0)
+        err = launch_checkpoint<P>(d_desc, D, 0, std::max(1, cus * 2), stream);
+      if (err == hipSuccess) err = hipEventRecord(e[0], stream);
       if (err == hipSuccess)
-        err = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
+        err = launch_electron_impl<P>(d_desc, D, grid_e, tab_max, nn_max, nb1_max, fluid_nn,
+                                      K_max, elec_variant, stream);
       if (err == hipSuccess) err = hipEventRecord(e[1], stream);
       if (err == hipSuccess) err = hipEventRecord(e[2], stream);
       if (err == hipSuccess) err = launch_finalize<P>(d_desc, D, 0, nn_max, grid_a, stream);
@@ -998,6 +1275,119 @@ struct Batch : BatchBase {
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (err != hipSuccess) return fail(HD_EDEVICE, hipGetErrorString(err));
     for (int k = 0; k < 5; ++k) out_ms[k] = k == 3 ? (nsort ? acc[3] / nsort : 0.0) : acc[k] / n;
+    return HD_OK;
+  }
+
+  // The autotuner (see hd_batch_autotune).  Steps are real steps of the run,
+  // launched one kernel at a time with the candidates taken in turn.
+  int autotune(int64_t max_steps, hd_launch_config* out) {
+    if (error) return fail(error, "handle is in an error state");
+    const int64_t n = max_steps / sort_every * sort_every;
+    if (n < 2 * (int64_t)sort_every) return fail(HD_EINVAL, "max_steps below two sort intervals");
+    int rc = ensure_volt(host_step + n + 1);
+    if (rc) return rc;
+    struct Cand {
+      hd_launch_config c;
+      double ms = 0.0;
+      int runs = 0;
+    };
+    std::vector<Cand> ce, cs, ca;  // electron, sort, append candidates
+    for (int v = 0; v < electron_variants(); ++v) {
+      const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v);
+      if (occ < 1) continue;
+      const int full = std::min(cus * occ, (int)kMaxSegs);
+      for (int g : {full, std::max(1, full * 3 / 4), std::max(1, full / 2)}) {
+        hd_launch_config c = launch;
+        c.electron_variant = v;
+        c.electron_groups = g;
+        ce.push_back({c});
+      }
+    }
+    for (int f : {2, 4, 8}) {
+      hd_launch_config c = launch;
+      c.sort_groups = cus * f;
+      cs.push_back({c});
+    }
+    for (int f : {8, 4, 2}) {
+      hd_launch_config c = launch;
+      c.append_groups = std::max(1, cus / f);
+      ca.push_back({c});
+    }
+    const hd_launch_config keep = launch;
+    HD_TRY(launch_set_steps<P>(d_desc, D, n, stream));
+    std::vector<hipEvent_t> ev((size_t)n * 6);
+    for (auto& e : ev) HD_TRY(hipEventCreate(&e));
+    std::vector<int> which((size_t)n * 3, -1);
+    hipError_t err = hipSuccess;
+    int nsort = 0;
+    for (int64_t s = 0; s < n && err == hipSuccess; ++s) {
+      hipEvent_t* e = &ev[(size_t)s * 6];
+      const bool srt = ((host_step + 1) % sort_every) == 0;
+      const int ie = (int)(s % (int64_t)ce.size()), ia = (int)(s % (int64_t)ca.size());
+      const int is = srt ? nsort++ % (int)cs.size() : -1;
+      which[(size_t)s * 3] = ie;
+      which[(size_t)s * 3 + 1] = ia;
+      which[(size_t)s * 3 + 2] = is;
+      const int ge = D + ce[ie].c.electron_groups;
+      if (host_step % sort_every == 0)
+        err = launch_checkpoint<P>(d_desc, D, 0, std::max(1, cus * 2), stream);
+      if (err == hipSuccess) err = hipEventRecord(e[0], stream);
+      if (err == hipSuccess)
+        err = launch_electron_impl<P>(d_desc, D, ge, tab_max, nn_max, nb1_max, fluid_nn, K_max,
+                                      ce[ie].c.electron_variant, stream);
+      if (err == hipSuccess) err = hipEventRecord(e[1], stream);
+      if (err == hipSuccess) err = hipEventRecord(e[2], stream);
+      if (err == hipSuccess)
+        err = launch_finalize<P>(d_desc, D, 0, nn_max, ca[ia].c.append_groups, stream);
+      if (err == hipSuccess) err = hipEventRecord(e[3], stream);
+      if (err == hipSuccess) err = hipEventRecord(e[4], stream);
+      if (err == hipSuccess && srt)
+        err = launch_sort_impl<P>(d_desc, D, cs[is].c.sort_groups, nc_max, stream);
+      if (err == hipSuccess) err = hipEventRecord(e[5], stream);
+      host_step += 1;
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    for (int64_t s = 0; s < n && err == hipSuccess; ++s) {
+      hipEvent_t* e = &ev[(size_t)s * 6];
+      float t0 = 0, t1 = 0, t2 = 0;
+      err = hipEventElapsedTime(&t0, e[0], e[1]);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t1, e[2], e[3]);
+      if (err == hipSuccess) err = hipEventElapsedTime(&t2, e[4], e[5]);
+      if (err != hipSuccess) break;
+      Cand& a = ce[which[(size_t)s * 3]];
+      a.ms += t0;
+      a.runs += 1;
+      Cand& b = ca[which[(size_t)s * 3 + 1]];
+      b.ms += t1;
+      b.runs += 1;
+      if (which[(size_t)s * 3 + 2] >= 0) {
+        Cand& c = cs[which[(size_t)s * 3 + 2]];
+        c.ms += t2;
+        c.runs += 1;
+      }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (err != hipSuccess) return fail(HD_EDEVICE, hipGetErrorString(err));
+    auto best = [](const std::vector<Cand>& v) {
+      size_t b = 0;
+      double bm = 1e300;
+      for (size_t i = 0; i < v.size(); ++i)
+        if (v[i].runs && v[i].ms / v[i].runs < bm) {
+          bm = v[i].ms / v[i].runs;
+          b = i;
+        }
+      return v[b].c;
+    };
+    hd_launch_config c = keep;
+    const hd_launch_config be = best(ce), bs = best(cs), ba = best(ca);
+    c.electron_variant = be.electron_variant;
+    c.electron_groups = be.electron_groups;
+    c.sort_groups = bs.sort_groups;
+    c.append_groups = ba.append_groups;
+    rc = apply_launch(c);
+    if (rc) return rc;
+    tune_store(tune_key, launch);
+    if (out) *out = launch;
     return HD_OK;
   }
 
@@ -1063,6 +1453,7 @@ struct Server : ServerBase {
   int S = 0;
   Disch<P>* d_desc = nullptr;
   State* d_idle = nullptr;
+  DevMem mem;  // the admitted jobs' blocks (hipMalloc; released when a job retires)
   std::vector<Host<P>> hs;
   std::vector<Job*> slot_job;
   std::vector<int64_t> slot_done;  // steps completed by the job in the slot
@@ -1091,7 +1482,7 @@ struct Server : ServerBase {
     if (worker.joinable()) worker.join();
     if (graph) (void)hipGraphExecDestroy(graph);
     for (auto& h : hs)
-      if (h.base) (void)hipFree(h.base);
+      if (h.base) mem.release(h.base);
     if (d_desc) (void)hipFree(d_desc);
     if (d_idle) (void)hipFree(d_idle);
     if (own_stream) (void)hipStreamDestroy(own_stream);
@@ -1107,6 +1498,7 @@ struct Server : ServerBase {
   }
 
   int create(const hd_server_config* c, const hd_device_ctx* ctx) {
+    if (ctx && ctx->arena) return fail(HD_EINVAL, "the server takes no arena");
     cfg = *c;
     S = cfg.max_slots;
     device = ctx ? ctx->device : 0;
@@ -1128,7 +1520,7 @@ struct Server : ServerBase {
     if (lds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "slot caps exceed LDS");
     HD_TRY(sort_set_lds<P>(nc_max));
     HD_TRY(finalize_set_lds<P>(nn_max));
-    const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, S);
+    const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, S, 0);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
     grid_e = S + std::min(prop.multiProcessorCount * occ, (int)kMaxSegs);
     grid_a = std::max(1, prop.multiProcessorCount / 4);
@@ -1147,7 +1539,8 @@ struct Server : ServerBase {
     HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int s = 0; s < cfg.sort_every && e == hipSuccess; ++s) {
-      e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, stream);
+      e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, 0,
+                                  stream);
       if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, grid_a, stream);
       if (e == hipSuccess && s == cfg.sort_every - 1)
         e = launch_sort_impl<P>(d_desc, S, grid_s, nc_max, stream);
@@ -1215,7 +1608,7 @@ struct Server : ServerBase {
     h.p.channels = job->ch.empty() ? nullptr : job->ch.data();
     typename B::Prepared pr;
     B::prepare_host(h, std::max<int64_t>(kVoltInitial, job->n_steps + 2), pr);
-    int rc = B::upload_state(h, pr, stream);
+    int rc = B::upload_state(h, pr, stream, mem);
     if (rc) return rc;
     HD_TRY(hipMemcpyAsync(d_desc + slot, &h.dd, sizeof(Disch<P>), hipMemcpyHostToDevice, stream));
     HD_TRY(launch_finalize<P>(d_desc + slot, 1, 1, nn_max, 0, stream));
@@ -1259,7 +1652,7 @@ struct Server : ServerBase {
     const int rc = B::fill_moments(h, st, &m);
     const Disch<P> ie = idle_entry(slot);
     HD_TRY(hipMemcpy(d_desc + slot, &ie, sizeof(Disch<P>), hipMemcpyHostToDevice));
-    (void)hipFree(h.base);
+    mem.release(h.base);
     h.base = nullptr;
     std::lock_guard<std::mutex> g(mu);
     job->t_done = now_s();
@@ -1427,6 +1820,59 @@ bool swarm_valid(const hd_swarm_params* p, std::string& why) {
   return true;
 }
 
+// The swarm's constants from its parameters: the same formulas as the
+// oracle, FP64 then rounded to P.  Fills w's scalars, the rate table
+// tab[n_energy] = P_max nu_i / nu_max and the velocity gain acc[n_fields]
+// = e E0 dt / M; returns M.
+template <class P>
+double swarm_constants(const hd_swarm_params& p, SwarmDev<P>& w, P* tab, P* acc) {
+  const int ne = p.n_energy, D = p.n_fields;
+  const double M = p.m_ion_amu * kAmu;
+  const double MN = p.m_gas_amu * kAmu;
+  const double Mr = (M * MN) / (M + MN);
+  double nu_max = 0.0;
+  for (int i = 0; i < ne; ++i) {
+    const double nu = p.n_gas_m3 * p.rate_m3_s[i];
+    if (nu > nu_max) nu_max = nu;
+  }
+  const double Pmax = 1.0 - std::exp(-nu_max * p.dt_s);
+  for (int i = 0; i < ne; ++i) {
+    const double nu = p.n_gas_m3 * p.rate_m3_s[i];
+    tab[i] = (P)(nu_max > 0 ? Pmax * (nu / nu_max) : 0.0);
+  }
+  for (int f = 0; f < D; ++f) acc[f] = (P)(((kE * p.e0_V_m[f]) * p.dt_s) / M);
+  w.n_fields = D;
+  w.ne = ne;
+  w.n_ions = p.n_ions;
+  w.seed = p.seed;
+  w.Pmax = (P)Pmax;
+  w.KEr = (P)(Mr / (2.0 * kE));
+  w.inv_dE = (P)p.inv_de_per_eV;
+  w.m1 = (P)(M / (M + MN));
+  w.m2 = (P)(MN / (M + MN));
+  w.vth_n = std::sqrt(kKb * p.t_gas_K / MN);
+  w.vth_i0 = std::sqrt(kKb * p.t_i0_K / M);
+  return M;
+}
+
+// Results of the swarms from the ion sums over n_acc accumulated steps.
+void swarm_fill_results(const hd_swarm_params& p, double M, int64_t n_acc, const double* sums,
+                        const uint64_t* coll, const uint64_t* over, hd_swarm_result* out) {
+  const int64_t samples = n_acc * p.n_ions;
+  for (int f = 0; f < p.n_fields; ++f) {
+    const double e0 = p.e0_V_m[f];
+    hd_swarm_result& r = out[f];
+    r.e0_V_m = e0;
+    r.drift_m_s = samples ? sums[2 * f] / (double)samples : 0.0;
+    r.mean_energy_eV = samples ? ((0.5 * M) * (sums[2 * f + 1] / (double)samples)) / kE : 0.0;
+    r.mobility_m2_Vs = e0 != 0.0 ? r.drift_m_s / e0 : 0.0;
+    r.nu_s = r.drift_m_s != 0.0 ? (kE * e0) / (M * r.drift_m_s) : 0.0;
+    r.collisions = coll[f];
+    r.overflow = over[f];
+    r.samples = samples;
+  }
+}
+
 template <class P>
 struct SwarmImpl : SwarmBase {
   hd_swarm_params p{};
@@ -1456,32 +1902,9 @@ struct SwarmImpl : SwarmBase {
       HD_TRY(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
       stream = own_stream;
     }
-    // constants: the same formulas as the oracle, FP64 then rounded to P
     const int ne = p.n_energy, D = p.n_fields;
-    M = p.m_ion_amu * kAmu;
-    const double MN = p.m_gas_amu * kAmu;
-    const double Mr = (M * MN) / (M + MN);
-    std::vector<double> nu(ne);
-    double nu_max = 0.0;
-    for (int i = 0; i < ne; ++i) {
-      nu[i] = p.n_gas_m3 * rate[i];
-      if (nu[i] > nu_max) nu_max = nu[i];
-    }
-    const double Pmax = 1.0 - std::exp(-nu_max * p.dt_s);
     std::vector<P> tab(ne), acc(D);
-    for (int i = 0; i < ne; ++i) tab[i] = (P)(nu_max > 0 ? Pmax * (nu[i] / nu_max) : 0.0);
-    for (int f = 0; f < D; ++f) acc[f] = (P)(((kE * e0[f]) * p.dt_s) / M);
-    w.n_fields = D;
-    w.ne = ne;
-    w.n_ions = p.n_ions;
-    w.seed = p.seed;
-    w.Pmax = (P)Pmax;
-    w.KEr = (P)(Mr / (2.0 * kE));
-    w.inv_dE = (P)p.inv_de_per_eV;
-    w.m1 = (P)(M / (M + MN));
-    w.m2 = (P)(MN / (M + MN));
-    w.vth_n = std::sqrt(kKb * p.t_gas_K / MN);
-    w.vth_i0 = std::sqrt(kKb * p.t_i0_K / M);
+    M = swarm_constants<P>(p, w, tab.data(), acc.data());
     // one device block: a, tab, vx, vy, vz, avz, av2, coll, over, sums
     const size_t n = (size_t)D * (size_t)p.n_ions;
     size_t off = 0;
@@ -1540,18 +1963,7 @@ struct SwarmImpl : SwarmBase {
     HD_TRY(hipMemcpyAsync(coll.data(), w.coll, D * 8, hipMemcpyDeviceToHost, stream));
     HD_TRY(hipMemcpyAsync(over.data(), w.over, D * 8, hipMemcpyDeviceToHost, stream));
     HD_TRY(hipStreamSynchronize(stream));
-    const int64_t samples = n_acc * p.n_ions;
-    for (int f = 0; f < D; ++f) {
-      hd_swarm_result& r = out[f];
-      r.e0_V_m = e0[f];
-      r.drift_m_s = samples ? sums[2 * f] / (double)samples : 0.0;
-      r.mean_energy_eV = samples ? ((0.5 * M) * (sums[2 * f + 1] / (double)samples)) / kE : 0.0;
-      r.mobility_m2_Vs = e0[f] != 0.0 ? r.drift_m_s / e0[f] : 0.0;
-      r.nu_s = r.drift_m_s != 0.0 ? (kE * e0[f]) / (M * r.drift_m_s) : 0.0;
-      r.collisions = coll[f];
-      r.overflow = over[f];
-      r.samples = samples;
-    }
+    swarm_fill_results(p, M, n_acc, sums.data(), coll.data(), over.data(), out);
     return HD_OK;
   }
 
@@ -1734,6 +2146,11 @@ int hd_profile_steps(hd_discharge* h, int64_t n, double* out_ms) {
   return dispatch(h->b.impl, [&](auto* x) { return x->profile(n, out_ms); });
 }
 
+int hd_grow(hd_discharge* h, int64_t new_capacity) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl, [&](auto* x) { return x->grow(new_capacity); });
+}
+
 int hd_free(hd_discharge* h) {
   if (!h) return HD_OK;
   delete h->b.impl;
@@ -1775,6 +2192,40 @@ int hd_batch_free(hd_batch* b) {
   return HD_OK;
 }
 
+int hd_batch_get_launch(hd_batch* b, hd_launch_config* out) {
+  if (!b || !out) return hd::fail(HD_EINVAL, "null handle or output");
+  *out = b->impl->launch;
+  return HD_OK;
+}
+
+int hd_batch_set_launch(hd_batch* b, const hd_launch_config* cfg) {
+  if (!b || !cfg) return hd::fail(HD_EINVAL, "null handle or configuration");
+  if (b->impl->error) return hd::fail(b->impl->error, "handle is in an error state");
+  return dispatch(b->impl, [&](auto* x) { return x->apply_launch(*cfg); });
+}
+
+int hd_batch_autotune(hd_batch* b, int64_t max_steps, hd_launch_config* out) {
+  if (!b) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(b->impl, [&](auto* x) { return x->autotune(max_steps, out); });
+}
+
+int hd_get_launch(hd_discharge* h, hd_launch_config* out) {
+  if (!h || !out) return hd::fail(HD_EINVAL, "null handle or output");
+  *out = h->b.impl->launch;
+  return HD_OK;
+}
+
+int hd_set_launch(hd_discharge* h, const hd_launch_config* cfg) {
+  if (!h || !cfg) return hd::fail(HD_EINVAL, "null handle or configuration");
+  if (h->b.impl->error) return hd::fail(h->b.impl->error, "handle is in an error state");
+  return dispatch(h->b.impl, [&](auto* x) { return x->apply_launch(*cfg); });
+}
+
+int hd_autotune(hd_discharge* h, int64_t max_steps, hd_launch_config* out) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl, [&](auto* x) { return x->autotune(max_steps, out); });
+}
+
 int hd_diag_arith(int32_t precision, int64_t n, const void* a, const void* b, void* out,
                   const hd_device_ctx* ctx) {
   if (n < 0 || (n > 0 && (!a || !b || !out))) return hd::fail(HD_EINVAL, "bad arguments");
@@ -1814,6 +2265,7 @@ int hd_swarm_create(const hd_swarm_params* params, const hd_device_ctx* ctx, hd_
   if (!out) return hd::fail(HD_EINVAL, "null out");
   std::string why;
   if (!hd::swarm_valid(params, why)) return hd::fail(HD_EINVAL, why);
+  if (ctx && ctx->arena) return hd::fail(HD_EINVAL, "the ion swarm takes no arena");
   hd::SwarmBase* b = nullptr;
   int rc;
   if (params->precision == HD_FP32) {

@@ -261,29 +261,64 @@ struct WaveCounts {  // per lane; summed over the wave once per segment
   uint32_t absl = 0, absr = 0, ovf = 0, pushed = 0;
 };
 
+// One thread's four slots of a chunk as loaded from HBM.
+template <class P>
+struct ChunkIn {
+  uint32_t id[4];
+  int32_t c[4];
+  P off[4], vz[4], vx[4], vy[4];
+};
+
+// Issue the loads of chunk lc (ids first: the random numbers need only them).
+template <class P>
+__device__ __forceinline__ void chunk_load(const Seg<P>& g, uint32_t lc, ChunkIn<P>& x) {
+  const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)threadIdx.x * (uint32_t)kPerThread;
+  gld4(g.id + i0, x.id);
+  __builtin_amdgcn_sched_barrier(0);  // keep the id load ahead of the others
+  gld4(g.cell + i0, x.c);
+  gld4(g.off + i0, x.off);
+  gld4(g.vz + i0, x.vz);
+  gld4(g.vx + i0, x.vx);
+  gld4(g.vy + i0, x.vy);
+}
+
 // One wave's 256 slots of a chunk: push, removal and write-back, then the
 // null-collision test and channel, the deposit at x^{n+1}; collisions are
 // queued.  No workgroup barrier is involved.
-template <class P, int KC>
+//
+// How a chunk's particle data arrive (the vector-memory counter counts
+// loads and stores alike, and while both are outstanding the compiler can
+// only wait for all of them):
+// LM = 0: the previous chunk's stores drain first, then this chunk's loads
+//   go out, so that each use below waits for its own load (the ids first,
+//   for the random numbers) instead of for all of them.
+// LM = 1: nx holds this chunk's loads, issued one chunk earlier; after the
+//   drain (which now also covers them) the next chunk's loads go out into
+//   nx, so that they arrive while this chunk computes (24 more registers).
+// LM = 2: the loads go out at once, without the drain; the first use waits
+//   for them and for the previous chunk's stores together, so that the
+//   store and load latencies overlap.
+template <class P, int KC, int LM>
 __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEntry<P>* q,
-                           uint32_t& qn, WaveCounts& wc) {
+                           uint32_t& qn, WaveCounts& wc, ChunkIn<P>& nx, bool more) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
-  int32_t c[4];
-  P off[4], vx[4], vy[4], vz[4];
-  uint32_t id[4];
-  // Drain the vector-memory counter (the previous chunk's stores) before the
-  // loads: with loads alone outstanding the counter retires in order, so
-  // each use below waits for its own load instead of for all of them.
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt untouched
-  gld4(g.id + i0, id);
-  __builtin_amdgcn_sched_barrier(0);  // keep the id load ahead of the others
-  gld4(g.cell + i0, c);
-  gld4(g.off + i0, off);
-  gld4(g.vz + i0, vz);
-  gld4(g.vx + i0, vx);
-  gld4(g.vy + i0, vy);
+  if constexpr (LM != 2) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) only
+  ChunkIn<P> in;
+  if constexpr (LM == 1) {
+    in = nx;
+    if (more) chunk_load<P>(g, lc + 1u, nx);
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+    chunk_load<P>(g, lc, in);
+  }
+  int32_t(&c)[4] = in.c;
+  P(&off)[4] = in.off;
+  P(&vx)[4] = in.vx;
+  P(&vy)[4] = in.vy;
+  P(&vz)[4] = in.vz;
+  const uint32_t(&id)[4] = in.id;
   // the null-collision numbers first: one Philox block of stream (tag 0,
   // id, step) per slot needs only the ids, so it runs while the other
   // particle arrays are still arriving
@@ -452,7 +487,7 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* 
 // Chunks [lc0, lc1) of discharge d by particle workgroup pb; chunk0 is the
 // launch-wide index of the discharge's first chunk and per the chunks per
 // workgroup.
-template <class P>
+template <class P, int LM>
 __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned char* smem,
                         const Lds& L, uint32_t pb, uint32_t chunk0, uint32_t per) {
   const int tid = threadIdx.x, wv = tid >> 6;
@@ -507,11 +542,15 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   __syncthreads();
   uint32_t qn = 0;
   WaveCounts wc;
+  ChunkIn<P> nx;
+  if constexpr (LM == 1) chunk_load<P>(g, lc0, nx);
   if (g.K == 3 && g.att_mask == 0) {  // elastic, excitation, ionization: unrolled
-    for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P, 3>(d, g, lc, q, qn, wc);
+    for (uint32_t lc = lc0; lc < lc1; ++lc)
+      wave_chunk<P, 3, LM>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
     if (qn) drain<P, false>(d, g, q, qn, qn);
   } else {
-    for (uint32_t lc = lc0; lc < lc1; ++lc) wave_chunk<P, 0>(d, g, lc, q, qn, wc);
+    for (uint32_t lc = lc0; lc < lc1; ++lc)
+      wave_chunk<P, 0, LM>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
     if (qn) drain<P, true>(d, g, q, qn, qn);
   }
   wc.absl = wave_sum_u32(wc.absl);
@@ -800,7 +839,7 @@ __device__ void fluid_species(const Disch<P>& d, double* lds) {
 
 // Blocks [0, D) advance the ion fluid of discharge blockIdx.x; the others
 // share the particle chunks of all discharges in contiguous segments.
-template <class P>
+template <class P, int LM>
 __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, const ElecArgs& a,
                                               unsigned char* smem) {
   const int D = a.D;
@@ -840,7 +879,7 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
     const uint32_t end = min(g1, pre[di + 1]);
     // a discharge with no chunks (idle, or an empty slot whose descriptor
     // has no arrays) between two others gets no segment
-    if (end > g0) segment<P>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
+    if (end > g0) segment<P, LM>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
     g0 = end;
     ++di;
   }
@@ -850,24 +889,55 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
 __global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
 k_electron_f32(const Disch<float>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float>(ds, a, smem);
+  electron_body<float, 0>(ds, a, smem);
+}
+
+// FP32 with the next chunk's loads in flight: at most 168 VGPRs, three
+// waves per SIMD.
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(3))) void
+k_electron_f32_pf(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float, 1>(ds, a, smem);
+}
+
+// FP32, loads issued without draining the stores first.
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_electron_f32_nd(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float, 2>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64(const Disch<double>* __restrict__ ds,
                                                                ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double>(ds, a, smem);
+  electron_body<double, 0>(ds, a, smem);
 }
 
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64_pf(
+    const Disch<double>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double, 1>(ds, a, smem);
+}
+
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd(
+    const Disch<double>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double, 2>(ds, a, smem);
+}
+
+// Kernel variants of one precision, by how the particle data arrive (LM).
+constexpr int kElecVariants = 3;
 template <class P>
 struct ElecKernel;
 template <>
 struct ElecKernel<float> {
-  static constexpr auto fn = k_electron_f32;
+  static constexpr decltype(&k_electron_f32) fn[kElecVariants] = {k_electron_f32, k_electron_f32_pf,
+                                                                  k_electron_f32_nd};
 };
 template <>
 struct ElecKernel<double> {
-  static constexpr auto fn = k_electron_f64;
+  static constexpr decltype(&k_electron_f64) fn[kElecVariants] = {k_electron_f64, k_electron_f64_pf,
+                                                                  k_electron_f64_nd};
 };
 
 }  // namespace
@@ -880,32 +950,38 @@ size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid
 
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
-                                int nb1_max, int fluid_nn, int K_max, hipStream_t s) {
+                                int nb1_max, int fluid_nn, int K_max, int variant, hipStream_t s) {
   ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max};
   const size_t lds = lds_layout<P>(a).total;
-  hipLaunchKernelGGL(ElecKernel<P>::fn, dim3(grid), dim3(kElecThreads), lds, s, d_dev, a);
+  if (variant < 0 || variant >= kElecVariants) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ElecKernel<P>::fn[variant], dim3(grid), dim3(kElecThreads), lds, s, d_dev, a);
   return hipGetLastError();
 }
 
 template <class P>
-int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D) {
+int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D,
+                       int variant) {
   int nb = 0;
+  if (variant < 0 || variant >= kElecVariants) return 0;
   const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max);
-  if (hipFuncSetAttribute((const void*)ElecKernel<P>::fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)lds) != hipSuccess)
+  const void* fn = (const void*)ElecKernel<P>::fn[variant];
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ElecKernel<P>::fn, kElecThreads, lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ElecKernel<P>::fn[variant], kElecThreads,
+                                                   lds) != hipSuccess)
     return 0;
   return nb;
 }
 
+int electron_variants() { return kElecVariants; }
+
 template size_t electron_lds_bytes<float>(int, int, int, int, int, int);
 template size_t electron_lds_bytes<double>(int, int, int, int, int, int);
 template hipError_t launch_electron_impl<float>(const Disch<float>*, int, int, int, int, int, int,
-                                                int, hipStream_t);
+                                                int, int, hipStream_t);
 template hipError_t launch_electron_impl<double>(const Disch<double>*, int, int, int, int, int,
-                                                 int, int, hipStream_t);
-template int electron_occupancy<float>(int, int, int, int, int, int);
-template int electron_occupancy<double>(int, int, int, int, int, int);
+                                                 int, int, int, hipStream_t);
+template int electron_occupancy<float>(int, int, int, int, int, int, int);
+template int electron_occupancy<double>(int, int, int, int, int, int, int);
 
 }  // namespace hd

@@ -591,7 +591,7 @@ __device__ void append_blocks(const Disch<P>* __restrict__ ds, int D) {
     }
     __syncthreads();
     if (!ok) {
-      if (tid == 0) st->error = -6;  // the end-of-step workgroup never published
+      if (tid == 0) st->error = HD_ESYNC;  // the end-of-step workgroup never published
     } else if (st->append_pending) {
       const int buf = st->buf;
       const uint32_t nch = st->n_chunks, base = st->append_base, idb = st->id_base;
@@ -891,8 +891,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     st->n_kids = n_kids;
     st->n_see[0] = ns0;
     st->n_see[1] = ns1;
-    if ((uint64_t)n_main + n_app > (uint64_t)d.capacity) {
-      st->error = -4;  // capacity exceeded
+    const bool over = (uint64_t)n_main + n_app > (uint64_t)d.capacity;
+    if (over) {
+      // capacity exceeded: nothing is appended and no sort follows, so that
+      // the other particle buffer still holds the interval's checkpoint
+      st->error = HD_ECAPACITY;
+      st->error_step = step0;
       st->append_pending = 0;
       st->steps_left = 0;
     } else {
@@ -905,7 +909,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
     }
     st->step = step1;
     atomicAdd(reinterpret_cast<unsigned long long*>(&d.st->n_acc), 1ull);
-    st->sort_due = (step1 % d.sort_every) == 0 ? 1 : 0;
+    st->sort_due = (!over && (step1 % d.sort_every) == 0) ? 1 : 0;
     st->cbuf = cur;
     // the append workgroups of this launch may start (they run beside the
     // field solve)
@@ -934,6 +938,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
   Gp<P>* gEp = gptr(d.Ep);
   Gp<int64_t>* nxt = gptr(d.cnt[cur ^ 1]);
   double e0_new = 0.0;
+  bool finite = true;
 #pragma unroll
   for (int u = 0; u < kNodeSlots; ++u) {
     const int j = nt + u * kNodeThreads;
@@ -945,6 +950,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
         e = (phi(nc - 1) - phi(nc)) * d.inv_dz + rho_n * d.hdz_eps;
       else
         e = (phi(j - 1) - phi(j + 1)) * d.inv_2dz;
+      finite = finite && (fabs(e) <= 1.7976931348623157e308);  // false for inf and NaN
       gphi[j] = phi(j);
       gE[j] = e;
       gEp[j] = (P)(d.qm_dt * e);
@@ -965,6 +971,13 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const Disch<P>* __rest
       sum = 0.0;
     }
     st->pw_sum = sum;
+  }
+  // a field that is not finite stops the discharge: its next steps idle
+  if (__syncthreads_or(finite ? 0 : 1) && tid == 0) {
+    st->error = HD_ENUMERIC;
+    st->error_step = step0;
+    st->steps_left = 0;
+    st->sort_due = 0;
   }
 }
 

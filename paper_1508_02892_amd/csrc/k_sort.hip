@@ -396,8 +396,78 @@ __global__ void k_sort_finish(const Disch<P>* __restrict__ ds, int D) {
   State* st = ds[di].st;
   if (!st->sort_due) return;
   st->buf ^= 1;
-  st->n_main = st->n_live_sorted;
+  const uint32_t n = st->n_live_sorted;
+  st->n_main = n;
   st->sort_due = 0;
+  // Checkpoint the coming interval's start when it is close to capacity:
+  // fewer free slots than twice the last interval's growth plus the most
+  // secondaries an interval can bring (both walls, every step).
+  const Disch<P>& d = ds[di];
+  const uint32_t grow = n > st->prev_n_main ? n - st->prev_n_main : 0u;
+  const uint64_t need = 2ull * grow + 2ull * (uint64_t)kSeeMax * (uint64_t)d.sort_every;
+  st->ckpt_due = (uint64_t)n + need > (uint64_t)d.capacity ? 1 : 0;
+  st->prev_n_main = n;
+}
+
+// Checkpoint of a sort interval's start, for rolling back an interval whose
+// particles overflow the capacity.  restore = 0, at the interval's start:
+// when the start was judged close to capacity (ckpt_due) the live slots
+// [0, n_main) go to the other particle buffer (unused until the interval's
+// sort, which an overflow suppresses) and the grid region and the State to
+// the checkpoint area; otherwise the checkpoint is marked invalid.
+// restore = 1: everything is copied back (the State last, by one thread;
+// the copies read only the checkpoint).
+template <class P>
+__global__ __launch_bounds__(kThreads) void k_checkpoint(const Disch<P>* __restrict__ ds, int D,
+                                                         int restore) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t gsz = (size_t)gridDim.x * blockDim.x;
+  for (int di = 0; di < D; ++di) {
+    const Disch<P>& d = ds[di];
+    State* st = d.st;
+    State* sv = reinterpret_cast<State*>(d.ckpt + d.grid_bytes);
+    if (!restore) {
+      if (st->error) continue;  // an interval stopped by an error keeps its checkpoint
+      if (!(st->ckpt_due && st->steps_left > 0)) {
+        if (gid == 0) st->ckpt_valid = 0;
+        continue;
+      }
+    } else if (!st->ckpt_valid) {
+      continue;
+    }
+    const int cur = restore ? sv->buf : st->buf;
+    const size_t n = restore ? sv->n_main : st->n_main;
+    const int src = restore ? cur ^ 1 : cur, dst = src ^ 1;
+    for (size_t i = gid; i < n; i += gsz) {
+      d.cell[dst][i] = d.cell[src][i];
+      d.off[dst][i] = d.off[src][i];
+      d.vx[dst][i] = d.vx[src][i];
+      d.vy[dst][i] = d.vy[src][i];
+      d.vz[dst][i] = d.vz[src][i];
+      d.id[dst][i] = d.id[src][i];
+    }
+    uint4* grid = reinterpret_cast<uint4*>(d.cnt[0]);
+    uint4* keep = reinterpret_cast<uint4*>(d.ckpt);
+    const size_t words = d.grid_bytes / 16;
+    for (size_t w = gid; w < words; w += gsz) {
+      if (restore)
+        grid[w] = keep[w];
+      else
+        keep[w] = grid[w];
+    }
+    if (gid == 0) {
+      if (!restore) {
+        *sv = *st;
+        st->ckpt_valid = 1;
+        st->ckpt_step = st->step;
+      } else {
+        State x = *sv;
+        x.ckpt_valid = 1;  // the checkpoint still holds this state
+        x.ckpt_step = x.step;
+        *st = x;
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -409,6 +479,12 @@ hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, 
   hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
   hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
+  return hipGetLastError();
+}
+
+template <class P>
+hipError_t launch_checkpoint(const Disch<P>* d_dev, int D, int restore, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_checkpoint<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D, restore);
   return hipGetLastError();
 }
 
@@ -426,6 +502,8 @@ hipError_t sort_set_lds(int nc_max) {
 size_t sort_parts(size_t nc, size_t tiles) { return (nc * tiles + kScanBlock - 1) / kScanBlock + 1; }
 
 template hipError_t launch_sort_impl<float>(const Disch<float>*, int, int, int, hipStream_t);
+template hipError_t launch_checkpoint<float>(const Disch<float>*, int, int, int, hipStream_t);
+template hipError_t launch_checkpoint<double>(const Disch<double>*, int, int, int, hipStream_t);
 template hipError_t launch_sort_impl<double>(const Disch<double>*, int, int, int, hipStream_t);
 template hipError_t sort_set_lds<float>(int);
 template hipError_t sort_set_lds<double>(int);

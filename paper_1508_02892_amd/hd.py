@@ -16,10 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhd.so")
 
-HD_ABI_VERSION = 3
+HD_ABI_VERSION = 4
 HD_MAX_CHANNELS = 16
 STATUS = {0: "HD_OK", -1: "HD_EINVAL", -2: "HD_ENOMEM", -3: "HD_EDEVICE", -4: "HD_ECAPACITY",
-          -5: "HD_ENUMERIC", -6: "HD_ESTATE"}
+          -5: "HD_ENUMERIC", -6: "HD_ESTATE", -7: "HD_ESYNC"}
 KIND = {"elastic": 0, "excitation": 1, "ionization": 2, "attachment": 3}
 
 # Every entry point declared in include/hd.h.
@@ -29,7 +29,8 @@ SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_disc
            "hd_batch_free", "hd_server_create", "hd_server_submit", "hd_server_poll",
            "hd_server_stats", "hd_server_drain", "hd_server_free", "hd_profile_steps",
            "hd_diag_arith", "hd_swarm_create", "hd_swarm_run", "hd_swarm_results",
-           "hd_swarm_get_ions", "hd_swarm_free"]
+           "hd_swarm_get_ions", "hd_swarm_free", "hd_batch_get_launch", "hd_batch_set_launch",
+           "hd_batch_autotune", "hd_get_launch", "hd_set_launch", "hd_autotune", "hd_grow"]
 
 
 class HdError(RuntimeError):
@@ -69,8 +70,25 @@ class Params(C.Structure):
     ]
 
 
+class LaunchConfig(C.Structure):
+    _fields_ = [("electron_variant", C.c_int32), ("electron_groups", C.c_int32),
+                ("sort_groups", C.c_int32), ("append_groups", C.c_int32)]
+
+
+def _launch_dict(c: LaunchConfig) -> dict:
+    return {k: int(getattr(c, k)) for k, _ in LaunchConfig._fields_}
+
+
+def _launch_struct(d: dict) -> LaunchConfig:
+    c = LaunchConfig()
+    for k, _ in LaunchConfig._fields_:
+        setattr(c, k, int(d.get(k, 0)))
+    return c
+
+
 class DeviceCtx(C.Structure):
-    _fields_ = [("stream", C.c_void_p), ("device", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("stream", C.c_void_p), ("device", C.c_int32), ("reserved", C.c_int32),
+                ("arena", C.c_void_p), ("arena_bytes", C.c_size_t)]
 
 
 _D = C.POINTER(C.c_double)
@@ -89,6 +107,7 @@ class MomentSet(C.Structure):
         ("emitted", C.c_uint64 * 2), ("created", C.c_uint64), ("e_overflow", C.c_uint64),
         ("see_clamped", C.c_uint64), ("n_acc", C.c_uint64), ("pushed", C.c_uint64),
         ("volt_amp", C.c_double), ("p_abs", C.c_double), ("rf_periods", C.c_int64),
+        ("graph_steps", C.c_int64), ("rollbacks", C.c_int64),
     ]
 
 
@@ -171,6 +190,13 @@ def lib():
         L.hd_swarm_results.argtypes = [vp, C.POINTER(SwarmResult)]
         L.hd_swarm_get_ions.argtypes = [vp, C.c_int32] + [vp] * 5 + [C.c_int64]
         L.hd_swarm_free.argtypes = [vp]
+        for f in ("hd_batch_get_launch", "hd_get_launch"):
+            getattr(L, f).argtypes = [vp, C.POINTER(LaunchConfig)]
+        for f in ("hd_batch_set_launch", "hd_set_launch"):
+            getattr(L, f).argtypes = [vp, C.POINTER(LaunchConfig)]
+        L.hd_grow.argtypes = [vp, C.c_int64]
+        for f in ("hd_batch_autotune", "hd_autotune"):
+            getattr(L, f).argtypes = [vp, C.c_int64, C.POINTER(LaunchConfig)]
         _lib = L
     return _lib
 
@@ -229,8 +255,15 @@ def make_params(p: dict):
     return P, keep
 
 
-def _ctx(stream=None, device=0):
+def _ctx(stream=None, device=0, arena=None):
+    """Device context; arena: a torch uint8 tensor on the device (its memory
+    holds the handle's device state; the caller keeps it alive)."""
     c = DeviceCtx()
+    if arena is not None:
+        if arena.dtype.itemsize != 1 or not arena.is_contiguous() or arena.device.type != "cuda":
+            raise ValueError("arena must be a contiguous byte tensor on the GPU")
+        c.arena = arena.data_ptr()
+        c.arena_bytes = arena.numel()
     if stream is None:
         try:
             import torch
@@ -271,17 +304,21 @@ class _Moments:
                    emitted=np.array(m.emitted[:], np.uint64), created=int(m.created),
                    overflow=int(m.e_overflow), see_clamped=int(m.see_clamped),
                    n_acc=int(m.n_acc), pushed=int(m.pushed), volt_amp=float(m.volt_amp),
-                   p_abs=float(m.p_abs), rf_periods=int(m.rf_periods))
+                   p_abs=float(m.p_abs), rf_periods=int(m.rf_periods),
+                   graph_steps=int(m.graph_steps), rollbacks=int(m.rollbacks))
         return out
 
 
 class Discharge:
-    """One discharge: hd_init_discharge / hd_step / hd_moments / hd_free."""
+    """One discharge: hd_init_discharge / hd_step / hd_moments / hd_free.
+    arena: optional torch uint8 GPU tensor of at least required_bytes(params)
+    that holds the discharge's device state (kept referenced here)."""
 
-    def __init__(self, params: dict, stream=None, device: int = 0):
+    def __init__(self, params: dict, stream=None, device: int = 0, arena=None):
         self.params = dict(params)
         self._P, self._keep = make_params(params)
-        self._ctx = _ctx(stream, device)
+        self._arena = arena
+        self._ctx = _ctx(stream, device, arena)
         h = C.c_void_p()
         _check(lib().hd_init_discharge(C.byref(self._P), C.byref(self._ctx), C.byref(h)))
         self.h = h
@@ -313,6 +350,24 @@ class Discharge:
         _check(lib().hd_get_push_field(self.h, _ptr(ep)))
         return ep
 
+    def grow(self, new_capacity: int):
+        """Raise the particle capacity (continues a run rolled back at an overflow)."""
+        _check(lib().hd_grow(self.h, int(new_capacity)))
+        self.params["capacity"] = int(new_capacity)
+
+    def get_launch(self) -> dict:
+        c = LaunchConfig()
+        _check(lib().hd_get_launch(self.h, C.byref(c)))
+        return _launch_dict(c)
+
+    def set_launch(self, cfg: dict):
+        _check(lib().hd_set_launch(self.h, C.byref(_launch_struct(cfg))))
+
+    def autotune(self, max_steps: int = 128) -> dict:
+        c = LaunchConfig()
+        _check(lib().hd_autotune(self.h, int(max_steps), C.byref(c)))
+        return _launch_dict(c)
+
     def profile_steps(self, n: int) -> dict:
         """Advance n real steps with per-kernel HIP events; mean ms per kernel."""
         out = np.zeros(5)
@@ -334,19 +389,33 @@ class Discharge:
 class Batch:
     """Independent discharges advanced together: hd_batch_*."""
 
-    def __init__(self, params_list, stream=None, device: int = 0):
+    def __init__(self, params_list, stream=None, device: int = 0, arena=None):
         self.params = [dict(p) for p in params_list]
         made = [make_params(p) for p in params_list]
         self._keep = made
         arr = (C.POINTER(Params) * len(made))(*[C.pointer(m[0]) for m in made])
         self._arr = arr
-        self._ctx = _ctx(stream, device)
+        self._arena = arena
+        self._ctx = _ctx(stream, device, arena)
         h = C.c_void_p()
         _check(lib().hd_batch_create(arr, len(made), C.byref(self._ctx), C.byref(h)))
         self.h = h
 
     def step(self, n: int = 1):
         _check(lib().hd_batch_step(self.h, int(n)))
+
+    def get_launch(self) -> dict:
+        c = LaunchConfig()
+        _check(lib().hd_batch_get_launch(self.h, C.byref(c)))
+        return _launch_dict(c)
+
+    def set_launch(self, cfg: dict):
+        _check(lib().hd_batch_set_launch(self.h, C.byref(_launch_struct(cfg))))
+
+    def autotune(self, max_steps: int = 128) -> dict:
+        c = LaunchConfig()
+        _check(lib().hd_batch_autotune(self.h, int(max_steps), C.byref(c)))
+        return _launch_dict(c)
 
     def moments(self, i: int) -> dict:
         p = self.params[i]
@@ -444,24 +513,30 @@ def diag_arith(precision: int, a, b) -> np.ndarray:
     return out
 
 
+def _swarm_params(params: dict):
+    """hd_swarm_params and the arrays it points into (keep them alive)."""
+    rate = np.ascontiguousarray(params["rate_m3_s"], np.float64)
+    e0 = np.ascontiguousarray(params["e0_V_m"], np.float64)
+    P = SwarmParams()
+    P.abi_version = HD_ABI_VERSION
+    for name, _ in SwarmParams._fields_:
+        if name in ("abi_version", "rate_m3_s", "e0_V_m", "n_energy", "n_fields"):
+            continue
+        setattr(P, name, params[name])
+    P.n_energy = len(rate)
+    P.n_fields = len(e0)
+    P.rate_m3_s = rate.ctypes.data_as(_D)
+    P.e0_V_m = e0.ctypes.data_as(_D)
+    return P, rate, e0
+
+
 class Swarm:
     """Auxiliary ion swarms (one per field value): hd_swarm_create / run /
     results / get_ions / free."""
 
     def __init__(self, params: dict, stream=None, device: int = 0):
         self.params = dict(params)
-        self._rate = np.ascontiguousarray(params["rate_m3_s"], np.float64)
-        self._e0 = np.ascontiguousarray(params["e0_V_m"], np.float64)
-        P = SwarmParams()
-        P.abi_version = HD_ABI_VERSION
-        for name, _ in SwarmParams._fields_:
-            if name in ("abi_version", "rate_m3_s", "e0_V_m", "n_energy", "n_fields"):
-                continue
-            setattr(P, name, params[name])
-        P.n_energy = len(self._rate)
-        P.n_fields = len(self._e0)
-        P.rate_m3_s = self._rate.ctypes.data_as(_D)
-        P.e0_V_m = self._e0.ctypes.data_as(_D)
+        P, self._rate, self._e0 = _swarm_params(params)
         self._P = P
         self._ctx = _ctx(stream, device)
         h = C.c_void_p()

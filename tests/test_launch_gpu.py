@@ -1,0 +1,110 @@
+"""Launch shapes do not change results.
+
+Every shape the autotuner may pick (the electron kernel variant and its
+workgroup count, the sort's and the append's workgroup counts) must give
+bitwise the same run: particles are processed in fixed chunks, deposits are
+integer sums, children are appended in parent order and the sort's tiles
+are fixed, so no launch shape can reach a result.  The batch is shaped like
+the batched sweep (uneven gaps, grids, voltages and particle counts); two
+members are also checked against the oracle, and a run whose first steps
+were taken by the autotuner equals a run with a fixed shape.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1508_02892_amd import hd, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 40  # two sorts and a partial interval
+
+
+def _params():
+    ps = W.c3(n_discharges=6, total_electrons=0)
+    sizes = [20_000, 150_000, 4_097, 60_000, 90_001, 33_000]
+    return [W.scaled(p, n) for p, n in zip(ps, sizes)]
+
+
+def _run(ps, cfg=None, tune=0):
+    b = hd.Batch(ps)
+    if cfg is not None:
+        b.set_launch(cfg)
+    used = b.get_launch()
+    if tune:
+        used = b.autotune(tune)
+        b.step(STEPS - tune)
+    else:
+        b.step(7)
+        b.step(STEPS - 7)
+    out = [(b.moments(i), b.particles(i)) for i in range(len(ps))]
+    b.close()
+    return out, used
+
+
+def _same(a, b):
+    for (ma, pa), (mb, pb) in zip(a, b):
+        for k in pa:
+            np.testing.assert_array_equal(pa[k], pb[k], err_msg=k)
+        for k, v in ma.items():
+            if k in ("graph_steps", "rollbacks"):  # how the steps were launched
+                continue
+            if isinstance(v, np.ndarray):
+                np.testing.assert_array_equal(v, mb[k], err_msg=k)
+            else:
+                assert v == mb[k], k
+
+
+CONFIGS = [
+    {"electron_variant": 1},
+    {"electron_variant": 2},
+    {"electron_variant": 2, "electron_groups": 100},
+    {"electron_variant": 0, "electron_groups": 7},
+    {"electron_variant": 1, "electron_groups": 33},
+    {"sort_groups": 3},
+    {"append_groups": 1},
+    {"electron_variant": 1, "electron_groups": 1, "sort_groups": 1000, "append_groups": 64},
+]
+
+
+def test_every_launch_shape_gives_the_same_run():
+    ps = _params()
+    ref, used = _run(ps, {})
+    print("default shape:", used)
+    for cfg in CONFIGS:
+        got, used = _run(ps, cfg)
+        print("shape:", used)
+        for k, v in cfg.items():
+            assert used[k] == v
+        _same(ref, got)
+    for i in (0, 2):
+        orc = oracle.Oracle(ps[i], contract=True)
+        orc.step(STEPS)
+        m, p = ref[i]
+        o = orc.particles()
+        np.testing.assert_array_equal(p["cell"], o["cell"])
+        live = o["cell"] >= 0
+        for k in ("off", "vx", "vy", "vz", "id"):
+            np.testing.assert_array_equal(p[k][live], o[k][live], err_msg=k)
+        np.testing.assert_array_equal(m["cnt"], orc.grid()["cnt"])
+        np.testing.assert_array_equal(m["phi"], orc.grid()["phi"])
+
+
+def test_autotuned_run_equals_fixed_shape_run():
+    ps = _params()
+    ref, _ = _run(ps, {})
+    got, chosen = _run(ps, tune=32)
+    print("autotuner chose:", chosen)
+    _same(ref, got)
+
+
+def test_invalid_shapes_are_rejected():
+    b = hd.Batch(_params()[:2])
+    for cfg in ({"electron_variant": 9}, {"electron_groups": 5000}, {"sort_groups": -1},
+                {"append_groups": 100000}):
+        with pytest.raises(hd.HdError) as e:
+            b.set_launch(cfg)
+        assert e.value.code == -1
+    with pytest.raises(hd.HdError):
+        b.autotune(8)  # below two sort intervals
+    b.close()
