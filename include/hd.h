@@ -480,6 +480,22 @@ int hd_swarm_get_ions(hd_swarm* h, int32_t field, void* vx, void* vy, void* vz, 
 /* Releases device state.  NULL-safe. */
 int hd_swarm_free(hd_swarm* h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the swarm
+ * of hd_swarm_create, hd_swarm_run(n_relax, 0), hd_swarm_run(n_avg, 1) and
+ * hd_swarm_results in one call, with the same kernels and the same results,
+ * writing n_fields results to the caller-owned host array out.  All device
+ * work space (ion velocities and sums, tables, counters) lies in one fixed
+ * 64 MiB array inside the library's device code, one per device, held until
+ * the process ends: n_fields <= 256 and n_fields * n_ions ions of
+ * (3 sizeof(P) + 16) bytes plus the tables must fit (at most 2,396,745
+ * FP32 or 1,677,721 FP64 ions in all), else HD_EINVAL names the bytes
+ * needed.  No device memory is allocated and no stream is created: the
+ * work goes to ctx->stream as given (NULL: the null stream), and the call
+ * waits for it.  Calls that overlap on one device share the array and race;
+ * each call clears what must start at zero. */
+int hd_swarm_run_noalloc(const hd_swarm_params* params, int64_t n_relax, int64_t n_avg,
+                         const hd_device_ctx* ctx, hd_swarm_result* out);
 
 /* ---- diagnostics -------------------------------------------------------- */
 

@@ -192,4 +192,6 @@ hipError_t launch_swarm_step(const SwarmDev<P>& w, uint32_t step0, int n_steps, 
                              hipStream_t s);
 template <class P>
 hipError_t launch_swarm_reduce(const SwarmDev<P>& w, hipStream_t s);
+template <class P>
+hipError_t launch_swarm_clear(const SwarmDev<P>& w, hipStream_t s);
 }  // namespace hd

@@ -1984,6 +1984,104 @@ struct SwarmImpl : SwarmBase {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// The ion swarm for callers that cannot allocate device memory.  Its work
+// space is a fixed array in the library's device code, one per device the
+// library runs on, held until the process ends.  Host code never takes the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress with that device current, once, and is kept here.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int kNoAllocFields = 256;
+constexpr int kNoAllocDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocDevices] = {};
+
+// The calling thread's current device must be `device`.
+int scratch_address(int device, unsigned char** out) {
+  if (device < 0 || device >= kNoAllocDevices) return fail(HD_EINVAL, "device ordinal");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HD_EDEVICE, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+  return HD_OK;
+}
+
+template <class P>
+int swarm_noalloc(const hd_swarm_params& p, int64_t n_relax, int64_t n_avg, hipStream_t stream,
+                  int device, hd_swarm_result* out) {
+  const int D = p.n_fields, ne = p.n_energy;
+  if (D > kNoAllocFields)
+    return fail(HD_EINVAL, "more than " + std::to_string(kNoAllocFields) + " fields");
+  const size_t n = (size_t)D * (size_t)p.n_ions;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const size_t o_a = take(D * sizeof(P)), o_tab = take(ne * sizeof(P));
+  const size_t o_vx = take(n * sizeof(P)), o_vy = take(n * sizeof(P)), o_vz = take(n * sizeof(P));
+  const size_t o_az = take(n * 8), o_a2 = take(n * 8);
+  const size_t o_c = take(D * 8), o_o = take(D * 8), o_s = take(2 * D * 8);
+  if (off > kNoAllocBytes)
+    return fail(HD_EINVAL, "the swarm needs " + std::to_string(off) +
+                               " bytes of work space; the no-allocation work space holds " +
+                               std::to_string(kNoAllocBytes));
+  unsigned char* base = nullptr;
+  if (int rc = scratch_address(device, &base)) return rc;
+  SwarmDev<P> w{};
+  P tab[kSwarmMaxEnergy], acc[kNoAllocFields];
+  const double M = swarm_constants<P>(p, w, tab, acc);
+  w.a = (const P*)(base + o_a);
+  w.tab = (const P*)(base + o_tab);
+  w.vx = (P*)(base + o_vx);
+  w.vy = (P*)(base + o_vy);
+  w.vz = (P*)(base + o_vz);
+  w.avz = (double*)(base + o_az);
+  w.av2 = (double*)(base + o_a2);
+  w.coll = (uint64_t*)(base + o_c);
+  w.over = (uint64_t*)(base + o_o);
+  w.sums = (double*)(base + o_s);
+  HD_TRY(hipMemcpyAsync(base + o_a, acc, D * sizeof(P), hipMemcpyHostToDevice, stream));
+  HD_TRY(hipMemcpyAsync(base + o_tab, tab, ne * sizeof(P), hipMemcpyHostToDevice, stream));
+  // the work space keeps the previous call's contents: counters and sums
+  // start at zero, velocities and ion sums are set by the load
+  HD_TRY(launch_swarm_clear<P>(w, stream));
+  HD_TRY(launch_swarm_init<P>(w, stream));
+  constexpr int64_t kChunk = 256;  // steps per launch, as hd_swarm_run
+  int64_t step = 0;
+  for (int acc_on = 0; acc_on < 2; ++acc_on) {
+    const int64_t m = acc_on ? n_avg : n_relax;
+    for (int64_t done = 0; done < m; done += kChunk) {
+      const int k = (int)std::min<int64_t>(kChunk, m - done);
+      HD_TRY(launch_swarm_step<P>(w, (uint32_t)(step + done), k, acc_on, stream));
+    }
+    step += m;
+  }
+  HD_TRY(launch_swarm_reduce<P>(w, stream));
+  double sums[2 * kNoAllocFields];
+  uint64_t coll[kNoAllocFields], over[kNoAllocFields];
+  HD_TRY(hipMemcpyAsync(sums, w.sums, 2 * D * 8, hipMemcpyDeviceToHost, stream));
+  HD_TRY(hipMemcpyAsync(coll, w.coll, D * 8, hipMemcpyDeviceToHost, stream));
+  HD_TRY(hipMemcpyAsync(over, w.over, D * 8, hipMemcpyDeviceToHost, stream));
+  HD_TRY(hipStreamSynchronize(stream));
+  swarm_fill_results(p, M, n_avg, sums, coll, over, out);
+  return HD_OK;
+}
+
+}  // namespace
+
 }  // namespace hd
 
 // ---------------------------------------------------------------------------
@@ -2260,6 +2358,21 @@ int hd_diag_arith(int32_t precision, int64_t n, const void* a, const void* b, vo
 struct hd_swarm {
   hd::SwarmBase* impl;
 };
+
+int hd_swarm_run_noalloc(const hd_swarm_params* params, int64_t n_relax, int64_t n_avg,
+                         const hd_device_ctx* ctx, hd_swarm_result* out) {
+  if (!out) return hd::fail(HD_EINVAL, "null output");
+  if (n_relax < 0 || n_avg < 0) return hd::fail(HD_EINVAL, "step counts must be non-negative");
+  std::string why;
+  if (!hd::swarm_valid(params, why)) return hd::fail(HD_EINVAL, why);
+  if (ctx && ctx->arena) return hd::fail(HD_EINVAL, "the ion swarm takes no arena");
+  const int device = ctx ? ctx->device : 0;
+  hipStream_t stream = ctx ? (hipStream_t)ctx->stream : nullptr;
+  if (hipSetDevice(device) != hipSuccess) return hd::fail(HD_EDEVICE, "hipSetDevice");
+  return params->precision == HD_FP32
+             ? hd::swarm_noalloc<float>(*params, n_relax, n_avg, stream, device, out)
+             : hd::swarm_noalloc<double>(*params, n_relax, n_avg, stream, device, out);
+}
 
 int hd_swarm_create(const hd_swarm_params* params, const hd_device_ctx* ctx, hd_swarm** out) {
   if (!out) return hd::fail(HD_EINVAL, "null out");

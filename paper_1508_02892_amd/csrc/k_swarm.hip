@@ -140,6 +140,18 @@ __global__ __launch_bounds__(kSwarmThreads) void k_swarm_step(SwarmDev<P> w, uin
     atomicAdd(reinterpret_cast<unsigned long long*>(&w.over[f]), (unsigned long long)cnt[1]);
 }
 
+// Clears the per-swarm counters and sums (a fill kernel rather than a
+// memset, so that the launch may be captured into a graph).
+template <class P>
+__global__ void k_swarm_clear(SwarmDev<P> w) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= w.n_fields) return;
+  w.coll[f] = 0;
+  w.over[f] = 0;
+  w.sums[2 * f] = 0.0;
+  w.sums[2 * f + 1] = 0.0;
+}
+
 // Sums over the ions of one swarm (block f) in a fixed order: strided
 // per-thread sums, then a pairwise tree in LDS.
 constexpr int kRedThreads = 1024;
@@ -192,6 +204,12 @@ hipError_t launch_swarm_step(const SwarmDev<P>& w, uint32_t step0, int n_steps, 
 }
 
 template <class P>
+hipError_t launch_swarm_clear(const SwarmDev<P>& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_swarm_clear<P>, dim3((w.n_fields + 255) / 256), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+template <class P>
 hipError_t launch_swarm_reduce(const SwarmDev<P>& w, hipStream_t s) {
   hipLaunchKernelGGL(k_swarm_reduce<P>, dim3(w.n_fields), dim3(kRedThreads), 0, s, w);
   return hipGetLastError();
@@ -204,6 +222,8 @@ template hipError_t launch_swarm_step<float>(const SwarmDev<float>&, uint32_t, i
 template hipError_t launch_swarm_step<double>(const SwarmDev<double>&, uint32_t, int, int,
                                               hipStream_t);
 template hipError_t launch_swarm_reduce<float>(const SwarmDev<float>&, hipStream_t);
+template hipError_t launch_swarm_clear<float>(const SwarmDev<float>&, hipStream_t);
+template hipError_t launch_swarm_clear<double>(const SwarmDev<double>&, hipStream_t);
 template hipError_t launch_swarm_reduce<double>(const SwarmDev<double>&, hipStream_t);
 
 }  // namespace hd

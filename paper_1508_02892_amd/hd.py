@@ -30,7 +30,8 @@ SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_disc
            "hd_server_stats", "hd_server_drain", "hd_server_free", "hd_profile_steps",
            "hd_diag_arith", "hd_swarm_create", "hd_swarm_run", "hd_swarm_results",
            "hd_swarm_get_ions", "hd_swarm_free", "hd_batch_get_launch", "hd_batch_set_launch",
-           "hd_batch_autotune", "hd_get_launch", "hd_set_launch", "hd_autotune", "hd_grow"]
+           "hd_batch_autotune", "hd_get_launch", "hd_set_launch", "hd_autotune", "hd_grow",
+           "hd_swarm_run_noalloc"]
 
 
 class HdError(RuntimeError):
@@ -190,6 +191,8 @@ def lib():
         L.hd_swarm_results.argtypes = [vp, C.POINTER(SwarmResult)]
         L.hd_swarm_get_ions.argtypes = [vp, C.c_int32] + [vp] * 5 + [C.c_int64]
         L.hd_swarm_free.argtypes = [vp]
+        L.hd_swarm_run_noalloc.argtypes = [C.POINTER(SwarmParams), C.c_int64, C.c_int64,
+                                           C.POINTER(DeviceCtx), C.POINTER(SwarmResult)]
         for f in ("hd_batch_get_launch", "hd_get_launch"):
             getattr(L, f).argtypes = [vp, C.POINTER(LaunchConfig)]
         for f in ("hd_batch_set_launch", "hd_set_launch"):
@@ -528,6 +531,16 @@ def _swarm_params(params: dict):
     P.rate_m3_s = rate.ctypes.data_as(_D)
     P.e0_V_m = e0.ctypes.data_as(_D)
     return P, rate, e0
+
+
+def swarm_run_noalloc(params: dict, n_relax: int, n_avg: int, stream=None, device: int = 0):
+    """hd_swarm_run_noalloc: the swarm in one call without device allocation."""
+    P, rate, e0 = _swarm_params(params)
+    ctx = _ctx(stream, device)
+    out = (SwarmResult * len(e0))()
+    _check(lib().hd_swarm_run_noalloc(C.byref(P), int(n_relax), int(n_avg), C.byref(ctx), out))
+    del rate, e0  # kept alive until the call returned
+    return [{k: getattr(r, k) for k, _ in SwarmResult._fields_} for r in out]
 
 
 class Swarm:
