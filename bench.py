@@ -143,6 +143,46 @@ def precision_leg() -> dict:
     return out
 
 
+def cpu_table(a):
+    """The CPU oracle's rates on this host for the set of workloads the
+    baseline plan names: the small plain discharge in full (FP64 particles,
+    and in FP32), the single large discharge for a bounded number of steps,
+    and one discharge of the batched sweep per size octave (100 steps each),
+    each single-threaded and on all usable cores.  No GPU is used."""
+    import oracle
+    from paper_1508_02892_amd import workloads as W
+    host = host_info()
+    cores = host.get("usable_cores") or host["nproc"] or 1
+    cases = [("small plain discharge, FP64, all 2,000 steps", W.c0(), W.C0_STEPS),
+             ("small plain discharge, FP32 particles, all 2,000 steps", W.c0(precision=0),
+              W.C0_STEPS),
+             ("single large discharge, %d steps" % a.cpu_steps, W.c1(), a.cpu_steps)]
+    ps = W.c3()
+    for lo in range(18, 23):
+        pick = [p for p in ps if (1 << lo) <= p["n_macro"] < (1 << (lo + 1))]
+        if pick:
+            cases.append(("batched-sweep member with %d electrons (octave 2^%d), 100 steps"
+                          % (pick[0]["n_macro"], lo), pick[0], 100))
+    rows = []
+    for name, p, steps in cases:
+        row = {"workload": name, "electrons": int(p["n_macro"])}
+        for t in (1, cores):
+            oracle.set_threads(t)
+            try:
+                o = oracle.Oracle(p)
+                c0 = o.counters()["pushed"]
+                t0 = time.perf_counter()
+                o.step(steps)
+                dt = time.perf_counter() - t0
+                row["threads_%d" % t] = (o.counters()["pushed"] - c0) / dt
+            finally:
+                oracle.set_threads(1)
+            del o
+        print("bench: %s: %s" % (name, row), file=sys.stderr, flush=True)
+        rows.append(row)
+    print(json.dumps({"cpu_oracle_particle_steps_per_s": rows, "host": host}), flush=True)
+
+
 def batched(a):
     """Batched sweep: 64 independent discharges (64M electrons in total) in one
     launch per phase, against the same discharges as separate handles (one
@@ -153,6 +193,7 @@ def batched(a):
     ps = W.c3(n_discharges=a.discharges, total_electrons=a.total_electrons)
     print("bench: building batch of %d" % len(ps), file=sys.stderr, flush=True)
     b = hd.Batch(ps, device=0)
+    launch = b.autotune(a.tune_steps) if a.tune_steps else b.get_launch()
     b.step(a.warmup)
     torch.cuda.synchronize()
     p0 = sum(b.moments(i)["pushed"] for i in range(len(ps)))
@@ -190,6 +231,7 @@ def batched(a):
                                "cells, 100-400 V, %d FP32 electrons in total, DD ions, one "
                                "launch per phase" % (len(ps), a.total_electrons)},
         "one_launch_per_discharge": sep,
+        "launch": launch,
     }
     print(json.dumps(line), flush=True)
 
@@ -257,23 +299,36 @@ def served(a):
     import numpy as np
 
     from paper_1508_02892_amd import hd, workloads as W
-    jobs = W.c4_jobs(rate_per_s=a.rate, duration_s=a.duration, seed=4, size_scale=a.size_scale,
-                     steps_range=(a.min_steps, a.max_steps))
-    srv = hd.Server(precision=0, max_slots=a.slots, max_cells=4096,
-                    hbm_budget_bytes=int(a.budget_gb * 1e9))
-    print("bench: serving %d jobs" % len(jobs), file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    ids = []
-    for j in jobs:
-        wait = t0 + j["arrival_s"] - time.perf_counter()
-        if wait > 0:
-            time.sleep(wait)
-        ids.append(srv.submit(j["params"], j["steps"]))
-    srv.drain(3600.0)
-    wall = time.perf_counter() - t0
-    lat = np.array([srv.poll(i)[1][1] for i in ids])
-    st = srv.stats()
-    srv.close()
+
+    def stream(rate):
+        jobs = W.c4_jobs(rate_per_s=rate, duration_s=a.duration, seed=4,
+                         size_scale=a.size_scale, steps_range=(a.min_steps, a.max_steps))
+        srv = hd.Server(precision=0, max_slots=a.slots, max_cells=4096,
+                        hbm_budget_bytes=int(a.budget_gb * 1e9))
+        print("bench: serving %d jobs at %g/s" % (len(jobs), rate), file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ids = []
+        for j in jobs:
+            wait = t0 + j["arrival_s"] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            ids.append(srv.submit(j["params"], j["steps"]))
+        srv.drain(3600.0)
+        wall = time.perf_counter() - t0
+        lat = np.array([srv.poll(i)[1][1] for i in ids])
+        st = srv.stats()
+        srv.close()
+        print("bench: %d jobs done in %.1f s" % (len(jobs), wall), file=sys.stderr, flush=True)
+        return jobs, wall, lat, st
+
+    jobs, wall, lat, st = stream(a.rate)
+    sub = None
+    if a.sub_rate > 0:
+        j2, w2, l2, s2 = stream(a.sub_rate)
+        sub = {"rate_jobs_per_s": a.sub_rate, "jobs": len(j2),
+               "value": s2["particle_steps"] / w2, "wall_s": w2,
+               "latency_s": {"p50": float(np.percentile(l2, 50)),
+                             "p99": float(np.percentile(l2, 99)), "max": float(l2.max())}}
     line = {
         "metric": "electron particle-steps/s (push+MCC+deposit), % HBM peak; p50/p99 job latency",
         "value": st["particle_steps"] / wall, "unit": "particle-steps/s", "n_gpus": 1,
@@ -289,6 +344,8 @@ def served(a):
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
         "server": st,
+        "sub_saturation": sub,
+        "wall_s": wall,
     }
     print(json.dumps(line), flush=True)
 
@@ -310,11 +367,14 @@ def main():
     ap.add_argument("--power-alpha", type=float, default=0.05)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration runs)")
-    ap.add_argument("--rate", type=float, default=2.0, help="served stream: jobs/s")
-    ap.add_argument("--duration", type=float, default=20.0, help="served stream: arrival window")
-    ap.add_argument("--size-scale", type=float, default=0.125)
+    ap.add_argument("--rate", type=float, default=20.0, help="served stream: jobs/s")
+    ap.add_argument("--sub-rate", type=float, default=7.0,
+                    help="served stream: a second, sub-saturation arrival rate (0: none)")
+    ap.add_argument("--duration", type=float, default=20.0,
+                    help="served stream: arrival window in seconds (the stated stream is 600 s)")
+    ap.add_argument("--size-scale", type=float, default=1.0)
     ap.add_argument("--min-steps", type=int, default=2000)
-    ap.add_argument("--max-steps", type=int, default=4000)
+    ap.add_argument("--max-steps", type=int, default=20000)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--discharges", type=int, default=64, help="batched sweep size")
@@ -338,6 +398,8 @@ def main():
         return batched(a)
     if a.workload == "swarm":
         return swarm(a)
+    if a.workload == "cpu":
+        return cpu_table(a)
 
     import torch
     from paper_1508_02892_amd import hd

@@ -1434,6 +1434,8 @@ struct Job {
   int err = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   JobResult res;
+  int prep_state = 0;           // host preparation: 0 not started, 1 running, 2 done
+  std::shared_ptr<void> prep;   // the prepared host state (the server's type)
 };
 
 struct ServerBase {
@@ -1473,6 +1475,15 @@ struct Server : ServerBase {
   uint64_t chunks = 0, pushed_done = 0, completed = 0, failed = 0;
   double busy_s = 0, t_start = 0;
 
+  // A job's host-side state, prepared ahead of admission.
+  struct Prep {
+    Host<P> h;
+    typename B::Prepared pr;
+  };
+  static constexpr size_t kPrepAhead = 32;  // queued jobs prepared ahead at most
+  std::vector<std::thread> preppers;
+  bool stop_prep = false;
+
   ~Server() override {
     {
       std::lock_guard<std::mutex> g(mu);
@@ -1480,6 +1491,13 @@ struct Server : ServerBase {
     }
     cv.notify_all();
     if (worker.joinable()) worker.join();
+    {
+      std::lock_guard<std::mutex> g(mu);
+      stop_prep = true;
+    }
+    cv.notify_all();
+    for (auto& t : preppers)
+      if (t.joinable()) t.join();
     if (graph) (void)hipGraphExecDestroy(graph);
     for (auto& h : hs)
       if (h.base) mem.release(h.base);
@@ -1553,7 +1571,46 @@ struct Server : ServerBase {
     if (e != hipSuccess) return fail(HD_EDEVICE, hipGetErrorString(e));
     t_start = now_s();
     worker = std::thread([this]() { loop(); });
+    const unsigned hc = std::thread::hardware_concurrency();
+    const int np = (int)std::min(16u, std::max(2u, hc / 2));
+    for (int t = 0; t < np; ++t) preppers.emplace_back([this]() { prep_loop(); });
     return HD_OK;
+  }
+
+  // Host-side preparation of queued jobs (tables, initial load, drive table)
+  // ahead of admission, on threads of their own, so that admitting a job
+  // only uploads it; the first kPrepAhead queued jobs in order.
+  void prep_loop() {
+    for (;;) {
+      Job* j = nullptr;
+      {
+        std::unique_lock<std::mutex> g(mu);
+        for (;;) {
+          if (stop_prep) return;
+          size_t k = 0;
+          for (Job* q : queue) {
+            if (k++ >= kPrepAhead) break;
+            if (q->prep_state == 0) {
+              j = q;
+              break;
+            }
+          }
+          if (j) break;
+          cv.wait_for(g, std::chrono::milliseconds(5));
+        }
+        j->prep_state = 1;
+      }
+      auto pp = std::make_shared<Prep>();
+      pp->h.p = j->p;
+      pp->h.p.channels = j->ch.empty() ? nullptr : j->ch.data();
+      B::prepare_host(pp->h, std::max<int64_t>(kVoltInitial, j->n_steps + 2), pp->pr);
+      {
+        std::lock_guard<std::mutex> g(mu);
+        j->prep = pp;
+        j->prep_state = 2;
+      }
+      cv.notify_all();
+    }
   }
 
   int submit(const hd_params* p, int64_t n, uint64_t* id) override {
@@ -1602,13 +1659,16 @@ struct Server : ServerBase {
 
   // Admit one job into a slot (worker thread; device calls on the stream).
   int admit(int slot, Job* job) {
+    std::shared_ptr<Prep> pp;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      pp = std::static_pointer_cast<Prep>(job->prep);
+      job->prep.reset();
+    }
     Host<P>& h = hs[slot];
-    h = Host<P>();
-    h.p = job->p;
-    h.p.channels = job->ch.empty() ? nullptr : job->ch.data();
-    typename B::Prepared pr;
-    B::prepare_host(h, std::max<int64_t>(kVoltInitial, job->n_steps + 2), pr);
-    int rc = B::upload_state(h, pr, stream, mem);
+    h = std::move(pp->h);
+    int rc = B::upload_state(h, pp->pr, stream, mem);
+    pp.reset();
     if (rc) return rc;
     HD_TRY(hipMemcpyAsync(d_desc + slot, &h.dd, sizeof(Disch<P>), hipMemcpyHostToDevice, stream));
     HD_TRY(launch_finalize<P>(d_desc + slot, 1, 1, nn_max, 0, stream));
@@ -1675,6 +1735,7 @@ struct Server : ServerBase {
         for (int s = 0; s < S && !queue.empty(); ++s) {
           if (slot_job[s]) continue;
           Job* j = queue.front();
+          if (j->prep_state != 2) break;  // first come, first admitted: wait for its host state
           if (used + j->bytes > cfg.hbm_budget_bytes) break;
           queue.pop_front();
           used += j->bytes;

@@ -108,3 +108,33 @@ def test_invalid_shapes_are_rejected():
     with pytest.raises(hd.HdError):
         b.autotune(8)  # below two sort intervals
     b.close()
+
+
+def test_c3_full_scale_batch_equals_single_handles():
+    # The batched sweep at full size: 64 discharges, 2^26 electrons in all,
+    # 256-4096 cells.  After 17 steps (one sort), every member equals the
+    # same discharge run alone, bit for bit; three members (the smallest,
+    # one in the middle and the largest grid) also equal the oracle.
+    ps = W.c3()
+    assert sum(p["n_macro"] for p in ps) == 1 << 26
+    b = hd.Batch(ps)
+    b.step(17)
+    for i, p in enumerate(ps):
+        d = hd.Discharge(p)
+        d.step(17)
+        _same([(b.moments(i), b.particles(i))], [(d.moments(), d.particles())])
+        d.close()
+    picks = {int(np.argmin([p["n_macro"] for p in ps])), len(ps) // 2,
+             int(np.argmax([p["n_cells"] for p in ps]))}
+    for i in sorted(picks):
+        orc = oracle.Oracle(ps[i], contract=True)
+        orc.step(17)
+        m, p = b.moments(i), b.particles(i)
+        o = orc.particles()
+        np.testing.assert_array_equal(p["cell"], o["cell"])
+        live = o["cell"] >= 0
+        for k in ("off", "vx", "vy", "vz", "id"):
+            np.testing.assert_array_equal(p[k][live], o[k][live], err_msg=k)
+        for k in ("cnt", "n_i", "phi", "E"):
+            np.testing.assert_array_equal(m[k], orc.grid()[k], err_msg=k)
+    b.close()
