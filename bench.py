@@ -7,9 +7,13 @@ full-inertia ion fluid, re-sort every 16 steps -- with seeded synthetic
 cross sections and initial load.  A step is one pass of the whole hot path
 (field, ion fluid, push / MCC / deposit, emission, append, sort when due).
 
-The timed region is --steps steps replayed from captured graphs with the
-particle state resident in HBM, bracketed by device synchronisation.  value
-= particle-steps (live electrons pushed, counted on the device) / seconds.
+Before the timed region the autotuner takes --tune-steps real steps to pick
+the launch shapes (they never change results), then the warmup runs at
+least --warmup steps, up to a sort-interval boundary.  The timed region is
+exactly --steps steps, whole intervals replayed from captured graphs and a
+partial last interval launched kernel by kernel, with the particle state
+resident in HBM, bracketed by device synchronisation.  value = particle-steps
+(live electrons pushed, counted on the device) / seconds.
 
 roofline: the fused electron kernel is timed with HIP events on the
 library's stream over --profile-steps further real steps; its algorithmic
@@ -18,8 +22,11 @@ and id; write cell, offset, v_z) plus 8 B per collision (v_x, v_y).
 traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 (profiles/), scaled by the same counters on a plain copy of known size;
 null when the kernel source changed since they were taken.
-cpu_baseline: the CPU oracle on this host, single thread, for a bounded
-number of steps of the same workload.
+cpu_baseline: the plain CPU oracle on this host for a bounded number of
+steps of the same workload, on all usable cores and on one (host recorded).
+fp32_vs_fp64: the error of FP32 particle arithmetic against FP64 per result,
+by decision-locked replay on the CPU (the oracle's float run is the device's
+bit for bit).
 """
 from __future__ import annotations
 
@@ -193,7 +200,9 @@ def batched(a):
     ps = W.c3(n_discharges=a.discharges, total_electrons=a.total_electrons)
     print("bench: building batch of %d" % len(ps), file=sys.stderr, flush=True)
     b = hd.Batch(ps, device=0)
-    launch = b.autotune(a.tune_steps) if a.tune_steps else b.get_launch()
+    # the batched sweep's launch shapes come from the autotuner (128 real
+    # steps unless --tune-steps says otherwise)
+    launch = b.autotune(a.tune_steps or 128)
     b.step(a.warmup)
     torch.cuda.synchronize()
     p0 = sum(b.moments(i)["pushed"] for i in range(len(ps)))
@@ -385,7 +394,7 @@ def main():
     ap.add_argument("--launch", default="",
                     help="launch shape variant,electron_groups,sort_groups,append_groups "
                          "(0: default) instead of the autotuner")
-    ap.add_argument("--tune-steps", type=int, default=128,
+    ap.add_argument("--tune-steps", type=int, default=0,
                     help="steps the autotuner may take (within the warmup); 0: no tuning")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -435,8 +444,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    print("bench: warmup %d steps" % a.warmup, file=sys.stderr, flush=True)
-    dev.step(a.warmup)
+    # untimed warmup: at least the steps asked for, up to the next sort
+    # interval boundary, so that the timed steps start with a captured
+    # interval (the tuner's steps, if any, came before)
+    se = int(p["sort_every"])
+    done = dev.moments()["step"]
+    warm = a.warmup + (-(done + a.warmup)) % se
+    print("bench: warmup %d steps (asked %d; from step %d to an interval boundary)"
+          % (warm, a.warmup, done), file=sys.stderr, flush=True)
+    dev.step(warm)
     torch.cuda.synchronize()
     m0 = dev.moments()
     torch.cuda.synchronize()
@@ -448,7 +464,10 @@ def main():
     pushed = m1["pushed"] - m0["pushed"]
     secs = t1 - t0
     value = pushed / secs
-    print("bench: timed %d steps in %.3f s" % (a.steps, secs), file=sys.stderr, flush=True)
+    graph_steps = m1["graph_steps"] - m0["graph_steps"]
+    sorts = (m1["step"] // se) - (m0["step"] // se)
+    print("bench: timed %d steps in %.3f s (%d replayed from captured intervals, %d sorts)"
+          % (a.steps, secs, graph_steps, sorts), file=sys.stderr, flush=True)
 
     kms = dev.profile_steps(a.profile_steps)
     m2 = dev.moments()
@@ -474,7 +493,9 @@ def main():
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "electrons": int(p["n_macro"]), "cells": p["n_cells"],
-                   "live_electrons_end": int(m1["n_live"]), "parallelism": "1 GPU"},
+                   "live_electrons_end": int(m1["n_live"]), "parallelism": "1 GPU",
+                   "warmup_steps_run": warm, "timed_graph_steps": graph_steps,
+                   "timed_sorts": sorts},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_electron", "alg_bytes_per_launch": alg_bytes,
