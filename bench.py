@@ -21,7 +21,10 @@ bytes are 36 B per FP32 particle-step (read cell, offset, three velocities
 and id; write cell, offset, v_z) plus 8 B per collision (v_x, v_y).
 traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 (profiles/), scaled by the same counters on a plain copy of known size;
-null when the kernel source changed since they were taken.
+null when the kernel source changed since they were taken.  copy_measured:
+a 1 GiB device-to-device copy timed on the same GPU (read + write bytes per
+second), the practical ceiling beside the published peak; frac_of_copy is
+the kernel's rate against it.
 cpu_baseline: the plain CPU oracle on this host for a bounded number of
 steps of the same workload, on all usable cores and on one (host recorded).
 fp32_vs_fp64: the error of FP32 particle arithmetic against FP64 per result,
@@ -53,6 +56,24 @@ def kernel_hash() -> str:
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def measured_copy_gbs(n_bytes=1 << 30, reps=5):
+    """Device-to-device copy rate on this GPU (bytes read plus written per
+    second, GB/s), the practical ceiling beside the published 8 TB/s."""
+    import torch
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * n_bytes / (ms * 1e-3) / 1e9
 
 
 def read_traffic():
@@ -482,6 +503,7 @@ def main():
     alg_bytes = per_particle * n_push + per_coll * n_coll
     achieved = alg_bytes / (kms["electron"] * 1e-3) / 1e9
     traffic = read_traffic()
+    copy_gbs = measured_copy_gbs()
     line = {
         "metric": "electron particle-steps/s (push+MCC+deposit), % HBM peak; p50/p99 job latency",
         "value": value,
@@ -502,7 +524,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_electron", "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": kms["electron"]},
+                     "avg_launch_ms": kms["electron"], "copy_measured": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs},
         "kernel_ms": kms,
         "launch": launch,
     }

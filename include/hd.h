@@ -316,7 +316,12 @@ typedef struct hd_launch_config {
                                previous chunk's stores have drained (FP32:
                                four waves per SIMD); 1: the next chunk's
                                loads stay in flight while a chunk is worked
-                               on (FP32: three waves per SIMD)             */
+                               on (FP32: three waves per SIMD); 2: loads
+                               issued without the drain; 3, 4: as 0 and 2
+                               with the nontemporal hint on the particle
+                               loads and write-backs, which pays when the
+                               particle store is far larger than the 256 MB
+                               MALL and costs when it would stay there     */
   int32_t electron_groups;  /* particle workgroups of the electron launch,
                                1 .. 4096 (0: as many as fit on the device at
                                once)                                       */
@@ -333,10 +338,12 @@ int hd_batch_get_launch(hd_batch* b, hd_launch_config* out);
  * range or if a variant cannot be resident with this batch's LDS needs). */
 int hd_batch_set_launch(hd_batch* b, const hd_launch_config* cfg);
 /* Autotuner.  Advances the batch by up to max_steps real steps (whole sort
- * intervals, at least two), launched one kernel at a time with the
- * candidate shapes taken in turn and timed with HIP events on the handle's
- * stream: the electron variant and workgroup count, the sort's workgroup
- * count and the append workgroups are each given the fastest mean.  The
+ * intervals, at least two), launched one kernel at a time and timed with
+ * HIP events on the handle's stream: each electron candidate (variant and
+ * workgroup count) runs a block of consecutive steps whose first step is
+ * not timed (a variant leaves the caches in its own state), the sort's and
+ * the append's workgroup counts are taken in turn, and each is given the
+ * fastest mean.  The
  * steps are ordinary steps of the run (the shapes do not change results).
  * The choice is applied, written to *out (may be NULL) and kept in a
  * process-wide cache keyed by the device and the batch's shape (precision,

@@ -254,26 +254,46 @@ __device__ __forceinline__ int wave_max_i32(int x) {
   return max(t, __builtin_amdgcn_readlane(x, 63));
 }
 
-template <class T>
+// Vector load / store of global memory, with the nontemporal hint when NT:
+// data streamed once per launch then bypass the caches' normal retention,
+// which pays when the arrays are far larger than the MALL and costs when
+// they would have stayed in it.
+template <bool NT, class V>
+__device__ __forceinline__ V vld(const Gp<V>* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <bool NT, class V>
+__device__ __forceinline__ void vst(Gp<V>* p, const V& v) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Four consecutive elements as 16-byte vectors (two for 8-byte elements).
+template <bool NT = false, class T>
 __device__ __forceinline__ void gld4(const Gp<T>* p, T (&o)[4]) {
   if constexpr (sizeof(T) == 4) {
     typedef __attribute__((ext_vector_type(4))) T v4;
-    const v4 t = *reinterpret_cast<const Gp<v4>*>(p);
+    const v4 t = vld<NT>(reinterpret_cast<const Gp<v4>*>(p));
     o[0] = t[0];
     o[1] = t[1];
     o[2] = t[2];
     o[3] = t[3];
   } else {
     typedef __attribute__((ext_vector_type(2))) T v2;
-    const v2 a = *reinterpret_cast<const Gp<v2>*>(p);
-    const v2 b = *reinterpret_cast<const Gp<v2>*>(p + 2);
+    const v2 a = vld<NT>(reinterpret_cast<const Gp<v2>*>(p));
+    const v2 b = vld<NT>(reinterpret_cast<const Gp<v2>*>(p + 2));
     o[0] = a[0];
     o[1] = a[1];
     o[2] = b[0];
     o[3] = b[1];
   }
 }
-template <class T>
+template <bool NT = false, class T>
 __device__ __forceinline__ void gst4(Gp<T>* p, const T (&o)[4]) {
   if constexpr (sizeof(T) == 4) {
     typedef __attribute__((ext_vector_type(4))) T v4;
@@ -282,7 +302,7 @@ __device__ __forceinline__ void gst4(Gp<T>* p, const T (&o)[4]) {
     t[1] = o[1];
     t[2] = o[2];
     t[3] = o[3];
-    *reinterpret_cast<Gp<v4>*>(p) = t;
+    vst<NT>(reinterpret_cast<Gp<v4>*>(p), t);
   } else {
     typedef __attribute__((ext_vector_type(2))) T v2;
     v2 a, b;
@@ -290,8 +310,8 @@ __device__ __forceinline__ void gst4(Gp<T>* p, const T (&o)[4]) {
     a[1] = o[1];
     b[0] = o[2];
     b[1] = o[3];
-    *reinterpret_cast<Gp<v2>*>(p) = a;
-    *reinterpret_cast<Gp<v2>*>(p + 2) = b;
+    vst<NT>(reinterpret_cast<Gp<v2>*>(p), a);
+    vst<NT>(reinterpret_cast<Gp<v2>*>(p + 2), b);
   }
 }
 

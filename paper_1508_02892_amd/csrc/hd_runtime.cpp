@@ -1318,12 +1318,19 @@ struct Batch : BatchBase {
     std::vector<hipEvent_t> ev((size_t)n * 6);
     for (auto& e : ev) HD_TRY(hipEventCreate(&e));
     std::vector<int> which((size_t)n * 3, -1);
+    // Electron candidates run in blocks of consecutive steps and the first
+    // step of a block is not timed: a variant leaves the caches (the MALL
+    // above all) in its own state, which the next step inherits.  The other
+    // candidates take steps (append) and sorts (sort) in turn.
+    const int64_t nce = (int64_t)ce.size();
+    const int64_t blk = std::max<int64_t>(2, n / nce);
     hipError_t err = hipSuccess;
     int nsort = 0;
     for (int64_t s = 0; s < n && err == hipSuccess; ++s) {
       hipEvent_t* e = &ev[(size_t)s * 6];
       const bool srt = ((host_step + 1) % sort_every) == 0;
-      const int ie = (int)(s % (int64_t)ce.size()), ia = (int)(s % (int64_t)ca.size());
+      const int ie = (int)std::min<int64_t>(s / blk, nce - 1);
+      const int ia = (int)(s % (int64_t)ca.size());
       const int is = srt ? nsort++ % (int)cs.size() : -1;
       which[(size_t)s * 3] = ie;
       which[(size_t)s * 3 + 1] = ia;
@@ -1354,9 +1361,11 @@ struct Batch : BatchBase {
       if (err == hipSuccess) err = hipEventElapsedTime(&t1, e[2], e[3]);
       if (err == hipSuccess) err = hipEventElapsedTime(&t2, e[4], e[5]);
       if (err != hipSuccess) break;
-      Cand& a = ce[which[(size_t)s * 3]];
-      a.ms += t0;
-      a.runs += 1;
+      if (s % blk != 0) {
+        Cand& a = ce[which[(size_t)s * 3]];
+        a.ms += t0;
+        a.runs += 1;
+      }
       Cand& b = ca[which[(size_t)s * 3 + 1]];
       b.ms += t1;
       b.runs += 1;

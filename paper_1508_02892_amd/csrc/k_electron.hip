@@ -270,16 +270,16 @@ struct ChunkIn {
 };
 
 // Issue the loads of chunk lc (ids first: the random numbers need only them).
-template <class P>
+template <class P, bool NT>
 __device__ __forceinline__ void chunk_load(const Seg<P>& g, uint32_t lc, ChunkIn<P>& x) {
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)threadIdx.x * (uint32_t)kPerThread;
-  gld4(g.id + i0, x.id);
+  gld4<NT>(g.id + i0, x.id);
   __builtin_amdgcn_sched_barrier(0);  // keep the id load ahead of the others
-  gld4(g.cell + i0, x.c);
-  gld4(g.off + i0, x.off);
-  gld4(g.vz + i0, x.vz);
-  gld4(g.vx + i0, x.vx);
-  gld4(g.vy + i0, x.vy);
+  gld4<NT>(g.cell + i0, x.c);
+  gld4<NT>(g.off + i0, x.off);
+  gld4<NT>(g.vz + i0, x.vz);
+  gld4<NT>(g.vx + i0, x.vx);
+  gld4<NT>(g.vy + i0, x.vy);
 }
 
 // One wave's 256 slots of a chunk: push, removal and write-back, then the
@@ -298,9 +298,13 @@ __device__ __forceinline__ void chunk_load(const Seg<P>& g, uint32_t lc, ChunkIn
 // LM = 2: the loads go out at once, without the drain; the first use waits
 //   for them and for the previous chunk's stores together, so that the
 //   store and load latencies overlap.
-template <class P, int KC, int LM>
+// M = LM + 4 * NT: with NT the particle loads and write-backs carry the
+// nontemporal hint (the arrays are streamed once per launch).
+template <class P, int KC, int M>
 __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEntry<P>* q,
                            uint32_t& qn, WaveCounts& wc, ChunkIn<P>& nx, bool more) {
+  constexpr int LM = M & 3;
+  constexpr bool NT = (M & 4) != 0;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
@@ -308,10 +312,10 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   ChunkIn<P> in;
   if constexpr (LM == 1) {
     in = nx;
-    if (more) chunk_load<P>(g, lc + 1u, nx);
+    if (more) chunk_load<P, NT>(g, lc + 1u, nx);
     __builtin_amdgcn_sched_barrier(0);
   } else {
-    chunk_load<P>(g, lc, in);
+    chunk_load<P, NT>(g, lc, in);
   }
   int32_t(&c)[4] = in.c;
   P(&off)[4] = in.off;
@@ -362,9 +366,9 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   }
   // write back (vx, vy unchanged; collided particles get theirs when
   // scattered); issued early so that they retire behind the Philox work
-  gst4(g.cell + i0, c);
-  gst4(g.off + i0, off);
-  gst4(g.vz + i0, vz);
+  gst4<NT>(g.cell + i0, c);
+  gst4<NT>(g.off + i0, off);
+  gst4<NT>(g.vz + i0, vz);
   int ch[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -487,7 +491,7 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* 
 // Chunks [lc0, lc1) of discharge d by particle workgroup pb; chunk0 is the
 // launch-wide index of the discharge's first chunk and per the chunks per
 // workgroup.
-template <class P, int LM>
+template <class P, int M>
 __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned char* smem,
                         const Lds& L, uint32_t pb, uint32_t chunk0, uint32_t per) {
   const int tid = threadIdx.x, wv = tid >> 6;
@@ -543,14 +547,14 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   uint32_t qn = 0;
   WaveCounts wc;
   ChunkIn<P> nx;
-  if constexpr (LM == 1) chunk_load<P>(g, lc0, nx);
+  if constexpr ((M & 3) == 1) chunk_load<P, (M & 4) != 0>(g, lc0, nx);
   if (g.K == 3 && g.att_mask == 0) {  // elastic, excitation, ionization: unrolled
     for (uint32_t lc = lc0; lc < lc1; ++lc)
-      wave_chunk<P, 3, LM>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
+      wave_chunk<P, 3, M>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
     if (qn) drain<P, false>(d, g, q, qn, qn);
   } else {
     for (uint32_t lc = lc0; lc < lc1; ++lc)
-      wave_chunk<P, 0, LM>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
+      wave_chunk<P, 0, M>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
     if (qn) drain<P, true>(d, g, q, qn, qn);
   }
   wc.absl = wave_sum_u32(wc.absl);
@@ -839,7 +843,7 @@ __device__ void fluid_species(const Disch<P>& d, double* lds) {
 
 // Blocks [0, D) advance the ion fluid of discharge blockIdx.x; the others
 // share the particle chunks of all discharges in contiguous segments.
-template <class P, int LM>
+template <class P, int M>
 __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, const ElecArgs& a,
                                               unsigned char* smem) {
   const int D = a.D;
@@ -879,7 +883,7 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
     const uint32_t end = min(g1, pre[di + 1]);
     // a discharge with no chunks (idle, or an empty slot whose descriptor
     // has no arrays) between two others gets no segment
-    if (end > g0) segment<P, LM>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
+    if (end > g0) segment<P, M>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
     g0 = end;
     ++di;
   }
@@ -907,6 +911,19 @@ k_electron_f32_nd(const Disch<float>* __restrict__ ds, ElecArgs a) {
   electron_body<float, 2>(ds, a, smem);
 }
 
+// FP32 with nontemporal particle loads and write-backs (for particle
+// stores far beyond the MALL), with and without the drain.
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_electron_f32_nt(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float, 4>(ds, a, smem);
+}
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_electron_f32_nd_nt(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float, 6>(ds, a, smem);
+}
+
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64(const Disch<double>* __restrict__ ds,
                                                                ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -925,19 +942,33 @@ __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd(
   electron_body<double, 2>(ds, a, smem);
 }
 
-// Kernel variants of one precision, by how the particle data arrive (LM).
-constexpr int kElecVariants = 3;
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64_nt(
+    const Disch<double>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double, 4>(ds, a, smem);
+}
+
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd_nt(
+    const Disch<double>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double, 6>(ds, a, smem);
+}
+
+// Kernel variants of one precision, by how the particle data arrive: 0 drain
+// then load, 1 next chunk prefetched, 2 no drain, 3 and 4 as 0 and 2 with
+// nontemporal particle traffic.
+constexpr int kElecVariants = 5;
 template <class P>
 struct ElecKernel;
 template <>
 struct ElecKernel<float> {
-  static constexpr decltype(&k_electron_f32) fn[kElecVariants] = {k_electron_f32, k_electron_f32_pf,
-                                                                  k_electron_f32_nd};
+  static constexpr decltype(&k_electron_f32) fn[kElecVariants] = {
+      k_electron_f32, k_electron_f32_pf, k_electron_f32_nd, k_electron_f32_nt, k_electron_f32_nd_nt};
 };
 template <>
 struct ElecKernel<double> {
-  static constexpr decltype(&k_electron_f64) fn[kElecVariants] = {k_electron_f64, k_electron_f64_pf,
-                                                                  k_electron_f64_nd};
+  static constexpr decltype(&k_electron_f64) fn[kElecVariants] = {
+      k_electron_f64, k_electron_f64_pf, k_electron_f64_nd, k_electron_f64_nt, k_electron_f64_nd_nt};
 };
 
 }  // namespace

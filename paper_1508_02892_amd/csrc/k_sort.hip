@@ -142,17 +142,23 @@ __device__ __forceinline__ void load_items(const Gp<uint32_t>* h, uint64_t base,
     }
   }
 }
+// Stores back the scanned entries of load_items, skipping every 16-byte
+// vector whose counts are all zero: those entries are zero and stay zero
+// (an empty (cell, tile) keeps 0), so only the few vectors that hold a
+// count are written.
 __device__ __forceinline__ void store_items(Gp<uint32_t>* h, uint64_t base, uint64_t n,
-                                            const uint32_t (&v)[kScanItems]) {
+                                            const uint32_t (&v)[kScanItems],
+                                            const uint32_t (&cnt)[kScanItems]) {
 #pragma unroll
   for (int q = 0; q < kScanItems / 4; ++q) {
     const uint64_t i = base + 4u * (uint64_t)q;
     if (i + 4 <= n) {
-      *reinterpret_cast<Gp<u32x4>*>(h + i) = u32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+      if (cnt[4 * q] | cnt[4 * q + 1] | cnt[4 * q + 2] | cnt[4 * q + 3])
+        *reinterpret_cast<Gp<u32x4>*>(h + i) = u32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
     } else {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (i + k < n) h[i + k] = v[4 * q + k];
+        if (i + k < n && cnt[4 * q + k]) h[i + k] = v[4 * q + k];
     }
   }
 }
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restri
       // matrix is then zero again once the scatter has read the others
 #pragma unroll
       for (int k = 0; k < kScanItems; ++k) v[k] = cnt[k] ? v[k] + off : 0u;
-      store_items(gptr(d.hist), base, n, v);
+      store_items(gptr(d.hist), base, n, v, cnt);
       __syncthreads();  // sh_off is rewritten for the next block
     }
   }

@@ -1,6 +1,7 @@
 """Launch shapes do not change results.
 
-Every shape the autotuner may pick (the electron kernel variant and its
+Every shape the autotuner may pick (the electron kernel variant -- how the
+particle data are loaded, with or without the nontemporal hint -- and its
 workgroup count, the sort's and the append's workgroup counts) must give
 bitwise the same run: particles are processed in fixed chunks, deposits are
 integer sums, children are appended in parent order and the sort's tiles
@@ -61,6 +62,8 @@ CONFIGS = [
     {"electron_variant": 2, "electron_groups": 100},
     {"electron_variant": 0, "electron_groups": 7},
     {"electron_variant": 1, "electron_groups": 33},
+    {"electron_variant": 3},
+    {"electron_variant": 4, "electron_groups": 77},
     {"sort_groups": 3},
     {"append_groups": 1},
     {"electron_variant": 1, "electron_groups": 1, "sort_groups": 1000, "append_groups": 64},
