@@ -310,7 +310,10 @@ int hd_batch_free(hd_batch* b);
  * every order that reaches a result (deposit sums in 64-bit integers,
  * children in parent order, stable sort tiles of 4,096) is independent of
  * the launch shape, so results are bitwise identical under every valid
- * configuration.  A value of 0 selects the default. */
+ * configuration.  A value of 0 selects the default; a new handle starts
+ * from the autotuner's cached choice for its shape if there is one, else
+ * from the defaults with electron variant 3 when its initial particle state
+ * exceeds the 256 MB MALL and 0 otherwise. */
 typedef struct hd_launch_config {
   int32_t electron_variant; /* 0: each chunk of particles is loaded after the
                                previous chunk's stores have drained (FP32:
@@ -367,7 +370,10 @@ int hd_autotune(hd_discharge* h, int64_t max_steps, hd_launch_config* out);
  * sequence, and retires a job once it has run its steps, keeping its final
  * moments.  Jobs start at interval boundaries, so each job's result is
  * bitwise identical to the same discharge run alone.  Every job must match
- * the server's precision, sort_every and eedf_every and fit its caps. */
+ * the server's precision, sort_every and eedf_every and fit its caps.  An
+ * interval runs with electron variant 3 (nontemporal particle traffic) when
+ * the admitted jobs' initial particle state exceeds the 256 MB MALL, else
+ * with variant 0. */
 typedef struct hd_server hd_server;
 
 typedef struct hd_server_config {

@@ -35,6 +35,11 @@ template <class P>
 int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D,
                        int variant);
 int electron_variants();
+// The electron variant with nontemporal particle traffic (drain, then load),
+// and the size of MI355X's memory-side cache (MALL, the Infinity Cache):
+// particle state beyond it streams from HBM on every step.
+constexpr int kElecVariantStreaming = 3;
+constexpr uint64_t kMallBytes = 256ull << 20;
 template <class P>
 hipError_t finalize_set_lds(int nn_max);
 template <class P>
@@ -829,9 +834,17 @@ struct Batch : BatchBase {
         << "/nc" << nc_max << "/K" << K_max << "/m" << models;
       tune_key = k.str();
     }
+    // Untuned default: nontemporal particle traffic once the initial particle
+    // state is larger than the MALL, which it then cannot stay in.
+    hd_launch_config lc0{};
+    {
+      uint64_t bytes = 0;
+      for (const auto& h : hs) bytes += (uint64_t)h.p.n_macro * (8u + 4u * sizeof(P));
+      if (bytes > kMallBytes) lc0.electron_variant = kElecVariantStreaming;
+    }
     hd_launch_config lc{};
     if (!tune_lookup(tune_key, lc) || apply_launch(lc) != HD_OK) {
-      lc = hd_launch_config{};
+      lc = lc0;
       const int rc = apply_launch(lc);
       if (rc) return rc;
     }
@@ -1470,7 +1483,10 @@ struct Server : ServerBase {
   std::vector<int64_t> slot_done;  // steps completed by the job in the slot
   int grid_e = 0, grid_a = 0, grid_s = 0, tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0,
       fluid_nn = 0, K_max = 1;
-  hipGraphExec_t graph = nullptr;
+  // One interval over all slots, captured twice: with the default electron
+  // variant, and with nontemporal particle traffic for when the admitted
+  // jobs' particle state is far larger than the MALL (results are the same).
+  hipGraphExec_t graph = nullptr, graph_nt = nullptr;
   std::mutex mu;
   std::condition_variable cv;
   std::thread worker;
@@ -1508,6 +1524,7 @@ struct Server : ServerBase {
     for (auto& t : preppers)
       if (t.joinable()) t.join();
     if (graph) (void)hipGraphExecDestroy(graph);
+    if (graph_nt) (void)hipGraphExecDestroy(graph_nt);
     for (auto& h : hs)
       if (h.base) mem.release(h.base);
     if (d_desc) (void)hipFree(d_desc);
@@ -1561,23 +1578,25 @@ struct Server : ServerBase {
     std::vector<Disch<P>> v;
     for (int i = 0; i < S; ++i) v.push_back(idle_entry(i));
     HD_TRY(hipMemcpy(d_desc, v.data(), sizeof(Disch<P>) * S, hipMemcpyHostToDevice));
-    // capture one interval of sort_every steps over all slots
-    hipGraph_t g = nullptr;
-    HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int s = 0; s < cfg.sort_every && e == hipSuccess; ++s) {
-      e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max, 0,
-                                  stream);
-      if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, grid_a, stream);
-      if (e == hipSuccess && s == cfg.sort_every - 1)
-        e = launch_sort_impl<P>(d_desc, S, grid_s, nc_max, stream);
+    // capture one interval of sort_every steps over all slots, per variant
+    for (int nt = 0; nt < 2; ++nt) {
+      hipGraph_t g = nullptr;
+      HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int s = 0; s < cfg.sort_every && e == hipSuccess; ++s) {
+        e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max,
+                                    nt ? kElecVariantStreaming : 0, stream);
+        if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, grid_a, stream);
+        if (e == hipSuccess && s == cfg.sort_every - 1)
+          e = launch_sort_impl<P>(d_desc, S, grid_s, nc_max, stream);
+      }
+      const hipError_t e2 = hipStreamEndCapture(stream, &g);
+      if (e != hipSuccess || e2 != hipSuccess)
+        return fail(HD_EDEVICE, std::string("capture failed: ") + hipGetErrorString(e ? e : e2));
+      e = hipGraphInstantiate(nt ? &graph_nt : &graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(HD_EDEVICE, hipGetErrorString(e));
     }
-    const hipError_t e2 = hipStreamEndCapture(stream, &g);
-    if (e != hipSuccess || e2 != hipSuccess)
-      return fail(HD_EDEVICE, std::string("capture failed: ") + hipGetErrorString(e ? e : e2));
-    e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return fail(HD_EDEVICE, hipGetErrorString(e));
     t_start = now_s();
     worker = std::thread([this]() { loop(); });
     const unsigned hc = std::thread::hardware_concurrency();
@@ -1765,8 +1784,14 @@ struct Server : ServerBase {
         const int rc = admit(a.first, a.second);
         if (rc) return set_error(rc, g_err);
       }
+      // particle bytes of the admitted jobs (their initial loads): beyond the
+      // MALL the interval runs with nontemporal particle traffic
+      uint64_t resident = 0;
+      for (int s = 0; s < S; ++s)
+        if (slot_job[s]) resident += (uint64_t)slot_job[s]->p.n_macro * (8u + 4u * sizeof(P));
+      hipGraphExec_t run = resident > kMallBytes ? graph_nt : graph;
       const double t0 = now_s();
-      if (hipGraphLaunch(graph, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+      if (hipGraphLaunch(run, stream) != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
         return set_error(HD_EDEVICE, "interval launch failed");
       busy_s += now_s() - t0;
       chunks += 1;

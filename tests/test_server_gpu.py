@@ -56,6 +56,30 @@ def test_jobs_equal_alone_and_in_the_mix():
     srv.close()
 
 
+def test_jobs_beyond_the_mall_equal_alone():
+    # 7M + 5M admitted electrons (288 MB of FP32 particle state) exceed the
+    # 256 MB MALL, so those intervals run the nontemporal electron variant;
+    # once the 7M job retires the rest fit and run the default one.  Every
+    # job still equals the same discharge run alone (which, at most 7M
+    # electrons, uses the default variant throughout).
+    specs = [(512, 7_000_000, 41, 250.0, 32), (384, 5_000_000, 42, 200.0, 48),
+             (256, 3_000_000, 43, 150.0, 16), (512, 1_000_000, 44, 300.0, 64)]
+    srv = hd.Server(precision=0, max_slots=3, max_cells=512)
+    ids = [(srv.submit(_job(nc, nm, seed, v), steps), nc, nm, seed, v, steps)
+           for nc, nm, seed, v, steps in specs]
+    srv.drain(300)
+    st = srv.stats()
+    assert st["completed"] == len(specs) and st["failed"] == 0 and st["error"] == 0
+    for jid, nc, nm, seed, v, steps in ids:
+        state, _, mix = srv.poll(jid)
+        assert state == 2
+        alone = hd.Discharge(_job(nc, nm, seed, v))
+        alone.step(steps)
+        _same(mix, alone.moments())
+        alone.close()
+    srv.close()
+
+
 def test_admission_respects_budget():
     p = _job(128, 8000, 31, 150.0)
     one = hd.required_bytes(p)
