@@ -312,7 +312,7 @@ int hd_batch_free(hd_batch* b);
  * the launch shape, so results are bitwise identical under every valid
  * configuration.  A value of 0 selects the default; a new handle starts
  * from the autotuner's cached choice for its shape if there is one, else
- * from the defaults with electron variant 3 when its initial particle state
+ * from the defaults with electron variant 5 when its initial particle state
  * exceeds the 256 MB MALL and 0 otherwise. */
 typedef struct hd_launch_config {
   int32_t electron_variant; /* 0: each chunk of particles is loaded after the
@@ -324,7 +324,13 @@ typedef struct hd_launch_config {
                                with the nontemporal hint on the particle
                                loads and write-backs, which pays when the
                                particle store is far larger than the 256 MB
-                               MALL and costs when it would stay there     */
+                               MALL and costs when it would stay there;
+                               5, 6: as 3 and 4 with the hint on ids, cells
+                               and offsets only (the velocities, which the
+                               collision handler rewrites, stay cached);
+                               7: as 3, with each chunk's collisions handled
+                               before its velocities are written, in whole
+                               64-byte segments                            */
   int32_t electron_groups;  /* particle workgroups of the electron launch,
                                1 .. 4096 (0: as many as fit on the device at
                                once)                                       */
@@ -371,9 +377,9 @@ int hd_autotune(hd_discharge* h, int64_t max_steps, hd_launch_config* out);
  * moments.  Jobs start at interval boundaries, so each job's result is
  * bitwise identical to the same discharge run alone.  Every job must match
  * the server's precision, sort_every and eedf_every and fit its caps.  An
- * interval runs with electron variant 3 (nontemporal particle traffic) when
- * the admitted jobs' initial particle state exceeds the 256 MB MALL, else
- * with variant 0. */
+ * interval runs with electron variant 5 (nontemporal traffic of ids, cells
+ * and offsets) when the admitted jobs' initial particle state exceeds the
+ * 256 MB MALL, else with variant 0. */
 typedef struct hd_server hd_server;
 
 typedef struct hd_server_config {

@@ -35,10 +35,11 @@ template <class P>
 int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D,
                        int variant);
 int electron_variants();
-// The electron variant with nontemporal particle traffic (drain, then load),
-// and the size of MI355X's memory-side cache (MALL, the Infinity Cache):
-// particle state beyond it streams from HBM on every step.
-constexpr int kElecVariantStreaming = 3;
+// The electron variant with nontemporal traffic of ids, cells and offsets
+// (drain, then load; velocities left to the caches), and the size of
+// MI355X's memory-side cache (MALL, the Infinity Cache): particle state
+// beyond it streams from HBM on every step.
+constexpr int kElecVariantStreaming = 5;
 constexpr uint64_t kMallBytes = 256ull << 20;
 template <class P>
 hipError_t finalize_set_lds(int nn_max);
@@ -834,8 +835,9 @@ struct Batch : BatchBase {
         << "/nc" << nc_max << "/K" << K_max << "/m" << models;
       tune_key = k.str();
     }
-    // Untuned default: nontemporal particle traffic once the initial particle
-    // state is larger than the MALL, which it then cannot stay in.
+    // Untuned default: nontemporal traffic of ids, cells and offsets once the
+    // initial particle state is larger than the MALL, which it then cannot
+    // stay in.
     hd_launch_config lc0{};
     {
       uint64_t bytes = 0;
@@ -1484,8 +1486,9 @@ struct Server : ServerBase {
   int grid_e = 0, grid_a = 0, grid_s = 0, tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0,
       fluid_nn = 0, K_max = 1;
   // One interval over all slots, captured twice: with the default electron
-  // variant, and with nontemporal particle traffic for when the admitted
-  // jobs' particle state is far larger than the MALL (results are the same).
+  // variant, and with nontemporal traffic of ids, cells and offsets for when
+  // the admitted jobs' particle state is larger than the MALL (results are
+  // the same).
   hipGraphExec_t graph = nullptr, graph_nt = nullptr;
   std::mutex mu;
   std::condition_variable cv;
@@ -1785,7 +1788,7 @@ struct Server : ServerBase {
         if (rc) return set_error(rc, g_err);
       }
       // particle bytes of the admitted jobs (their initial loads): beyond the
-      // MALL the interval runs with nontemporal particle traffic
+      // MALL the interval runs the streaming electron variant
       uint64_t resident = 0;
       for (int s = 0; s < S; ++s)
         if (slot_job[s]) resident += (uint64_t)slot_job[s]->p.n_macro * (8u + 4u * sizeof(P));

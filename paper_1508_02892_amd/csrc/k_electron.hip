@@ -114,8 +114,10 @@ __device__ __forceinline__ int eedf_bin(P vx, P vy, P vz, const Seg<P>& g) {
 // its deposit, ion source (of the channel's product species) and EEDF
 // sample; an attached electron's slot becomes a hole and its charge joins
 // the negative-ion source at its position (it was not deposited).
-template <class P, bool ATT>
-__device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
+// With SW the new velocity goes back into the queue entry, for the slot's
+// own lane to pick up, instead of to the particle arrays.
+template <class P, bool ATT, bool SW>
+__device__ void handle(const Disch<P>& d, const Seg<P>& g, QEntry<P>& e) {
   StreamT<true> s(d.seed, kTagElectron, e.id, g.step);
   for (int w = 0; w < Uni<P>::kWords; ++w) (void)s.word();  // R used by the null test
   const int ch = (int)(e.meta & 0xFFu);
@@ -182,9 +184,15 @@ __device__ void handle(const Disch<P>& d, const Seg<P>& g, const QEntry<P>& e) {
     if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(cvx, cvy, cvz, g)], 1u);
     atomicAdd(&g.ctr[kCtrCreated], 1u);
   }
-  g.vx[e.slot] = ox;
-  g.vy[e.slot] = oy;
-  g.vz[e.slot] = oz;
+  if constexpr (SW) {
+    e.vx = ox;
+    e.vy = oy;
+    e.vz = oz;
+  } else {
+    g.vx[e.slot] = ox;
+    g.vy[e.slot] = oy;
+    g.vz[e.slot] = oz;
+  }
   if (g.sample) atomicAdd(&g.eedf[eedf_bin<P>(ox, oy, oz, g)], 1u);
   atomicAdd(&g.ctr[ch], 1u);
 }
@@ -195,7 +203,7 @@ template <class P, bool ATT>
 __device__ __forceinline__ void drain(const Disch<P>& d, const Seg<P>& g, QEntry<P>* q,
                                       uint32_t& qn, uint32_t n) {
   const uint32_t lane = (uint32_t)(threadIdx.x & 63);
-  if (lane < n) handle<P, ATT>(d, g, q[lane]);
+  if (lane < n) handle<P, ATT, false>(d, g, q[lane]);
   const uint32_t rest = qn - n;
   QEntry<P> t;
   if (lane < rest) t = q[n + lane];
@@ -270,16 +278,17 @@ struct ChunkIn {
 };
 
 // Issue the loads of chunk lc (ids first: the random numbers need only them).
-template <class P, bool NT>
+// NP: nontemporal hint on ids, cells and offsets; NV: on the velocities.
+template <class P, bool NP, bool NV>
 __device__ __forceinline__ void chunk_load(const Seg<P>& g, uint32_t lc, ChunkIn<P>& x) {
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)threadIdx.x * (uint32_t)kPerThread;
-  gld4<NT>(g.id + i0, x.id);
+  gld4<NP>(g.id + i0, x.id);
   __builtin_amdgcn_sched_barrier(0);  // keep the id load ahead of the others
-  gld4<NT>(g.cell + i0, x.c);
-  gld4<NT>(g.off + i0, x.off);
-  gld4<NT>(g.vz + i0, x.vz);
-  gld4<NT>(g.vx + i0, x.vx);
-  gld4<NT>(g.vy + i0, x.vy);
+  gld4<NP>(g.cell + i0, x.c);
+  gld4<NP>(g.off + i0, x.off);
+  gld4<NV>(g.vz + i0, x.vz);
+  gld4<NV>(g.vx + i0, x.vx);
+  gld4<NV>(g.vy + i0, x.vy);
 }
 
 // One wave's 256 slots of a chunk: push, removal and write-back, then the
@@ -298,13 +307,22 @@ __device__ __forceinline__ void chunk_load(const Seg<P>& g, uint32_t lc, ChunkIn
 // LM = 2: the loads go out at once, without the drain; the first use waits
 //   for them and for the previous chunk's stores together, so that the
 //   store and load latencies overlap.
-// M = LM + 4 * NT: with NT the particle loads and write-backs carry the
-// nontemporal hint (the arrays are streamed once per launch).
+// M = LM + 4 NP + 8 NV + 16 SW: with NP the loads and write-backs of ids,
+// cells and offsets carry the nontemporal hint (streamed once per launch),
+// with NV those of the velocities too.  Velocities without the hint stay in
+// the caches, where the collision handler's scattered velocity writes then
+// land (as partial writes to lines that have left the caches they cost a
+// read-modify-write in memory), and at particle counts whose velocities fit
+// the MALL, they stay there between steps.  With SW the chunk's collisions
+// are all handled before its velocities are written: the new velocities
+// return to their lanes, v_z is written whole, and v_x, v_y are written for
+// every 16-particle (64-byte) segment that holds a collision, so that no
+// write is narrower than a segment.
 template <class P, int KC, int M>
 __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEntry<P>* q,
                            uint32_t& qn, WaveCounts& wc, ChunkIn<P>& nx, bool more) {
   constexpr int LM = M & 3;
-  constexpr bool NT = (M & 4) != 0;
+  constexpr bool NP = (M & 4) != 0, NV = (M & 8) != 0, SW = (M & 16) != 0;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
@@ -312,10 +330,10 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   ChunkIn<P> in;
   if constexpr (LM == 1) {
     in = nx;
-    if (more) chunk_load<P, NT>(g, lc + 1u, nx);
+    if (more) chunk_load<P, NP, NV>(g, lc + 1u, nx);
     __builtin_amdgcn_sched_barrier(0);
   } else {
-    chunk_load<P, NT>(g, lc, in);
+    chunk_load<P, NP, NV>(g, lc, in);
   }
   int32_t(&c)[4] = in.c;
   P(&off)[4] = in.off;
@@ -366,9 +384,9 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   }
   // write back (vx, vy unchanged; collided particles get theirs when
   // scattered); issued early so that they retire behind the Philox work
-  gst4<NT>(g.cell + i0, c);
-  gst4<NT>(g.off + i0, off);
-  gst4<NT>(g.vz + i0, vz);
+  gst4<NP>(g.cell + i0, c);
+  gst4<NP>(g.off + i0, off);
+  if constexpr (!SW) gst4<NV>(g.vz + i0, vz);
   int ch[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -441,6 +459,33 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   }
   if (lane == 0) gptr(d.chunk_kids)[lc * (uint32_t)kWaves + (uint32_t)wv] = nk;
   // queue the collisions, one slot index j at a time, and scatter in 64s
+  // SW: byte j of qp is the queue index of this lane's slot j while its
+  // collision waits (0xFF: none); handle the first n entries, bring their
+  // new velocities back to the slots' lanes, then move the rest to the front
+  uint32_t qp = 0xFFFFFFFFu;
+  auto batch = [&](uint32_t n) {
+    if ((uint32_t)lane < n) handle<P, KC == 0, true>(d, g, q[lane]);
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t at = (qp >> (8 * j)) & 0xFFu;
+      if (at < n) {
+        vx[j] = q[at].vx;
+        vy[j] = q[at].vy;
+        vz[j] = q[at].vz;
+        qp |= 0xFFu << (8 * j);
+      } else if (at != 0xFFu) {
+        qp -= n << (8 * j);
+      }
+    }
+    const uint32_t rest = qn - n;
+    QEntry<P> t;
+    if ((uint32_t)lane < rest) t = q[n + (uint32_t)lane];
+    __builtin_amdgcn_wave_barrier();
+    if ((uint32_t)lane < rest) q[lane] = t;
+    __builtin_amdgcn_wave_barrier();
+    qn = rest;
+  };
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const bool col = ch[j] >= 0;
@@ -448,7 +493,8 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     if (mk == 0) continue;
     if (col) {
       const bool ion = (g.ion_mask >> ch[j]) & 1u;
-      QEntry<P>& e = q[qn + (uint32_t)__popcll(mk & lt)];
+      const uint32_t at = qn + (uint32_t)__popcll(mk & lt);
+      QEntry<P>& e = q[at];
       e.vx = vx[j];
       e.vy = vy[j];
       e.vz = vz[j];
@@ -458,9 +504,25 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
       e.slot = i0 + (uint32_t)j;
       e.meta = (uint32_t)ch[j] | (ion ? (0x100u | (kid << 16)) : 0u);
       kid += ion ? 1u : 0u;
+      if constexpr (SW) qp = (qp & ~(0xFFu << (8 * j))) | (at << (8 * j));
     }
     qn += (uint32_t)__popcll(mk);
-    if (qn >= 64u) drain<P, KC == 0>(d, g, q, qn, 64u);
+    if (qn >= 64u) {
+      if constexpr (SW)
+        batch(64u);
+      else
+        drain<P, KC == 0>(d, g, q, qn, 64u);
+    }
+  }
+  if constexpr (SW) {
+    if (qn) batch(qn);  // the rest of this chunk's collisions
+    gst4<NV>(g.vz + i0, vz);
+    const bool hit = (ch[0] >= 0) || (ch[1] >= 0) || (ch[2] >= 0) || (ch[3] >= 0);
+    const uint64_t seg = __ballot(hit) >> ((uint32_t)lane & ~3u);
+    if (seg & 0xFull) {  // a collision among the 16 slots of these four lanes
+      gst4<NV>(g.vx + i0, vx);
+      gst4<NV>(g.vy + i0, vy);
+    }
   }
 }
 
@@ -547,7 +609,7 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   uint32_t qn = 0;
   WaveCounts wc;
   ChunkIn<P> nx;
-  if constexpr ((M & 3) == 1) chunk_load<P, (M & 4) != 0>(g, lc0, nx);
+  if constexpr ((M & 3) == 1) chunk_load<P, (M & 4) != 0, (M & 8) != 0>(g, lc0, nx);
   if (g.K == 3 && g.att_mask == 0) {  // elastic, excitation, ionization: unrolled
     for (uint32_t lc = lc0; lc < lc1; ++lc)
       wave_chunk<P, 3, M>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
@@ -912,16 +974,35 @@ k_electron_f32_nd(const Disch<float>* __restrict__ ds, ElecArgs a) {
 }
 
 // FP32 with nontemporal particle loads and write-backs (for particle
-// stores far beyond the MALL), with and without the drain.
+// stores far beyond the MALL), with and without the drain; then the same
+// with the velocities left to the caches.
 __global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
 k_electron_f32_nt(const Disch<float>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 4>(ds, a, smem);
+  electron_body<float, 12>(ds, a, smem);
 }
 __global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
 k_electron_f32_nd_nt(const Disch<float>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float, 14>(ds, a, smem);
+}
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_electron_f32_np(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float, 4>(ds, a, smem);
+}
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_electron_f32_nd_np(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
   electron_body<float, 6>(ds, a, smem);
+}
+
+// FP32 with all particle traffic nontemporal and each chunk's collisions
+// handled before its velocities are written (whole segments only).
+__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
+k_electron_f32_nt_sw(const Disch<float>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<float, 28>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64(const Disch<double>* __restrict__ ds,
@@ -945,30 +1026,52 @@ __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd(
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nt(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 4>(ds, a, smem);
+  electron_body<double, 12>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd_nt(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double, 14>(ds, a, smem);
+}
+
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64_np(
+    const Disch<double>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double, 4>(ds, a, smem);
+}
+
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd_np(
+    const Disch<double>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
   electron_body<double, 6>(ds, a, smem);
 }
 
-// Kernel variants of one precision, by how the particle data arrive: 0 drain
-// then load, 1 next chunk prefetched, 2 no drain, 3 and 4 as 0 and 2 with
-// nontemporal particle traffic.
-constexpr int kElecVariants = 5;
+__global__ __launch_bounds__(kElecThreads) void k_electron_f64_nt_sw(
+    const Disch<double>* __restrict__ ds, ElecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  electron_body<double, 28>(ds, a, smem);
+}
+
+// Kernel variants of one precision, by how the particle data arrive and
+// leave: 0 drain then load, 1 next chunk prefetched, 2 no drain; 3 and 4 as
+// 0 and 2 with nontemporal particle traffic; 5 and 6 as 0 and 2 with
+// nontemporal traffic of ids, cells and offsets only; 7 as 3 with each
+// chunk's velocities written after its collisions.
+constexpr int kElecVariants = 8;
 template <class P>
 struct ElecKernel;
 template <>
 struct ElecKernel<float> {
   static constexpr decltype(&k_electron_f32) fn[kElecVariants] = {
-      k_electron_f32, k_electron_f32_pf, k_electron_f32_nd, k_electron_f32_nt, k_electron_f32_nd_nt};
+      k_electron_f32,       k_electron_f32_pf, k_electron_f32_nd,    k_electron_f32_nt,
+      k_electron_f32_nd_nt, k_electron_f32_np, k_electron_f32_nd_np, k_electron_f32_nt_sw};
 };
 template <>
 struct ElecKernel<double> {
   static constexpr decltype(&k_electron_f64) fn[kElecVariants] = {
-      k_electron_f64, k_electron_f64_pf, k_electron_f64_nd, k_electron_f64_nt, k_electron_f64_nd_nt};
+      k_electron_f64,       k_electron_f64_pf, k_electron_f64_nd,    k_electron_f64_nt,
+      k_electron_f64_nd_nt, k_electron_f64_np, k_electron_f64_nd_np, k_electron_f64_nt_sw};
 };
 
 }  // namespace

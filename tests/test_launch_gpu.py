@@ -64,6 +64,10 @@ CONFIGS = [
     {"electron_variant": 1, "electron_groups": 33},
     {"electron_variant": 3},
     {"electron_variant": 4, "electron_groups": 77},
+    {"electron_variant": 5, "electron_groups": 200},
+    {"electron_variant": 6},
+    {"electron_variant": 7},
+    {"electron_variant": 7, "electron_groups": 3},
     {"sort_groups": 3},
     {"append_groups": 1},
     {"electron_variant": 1, "electron_groups": 1, "sort_groups": 1000, "append_groups": 64},
@@ -103,8 +107,8 @@ def test_autotuned_run_equals_fixed_shape_run():
 
 def test_invalid_shapes_are_rejected():
     b = hd.Batch(_params()[:2])
-    for cfg in ({"electron_variant": 9}, {"electron_groups": 5000}, {"sort_groups": -1},
-                {"append_groups": 100000}):
+    for cfg in ({"electron_variant": 99}, {"electron_variant": -1}, {"electron_groups": 5000},
+                {"sort_groups": -1}, {"append_groups": 100000}):
         with pytest.raises(hd.HdError) as e:
             b.set_launch(cfg)
         assert e.value.code == -1
