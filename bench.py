@@ -502,7 +502,11 @@ def main():
     per_coll = 8.0 if fp32 else 16.0
     alg_bytes = per_particle * n_push + per_coll * n_coll
     achieved = alg_bytes / (kms["electron"] * 1e-3) / 1e9
-    traffic = read_traffic()
+    # the recorded counters belong to the default workload in its default
+    # launch shape only
+    default_run = (a.workload == "c1" and a.ion == "default" and a.power_w_m2 <= 0
+                   and not a.electrons and launch["electron_variant"] == 0)
+    traffic = read_traffic() if default_run else None
     copy_gbs = measured_copy_gbs()
     line = {
         "metric": "electron particle-steps/s (push+MCC+deposit), % HBM peak; p50/p99 job latency",

@@ -336,7 +336,10 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
         }
       }
       __syncthreads();
-      constexpr int R = 8;  // rounds of 64 items whose loads are issued together
+      // rounds of 64 items whose loads are issued together; the source
+      // arrays are read once, with the nontemporal hint, so that they do not
+      // displace the destination's partly written lines from the caches
+      constexpr int R = 8;
       for (uint32_t r = b; r < e; r += 64u * R) {
         int key[R];
         P o_[R], x_[R], y_[R], z_[R];
@@ -346,13 +349,13 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
           const uint32_t i = r + 64u * q + (uint32_t)lane;
           key[q] = nc;
           if (i < e) {
-            const int c = cell[i];
+            const int c = __builtin_nontemporal_load(cell + i);
             key[q] = c >= 0 ? c : nc;
-            o_[q] = s_off[i];
-            x_[q] = s_vx[i];
-            y_[q] = s_vy[i];
-            z_[q] = s_vz[i];
-            id_[q] = s_id[i];
+            o_[q] = __builtin_nontemporal_load(s_off + i);
+            x_[q] = __builtin_nontemporal_load(s_vx + i);
+            y_[q] = __builtin_nontemporal_load(s_vy + i);
+            z_[q] = __builtin_nontemporal_load(s_vz + i);
+            id_[q] = __builtin_nontemporal_load(s_id + i);
           }
         }
         uint32_t dest[R];
