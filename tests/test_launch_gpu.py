@@ -10,6 +10,11 @@ the batched sweep (uneven gaps, grids, voltages and particle counts); two
 members are also checked against the oracle, and a run whose first steps
 were taken by the autotuner equals a run with a fixed shape.
 """
+import json
+import os
+import subprocess
+import sys
+
 import numpy as np
 import pytest
 
@@ -145,3 +150,54 @@ def test_c3_full_scale_batch_equals_single_handles():
         for k in ("cnt", "n_i", "phi", "E"):
             np.testing.assert_array_equal(m[k], orc.grid()[k], err_msg=k)
     b.close()
+
+
+_TUNE_CHILD = """
+import json, sys
+sys.path.insert(0, sys.argv[2])
+from paper_1508_02892_amd import hd, workloads as W
+ps = [W.scaled(p, n) for p, n in zip(W.c3(n_discharges=3, total_electrons=0), [30000, 50000, 20000])]
+b = hd.Batch(ps)
+c = b.autotune(32) if sys.argv[1] == "tune" else b.get_launch()
+print(json.dumps(c))
+b.close()
+"""
+
+
+def test_tune_cache_file_carries_the_choice_across_processes(tmp_path):
+    # A process that autotunes appends its choice to the HD_TUNE_CACHE file;
+    # a later process with a batch of the same shape starts from the file's
+    # last entry for that shape (here rewritten to a shape the tuner would
+    # not pick, so that it can only have come from the file).
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, HD_TUNE_CACHE=str(cache))
+
+    def child(mode):
+        r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, mode, root], env=env,
+                           capture_output=True, text=True, timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    tuned = child("tune")
+    lines = cache.read_text().split("\n")
+    key, *vals = lines[0].split()
+    assert [int(v) for v in vals] == [tuned[k] for k in ("electron_variant", "electron_groups",
+                                                        "sort_groups", "append_groups")]
+    assert child("fresh") == tuned
+    with open(cache, "a") as f:
+        f.write("%s 1 77 333 5\n" % key)
+    assert child("fresh") == {"electron_variant": 1, "electron_groups": 77, "sort_groups": 333,
+                              "append_groups": 5}
+
+
+def test_untuned_default_follows_the_mall():
+    # Without a cached choice a handle starts cached (variant 0) while its
+    # initial particle state fits the 256 MB MALL, else with nontemporal
+    # ids, cells and offsets (variant 5).
+    small = hd.Discharge(W.scaled(W.c1(), 4 << 20))
+    big = hd.Discharge(W.scaled(W.c1(), 12 << 20))
+    assert small.get_launch()["electron_variant"] == 0
+    assert big.get_launch()["electron_variant"] == 5
+    small.close()
+    big.close()
