@@ -18,7 +18,7 @@ constexpr int kMaxCells = 4096;    // cells per discharge
 constexpr int kMaxNodes = kMaxCells + 1;
 constexpr int kMaxSegs = 4096;    // particle workgroups of one electron launch
 constexpr int kSphereTries = 64;   // bound of the rejection loops
-constexpr int kSortTile = 4096;    // items per sort tile (one wave)
+constexpr int kSortTile = 4096;    // items per sort tile (one workgroup of the sort)
 constexpr int kFinThreads = 1024;  // field/finalize workgroup
 constexpr int kMaxSpecies = 4;     // ion species of the multi-species model
 constexpr int kMaxMu = 256;        // mobility-table points per species

@@ -33,8 +33,9 @@ template <class P>
 __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restrict__ ds, int D,
                                                          int stride) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sh_lo[kWavesPerBlock], sh_hi[kWavesPerBlock];
+  constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const uint32_t gw = blockIdx.x * kWavesPerBlock + wv, nw = gridDim.x * kWavesPerBlock;
   for (int di = 0; di < D; ++di) {
     const Disch<P>& d = ds[di];
     const State* st = d.st;
@@ -42,18 +43,21 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
     const uint32_t n = st->n_main, nt = n_tiles(d);
     const int nc = d.nc;
     // each wave owns stride (>= nc + 1) words for the whole launch
-    uint32_t* h = reinterpret_cast<uint32_t*>(smem) + (size_t)wv * (size_t)stride;
+    uint32_t* run = reinterpret_cast<uint32_t*>(smem);
+    uint32_t* h = run + (size_t)wv * (size_t)stride;
     const Gp<int32_t>* cell = gptr(d.cell[st->buf]);
     Gp<uint32_t>* hist = gptr(d.hist);
     for (int c = lane; c < nc; c += 64) h[c] = 0u;
-    for (uint32_t t = gw; t < nt; t += nw) {
-      int lo = nc, hi = -1;
-      const uint32_t b = t * (uint32_t)kSortTile;
-      const uint32_t e = min(n, b + (uint32_t)kSortTile);
-      // 4 consecutive slots per lane per 256-slot round, all 16 rounds of
-      // the tile loaded before they are counted (the capacity is a multiple
-      // of the tile, so every vector load stays inside the array)
-      constexpr int kRounds = kSortTile / 256;
+    // The four waves of a workgroup share a tile, a quarter each, so that a
+    // tile's loads and counts are spread over four waves rather than
+    // serialised in one.
+    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
+      const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
+      const uint32_t e = min(n, b + kQuarter);
+      // 4 consecutive slots per lane per 256-slot round, all rounds loaded
+      // before they are counted (the capacity is a multiple of the tile, so
+      // every vector load stays inside the array)
+      constexpr int kRounds = (int)(kQuarter / 256u);
       int32_t c4[kRounds][4];
 #pragma unroll
       for (int q = 0; q < kRounds; ++q) {
@@ -61,6 +65,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
         if (i < e) gld4(cell + i, c4[q]);
       }
       // the tile's cell range first
+      int lo = nc, hi = -1;
 #pragma unroll
       for (int q = 0; q < kRounds; ++q) {
         const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
@@ -75,11 +80,21 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
       }
       lo = wave_min_i32(lo);
       hi = wave_max_i32(hi);
+      if (lane == 0) {
+        sh_lo[wv] = lo;
+        sh_hi[wv] = hi;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        lo = min(lo, sh_lo[w]);
+        hi = max(hi, sh_hi[w]);
+      }
       // Cells lo .. lo + 7 are counted in 8-bit fields of one register per
-      // lane (at most 64 items per lane), then in 16-bit fields summed over
-      // the wave (at most kSortTile per cell); other cells go straight to
-      // the wave's histogram.  With nearly sorted cells an atomic per item
-      // would have all 64 lanes on one address.
+      // lane (at most 16 items per lane), then in 16-bit fields summed over
+      // the wave (at most kQuarter per cell); other cells go straight to the
+      // wave's histogram.  With nearly sorted cells an atomic per item would
+      // have all 64 lanes on one address.
       uint64_t a8 = 0;
 #pragma unroll
       for (int q = 0; q < kRounds; ++q) {
@@ -101,23 +116,30 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
                                        ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
       const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
                                        ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
-      if (lane < 8) {
+      if (lane < 8 && lo + lane < nc) {
         const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
         if (v) h[lo + lane] += v;
       }
-      for (int c = lo + lane; c <= hi; c += 64) {
-        const uint32_t v = h[c];
+      __syncthreads();
+      // the tile's count of each cell: the sum over the four waves
+      for (int c = lo + (int)threadIdx.x; c <= hi; c += kThreads) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+          v += run[w * stride + c];
+          run[w * stride + c] = 0u;
+        }
         if (v) {
           hist[(size_t)c * nt + t] = v;
           // the total of the scan block holding this entry
           atomicAdd(&d.bin_start[((size_t)c * nt + t) / (size_t)kScanBlock], v);
         }
-        h[c] = 0u;
       }
-      if (lane == 0) {
+      if (threadIdx.x == 0) {
         gptr(d.tile_rng)[2 * t] = lo;
         gptr(d.tile_rng)[2 * t + 1] = hi;
       }
+      __syncthreads();  // histograms and ranges are reused by the next tile
     }
   }
 }
