@@ -272,6 +272,22 @@ int hd_step(hd_discharge* h, int64_t n_steps);
  * new block is taken from the arena's unused part. */
 int hd_grow(hd_discharge* h, int64_t new_capacity);
 
+/* Snapshot and resume of a run (the state of Sec. II at a step boundary:
+ * particles, ion fluid, fields, run sums).  hd_save waits for the handle's
+ * stream and writes the discharge's state -- the state record, the particle
+ * slots in use and the grids -- into the caller's host buffer out of
+ * capacity_bytes; *used_bytes gets the snapshot's size (out = NULL only
+ * queries it).  hd_restore loads a snapshot into a handle created with the
+ * same parameters (capacity may differ; HD_ECAPACITY if the snapshot's slots
+ * do not fit, hd_grow first), which then stands at the snapshot's step.  The
+ * random streams are keyed by particle id and step (Sec. II.A), so a
+ * resumed run is bitwise the uninterrupted one.  HD_EINVAL for a buffer
+ * that is too small, not a snapshot of this library and precision, or of a
+ * discharge with other parameters; a handle in an error state refuses
+ * both.  Single discharges only. */
+int hd_save(hd_discharge* h, void* out, size_t capacity_bytes, size_t* used_bytes);
+int hd_restore(hd_discharge* h, const void* in, size_t bytes);
+
 /* Waits for the handle's stream and fills *out (see hd_moment_set). */
 int hd_moments(hd_discharge* h, hd_moment_set* out);
 

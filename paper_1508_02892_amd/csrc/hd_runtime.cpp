@@ -1066,6 +1066,143 @@ struct Batch : BatchBase {
                                   " (hd_grow, then hd_step)");
   }
 
+  // ---- snapshot and resume of a single discharge --------------------------
+  // The run's whole state at a step boundary: the state record, the particle
+  // slots in use and the grids (deposits, ion densities and fluxes, fields,
+  // run sums, EEDF).  The random streams are keyed by particle id and step,
+  // so nothing else is needed for a resumed run to continue bit for bit as
+  // the uninterrupted one.  A snapshot is restored only into a handle of the
+  // same parameters (capacity aside), checked by a fingerprint of them.
+  struct SaveHead {
+    char magic[8];
+    uint64_t fingerprint;
+    int32_t abi, p_bytes;
+    uint64_t state_bytes, n_main, grid_bytes, total;
+  };
+  static constexpr char kSaveMagic[8] = {'H', 'D', 'S', 'A', 'V', 'E', '0', '1'};
+
+  uint64_t fingerprint() const {  // FNV-1a over the parameters and their tables
+    const Host<P>& h = hs[0];
+    uint64_t fp = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+      const unsigned char* c = static_cast<const unsigned char*>(p);
+      for (size_t i = 0; i < n; ++i) fp = (fp ^ c[i]) * 1099511628211ull;
+    };
+    hd_params q = h.p;  // no padding: 10 int32, 3 64-bit integers, doubles, pointers
+    q.capacity = 0;
+    q.channels = nullptr;
+    q.species = nullptr;
+    mix(&q, sizeof q);
+    for (size_t k = 0; k < h.ch.size(); ++k) {
+      hd_xs_channel c = h.ch[k];
+      c.sigma_m2 = nullptr;
+      mix(&c, sizeof c);
+      mix(h.sig[k].data(), h.sig[k].size() * sizeof(double));
+    }
+    for (size_t k = 0; k < h.sp.size(); ++k) {
+      hd_ion_species c = h.sp[k];
+      c.mu_m2_Vs = nullptr;
+      mix(&c, sizeof c);
+      mix(h.mu[k].data(), h.mu[k].size() * sizeof(double));
+    }
+    return fp;
+  }
+
+  int save(void* out, size_t cap, size_t* used) {
+    if (D != 1) return fail(HD_EINVAL, "hd_save is for single discharges");
+    if (!used) return fail(HD_EINVAL, "null size output");
+    if (error) return fail(error, "handle is in an error state");
+    State st;
+    if (int rc = sync_state(0, st)) return rc;
+    if (rolled_back) return fail(HD_ECAPACITY, "stopped at a capacity overflow: hd_grow first");
+    const Host<P>& h = hs[0];
+    const Offsets<P> o = layout<P>(h.p, h.volt_len0);
+    SaveHead hd{};
+    std::memcpy(hd.magic, kSaveMagic, 8);
+    hd.fingerprint = fingerprint();
+    hd.abi = HD_ABI_VERSION;
+    hd.p_bytes = (int32_t)sizeof(P);
+    hd.state_bytes = sizeof(State);
+    hd.n_main = st.n_main;
+    hd.grid_bytes = o.ip - o.cnt[0];
+    hd.total = sizeof(SaveHead) + hd.state_bytes + hd.n_main * (8 + 4 * sizeof(P)) + hd.grid_bytes;
+    *used = hd.total;
+    if (!out) return HD_OK;  // size query
+    if (cap < hd.total) return fail(HD_EINVAL, "snapshot buffer smaller than " + std::to_string(hd.total) + " bytes");
+    unsigned char* w = static_cast<unsigned char*>(out);
+    std::memcpy(w, &hd, sizeof hd);
+    w += sizeof hd;
+    std::memcpy(w, &st, sizeof st);
+    w += sizeof st;
+    const int b = st.buf;
+    const size_t n = hd.n_main;
+    auto get = [&](size_t off, size_t bytes) {
+      hipError_t e = hipMemcpy(w, h.base + off, bytes, hipMemcpyDeviceToHost);
+      w += bytes;
+      return e;
+    };
+    HD_TRY(get(o.cell[b], n * 4));
+    HD_TRY(get(o.off[b], n * sizeof(P)));
+    HD_TRY(get(o.vx[b], n * sizeof(P)));
+    HD_TRY(get(o.vy[b], n * sizeof(P)));
+    HD_TRY(get(o.vz[b], n * sizeof(P)));
+    HD_TRY(get(o.id[b], n * 4));
+    HD_TRY(get(o.cnt[0], hd.grid_bytes));
+    return HD_OK;
+  }
+
+  int restore(const void* in, size_t bytes) {
+    if (D != 1) return fail(HD_EINVAL, "hd_restore is for single discharges");
+    if (!in || bytes < sizeof(SaveHead)) return fail(HD_EINVAL, "not a snapshot");
+    if (error) return fail(error, "handle is in an error state");
+    SaveHead hd;
+    std::memcpy(&hd, in, sizeof hd);
+    if (std::memcmp(hd.magic, kSaveMagic, 8) != 0 || hd.abi != HD_ABI_VERSION ||
+        hd.p_bytes != (int32_t)sizeof(P) || hd.state_bytes != sizeof(State))
+      return fail(HD_EINVAL, "not a snapshot of this library and precision");
+    if (hd.fingerprint != fingerprint())
+      return fail(HD_EINVAL, "snapshot of a discharge with other parameters");
+    Host<P>& h = hs[0];
+    const Offsets<P> o = layout<P>(h.p, h.volt_len0);
+    if (hd.grid_bytes != o.ip - o.cnt[0] ||
+        hd.total != sizeof(SaveHead) + hd.state_bytes + hd.n_main * (8 + 4 * sizeof(P)) + hd.grid_bytes)
+      return fail(HD_EINVAL, "inconsistent snapshot");
+    if (bytes < hd.total) return fail(HD_EINVAL, "truncated snapshot");
+    const unsigned char* r = static_cast<const unsigned char*>(in) + sizeof hd;
+    State st;
+    std::memcpy(&st, r, sizeof st);
+    r += sizeof st;
+    const size_t n = hd.n_main, cap_slots = round_capacity(h.p.capacity);
+    if (n != st.n_main || st.error || (st.buf != 0 && st.buf != 1) || (st.cbuf != 0 && st.cbuf != 1))
+      return fail(HD_EINVAL, "inconsistent snapshot");
+    if (n > cap_slots) return fail(HD_ECAPACITY, "snapshot needs " + std::to_string(n) + " particle slots (hd_grow first)");
+    HD_TRY(hipStreamSynchronize(stream));
+    const int b = st.buf;
+    auto put = [&](size_t off, size_t bytes) {
+      hipError_t e = hipMemcpy(h.base + off, r, bytes, hipMemcpyHostToDevice);
+      r += bytes;
+      return e;
+    };
+    HD_TRY(put(o.cell[b], n * 4));
+    HD_TRY(put(o.off[b], n * sizeof(P)));
+    HD_TRY(put(o.vx[b], n * sizeof(P)));
+    HD_TRY(put(o.vy[b], n * sizeof(P)));
+    HD_TRY(put(o.vz[b], n * sizeof(P)));
+    HD_TRY(put(o.id[b], n * 4));
+    HD_TRY(put(o.cnt[0], hd.grid_bytes));
+    st.steps_left = 0;
+    st.ckpt_valid = 0;
+    st.ckpt_due = (uint64_t)n + 2ull * kSeeMax * (uint64_t)sort_every > (uint64_t)cap_slots ? 1 : 0;
+    HD_TRY(hipMemcpy(h.dd.st, &st, sizeof(State), hipMemcpyHostToDevice));
+    host_step = st.step;
+    rolled_back = false;
+    if (graph) {  // a graph holds no step-dependent input, but start clean
+      (void)hipGraphExecDestroy(graph);
+      graph = nullptr;
+    }
+    return ensure_volt(host_step + 1);
+  }
+
   // Raises the capacity of a single discharge: a new block of the larger
   // layout, the live state copied over, the old block released.
   int grow(int64_t cap) {
@@ -2345,6 +2482,16 @@ int hd_profile_steps(hd_discharge* h, int64_t n, double* out_ms) {
 int hd_grow(hd_discharge* h, int64_t new_capacity) {
   if (!h) return hd::fail(HD_EINVAL, "null handle");
   return dispatch(h->b.impl, [&](auto* x) { return x->grow(new_capacity); });
+}
+
+int hd_save(hd_discharge* h, void* out, size_t capacity_bytes, size_t* used_bytes) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl, [&](auto* x) { return x->save(out, capacity_bytes, used_bytes); });
+}
+
+int hd_restore(hd_discharge* h, const void* in, size_t bytes) {
+  if (!h) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(h->b.impl, [&](auto* x) { return x->restore(in, bytes); });
 }
 
 int hd_free(hd_discharge* h) {

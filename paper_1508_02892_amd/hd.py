@@ -31,6 +31,7 @@ SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_disc
            "hd_diag_arith", "hd_swarm_create", "hd_swarm_run", "hd_swarm_results",
            "hd_swarm_get_ions", "hd_swarm_free", "hd_batch_get_launch", "hd_batch_set_launch",
            "hd_batch_autotune", "hd_get_launch", "hd_set_launch", "hd_autotune", "hd_grow",
+           "hd_save", "hd_restore",
            "hd_swarm_run_noalloc"]
 
 
@@ -198,6 +199,8 @@ def lib():
         for f in ("hd_batch_set_launch", "hd_set_launch"):
             getattr(L, f).argtypes = [vp, C.POINTER(LaunchConfig)]
         L.hd_grow.argtypes = [vp, C.c_int64]
+        L.hd_save.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.hd_restore.argtypes = [vp, vp, C.c_size_t]
         for f in ("hd_batch_autotune", "hd_autotune"):
             getattr(L, f).argtypes = [vp, C.c_int64, C.POINTER(LaunchConfig)]
         _lib = L
@@ -357,6 +360,18 @@ class Discharge:
         """Raise the particle capacity (continues a run rolled back at an overflow)."""
         _check(lib().hd_grow(self.h, int(new_capacity)))
         self.params["capacity"] = int(new_capacity)
+
+    def save(self) -> bytes:
+        """Snapshot of the run at its current step (for resume)."""
+        n = C.c_size_t(0)
+        _check(lib().hd_save(self.h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().hd_save(self.h, buf, n.value, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def restore(self, snapshot: bytes):
+        """Continue from a snapshot taken from a discharge of the same parameters."""
+        _check(lib().hd_restore(self.h, snapshot, len(snapshot)))
 
     def get_launch(self) -> dict:
         c = LaunchConfig()
