@@ -420,7 +420,7 @@ typedef struct hd_server_counters {
   double busy_s;            /* host time spent waiting on intervals        */
   double wall_s;            /* since creation                              */
   int32_t error;
-  int32_t reserved;
+  int32_t cancelled;        /* jobs cancelled (hd_server_cancel)           */
 } hd_server_counters;
 
 int hd_server_create(const hd_server_config* cfg, const hd_device_ctx* ctx, hd_server** out);
@@ -429,7 +429,7 @@ int hd_server_create(const hd_server_config* cfg, const hd_device_ctx* ctx, hd_s
  * job alone exceeds the budget, HD_EINVAL if it does not fit the slots. */
 int hd_server_submit(hd_server* s, const hd_params* params, int64_t n_steps, uint64_t* job_id);
 
-/* *state: 0 queued, 1 running, 2 done, 3 failed.  times (may be NULL) gets
+/* *state: 0 queued, 1 running, 2 done, 3 failed, 4 cancelled.  times (may be NULL) gets
  * [submit->admit, submit->done, admit->done] in seconds (-1 if not yet).
  * When done and out != NULL, out is filled like hd_moments. */
 int hd_server_poll(hd_server* s, uint64_t job_id, int32_t* state, hd_moment_set* out,
@@ -439,6 +439,12 @@ int hd_server_stats(hd_server* s, hd_server_counters* out);
 
 /* Waits until every submitted job has finished (HD_ESTATE on timeout). */
 int hd_server_drain(hd_server* s, double timeout_s);
+
+/* Cancels a job (for callers whose request went away): a queued job leaves
+ * the queue at once, a running one is retired after the interval in flight,
+ * freeing its slot and budget; either ends in state 4 with no result.
+ * Finished jobs are left as they are.  HD_EINVAL for an unknown id. */
+int hd_server_cancel(hd_server* s, uint64_t job_id);
 
 /* Stops after the queued and running jobs finish, then releases everything.
  * NULL-safe. */

@@ -1597,6 +1597,7 @@ struct Job {
   JobResult res;
   int prep_state = 0;           // host preparation: 0 not started, 1 running, 2 done
   std::shared_ptr<void> prep;   // the prepared host state (the server's type)
+  std::atomic<bool> cancel{false};  // running job to retire after the interval in flight
 };
 
 struct ServerBase {
@@ -1605,6 +1606,7 @@ struct ServerBase {
   virtual int poll(uint64_t id, int32_t* state, hd_moment_set* out, double* times) = 0;
   virtual int stats(hd_server_counters* out) = 0;
   virtual int drain(double timeout_s) = 0;
+  virtual int cancel(uint64_t id) = 0;
 };
 
 template <class P>
@@ -1637,7 +1639,7 @@ struct Server : ServerBase {
   std::deque<Job*> queue;
   uint64_t next_job = 1;
   size_t used = 0;
-  uint64_t chunks = 0, pushed_done = 0, completed = 0, failed = 0;
+  uint64_t chunks = 0, pushed_done = 0, completed = 0, failed = 0, cancelled = 0;
   double busy_s = 0, t_start = 0;
 
   // A job's host-side state, prepared ahead of admission.
@@ -1885,8 +1887,13 @@ struct Server : ServerBase {
     std::lock_guard<std::mutex> g(mu);
     job->t_done = now_s();
     job->err = st.error ? st.error : rc;
-    job->state = job->err ? 3 : 2;
-    (job->err ? failed : completed) += 1;
+    if (job->cancel) {
+      job->state = 4;
+      cancelled += 1;
+    } else {
+      job->state = job->err ? 3 : 2;
+      (job->err ? failed : completed) += 1;
+    }
     pushed_done += st.pushed;
     used -= job->bytes;
     slot_job[slot] = nullptr;
@@ -1939,7 +1946,7 @@ struct Server : ServerBase {
         Job* j = slot_job[s];
         if (!j) continue;
         slot_done[s] += cfg.sort_every;
-        if (slot_done[s] >= j->n_steps) {
+        if (slot_done[s] >= j->n_steps || j->cancel) {
           const int rc = retire(s);
           if (rc) return set_error(rc, g_err);
         }
@@ -1964,7 +1971,7 @@ struct Server : ServerBase {
       times[1] = j->state >= 2 ? j->t_done - j->t_submit : -1.0;
       times[2] = j->state >= 2 ? j->t_done - j->t_admit : -1.0;
     }
-    if (j->state < 2 || !out) return HD_OK;
+    if (j->state < 2 || j->state == 4 || !out) return HD_OK;  // no result (yet)
     const hd_moment_set& m = j->res.m;
     double* arr_out[] = {out->n_e, out->n_i, out->phi, out->E, out->gamma_i, out->n_e_avg,
                          out->n_i_avg};
@@ -2004,7 +2011,28 @@ struct Server : ServerBase {
     out->busy_s = busy_s;
     out->wall_s = now_s() - t_start;
     out->error = worker_err;
+    out->cancelled = (int32_t)cancelled;
     return worker_err ? fail(worker_err, worker_msg) : HD_OK;
+  }
+
+  // A queued job leaves the queue at once; a running one is retired after
+  // the interval in flight (its slot and bytes freed, no result kept).
+  int cancel(uint64_t id) override {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = jobs.find(id);
+    if (it == jobs.end()) return fail(HD_EINVAL, "unknown job");
+    Job* j = it->second.get();
+    if (j->state == 0) {
+      auto q = std::find(queue.begin(), queue.end(), j);
+      if (q != queue.end()) queue.erase(q);
+      j->state = 4;
+      j->t_done = now_s();
+      cancelled += 1;
+      cv.notify_all();
+    } else if (j->state == 1) {
+      j->cancel = true;
+    }
+    return HD_OK;
   }
 
   int drain(double timeout_s) override {
@@ -2465,6 +2493,11 @@ int hd_server_stats(hd_server* s, hd_server_counters* out) {
 int hd_server_drain(hd_server* s, double timeout_s) {
   if (!s) return hd::fail(HD_EINVAL, "null handle");
   return s->impl->drain(timeout_s);
+}
+
+int hd_server_cancel(hd_server* s, uint64_t job_id) {
+  if (!s) return hd::fail(HD_EINVAL, "null server");
+  return s->impl->cancel(job_id);
 }
 
 int hd_server_free(hd_server* s) {

@@ -31,7 +31,7 @@ SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_disc
            "hd_diag_arith", "hd_swarm_create", "hd_swarm_run", "hd_swarm_results",
            "hd_swarm_get_ions", "hd_swarm_free", "hd_batch_get_launch", "hd_batch_set_launch",
            "hd_batch_autotune", "hd_get_launch", "hd_set_launch", "hd_autotune", "hd_grow",
-           "hd_save", "hd_restore",
+           "hd_save", "hd_restore", "hd_server_cancel",
            "hd_swarm_run_noalloc"]
 
 
@@ -144,7 +144,7 @@ class ServerCounters(C.Structure):
                 ("queued", C.c_uint64), ("running", C.c_uint64), ("intervals", C.c_uint64),
                 ("particle_steps", C.c_uint64), ("bytes_in_use", C.c_uint64),
                 ("busy_s", C.c_double), ("wall_s", C.c_double), ("error", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("cancelled", C.c_int32)]
 
 
 _lib = None
@@ -185,6 +185,7 @@ def lib():
                                      C.POINTER(MomentSet), vp]
         L.hd_server_stats.argtypes = [vp, C.POINTER(ServerCounters)]
         L.hd_server_drain.argtypes = [vp, C.c_double]
+        L.hd_server_cancel.argtypes = [vp, C.c_uint64]
         L.hd_server_free.argtypes = [vp]
         L.hd_swarm_create.argtypes = [C.POINTER(SwarmParams), C.POINTER(DeviceCtx),
                                       C.POINTER(vp)]
@@ -490,7 +491,8 @@ class Server:
         return jid.value
 
     def poll(self, job_id: int):
-        """(state, times[3], moments or None); state 0 queued, 1 running, 2 done, 3 failed."""
+        """(state, times[3], moments or None); state 0 queued, 1 running, 2 done, 3 failed,
+        4 cancelled."""
         p = self.jobs[job_id]
         M = _Moments(p["n_cells"] + 1, p["n_eedf_bins"], len(p["channels"]),
                      max(1, len(p.get("species", []))))
@@ -503,7 +505,11 @@ class Server:
     def stats(self) -> dict:
         c = ServerCounters()
         _check(lib().hd_server_stats(self.h, C.byref(c)))
-        return {k: getattr(c, k) for k, _ in ServerCounters._fields_ if k != "reserved"}
+        return {k: getattr(c, k) for k, _ in ServerCounters._fields_}
+
+    def cancel(self, job_id: int):
+        """Cancel a queued or running job (state 4, no result)."""
+        _check(lib().hd_server_cancel(self.h, int(job_id)))
 
     def drain(self, timeout_s: float = 600.0):
         _check(lib().hd_server_drain(self.h, float(timeout_s)))

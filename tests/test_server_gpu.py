@@ -80,6 +80,41 @@ def test_jobs_beyond_the_mall_equal_alone():
     srv.close()
 
 
+def test_cancel_queued_and_running_jobs():
+    # One slot: the first job runs and the others queue.  A cancelled queued
+    # job leaves at once; the cancelled running job is retired after the
+    # interval in flight and the next job is admitted.  The job that was not
+    # cancelled still equals its run alone; cancelling a finished job leaves
+    # it as it is.
+    srv = hd.Server(precision=0, max_slots=1, max_cells=128)
+    long = srv.submit(_job(128, 20000, 51, 200.0), 100_000)
+    mid = srv.submit(_job(64, 3000, 52, 150.0), 48)
+    late = srv.submit(_job(64, 3000, 53, 150.0), 48)
+    t_end = time.time() + 60
+    while srv.poll(long)[0] != 1 and time.time() < t_end:
+        time.sleep(0.002)
+    assert srv.poll(long)[0] == 1
+    srv.cancel(late)
+    assert srv.poll(late)[0] == 4
+    srv.cancel(long)
+    srv.drain(120)
+    st = srv.stats()
+    assert st["cancelled"] == 2 and st["completed"] == 1 and st["failed"] == 0
+    state, _, res = srv.poll(long)
+    assert state == 4 and res is None
+    state, _, mix = srv.poll(mid)
+    assert state == 2
+    alone = hd.Discharge(_job(64, 3000, 52, 150.0))
+    alone.step(48)
+    _same(mix, alone.moments())
+    alone.close()
+    srv.cancel(mid)
+    assert srv.poll(mid)[0] == 2
+    with pytest.raises(hd.HdError):
+        srv.cancel(10 ** 9)
+    srv.close()
+
+
 def test_admission_respects_budget():
     p = _job(128, 8000, 31, 150.0)
     one = hd.required_bytes(p)
