@@ -236,6 +236,15 @@ def batched(a):
     secs = time.perf_counter() - t0
     p1 = sum(b.moments(i)["pushed"] for i in range(len(ps)))
     value = (p1 - p0) / secs
+    # the electron launch of the whole batch against the roofline, as for
+    # the single discharge
+    m1 = [b.moments(i) for i in range(len(ps))]
+    kms = b.profile_steps(a.profile_steps)
+    m2 = [b.moments(i) for i in range(len(ps))]
+    n_push = sum(y["pushed"] - x["pushed"] for x, y in zip(m1, m2)) / a.profile_steps
+    n_coll = sum(float(y["coll"].sum() - x["coll"].sum()) for x, y in zip(m1, m2)) / a.profile_steps
+    alg_bytes = 36.0 * n_push + 8.0 * n_coll
+    achieved = alg_bytes / (kms["electron"] * 1e-3) / 1e9
     b.close()
     del b
     sep = None
@@ -263,6 +272,10 @@ def batched(a):
         "config": {"workload": "batched sweep: %d He discharges, gaps U(0.3,2) mm, 256-4096 "
                                "cells, 100-400 V, %d FP32 electrons in total, DD ions, one "
                                "launch per phase" % (len(ps), a.total_electrons)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_electron",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": kms["electron"]},
+        "kernel_ms": kms,
         "one_launch_per_discharge": sep,
         "launch": launch,
     }

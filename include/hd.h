@@ -548,6 +548,8 @@ int hd_swarm_run_noalloc(const hd_swarm_params* params, int64_t n_relax, int64_t
  * [2] append, [3] compaction + sort (mean over the sorts that ran, 0 if
  * none), [4] whole step.  Used to price the kernels against the roofline. */
 int hd_profile_steps(hd_discharge* h, int64_t n_steps, double* out_ms);
+/* The same for a batch (every discharge advances by n_steps). */
+int hd_batch_profile_steps(hd_batch* b, int64_t n_steps, double* out_ms);
 
 /* Evaluates, on the device, the correctly-rounded primitives the particle
  * arithmetic relies on, for n inputs: out[4k+0] = sqrt(a[k]),

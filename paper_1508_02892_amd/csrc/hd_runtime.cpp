@@ -2512,6 +2512,11 @@ int hd_profile_steps(hd_discharge* h, int64_t n, double* out_ms) {
   return dispatch(h->b.impl, [&](auto* x) { return x->profile(n, out_ms); });
 }
 
+int hd_batch_profile_steps(hd_batch* b, int64_t n, double* out_ms) {
+  if (!b) return hd::fail(HD_EINVAL, "null handle");
+  return dispatch(b->impl, [&](auto* x) { return x->profile(n, out_ms); });
+}
+
 int hd_grow(hd_discharge* h, int64_t new_capacity) {
   if (!h) return hd::fail(HD_EINVAL, "null handle");
   return dispatch(h->b.impl, [&](auto* x) { return x->grow(new_capacity); });

@@ -31,7 +31,7 @@ SYMBOLS = ["hd_abi_version", "hd_last_error", "hd_required_bytes", "hd_init_disc
            "hd_diag_arith", "hd_swarm_create", "hd_swarm_run", "hd_swarm_results",
            "hd_swarm_get_ions", "hd_swarm_free", "hd_batch_get_launch", "hd_batch_set_launch",
            "hd_batch_autotune", "hd_get_launch", "hd_set_launch", "hd_autotune", "hd_grow",
-           "hd_save", "hd_restore", "hd_server_cancel",
+           "hd_save", "hd_restore", "hd_server_cancel", "hd_batch_profile_steps",
            "hd_swarm_run_noalloc"]
 
 
@@ -177,6 +177,7 @@ def lib():
         L.hd_batch_free.argtypes = [vp]
         L.hd_diag_arith.argtypes = [C.c_int32, C.c_int64, vp, vp, vp, C.POINTER(DeviceCtx)]
         L.hd_profile_steps.argtypes = [vp, C.c_int64, vp]
+        L.hd_batch_profile_steps.argtypes = [vp, C.c_int64, vp]
         L.hd_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(DeviceCtx),
                                        C.POINTER(vp)]
         L.hd_server_submit.argtypes = [vp, C.POINTER(Params), C.c_int64,
@@ -435,6 +436,12 @@ class Batch:
         c = LaunchConfig()
         _check(lib().hd_batch_autotune(self.h, int(max_steps), C.byref(c)))
         return _launch_dict(c)
+
+    def profile_steps(self, n: int) -> dict:
+        """Advance n real steps with per-kernel HIP events; mean ms per kernel."""
+        out = np.zeros(5)
+        _check(lib().hd_batch_profile_steps(self.h, int(n), _ptr(out)))
+        return dict(zip(["electron", "finalize_field", "append", "sort", "step"], out.tolist()))
 
     def moments(self, i: int) -> dict:
         p = self.params[i]
