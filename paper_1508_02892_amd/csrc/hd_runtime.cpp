@@ -46,7 +46,8 @@ hipError_t finalize_set_lds(int nn_max);
 template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s);
 template <class P>
-hipError_t sort_set_lds(int nc_max);
+hipError_t sort_set_lds(int nc_max, int D);
+size_t sort_lds_bytes(int nc_max, int D);
 template <class P>
 hipError_t launch_checkpoint(const Disch<P>* d_dev, int D, int restore, int grid, hipStream_t s);
 size_t sort_parts(size_t nc, size_t tiles);
@@ -818,9 +819,9 @@ struct Batch : BatchBase {
       return fail(HD_EINVAL, "electron kernel needs " + std::to_string(lds) +
                                  " B of LDS, device allows " +
                                  std::to_string(prop.sharedMemPerBlock));
-    const size_t slds = (size_t)4 * (nc_max + 1) * 4;
-    if (slds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "sort LDS too large");
-    HD_TRY(sort_set_lds<P>(nc_max));
+    if (sort_lds_bytes(nc_max, D) > (size_t)prop.sharedMemPerBlock)
+      return fail(HD_EINVAL, "sort LDS too large");
+    HD_TRY(sort_set_lds<P>(nc_max, D));
     HD_TRY(finalize_set_lds<P>(nn_max));
     cus = prop.multiProcessorCount;
     {
@@ -1704,7 +1705,7 @@ struct Server : ServerBase {
     HD_TRY(hipGetDeviceProperties(&prop, device));
     const size_t lds = electron_lds_bytes<P>(S, tab_max, nn_max, nb1_max, fluid_nn, K_max);
     if (lds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "slot caps exceed LDS");
-    HD_TRY(sort_set_lds<P>(nc_max));
+    HD_TRY(sort_set_lds<P>(nc_max, S));
     HD_TRY(finalize_set_lds<P>(nn_max));
     const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, S, 0);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");

@@ -569,11 +569,17 @@ __device__ void append_blocks(const Disch<P>* __restrict__ ds, int D) {
   __shared__ int gave_up;  // a wait timed out: wait for no further discharge
   const uint32_t tid = threadIdx.x, lane = tid & 63u;
   if (tid == 0) gave_up = 0;
+  // The append workgroups form groups of G, each group serving every
+  // groups-th discharge: all of them on one discharge when it is alone, one
+  // per discharge when the batch has as many discharges as workgroups, so
+  // that a batch's discharges are appended side by side, not one by one.
   const uint32_t ab = blockIdx.x - (uint32_t)D, nab = gridDim.x - (uint32_t)D;
-  const uint32_t wave = (ab * (uint32_t)kFinThreads + tid) >> 6;
-  const uint32_t nwaves = nab * (uint32_t)(kFinThreads / 64);
-  const uint32_t gid = ab * (uint32_t)kFinThreads + tid, gsz = nab * (uint32_t)kFinThreads;
-  for (int di = 0; di < D; ++di) {
+  const uint32_t G = max(1u, nab / (uint32_t)D), groups = nab / G, gi = ab / G, gr = ab % G;
+  if (gi >= groups) return;  // the remainder of nab / G: no group
+  const uint32_t wave = (gr * (uint32_t)kFinThreads + tid) >> 6;
+  const uint32_t nwaves = G * (uint32_t)(kFinThreads / 64);
+  const uint32_t gid = gr * (uint32_t)kFinThreads + tid, gsz = G * (uint32_t)kFinThreads;
+  for (int di = (int)gi; di < D; di += (int)groups) {
     const Disch<P>& d = ds[di];
     State* st = d.st;
     if (tid == 0) {
@@ -627,7 +633,7 @@ __device__ void append_blocks(const Disch<P>* __restrict__ ds, int D) {
     }
     __syncthreads();
     if (tid == 0) {
-      if (atomicAdd(&st->app_done, 1u) == nab - 1u) {  // the last: re-arm for the next launch
+      if (atomicAdd(&st->app_done, 1u) == G - 1u) {  // the group's last: re-arm for the next launch
         st->app_done = 0u;
         __hip_atomic_store(&st->fin_ready, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }

@@ -29,121 +29,6 @@ __device__ __forceinline__ uint32_t n_tiles(const Disch<P>& d) {
   return (d.st->n_main + (uint32_t)kSortTile - 1u) / (uint32_t)kSortTile;
 }
 
-template <class P>
-__global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restrict__ ds, int D,
-                                                         int stride) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int sh_lo[kWavesPerBlock], sh_hi[kWavesPerBlock];
-  constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int di = 0; di < D; ++di) {
-    const Disch<P>& d = ds[di];
-    const State* st = d.st;
-    if (!st->sort_due) continue;
-    const uint32_t n = st->n_main, nt = n_tiles(d);
-    const int nc = d.nc;
-    // each wave owns stride (>= nc + 1) words for the whole launch
-    uint32_t* run = reinterpret_cast<uint32_t*>(smem);
-    uint32_t* h = run + (size_t)wv * (size_t)stride;
-    const Gp<int32_t>* cell = gptr(d.cell[st->buf]);
-    Gp<uint32_t>* hist = gptr(d.hist);
-    for (int c = lane; c < nc; c += 64) h[c] = 0u;
-    // The four waves of a workgroup share a tile, a quarter each, so that a
-    // tile's loads and counts are spread over four waves rather than
-    // serialised in one.
-    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
-      const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
-      const uint32_t e = min(n, b + kQuarter);
-      // 4 consecutive slots per lane per 256-slot round, all rounds loaded
-      // before they are counted (the capacity is a multiple of the tile, so
-      // every vector load stays inside the array)
-      constexpr int kRounds = (int)(kQuarter / 256u);
-      int32_t c4[kRounds][4];
-#pragma unroll
-      for (int q = 0; q < kRounds; ++q) {
-        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
-        if (i < e) gld4(cell + i, c4[q]);
-      }
-      // the tile's cell range first
-      int lo = nc, hi = -1;
-#pragma unroll
-      for (int q = 0; q < kRounds; ++q) {
-        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int c = c4[q][k];
-          if (i + (uint32_t)k < e && c >= 0) {
-            lo = min(lo, c);
-            hi = max(hi, c);
-          }
-        }
-      }
-      lo = wave_min_i32(lo);
-      hi = wave_max_i32(hi);
-      if (lane == 0) {
-        sh_lo[wv] = lo;
-        sh_hi[wv] = hi;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) {
-        lo = min(lo, sh_lo[w]);
-        hi = max(hi, sh_hi[w]);
-      }
-      // Cells lo .. lo + 7 are counted in 8-bit fields of one register per
-      // lane (at most 16 items per lane), then in 16-bit fields summed over
-      // the wave (at most kQuarter per cell); other cells go straight to the
-      // wave's histogram.  With nearly sorted cells an atomic per item would
-      // have all 64 lanes on one address.
-      uint64_t a8 = 0;
-#pragma unroll
-      for (int q = 0; q < kRounds; ++q) {
-        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int c = c4[q][k];
-          if (i + (uint32_t)k < e && c >= 0) {
-            const uint32_t o = (uint32_t)(c - lo);
-            if (o < 8u)
-              a8 += 1ull << (8u * o);
-            else
-              atomicAdd(&h[c], 1u);
-          }
-        }
-      }
-      const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
-      const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
-                                       ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
-      const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
-                                       ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
-      if (lane < 8 && lo + lane < nc) {
-        const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
-        if (v) h[lo + lane] += v;
-      }
-      __syncthreads();
-      // the tile's count of each cell: the sum over the four waves
-      for (int c = lo + (int)threadIdx.x; c <= hi; c += kThreads) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-          v += run[w * stride + c];
-          run[w * stride + c] = 0u;
-        }
-        if (v) {
-          hist[(size_t)c * nt + t] = v;
-          // the total of the scan block holding this entry
-          atomicAdd(&d.bin_start[((size_t)c * nt + t) / (size_t)kScanBlock], v);
-        }
-      }
-      if (threadIdx.x == 0) {
-        gptr(d.tile_rng)[2 * t] = lo;
-        gptr(d.tile_rng)[2 * t + 1] = hi;
-      }
-      __syncthreads();  // histograms and ranges are reused by the next tile
-    }
-  }
-}
-
 // kScanItems consecutive matrix entries from base (a multiple of 16), as
 // 16-byte vectors where the whole vector lies below n.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -223,42 +108,205 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t (&v)[kScanItems], u
   return tot;
 }
 
+// Work units (sort tiles, scan blocks) of all discharges due for a sort are
+// numbered one after another, so that the workgroups of a launch share the
+// whole batch's work whatever the sizes of its discharges (taking the
+// discharges in turn left most workgroups idle on the small ones): the
+// first unit of discharge i is pre[i] and the total pre[D], in LDS
+// (D + 1 words), computed by every workgroup from the discharges' states.
+template <class P>
+__device__ __forceinline__ uint32_t tiles_due(const Disch<P>& d) {
+  return d.st->sort_due ? n_tiles(d) : 0u;
+}
+template <class P>
+__device__ __forceinline__ uint32_t scan_blocks(const Disch<P>& d) {
+  const uint64_t n = (uint64_t)d.nc * n_tiles(d);
+  return (uint32_t)((n + kScanBlock - 1) / kScanBlock);
+}
+template <class P>
+__device__ __forceinline__ uint32_t scan_blocks_due(const Disch<P>& d) {
+  return d.st->sort_due ? scan_blocks(d) : 0u;
+}
+template <class P, class U>
+__device__ void unit_prefix(const Disch<P>* __restrict__ ds, int D, uint32_t* pre, U units) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    uint32_t carry = 0;
+    for (int b = 0; b < D; b += 64) {
+      const int i = b + lane;
+      const uint32_t v = i < D ? units(ds[i]) : 0u;
+      const uint32_t inc = wave_incl_scan(v);
+      if (i < D) pre[i + 1] = carry + inc;
+      carry += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) pre[0] = 0u;
+  }
+  __syncthreads();
+}
+
+template <class P>
+__global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restrict__ ds, int D,
+                                                         int stride) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sh_lo[kWavesPerBlock], sh_hi[kWavesPerBlock];
+  constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // each wave owns stride (>= the largest nc + 1) words for the whole
+  // launch, zero between tiles; the unit prefix follows them
+  uint32_t* run = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* h = run + (size_t)wv * (size_t)stride;
+  uint32_t* pre = run + (size_t)kWavesPerBlock * (size_t)stride;
+  for (int c = lane; c < stride; c += 64) h[c] = 0u;
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due(d); });
+  const uint32_t total = pre[D];
+  int di = 0;
+  // The four waves of a workgroup share a tile, a quarter each, so that a
+  // tile's loads and counts are spread over four waves rather than
+  // serialised in one.
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+    while (pre[di + 1] <= g) ++di;
+    const Disch<P>& d = ds[di];
+    const State* st = d.st;
+    const uint32_t t = g - pre[di];
+    const uint32_t n = st->n_main, nt = n_tiles(d);
+    const int nc = d.nc;
+    const Gp<int32_t>* cell = gptr(d.cell[st->buf]);
+    Gp<uint32_t>* hist = gptr(d.hist);
+    const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
+    const uint32_t e = min(n, b + kQuarter);
+    // 4 consecutive slots per lane per 256-slot round, all rounds loaded
+    // before they are counted (the capacity is a multiple of the tile, so
+    // every vector load stays inside the array)
+    constexpr int kRounds = (int)(kQuarter / 256u);
+    int32_t c4[kRounds][4];
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+      const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+      if (i < e) gld4(cell + i, c4[q]);
+    }
+    // the tile's cell range first
+    int lo = nc, hi = -1;
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+      const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = c4[q][k];
+        if (i + (uint32_t)k < e && c >= 0) {
+          lo = min(lo, c);
+          hi = max(hi, c);
+        }
+      }
+    }
+    lo = wave_min_i32(lo);
+    hi = wave_max_i32(hi);
+    if (lane == 0) {
+      sh_lo[wv] = lo;
+      sh_hi[wv] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) {
+      lo = min(lo, sh_lo[w]);
+      hi = max(hi, sh_hi[w]);
+    }
+    // Cells lo .. lo + 7 are counted in 8-bit fields of one register per
+    // lane (at most 16 items per lane), then in 16-bit fields summed over
+    // the wave (at most kQuarter per cell); other cells go straight to the
+    // wave's histogram.  With nearly sorted cells an atomic per item would
+    // have all 64 lanes on one address.
+    uint64_t a8 = 0;
+#pragma unroll
+    for (int q = 0; q < kRounds; ++q) {
+      const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = c4[q][k];
+        if (i + (uint32_t)k < e && c >= 0) {
+          const uint32_t o = (uint32_t)(c - lo);
+          if (o < 8u)
+            a8 += 1ull << (8u * o);
+          else
+            atomicAdd(&h[c], 1u);
+        }
+      }
+    }
+    const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
+    const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
+                                     ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
+    const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
+                                     ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
+    if (lane < 8 && lo + lane < nc) {
+      const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
+      if (v) h[lo + lane] += v;
+    }
+    __syncthreads();
+    // the tile's count of each cell: the sum over the four waves
+    for (int c = lo + (int)threadIdx.x; c <= hi; c += kThreads) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        v += run[w * stride + c];
+        run[w * stride + c] = 0u;
+      }
+      if (v) {
+        hist[(size_t)c * nt + t] = v;
+        // the total of the scan block holding this entry
+        atomicAdd(&d.bin_start[((size_t)c * nt + t) / (size_t)kScanBlock], v);
+      }
+    }
+    if (threadIdx.x == 0) {
+      gptr(d.tile_rng)[2 * t] = lo;
+      gptr(d.tile_rng)[2 * t + 1] = hi;
+    }
+    __syncthreads();  // histograms and ranges are reused by the next tile
+  }
+}
+
 template <class P>
 __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restrict__ ds, int D) {
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t sh[kWavesPerBlock];
   __shared__ uint32_t sh_off[kWavesPerBlock];
-  for (int di = 0; di < D; ++di) {
+  uint32_t* pre = reinterpret_cast<uint32_t*>(smem);
+  // a discharge due for a sort with no slots in use sorts to nothing
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < D; i += kThreads) {
+      State* st = ds[i].st;
+      if (st->sort_due && scan_blocks(ds[i]) == 0) st->n_live_sorted = 0;
+    }
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return scan_blocks_due(d); });
+  const uint32_t total = pre[D];
+  int di = 0;
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+    while (pre[di + 1] <= g) ++di;
     const Disch<P>& d = ds[di];
     State* st = d.st;
-    if (!st->sort_due) continue;
     const uint64_t n = (uint64_t)d.nc * n_tiles(d);
-    const uint32_t nb = (uint32_t)((n + kScanBlock - 1) / kScanBlock);
-    if (nb == 0 && blockIdx.x == 0 && threadIdx.x == 0) st->n_live_sorted = 0;
-    for (uint32_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
-      uint32_t v[kScanItems];
-      const uint64_t base = (uint64_t)blk * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
-      load_items(gptr(d.hist), base, n, v);
-      // the block's offset: the totals of the blocks before it (each block
-      // sums them itself instead of a separate pass scanning the totals)
-      uint32_t part = 0;
-      for (uint32_t b2 = threadIdx.x; b2 < blk; b2 += (uint32_t)kThreads) part += d.bin_start[b2];
-      part = wave_sum_u32(part);
-      if ((threadIdx.x & 63) == 0) sh_off[threadIdx.x >> 6] = part;
-      uint32_t cnt[kScanItems];
+    const uint32_t nb = pre[di + 1] - pre[di], blk = g - pre[di];
+    uint32_t v[kScanItems];
+    const uint64_t base = (uint64_t)blk * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
+    load_items(gptr(d.hist), base, n, v);
+    // the block's offset: the totals of the blocks before it (each block
+    // sums them itself instead of a separate pass scanning the totals)
+    uint32_t part = 0;
+    for (uint32_t b2 = threadIdx.x; b2 < blk; b2 += (uint32_t)kThreads) part += d.bin_start[b2];
+    part = wave_sum_u32(part);
+    if ((threadIdx.x & 63) == 0) sh_off[threadIdx.x >> 6] = part;
+    uint32_t cnt[kScanItems];
 #pragma unroll
-      for (int k = 0; k < kScanItems; ++k) cnt[k] = v[k];
-      const uint32_t tot = block_excl_scan(v, sh);  // its barriers also publish sh_off
-      uint32_t off = 0;
+    for (int k = 0; k < kScanItems; ++k) cnt[k] = v[k];
+    const uint32_t tot = block_excl_scan(v, sh);  // its barriers also publish sh_off
+    uint32_t off = 0;
 #pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) off += sh_off[w];
-      if (blk == nb - 1 && threadIdx.x == 0) st->n_live_sorted = off + tot;
-      // an empty (cell, tile) keeps 0: no item reads its start, and the
-      // matrix is then zero again once the scatter has read the others
+    for (int w = 0; w < kWavesPerBlock; ++w) off += sh_off[w];
+    if (blk == nb - 1 && threadIdx.x == 0) st->n_live_sorted = off + tot;
+    // an empty (cell, tile) keeps 0: no item reads its start, and the
+    // matrix is then zero again once the scatter has read the others
 #pragma unroll
-      for (int k = 0; k < kScanItems; ++k) v[k] = cnt[k] ? v[k] + off : 0u;
-      store_items(gptr(d.hist), base, n, v, cnt);
-      __syncthreads();  // sh_off is rewritten for the next block
-    }
+    for (int k = 0; k < kScanItems; ++k) v[k] = cnt[k] ? v[k] + off : 0u;
+    store_items(gptr(d.hist), base, n, v, cnt);
+    __syncthreads();  // sh_off is rewritten for the next block
   }
 }
 
@@ -269,15 +317,27 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
   constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint64_t lt = lanemask_lt();
+  // run[w][c - lo]: cursor of wave w for cell c; the unit prefix follows
+  uint32_t* run = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* pre = run + (size_t)kWavesPerBlock * (size_t)stride;
+  // the scan blocks' totals are zero again for the next sort's counts
   for (int di = 0; di < D; ++di) {
     const Disch<P>& d = ds[di];
+    if (!d.st->sort_due) continue;
+    const uint32_t nb = scan_blocks(d);
+    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nb; i += gridDim.x * kThreads) d.bin_start[i] = 0u;
+  }
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due(d); });
+  const uint32_t total = pre[D];
+  int di = 0;
+  for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
+    while (pre[di + 1] <= g) ++di;
+    const Disch<P>& d = ds[di];
     const State* st = d.st;
-    if (!st->sort_due) continue;
+    const uint32_t t = g - pre[di];
     const uint32_t n = st->n_main, nt = n_tiles(d);
     const int nc = d.nc;
     const int nbits = 32 - __clz((uint32_t)nc);  // keys 0 .. nc (nc marks a hole)
-    // run[w][c - lo]: cursor of wave w for cell c
-    uint32_t* run = reinterpret_cast<uint32_t*>(smem);
     const int src = st->buf, dst = src ^ 1;
     const Gp<int32_t>* cell = gptr(d.cell[src]);
     const Gp<P>* s_off = gptr(d.off[src]);
@@ -291,132 +351,126 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     Gp<P>* d_vy = gptr(d.vy[dst]);
     Gp<P>* d_vz = gptr(d.vz[dst]);
     Gp<uint32_t>* d_id = gptr(d.id[dst]);
-    {  // the scan blocks' totals are zero again for the next sort's counts
-      const uint32_t nb = (uint32_t)(((uint64_t)nc * nt + kScanBlock - 1) / kScanBlock);
-      for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nb; i += gridDim.x * kThreads) d.bin_start[i] = 0u;
+    const int lo = gptr(d.tile_rng)[2 * t], hi = gptr(d.tile_rng)[2 * t + 1];
+    const int span = hi - lo + 1;  // 0 for a tile of holes only
+    const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
+    const uint32_t e = min(n, b + kQuarter);
+    uint32_t* myrun = run + wv * stride;
+    // counts of this wave's quarter
+    for (int c = lane; c < span; c += 64) myrun[c] = 0u;
+    __builtin_amdgcn_wave_barrier();
+    {
+      constexpr int kRounds = (int)(kQuarter / 256u);
+      int32_t c4[kRounds][4];
+#pragma unroll
+      for (int q = 0; q < kRounds; ++q) {
+        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+        if (i < e) gld4(cell + i, c4[q]);
+      }
+      // cells lo .. lo + 7 in packed fields as in the count (at most 16
+      // items per lane, kQuarter per cell), the others by atomics
+      uint64_t a8 = 0;
+#pragma unroll
+      for (int q = 0; q < kRounds; ++q) {
+        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (i + (uint32_t)k < e && c4[q][k] >= 0) {
+            const uint32_t o = (uint32_t)(c4[q][k] - lo);
+            if (o < 8u)
+              a8 += 1ull << (8u * o);
+            else
+              atomicAdd(&myrun[o], 1u);
+          }
+      }
+      const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
+      const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
+                                       ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
+      const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
+                                       ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
+      if (lane < 8) {
+        const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
+        if (v) myrun[lane] += v;
+      }
     }
-    for (uint32_t t = blockIdx.x; t < nt; t += gridDim.x) {
-      const int lo = gptr(d.tile_rng)[2 * t], hi = gptr(d.tile_rng)[2 * t + 1];
-      const int span = hi - lo + 1;  // 0 for a tile of holes only
-      const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
-      const uint32_t e = min(n, b + kQuarter);
-      uint32_t* myrun = run + wv * stride;
-      // counts of this wave's quarter
-      for (int c = lane; c < span; c += 64) myrun[c] = 0u;
-      __builtin_amdgcn_wave_barrier();
-      {
-        constexpr int kRounds = (int)(kQuarter / 256u);
-        int32_t c4[kRounds][4];
+    __syncthreads();
+    // cursors: the tile's first slot for the cell, then the earlier waves
+    // (only cells present in the tile: the range can be wide and sparse)
+    for (int c = threadIdx.x; c < span; c += kThreads) {
+      uint32_t k[kWavesPerBlock], tot = 0;
 #pragma unroll
-        for (int q = 0; q < kRounds; ++q) {
-          const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
-          if (i < e) gld4(cell + i, c4[q]);
-        }
-        // cells lo .. lo + 7 in packed fields as in the count (at most 16
-        // items per lane, kQuarter per cell), the others by atomics
-        uint64_t a8 = 0;
-#pragma unroll
-        for (int q = 0; q < kRounds; ++q) {
-          const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (i + (uint32_t)k < e && c4[q][k] >= 0) {
-              const uint32_t o = (uint32_t)(c4[q][k] - lo);
-              if (o < 8u)
-                a8 += 1ull << (8u * o);
-              else
-                atomicAdd(&myrun[o], 1u);
-            }
-        }
-        const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
-        const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
-                                         ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
-        const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
-                                         ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
-        if (lane < 8) {
-          const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
-          if (v) myrun[lane] += v;
-        }
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        k[w] = run[w * stride + c];
+        tot += k[w];
       }
-      __syncthreads();
-      // cursors: the tile's first slot for the cell, then the earlier waves
-      // (only cells present in the tile: the range can be wide and sparse)
-      for (int c = threadIdx.x; c < span; c += kThreads) {
-        uint32_t k[kWavesPerBlock], tot = 0;
+      if (tot == 0) continue;
+      uint32_t r = gptr(d.hist)[(size_t)(lo + c) * nt + t];
+      gptr(d.hist)[(size_t)(lo + c) * nt + t] = 0u;  // zero for the next sort's counts
 #pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-          k[w] = run[w * stride + c];
-          tot += k[w];
-        }
-        if (tot == 0) continue;
-        uint32_t r = gptr(d.hist)[(size_t)(lo + c) * nt + t];
-        gptr(d.hist)[(size_t)(lo + c) * nt + t] = 0u;  // zero for the next sort's counts
-#pragma unroll
-        for (int w = 0; w < kWavesPerBlock; ++w) {
-          run[w * stride + c] = r;
-          r += k[w];
-        }
+      for (int w = 0; w < kWavesPerBlock; ++w) {
+        run[w * stride + c] = r;
+        r += k[w];
       }
-      __syncthreads();
-      // rounds of 64 items whose loads are issued together; the source
-      // arrays are read once, with the nontemporal hint, so that they do not
-      // displace the destination's partly written lines from the caches
-      constexpr int R = 8;
-      for (uint32_t r = b; r < e; r += 64u * R) {
-        int key[R];
-        P o_[R], x_[R], y_[R], z_[R];
-        uint32_t id_[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const uint32_t i = r + 64u * q + (uint32_t)lane;
-          key[q] = nc;
-          if (i < e) {
-            const int c = __builtin_nontemporal_load(cell + i);
-            key[q] = c >= 0 ? c : nc;
-            o_[q] = __builtin_nontemporal_load(s_off + i);
-            x_[q] = __builtin_nontemporal_load(s_vx + i);
-            y_[q] = __builtin_nontemporal_load(s_vy + i);
-            z_[q] = __builtin_nontemporal_load(s_vz + i);
-            id_[q] = __builtin_nontemporal_load(s_id + i);
-          }
-        }
-        uint32_t dest[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const int k = key[q];
-          const int k0 = __builtin_amdgcn_readfirstlane(k);
-          uint64_t peers = ~0ull;
-          if (__ballot(k == k0) != ~0ull) {
-            for (int bit = 0; bit < nbits; ++bit) {
-              const bool on = (k >> bit) & 1;
-              const uint64_t m = __ballot(on);
-              peers &= on ? m : ~m;
-            }
-          }
-          const uint32_t rank = (uint32_t)__popcll(peers & lt);
-          const uint32_t cntk = (uint32_t)__popcll(peers);
-          dest[q] = 0;
-          if (k < nc) {
-            const uint32_t base = myrun[k - lo];
-            if (rank == 0) myrun[k - lo] = base + cntk;
-            dest[q] = base + rank;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          if (key[q] < nc) {
-            const uint32_t o = dest[q];
-            d_cell[o] = key[q];
-            d_off[o] = o_[q];
-            d_vx[o] = x_[q];
-            d_vy[o] = y_[q];
-            d_vz[o] = z_[q];
-            d_id[o] = id_[q];
-          }
-        }
-      }
-      __syncthreads();  // cursors are rewritten for the next tile
     }
+    __syncthreads();
+    // rounds of 64 items whose loads are issued together; the source
+    // arrays are read once, with the nontemporal hint, so that they do not
+    // displace the destination's partly written lines from the caches
+    constexpr int R = 8;
+    for (uint32_t r = b; r < e; r += 64u * R) {
+      int key[R];
+      P o_[R], x_[R], y_[R], z_[R];
+      uint32_t id_[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint32_t i = r + 64u * q + (uint32_t)lane;
+        key[q] = nc;
+        if (i < e) {
+          const int c = __builtin_nontemporal_load(cell + i);
+          key[q] = c >= 0 ? c : nc;
+          o_[q] = __builtin_nontemporal_load(s_off + i);
+          x_[q] = __builtin_nontemporal_load(s_vx + i);
+          y_[q] = __builtin_nontemporal_load(s_vy + i);
+          z_[q] = __builtin_nontemporal_load(s_vz + i);
+          id_[q] = __builtin_nontemporal_load(s_id + i);
+        }
+      }
+      uint32_t dest[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int k = key[q];
+        const int k0 = __builtin_amdgcn_readfirstlane(k);
+        uint64_t peers = ~0ull;
+        if (__ballot(k == k0) != ~0ull) {
+          for (int bit = 0; bit < nbits; ++bit) {
+            const bool on = (k >> bit) & 1;
+            const uint64_t m = __ballot(on);
+            peers &= on ? m : ~m;
+          }
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const uint32_t cntk = (uint32_t)__popcll(peers);
+        dest[q] = 0;
+        if (k < nc) {
+          const uint32_t base = myrun[k - lo];
+          if (rank == 0) myrun[k - lo] = base + cntk;
+          dest[q] = base + rank;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        if (key[q] < nc) {
+          const uint32_t o = dest[q];
+          d_cell[o] = key[q];
+          d_off[o] = o_[q];
+          d_vx[o] = x_[q];
+          d_vy[o] = y_[q];
+          d_vz[o] = z_[q];
+          d_id[o] = id_[q];
+        }
+      }
+    }
+    __syncthreads();  // cursors are rewritten for the next tile
   }
 }
 
@@ -505,9 +559,10 @@ __global__ __launch_bounds__(kThreads) void k_checkpoint(const Disch<P>* __restr
 
 template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
-  const size_t lds = (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u;
+  const size_t pre = (size_t)(D + 1) * 4u;
+  const size_t lds = (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u + pre;
   hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
-  hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), 0, s, d_dev, D);
+  hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), pre, s, d_dev, D);
   hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
   return hipGetLastError();
@@ -520,13 +575,22 @@ hipError_t launch_checkpoint(const Disch<P>* d_dev, int D, int restore, int grid
 }
 
 template <class P>
-hipError_t sort_set_lds(int nc_max) {
-  const int lds = kWavesPerBlock * (nc_max + 1) * 4;
+hipError_t sort_set_lds(int nc_max, int D) {
+  const int pre = (D + 1) * 4;
+  const int lds = kWavesPerBlock * (nc_max + 1) * 4 + pre;
   hipError_t e = hipFuncSetAttribute((const void*)k_sort_count<P>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_scan_down<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          pre);
+  if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_sort_scatter<P>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+// LDS of the sort's count and scatter launches.
+size_t sort_lds_bytes(int nc_max, int D) {
+  return (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u + (size_t)(D + 1) * 4u;
 }
 
 // Scan-partials entries needed per discharge.
@@ -536,7 +600,7 @@ template hipError_t launch_sort_impl<float>(const Disch<float>*, int, int, int, 
 template hipError_t launch_checkpoint<float>(const Disch<float>*, int, int, int, hipStream_t);
 template hipError_t launch_checkpoint<double>(const Disch<double>*, int, int, int, hipStream_t);
 template hipError_t launch_sort_impl<double>(const Disch<double>*, int, int, int, hipStream_t);
-template hipError_t sort_set_lds<float>(int);
-template hipError_t sort_set_lds<double>(int);
+template hipError_t sort_set_lds<float>(int, int);
+template hipError_t sort_set_lds<double>(int, int);
 
 }  // namespace hd
