@@ -46,28 +46,48 @@ struct ElecArgs {
 
 struct Lds {
   uint32_t tab, ep, bins, q, eedf, ctr, pre, total;
+  uint32_t rows;  // collision-table rows held in LDS
 };
 
 // LDS counters: [0, kMaxK) collisions per channel, then these.
 enum { kCtrAbsL = kMaxK, kCtrAbsR, kCtrCreated, kCtrOverflow, kCtrPushed, kCtrN };
 
+// The collision table keeps its first kTabLds rows in LDS, fewer when that
+// would leave room for only one workgroup per CU (many channels, large
+// grids) while the rest of the launch's LDS would allow two: rows above
+// come through the cache, which only the rare fast electrons read.
+constexpr uint32_t kTwoPerCu = (80u << 10) - 1024u;  // LDS per workgroup for two per CU
+constexpr uint32_t kTabMinLds = 128;
+
 template <class P>
 __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
   auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
-  // min(ne, kTabLds) * K of any discharge is at most this
-  const uint32_t tab_lds = (uint32_t)a.tab_max < (uint32_t)(kTabLds * a.K_max)
-                               ? (uint32_t)a.tab_max : (uint32_t)(kTabLds * a.K_max);
-  Lds L;
-  L.tab = 0;
-  L.ep = al(L.tab + tab_lds * (uint32_t)sizeof(P));
-  L.bins = al(L.ep + (uint32_t)a.nn_max * (uint32_t)sizeof(P));
-  L.q = al(L.bins + (uint32_t)a.nn_max * 8u);
-  L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
-  L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
-  L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
-  L.total = al(L.pre + (uint32_t)(a.D + 1) * 4u);
   // a, b, c, r of Eq (2.3) and the reduced system of the partitioned solve
   const uint32_t fluid = a.fluid_nn ? (4u * (uint32_t)a.fluid_nn + 7u * (uint32_t)kTriRed) * 8u : 0u;
+  auto place = [&](uint32_t rows) {
+    // min(ne, rows) * K of any discharge is at most this
+    const uint32_t tab_lds = (uint32_t)a.tab_max < rows * (uint32_t)a.K_max
+                                 ? (uint32_t)a.tab_max : rows * (uint32_t)a.K_max;
+    Lds L;
+    L.rows = rows;
+    L.tab = 0;
+    L.ep = al(L.tab + tab_lds * (uint32_t)sizeof(P));
+    L.bins = al(L.ep + (uint32_t)a.nn_max * (uint32_t)sizeof(P));
+    L.q = al(L.bins + (uint32_t)a.nn_max * 8u);
+    L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
+    L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
+    L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
+    L.total = al(L.pre + (uint32_t)(a.D + 1) * 4u);
+    return L;
+  };
+  Lds L = place((uint32_t)kTabLds);
+  if (L.total > kTwoPerCu && fluid <= kTwoPerCu) {
+    const uint32_t rest = L.total - L.ep;  // everything but the table
+    const uint32_t row = (uint32_t)a.K_max * (uint32_t)sizeof(P);
+    uint32_t rows = rest < kTwoPerCu ? (kTwoPerCu - rest) / row : 0u;
+    rows = rows < kTabMinLds ? kTabMinLds : rows;
+    if (rows < (uint32_t)kTabLds) L = place(rows);
+  }
   if (fluid > L.total) L.total = al(fluid);
   return L;
 }
@@ -579,7 +599,7 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   g.KE = d.KE;
   g.inv_dE = d.inv_dE;
   g.keedf = d.keedf;
-  g.tab_rows = d.ne < kTabLds ? d.ne : kTabLds;
+  g.tab_rows = d.ne < (int)L.rows ? d.ne : (int)L.rows;
   g.nc = d.nc;
   g.ne = d.ne;
   g.K = d.K;
