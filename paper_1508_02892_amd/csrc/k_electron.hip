@@ -82,11 +82,11 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
   };
   Lds L = place((uint32_t)kTabLds);
   if (L.total > kTwoPerCu && fluid <= kTwoPerCu) {
+    // only where fewer rows do make room for a second workgroup
     const uint32_t rest = L.total - L.ep;  // everything but the table
     const uint32_t row = (uint32_t)a.K_max * (uint32_t)sizeof(P);
-    uint32_t rows = rest < kTwoPerCu ? (kTwoPerCu - rest) / row : 0u;
-    rows = rows < kTabMinLds ? kTabMinLds : rows;
-    if (rows < (uint32_t)kTabLds) L = place(rows);
+    const uint32_t rows = rest < kTwoPerCu ? (kTwoPerCu - rest) / row : 0u;
+    if (rows >= kTabMinLds && rows < (uint32_t)kTabLds) L = place(rows);
   }
   if (fluid > L.total) L.total = al(fluid);
   return L;
