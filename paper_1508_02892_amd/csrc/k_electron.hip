@@ -42,6 +42,7 @@ struct ElecArgs {
   int nb1_max;    // max eedf bins + 1
   int fluid_nn;   // max nodes of a full-fluid discharge (its solver lives in LDS), 0 if none
   int K_max;      // max channels
+  int tab_rows;   // collision-table rows held in LDS (tab_rows_lds)
 };
 
 struct Lds {
@@ -52,44 +53,48 @@ struct Lds {
 // LDS counters: [0, kMaxK) collisions per channel, then these.
 enum { kCtrAbsL = kMaxK, kCtrAbsR, kCtrCreated, kCtrOverflow, kCtrPushed, kCtrN };
 
+template <class P>
+__host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
+  auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
+  const uint32_t rows = (uint32_t)a.tab_rows;
+  // min(ne, rows) * K of any discharge is at most this
+  const uint32_t tab_lds = (uint32_t)a.tab_max < rows * (uint32_t)a.K_max
+                               ? (uint32_t)a.tab_max : rows * (uint32_t)a.K_max;
+  Lds L;
+  L.rows = rows;
+  L.tab = 0;
+  L.ep = al(L.tab + tab_lds * (uint32_t)sizeof(P));
+  L.bins = al(L.ep + (uint32_t)a.nn_max * (uint32_t)sizeof(P));
+  L.q = al(L.bins + (uint32_t)a.nn_max * 8u);
+  L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
+  L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
+  L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
+  L.total = al(L.pre + (uint32_t)(a.D + 1) * 4u);
+  // a, b, c, r of Eq (2.3) and the reduced system of the partitioned solve
+  const uint32_t fluid = a.fluid_nn ? (4u * (uint32_t)a.fluid_nn + 7u * (uint32_t)kTriRed) * 8u : 0u;
+  if (fluid > L.total) L.total = al(fluid);
+  return L;
+}
+
 // The collision table keeps its first kTabLds rows in LDS, fewer when that
 // would leave room for only one workgroup per CU (many channels, large
-// grids) while the rest of the launch's LDS would allow two: rows above
-// come through the cache, which only the rare fast electrons read.
+// grids) while fewer rows make room for two: rows above come through the
+// cache, which only the rare fast electrons read.  Chosen on the host.
 constexpr uint32_t kTwoPerCu = (80u << 10) - 1024u;  // LDS per workgroup for two per CU
 constexpr uint32_t kTabMinLds = 128;
 
 template <class P>
-__host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
-  auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
-  // a, b, c, r of Eq (2.3) and the reduced system of the partitioned solve
-  const uint32_t fluid = a.fluid_nn ? (4u * (uint32_t)a.fluid_nn + 7u * (uint32_t)kTriRed) * 8u : 0u;
-  auto place = [&](uint32_t rows) {
-    // min(ne, rows) * K of any discharge is at most this
-    const uint32_t tab_lds = (uint32_t)a.tab_max < rows * (uint32_t)a.K_max
-                                 ? (uint32_t)a.tab_max : rows * (uint32_t)a.K_max;
-    Lds L;
-    L.rows = rows;
-    L.tab = 0;
-    L.ep = al(L.tab + tab_lds * (uint32_t)sizeof(P));
-    L.bins = al(L.ep + (uint32_t)a.nn_max * (uint32_t)sizeof(P));
-    L.q = al(L.bins + (uint32_t)a.nn_max * 8u);
-    L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
-    L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
-    L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
-    L.total = al(L.pre + (uint32_t)(a.D + 1) * 4u);
-    return L;
-  };
-  Lds L = place((uint32_t)kTabLds);
+ElecArgs elec_args(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max) {
+  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max, kTabLds};
+  const Lds L = lds_layout<P>(a);
+  const uint32_t fluid = fluid_nn ? (4u * (uint32_t)fluid_nn + 7u * (uint32_t)kTriRed) * 8u : 0u;
   if (L.total > kTwoPerCu && fluid <= kTwoPerCu) {
-    // only where fewer rows do make room for a second workgroup
     const uint32_t rest = L.total - L.ep;  // everything but the table
-    const uint32_t row = (uint32_t)a.K_max * (uint32_t)sizeof(P);
+    const uint32_t row = (uint32_t)K_max * (uint32_t)sizeof(P);
     const uint32_t rows = rest < kTwoPerCu ? (kTwoPerCu - rest) / row : 0u;
-    if (rows >= kTabMinLds && rows < (uint32_t)kTabLds) L = place(rows);
+    if (rows >= kTabMinLds && rows < (uint32_t)kTabLds) a.tab_rows = (int)rows;
   }
-  if (fluid > L.total) L.total = al(fluid);
-  return L;
+  return a;
 }
 
 __device__ __forceinline__ void lds_add_i64(int64_t* p, uint64_t v) {
@@ -1098,14 +1103,13 @@ struct ElecKernel<double> {
 
 template <class P>
 size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max) {
-  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max};
-  return lds_layout<P>(a).total;
+  return lds_layout<P>(elec_args<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max)).total;
 }
 
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
                                 int nb1_max, int fluid_nn, int K_max, int variant, hipStream_t s) {
-  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max};
+  const ElecArgs a = elec_args<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max);
   const size_t lds = lds_layout<P>(a).total;
   if (variant < 0 || variant >= kElecVariants) return hipErrorInvalidValue;
   hipLaunchKernelGGL(ElecKernel<P>::fn[variant], dim3(grid), dim3(kElecThreads), lds, s, d_dev, a);
