@@ -88,6 +88,8 @@ struct Disch {
   P delta_k[kMaxK];      // elastic recoil 2 m_e / M_target per channel
   int32_t kind[kMaxK];
   int32_t product[kMaxK];  // ion species of an ionization / attachment
+  uint32_t ion_mask;       // bit k: channel k is an ionization
+  uint32_t att_mask;       // bit k: channel k is an attachment
   // FP64 constants of the field, fluid and emission
   double dz, L, w, kp, inv_dz, inv_2dz, hdz_eps, qm_dt, scale_in, scale_wall;
   double mu, nu, mu_full, TN, kappa, M, dt, dt_2dz, dt_dz, e_M_dt, dt_2dzM, hdt, nfloor;

@@ -417,9 +417,13 @@ void derive(Host<P>& h, std::vector<double>& ip, std::vector<P>& tab) {
   }
   h.keedf = (double)p.n_eedf_bins / p.eedf_emax_eV;
   d.keedf = (P)h.keedf;
+  d.ion_mask = 0;
+  d.att_mask = 0;
   for (int k = 0; k < kMaxK; ++k) {
     d.thr[k] = k < K ? (P)p.channels[k].threshold_eV : (P)0;
     d.kind[k] = k < K ? p.channels[k].kind : 0;
+    if (k < K && d.kind[k] == HD_XS_IONIZATION) d.ion_mask |= 1u << k;
+    if (k < K && d.kind[k] == HD_XS_ATTACHMENT) d.att_mask |= 1u << k;
   }
 }
 

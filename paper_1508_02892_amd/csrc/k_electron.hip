@@ -551,6 +551,32 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
   }
 }
 
+// Copies na elements of sa to da and nb of sb to db (LDS), issuing all of a
+// thread's loads of a round before its first store, so that a segment's set-up
+// waits for one memory round trip per round instead of one per element.
+template <class T>
+__device__ __forceinline__ void lds_copy2(T* da, const Gp<T>* sa, int na, T* db,
+                                          const Gp<T>* sb, int nb) {
+  constexpr int B = 8;  // elements per thread and array per round
+  const int tid = threadIdx.x;
+  const int n = na > nb ? na : nb;
+  for (int r = 0; r < n; r += B * kElecThreads) {
+    T va[B], vb[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = r + u * kElecThreads + tid;
+      if (i < na) va[u] = sa[i];
+      if (i < nb) vb[u] = sb[i];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = r + u * kElecThreads + tid;
+      if (i < na) da[i] = va[u];
+      if (i < nb) db[i] = vb[u];
+    }
+  }
+}
+
 // Block-wide exclusive scan of one value per thread (kElecThreads); writes
 // the total to *total.  sh: kWaves words of LDS.
 __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
@@ -609,24 +635,16 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   g.ne = d.ne;
   g.K = d.K;
   g.nbins = d.nbins;
-  uint32_t im = 0;
-  for (int k = 0; k < d.K; ++k) im |= (d.kind[k] == 2 ? 1u : 0u) << k;
-  g.ion_mask = im;
-  uint32_t am = 0;
-  for (int k = 0; k < d.K; ++k) am |= (d.kind[k] == 3 ? 1u : 0u) << k;
-  g.att_mask = am;
+  g.ion_mask = d.ion_mask;
+  g.att_mask = d.att_mask;
   g.seed_lo = (uint32_t)d.seed;
   g.seed_hi = (uint32_t)(d.seed >> 32);
   g.step = (uint32_t)st->step;
   g.n_main = st->n_main;
   g.sample = ((st->step + 1) % d.eedf_every) == 0;
   QEntry<P>* q = reinterpret_cast<QEntry<P>*>(smem + L.q) + (size_t)wv * kWQ;
-  const int tabN = g.tab_rows * d.K;
-  for (int i = tid; i < tabN; i += kElecThreads) tab[i] = d.tab[i];
-  for (int i = tid; i < d.nn; i += kElecThreads) {
-    g.bins[i] = 0;
-    ep[i] = d.Ep[i];
-  }
+  lds_copy2<P>(tab, gptr(d.tab), g.tab_rows * d.K, ep, gptr(d.Ep), d.nn);
+  for (int i = tid; i < d.nn; i += kElecThreads) g.bins[i] = 0;
   for (int i = tid; i <= d.nbins; i += kElecThreads) g.eedf[i] = 0;
   if (tid < kCtrN) g.ctr[tid] = 0;
   int64_t* cnt = d.cnt[st->cbuf ^ 1];
@@ -951,7 +969,10 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
   uint32_t* pre = reinterpret_cast<uint32_t*>(smem + L.pre);
   for (int i = tid; i < D; i += kElecThreads) {
     const State* st = ds[i].st;
-    pre[i + 1] = (st->steps_left > 0) ? (st->n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile : 0u;
+    const int64_t left = st->steps_left;  // both loads issued together
+    const uint32_t n_main = st->n_main;
+    const uint32_t nch = (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile;
+    pre[i + 1] = nch & (left > 0 ? ~0u : 0u);
   }
   if (tid == 0) pre[0] = 0;
   __syncthreads();
