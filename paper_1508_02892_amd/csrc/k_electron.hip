@@ -23,6 +23,23 @@ constexpr int kWaves = kElecThreads / 64;      // waves per workgroup
 constexpr int kWQ = 128;                   // per-wave collision queue entries
 constexpr int kTabLds = 1024;              // collision-table rows kept in LDS (0 .. 102.3 eV
                                            // at 10 points per eV); higher rows via the cache
+constexpr uint32_t kKidsLds = 256;         // sub-chunk child counts of a segment kept in LDS
+static_assert(kKidsLds <= (uint32_t)kElecThreads, "the LDS counts are scanned in one round");
+
+// Workgroup barrier that orders LDS accesses only: the wave's global stores
+// may still be in flight when it passes, where __syncthreads waits for them.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// A pointer that is the same in every lane, moved to scalar registers.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(((uint64_t)hi << 32) | lo);
+}
 
 // A collision waiting to be scattered.  meta: bits 0-7 channel, bit 8 set if
 // a child is created, bits 16-23 the child's index within the sub-chunk.
@@ -46,7 +63,7 @@ struct ElecArgs {
 };
 
 struct Lds {
-  uint32_t tab, ep, bins, q, eedf, ctr, pre, total;
+  uint32_t tab, ep, bins, q, eedf, ctr, pre, kids, total;
   uint32_t rows;  // collision-table rows held in LDS
 };
 
@@ -69,7 +86,8 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
   L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
   L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
   L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
-  L.total = al(L.pre + (uint32_t)(a.D + 1) * 4u);
+  L.kids = al(L.pre + (uint32_t)(a.D + 1) * 4u);
+  L.total = al(L.kids + kKidsLds * 4u);
   // a, b, c, r of Eq (2.3) and the reduced system of the partitioned solve
   const uint32_t fluid = a.fluid_nn ? (4u * (uint32_t)a.fluid_nn + 7u * (uint32_t)kTriRed) * 8u : 0u;
   if (fluid > L.total) L.total = al(fluid);
@@ -123,6 +141,8 @@ struct Seg {
   uint32_t ion_mask;  // bit k: channel k is an ionization
   uint32_t att_mask;  // bit k: channel k is an attachment
   uint32_t seed_lo, seed_hi, step, n_main;
+  uint32_t* kl;       // LDS copy of the segment's first kKidsLds sub-chunk child counts
+  uint32_t kbase;     // index of the segment's first sub-chunk
   bool sample;
 };
 
@@ -482,7 +502,11 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     kid += (uint32_t)__popcll(mk & lt);
     nk += (uint32_t)__popcll(mk);
   }
-  if (lane == 0) gptr(d.chunk_kids)[lc * (uint32_t)kWaves + (uint32_t)wv] = nk;
+  if (lane == 0) {
+    const uint32_t u = lc * (uint32_t)kWaves + (uint32_t)wv;
+    gptr(d.chunk_kids)[u] = nk;
+    if (u - g.kbase < kKidsLds) g.kl[u - g.kbase] = nk;
+  }
   // queue the collisions, one slot index j at a time, and scatter in 64s
   // SW: byte j of qp is the queue index of this lane's slot j while its
   // collision waits (0xFF: none); handle the first n entries, bring their
@@ -588,7 +612,7 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* 
     if (lane >= o) x += y;
   }
   if (lane == 63) sh[wv] = x;
-  __syncthreads();
+  lds_barrier();
   uint32_t base = 0, tot = 0;
 #pragma unroll
   for (int w = 0; w < kWaves; ++w) {
@@ -596,7 +620,7 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* 
     if (w < wv) base += s;
     tot += s;
   }
-  __syncthreads();
+  lds_barrier();
   *total = tot;
   return base + x - v;
 }
@@ -642,13 +666,18 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   g.step = (uint32_t)st->step;
   g.n_main = st->n_main;
   g.sample = ((st->step + 1) % d.eedf_every) == 0;
+  g.kl = reinterpret_cast<uint32_t*>(smem + L.kids);
+  g.kbase = lc0 * (uint32_t)kWaves;
   QEntry<P>* q = reinterpret_cast<QEntry<P>*>(smem + L.q) + (size_t)wv * kWQ;
   lds_copy2<P>(tab, gptr(d.tab), g.tab_rows * d.K, ep, gptr(d.Ep), d.nn);
   for (int i = tid; i < d.nn; i += kElecThreads) g.bins[i] = 0;
   for (int i = tid; i <= d.nbins; i += kElecThreads) g.eedf[i] = 0;
   if (tid < kCtrN) g.ctr[tid] = 0;
-  int64_t* cnt = d.cnt[st->cbuf ^ 1];
-  __syncthreads();
+  // the deposit grid's pointer goes to scalar registers now, so that no wait
+  // for it (and for the particle stores in flight behind it) is left for the
+  // flush at the end
+  int64_t* cnt = uniform_ptr(d.cnt[st->cbuf ^ 1]);
+  lds_barrier();  // LDS stores wait for the loads they copy
   uint32_t qn = 0;
   WaveCounts wc;
   ChunkIn<P> nx;
@@ -672,7 +701,45 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
     if (wc.ovf) atomicAdd(&g.ctr[kCtrOverflow], wc.ovf);
     if (wc.pushed) atomicAdd(&g.ctr[kCtrPushed], wc.pushed);
   }
-  __syncthreads();
+  // Offsets of the segment's children relative to the segment (exclusive
+  // scan of the sub-chunk counts) and the segment's total, ahead of the
+  // flushes so that nothing waits for their atomics.  The counts come from
+  // LDS when the segment has at most kKidsLds sub-chunks; otherwise from
+  // memory, after a barrier that waits for every wave's stores.
+  const uint32_t k0 = lc0 * (uint32_t)kWaves, k1 = lc1 * (uint32_t)kWaves;
+  const bool kids_lds = k1 - k0 <= kKidsLds;
+  if (kids_lds)
+    lds_barrier();
+  else
+    __syncthreads();
+  {
+    __shared__ uint32_t sh[kWaves];
+    Gp<uint32_t>* kbase = gptr(d.chunk_base);
+    uint32_t carry = 0;
+    if (kids_lds) {  // at most kKidsLds <= kElecThreads counts: one round
+      const uint32_t k = k0 + (uint32_t)tid;
+      const uint32_t v = k < k1 ? g.kl[tid] : 0u;
+      const uint32_t ex = wg_scan(v, sh, &carry);
+      if (k < k1) kbase[k] = ex;
+    } else {
+      const Gp<uint32_t>* kids = gptr(d.chunk_kids);
+      for (uint32_t kb = k0; kb < k1; kb += (uint32_t)kElecThreads) {
+        const uint32_t k = kb + (uint32_t)tid;
+        const uint32_t v = k < k1 ? kids[k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = wg_scan(v, sh, &tot);
+        if (k < k1) kbase[k] = carry + ex;
+        carry += tot;
+      }
+    }
+    if (tid == 0) {
+      gptr(d.seg)[pb] = carry;
+      if (lc0 == 0) {
+        st->seg_off = chunk0;
+        st->seg_per = per;
+      }
+    }
+  }
   for (int i = tid; i < d.nn; i += kElecThreads) {
     const int64_t v = g.bins[i];
     if (v) atomic_add_i64(&cnt[i], v);
@@ -694,31 +761,7 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->overflow), (unsigned long long)ctr[tid]);
   if (tid == kCtrPushed && ctr[tid])
     atomicAdd(reinterpret_cast<unsigned long long*>(&st->pushed), (unsigned long long)ctr[tid]);
-  // offsets of the segment's children relative to the segment (exclusive
-  // scan of the sub-chunk counts written above) and the segment's total
-  {
-    __shared__ uint32_t sh[kWaves];
-    const uint32_t k0 = lc0 * (uint32_t)kWaves, k1 = lc1 * (uint32_t)kWaves;
-    const Gp<uint32_t>* kids = gptr(d.chunk_kids);
-    Gp<uint32_t>* kbase = gptr(d.chunk_base);
-    uint32_t carry = 0;
-    for (uint32_t kb = k0; kb < k1; kb += (uint32_t)kElecThreads) {
-      const uint32_t k = kb + (uint32_t)tid;
-      const uint32_t v = k < k1 ? kids[k] : 0u;
-      uint32_t tot;
-      const uint32_t ex = wg_scan(v, sh, &tot);
-      if (k < k1) kbase[k] = carry + ex;
-      carry += tot;
-    }
-    if (tid == 0) {
-      gptr(d.seg)[pb] = carry;
-      if (lc0 == 0) {
-        st->seg_off = chunk0;
-        st->seg_per = per;
-      }
-    }
-  }
-  __syncthreads();
+  lds_barrier();  // the next segment of this workgroup reuses the LDS
 }
 
 // ---- ion fluid -----------------------------------------------------------
@@ -975,10 +1018,10 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
     pre[i + 1] = nch & (left > 0 ? ~0u : 0u);
   }
   if (tid == 0) pre[0] = 0;
-  __syncthreads();
+  lds_barrier();
   if (tid == 0)
     for (int i = 0; i < D; ++i) pre[i + 1] += pre[i];
-  __syncthreads();
+  lds_barrier();
   const uint32_t total = pre[D];
   const uint32_t G = gridDim.x - (uint32_t)D, pb = blockIdx.x - (uint32_t)D;
   const uint32_t per = (total + G - 1u) / G;
