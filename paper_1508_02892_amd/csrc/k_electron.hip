@@ -260,7 +260,7 @@ __device__ __forceinline__ void drain(const Disch<P>& d, const Seg<P>& g, QEntry
 // probability exceeds R (-1: null collision).  All K comparisons are made and
 // the first true one is taken, so the loop has the same trip count on every
 // lane.
-template <class P, int KC>
+template <class P, int KC, bool VEC>
 __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy, P vz,
                                               bool& ovf) {
   const int K = KC > 0 ? KC : g.K;  // KC: channel count fixed at compile time (0: any)
@@ -303,7 +303,31 @@ __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy,
     return hit ? __builtin_ctz(hit) : -1;
   };
   // rows i and i+1 from LDS when both are there, else through the cache
-  if (i + 1 < g.tab_rows) return scan(g.tab + i * K);
+  if (i + 1 < g.tab_rows) {
+    if constexpr (KC == 0 && VEC) {
+      // rows of a whole number of 16-byte vectors (K a multiple of 4 in
+      // FP32, of 2 in FP64) start 16-byte aligned: one LDS read per vector
+      // (left out where the registers are short: the segment-write variant)
+      constexpr int kL = 16 / (int)sizeof(P);
+      if (K % kL == 0) {
+        typedef __attribute__((ext_vector_type(kL))) P V;
+        const P* ra = g.tab + i * K;
+        uint32_t hit = 0;
+#pragma unroll 1
+        for (int k = 0; k < K; k += kL) {
+          const V a = *reinterpret_cast<const V*>(ra + k);
+          const V b = *reinterpret_cast<const V*>(ra + K + k);
+#pragma unroll
+          for (int l = 0; l < kL; ++l) {
+            const P pk = a[l] + t * (b[l] - a[l]);
+            hit |= (u0 < pk ? 1u : 0u) << (k + l);
+          }
+        }
+        return hit ? __builtin_ctz(hit) : -1;
+      }
+    }
+    return scan(g.tab + i * K);
+  }
   return scan(g.tab_g + (size_t)i * K);
 }
 
@@ -438,7 +462,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     // null-collision test
     ch[j] = -1;
     bool ovf = false;
-    if (alive[j] && u0[j] < g.Pmax) ch[j] = select_channel<P, KC>(g, u0[j], vx[j], vy[j], vz[j], ovf);
+    if (alive[j] && u0[j] < g.Pmax) ch[j] = select_channel<P, KC, !SW>(g, u0[j], vx[j], vy[j], vz[j], ovf);
     wc.ovf += ovf ? 1u : 0u;
     // an attached electron leaves before the deposit (its charge goes to
     // the negative ion when the collision is handled); the three-channel
