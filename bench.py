@@ -214,6 +214,12 @@ def cpu_table(a):
     print(json.dumps({"cpu_oracle_particle_steps_per_s": rows, "host": host}), flush=True)
 
 
+def launch_cfg(text: str) -> dict:
+    """--launch "variant,electron_groups,sort_groups,append_groups" (0: default)."""
+    v = [int(x) for x in text.split(",")]
+    return dict(zip(["electron_variant", "electron_groups", "sort_groups", "append_groups"], v))
+
+
 def batched(a):
     """Batched sweep: 64 independent discharges (64M electrons in total) in one
     launch per phase, against the same discharges as separate handles (one
@@ -225,8 +231,18 @@ def batched(a):
     print("bench: building batch of %d" % len(ps), file=sys.stderr, flush=True)
     b = hd.Batch(ps, device=0)
     # the batched sweep's launch shapes come from the autotuner (128 real
-    # steps unless --tune-steps says otherwise)
-    launch = b.autotune(a.tune_steps or 128)
+    # steps unless --tune-steps says otherwise), or from --launch
+    if a.launch:
+        b.set_launch(launch_cfg(a.launch))
+        launch = b.get_launch()
+    else:
+        launch = b.autotune(a.tune_steps or 128)
+    if a.copy_calib:  # a 1 GiB copy that scales the HBM counters of a profiled run
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     b.step(a.warmup)
     torch.cuda.synchronize()
     p0 = sum(b.moments(i)["pushed"] for i in range(len(ps)))
@@ -468,9 +484,7 @@ def main():
         desc += "; electrons overridden: %d" % a.electrons
     dev = hd.Discharge(p, device=0)
     if a.launch:
-        v = [int(x) for x in a.launch.split(",")]
-        dev.set_launch(dict(zip(["electron_variant", "electron_groups", "sort_groups",
-                                 "append_groups"], v)))
+        dev.set_launch(launch_cfg(a.launch))
     elif a.tune_steps:
         print("bench: autotuning over %d steps" % a.tune_steps, file=sys.stderr, flush=True)
         dev.autotune(a.tune_steps)
