@@ -13,6 +13,7 @@ constexpr int kPerThread = 4;      // particles per thread per chunk (vector loa
 constexpr int kElecThreads = 512;  // electron-kernel workgroup (8 waves)
 constexpr int kTile = kElecThreads * kPerThread;  // particles per chunk
 constexpr int kSub = 64 * kPerThread;  // particles of one wave in a chunk (a sub-chunk)
+constexpr int kElecWide = 8;  // electron launch variants kElecWide + v: kernel v, 1,024-thread workgroups
 constexpr int kSeeMax = 4096;      // secondaries per wall per step
 constexpr int kMaxCells = 4096;    // cells per discharge
 constexpr int kMaxNodes = kMaxCells + 1;

@@ -27,7 +27,8 @@ namespace hd {
 
 // kernel-side entry points (k_electron.hip, k_field.hip, k_sort.hip)
 template <class P>
-size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max);
+size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max,
+                          int variant);
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
                                 int nb1_max, int fluid_nn, int K_max, int variant, hipStream_t s);
@@ -41,6 +42,18 @@ int electron_variants();
 // beyond it streams from HBM on every step.
 constexpr int kElecVariantStreaming = 5;
 constexpr uint64_t kMallBytes = 256ull << 20;
+
+// The wide form of electron variant v (kElecWide + v: the same kernel with
+// 1,024-thread workgroups) where v's workgroups fit only one per CU (large
+// grids) and the wide ones fit: sixteen waves per CU instead of eight.
+template <class P>
+int widen_variant(int v, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max, int D) {
+  if (v >= kElecWide) return v;
+  if (electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v) != 1) return v;
+  return electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v + kElecWide) >= 1
+             ? v + kElecWide
+             : v;
+}
 template <class P>
 hipError_t finalize_set_lds(int nn_max);
 template <class P>
@@ -818,7 +831,7 @@ struct Batch : BatchBase {
     // launch geometry
     hipDeviceProp_t prop;
     HD_TRY(hipGetDeviceProperties(&prop, device));
-    const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max);
+    const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max, 0);
     if (lds > (size_t)prop.sharedMemPerBlock)
       return fail(HD_EINVAL, "electron kernel needs " + std::to_string(lds) +
                                  " B of LDS, device allows " +
@@ -848,6 +861,8 @@ struct Batch : BatchBase {
       uint64_t bytes = 0;
       for (const auto& h : hs) bytes += (uint64_t)h.p.n_macro * (8u + 4u * sizeof(P));
       if (bytes > kMallBytes) lc0.electron_variant = kElecVariantStreaming;
+      lc0.electron_variant = widen_variant<P>(lc0.electron_variant, tab_max, nn_max, nb1_max,
+                                              fluid_nn, K_max, D);
     }
     hd_launch_config lc{};
     if (!tune_lookup(tune_key, lc) || apply_launch(lc) != HD_OK) {
@@ -1452,8 +1467,14 @@ struct Batch : BatchBase {
     for (int v = 0; v < electron_variants(); ++v) {
       const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v);
       if (occ < 1) continue;
+      // wide workgroups only where the narrow ones fit one per CU, and then
+      // only as many as the CUs (fewer would leave CUs idle)
+      if (v >= kElecWide &&
+          electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v - kElecWide) != 1)
+        continue;
       const int full = std::min(cus * occ, (int)kMaxSegs);
       for (int g : {full, std::max(1, full * 3 / 4), std::max(1, full / 2)}) {
+        if (v >= kElecWide && g != full) continue;
         hd_launch_config c = launch;
         c.electron_variant = v;
         c.electron_groups = g;
@@ -1707,12 +1728,15 @@ struct Server : ServerBase {
     fluid_nn = cfg.allow_full_fluid ? nn_max : 0;
     hipDeviceProp_t prop;
     HD_TRY(hipGetDeviceProperties(&prop, device));
-    const size_t lds = electron_lds_bytes<P>(S, tab_max, nn_max, nb1_max, fluid_nn, K_max);
+    const size_t lds = electron_lds_bytes<P>(S, tab_max, nn_max, nb1_max, fluid_nn, K_max, 0);
     if (lds > (size_t)prop.sharedMemPerBlock) return fail(HD_EINVAL, "slot caps exceed LDS");
     HD_TRY(sort_set_lds<P>(nc_max, S));
     HD_TRY(finalize_set_lds<P>(nn_max));
     const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, S, 0);
     if (occ < 1) return fail(HD_EDEVICE, "electron kernel cannot be resident");
+    const int v_plain = widen_variant<P>(0, tab_max, nn_max, nb1_max, fluid_nn, K_max, S);
+    const int v_stream =
+        widen_variant<P>(kElecVariantStreaming, tab_max, nn_max, nb1_max, fluid_nn, K_max, S);
     grid_e = S + std::min(prop.multiProcessorCount * occ, (int)kMaxSegs);
     grid_a = std::max(1, prop.multiProcessorCount / 4);
     grid_s = prop.multiProcessorCount * 4;
@@ -1732,7 +1756,7 @@ struct Server : ServerBase {
       hipError_t e = hipSuccess;
       for (int s = 0; s < cfg.sort_every && e == hipSuccess; ++s) {
         e = launch_electron_impl<P>(d_desc, S, grid_e, tab_max, nn_max, nb1_max, fluid_nn, K_max,
-                                    nt ? kElecVariantStreaming : 0, stream);
+                                    nt ? v_stream : v_plain, stream);
         if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, grid_a, stream);
         if (e == hipSuccess && s == cfg.sort_every - 1)
           e = launch_sort_impl<P>(d_desc, S, grid_s, nc_max, stream);

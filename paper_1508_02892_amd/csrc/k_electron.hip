@@ -19,7 +19,12 @@ namespace hd {
 namespace {
 
 constexpr double kECharge = 1.602176634e-19;
-constexpr int kWaves = kElecThreads / 64;      // waves per workgroup
+// Workgroups are kElecThreads (eight waves) or, in the wide variants,
+// kElecThreadsWide (sixteen waves, one workgroup per CU where the LDS of a
+// large grid leaves room for only one narrow one); a chunk is four particles
+// per thread, so 2,048 or 4,096 slots.
+constexpr int kElecThreadsWide = 2 * kElecThreads;
+constexpr int kMaxWaves = kElecThreadsWide / 64;
 constexpr int kWQ = 128;                   // per-wave collision queue entries
 constexpr int kTabLds = 1024;              // collision-table rows kept in LDS (0 .. 102.3 eV
                                            // at 10 points per eV); higher rows via the cache
@@ -60,11 +65,13 @@ struct ElecArgs {
   int fluid_nn;   // max nodes of a full-fluid discharge (its solver lives in LDS), 0 if none
   int K_max;      // max channels
   int tab_rows;   // collision-table rows held in LDS (tab_rows_lds)
+  int waves;      // waves per workgroup (8, or 16 in the wide variants)
 };
 
 struct Lds {
   uint32_t tab, ep, bins, q, eedf, ctr, pre, kids, total;
-  uint32_t rows;  // collision-table rows held in LDS
+  uint32_t rows;   // collision-table rows held in LDS
+  uint32_t waves;  // waves per workgroup
 };
 
 // LDS counters: [0, kMaxK) collisions per channel, then these.
@@ -79,11 +86,12 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
                                ? (uint32_t)a.tab_max : rows * (uint32_t)a.K_max;
   Lds L;
   L.rows = rows;
+  L.waves = (uint32_t)a.waves;
   L.tab = 0;
   L.ep = al(L.tab + tab_lds * (uint32_t)sizeof(P));
   L.bins = al(L.ep + (uint32_t)a.nn_max * (uint32_t)sizeof(P));
   L.q = al(L.bins + (uint32_t)a.nn_max * 8u);
-  L.eedf = al(L.q + (uint32_t)(kWaves * kWQ) * (uint32_t)sizeof(QEntry<P>));
+  L.eedf = al(L.q + (uint32_t)a.waves * (uint32_t)kWQ * (uint32_t)sizeof(QEntry<P>));
   L.ctr = al(L.eedf + (uint32_t)a.nb1_max * 4u);
   L.pre = al(L.ctr + (uint32_t)kCtrN * 4u);
   L.kids = al(L.pre + (uint32_t)(a.D + 1) * 4u);
@@ -95,21 +103,25 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
 }
 
 // The collision table keeps its first kTabLds rows in LDS, fewer when that
-// would leave room for only one workgroup per CU (many channels, large
-// grids) while fewer rows make room for two: rows above come through the
-// cache, which only the rare fast electrons read.  Chosen on the host.
-constexpr uint32_t kTwoPerCu = (80u << 10) - 1024u;  // LDS per workgroup for two per CU
+// would leave room for only one narrow workgroup per CU (many channels, large
+// grids) while fewer rows make room for two (one wide workgroup: the whole
+// CU's LDS): rows above come through the cache, which only the rare fast
+// electrons read.  Chosen on the host.
+constexpr uint32_t kTwoPerCu = (80u << 10) - 1024u;   // LDS per workgroup for two per CU
+constexpr uint32_t kOnePerCu = (160u << 10) - 1024u;  // LDS of a wide workgroup
 constexpr uint32_t kTabMinLds = 128;
 
 template <class P>
-ElecArgs elec_args(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max) {
-  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max, kTabLds};
+ElecArgs elec_args(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max,
+                   int waves) {
+  ElecArgs a{D, tab_max, nn_max, nb1_max, fluid_nn, K_max, kTabLds, waves};
   const Lds L = lds_layout<P>(a);
+  const uint32_t budget = waves > kElecThreads / 64 ? kOnePerCu : kTwoPerCu;
   const uint32_t fluid = fluid_nn ? (4u * (uint32_t)fluid_nn + 7u * (uint32_t)kTriRed) * 8u : 0u;
-  if (L.total > kTwoPerCu && fluid <= kTwoPerCu) {
+  if (L.total > budget && fluid <= budget) {
     const uint32_t rest = L.total - L.ep;  // everything but the table
     const uint32_t row = (uint32_t)K_max * (uint32_t)sizeof(P);
-    const uint32_t rows = rest < kTwoPerCu ? (kTwoPerCu - rest) / row : 0u;
+    const uint32_t rows = rest < budget ? (budget - rest) / row : 0u;
     if (rows >= kTabMinLds && rows < (uint32_t)kTabLds) a.tab_rows = (int)rows;
   }
   return a;
@@ -143,6 +155,8 @@ struct Seg {
   uint32_t seed_lo, seed_hi, step, n_main;
   uint32_t* kl;       // LDS copy of the segment's first kKidsLds sub-chunk child counts
   uint32_t kbase;     // index of the segment's first sub-chunk
+  uint32_t waves;     // waves per workgroup (sub-chunks per chunk)
+  uint32_t chunk;     // slots per chunk
   bool sample;
 };
 
@@ -348,9 +362,9 @@ struct ChunkIn {
 
 // Issue the loads of chunk lc (ids first: the random numbers need only them).
 // NP: nontemporal hint on ids, cells and offsets; NV: on the velocities.
-template <class P, bool NP, bool NV>
+template <class P, bool NP, bool NV, int W>
 __device__ __forceinline__ void chunk_load(const Seg<P>& g, uint32_t lc, ChunkIn<P>& x) {
-  const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)threadIdx.x * (uint32_t)kPerThread;
+  const uint32_t i0 = lc * (uint32_t)(W * kSub) + (uint32_t)threadIdx.x * (uint32_t)kPerThread;
   gld4<NP>(g.id + i0, x.id);
   __builtin_amdgcn_sched_barrier(0);  // keep the id load ahead of the others
   gld4<NP>(g.cell + i0, x.c);
@@ -387,22 +401,22 @@ __device__ __forceinline__ void chunk_load(const Seg<P>& g, uint32_t lc, ChunkIn
 // return to their lanes, v_z is written whole, and v_x, v_y are written for
 // every 16-particle (64-byte) segment that holds a collision, so that no
 // write is narrower than a segment.
-template <class P, int KC, int M>
+template <class P, int KC, int M, int W>
 __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEntry<P>* q,
                            uint32_t& qn, WaveCounts& wc, ChunkIn<P>& nx, bool more) {
   constexpr int LM = M & 3;
   constexpr bool NP = (M & 4) != 0, NV = (M & 8) != 0, SW = (M & 16) != 0;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const uint32_t i0 = lc * (uint32_t)kTile + (uint32_t)tid * (uint32_t)kPerThread;
+  const uint32_t i0 = lc * (uint32_t)(W * kSub) + (uint32_t)tid * (uint32_t)kPerThread;
   if constexpr (LM != 2) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) only
   ChunkIn<P> in;
   if constexpr (LM == 1) {
     in = nx;
-    if (more) chunk_load<P, NP, NV>(g, lc + 1u, nx);
+    if (more) chunk_load<P, NP, NV, W>(g, lc + 1u, nx);
     __builtin_amdgcn_sched_barrier(0);
   } else {
-    chunk_load<P, NP, NV>(g, lc, in);
+    chunk_load<P, NP, NV, W>(g, lc, in);
   }
   int32_t(&c)[4] = in.c;
   P(&off)[4] = in.off;
@@ -527,7 +541,7 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
     nk += (uint32_t)__popcll(mk);
   }
   if (lane == 0) {
-    const uint32_t u = lc * (uint32_t)kWaves + (uint32_t)wv;
+    const uint32_t u = lc * (uint32_t)W + (uint32_t)wv;
     gptr(d.chunk_kids)[u] = nk;
     if (u - g.kbase < kKidsLds) g.kl[u - g.kbase] = nk;
   }
@@ -602,31 +616,33 @@ __device__ void wave_chunk(const Disch<P>& d, const Seg<P>& g, uint32_t lc, QEnt
 // Copies na elements of sa to da and nb of sb to db (LDS), issuing all of a
 // thread's loads of a round before its first store, so that a segment's set-up
 // waits for one memory round trip per round instead of one per element.
-template <class T>
+template <int NT, class T>
 __device__ __forceinline__ void lds_copy2(T* da, const Gp<T>* sa, int na, T* db,
                                           const Gp<T>* sb, int nb) {
   constexpr int B = 8;  // elements per thread and array per round
+  constexpr int nt = NT;
   const int tid = threadIdx.x;
   const int n = na > nb ? na : nb;
-  for (int r = 0; r < n; r += B * kElecThreads) {
+  for (int r = 0; r < n; r += B * nt) {
     T va[B], vb[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
-      const int i = r + u * kElecThreads + tid;
+      const int i = r + u * nt + tid;
       if (i < na) va[u] = sa[i];
       if (i < nb) vb[u] = sb[i];
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) {
-      const int i = r + u * kElecThreads + tid;
+      const int i = r + u * nt + tid;
       if (i < na) da[i] = va[u];
       if (i < nb) db[i] = vb[u];
     }
   }
 }
 
-// Block-wide exclusive scan of one value per thread (kElecThreads); writes
-// the total to *total.  sh: kWaves words of LDS.
+// Block-wide exclusive scan of one value per thread of a workgroup of W
+// waves; writes the total to *total.  sh: W words of LDS.
+template <int W>
 __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   uint32_t x = v;
@@ -639,7 +655,7 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* 
   lds_barrier();
   uint32_t base = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
+  for (int w = 0; w < W; ++w) {
     const uint32_t s = sh[w];
     if (w < wv) base += s;
     tot += s;
@@ -651,11 +667,11 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t v, uint32_t* sh, uint32_t* 
 
 // Chunks [lc0, lc1) of discharge d by particle workgroup pb; chunk0 is the
 // launch-wide index of the discharge's first chunk and per the chunks per
-// workgroup.
-template <class P, int M>
+// workgroup (chunks of this launch's workgroup size).
+template <class P, int M, int W>
 __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned char* smem,
                         const Lds& L, uint32_t pb, uint32_t chunk0, uint32_t per) {
-  const int tid = threadIdx.x, wv = tid >> 6;
+  const int tid = threadIdx.x, wv = tid >> 6, nt = W * 64;
   P* tab = reinterpret_cast<P*>(smem + L.tab);
   P* ep = reinterpret_cast<P*>(smem + L.ep);
   State* st = d.st;
@@ -691,11 +707,13 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   g.n_main = st->n_main;
   g.sample = ((st->step + 1) % d.eedf_every) == 0;
   g.kl = reinterpret_cast<uint32_t*>(smem + L.kids);
-  g.kbase = lc0 * (uint32_t)kWaves;
+  g.waves = (uint32_t)W;
+  g.chunk = (uint32_t)(W * kSub);
+  g.kbase = lc0 * g.waves;
   QEntry<P>* q = reinterpret_cast<QEntry<P>*>(smem + L.q) + (size_t)wv * kWQ;
-  lds_copy2<P>(tab, gptr(d.tab), g.tab_rows * d.K, ep, gptr(d.Ep), d.nn);
-  for (int i = tid; i < d.nn; i += kElecThreads) g.bins[i] = 0;
-  for (int i = tid; i <= d.nbins; i += kElecThreads) g.eedf[i] = 0;
+  lds_copy2<W * 64>(tab, gptr(d.tab), g.tab_rows * d.K, ep, gptr(d.Ep), d.nn);
+  for (int i = tid; i < d.nn; i += nt) g.bins[i] = 0;
+  for (int i = tid; i <= d.nbins; i += nt) g.eedf[i] = 0;
   if (tid < kCtrN) g.ctr[tid] = 0;
   // the deposit grid's pointer goes to scalar registers now, so that no wait
   // for it (and for the particle stores in flight behind it) is left for the
@@ -705,14 +723,14 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   uint32_t qn = 0;
   WaveCounts wc;
   ChunkIn<P> nx;
-  if constexpr ((M & 3) == 1) chunk_load<P, (M & 4) != 0, (M & 8) != 0>(g, lc0, nx);
+  if constexpr ((M & 3) == 1) chunk_load<P, (M & 4) != 0, (M & 8) != 0, W>(g, lc0, nx);
   if (g.K == 3 && g.att_mask == 0) {  // elastic, excitation, ionization: unrolled
     for (uint32_t lc = lc0; lc < lc1; ++lc)
-      wave_chunk<P, 3, M>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
+      wave_chunk<P, 3, M, W>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
     if (qn) drain<P, false>(d, g, q, qn, qn);
   } else {
     for (uint32_t lc = lc0; lc < lc1; ++lc)
-      wave_chunk<P, 0, M>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
+      wave_chunk<P, 0, M, W>(d, g, lc, q, qn, wc, nx, lc + 1u < lc1);
     if (qn) drain<P, true>(d, g, q, qn, qn);
   }
   wc.absl = wave_sum_u32(wc.absl);
@@ -730,46 +748,47 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   // flushes so that nothing waits for their atomics.  The counts come from
   // LDS when the segment has at most kKidsLds sub-chunks; otherwise from
   // memory, after a barrier that waits for every wave's stores.
-  const uint32_t k0 = lc0 * (uint32_t)kWaves, k1 = lc1 * (uint32_t)kWaves;
+  const uint32_t k0 = lc0 * g.waves, k1 = lc1 * g.waves;
   const bool kids_lds = k1 - k0 <= kKidsLds;
   if (kids_lds)
     lds_barrier();
   else
     __syncthreads();
   {
-    __shared__ uint32_t sh[kWaves];
+    __shared__ uint32_t sh[kMaxWaves];
     Gp<uint32_t>* kbase = gptr(d.chunk_base);
     uint32_t carry = 0;
     if (kids_lds) {  // at most kKidsLds <= kElecThreads counts: one round
       const uint32_t k = k0 + (uint32_t)tid;
       const uint32_t v = k < k1 ? g.kl[tid] : 0u;
-      const uint32_t ex = wg_scan(v, sh, &carry);
+      const uint32_t ex = wg_scan<W>(v, sh, &carry);
       if (k < k1) kbase[k] = ex;
     } else {
       const Gp<uint32_t>* kids = gptr(d.chunk_kids);
-      for (uint32_t kb = k0; kb < k1; kb += (uint32_t)kElecThreads) {
+      for (uint32_t kb = k0; kb < k1; kb += (uint32_t)nt) {
         const uint32_t k = kb + (uint32_t)tid;
         const uint32_t v = k < k1 ? kids[k] : 0u;
         uint32_t tot;
-        const uint32_t ex = wg_scan(v, sh, &tot);
+        const uint32_t ex = wg_scan<W>(v, sh, &tot);
         if (k < k1) kbase[k] = carry + ex;
         carry += tot;
       }
     }
     if (tid == 0) {
       gptr(d.seg)[pb] = carry;
-      if (lc0 == 0) {
-        st->seg_off = chunk0;
-        st->seg_per = per;
+      if (lc0 == 0) {  // in chunks of kTile slots, whatever this launch's chunk
+        const uint32_t r = g.chunk / (uint32_t)kTile;
+        st->seg_off = chunk0 * r;
+        st->seg_per = per * r;
       }
     }
   }
-  for (int i = tid; i < d.nn; i += kElecThreads) {
+  for (int i = tid; i < d.nn; i += nt) {
     const int64_t v = g.bins[i];
     if (v) atomic_add_i64(&cnt[i], v);
   }
   if (g.sample)
-    for (int i = tid; i <= d.nbins; i += kElecThreads)
+    for (int i = tid; i <= d.nbins; i += nt)
       if (g.eedf[i]) atomicAdd(reinterpret_cast<unsigned long long*>(&d.eedf[i]),
                                (unsigned long long)g.eedf[i]);
   const uint32_t* ctr = g.ctr;
@@ -834,7 +853,7 @@ __device__ void fluid_dd(const Disch<P>& d, double* lds) {
   const double* __restrict__ E = d.E;
   double* G = lds;
   const bool fit = d.ion_model == HD_ION_DD_FIT_MU;
-  for (int j = tid; j < nn; j += kElecThreads) {
+  for (int j = tid; j < nn; j += (int)blockDim.x) {
     const double ej = E[j];
     const double mu = fit ? mobility_fit(ej) : d.mu;
     double g;
@@ -851,7 +870,7 @@ __device__ void fluid_dd(const Disch<P>& d, double* lds) {
     G[j] = g;
   }
   __syncthreads();
-  for (int j = tid; j < nn; j += kElecThreads) {
+  for (int j = tid; j < nn; j += (int)blockDim.x) {
     double v;
     if (j == 0)
       v = ni[0] - d.dt_dz * (G[1] - G[0]);
@@ -894,7 +913,7 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
   double* Lb = La + nn;
   double* Lc = Lb + nn;
   double* Lr = Lc + nn;
-  for (int j = 1 + tid; j <= m; j += kElecThreads) {
+  for (int j = 1 + tid; j <= m; j += (int)blockDim.x) {
     const double nl = ni[j - 1], nj = ni[j], nr = ni[j + 1];
     const double gl_ = gam[j - 1], gj = gam[j], gr_ = gam[j + 1];
     const double el = E[j - 1], ej = E[j], er = E[j + 1];
@@ -917,7 +936,7 @@ __device__ void fluid_full(const Disch<P>& d, double* lds) {
     d.st->wall[1] = gr;
   }
   solve_tridiag_block<2>(m, La, Lb, Lc, Lr, lds + 4 * nn);  // Gamma^{n+1/2} -> Lb
-  for (int j = tid; j < nn; j += kElecThreads) {
+  for (int j = tid; j < nn; j += (int)blockDim.x) {
     // Gamma^{n+1/2} at j-1, j, j+1 (walls: gl, gr) and the continuity update
     auto G = [&](int i) { return i == 0 ? gl : (i == nc ? gr : Lb[i - 1]); };
     double v;
@@ -966,7 +985,7 @@ __device__ void fluid_species(const Disch<P>& d, double* lds) {
     double* __restrict__ gam = d.gam + (size_t)q * nn;
     const double Zd = (double)d.Z[q];
     const double kap = d.kappa_s[q];
-    for (int j = tid; j < nn; j += kElecThreads) {
+    for (int j = tid; j < nn; j += (int)blockDim.x) {
       const double ej = E[j];
       const double mu = species_mu(d, q, ej);
       double g;
@@ -984,7 +1003,7 @@ __device__ void fluid_species(const Disch<P>& d, double* lds) {
       G[j] = g;
     }
     __syncthreads();
-    for (int j = tid; j < nn; j += kElecThreads) {
+    for (int j = tid; j < nn; j += (int)blockDim.x) {
       double v;
       if (j == 0)
         v = ni[0] - d.dt_dz * (G[1] - G[0]);
@@ -1015,7 +1034,7 @@ __device__ void fluid_species(const Disch<P>& d, double* lds) {
 
 // Blocks [0, D) advance the ion fluid of discharge blockIdx.x; the others
 // share the particle chunks of all discharges in contiguous segments.
-template <class P, int M>
+template <class P, int M, int W>
 __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, const ElecArgs& a,
                                               unsigned char* smem) {
   const int D = a.D;
@@ -1034,11 +1053,12 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
   }
   const Lds L = lds_layout<P>(a);
   uint32_t* pre = reinterpret_cast<uint32_t*>(smem + L.pre);
-  for (int i = tid; i < D; i += kElecThreads) {
+  for (int i = tid; i < D; i += W * 64) {
     const State* st = ds[i].st;
     const int64_t left = st->steps_left;  // both loads issued together
     const uint32_t n_main = st->n_main;
-    const uint32_t nch = (n_main + (uint32_t)kTile - 1u) / (uint32_t)kTile;
+    constexpr uint32_t chunk = (uint32_t)(W * kSub);
+    const uint32_t nch = (n_main + chunk - 1u) / chunk;
     pre[i + 1] = nch & (left > 0 ? ~0u : 0u);
   }
   if (tid == 0) pre[0] = 0;
@@ -1058,149 +1078,161 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
     const uint32_t end = min(g1, pre[di + 1]);
     // a discharge with no chunks (idle, or an empty slot whose descriptor
     // has no arrays) between two others gets no segment
-    if (end > g0) segment<P, M>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
+    if (end > g0)
+      segment<P, M, W>(ds[di], g0 - pre[di], end - pre[di], smem, L, pb, pre[di], per);
     g0 = end;
     ++di;
   }
 }
 
-// FP32: at most 128 VGPRs so that four waves share each SIMD.
-__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_electron_f32(const Disch<float>* __restrict__ ds, ElecArgs a) {
+// FP32: at most 128 VGPRs so that four waves share each SIMD.  Each kernel
+// but the register-prefetch one has a wide twin (suffix _w): the same body
+// with 1,024-thread workgroups, one per CU, for grids whose LDS leaves room
+// for only one narrow workgroup per CU.
+template <int M, int W>
+__device__ __forceinline__ void f32_body(const Disch<float>* __restrict__ ds, const ElecArgs& a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 0>(ds, a, smem);
+  electron_body<float, M, W>(ds, a, smem);
 }
+#define HD_F32_KERNEL(NAME, M)                                                                \
+  __global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void     \
+  NAME(const Disch<float>* __restrict__ ds, ElecArgs a) {                                    \
+    f32_body<M, 8>(ds, a);                                                                   \
+  }                                                                                          \
+  __global__ __launch_bounds__(kElecThreadsWide) __attribute__((amdgpu_waves_per_eu(4))) void \
+  NAME##_w(const Disch<float>* __restrict__ ds, ElecArgs a) {                                \
+    f32_body<M, 16>(ds, a);                                                                  \
+  }
+HD_F32_KERNEL(k_electron_f32, 0)
+// loads issued without draining the stores first
+HD_F32_KERNEL(k_electron_f32_nd, 2)
+// nontemporal particle loads and write-backs (for particle stores far beyond
+// the MALL), with and without the drain; then the same with the velocities
+// left to the caches
+HD_F32_KERNEL(k_electron_f32_nt, 12)
+HD_F32_KERNEL(k_electron_f32_nd_nt, 14)
+HD_F32_KERNEL(k_electron_f32_np, 4)
+HD_F32_KERNEL(k_electron_f32_nd_np, 6)
+// all particle traffic nontemporal and each chunk's collisions handled
+// before its velocities are written (whole segments only)
+HD_F32_KERNEL(k_electron_f32_nt_sw, 28)
+#undef HD_F32_KERNEL
 
 // FP32 with the next chunk's loads in flight: at most 168 VGPRs, three
 // waves per SIMD.
 __global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(3))) void
 k_electron_f32_pf(const Disch<float>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 1>(ds, a, smem);
-}
-
-// FP32, loads issued without draining the stores first.
-__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_electron_f32_nd(const Disch<float>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 2>(ds, a, smem);
-}
-
-// FP32 with nontemporal particle loads and write-backs (for particle
-// stores far beyond the MALL), with and without the drain; then the same
-// with the velocities left to the caches.
-__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_electron_f32_nt(const Disch<float>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 12>(ds, a, smem);
-}
-__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_electron_f32_nd_nt(const Disch<float>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 14>(ds, a, smem);
-}
-__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_electron_f32_np(const Disch<float>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 4>(ds, a, smem);
-}
-__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_electron_f32_nd_np(const Disch<float>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 6>(ds, a, smem);
-}
-
-// FP32 with all particle traffic nontemporal and each chunk's collisions
-// handled before its velocities are written (whole segments only).
-__global__ __launch_bounds__(kElecThreads) __attribute__((amdgpu_waves_per_eu(4))) void
-k_electron_f32_nt_sw(const Disch<float>* __restrict__ ds, ElecArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<float, 28>(ds, a, smem);
+  f32_body<1, 8>(ds, a);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64(const Disch<double>* __restrict__ ds,
                                                                ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 0>(ds, a, smem);
+  electron_body<double, 0, 8>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_pf(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 1>(ds, a, smem);
+  electron_body<double, 1, 8>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 2>(ds, a, smem);
+  electron_body<double, 2, 8>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nt(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 12>(ds, a, smem);
+  electron_body<double, 12, 8>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd_nt(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 14>(ds, a, smem);
+  electron_body<double, 14, 8>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_np(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 4>(ds, a, smem);
+  electron_body<double, 4, 8>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nd_np(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 6>(ds, a, smem);
+  electron_body<double, 6, 8>(ds, a, smem);
 }
 
 __global__ __launch_bounds__(kElecThreads) void k_electron_f64_nt_sw(
     const Disch<double>* __restrict__ ds, ElecArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  electron_body<double, 28>(ds, a, smem);
+  electron_body<double, 28, 8>(ds, a, smem);
 }
 
-// Kernel variants of one precision, by how the particle data arrive and
-// leave: 0 drain then load, 1 next chunk prefetched, 2 no drain; 3 and 4 as
-// 0 and 2 with nontemporal particle traffic; 5 and 6 as 0 and 2 with
-// nontemporal traffic of ids, cells and offsets only; 7 as 3 with each
-// chunk's velocities written after its collisions.
-constexpr int kElecVariants = 8;
+// Kernels of one precision, by how the particle data arrive and leave:
+// 0 drain then load, 1 next chunk prefetched, 2 no drain; 3 and 4 as 0 and 2
+// with nontemporal particle traffic; 5 and 6 as 0 and 2 with nontemporal
+// traffic of ids, cells and offsets only; 7 as 3 with each chunk's
+// velocities written after its collisions.  Launch variants 8-15 are the
+// same kernels with wide workgroups.
+constexpr int kElecKernels = 8;                    // kernels per precision
+constexpr int kElecVariants = kElecWide + kElecKernels;  // and each with wide workgroups
 template <class P>
 struct ElecKernel;
 template <>
 struct ElecKernel<float> {
-  static constexpr decltype(&k_electron_f32) fn[kElecVariants] = {
+  static constexpr decltype(&k_electron_f32) fn[kElecKernels] = {
       k_electron_f32,       k_electron_f32_pf, k_electron_f32_nd,    k_electron_f32_nt,
       k_electron_f32_nd_nt, k_electron_f32_np, k_electron_f32_nd_np, k_electron_f32_nt_sw};
+  static constexpr decltype(&k_electron_f32) wide[kElecKernels] = {
+      k_electron_f32_w,       nullptr,           k_electron_f32_nd_w,    k_electron_f32_nt_w,
+      k_electron_f32_nd_nt_w, k_electron_f32_np_w, k_electron_f32_nd_np_w, k_electron_f32_nt_sw_w};
 };
 template <>
 struct ElecKernel<double> {
-  static constexpr decltype(&k_electron_f64) fn[kElecVariants] = {
+  static constexpr decltype(&k_electron_f64) fn[kElecKernels] = {
       k_electron_f64,       k_electron_f64_pf, k_electron_f64_nd,    k_electron_f64_nt,
       k_electron_f64_nd_nt, k_electron_f64_np, k_electron_f64_nd_np, k_electron_f64_nt_sw};
+  static constexpr decltype(&k_electron_f64) wide[kElecKernels] = {};
 };
+
+// The kernel of a launch variant (nullptr: no such kernel).
+template <class P>
+auto elec_kernel(int variant) {
+  return variant >= kElecWide ? ElecKernel<P>::wide[variant - kElecWide] : ElecKernel<P>::fn[variant];
+}
 
 }  // namespace
 
+// Variant v < kElecWide: kernel v with kElecThreads per workgroup;
+// kElecWide + v: its wide twin with kElecThreadsWide (FP32 only: the FP64
+// kernels and the register-prefetch kernel use more registers than sixteen
+// waves per CU allow, so they have none and those variants are rejected).
+inline int elec_threads(int variant) {
+  return variant >= kElecWide ? kElecThreadsWide : kElecThreads;
+}
+
 template <class P>
-size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max) {
-  return lds_layout<P>(elec_args<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max)).total;
+size_t electron_lds_bytes(int D, int tab_max, int nn_max, int nb1_max, int fluid_nn, int K_max,
+                          int variant) {
+  return lds_layout<P>(elec_args<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max,
+                                    elec_threads(variant) / 64)).total;
 }
 
 template <class P>
 hipError_t launch_electron_impl(const Disch<P>* d_dev, int D, int grid, int tab_max, int nn_max,
                                 int nb1_max, int fluid_nn, int K_max, int variant, hipStream_t s) {
-  const ElecArgs a = elec_args<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max);
-  const size_t lds = lds_layout<P>(a).total;
   if (variant < 0 || variant >= kElecVariants) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ElecKernel<P>::fn[variant], dim3(grid), dim3(kElecThreads), lds, s, d_dev, a);
+  const int nt = elec_threads(variant);
+  const ElecArgs a = elec_args<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max, nt / 64);
+  const size_t lds = lds_layout<P>(a).total;
+  const auto fk = elec_kernel<P>(variant);
+  if (!fk) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fk, dim3(grid), dim3(nt), lds, s, d_dev, a);
   return hipGetLastError();
 }
 
@@ -1209,20 +1241,22 @@ int electron_occupancy(int tab_max, int nn_max, int nb1_max, int fluid_nn, int K
                        int variant) {
   int nb = 0;
   if (variant < 0 || variant >= kElecVariants) return 0;
-  const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max);
-  const void* fn = (const void*)ElecKernel<P>::fn[variant];
-  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+  const size_t lds = electron_lds_bytes<P>(D, tab_max, nn_max, nb1_max, fluid_nn, K_max, variant);
+  const auto fk = elec_kernel<P>(variant);
+  if (!fk) return 0;  // no wide twin
+  if (hipFuncSetAttribute((const void*)fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+      hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ElecKernel<P>::fn[variant], kElecThreads,
-                                                   lds) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk, elec_threads(variant), lds) !=
+      hipSuccess)
     return 0;
   return nb;
 }
 
 int electron_variants() { return kElecVariants; }
 
-template size_t electron_lds_bytes<float>(int, int, int, int, int, int);
-template size_t electron_lds_bytes<double>(int, int, int, int, int, int);
+template size_t electron_lds_bytes<float>(int, int, int, int, int, int, int);
+template size_t electron_lds_bytes<double>(int, int, int, int, int, int, int);
 template hipError_t launch_electron_impl<float>(const Disch<float>*, int, int, int, int, int, int,
                                                 int, int, hipStream_t);
 template hipError_t launch_electron_impl<double>(const Disch<double>*, int, int, int, int, int,

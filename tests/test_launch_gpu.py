@@ -73,6 +73,11 @@ CONFIGS = [
     {"electron_variant": 6},
     {"electron_variant": 7},
     {"electron_variant": 7, "electron_groups": 3},
+    {"electron_variant": 8},                          # wide workgroups (1,024 threads)
+    {"electron_variant": 10, "electron_groups": 5},
+    {"electron_variant": 13, "electron_groups": 100},
+    {"electron_variant": 14},
+    {"electron_variant": 15, "electron_groups": 2},
     {"sort_groups": 3},
     {"append_groups": 1},
     {"electron_variant": 1, "electron_groups": 1, "sort_groups": 1000, "append_groups": 64},
@@ -119,6 +124,17 @@ def test_invalid_shapes_are_rejected():
         assert e.value.code == -1
     with pytest.raises(hd.HdError):
         b.autotune(8)  # below two sort intervals
+    b.close()
+    # FP64 and the register-prefetch kernel have no wide workgroups
+    d = hd.Discharge(W.c0())
+    with pytest.raises(hd.HdError) as e:
+        d.set_launch({"electron_variant": 8})
+    assert e.value.code == -1
+    d.close()
+    b = hd.Batch(_params()[:2])
+    with pytest.raises(hd.HdError) as e:
+        b.set_launch({"electron_variant": 9})
+    assert e.value.code == -1
     b.close()
 
 
@@ -194,10 +210,14 @@ def test_tune_cache_file_carries_the_choice_across_processes(tmp_path):
 def test_untuned_default_follows_the_mall():
     # Without a cached choice a handle starts cached (variant 0) while its
     # initial particle state fits the 256 MB MALL, else with nontemporal
-    # ids, cells and offsets (variant 5).
-    small = hd.Discharge(W.scaled(W.c1(), 4 << 20))
-    big = hd.Discharge(W.scaled(W.c1(), 12 << 20))
-    assert small.get_launch()["electron_variant"] == 0
-    assert big.get_launch()["electron_variant"] == 5
-    small.close()
-    big.close()
+    # ids, cells and offsets (variant 5); on a grid so large that a narrow
+    # workgroup's LDS leaves room for only one per CU, with wide workgroups
+    # (variants 8 and 13).
+    for cells, gap, wide in ((2048, 1e-3, 0), (4096, 2e-3, 8)):
+        p = W.c1(n_cells=cells, gap_m=gap, ion_model=W.ION_DD)
+        small = hd.Discharge(W.scaled(p, 4 << 20))
+        big = hd.Discharge(W.scaled(p, 12 << 20))
+        assert small.get_launch()["electron_variant"] == 0 + wide
+        assert big.get_launch()["electron_variant"] == 5 + wide
+        small.close()
+        big.close()
