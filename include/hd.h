@@ -322,14 +322,16 @@ int hd_batch_free(hd_batch* b);
 /* ---- launch shapes and the autotuner ------------------------------------- */
 
 /* How the kernels of one handle are launched.  No field changes any result:
- * particles are processed in fixed chunks of 2,048 (eight waves of 256) and
- * every order that reaches a result (deposit sums in 64-bit integers,
- * children in parent order, stable sort tiles of 4,096) is independent of
- * the launch shape, so results are bitwise identical under every valid
- * configuration.  A value of 0 selects the default; a new handle starts
- * from the autotuner's cached choice for its shape if there is one, else
- * from the defaults with electron variant 5 when its initial particle state
- * exceeds the 256 MB MALL and 0 otherwise. */
+ * particles are processed in fixed sub-chunks of 256 (one wave's four
+ * particles per lane), and every order that reaches a result (deposit sums
+ * in 64-bit integers, children in parent order, stable sort tiles of 4,096)
+ * is independent of the launch shape, so results are bitwise identical
+ * under every valid configuration.  A value of 0 selects the default; a new
+ * handle starts from the autotuner's cached choice for its shape if there
+ * is one, else from the defaults with electron variant 5 when its initial
+ * particle state exceeds the 256 MB MALL and 0 otherwise, each moved to its
+ * wide form (variant + 8) when the grid is so large that the LDS of a
+ * 512-thread workgroup leaves room for only one per compute unit. */
 typedef struct hd_launch_config {
   int32_t electron_variant; /* 0: each chunk of particles is loaded after the
                                previous chunk's stores have drained (FP32:
@@ -346,7 +348,13 @@ typedef struct hd_launch_config {
                                collision handler rewrites, stay cached);
                                7: as 3, with each chunk's collisions handled
                                before its velocities are written, in whole
-                               64-byte segments                            */
+                               64-byte segments.  These use 512-thread
+                               workgroups (chunks of 2,048 particles);
+                               8 + v: variant v with 1,024-thread workgroups
+                               (chunks of 4,096), one per compute unit with
+                               four waves per SIMD where large grids leave
+                               LDS for only one narrow workgroup; FP32 only,
+                               and not for variant 1 (9 is rejected)     */
   int32_t electron_groups;  /* particle workgroups of the electron launch,
                                1 .. 4096 (0: as many as fit on the device at
                                once)                                       */
@@ -395,7 +403,9 @@ int hd_autotune(hd_discharge* h, int64_t max_steps, hd_launch_config* out);
  * the server's precision, sort_every and eedf_every and fit its caps.  An
  * interval runs with electron variant 5 (nontemporal traffic of ids, cells
  * and offsets) when the admitted jobs' initial particle state exceeds the
- * 256 MB MALL, else with variant 0. */
+ * 256 MB MALL, else with variant 0, each in its wide form (13, 8) when the
+ * slots' largest grid leaves LDS for only one 512-thread workgroup per
+ * compute unit. */
 typedef struct hd_server hd_server;
 
 typedef struct hd_server_config {
