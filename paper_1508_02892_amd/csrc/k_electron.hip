@@ -24,7 +24,6 @@ constexpr double kECharge = 1.602176634e-19;
 // large grid leaves room for only one narrow one); a chunk is four particles
 // per thread, so 2,048 or 4,096 slots.
 constexpr int kElecThreadsWide = 2 * kElecThreads;
-constexpr int kMaxWaves = kElecThreadsWide / 64;
 constexpr int kWQ = 128;                   // per-wave collision queue entries
 constexpr int kTabLds = 1024;              // collision-table rows kept in LDS (0 .. 102.3 eV
                                            // at 10 points per eV); higher rows via the cache
@@ -70,8 +69,7 @@ struct ElecArgs {
 
 struct Lds {
   uint32_t tab, ep, bins, q, eedf, ctr, pre, kids, total;
-  uint32_t rows;   // collision-table rows held in LDS
-  uint32_t waves;  // waves per workgroup
+  uint32_t rows;  // collision-table rows held in LDS
 };
 
 // LDS counters: [0, kMaxK) collisions per channel, then these.
@@ -86,7 +84,6 @@ __host__ __device__ inline Lds lds_layout(const ElecArgs& a) {
                                ? (uint32_t)a.tab_max : rows * (uint32_t)a.K_max;
   Lds L;
   L.rows = rows;
-  L.waves = (uint32_t)a.waves;
   L.tab = 0;
   L.ep = al(L.tab + tab_lds * (uint32_t)sizeof(P));
   L.bins = al(L.ep + (uint32_t)a.nn_max * (uint32_t)sizeof(P));
@@ -155,8 +152,6 @@ struct Seg {
   uint32_t seed_lo, seed_hi, step, n_main;
   uint32_t* kl;       // LDS copy of the segment's first kKidsLds sub-chunk child counts
   uint32_t kbase;     // index of the segment's first sub-chunk
-  uint32_t waves;     // waves per workgroup (sub-chunks per chunk)
-  uint32_t chunk;     // slots per chunk
   bool sample;
 };
 
@@ -707,9 +702,7 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   g.n_main = st->n_main;
   g.sample = ((st->step + 1) % d.eedf_every) == 0;
   g.kl = reinterpret_cast<uint32_t*>(smem + L.kids);
-  g.waves = (uint32_t)W;
-  g.chunk = (uint32_t)(W * kSub);
-  g.kbase = lc0 * g.waves;
+  g.kbase = lc0 * (uint32_t)W;
   QEntry<P>* q = reinterpret_cast<QEntry<P>*>(smem + L.q) + (size_t)wv * kWQ;
   lds_copy2<W * 64>(tab, gptr(d.tab), g.tab_rows * d.K, ep, gptr(d.Ep), d.nn);
   for (int i = tid; i < d.nn; i += nt) g.bins[i] = 0;
@@ -748,14 +741,14 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
   // flushes so that nothing waits for their atomics.  The counts come from
   // LDS when the segment has at most kKidsLds sub-chunks; otherwise from
   // memory, after a barrier that waits for every wave's stores.
-  const uint32_t k0 = lc0 * g.waves, k1 = lc1 * g.waves;
+  const uint32_t k0 = lc0 * (uint32_t)W, k1 = lc1 * (uint32_t)W;
   const bool kids_lds = k1 - k0 <= kKidsLds;
   if (kids_lds)
     lds_barrier();
   else
     __syncthreads();
   {
-    __shared__ uint32_t sh[kMaxWaves];
+    __shared__ uint32_t sh[W];
     Gp<uint32_t>* kbase = gptr(d.chunk_base);
     uint32_t carry = 0;
     if (kids_lds) {  // at most kKidsLds <= kElecThreads counts: one round
@@ -777,7 +770,7 @@ __device__ void segment(const Disch<P>& d, uint32_t lc0, uint32_t lc1, unsigned 
     if (tid == 0) {
       gptr(d.seg)[pb] = carry;
       if (lc0 == 0) {  // in chunks of kTile slots, whatever this launch's chunk
-        const uint32_t r = g.chunk / (uint32_t)kTile;
+        constexpr uint32_t r = (uint32_t)(W * kSub / kTile);
         st->seg_off = chunk0 * r;
         st->seg_per = per * r;
       }
