@@ -321,6 +321,13 @@ __device__ __forceinline__ int select_channel(const Seg<P>& g, P u0, P vx, P vy,
       if (K % kL == 0) {
         typedef __attribute__((ext_vector_type(kL))) P V;
         const P* ra = g.tab + i * K;
+        // Each interpolated value a + t (b - a), 0 <= t <= 1, is at most
+        // max(a, b)(1 + 3u) with u the unit roundoff, and the cumulative rows
+        // peak at their last channel: at or above this bound no channel is
+        // hit, so most null candidates skip the loop.
+        constexpr double kSlack = sizeof(P) == 4 ? 0x1p-21 : 0x1p-50;
+        const P top = fmax(ra[K - 1], ra[2 * K - 1]) * (P)(1.0 + kSlack);
+        if (!(u0 < top)) return -1;
         uint32_t hit = 0;
 #pragma unroll 1
         for (int k = 0; k < K; k += kL) {
