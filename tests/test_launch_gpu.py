@@ -75,6 +75,8 @@ CONFIGS = [
     {"electron_variant": 7, "electron_groups": 3},
     {"electron_variant": 8},                          # wide workgroups (1,024 threads)
     {"electron_variant": 10, "electron_groups": 5},
+    {"electron_variant": 11},
+    {"electron_variant": 12, "electron_groups": 50},
     {"electron_variant": 13, "electron_groups": 100},
     {"electron_variant": 14},
     {"electron_variant": 15, "electron_groups": 2},
