@@ -507,51 +507,69 @@ __global__ __launch_bounds__(kThreads) void k_checkpoint(const Disch<P>* __restr
                                                          int restore) {
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t gsz = (size_t)gridDim.x * blockDim.x;
-  for (int di = 0; di < D; ++di) {
-    const Disch<P>& d = ds[di];
-    State* st = d.st;
-    State* sv = reinterpret_cast<State*>(d.ckpt + d.grid_bytes);
+  // restore = 0: the decisions of kThreads discharges at a time are read in
+  // parallel (1: take a checkpoint, 2: mark it invalid, 0: keep it), so that
+  // a batch does not wait for one state's round trip per discharge
+  __shared__ uint8_t take[kThreads];
+  for (int g0 = 0; g0 < D; g0 += kThreads) {
+    const int ng = min(kThreads, D - g0);
     if (!restore) {
-      if (st->error) continue;  // an interval stopped by an error keeps its checkpoint
-      if (!(st->ckpt_due && st->steps_left > 0)) {
-        if (gid == 0) st->ckpt_valid = 0;
+      uint8_t f = 0;
+      if ((int)threadIdx.x < ng) {
+        State* st = ds[g0 + (int)threadIdx.x].st;
+        const int err = st->error;
+        const int due = st->ckpt_due;
+        const int64_t left = st->steps_left;
+        // an interval stopped by an error keeps its checkpoint
+        f = err ? 0 : ((due && left > 0) ? 1 : 2);
+        if (f == 2 && blockIdx.x == 0) st->ckpt_valid = 0;
+      }
+      take[threadIdx.x] = f;
+      __syncthreads();
+    }
+    for (int di = g0; di < g0 + ng; ++di) {
+      const Disch<P>& d = ds[di];
+      State* st = d.st;
+      State* sv = reinterpret_cast<State*>(d.ckpt + d.grid_bytes);
+      if (!restore) {
+        if (take[di - g0] != 1) continue;
+      } else if (!st->ckpt_valid) {
         continue;
       }
-    } else if (!st->ckpt_valid) {
-      continue;
-    }
-    const int cur = restore ? sv->buf : st->buf;
-    const size_t n = restore ? sv->n_main : st->n_main;
-    const int src = restore ? cur ^ 1 : cur, dst = src ^ 1;
-    for (size_t i = gid; i < n; i += gsz) {
-      d.cell[dst][i] = d.cell[src][i];
-      d.off[dst][i] = d.off[src][i];
-      d.vx[dst][i] = d.vx[src][i];
-      d.vy[dst][i] = d.vy[src][i];
-      d.vz[dst][i] = d.vz[src][i];
-      d.id[dst][i] = d.id[src][i];
-    }
-    uint4* grid = reinterpret_cast<uint4*>(d.cnt[0]);
-    uint4* keep = reinterpret_cast<uint4*>(d.ckpt);
-    const size_t words = d.grid_bytes / 16;
-    for (size_t w = gid; w < words; w += gsz) {
-      if (restore)
-        grid[w] = keep[w];
-      else
-        keep[w] = grid[w];
-    }
-    if (gid == 0) {
-      if (!restore) {
-        *sv = *st;
-        st->ckpt_valid = 1;
-        st->ckpt_step = st->step;
-      } else {
-        State x = *sv;
-        x.ckpt_valid = 1;  // the checkpoint still holds this state
-        x.ckpt_step = x.step;
-        *st = x;
+      const int cur = restore ? sv->buf : st->buf;
+      const size_t n = restore ? sv->n_main : st->n_main;
+      const int src = restore ? cur ^ 1 : cur, dst = src ^ 1;
+      for (size_t i = gid; i < n; i += gsz) {
+        d.cell[dst][i] = d.cell[src][i];
+        d.off[dst][i] = d.off[src][i];
+        d.vx[dst][i] = d.vx[src][i];
+        d.vy[dst][i] = d.vy[src][i];
+        d.vz[dst][i] = d.vz[src][i];
+        d.id[dst][i] = d.id[src][i];
+      }
+      uint4* grid = reinterpret_cast<uint4*>(d.cnt[0]);
+      uint4* keep = reinterpret_cast<uint4*>(d.ckpt);
+      const size_t words = d.grid_bytes / 16;
+      for (size_t w = gid; w < words; w += gsz) {
+        if (restore)
+          grid[w] = keep[w];
+        else
+          keep[w] = grid[w];
+      }
+      if (gid == 0) {
+        if (!restore) {
+          *sv = *st;
+          st->ckpt_valid = 1;
+          st->ckpt_step = st->step;
+        } else {
+          State x = *sv;
+          x.ckpt_valid = 1;  // the checkpoint still holds this state
+          x.ckpt_step = x.step;
+          *st = x;
+        }
       }
     }
+    if (!restore) __syncthreads();  // take[] is refilled for the next discharges
   }
 }
 
