@@ -320,13 +320,19 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
   // run[w][c - lo]: cursor of wave w for cell c; the unit prefix follows
   uint32_t* run = reinterpret_cast<uint32_t*>(smem);
   uint32_t* pre = run + (size_t)kWavesPerBlock * (size_t)stride;
-  // the scan blocks' totals are zero again for the next sort's counts
-  for (int di = 0; di < D; ++di) {
-    const Disch<P>& d = ds[di];
-    if (!d.st->sort_due) continue;
-    const uint32_t nb = scan_blocks(d);
-    for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nb; i += gridDim.x * kThreads) d.bin_start[i] = 0u;
+  // the scan blocks' totals are zero again for the next sort's counts: one
+  // flat index over the due discharges' blocks (their counts read in
+  // parallel, not one discharge's state after another)
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return scan_blocks_due(d); });
+  {
+    const uint32_t nz = pre[D];
+    int dz = 0;
+    for (uint32_t u = blockIdx.x * kThreads + threadIdx.x; u < nz; u += gridDim.x * kThreads) {
+      while (pre[dz + 1] <= u) ++dz;
+      ds[dz].bin_start[u - pre[dz]] = 0u;
+    }
   }
+  __syncthreads();  // pre[] is reused for the tiles
   unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due(d); });
   const uint32_t total = pre[D];
   int di = 0;
