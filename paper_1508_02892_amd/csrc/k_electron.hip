@@ -1053,18 +1053,37 @@ __device__ __forceinline__ void electron_body(const Disch<P>* __restrict__ ds, c
   }
   const Lds L = lds_layout<P>(a);
   uint32_t* pre = reinterpret_cast<uint32_t*>(smem + L.pre);
-  for (int i = tid; i < D; i += W * 64) {
+  // chunks of discharge i (none when it has no steps left)
+  auto chunks = [&](int i) {
     const State* st = ds[i].st;
     const int64_t left = st->steps_left;  // both loads issued together
     const uint32_t n_main = st->n_main;
     constexpr uint32_t chunk = (uint32_t)(W * kSub);
     const uint32_t nch = (n_main + chunk - 1u) / chunk;
-    pre[i + 1] = nch & (left > 0 ? ~0u : 0u);
+    return nch & (left > 0 ? ~0u : 0u);
+  };
+  if (D <= 4) {  // a few discharges: a serial prefix in LDS
+    if (tid < D) pre[tid + 1] = chunks(tid);
+    if (tid == 0) pre[0] = 0;
+    lds_barrier();
+    if (tid == 0)
+      for (int i = 0; i < D; ++i) pre[i + 1] += pre[i];
+  } else if (tid < 64) {  // a batch: wave scans of 64 discharges at a time
+    uint32_t carry = 0;
+    for (int b = 0; b < D; b += 64) {
+      const int i = b + tid;
+      const uint32_t v = i < D ? chunks(i) : 0u;
+      uint32_t x = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (tid >= o) x += y;
+      }
+      if (i < D) pre[i + 1] = carry + x;
+      carry += __shfl(x, 63, 64);
+    }
+    if (tid == 0) pre[0] = 0;
   }
-  if (tid == 0) pre[0] = 0;
-  lds_barrier();
-  if (tid == 0)
-    for (int i = 0; i < D; ++i) pre[i + 1] += pre[i];
   lds_barrier();
   const uint32_t total = pre[D];
   const uint32_t G = gridDim.x - (uint32_t)D, pb = blockIdx.x - (uint32_t)D;
