@@ -1467,11 +1467,8 @@ struct Batch : BatchBase {
     for (int v = 0; v < electron_variants(); ++v) {
       const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v);
       if (occ < 1) continue;
-      // wide workgroups only where the narrow ones fit one per CU, and then
-      // only as many as the CUs (fewer would leave CUs idle)
-      if (v >= kElecWide &&
-          electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v - kElecWide) != 1)
-        continue;
+      // wide workgroups only as many as fit at once (fewer would leave CUs
+      // idle)
       const int full = std::min(cus * occ, (int)kMaxSegs);
       for (int g : {full, std::max(1, full * 3 / 4), std::max(1, full / 2)}) {
         if (v >= kElecWide && g != full) continue;
