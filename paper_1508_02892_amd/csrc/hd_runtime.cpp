@@ -634,6 +634,7 @@ struct BatchBase {
   int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0, fluid_nn = 0, K_max = 1;
   int cus = 0;              // compute units of the device
   int elec_variant = 0;     // electron kernel variant (hd_launch_config)
+  uint64_t state_bytes = 0; // initial particle state of all discharges
   hd_launch_config launch{};  // the applied shapes, defaults resolved
   std::string tune_key;     // the batch's key in the autotuner's cache
   int64_t host_step = 0;  // steps enqueued (all discharges advance together)
@@ -860,6 +861,7 @@ struct Batch : BatchBase {
     {
       uint64_t bytes = 0;
       for (const auto& h : hs) bytes += (uint64_t)h.p.n_macro * (8u + 4u * sizeof(P));
+      state_bytes = bytes;
       if (bytes > kMallBytes) lc0.electron_variant = kElecVariantStreaming;
       lc0.electron_variant = widen_variant<P>(lc0.electron_variant, tab_max, nn_max, nb1_max,
                                               fluid_nn, K_max, D);
@@ -1467,8 +1469,13 @@ struct Batch : BatchBase {
     for (int v = 0; v < electron_variants(); ++v) {
       const int occ = electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v);
       if (occ < 1) continue;
-      // wide workgroups only as many as fit at once (fewer would leave CUs
-      // idle)
+      // wide workgroups where the narrow ones fit once per CU or the
+      // particle state streams from HBM (measured faster in both cases, and
+      // slower where two narrow workgroups per CU work in the MALL), and
+      // only as many as fit at once (fewer would leave CUs idle)
+      if (v >= kElecWide && state_bytes <= kMallBytes &&
+          electron_occupancy<P>(tab_max, nn_max, nb1_max, fluid_nn, K_max, D, v - kElecWide) != 1)
+        continue;
       const int full = std::min(cus * occ, (int)kMaxSegs);
       for (int g : {full, std::max(1, full * 3 / 4), std::max(1, full / 2)}) {
         if (v >= kElecWide && g != full) continue;
