@@ -353,8 +353,10 @@ typedef struct hd_launch_config {
                                8 + v: variant v with 1,024-thread workgroups
                                (chunks of 4,096), one per compute unit with
                                four waves per SIMD where large grids leave
-                               LDS for only one narrow workgroup; FP32 only,
-                               and not for variant 1 (9 is rejected)     */
+                               LDS for only one narrow workgroup (the
+                               autotuner also tries them when the particle
+                               state exceeds the MALL); FP32 only, and not
+                               for variant 1 (9 is rejected)               */
   int32_t electron_groups;  /* particle workgroups of the electron launch,
                                1 .. 4096 (0: as many as fit on the device at
                                once)                                       */
