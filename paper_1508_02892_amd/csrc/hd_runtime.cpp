@@ -642,7 +642,18 @@ struct BatchBase {
   int64_t rollbacks = 0;    // capacity overflows rolled back
   bool replaying = false;   // re-running the steps of a rolled-back interval
   bool rolled_back = false; // stopped at an overflow; hd_grow clears it
-  hipGraphExec_t graph = nullptr;
+  hipGraphExec_t graph = nullptr;       // one sort interval
+  hipGraphExec_t graph_long = nullptr;  // kLongIntervals sort intervals
+  // Intervals in the long graph: every graph launch leaves the GPU idle for
+  // a few microseconds between the graphs, which the long one pays once per
+  // kLongIntervals intervals.
+  static constexpr int kLongIntervals = 8;
+  void drop_graphs() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (graph_long) (void)hipGraphExecDestroy(graph_long);
+    graph = nullptr;
+    graph_long = nullptr;
+  }
   bool graph_ok = true;   // capture supported
   int error = 0;
   hipStream_t own_stream = nullptr;  // created when the caller passes the null stream
@@ -658,9 +669,7 @@ struct Batch : BatchBase {
 
   DevMem mem;
 
-  ~Batch() override {
-    if (graph) (void)hipGraphExecDestroy(graph);
-  }
+  ~Batch() override { drop_graphs(); }
 
   // Host-side preparation of one discharge (no device calls): derived
   // constants, tables, the initial load and the voltage table.
@@ -924,10 +933,7 @@ struct Batch : BatchBase {
     if (changed) {
       HD_TRY(hipStreamSynchronize(stream));
       HD_TRY(upload_desc());
-      if (graph) {
-        (void)hipGraphExecDestroy(graph);
-        graph = nullptr;
-      }
+      drop_graphs();
     }
     return HD_OK;
   }
@@ -954,10 +960,7 @@ struct Batch : BatchBase {
     grid_s = c.sort_groups;
     grid_a = c.append_groups;
     launch = c;
-    if (graph) {  // captured with the old shapes
-      (void)hipGraphExecDestroy(graph);
-      graph = nullptr;
-    }
+    drop_graphs();  // captured with the old shapes
     return HD_OK;
   }
 
@@ -975,22 +978,24 @@ struct Batch : BatchBase {
     return e;
   }
 
-  int capture() {
+  // Captures `intervals` sort intervals of steps into out; on failure the
+  // handle falls back to direct launches of the same kernels.
+  int capture(hipGraphExec_t& out, int intervals) {
     hipGraph_t g = nullptr;
     HD_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int s = 0; s < sort_every && e == hipSuccess; ++s)
-      e = enqueue_step(s == sort_every - 1, s == 0);
+    for (int s = 0; s < intervals * sort_every && e == hipSuccess; ++s)
+      e = enqueue_step(s % sort_every == sort_every - 1, s % sort_every == 0);
     hipError_t e2 = hipStreamEndCapture(stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
       graph_ok = false;
-      return HD_OK;  // fall back to direct launches of the same kernels
+      return HD_OK;
     }
-    e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-      graph = nullptr;
+      out = nullptr;
       graph_ok = false;
     }
     return HD_OK;
@@ -1009,14 +1014,20 @@ struct Batch : BatchBase {
     while (host_step < target) {
       const int64_t left = target - host_step;
       if (host_step % sort_every == 0 && left >= sort_every && graph_ok && use_graph) {
-        if (!graph) {
-          rc = capture();
+        if (!graph) {  // both graphs at once, so that neither is captured mid-run
+          rc = capture(graph, 1);
+          if (rc == HD_OK && graph_ok) rc = capture(graph_long, kLongIntervals);
           if (rc) return rc;
-          if (!graph) continue;
+          if (!graph || !graph_long) {
+            drop_graphs();
+            continue;
+          }
         }
-        HD_TRY(hipGraphLaunch(graph, stream));
-        host_step += sort_every;
-        graph_steps += sort_every;
+        const bool lng = left >= (int64_t)kLongIntervals * sort_every;
+        HD_TRY(hipGraphLaunch(lng ? graph_long : graph, stream));
+        const int64_t k = (int64_t)(lng ? kLongIntervals : 1) * sort_every;
+        host_step += k;
+        graph_steps += k;
       } else {
         const bool srt = ((host_step + 1) % sort_every) == 0;
         HD_TRY(enqueue_step(srt, host_step % sort_every == 0 && !replaying));
@@ -1218,10 +1229,7 @@ struct Batch : BatchBase {
     HD_TRY(hipMemcpy(h.dd.st, &st, sizeof(State), hipMemcpyHostToDevice));
     host_step = st.step;
     rolled_back = false;
-    if (graph) {  // a graph holds no step-dependent input, but start clean
-      (void)hipGraphExecDestroy(graph);
-      graph = nullptr;
-    }
+    drop_graphs();  // a graph holds no step-dependent input, but start clean
     return ensure_volt(host_step + 1);
   }
 
@@ -1272,10 +1280,7 @@ struct Batch : BatchBase {
     }
     HD_TRY(upload_desc());
     mem.release(ob);
-    if (graph) {
-      (void)hipGraphExecDestroy(graph);
-      graph = nullptr;
-    }
+    drop_graphs();
     rolled_back = false;
     return HD_OK;
   }
