@@ -151,12 +151,13 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
   __shared__ int sh_lo[kWavesPerBlock], sh_hi[kWavesPerBlock];
   constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // each wave owns stride (>= the largest nc + 1) words for the whole
-  // launch, zero between tiles; the unit prefix follows them
-  uint32_t* run = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* h = run + (size_t)wv * (size_t)stride;
-  uint32_t* pre = run + (size_t)kWavesPerBlock * (size_t)stride;
-  for (int c = lane; c < stride; c += 64) h[c] = 0u;
+  // one histogram of stride (>= the largest nc + 1) words for the whole
+  // launch, shared by the four waves (LDS atomics) and zero between tiles,
+  // so that the LDS of a large grid still lets several workgroups share a
+  // CU; the unit prefix follows it
+  uint32_t* h = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* pre = h + (size_t)stride;
+  for (int c = (int)threadIdx.x; c < stride; c += kThreads) h[c] = 0u;
   unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due(d); });
   const uint32_t total = pre[D];
   int di = 0;
@@ -213,8 +214,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
     // Cells lo .. lo + 7 are counted in 8-bit fields of one register per
     // lane (at most 16 items per lane), then in 16-bit fields summed over
     // the wave (at most kQuarter per cell); other cells go straight to the
-    // wave's histogram.  With nearly sorted cells an atomic per item would
-    // have all 64 lanes on one address.
+    // histogram.  With nearly sorted cells an atomic per item would have
+    // all 64 lanes on one address.
     uint64_t a8 = 0;
 #pragma unroll
     for (int q = 0; q < kRounds; ++q) {
@@ -238,17 +239,13 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
                                      ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
     if (lane < 8 && lo + lane < nc) {
       const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
-      if (v) h[lo + lane] += v;
+      if (v) atomicAdd(&h[lo + lane], v);
     }
     __syncthreads();
-    // the tile's count of each cell: the sum over the four waves
+    // the tile's count of each cell
     for (int c = lo + (int)threadIdx.x; c <= hi; c += kThreads) {
-      uint32_t v = 0;
-#pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) {
-        v += run[w * stride + c];
-        run[w * stride + c] = 0u;
-      }
+      const uint32_t v = h[c];
+      h[c] = 0u;
       if (v) {
         hist[(size_t)c * nt + t] = v;
         // the total of the scan block holding this entry
@@ -585,7 +582,8 @@ template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
   const size_t pre = (size_t)(D + 1) * 4u;
   const size_t lds = (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u + pre;
-  hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
+  const size_t lds_count = (size_t)(nc_max + 1) * 4u + pre;
+  hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds_count, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), pre, s, d_dev, D);
   hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
@@ -603,7 +601,8 @@ hipError_t sort_set_lds(int nc_max, int D) {
   const int pre = (D + 1) * 4;
   const int lds = kWavesPerBlock * (nc_max + 1) * 4 + pre;
   hipError_t e = hipFuncSetAttribute((const void*)k_sort_count<P>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (nc_max + 1) * 4 + pre);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_scan_down<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           pre);
