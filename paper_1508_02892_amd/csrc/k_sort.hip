@@ -23,6 +23,9 @@ namespace {
 constexpr int kScanItems = 16;                         // per thread
 constexpr int kScanBlock = kThreads * kScanItems;      // elements per scan block
 constexpr int kWavesPerBlock = kThreads / 64;
+constexpr int kScatterWindow = 1024;  // cells per window of the scatter's cursor arrays
+// Cursor words per wave of the scatter.
+inline int scatter_stride(int nc_max) { return nc_max + 1 < kScatterWindow ? nc_max + 1 : kScatterWindow; }
 
 template <class P>
 __device__ __forceinline__ uint32_t n_tiles(const Disch<P>& d) {
@@ -355,123 +358,135 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     Gp<P>* d_vz = gptr(d.vz[dst]);
     Gp<uint32_t>* d_id = gptr(d.id[dst]);
     const int lo = gptr(d.tile_rng)[2 * t], hi = gptr(d.tile_rng)[2 * t + 1];
-    const int span = hi - lo + 1;  // 0 for a tile of holes only
     const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
     const uint32_t e = min(n, b + kQuarter);
     uint32_t* myrun = run + wv * stride;
-    // counts of this wave's quarter
-    for (int c = lane; c < span; c += 64) myrun[c] = 0u;
-    __builtin_amdgcn_wave_barrier();
-    {
-      constexpr int kRounds = (int)(kQuarter / 256u);
-      int32_t c4[kRounds][4];
+    // The tile's cells in windows of at most stride cells (one window for
+    // all but the most spread-out tiles: the LDS then fits several
+    // workgroups per CU at the largest grids); a tile of holes only has none.
+    for (int wlo = lo; wlo <= hi; wlo += stride) {
+      const int whi = min(hi, wlo + stride - 1);
+      const int span = whi - wlo + 1;
+      // counts of this wave's quarter in the window
+      for (int c = lane; c < span; c += 64) myrun[c] = 0u;
+      __builtin_amdgcn_wave_barrier();
+      {
+        constexpr int kRounds = (int)(kQuarter / 256u);
+        int32_t c4[kRounds][4];
 #pragma unroll
-      for (int q = 0; q < kRounds; ++q) {
-        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
-        if (i < e) gld4(cell + i, c4[q]);
-      }
-      // cells lo .. lo + 7 in packed fields as in the count (at most 16
-      // items per lane, kQuarter per cell), the others by atomics
-      uint64_t a8 = 0;
+        for (int q = 0; q < kRounds; ++q) {
+          const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+          if (i < e) gld4(cell + i, c4[q]);
+        }
+        // cells wlo .. wlo + 7 in packed fields as in the count (at most 16
+        // items per lane, kQuarter per cell), the others by atomics
+        uint64_t a8 = 0;
 #pragma unroll
-      for (int q = 0; q < kRounds; ++q) {
-        const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
+        for (int q = 0; q < kRounds; ++q) {
+          const uint32_t i = b + 256u * (uint32_t)q + 4u * (uint32_t)lane;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (i + (uint32_t)k < e && c4[q][k] >= 0) {
-            const uint32_t o = (uint32_t)(c4[q][k] - lo);
-            if (o < 8u)
-              a8 += 1ull << (8u * o);
-            else
-              atomicAdd(&myrun[o], 1u);
-          }
-      }
-      const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
-      const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
-                                       ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
-      const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
-                                       ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
-      if (lane < 8) {
-        const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
-        if (v) myrun[lane] += v;
-      }
-    }
-    __syncthreads();
-    // cursors: the tile's first slot for the cell, then the earlier waves
-    // (only cells present in the tile: the range can be wide and sparse)
-    for (int c = threadIdx.x; c < span; c += kThreads) {
-      uint32_t k[kWavesPerBlock], tot = 0;
-#pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) {
-        k[w] = run[w * stride + c];
-        tot += k[w];
-      }
-      if (tot == 0) continue;
-      uint32_t r = gptr(d.hist)[(size_t)(lo + c) * nt + t];
-      gptr(d.hist)[(size_t)(lo + c) * nt + t] = 0u;  // zero for the next sort's counts
-#pragma unroll
-      for (int w = 0; w < kWavesPerBlock; ++w) {
-        run[w * stride + c] = r;
-        r += k[w];
-      }
-    }
-    __syncthreads();
-    // rounds of 64 items whose loads are issued together; the source
-    // arrays are read once, with the nontemporal hint, so that they do not
-    // displace the destination's partly written lines from the caches
-    constexpr int R = 8;
-    for (uint32_t r = b; r < e; r += 64u * R) {
-      int key[R];
-      P o_[R], x_[R], y_[R], z_[R];
-      uint32_t id_[R];
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const uint32_t i = r + 64u * q + (uint32_t)lane;
-        key[q] = nc;
-        if (i < e) {
-          const int c = __builtin_nontemporal_load(cell + i);
-          key[q] = c >= 0 ? c : nc;
-          o_[q] = __builtin_nontemporal_load(s_off + i);
-          x_[q] = __builtin_nontemporal_load(s_vx + i);
-          y_[q] = __builtin_nontemporal_load(s_vy + i);
-          z_[q] = __builtin_nontemporal_load(s_vz + i);
-          id_[q] = __builtin_nontemporal_load(s_id + i);
+          for (int k = 0; k < 4; ++k)
+            if (i + (uint32_t)k < e && c4[q][k] >= 0) {
+              const uint32_t o = (uint32_t)(c4[q][k] - wlo);
+              if (o < (uint32_t)span) {
+                if (o < 8u)
+                  a8 += 1ull << (8u * o);
+                else
+                  atomicAdd(&myrun[o], 1u);
+              }
+            }
+        }
+        const uint32_t w0 = (uint32_t)a8, w1 = (uint32_t)(a8 >> 32);
+        const uint64_t s0 = wave_sum_u64((uint64_t)(w0 & 0xffu) | ((uint64_t)((w0 >> 8) & 0xffu) << 16) |
+                                         ((uint64_t)((w0 >> 16) & 0xffu) << 32) | ((uint64_t)(w0 >> 24) << 48));
+        const uint64_t s1 = wave_sum_u64((uint64_t)(w1 & 0xffu) | ((uint64_t)((w1 >> 8) & 0xffu) << 16) |
+                                         ((uint64_t)((w1 >> 16) & 0xffu) << 32) | ((uint64_t)(w1 >> 24) << 48));
+        if (lane < 8) {
+          const uint32_t v = (uint32_t)(((lane < 4) ? s0 : s1) >> (16 * (lane & 3))) & 0xffffu;
+          if (v) myrun[lane] += v;
         }
       }
-      uint32_t dest[R];
+      __syncthreads();
+      // cursors: the tile's first slot for the cell, then the earlier waves
+      // (only cells present in the tile: the range can be wide and sparse)
+      for (int c = threadIdx.x; c < span; c += kThreads) {
+        uint32_t k[kWavesPerBlock], tot = 0;
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int k = key[q];
-        const int k0 = __builtin_amdgcn_readfirstlane(k);
-        uint64_t peers = ~0ull;
-        if (__ballot(k == k0) != ~0ull) {
-          for (int bit = 0; bit < nbits; ++bit) {
-            const bool on = (k >> bit) & 1;
-            const uint64_t m = __ballot(on);
-            peers &= on ? m : ~m;
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+          k[w] = run[w * stride + c];
+          tot += k[w];
+        }
+        if (tot == 0) continue;
+        uint32_t r = gptr(d.hist)[(size_t)(wlo + c) * nt + t];
+        gptr(d.hist)[(size_t)(wlo + c) * nt + t] = 0u;  // zero for the next sort's counts
+#pragma unroll
+        for (int w = 0; w < kWavesPerBlock; ++w) {
+          run[w * stride + c] = r;
+          r += k[w];
+        }
+      }
+      __syncthreads();
+      // rounds of 64 items whose loads are issued together; the source
+      // arrays are read once per window, with the nontemporal hint, so that
+      // they do not displace the destination's partly written lines from
+      // the caches; items of other windows wait for theirs
+      constexpr int R = 8;
+      for (uint32_t r = b; r < e; r += 64u * R) {
+        int key[R];
+        P o_[R], x_[R], y_[R], z_[R];
+        uint32_t id_[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const uint32_t i = r + 64u * q + (uint32_t)lane;
+          key[q] = nc;
+          if (i < e) {
+            const int c = __builtin_nontemporal_load(cell + i);
+            key[q] = c >= 0 ? c : nc;
+            o_[q] = __builtin_nontemporal_load(s_off + i);
+            x_[q] = __builtin_nontemporal_load(s_vx + i);
+            y_[q] = __builtin_nontemporal_load(s_vy + i);
+            z_[q] = __builtin_nontemporal_load(s_vz + i);
+            id_[q] = __builtin_nontemporal_load(s_id + i);
           }
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        const uint32_t cntk = (uint32_t)__popcll(peers);
-        dest[q] = 0;
-        if (k < nc) {
-          const uint32_t base = myrun[k - lo];
-          if (rank == 0) myrun[k - lo] = base + cntk;
-          dest[q] = base + rank;
-        }
-      }
+        uint32_t dest[R];
+        bool here[R];
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        if (key[q] < nc) {
-          const uint32_t o = dest[q];
-          d_cell[o] = key[q];
-          d_off[o] = o_[q];
-          d_vx[o] = x_[q];
-          d_vy[o] = y_[q];
-          d_vz[o] = z_[q];
-          d_id[o] = id_[q];
+        for (int q = 0; q < R; ++q) {
+          const int k = key[q];
+          const int k0 = __builtin_amdgcn_readfirstlane(k);
+          uint64_t peers = ~0ull;
+          if (__ballot(k == k0) != ~0ull) {
+            for (int bit = 0; bit < nbits; ++bit) {
+              const bool on = (k >> bit) & 1;
+              const uint64_t m = __ballot(on);
+              peers &= on ? m : ~m;
+            }
+          }
+          const uint32_t rank = (uint32_t)__popcll(peers & lt);
+          const uint32_t cntk = (uint32_t)__popcll(peers);
+          dest[q] = 0;
+          here[q] = k >= wlo && k <= whi;  // holes (nc) are never in a window
+          if (here[q]) {
+            const uint32_t base = myrun[k - wlo];
+            if (rank == 0) myrun[k - wlo] = base + cntk;
+            dest[q] = base + rank;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          if (here[q]) {
+            const uint32_t o = dest[q];
+            d_cell[o] = key[q];
+            d_off[o] = o_[q];
+            d_vx[o] = x_[q];
+            d_vy[o] = y_[q];
+            d_vz[o] = z_[q];
+            d_id[o] = id_[q];
+          }
         }
       }
+      __syncthreads();  // the window's cursors are rewritten by the next one
     }
     __syncthreads();  // cursors are rewritten for the next tile
   }
@@ -581,11 +596,12 @@ __global__ __launch_bounds__(kThreads) void k_checkpoint(const Disch<P>* __restr
 template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
   const size_t pre = (size_t)(D + 1) * 4u;
-  const size_t lds = (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u + pre;
   const size_t lds_count = (size_t)(nc_max + 1) * 4u + pre;
   hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds_count, s, d_dev, D, nc_max + 1);
   hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), pre, s, d_dev, D);
-  hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds, s, d_dev, D, nc_max + 1);
+  const int sw = scatter_stride(nc_max);
+  const size_t lds_scatter = (size_t)kWavesPerBlock * (size_t)sw * 4u + pre;
+  hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds_scatter, s, d_dev, D, sw);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
   return hipGetLastError();
 }
@@ -599,7 +615,7 @@ hipError_t launch_checkpoint(const Disch<P>* d_dev, int D, int restore, int grid
 template <class P>
 hipError_t sort_set_lds(int nc_max, int D) {
   const int pre = (D + 1) * 4;
-  const int lds = kWavesPerBlock * (nc_max + 1) * 4 + pre;
+  const int lds = kWavesPerBlock * scatter_stride(nc_max) * 4 + pre;
   hipError_t e = hipFuncSetAttribute((const void*)k_sort_count<P>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (nc_max + 1) * 4 + pre);
@@ -613,7 +629,10 @@ hipError_t sort_set_lds(int nc_max, int D) {
 
 // LDS of the sort's count and scatter launches.
 size_t sort_lds_bytes(int nc_max, int D) {
-  return (size_t)kWavesPerBlock * (size_t)(nc_max + 1) * 4u + (size_t)(D + 1) * 4u;
+  const size_t pre = (size_t)(D + 1) * 4u;
+  const size_t count = (size_t)(nc_max + 1) * 4u + pre;
+  const size_t scatter = (size_t)kWavesPerBlock * (size_t)scatter_stride(nc_max) * 4u + pre;
+  return count > scatter ? count : scatter;
 }
 
 // Scan-partials entries needed per discharge.
