@@ -215,9 +215,10 @@ def cpu_table(a):
 
 
 def launch_cfg(text: str) -> dict:
-    """--launch "variant,electron_groups,sort_groups,append_groups" (0: default)."""
+    """--launch "variant,electron_groups,sort_groups,append_groups[,sort_tile]" (0: default)."""
     v = [int(x) for x in text.split(",")]
-    return dict(zip(["electron_variant", "electron_groups", "sort_groups", "append_groups"], v))
+    return dict(zip(["electron_variant", "electron_groups", "sort_groups", "append_groups",
+                     "sort_tile"], v))
 
 
 def batched(a):

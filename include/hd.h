@@ -324,8 +324,8 @@ int hd_batch_free(hd_batch* b);
 /* How the kernels of one handle are launched.  No field changes any result:
  * particles are processed in fixed sub-chunks of 256 (one wave's four
  * particles per lane), and every order that reaches a result (deposit sums
- * in 64-bit integers, children in parent order, stable sort tiles of 4,096)
- * is independent of the launch shape, so results are bitwise identical
+ * in 64-bit integers, children in parent order, a stable sort) is
+ * independent of the launch shape, so results are bitwise identical
  * under every valid configuration.  A value of 0 selects the default; a new
  * handle starts from the autotuner's cached choice for its shape if there
  * is one, else from the defaults with electron variant 5 when its initial
@@ -365,6 +365,9 @@ typedef struct hd_launch_config {
   int32_t append_groups;    /* workgroups that append new particles in the
                                end-of-step launch, 1 .. compute units
                                (0: a quarter of the compute units)         */
+  int32_t sort_tile;        /* particle slots per tile of the sort (one
+                               workgroup's share): 2048, 4096 or 8192
+                               (0: 4096)                                   */
 } hd_launch_config;
 
 /* Current configuration with defaults resolved to actual counts. */
@@ -376,9 +379,9 @@ int hd_batch_set_launch(hd_batch* b, const hd_launch_config* cfg);
  * intervals, at least two), launched one kernel at a time and timed with
  * HIP events on the handle's stream: each electron candidate (variant and
  * workgroup count) runs a block of consecutive steps whose first step is
- * not timed (a variant leaves the caches in its own state), the sort's and
- * the append's workgroup counts are taken in turn, and each is given the
- * fastest mean.  The
+ * not timed (a variant leaves the caches in its own state), the sort's
+ * shapes (workgroup count and tile: 4096 or 2048) and the append's
+ * workgroup counts are taken in turn, and each is given the fastest mean.  The
  * steps are ordinary steps of the run (the shapes do not change results).
  * The choice is applied, written to *out (may be NULL) and kept in a
  * process-wide cache keyed by the device and the batch's shape (precision,

@@ -57,7 +57,8 @@ int widen_variant(int v, int tab_max, int nn_max, int nb1_max, int fluid_nn, int
 template <class P>
 hipError_t finalize_set_lds(int nn_max);
 template <class P>
-hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s);
+hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int tile, int nc_max,
+                            hipStream_t s);
 template <class P>
 hipError_t sort_set_lds(int nc_max, int D);
 size_t sort_lds_bytes(int nc_max, int D);
@@ -281,9 +282,9 @@ Offsets<P> layout(const hd_params& p, int64_t volt_len) {
   o.eedf = L.take(((size_t)p.n_eedf_bins + 1) * 8);
   o.ip = L.take(nn * 8);
   o.tab = L.take((size_t)p.n_energy * (size_t)std::max(p.n_channels, 1) * sizeof(P));
-  o.hist = L.take((size_t)p.n_cells * (C / kSortTile) * 4);
-  o.parts = L.take(sort_parts((size_t)p.n_cells, C / kSortTile) * 4);
-  o.tile_rng = L.take(2 * (C / kSortTile) * 4);
+  o.hist = L.take((size_t)p.n_cells * (C / kSortTileMin) * 4);
+  o.parts = L.take(sort_parts((size_t)p.n_cells, C / kSortTileMin) * 4);
+  o.tile_rng = L.take(2 * (C / kSortTileMin) * 4);
   o.st = L.take(sizeof(State));
   o.ckpt = L.take((o.ip - o.cnt[0]) + sizeof(State));
   o.volt = L.take((size_t)volt_len * 8);
@@ -538,8 +539,9 @@ double volt_at(const hd_params& p, int64_t n) {
 
 // Launch shapes chosen by the autotuner, per device and batch shape, for the
 // life of the process (and, when HD_TUNE_CACHE names a file, across
-// processes: one line "key variant electron_groups sort_groups append_groups"
-// per choice, the last line of a key winning).
+// processes: one line "key variant electron_groups sort_groups append_groups
+// sort_tile" per choice, the last line of a key winning; a line without the
+// tile keeps the default tile).
 std::mutex g_tune_mu;
 std::map<std::string, hd_launch_config> g_tune;
 bool g_tune_loaded = false;
@@ -555,8 +557,10 @@ void tune_load_locked() {
     std::istringstream ss(line);
     std::string key;
     hd_launch_config c{};
-    if (ss >> key >> c.electron_variant >> c.electron_groups >> c.sort_groups >> c.append_groups)
+    if (ss >> key >> c.electron_variant >> c.electron_groups >> c.sort_groups >> c.append_groups) {
+      if (!(ss >> c.sort_tile)) c.sort_tile = 0;
       g_tune[key] = c;
+    }
   }
 }
 
@@ -577,7 +581,7 @@ void tune_store(const std::string& key, const hd_launch_config& c) {
   if (!path || !*path) return;
   std::ofstream f(path, std::ios::app);
   f << key << ' ' << c.electron_variant << ' ' << c.electron_groups << ' ' << c.sort_groups << ' '
-    << c.append_groups << '\n';
+    << c.append_groups << ' ' << c.sort_tile << '\n';
 }
 
 }  // namespace
@@ -631,6 +635,7 @@ struct BatchBase {
   int device = 0;
   int sort_every = 16;
   int grid_e = 0, grid_a = 0, grid_s = 0;
+  int tile_s = kSortTile;   // items per sort tile (hd_launch_config)
   int tab_max = 0, nn_max = 0, nb1_max = 0, nc_max = 0, fluid_nn = 0, K_max = 1;
   int cus = 0;              // compute units of the device
   int elec_variant = 0;     // electron kernel variant (hd_launch_config)
@@ -749,7 +754,7 @@ struct Batch : BatchBase {
     const size_t C = round_capacity(h.p.capacity);
     d.capacity = (uint32_t)h.p.capacity;  // limit; buffers are rounded up to C
     d.cap_sub = (uint32_t)(C / kSub);
-    d.sort_tiles_max = (uint32_t)(C / kSortTile);
+    d.sort_tiles_max = (uint32_t)(C / kSortTileMin);
     for (int i = 0; i < 2; ++i) {
       d.cell[i] = (int32_t*)(b + o.cell[i]);
       d.off[i] = (P*)(b + o.off[i]);
@@ -949,6 +954,9 @@ struct Batch : BatchBase {
     if (c.electron_groups == 0) c.electron_groups = std::min(cus * occ, (int)kMaxSegs);
     if (c.sort_groups == 0) c.sort_groups = cus * 4;
     if (c.append_groups == 0) c.append_groups = std::max(1, cus / 4);
+    if (c.sort_tile == 0) c.sort_tile = kSortTile;
+    if (c.sort_tile != kSortTileMin && c.sort_tile != kSortTile && c.sort_tile != 2 * kSortTile)
+      return fail(HD_EINVAL, "sort_tile must be 2048, 4096 or 8192");
     if (c.electron_groups < 1 || c.electron_groups > kMaxSegs)
       return fail(HD_EINVAL, "electron_groups out of range");
     if (c.sort_groups < 1 || c.sort_groups > 65536)
@@ -958,6 +966,7 @@ struct Batch : BatchBase {
     elec_variant = c.electron_variant;
     grid_e = D + c.electron_groups;
     grid_s = c.sort_groups;
+    tile_s = c.sort_tile;
     grid_a = c.append_groups;
     launch = c;
     drop_graphs();  // captured with the old shapes
@@ -974,7 +983,7 @@ struct Batch : BatchBase {
     if (e != hipSuccess) return e;
     e = launch_finalize<P>(d_desc, D, 0, nn_max, grid_a, stream);
     if (e != hipSuccess) return e;
-    if (with_sort) e = launch_sort_impl<P>(d_desc, D, grid_s, nc_max, stream);
+    if (with_sort) e = launch_sort_impl<P>(d_desc, D, grid_s, tile_s, nc_max, stream);
     return e;
   }
 
@@ -1429,7 +1438,8 @@ struct Batch : BatchBase {
       if (err == hipSuccess) err = hipEventRecord(e[4], stream);
       if (err == hipSuccess) err = hipEventRecord(e[5], stream);
       if (err == hipSuccess) err = hipEventRecord(e[6], stream);
-      if (err == hipSuccess && srt) err = launch_sort_impl<P>(d_desc, D, grid_s, nc_max, stream);
+      if (err == hipSuccess && srt)
+        err = launch_sort_impl<P>(d_desc, D, grid_s, tile_s, nc_max, stream);
       if (err == hipSuccess) err = hipEventRecord(e[7], stream);
       host_step += 1;
     }
@@ -1490,9 +1500,20 @@ struct Batch : BatchBase {
         ce.push_back({c});
       }
     }
+    // sort: workgroups at the default tile and at the smallest (twice as
+    // many tiles, each a shorter chain of work: faster on many-cell batches,
+    // slower on one large discharge); the largest tile was slower on every
+    // workload measured and is left to hd_set_launch
     for (int f : {2, 4, 8}) {
       hd_launch_config c = launch;
       c.sort_groups = cus * f;
+      c.sort_tile = kSortTile;
+      cs.push_back({c});
+    }
+    for (int f : {4, 8}) {
+      hd_launch_config c = launch;
+      c.sort_groups = cus * f;
+      c.sort_tile = kSortTileMin;
       cs.push_back({c});
     }
     for (int f : {8, 4, 2}) {
@@ -1536,7 +1557,8 @@ struct Batch : BatchBase {
       if (err == hipSuccess) err = hipEventRecord(e[3], stream);
       if (err == hipSuccess) err = hipEventRecord(e[4], stream);
       if (err == hipSuccess && srt)
-        err = launch_sort_impl<P>(d_desc, D, cs[is].c.sort_groups, nc_max, stream);
+        err = launch_sort_impl<P>(d_desc, D, cs[is].c.sort_groups, cs[is].c.sort_tile, nc_max,
+                                  stream);
       if (err == hipSuccess) err = hipEventRecord(e[5], stream);
       host_step += 1;
     }
@@ -1579,6 +1601,7 @@ struct Batch : BatchBase {
     c.electron_variant = be.electron_variant;
     c.electron_groups = be.electron_groups;
     c.sort_groups = bs.sort_groups;
+    c.sort_tile = bs.sort_tile;
     c.append_groups = ba.append_groups;
     rc = apply_launch(c);
     if (rc) return rc;
@@ -1768,7 +1791,7 @@ struct Server : ServerBase {
                                     nt ? v_stream : v_plain, stream);
         if (e == hipSuccess) e = launch_finalize<P>(d_desc, S, 0, nn_max, grid_a, stream);
         if (e == hipSuccess && s == cfg.sort_every - 1)
-          e = launch_sort_impl<P>(d_desc, S, grid_s, nc_max, stream);
+          e = launch_sort_impl<P>(d_desc, S, grid_s, kSortTile, nc_max, stream);
       }
       const hipError_t e2 = hipStreamEndCapture(stream, &g);
       if (e != hipSuccess || e2 != hipSuccess)

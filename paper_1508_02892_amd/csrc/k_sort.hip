@@ -1,7 +1,7 @@
 // Compaction and stable counting sort of the particle slots by cell, run every
 // sort_every steps so that deposits of a workgroup fall on few nodes.
 //
-// Tiles of kSortTile consecutive slots.  A tile's per-cell counts go to a
+// Tiles of T consecutive slots (T = 2,048, 4,096 or 8,192).  A tile's per-cell counts go to a
 // bin-major matrix hist[c * nt + t]; an exclusive scan of that matrix in its
 // flat order gives, for every (cell, tile), the first destination slot, so
 // holes are dropped and equal cells keep their order.  The matrix and the
@@ -27,9 +27,13 @@ constexpr int kScatterWindow = 1024;  // cells per window of the scatter's curso
 // Cursor words per wave of the scatter.
 inline int scatter_stride(int nc_max) { return nc_max + 1 < kScatterWindow ? nc_max + 1 : kScatterWindow; }
 
-template <class P>
+// Sort tiles of T items (at least kSortTileMin, the tile the count matrix
+// and the tile ranges are allocated for): larger tiles mean fewer (cell,
+// tile) entries, smaller ones more tiles to spread over the workgroups and
+// shorter chains of work per tile.  The sort's result does not depend on T.
+template <int T, class P>
 __device__ __forceinline__ uint32_t n_tiles(const Disch<P>& d) {
-  return (d.st->n_main + (uint32_t)kSortTile - 1u) / (uint32_t)kSortTile;
+  return (d.st->n_main + (uint32_t)T - 1u) / (uint32_t)T;
 }
 
 // kScanItems consecutive matrix entries from base (a multiple of 16), as
@@ -117,18 +121,18 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t (&v)[kScanItems], u
 // discharges in turn left most workgroups idle on the small ones): the
 // first unit of discharge i is pre[i] and the total pre[D], in LDS
 // (D + 1 words), computed by every workgroup from the discharges' states.
-template <class P>
+template <int T, class P>
 __device__ __forceinline__ uint32_t tiles_due(const Disch<P>& d) {
-  return d.st->sort_due ? n_tiles(d) : 0u;
+  return d.st->sort_due ? n_tiles<T>(d) : 0u;
 }
-template <class P>
+template <int T, class P>
 __device__ __forceinline__ uint32_t scan_blocks(const Disch<P>& d) {
-  const uint64_t n = (uint64_t)d.nc * n_tiles(d);
+  const uint64_t n = (uint64_t)d.nc * n_tiles<T>(d);
   return (uint32_t)((n + kScanBlock - 1) / kScanBlock);
 }
-template <class P>
+template <int T, class P>
 __device__ __forceinline__ uint32_t scan_blocks_due(const Disch<P>& d) {
-  return d.st->sort_due ? scan_blocks(d) : 0u;
+  return d.st->sort_due ? scan_blocks<T>(d) : 0u;
 }
 template <class P, class U>
 __device__ void unit_prefix(const Disch<P>* __restrict__ ds, int D, uint32_t* pre, U units) {
@@ -147,12 +151,12 @@ __device__ void unit_prefix(const Disch<P>* __restrict__ ds, int D, uint32_t* pr
   __syncthreads();
 }
 
-template <class P>
+template <class P, int T>
 __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restrict__ ds, int D,
                                                          int stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int sh_lo[kWavesPerBlock], sh_hi[kWavesPerBlock];
-  constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
+  constexpr uint32_t kQuarter = (uint32_t)T / kWavesPerBlock;  // slots per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // one histogram of stride (>= the largest nc + 1) words for the whole
   // launch, shared by the four waves (LDS atomics) and zero between tiles,
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
   uint32_t* h = reinterpret_cast<uint32_t*>(smem);
   uint32_t* pre = h + (size_t)stride;
   for (int c = (int)threadIdx.x; c < stride; c += kThreads) h[c] = 0u;
-  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due(d); });
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due<T>(d); });
   const uint32_t total = pre[D];
   int di = 0;
   // The four waves of a workgroup share a tile, a quarter each, so that a
@@ -172,11 +176,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
     const Disch<P>& d = ds[di];
     const State* st = d.st;
     const uint32_t t = g - pre[di];
-    const uint32_t n = st->n_main, nt = n_tiles(d);
+    const uint32_t n = st->n_main, nt = n_tiles<T>(d);
     const int nc = d.nc;
     const Gp<int32_t>* cell = gptr(d.cell[st->buf]);
     Gp<uint32_t>* hist = gptr(d.hist);
-    const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
+    const uint32_t b = t * (uint32_t)T + (uint32_t)wv * kQuarter;
     const uint32_t e = min(n, b + kQuarter);
     // 4 consecutive slots per lane per 256-slot round, all rounds loaded
     // before they are counted (the capacity is a multiple of the tile, so
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_count(const Disch<P>* __restr
   }
 }
 
-template <class P>
+template <class P, int T>
 __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restrict__ ds, int D) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t sh[kWavesPerBlock];
@@ -273,16 +277,16 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restri
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < D; i += kThreads) {
       State* st = ds[i].st;
-      if (st->sort_due && scan_blocks(ds[i]) == 0) st->n_live_sorted = 0;
+      if (st->sort_due && scan_blocks<T>(ds[i]) == 0) st->n_live_sorted = 0;
     }
-  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return scan_blocks_due(d); });
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return scan_blocks_due<T>(d); });
   const uint32_t total = pre[D];
   int di = 0;
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
     while (pre[di + 1] <= g) ++di;
     const Disch<P>& d = ds[di];
     State* st = d.st;
-    const uint64_t n = (uint64_t)d.nc * n_tiles(d);
+    const uint64_t n = (uint64_t)d.nc * n_tiles<T>(d);
     const uint32_t nb = pre[di + 1] - pre[di], blk = g - pre[di];
     uint32_t v[kScanItems];
     const uint64_t base = (uint64_t)blk * kScanBlock + (uint64_t)threadIdx.x * kScanItems;
@@ -310,11 +314,11 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const Disch<P>* __restri
   }
 }
 
-template <class P>
+template <class P, int T>
 __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __restrict__ ds, int D,
                                                            int stride) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr uint32_t kQuarter = (uint32_t)kSortTile / kWavesPerBlock;  // slots per wave
+  constexpr uint32_t kQuarter = (uint32_t)T / kWavesPerBlock;  // slots per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint64_t lt = lanemask_lt();
   // run[w][c - lo]: cursor of wave w for cell c; the unit prefix follows
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
   // the scan blocks' totals are zero again for the next sort's counts: one
   // flat index over the due discharges' blocks (their counts read in
   // parallel, not one discharge's state after another)
-  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return scan_blocks_due(d); });
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return scan_blocks_due<T>(d); });
   {
     const uint32_t nz = pre[D];
     int dz = 0;
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     }
   }
   __syncthreads();  // pre[] is reused for the tiles
-  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due(d); });
+  unit_prefix(ds, D, pre, [](const Disch<P>& d) { return tiles_due<T>(d); });
   const uint32_t total = pre[D];
   int di = 0;
   for (uint32_t g = blockIdx.x; g < total; g += gridDim.x) {
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     const Disch<P>& d = ds[di];
     const State* st = d.st;
     const uint32_t t = g - pre[di];
-    const uint32_t n = st->n_main, nt = n_tiles(d);
+    const uint32_t n = st->n_main, nt = n_tiles<T>(d);
     const int nc = d.nc;
     const int nbits = 32 - __clz((uint32_t)nc);  // keys 0 .. nc (nc marks a hole)
     const int src = st->buf, dst = src ^ 1;
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(const Disch<P>* __res
     Gp<P>* d_vz = gptr(d.vz[dst]);
     Gp<uint32_t>* d_id = gptr(d.id[dst]);
     const int lo = gptr(d.tile_rng)[2 * t], hi = gptr(d.tile_rng)[2 * t + 1];
-    const uint32_t b = t * (uint32_t)kSortTile + (uint32_t)wv * kQuarter;
+    const uint32_t b = t * (uint32_t)T + (uint32_t)wv * kQuarter;
     const uint32_t e = min(n, b + kQuarter);
     uint32_t* myrun = run + wv * stride;
     // The tile's cells in windows of at most stride cells (one window for
@@ -593,15 +597,30 @@ __global__ __launch_bounds__(kThreads) void k_checkpoint(const Disch<P>* __restr
 
 }  // namespace
 
-template <class P>
-hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
+template <class P, int T>
+void launch_sort_tiles(const Disch<P>* d_dev, int D, int grid, int nc_max, hipStream_t s) {
   const size_t pre = (size_t)(D + 1) * 4u;
   const size_t lds_count = (size_t)(nc_max + 1) * 4u + pre;
-  hipLaunchKernelGGL(k_sort_count<P>, dim3(grid), dim3(kThreads), lds_count, s, d_dev, D, nc_max + 1);
-  hipLaunchKernelGGL(k_scan_down<P>, dim3(grid), dim3(kThreads), pre, s, d_dev, D);
+  hipLaunchKernelGGL((k_sort_count<P, T>), dim3(grid), dim3(kThreads), lds_count, s, d_dev, D,
+                     nc_max + 1);
+  hipLaunchKernelGGL((k_scan_down<P, T>), dim3(grid), dim3(kThreads), pre, s, d_dev, D);
   const int sw = scatter_stride(nc_max);
   const size_t lds_scatter = (size_t)kWavesPerBlock * (size_t)sw * 4u + pre;
-  hipLaunchKernelGGL(k_sort_scatter<P>, dim3(grid), dim3(kThreads), lds_scatter, s, d_dev, D, sw);
+  hipLaunchKernelGGL((k_sort_scatter<P, T>), dim3(grid), dim3(kThreads), lds_scatter, s, d_dev, D,
+                     sw);
+}
+
+// tile: items per sort tile, kSortTileMin, kSortTile or twice that (checked
+// by the caller).
+template <class P>
+hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int tile, int nc_max,
+                            hipStream_t s) {
+  if (tile == kSortTileMin)
+    launch_sort_tiles<P, kSortTileMin>(d_dev, D, grid, nc_max, s);
+  else if (tile == 2 * kSortTile)
+    launch_sort_tiles<P, 2 * kSortTile>(d_dev, D, grid, nc_max, s);
+  else
+    launch_sort_tiles<P, kSortTile>(d_dev, D, grid, nc_max, s);
   hipLaunchKernelGGL(k_sort_finish<P>, dim3((D + 63) / 64), dim3(64), 0, s, d_dev, D);
   return hipGetLastError();
 }
@@ -612,19 +631,27 @@ hipError_t launch_checkpoint(const Disch<P>* d_dev, int D, int restore, int grid
   return hipGetLastError();
 }
 
-template <class P>
-hipError_t sort_set_lds(int nc_max, int D) {
+template <class P, int T>
+hipError_t sort_set_lds_tiles(int nc_max, int D) {
   const int pre = (D + 1) * 4;
   const int lds = kWavesPerBlock * scatter_stride(nc_max) * 4 + pre;
-  hipError_t e = hipFuncSetAttribute((const void*)k_sort_count<P>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_sort_count<P, T>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (nc_max + 1) * 4 + pre);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_scan_down<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          pre);
+  e = hipFuncSetAttribute((const void*)k_scan_down<P, T>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, pre);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_sort_scatter<P>,
+  return hipFuncSetAttribute((const void*)k_sort_scatter<P, T>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+template <class P>
+hipError_t sort_set_lds(int nc_max, int D) {
+  hipError_t e = sort_set_lds_tiles<P, kSortTileMin>(nc_max, D);
+  if (e == hipSuccess) e = sort_set_lds_tiles<P, kSortTile>(nc_max, D);
+  if (e == hipSuccess) e = sort_set_lds_tiles<P, 2 * kSortTile>(nc_max, D);
+  return e;
 }
 
 // LDS of the sort's count and scatter launches.
@@ -638,10 +665,11 @@ size_t sort_lds_bytes(int nc_max, int D) {
 // Scan-partials entries needed per discharge.
 size_t sort_parts(size_t nc, size_t tiles) { return (nc * tiles + kScanBlock - 1) / kScanBlock + 1; }
 
-template hipError_t launch_sort_impl<float>(const Disch<float>*, int, int, int, hipStream_t);
+template hipError_t launch_sort_impl<float>(const Disch<float>*, int, int, int, int, hipStream_t);
 template hipError_t launch_checkpoint<float>(const Disch<float>*, int, int, int, hipStream_t);
 template hipError_t launch_checkpoint<double>(const Disch<double>*, int, int, int, hipStream_t);
-template hipError_t launch_sort_impl<double>(const Disch<double>*, int, int, int, hipStream_t);
+template hipError_t launch_sort_impl<double>(const Disch<double>*, int, int, int, int,
+                                            hipStream_t);
 template hipError_t sort_set_lds<float>(int, int);
 template hipError_t sort_set_lds<double>(int, int);
 

@@ -74,7 +74,8 @@ class Params(C.Structure):
 
 class LaunchConfig(C.Structure):
     _fields_ = [("electron_variant", C.c_int32), ("electron_groups", C.c_int32),
-                ("sort_groups", C.c_int32), ("append_groups", C.c_int32)]
+                ("sort_groups", C.c_int32), ("append_groups", C.c_int32),
+                ("sort_tile", C.c_int32)]
 
 
 def _launch_dict(c: LaunchConfig) -> dict:

@@ -1,14 +1,15 @@
 """Launch shapes do not change results.
 
 Every shape the autotuner may pick (the electron kernel variant -- how the
-particle data are loaded, with or without the nontemporal hint -- and its
-workgroup count, the sort's and the append's workgroup counts) must give
-bitwise the same run: particles are processed in fixed chunks, deposits are
-integer sums, children are appended in parent order and the sort's tiles
-are fixed, so no launch shape can reach a result.  The batch is shaped like
-the batched sweep (uneven gaps, grids, voltages and particle counts); two
-members are also checked against the oracle, and a run whose first steps
-were taken by the autotuner equals a run with a fixed shape.
+particle data are loaded, with or without the nontemporal hint, in 512- or
+1,024-thread workgroups -- and its workgroup count, the sort's workgroup
+count and tile, the append's workgroup count) must give bitwise the same
+run: particles are processed in fixed sub-chunks, deposits are integer
+sums, children are appended in parent order and the sort is stable, so no
+launch shape can reach a result.  The batch is shaped like the batched
+sweep (uneven gaps, grids, voltages and particle counts); two members are
+also checked against the oracle, and a run whose first steps were taken by
+the autotuner equals a run with a fixed shape.
 """
 import json
 import os
@@ -81,6 +82,8 @@ CONFIGS = [
     {"electron_variant": 14},
     {"electron_variant": 15, "electron_groups": 2},
     {"sort_groups": 3},
+    {"sort_tile": 2048},
+    {"sort_tile": 8192, "sort_groups": 7},
     {"append_groups": 1},
     {"electron_variant": 1, "electron_groups": 1, "sort_groups": 1000, "append_groups": 64},
 ]
@@ -120,7 +123,8 @@ def test_autotuned_run_equals_fixed_shape_run():
 def test_invalid_shapes_are_rejected():
     b = hd.Batch(_params()[:2])
     for cfg in ({"electron_variant": 99}, {"electron_variant": -1}, {"electron_groups": 5000},
-                {"sort_groups": -1}, {"append_groups": 100000}):
+                {"sort_groups": -1}, {"append_groups": 100000}, {"sort_tile": 16384},
+                {"sort_tile": 6000}):
         with pytest.raises(hd.HdError) as e:
             b.set_launch(cfg)
         assert e.value.code == -1
@@ -201,12 +205,17 @@ def test_tune_cache_file_carries_the_choice_across_processes(tmp_path):
     lines = cache.read_text().split("\n")
     key, *vals = lines[0].split()
     assert [int(v) for v in vals] == [tuned[k] for k in ("electron_variant", "electron_groups",
-                                                        "sort_groups", "append_groups")]
+                                                        "sort_groups", "append_groups",
+                                                        "sort_tile")]
     assert child("fresh") == tuned
     with open(cache, "a") as f:
-        f.write("%s 1 77 333 5\n" % key)
+        f.write("%s 1 77 333 5 8192\n" % key)
     assert child("fresh") == {"electron_variant": 1, "electron_groups": 77, "sort_groups": 333,
-                              "append_groups": 5}
+                              "append_groups": 5, "sort_tile": 8192}
+    with open(cache, "a") as f:  # a line without the tile keeps the default one
+        f.write("%s 2 50 100 4\n" % key)
+    assert child("fresh") == {"electron_variant": 2, "electron_groups": 50, "sort_groups": 100,
+                              "append_groups": 4, "sort_tile": 4096}
 
 
 def test_untuned_default_follows_the_mall():
