@@ -452,8 +452,9 @@ def main():
                     help="steps the autotuner may take (within the warmup); 0: no tuning")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
-              "design is described in DESIGN.md and not measured" % a.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only (got --gpus %d): independent discharges would "
+              "be spread over GPUs one process each, which is not implemented" % a.gpus,
+              file=sys.stderr)
         sys.exit(2)
     if a.workload == "served":
         return served(a)
