@@ -366,7 +366,7 @@ typedef struct hd_launch_config {
                                end-of-step launch, 1 .. compute units
                                (0: a quarter of the compute units)         */
   int32_t sort_tile;        /* particle slots per tile of the sort (one
-                               workgroup's share): 2048, 4096 or 8192
+                               workgroup's share): 4096 or 8192
                                (0: 4096)                                   */
 } hd_launch_config;
 
@@ -380,7 +380,7 @@ int hd_batch_set_launch(hd_batch* b, const hd_launch_config* cfg);
  * HIP events on the handle's stream: each electron candidate (variant and
  * workgroup count) runs a block of consecutive steps whose first step is
  * not timed (a variant leaves the caches in its own state), the sort's
- * shapes (workgroup count and tile: 4096 or 2048) and the append's
+ * shapes (workgroup count and tile: 4096 or 8192) and the append's
  * workgroup counts are taken in turn, and each is given the fastest mean.  The
  * steps are ordinary steps of the run (the shapes do not change results).
  * The choice is applied, written to *out (may be NULL) and kept in a

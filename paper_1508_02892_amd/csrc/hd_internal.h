@@ -19,9 +19,7 @@ constexpr int kMaxCells = 4096;    // cells per discharge
 constexpr int kMaxNodes = kMaxCells + 1;
 constexpr int kMaxSegs = 4096;    // particle workgroups of one electron launch
 constexpr int kSphereTries = 64;   // bound of the rejection loops
-constexpr int kSortTile = 4096;    // items per sort tile by default (one workgroup's share)
-constexpr int kSortTileMin = kSortTile / 2;  // smallest sort tile: the count matrix and
-                                             // tile ranges are sized for it
+constexpr int kSortTile = 4096;    // items per sort tile (one workgroup of the sort)
 constexpr int kFinThreads = 1024;  // field/finalize workgroup
 constexpr int kMaxSpecies = 4;     // ion species of the multi-species model
 constexpr int kMaxMu = 256;        // mobility-table points per species
@@ -82,7 +80,7 @@ struct Disch {
   int32_t nbins, sort_every, eedf_every, ion_model;
   uint32_t capacity;        // slots per particle buffer (multiple of kTile)
   uint32_t cap_sub;         // capacity / kSub
-  uint32_t sort_tiles_max;  // capacity / kSortTileMin
+  uint32_t sort_tiles_max;  // capacity / kSortTile (rounded up)
   uint32_t pad0;
   uint64_t seed;
   // electron constants rounded to P

@@ -282,9 +282,9 @@ Offsets<P> layout(const hd_params& p, int64_t volt_len) {
   o.eedf = L.take(((size_t)p.n_eedf_bins + 1) * 8);
   o.ip = L.take(nn * 8);
   o.tab = L.take((size_t)p.n_energy * (size_t)std::max(p.n_channels, 1) * sizeof(P));
-  o.hist = L.take((size_t)p.n_cells * (C / kSortTileMin) * 4);
-  o.parts = L.take(sort_parts((size_t)p.n_cells, C / kSortTileMin) * 4);
-  o.tile_rng = L.take(2 * (C / kSortTileMin) * 4);
+  o.hist = L.take((size_t)p.n_cells * (C / kSortTile) * 4);
+  o.parts = L.take(sort_parts((size_t)p.n_cells, C / kSortTile) * 4);
+  o.tile_rng = L.take(2 * (C / kSortTile) * 4);
   o.st = L.take(sizeof(State));
   o.ckpt = L.take((o.ip - o.cnt[0]) + sizeof(State));
   o.volt = L.take((size_t)volt_len * 8);
@@ -754,7 +754,7 @@ struct Batch : BatchBase {
     const size_t C = round_capacity(h.p.capacity);
     d.capacity = (uint32_t)h.p.capacity;  // limit; buffers are rounded up to C
     d.cap_sub = (uint32_t)(C / kSub);
-    d.sort_tiles_max = (uint32_t)(C / kSortTileMin);
+    d.sort_tiles_max = (uint32_t)(C / kSortTile);
     for (int i = 0; i < 2; ++i) {
       d.cell[i] = (int32_t*)(b + o.cell[i]);
       d.off[i] = (P*)(b + o.off[i]);
@@ -955,8 +955,8 @@ struct Batch : BatchBase {
     if (c.sort_groups == 0) c.sort_groups = cus * 4;
     if (c.append_groups == 0) c.append_groups = std::max(1, cus / 4);
     if (c.sort_tile == 0) c.sort_tile = kSortTile;
-    if (c.sort_tile != kSortTileMin && c.sort_tile != kSortTile && c.sort_tile != 2 * kSortTile)
-      return fail(HD_EINVAL, "sort_tile must be 2048, 4096 or 8192");
+    if (c.sort_tile != kSortTile && c.sort_tile != 2 * kSortTile)
+      return fail(HD_EINVAL, "sort_tile must be 4096 or 8192");
     if (c.electron_groups < 1 || c.electron_groups > kMaxSegs)
       return fail(HD_EINVAL, "electron_groups out of range");
     if (c.sort_groups < 1 || c.sort_groups > 65536)
@@ -1500,20 +1500,18 @@ struct Batch : BatchBase {
         ce.push_back({c});
       }
     }
-    // sort: workgroups at the default tile and at the smallest (twice as
-    // many tiles, each a shorter chain of work: faster on many-cell batches,
-    // slower on one large discharge); the largest tile was slower on every
-    // workload measured and is left to hd_set_launch
+    // sort: workgroups at the default tile, then the larger tile (half as
+    // many (cell, tile) entries to scan)
     for (int f : {2, 4, 8}) {
       hd_launch_config c = launch;
       c.sort_groups = cus * f;
       c.sort_tile = kSortTile;
       cs.push_back({c});
     }
-    for (int f : {4, 8}) {
+    {
       hd_launch_config c = launch;
-      c.sort_groups = cus * f;
-      c.sort_tile = kSortTileMin;
+      c.sort_groups = cus * 4;
+      c.sort_tile = 2 * kSortTile;
       cs.push_back({c});
     }
     for (int f : {8, 4, 2}) {

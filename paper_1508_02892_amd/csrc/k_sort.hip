@@ -1,7 +1,7 @@
 // Compaction and stable counting sort of the particle slots by cell, run every
 // sort_every steps so that deposits of a workgroup fall on few nodes.
 //
-// Tiles of T consecutive slots (T = 2,048, 4,096 or 8,192).  A tile's per-cell counts go to a
+// Tiles of T consecutive slots (T = 4,096 or 8,192).  A tile's per-cell counts go to a
 // bin-major matrix hist[c * nt + t]; an exclusive scan of that matrix in its
 // flat order gives, for every (cell, tile), the first destination slot, so
 // holes are dropped and equal cells keep their order.  The matrix and the
@@ -27,10 +27,10 @@ constexpr int kScatterWindow = 1024;  // cells per window of the scatter's curso
 // Cursor words per wave of the scatter.
 inline int scatter_stride(int nc_max) { return nc_max + 1 < kScatterWindow ? nc_max + 1 : kScatterWindow; }
 
-// Sort tiles of T items (at least kSortTileMin, the tile the count matrix
-// and the tile ranges are allocated for): larger tiles mean fewer (cell,
-// tile) entries, smaller ones more tiles to spread over the workgroups and
-// shorter chains of work per tile.  The sort's result does not depend on T.
+// Sort tiles of T items (at least kSortTile, the tile the count matrix and
+// the tile ranges are allocated for): larger tiles mean fewer (cell, tile)
+// entries, smaller ones more tiles to spread over the workgroups.  The
+// sort's result does not depend on T.
 template <int T, class P>
 __device__ __forceinline__ uint32_t n_tiles(const Disch<P>& d) {
   return (d.st->n_main + (uint32_t)T - 1u) / (uint32_t)T;
@@ -610,14 +610,12 @@ void launch_sort_tiles(const Disch<P>* d_dev, int D, int grid, int nc_max, hipSt
                      sw);
 }
 
-// tile: items per sort tile, kSortTileMin, kSortTile or twice that (checked
-// by the caller).
+// tile: items per sort tile, kSortTile or twice that (checked by the
+// caller).
 template <class P>
 hipError_t launch_sort_impl(const Disch<P>* d_dev, int D, int grid, int tile, int nc_max,
                             hipStream_t s) {
-  if (tile == kSortTileMin)
-    launch_sort_tiles<P, kSortTileMin>(d_dev, D, grid, nc_max, s);
-  else if (tile == 2 * kSortTile)
+  if (tile == 2 * kSortTile)
     launch_sort_tiles<P, 2 * kSortTile>(d_dev, D, grid, nc_max, s);
   else
     launch_sort_tiles<P, kSortTile>(d_dev, D, grid, nc_max, s);
@@ -648,8 +646,7 @@ hipError_t sort_set_lds_tiles(int nc_max, int D) {
 
 template <class P>
 hipError_t sort_set_lds(int nc_max, int D) {
-  hipError_t e = sort_set_lds_tiles<P, kSortTileMin>(nc_max, D);
-  if (e == hipSuccess) e = sort_set_lds_tiles<P, kSortTile>(nc_max, D);
+  hipError_t e = sort_set_lds_tiles<P, kSortTile>(nc_max, D);
   if (e == hipSuccess) e = sort_set_lds_tiles<P, 2 * kSortTile>(nc_max, D);
   return e;
 }

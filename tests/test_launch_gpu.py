@@ -82,7 +82,7 @@ CONFIGS = [
     {"electron_variant": 14},
     {"electron_variant": 15, "electron_groups": 2},
     {"sort_groups": 3},
-    {"sort_tile": 2048},
+    {"sort_tile": 8192},
     {"sort_tile": 8192, "sort_groups": 7},
     {"append_groups": 1},
     {"electron_variant": 1, "electron_groups": 1, "sort_groups": 1000, "append_groups": 64},
@@ -123,7 +123,7 @@ def test_autotuned_run_equals_fixed_shape_run():
 def test_invalid_shapes_are_rejected():
     b = hd.Batch(_params()[:2])
     for cfg in ({"electron_variant": 99}, {"electron_variant": -1}, {"electron_groups": 5000},
-                {"sort_groups": -1}, {"append_groups": 100000}, {"sort_tile": 16384},
+                {"sort_groups": -1}, {"append_groups": 100000}, {"sort_tile": 2048}, {"sort_tile": 16384},
                 {"sort_tile": 6000}):
         with pytest.raises(hd.HdError) as e:
             b.set_launch(cfg)
